@@ -1,0 +1,252 @@
+"""Column-wise schedules of the oracle and their FP64 plaintext layers.
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+
+The paper states the column-wise method in its abstract and contribution list
+(an A(m x n).B(n x p) product with each operand held as n ciphertexts; an
+h x w image held as w column ciphertexts of h slots) and, in "Secure
+Inference", says that operands split over ciphertexts are multiplied pair-wise
+and summed by linearity and that per-channel ciphertexts are summed.  It gives
+no algorithm for the split forms, so the schedules below are readings built
+from its single-ciphertext algorithms:
+
+  matmul  column k of tau_a(A) (the A encoding of "Encoding Method for Matrix
+          Multiplication") and column k of tau_b(B) are ciphertexts A_k and
+          Bbar_k, replicated with periods M' = pow2(m) and P' = pow2(p); the
+          revolver shift (RowShifter, which is one rotation when m mod p = 0,
+          per "Homomorphic Matrix Multiplication") becomes Rot(Bbar_k, idx), and
+          SumColVec becomes the sum over k:
+              D_idx = Rescale(Relin(sum_k A_k * Rot(Bbar_k, idx))),
+          slot i < m of D_idx holds C[i][(i + idx) mod P'].
+  conv    the CNN convolution of "Convolutional Neural Networks" with stride s
+          and zero padding pi; images are packed in blocks of H' = pow2(h+2pi)
+          slots (virtual ciphertexts, B' = S/H' images per ciphertext); output
+          column j' sums MulConst(Rot(col(c, s j'+v-pi), u), K[c'][c][u][v]) over
+          c, u, v, adds the bias and rescales; slot b H' + s i' holds output
+          row i' of image b.
+  square  Rescale(Relin(Tensor(Y, Y))).
+  fc      Rescale(sum_{c',j'} MulPlain(Y(c',j'), pt_{o,c',j'})), then the
+          SumColVec-style Z += Rot(Z, 2^t) over the H' block, then the bias.
+
+Parity status: "parity unpinned by the paper" -- the paper gives no worked
+example, figure or number for the split schedules; they are pinned only by the
+FP64 plaintext layers below (and special cases: identity matrix, delta kernel,
+constant image) to within 2^-20 normwise relative error.
+"""
+import numpy as np
+
+from .ckks import Context, Keys, pow2ceil, Plaintext
+
+# ------------------------------------------------------------ FP64 layers
+
+
+def ref_matmul(A, B):
+    return np.asarray(A, np.float64) @ np.asarray(B, np.float64)
+
+
+def ref_conv(X, K, bias, stride, pad):
+    """out[b][c'][i'][j'] = bias[c'] + sum_{c,u,v} K[c'][c][u][v] Xpad[b][c][s i'+u][s j'+v]."""
+    X = np.asarray(X, np.float64)
+    B, C, h, w = X.shape
+    Co, Ci, k, _ = K.shape
+    Xp = np.zeros((B, C, h + 2 * pad, w + 2 * pad))
+    Xp[:, :, pad:pad + h, pad:pad + w] = X
+    ho = (h + 2 * pad - k) // stride + 1
+    wo = (w + 2 * pad - k) // stride + 1
+    out = np.zeros((B, Co, ho, wo))
+    for co in range(Co):
+        acc = np.full((B, ho, wo), float(bias[co]))
+        for c in range(C):
+            for u in range(k):
+                for v in range(k):
+                    acc += K[co, c, u, v] * Xp[:, c, u:u + stride * ho:stride, v:v + stride * wo:stride]
+        out[:, co] = acc
+    return out
+
+
+def ref_fc(Y, W, bias):
+    """logits[b][o] = bias[o] + sum W[o][c][i][j] Y[b][c][i][j] (NCHW flatten)."""
+    Y = np.asarray(Y, np.float64)
+    return Y.reshape(Y.shape[0], -1) @ W.reshape(W.shape[0], -1).T + bias[None, :]
+
+
+def rel_error(y, ref):
+    """max |y - ref| / max |ref| over the valid outputs of one layer."""
+    y, ref = np.asarray(y, np.float64), np.asarray(ref, np.float64)
+    return float(np.max(np.abs(y - ref)) / np.max(np.abs(ref)))
+
+
+# ------------------------------------------------------------- encodings
+
+
+def image_block(h, pad):
+    return pow2ceil(h + 2 * pad)
+
+
+def image_column_slots(ctx: Context, X, c, j, pad):
+    """Slot b H' + pad + i holds X[b][c][i][j]; zeros elsewhere."""
+    B, C, h, w = X.shape
+    Hp = image_block(h, pad)
+    if B * Hp > ctx.slots:
+        raise ValueError("too many images for one ciphertext")
+    z = np.zeros(ctx.slots)
+    for b in range(B):
+        z[b * Hp + pad:b * Hp + pad + h] = X[b, c, :, j]
+    return z
+
+
+def encrypt_image_columns(ctx: Context, keys: Keys, X, pad, level, seed, first_ct_id):
+    """Ciphertext (c, j) has id first_ct_id + c*w + j; returned in that order."""
+    X = np.asarray(X, np.float64)
+    B, C, h, w = X.shape
+    out = []
+    for c in range(C):
+        for j in range(w):
+            pt = ctx.encode(image_column_slots(ctx, X, c, j, pad), level, ctx.scale)
+            out.append(ctx.encrypt(keys, pt, seed, first_ct_id + c * w + j))
+    return out
+
+
+def matrix_column_slots(ctx: Context, M, k, role, m, p):
+    """role 0: column k of A, slot s -> A[s mod M'][k]; role 1: Bbar_k, slot
+    s -> B[k][s mod P'] (zeros past m rows / p columns)."""
+    M = np.asarray(M, np.float64)
+    Mp, Pp = pow2ceil(m), pow2ceil(p)
+    s = np.arange(ctx.slots)
+    if role == 0:
+        r = s % Mp
+        return np.where(r < m, M[np.minimum(r, m - 1), k], 0.0)
+    r = s % Pp
+    return np.where(r < p, M[k, np.minimum(r, p - 1)], 0.0)
+
+
+def encrypt_matrix_columns(ctx: Context, keys: Keys, M, role, m, p, level, seed, first_ct_id):
+    M = np.asarray(M, np.float64)
+    n = M.shape[1] if role == 0 else M.shape[0]
+    return [ctx.encrypt(keys, ctx.encode(matrix_column_slots(ctx, M, k, role, m, p), level, ctx.scale),
+                        seed, first_ct_id + k) for k in range(n)]
+
+
+# ------------------------------------------------------------- schedules
+
+
+def matmul(ctx: Context, keys: Keys, A_cts, B_cts, m, n, p):
+    if m < p:
+        raise ValueError("matmul schedule needs m >= p (use the transpose)")
+    Pp = pow2ceil(p)
+    T = [None] * Pp
+    for k in range(n):
+        rots = [B_cts[k]] + ctx.rotate_many(B_cts[k], list(range(1, Pp)), keys)
+        for idx in range(Pp):
+            t = ctx.tensor(A_cts[k], rots[idx])
+            T[idx] = t if T[idx] is None else ctx.add(T[idx], t)
+    return [ctx.rescale(ctx.relinearize(T[idx], keys)) for idx in range(Pp)]
+
+
+def matmul_decode(ctx: Context, keys: Keys, D, m, p):
+    Pp = pow2ceil(p)
+    C = np.full((m, p), np.nan)
+    for idx in range(Pp):
+        z = ctx.decode(ctx.decrypt(keys, D[idx]))
+        for i in range(m):
+            col = (i + idx) % Pp
+            if col < p:
+                C[i, col] = z[i]
+    return C
+
+
+def conv_out_size(h, pad, k, stride):
+    return (h + 2 * pad - k) // stride + 1
+
+
+def conv2d(ctx: Context, keys: Keys, cts, C_in, h, w, pad, K, bias, C_out, k, stride):
+    K = np.asarray(K, np.float64)
+    wo = conv_out_size(w, pad, k, stride)
+    level = cts[0].level
+    dc = float(ctx.q[level])
+    rot = [[None] * w for _ in range(C_in)]
+    for c in range(C_in):
+        for j in range(w):
+            ct = cts[c * w + j]
+            rot[c][j] = [ct] + ctx.rotate_many(ct, list(range(1, k)), keys)
+    out = []
+    for co in range(C_out):
+        for jo in range(wo):
+            acc = None
+            for c in range(C_in):
+                for v in range(k):
+                    jj = stride * jo + v - pad
+                    if jj < 0 or jj >= w:
+                        continue
+                    for u in range(k):
+                        t = ctx.mul_const(rot[c][jj][u], K[co, c, u, v], dc)
+                        acc = t if acc is None else ctx.add(acc, t)
+            acc = ctx.add_const(acc, float(bias[co]))
+            out.append(ctx.rescale(acc))
+    return out
+
+
+def conv_decode(ctx: Context, keys: Keys, Y, B, C_out, h, pad, k, stride, w):
+    Hp = image_block(h, pad)
+    ho, wo = conv_out_size(h, pad, k, stride), conv_out_size(w, pad, k, stride)
+    out = np.zeros((B, C_out, ho, wo))
+    for co in range(C_out):
+        for jo in range(wo):
+            z = ctx.decode(ctx.decrypt(keys, Y[co * wo + jo]))
+            for b in range(B):
+                out[b, co, :, jo] = z[b * Hp + stride * np.arange(ho)]
+    return out
+
+
+def square(ctx: Context, keys: Keys, ct):
+    return ctx.rescale(ctx.relinearize(ctx.tensor(ct, ct), keys))
+
+
+def fc_plaintexts(ctx: Context, W, C, ho, wo, stride, Hp, level):
+    """pt[o][c*wo + j'] has slot b H' + s i' -> W[o][c][i'][j'] for i' < ho, every
+    block b; encoded at scale (double) q_level."""
+    W = np.asarray(W, np.float64).reshape(-1, C, ho, wo)
+    nb = ctx.slots // Hp
+    pts = []
+    for o in range(W.shape[0]):
+        row = []
+        for c in range(C):
+            for jo in range(wo):
+                z = np.zeros(ctx.slots)
+                for b in range(nb):
+                    z[b * Hp + stride * np.arange(ho)] = W[o, c, :, jo]
+                row.append(ctx.encode(z, level, float(ctx.q[level])))
+        pts.append(row)
+    return pts
+
+
+def fc(ctx: Context, keys: Keys, Y, pts, bias, Hp):
+    out = []
+    for o, row in enumerate(pts):
+        acc = None
+        for y, pt in zip(Y, row):
+            t = ctx.mul_plain(y, pt)
+            acc = t if acc is None else ctx.add(acc, t)
+        z = ctx.rescale(acc)
+        step = 1
+        while step < Hp:
+            z = ctx.add(z, ctx.rotate(z, step, keys))
+            step *= 2
+        out.append(ctx.add_const(z, float(bias[o])))
+    return out
+
+
+def fc_decode(ctx: Context, keys: Keys, Z, B, Hp):
+    out = np.zeros((B, len(Z)))
+    for o, z in enumerate(Z):
+        v = ctx.decode(ctx.decrypt(keys, z))
+        out[:, o] = v[np.arange(B) * Hp]
+    return out
+
+
+def fc_rotation_steps(Hp):
+    steps, s = [], 1
+    while s < Hp:
+        steps.append(s)
+        s *= 2
+    return steps

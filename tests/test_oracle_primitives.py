@@ -1,0 +1,317 @@
+"""Pins of the oracle's arithmetic primitives against things other than itself:
+sympy primality, RFC 8439 vectors, schoolbook negacyclic products, Horner
+evaluation, Python big-integer CRT, exact rounding, and sampler statistics."""
+import os
+import random
+
+import numpy as np
+import pytest
+import sympy
+
+from oracle import Context, Params, PRESETS, gen_primes, find_psi, cdt_table, security_bound
+from oracle._clib import lib, ptr
+from oracle.ckks import rha, rha_array
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# ------------------------------------------------------------------ primes
+
+@pytest.mark.parametrize("name", ["C1", "C2", "C3", "C1_literal"])
+def test_prime_chain_definition(name):
+    p = PRESETS[name]
+    n2 = 1 << (p.log_n + 1)
+    bits = list(p.q_bits) + list(p.p_bits)
+    primes = gen_primes(p.log_n, bits)
+    assert len(set(primes)) == len(primes)
+    for k, (q, b) in enumerate(zip(primes, bits)):
+        assert sympy.isprime(q)
+        assert q % n2 == 1
+        assert q.bit_length() == b
+        # nothing larger below 2^b qualifies unless an earlier entry took it
+        c = q + n2
+        while c < (1 << b):
+            assert (not sympy.isprime(c)) or c in primes[:k]
+            c += n2
+
+
+def test_security_bound():
+    assert Context(PRESETS["C1"]).secure
+    assert Context(PRESETS["C2"]).secure
+    assert Context(PRESETS["C3"]).secure
+    lit = PRESETS["C1_literal"]
+    assert not Context(lit).secure
+    with pytest.raises(ValueError):
+        Context(Params(lit.log_n, lit.q_bits, lit.p_bits, lit.dnum, lit.log2_scale))
+    assert security_bound(13) == 218 and security_bound(16) == 1740
+
+
+@pytest.mark.parametrize("log_n", [4, 13, 16])
+def test_psi_is_primitive_2n_root(log_n):
+    for q in gen_primes(16, [60, 50, 51, 40]):
+        psi = find_psi(q, log_n)
+        n = 1 << log_n
+        assert pow(psi, n, q) == q - 1
+        assert pow(psi, 2 * n, q) == 1
+
+
+# ---------------------------------------------------------- scalar arithmetic
+
+def test_mulmod_edges():
+    rnd = random.Random(1)
+    for q in gen_primes(16, [60, 50, 40]):
+        vals = [0, 1, 2, q - 1, q - 2, q // 2, q // 2 + 1] + [rnd.randrange(q) for _ in range(50)]
+        for a in vals:
+            for b in vals[:10]:
+                assert lib.orc_mulmod(a, b, q) == a * b % q
+        for x in [0, 1, -1, q, -q, 2 ** 62, -(2 ** 62), -(2 ** 63)]:
+            assert lib.orc_reduce_i64(x, q) == x % q
+
+
+def test_rha_half_away_from_zero():
+    assert [rha(x) for x in (0.5, -0.5, 1.5, -1.5, 2.4999, -2.5000001)] == [1, -1, 2, -2, 2, -3]
+    big = float(2 ** 52 + 1)
+    assert rha(big) == 2 ** 52 + 1          # floor(x + 0.5) would give 2^52 + 2
+    assert list(rha_array([0.5, -0.5, big])) == [1.0, -1.0, big]
+
+
+# --------------------------------------------------------------------- NTT
+
+def _schoolbook_negacyclic(a, b, q):
+    n = len(a)
+    out = [0] * n
+    for i in range(n):
+        for j in range(n):
+            k = i + j
+            if k < n:
+                out[k] += a[i] * b[j]
+            else:
+                out[k - n] -= a[i] * b[j]
+    return [x % q for x in out]
+
+
+def _brev(x, bits):
+    return int(format(x, "0%db" % bits)[::-1], 2)
+
+
+@pytest.mark.parametrize("log_n", [3, 4, 5, 6])
+def test_polymul_equals_schoolbook(log_n):
+    rnd = random.Random(log_n)
+    P = Params(log_n, [60, 40], [51], 1, 30.0, allow_insecure=True)
+    ctx = Context(P)
+    for q in ctx.q + ctx.p + gen_primes(16, [50]):
+        a = [rnd.randrange(q) for _ in range(ctx.n)]
+        b = [rnd.randrange(q) for _ in range(ctx.n)]
+        got = ctx.polymul(np.array(a, np.uint64), np.array(b, np.uint64), q)
+        assert [int(x) for x in got] == _schoolbook_negacyclic(a, b, q)
+
+
+@pytest.mark.parametrize("log_n", [3, 6])
+def test_ntt_order_is_bitreversed_evaluation(log_n):
+    """Output i equals the Horner value of a at psi^(2 brev(i) + 1)."""
+    rnd = random.Random(7)
+    ctx = Context(Params(log_n, [50], [51], 1, 30.0, allow_insecure=True))
+    q = ctx.q[0]
+    psi = find_psi(q, log_n)
+    a = [rnd.randrange(q) for _ in range(ctx.n)]
+    got = [int(x) for x in ctx.ntt(np.array(a, np.uint64), q)]
+    for i in range(ctx.n):
+        x = pow(psi, 2 * _brev(i, log_n) + 1, q)
+        acc = 0
+        for c in reversed(a):
+            acc = (acc * x + c) % q
+        assert got[i] == acc
+    back = ctx.intt(np.array(got, np.uint64), q)
+    assert [int(v) for v in back] == a
+
+
+def test_ntt_roundtrip_full_size():
+    ctx = Context(PRESETS["C2"])
+    rng = np.random.default_rng(3)
+    for q in (ctx.q[0], ctx.q[3], ctx.p[0]):
+        a = rng.integers(0, q, ctx.n, dtype=np.uint64)
+        assert np.array_equal(ctx.intt(ctx.ntt(a, q), q), a)
+
+
+# ------------------------------------------------------------------ ChaCha20
+
+def _golden_chacha():
+    d = {}
+    for line in open(os.path.join(GOLDEN, "rfc8439_chacha20.txt")):
+        if line.strip() and not line.startswith("#"):
+            k, *v = line.split()
+            d[k] = [int(x, 16) for x in v]
+    return d
+
+
+def test_chacha_quarter_round_rfc8439():
+    g = _golden_chacha()
+    s = np.array(g["quarter_in"], dtype=np.uint32)
+    lib.orc_chacha_quarter(ptr(s))
+    assert [int(x) for x in s] == g["quarter_out"]
+
+
+def test_chacha_block_rfc8439():
+    g = _golden_chacha()
+    key = np.array(g["block_key"], dtype=np.uint32)
+    nonce = np.array(g["block_nonce"], dtype=np.uint32)
+    out = np.zeros(16, dtype=np.uint32)
+    lib.orc_chacha20_block(ptr(key), g["block_counter"][0], ptr(nonce), ptr(out))
+    assert [int(x) for x in out] == g["block_out"]
+
+
+def test_stream_word_layout():
+    """word w = little-endian bytes 8w..8w+7 of the keystream (block w // 8)."""
+    ctx = Context(PRESETS["C1"])
+    seed, pur, obj = 0x1122334455667788, 6, 0x0000000a0000000b
+    words = ctx.stream_words(seed, pur, obj, 0, 24)
+    key = np.array([seed & 0xffffffff, seed >> 32, 0, 0, 0, 0, 0, 0], dtype=np.uint32)
+    nonce = np.array([pur, obj & 0xffffffff, obj >> 32], dtype=np.uint32)
+    for blk in range(3):
+        out = np.zeros(16, dtype=np.uint32)
+        lib.orc_chacha20_block(ptr(key), blk, ptr(nonce), ptr(out))
+        for j in range(8):
+            assert int(words[blk * 8 + j]) == int(out[2 * j]) | (int(out[2 * j + 1]) << 32)
+    assert np.array_equal(ctx.stream_words(seed, pur, obj, 5, 10), words[5:15])
+
+
+# ------------------------------------------------------------------ samplers
+
+def test_uniform_sampler_192bit_product():
+    ctx = Context(PRESETS["C3"])
+    q = ctx.p[2]
+    limb = 3
+    got = ctx.sample_uniform(9, 4, 70, limb, q)
+    w = ctx.stream_words(9, 4, 70, 2 * limb * ctx.n, 2 * ctx.n)
+    for t in list(range(64)) + [ctx.n - 1]:
+        W = int(w[2 * t]) | (int(w[2 * t + 1]) << 64)
+        assert int(got[t]) == (W * q) >> 128
+    assert got.max() < q
+    assert abs(float(got.astype(np.float64).mean()) / q - 0.5) < 0.01
+
+
+def test_ternary_sampler_frequencies():
+    ctx = Context(PRESETS["C3"])
+    s = ctx.sample_ternary(5, 1, 0)
+    vals, counts = np.unique(s, return_counts=True)
+    assert list(vals) == [-1, 0, 1]
+    assert np.all(np.abs(counts / s.size - 1 / 3) < 0.01)
+
+
+def test_cdt_table_properties():
+    t = cdt_table(3.2)
+    assert len(t) == 20 and t[-1] == 1 << 63
+    assert all(a < b for a, b in zip(t, t[1:]))
+    rho = np.exp(-np.arange(20) ** 2 / (2 * 3.2 ** 2))
+    z = rho[0] + 2 * rho[1:].sum()
+    assert abs(t[0] / 2.0 ** 63 - rho[0] / z) < 1e-12
+    assert abs(t[5] / 2.0 ** 63 - (rho[0] + 2 * rho[1:6].sum()) / z) < 1e-12
+
+
+def test_gaussian_sampler_statistics():
+    ctx = Context(PRESETS["C3"])
+    e = np.concatenate([ctx.sample_gauss(11, 3, k) for k in range(4)]).astype(np.float64)
+    assert abs(e.mean()) < 0.05
+    assert abs(e.var() / 3.2 ** 2 - 1) < 0.03
+    assert np.abs(e).max() <= 19
+    assert abs(np.mean(e > 0) - np.mean(e < 0)) < 0.01
+
+
+# ------------------------------------------------------------ base conversion
+
+def _crt(residues, moduli):
+    M = 1
+    for m in moduli:
+        M *= m
+    x = 0
+    for r, m in zip(residues, moduli):
+        Mi = M // m
+        x += int(r) * Mi * pow(Mi, -1, m)
+    return x % M, M
+
+
+@pytest.mark.parametrize("alpha", [1, 3, 9])
+def test_base_conversion_is_lift_plus_small_multiple(alpha):
+    """conv(x) = X + e Q_D exactly, |e| <= alpha/2, for X the centred CRT lift."""
+    ctx = Context(Params(3, [50] * 9, [51] * 9, 1, 30.0, allow_insecure=True))
+    rng = np.random.default_rng(alpha)
+    qin = ctx.q[:alpha]
+    qout = ctx.p + ctx.q[alpha:]
+    x = np.stack([rng.integers(0, q, ctx.n, dtype=np.uint64) for q in qin])
+    out = ctx.base_convert(x, qin, qout)
+    for t in range(ctx.n):
+        X, Q = _crt([x[i, t] for i in range(alpha)], qin)
+        if X > Q // 2:
+            X -= Q
+        es = set()
+        for o, to in enumerate(qout):
+            # find the e with out = X + e Q mod t_o among |e| <= alpha/2 + 1
+            cand = [e for e in range(-alpha, alpha + 1) if (X + e * Q - int(out[o, t])) % to == 0]
+            assert len(cand) == 1
+            es.add(cand[0])
+        assert len(es) == 1
+        assert abs(es.pop()) <= alpha / 2 + 0.5
+
+
+# ------------------------------------------------------------------- rescale
+
+def test_rescale_is_rounded_division():
+    ctx = Context(Params(3, [60, 50, 50, 50], [51], 4, 30.0, allow_insecure=True))
+    rng = np.random.default_rng(4)
+    from oracle import Ciphertext
+    lv = 3
+    c = np.stack([np.stack([rng.integers(0, q, ctx.n, dtype=np.uint64) for q in ctx.q])
+                  for _ in range(2)])
+    out = ctx.rescale(Ciphertext(c, lv, 2.0 ** 60))
+    for k in range(2):
+        for t in range(ctx.n):
+            X, Q = _crt([c[k, i, t] for i in range(lv + 1)], ctx.q)
+            ql = ctx.q[lv]
+            # round(X / q_l) with X taken modulo Q: the rescaled value modulo Q/q_l
+            Y = (2 * X + ql) // (2 * ql)
+            for i in range(lv):
+                assert int(out.c[k, i, t]) == Y % ctx.q[i]
+    assert out.scale == 2.0 ** 60 / ctx.q[lv]
+
+
+def test_mod_down_is_division_by_p():
+    """ModDown returns round(U / P) up to +-K/2 (centred base conversion)."""
+    ctx = Context(Params(3, [60, 50, 50], [51, 51, 51], 1, 30.0, allow_insecure=True))
+    rng = np.random.default_rng(8)
+    lv = 2
+    ext = ctx.ext_moduli(lv)
+    u = np.stack([rng.integers(0, q, ctx.n, dtype=np.uint64) for q in ext])
+    out = ctx.mod_down(u, lv)
+    P = 1
+    for p in ctx.p:
+        P *= p
+    Qm = 1
+    for q in ctx.q:
+        Qm *= q
+    for t in range(ctx.n):
+        U, M = _crt([u[i, t] for i in range(len(ext))], ext)
+        Y, _ = _crt([out[i, t] for i in range(lv + 1)], ctx.q)
+        diff = (Y - (2 * U + P) // (2 * P)) % Qm
+        if diff > Qm // 2:
+            diff -= Qm
+        assert abs(diff) <= ctx.K / 2 + 1
+
+
+# -------------------------------------------------------------- automorphism
+
+def test_automorphism_is_ring_homomorphism():
+    ctx = Context(Params(5, [50], [51], 1, 30.0, allow_insecure=True))
+    q = ctx.q[0]
+    rng = np.random.default_rng(5)
+    a = rng.integers(0, q, ctx.n, dtype=np.uint64)
+    b = rng.integers(0, q, ctx.n, dtype=np.uint64)
+    g, h = 5, 2 * ctx.n - 1
+    lhs = ctx.automorphism(ctx.automorphism(a, h, q), g, q)
+    assert np.array_equal(lhs, ctx.automorphism(a, g * h % (2 * ctx.n), q))
+    assert np.array_equal(ctx.automorphism(ctx.polymul(a, b, q), g, q),
+                          ctx.polymul(ctx.automorphism(a, g, q), ctx.automorphism(b, g, q), q))
+    # X -> X^g sends X to X^g
+    x = np.zeros(ctx.n, np.uint64)
+    x[1] = 1
+    y = ctx.automorphism(x, g, q)
+    assert int(y[g]) == 1 and int(y.sum()) == 1

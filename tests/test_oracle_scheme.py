@@ -1,0 +1,227 @@
+"""Pins of the oracle's CKKS scheme and column-wise schedules: closed forms of
+the encoder, decryption invariants, key-switching noise, rotation identities,
+and the schedules against FP64 plaintext layers (matmul, convolution, x^2,
+FC) including their special cases."""
+import numpy as np
+import pytest
+
+from oracle import Context, Params, PRESETS, Ciphertext
+from oracle import layers as Ly
+from oracle.ckks import rha
+
+EPS = 2.0 ** -20
+
+
+def small_ctx(log_n=8, q_bits=(60, 40, 40, 40), p_bits=(60,), dnum=4, log2_scale=40.0):
+    return Context(Params(log_n, list(q_bits), list(p_bits), dnum, log2_scale, allow_insecure=True))
+
+
+# ------------------------------------------------------------------ encoder
+
+def test_encode_constant_closed_form():
+    ctx = small_ctx()
+    for c in (0.75, -0.3, 1.0):
+        m = ctx.encode_int(np.full(ctx.slots, c), ctx.scale)
+        assert m[0] == rha(c * ctx.scale)
+        assert np.all(m[1:] == 0)
+
+
+def test_encode_single_slot_closed_form():
+    """z = e_j: m_t = RHA((2 scale / N) cos(pi g_j t / N))."""
+    ctx = small_ctx(log_n=6)
+    j = 3
+    z = np.zeros(ctx.slots)
+    z[j] = 1.0
+    m = ctx.encode_int(z, ctx.scale)
+    t = np.arange(ctx.n)
+    want = 2 * ctx.scale / ctx.n * np.cos(np.pi * ctx.gexp[j] * t / ctx.n)
+    assert np.max(np.abs(m - want)) <= 0.5 + 1e-3
+
+
+def test_decode_encode_roundtrip():
+    ctx = Context(PRESETS["C2"])
+    z = np.random.default_rng(0).uniform(-1, 1, ctx.slots)
+    pt = ctx.encode(z, 2, ctx.scale)
+    assert np.max(np.abs(ctx.decode(pt) - z)) < 2.0 ** -(40 - 10)
+
+
+def test_automorphism_5_rotates_slots_left():
+    ctx = small_ctx(log_n=7)
+    z = np.random.default_rng(1).uniform(-1, 1, ctx.slots)
+    pt = ctx.encode(z, 0, ctx.scale)
+    q = ctx.q[0]
+    pt.m[0] = ctx.automorphism(pt.m[0], 5, q)
+    assert np.max(np.abs(ctx.decode(pt) - np.roll(z, -1))) < 1e-9
+    # 5 has order S modulo 2N: rotation by S is the identity element
+    assert ctx.galois_element(ctx.slots) == 1
+
+
+# ---------------------------------------------------------- encrypt / decrypt
+
+@pytest.mark.parametrize("name", ["C1", "C2"])
+def test_decrypt_encrypt_noise(name):
+    ctx = Context(PRESETS[name])
+    keys = ctx.keygen(1000 + 1)
+    z = np.random.default_rng(2).uniform(-1, 1, ctx.slots)
+    ct = ctx.encrypt(keys, ctx.encode(z, ctx.L, ctx.scale), 77, 0)
+    err = np.max(np.abs(ctx.decode(ctx.decrypt(keys, ct)) - z))
+    assert err < 2.0 ** -21
+    # the public key is an encryption of zero: b + a s is small
+    q = ctx.q[1]
+    bas = ctx.vadd(keys.pk_b[1], ctx.polymul(keys.pk_a[1], ctx.reduce_int(keys.s, q), q), q)
+    cen = np.where(bas > q // 2, bas.astype(np.float64) - q, bas.astype(np.float64))
+    assert np.abs(cen).max() <= 19
+
+
+def test_encrypt_is_deterministic_in_seed_and_id():
+    ctx = small_ctx()
+    keys = ctx.keygen(3)
+    pt = ctx.encode(np.ones(4), 2, ctx.scale)
+    a = ctx.encrypt(keys, pt, 5, 1)
+    b = ctx.encrypt(keys, pt, 5, 1)
+    c = ctx.encrypt(keys, pt, 5, 2)
+    assert np.array_equal(a.c, b.c) and not np.array_equal(a.c, c.c)
+
+
+def test_key_switch_noise_bound():
+    """decrypt(KS(d)) - d s' is small for s' = s^2 (relinearisation key)."""
+    ctx = Context(PRESETS["C1"])
+    keys = ctx.keygen(9)
+    rng = np.random.default_rng(3)
+    lv = ctx.L
+    d = np.stack([rng.integers(0, q, ctx.n, dtype=np.uint64) for q in ctx.moduli(lv)])
+    o0, o1 = ctx.key_switch(d, keys.rlk, lv)
+    for i, q in enumerate(ctx.moduli(lv)):
+        s = ctx.reduce_int(keys.s, q)
+        got = ctx.vadd(o0[i], ctx.polymul(o1[i], s, q), q)
+        want = ctx.polymul(d[i], ctx.polymul(s, s, q), q)
+        e = ctx.vsub(got, want, q).astype(np.float64)
+        e = np.where(e > q // 2, e - q, e)
+        assert np.abs(e).max() < 2.0 ** 16
+
+
+# ----------------------------------------------------------------- rotations
+
+def test_rotation_invariants():
+    ctx = small_ctx(log_n=8)
+    keys = ctx.keygen(4, rot_steps=[1, 2, 3, 5])
+    z = np.random.default_rng(4).uniform(-1, 1, ctx.slots)
+    ct = ctx.encrypt(keys, ctx.encode(z, 3, ctx.scale), 1, 0)
+    r12 = ctx.rotate(ctx.rotate(ct, 1, keys), 2, keys)
+    r3 = ctx.rotate(ct, 3, keys)
+    d12 = ctx.decode(ctx.decrypt(keys, r12))
+    d3 = ctx.decode(ctx.decrypt(keys, r3))
+    assert np.max(np.abs(d3 - np.roll(z, -3))) < 1e-6
+    assert np.max(np.abs(d12 - d3)) < 1e-6
+    assert np.array_equal(ctx.rotate(ct, ctx.slots, keys).c, ct.c)
+    with pytest.raises(KeyError):
+        ctx.rotate(ct, 4, keys)
+    hoisted = ctx.rotate_many(ct, [1, 5], keys)
+    assert np.array_equal(hoisted[1].c, ctx.rotate(ct, 5, keys).c)
+
+
+def test_add_level_and_scale_checks():
+    ctx = small_ctx()
+    keys = ctx.keygen(1)
+    a = ctx.encrypt(keys, ctx.encode([1.0], 3, ctx.scale), 1, 0)
+    b = ctx.encrypt(keys, ctx.encode([1.0], 2, ctx.scale), 1, 1)
+    with pytest.raises(ValueError):
+        ctx.add(a, b)
+    c = Ciphertext(a.c, a.level, a.scale * 2)
+    with pytest.raises(ValueError):
+        ctx.add(a, c)
+
+
+def test_mul_const_add_const_rescale():
+    ctx = small_ctx(log_n=9)
+    keys = ctx.keygen(2)
+    z = np.random.default_rng(5).uniform(-1, 1, ctx.slots)
+    ct = ctx.encrypt(keys, ctx.encode(z, 3, ctx.scale), 1, 0)
+    y = ctx.rescale(ctx.add_const(ctx.mul_const(ct, -0.37, float(ctx.q[3])), 0.25))
+    assert y.level == 2 and y.scale == ctx.scale
+    assert np.max(np.abs(ctx.decode(ctx.decrypt(keys, y)) - (-0.37 * z + 0.25))) < 1e-7
+
+
+# ------------------------------------------------------- schedules vs FP64
+
+@pytest.fixture(scope="module")
+def ctx10():
+    ctx = small_ctx(log_n=10, q_bits=(49, 40, 40, 40), p_bits=(49,), dnum=4)
+    keys = ctx.keygen(1001, rot_steps=list(range(1, 16)) + [32, 64, 128])
+    return ctx, keys
+
+
+def test_matmul_schedule_random(ctx10):
+    ctx, keys = ctx10
+    m, n, p = 16, 16, 16
+    rng = np.random.default_rng(1)
+    A, B = rng.uniform(-1, 1, (m, n)), rng.uniform(-1, 1, (n, p))
+    Ac = Ly.encrypt_matrix_columns(ctx, keys, A, 0, m, p, 3, 1, 0)
+    Bc = Ly.encrypt_matrix_columns(ctx, keys, B, 1, m, p, 3, 1, 100)
+    D = Ly.matmul(ctx, keys, Ac, Bc, m, n, p)
+    assert len(D) == 16 and D[0].level == 2
+    C = Ly.matmul_decode(ctx, keys, D, m, p)
+    assert Ly.rel_error(C, A @ B) < EPS
+
+
+def test_matmul_schedule_identity_and_ragged(ctx10):
+    """B = I gives C = A; m=12 > p=5 pads to M'=16, P'=8 (ragged tail)."""
+    ctx, keys = ctx10
+    m, n, p = 12, 5, 5
+    rng = np.random.default_rng(2)
+    A = rng.uniform(-1, 1, (m, n))
+    Ac = Ly.encrypt_matrix_columns(ctx, keys, A, 0, m, p, 3, 2, 0)
+    Bc = Ly.encrypt_matrix_columns(ctx, keys, np.eye(n), 1, m, p, 3, 2, 100)
+    D = Ly.matmul(ctx, keys, Ac, Bc, m, n, p)
+    assert len(D) == 8
+    C = Ly.matmul_decode(ctx, keys, D, m, p)
+    assert not np.any(np.isnan(C))
+    assert Ly.rel_error(C, A) < EPS
+
+
+def test_conv_schedule_random_square_fc(ctx10):
+    ctx, keys = ctx10
+    B, Ci, h, w, Co, k, s, pad = 8, 2, 10, 9, 3, 3, 2, 1
+    rng = np.random.default_rng(3)
+    X = rng.uniform(0, 1, (B, Ci, h, w))
+    K = rng.normal(0, 0.1, (Co, Ci, k, k))
+    bias = rng.normal(0, 0.1, Co)
+    cts = Ly.encrypt_image_columns(ctx, keys, X, pad, 3, 3, 0)
+    Y = Ly.conv2d(ctx, keys, cts, Ci, h, w, pad, K, bias, Co, k, s)
+    ref = Ly.ref_conv(X, K, bias, s, pad)
+    got = Ly.conv_decode(ctx, keys, Y, B, Co, h, pad, k, s, w)
+    assert Ly.rel_error(got, ref) < EPS
+    Y2 = [Ly.square(ctx, keys, y) for y in Y]
+    got2 = Ly.conv_decode(ctx, keys, Y2, B, Co, h, pad, k, s, w)
+    assert Ly.rel_error(got2, ref ** 2) < EPS
+    Hp = Ly.image_block(h, pad)
+    ho, wo = ref.shape[2], ref.shape[3]
+    W = rng.normal(0, 0.05, (4, Co, ho, wo))
+    fb = rng.normal(0, 0.05, 4)
+    pts = Ly.fc_plaintexts(ctx, W, Co, ho, wo, s, Hp, Y2[0].level)
+    Z = Ly.fc(ctx, keys, Y2, pts, fb, Hp)
+    logits = Ly.fc_decode(ctx, keys, Z, B, Hp)
+    assert Ly.rel_error(logits, Ly.ref_fc(ref ** 2, W, fb)) < EPS
+
+
+def test_conv_special_cases(ctx10):
+    """A delta kernel returns the strided, shifted image; a constant image
+    returns the constant times the kernel sum (interior outputs)."""
+    ctx, keys = ctx10
+    B, h, w, k, s = 4, 12, 12, 3, 2
+    rng = np.random.default_rng(4)
+    X = rng.uniform(0, 1, (B, 1, h, w))
+    K = np.zeros((1, 1, k, k))
+    K[0, 0, 1, 2] = 1.0
+    cts = Ly.encrypt_image_columns(ctx, keys, X, 0, 2, 4, 0)
+    Y = Ly.conv2d(ctx, keys, cts, 1, h, w, 0, K, np.zeros(1), 1, k, s)
+    got = Ly.conv_decode(ctx, keys, Y, B, 1, h, 0, k, s, w)
+    ho = (h - k) // s + 1
+    want = X[:, :, 1:1 + s * ho:s, 2:2 + s * ho:s]
+    assert np.max(np.abs(got - want)) < 1e-6
+    Xc = np.full((B, 1, h, w), 0.6)
+    K2 = rng.normal(0, 0.1, (1, 1, k, k))
+    cts = Ly.encrypt_image_columns(ctx, keys, Xc, 0, 2, 5, 0)
+    Y = Ly.conv2d(ctx, keys, cts, 1, h, w, 0, K2, np.zeros(1), 1, k, s)
+    got = Ly.conv_decode(ctx, keys, Y, B, 1, h, 0, k, s, w)
+    assert np.max(np.abs(got - 0.6 * K2.sum())) < 1e-6
