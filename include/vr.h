@@ -1,0 +1,269 @@
+/*
+ * vr.h -- C ABI of the MI355X (gfx950) library for the column-wise encrypted
+ * inference path of "Volley Revolver: A Novel Matrix-Encoding Method for
+ * Privacy-Preserving Deep Learning (Inference++)".
+ *
+ * Scheme: RNS-CKKS.  The paper's HE interface is KeyGen, Enc_pk, Dec_sk, Add,
+ * Mul, cMul and Rot (left rotation), with rescaling treated as automatic
+ * (Preliminaries, "Fully Homomorphic Encryption").  The usage model ("Secure
+ * Inference", Usage Model) splits the roles: the data owner and model provider
+ * hold the secret key and call the client functions; the cloud calls the
+ * server functions, which never see a secret key.
+ *
+ * Conventions for every function:
+ *  - Returns vr_status; VR_OK is 0, errors are negative.  On error every
+ *    output handle is set to NULL, no partial result exists, and
+ *    vr_last_error() (thread-local) describes the failure.  No C++ exception
+ *    crosses this boundary.
+ *  - Handles are opaque and owned by the caller.  Every handle a function
+ *    returns is new and must be released with the matching vr_free_*.
+ *    Inputs are never modified.
+ *  - Host pointers (double*, uint64_t*, int32_t*) are read or written before
+ *    the call returns.  Device memory behind handles is allocated by the
+ *    context (stream-ordered) unless an allocator hook is installed.
+ *  - `stream` is a hipStream_t; NULL means the context's stream (the null
+ *    stream unless vr_context_set_stream was called).  Server calls only
+ *    enqueue work; vr_ct_export, vr_pt_export, vr_decode and the serving poll
+ *    synchronise.
+ *  - Polynomials are stored on the device in the evaluation (NTT) domain;
+ *    every export is in the coefficient domain, uint64 [component][limb][t],
+ *    limbs q_0..q_level, values in [0, q).
+ *  - The product path runs on the GPU only.  Without a usable gfx950 device,
+ *    vr_context_create fails with VR_EDEVICE.
+ */
+#ifndef VR_H
+#define VR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    VR_OK = 0,
+    VR_EINVAL = -1,     /* bad argument or shape                                  */
+    VR_ESECURITY = -2,  /* parameters above the 128-bit bound, allow_insecure = 0 */
+    VR_ELEVEL = -3,     /* operand levels differ / no level left                  */
+    VR_ESCALE = -4,     /* operand scales are not bitwise-equal doubles           */
+    VR_ENOKEY = -5,     /* missing rotation key                                   */
+    VR_ENOMEM = -6,     /* device allocation failed                               */
+    VR_EDEVICE = -7,    /* HIP runtime error or no gfx950 device                  */
+    VR_EBUSY = -8,      /* serving: request can never fit the memory budget       */
+    VR_ECANCELED = -9   /* serving: request cancelled (deadline)                  */
+} vr_status;
+
+typedef struct vr_context vr_context;
+typedef struct vr_ciphertext vr_ciphertext;
+typedef struct vr_plaintext vr_plaintext;
+typedef struct vr_secret_key vr_secret_key;
+typedef struct vr_eval_keys vr_eval_keys;
+typedef struct vr_server vr_server;
+
+/* RNS-CKKS parameters.  Primes: for each bit size in order (q_bits then
+ * p_bits), the largest prime q < 2^b with q = 1 mod 2N not taken yet.
+ * alpha = ceil(n_q / dnum) Q primes per key-switching digit.  sigma must be
+ * 3.2 (the error table is built for it). */
+typedef struct {
+    uint32_t log_n;          /* N = 2^log_n, 3 <= log_n <= 16           */
+    uint32_t n_q;            /* Q chain length L+1                      */
+    uint32_t n_p;            /* special primes K >= 1                   */
+    uint32_t dnum;           /* key-switching digits                    */
+    const uint32_t *q_bits;  /* [n_q], each in [20, 60]                 */
+    const uint32_t *p_bits;  /* [n_p]                                   */
+    double log2_scale;       /* default encoding scale 2^log2_scale     */
+    double sigma;            /* error standard deviation (3.2)          */
+    uint32_t allow_insecure; /* 1: skip the 128-bit bound (labelled)    */
+} vr_params;
+
+/* ---------------------------------------------------------------- context */
+
+/* Creates a context on `device`: primes, roots, twiddles and base-conversion
+ * constants go to device memory.  Checks the 128-bit bound (total prime bits
+ * <= 218 / 438 / 881 / 1740 for N = 2^13 / 2^14 / 2^15 / 2^16, HE standard
+ * 2018, 2^16 extrapolated conservatively): VR_ESECURITY unless allow_insecure. */
+vr_status vr_context_create(const vr_params *params, int device, vr_context **out);
+void vr_context_destroy(vr_context *ctx);  /* NULL-safe; frees device tables */
+
+/* moduli[0..n_q+n_p) = q_0..q_L, p_0..p_{K-1}; cap = capacity of moduli. */
+vr_status vr_context_moduli(const vr_context *ctx, uint64_t *moduli, size_t cap);
+/* info[0..8) = log_n, slots, n_q, n_p, dnum, alpha, secure, total_bits */
+vr_status vr_context_info(const vr_context *ctx, uint32_t *info8, double *default_scale);
+/* Stream used when a call passes stream = NULL. */
+vr_status vr_context_set_stream(vr_context *ctx, void *stream);
+/* Optional device allocator (e.g. a framework's caching allocator).  Both
+ * functions receive the stream the memory is used on and `user`.  NULL
+ * restores the built-in stream-ordered pool (hipMallocAsync). */
+vr_status vr_context_set_allocator(vr_context *ctx,
+                                   void *(*alloc_fn)(size_t bytes, void *stream, void *user),
+                                   void (*free_fn)(void *ptr, void *stream, void *user),
+                                   void *user);
+const char *vr_last_error(void);
+
+/* ------------------------------------------------------------ client side */
+
+/* Secret key s (ternary), public key, relinearisation key and one rotation
+ * key per distinct Galois element 5^(step mod S) in rot_steps (hybrid key
+ * switching, dnum digits, special primes P).  All randomness is the ChaCha20
+ * stream keyed by `seed` (purpose/object nonce per key part), so the keys are
+ * a deterministic function of (params, seed, steps). */
+vr_status vr_keygen(vr_context *ctx, uint64_t seed, const int32_t *rot_steps, size_t n_steps,
+                    vr_secret_key **sk, vr_eval_keys **ek);
+/* Adds rotation keys (same seed as the original keygen keeps them canonical). */
+vr_status vr_keys_add_rotations(vr_context *ctx, const vr_secret_key *sk, vr_eval_keys *ek,
+                                uint64_t seed, const int32_t *rot_steps, size_t n_steps);
+/* Canonical embedding: slot j of x (j < n <= S, rest zero) is the value at
+ * the root psi^(5^j); coefficients m_t = round-half-away((2 scale / N) Re
+ * sum_j x_j exp(-i pi 5^j t / N)), |m_t| < 2^62, reduced into q_0..q_level. */
+vr_status vr_encode(vr_context *ctx, const double *x, size_t n, uint32_t level, double scale,
+                    vr_plaintext **out);
+/* Public-key encryption (v b + e0 + m, v a + e1) with v, e0, e1 drawn from
+ * the stream of (seed, ct_id). */
+vr_status vr_encrypt(vr_context *ctx, const vr_eval_keys *ek, const vr_plaintext *pt,
+                     uint64_t seed, uint64_t ct_id, vr_ciphertext **out);
+/* Column-wise image encoding (abstract and contributions: an h x w image is
+ * w ciphertexts of h slots).  x is [B][C][h][w] row-major FP64.  Block height
+ * H' = pow2(h + 2 pad); image b occupies slots b H' .. b H' + H' - 1 of every
+ * column ciphertext (virtual ciphertexts), row i at b H' + pad + i.  Requires
+ * B H' <= S.  cols receives C*w handles, column (c, j) at index c*w + j,
+ * encrypted with ct_id = first_ct_id + c*w + j. */
+vr_status vr_encrypt_columns(vr_context *ctx, const vr_eval_keys *ek, const double *x,
+                             uint32_t B, uint32_t C, uint32_t h, uint32_t w, uint32_t pad,
+                             uint32_t level, uint64_t seed, uint64_t first_ct_id,
+                             vr_ciphertext **cols);
+/* Matrix operand as n column ciphertexts (abstract: A (m x n) and B (n x p)
+ * as n ciphertexts each).  role 0: M is A (rows x cols = m x n), ciphertext k
+ * holds slot s -> A[s mod M'][k] (column k of the tau_a encoding, period
+ * M' = pow2(m)).  role 1: M is B (n x p), ciphertext k holds slot s ->
+ * B[k][s mod P'] (column k of the tau_b encoding, period P' = pow2(p)).
+ * Zeros past m rows / p columns.  out receives n handles. */
+vr_status vr_encrypt_matrix_columns(vr_context *ctx, const vr_eval_keys *ek, const double *M,
+                                    uint32_t rows, uint32_t cols, uint32_t role, uint32_t m,
+                                    uint32_t p, uint32_t level, uint64_t seed,
+                                    uint64_t first_ct_id, vr_ciphertext **out);
+/* m' = c0 + c1 s (+ c2 s^2): plaintext at the ciphertext's level and scale. */
+vr_status vr_decrypt(vr_context *ctx, const vr_secret_key *sk, const vr_ciphertext *ct,
+                     vr_plaintext **out);
+/* Slots 0..n-1 from limb q_0 (centred): valid while |coefficients| < q_0/2. */
+vr_status vr_decode(vr_context *ctx, const vr_plaintext *pt, double *out, size_t n);
+
+/* ------------------------------------------------------------ server side */
+
+/* Add / Sub: levels equal (VR_ELEVEL) and scales bitwise equal (VR_ESCALE). */
+vr_status vr_add(vr_context *ctx, const vr_ciphertext *a, const vr_ciphertext *b,
+                 vr_ciphertext **out, void *stream);
+vr_status vr_sub(vr_context *ctx, const vr_ciphertext *a, const vr_ciphertext *b,
+                 vr_ciphertext **out, void *stream);
+/* cMul by a scalar: C = round-half-away(c * c_scale) as an exact integer,
+ * every limb times [C]_q; scale *= c_scale. */
+vr_status vr_mul_const(vr_context *ctx, const vr_ciphertext *a, double c, double c_scale,
+                       vr_ciphertext **out, void *stream);
+/* Adds [round-half-away(c * scale)]_q to the constant coefficient of c0. */
+vr_status vr_add_const(vr_context *ctx, const vr_ciphertext *a, double c, vr_ciphertext **out,
+                       void *stream);
+/* cMul by an encoded plaintext (limb-wise product); scale *= pt scale.  The
+ * plaintext level must be >= the ciphertext level. */
+vr_status vr_mul_plain(vr_context *ctx, const vr_ciphertext *a, const vr_plaintext *pt,
+                       vr_ciphertext **out, void *stream);
+/* (a0 b0, a0 b1 + a1 b0, a1 b1): a 3-component ciphertext. */
+vr_status vr_tensor(vr_context *ctx, const vr_ciphertext *a, const vr_ciphertext *b,
+                    vr_ciphertext **out, void *stream);
+/* Key-switches the s^2 component back to s (hybrid key switching). */
+vr_status vr_relinearize(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *a,
+                         vr_ciphertext **out, void *stream);
+/* Mul of the paper: tensor then relinearise (no rescale). */
+vr_status vr_mul(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *a,
+                 const vr_ciphertext *b, vr_ciphertext **out, void *stream);
+/* Divide by q_level with a centred last limb; level - 1; scale /= q_level. */
+vr_status vr_rescale(vr_context *ctx, const vr_ciphertext *a, vr_ciphertext **out, void *stream);
+/* Drop limbs above `level` (scale unchanged). */
+vr_status vr_mod_drop(vr_context *ctx, const vr_ciphertext *a, uint32_t level,
+                      vr_ciphertext **out, void *stream);
+/* Rot(ct, step): slots rotated left by step (Galois element 5^step). */
+vr_status vr_rotate(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *a,
+                    int32_t step, vr_ciphertext **out, void *stream);
+/* k rotations sharing one ModUp (hoisted); bit-identical to k vr_rotate calls. */
+vr_status vr_rotate_many(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *a,
+                         const int32_t *steps, size_t k, vr_ciphertext **outs, void *stream);
+
+/* Column-split matrix product (abstract and contributions; "Homomorphic
+ * Matrix Multiplication" with RowShifter reduced to one rotation and the
+ * ciphertext-pair split of "Parallelized Matrix Multiplication"): from A_k,
+ * Bbar_k (k < n, from vr_encrypt_matrix_columns), for idx < P',
+ *   C[idx] = Rescale(Relin(sum_k A_k * Rot(Bbar_k, idx))),
+ * slot i < m of C[idx] holding (A B)[i][(i + idx) mod P'].  Needs m >= p and
+ * rotation keys for steps 1..P'-1.  C receives P' handles. */
+vr_status vr_matmul(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *A,
+                    const vr_ciphertext *const *Bbar, uint32_t m, uint32_t n, uint32_t p,
+                    vr_ciphertext **C, void *stream);
+/* Column convolution (conv layer of "Convolutional Neural Networks", with
+ * per-channel accumulation of "Parallelized Convolution Operation"): inputs
+ * in[c*w + j] from vr_encrypt_columns; K is [C_out][C_in][k][k], bias
+ * [C_out] (FP64).  Output column (c', j') at index c'*w_out + j':
+ *   Rescale(sum_{c,u,v} MulConst(Rot(in[c][s j'+v-pad], u), K[c'][c][u][v],
+ *           q_level) + AddConst(bias[c'])),
+ * slot b H' + s i' holding output row i' of image b.  Needs rotation keys for
+ * steps 1..k-1. */
+vr_status vr_conv2d(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *in,
+                    uint32_t C_in, uint32_t h, uint32_t w, uint32_t pad, const double *K,
+                    const double *bias, uint32_t C_out, uint32_t k, uint32_t stride,
+                    vr_ciphertext **out, void *stream);
+/* x^2 activation on n ciphertexts: Rescale(Relin(Tensor(y, y))). */
+vr_status vr_square(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *in,
+                    size_t n, vr_ciphertext **out, void *stream);
+/* Fully connected layer on conv outputs Y[c*w_out + j'] (C channels):
+ *   Z_o = Rescale(sum_{c,j'} MulPlain(Y, W_pt[o][c*w_out + j'])), then
+ *   Z_o += Rot(Z_o, 2^t) for 2^t < block, then AddConst(bias[o]).
+ * W_pt from vr_encode_fc_weights; slot b*block holds logit o of image b.
+ * Needs rotation keys for steps 1, 2, 4, ..., block/2. */
+vr_status vr_fc(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *Y,
+                uint32_t C, uint32_t w_out, const vr_plaintext *const *W_pt, const double *bias,
+                uint32_t n_out, uint32_t block, vr_ciphertext **out, void *stream);
+/* Model-provider side of the FC layer: W is [n_out][C][h_out][w_out];
+ * plaintext (o, c, j') has slot b*block + stride*i' -> W[o][c][i'][j'] for
+ * i' < h_out in every block b, encoded at scale (double) q_level.  W_pt
+ * receives n_out*C*w_out handles, index (o*C + c)*w_out + j'. */
+vr_status vr_encode_fc_weights(vr_context *ctx, const double *W, uint32_t n_out, uint32_t C,
+                               uint32_t h_out, uint32_t w_out, uint32_t stride, uint32_t block,
+                               uint32_t level, vr_plaintext **W_pt);
+
+/* ---------------------------------------------------- parity and lifetime */
+
+/* Coefficient-domain export, uint64 [ncomp][level+1][N]; cap_words must hold
+ * it.  Synchronises the context stream. */
+vr_status vr_ct_export(vr_context *ctx, const vr_ciphertext *ct, uint64_t *host, size_t cap_words,
+                       uint32_t *ncomp, uint32_t *level, double *scale);
+vr_status vr_ct_import(vr_context *ctx, const uint64_t *host, uint32_t ncomp, uint32_t level,
+                       double scale, vr_ciphertext **out);
+vr_status vr_pt_export(vr_context *ctx, const vr_plaintext *pt, uint64_t *host, size_t cap_words,
+                       uint32_t *level, double *scale);
+vr_status vr_pt_import(vr_context *ctx, const uint64_t *host, uint32_t level, double scale,
+                       vr_plaintext **out);
+/* Secret key as int8 coefficients in {-1, 0, 1} (client-side check). */
+vr_status vr_sk_export(vr_context *ctx, const vr_secret_key *sk, int8_t *host, size_t n);
+/* Switching key in the coefficient domain, uint64 [dnum][2][n_q + n_p][N]
+ * (digit j: b_j then a_j; limbs q_0..q_L, p_0..p_{K-1}).  galois = 0 selects
+ * the relinearisation key, otherwise the rotation key of that Galois
+ * element (VR_ENOKEY if absent).  Synchronises. */
+vr_status vr_swk_export(vr_context *ctx, const vr_eval_keys *ek, uint32_t galois, uint64_t *host,
+                        size_t cap_words);
+/* Ciphertext metadata without a copy. */
+vr_status vr_ct_meta(const vr_ciphertext *ct, uint32_t *ncomp, uint32_t *level, double *scale);
+
+/* Negacyclic NTT of raw device limbs in place: data is [n_limbs][N] on the
+ * device, limb i reduced modulo moduli[mod_index[i]] (host array).  Forward
+ * output is in bit-reversed evaluation order: out[i] = sum_t a_t
+ * psi^((2 brev(i) + 1) t).  For kernel tests and benchmarks. */
+vr_status vr_ntt(vr_context *ctx, uint64_t *data, uint32_t n_limbs, const uint32_t *mod_index,
+                 int inverse, void *stream);
+
+void vr_free_ciphertext(vr_ciphertext *ct);
+void vr_free_plaintext(vr_plaintext *pt);
+void vr_free_keys(vr_secret_key *sk, vr_eval_keys *ek);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* VR_H */

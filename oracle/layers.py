@@ -159,19 +159,28 @@ def conv_out_size(h, pad, k, stride):
     return (h + 2 * pad - k) // stride + 1
 
 
-def conv2d(ctx: Context, keys: Keys, cts, C_in, h, w, pad, K, bias, C_out, k, stride):
+def conv2d(ctx: Context, keys: Keys, cts, C_in, h, w, pad, K, bias, C_out, k, stride,
+           only_cols=None):
+    """All C_out * w_out outputs (index c' * w_out + j'), or, with only_cols,
+    just the outputs of those output columns j' (same order, others None)."""
     K = np.asarray(K, np.float64)
     wo = conv_out_size(w, pad, k, stride)
     level = cts[0].level
     dc = float(ctx.q[level])
     rot = [[None] * w for _ in range(C_in)]
-    for c in range(C_in):
-        for j in range(w):
+
+    def rotated(c, j):
+        if rot[c][j] is None:
             ct = cts[c * w + j]
             rot[c][j] = [ct] + ctx.rotate_many(ct, list(range(1, k)), keys)
+        return rot[c][j]
+
     out = []
     for co in range(C_out):
         for jo in range(wo):
+            if only_cols is not None and jo not in only_cols:
+                out.append(None)
+                continue
             acc = None
             for c in range(C_in):
                 for v in range(k):
@@ -179,7 +188,7 @@ def conv2d(ctx: Context, keys: Keys, cts, C_in, h, w, pad, K, bias, C_out, k, st
                     if jj < 0 or jj >= w:
                         continue
                     for u in range(k):
-                        t = ctx.mul_const(rot[c][jj][u], K[co, c, u, v], dc)
+                        t = ctx.mul_const(rotated(c, jj)[u], K[co, c, u, v], dc)
                         acc = t if acc is None else ctx.add(acc, t)
             acc = ctx.add_const(acc, float(bias[co]))
             out.append(ctx.rescale(acc))

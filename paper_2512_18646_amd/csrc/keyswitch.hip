@@ -1,0 +1,393 @@
+// Hybrid key switching (Han & Ki, CT-RSA 2020) on gfx950: ModUp by fast base
+// conversion, inner product with the switching key, ModDown.
+//
+// Base conversion (Cheon, Han, Kim, Kim, Song, SAC 2018, without correction,
+// centred remainders): for input limbs d_i mod q_i (i in a digit) and every
+// target modulus t,
+//     y_i = [d_i * Qhat_i^-1]_{q_i} (taken in (-q_i/2, q_i/2]),
+//     x_t = sum_i y_i [Qhat_i]_t = sum_i y_i' [Qhat_i]_t + n_neg [-Q]_t  (mod t)
+// where y_i' is the [0, q_i) representative and n_neg counts the y_i above
+// q_i / 2 (each contributes -q_i Qhat_i = -Q).  One thread per coefficient
+// keeps the <= 16 inputs in registers and streams the targets; the 128-bit
+// dot product is reduced once per target.
+//
+// Inner product: every extended limb e reads the beta digits of X (through the
+// Galois permutation for rotations) and the key limbs b_j, a_j once; the
+// batched form keeps the key values in registers and loops over ciphertexts
+// that share the key, so the key streams from HBM once per batch.
+#include "vr_ops.h"
+
+namespace vr {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kMaxIn = 16;
+
+__device__ __forceinline__ u32 brev_n(u32 x, u32 log_n) { return __brev(x) >> (32 - log_n); }
+
+__device__ __forceinline__ u32 galois_src(u32 i, u32 g, u32 log_n)
+{
+    u32 mask = (2u << log_n) - 1;
+    u32 e = (u32)(((u64)g * (2 * brev_n(i, log_n) + 1)) & mask);
+    return brev_n((e - 1) >> 1, log_n);
+}
+
+struct ConvArgs {
+    const u64* in;            // input limb i: in + poly * in_stride + i * N
+    u64 in_stride;
+    u64* out;                 // output o: out + poly * out_stride + slot(o) * N
+    u64 out_stride;
+    u32 skip_at, skip_len;    // slot(o) = o < skip_at ? o : o + skip_len
+    const u64* tab;
+    u32 n_in, n_out;
+    u32 log_n;
+    const ModQ* mq;
+};
+
+__global__ __launch_bounds__(kThreads) void k_base_convert(ConvArgs a)
+{
+    const u32 n = 1u << a.log_n;
+    const u32 t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const u32 poly = blockIdx.y;
+    const u64* in = a.in + (size_t)poly * a.in_stride;
+    u64* out = a.out + (size_t)poly * a.out_stride;
+    const u64* qinv = a.tab;
+    const u64* qinv_s = a.tab + a.n_in;
+    const u64* qhat = a.tab + 2 * a.n_in;
+    const u64* negq = qhat + (size_t)a.n_in * a.n_out;
+    const u64* in_mod = negq + a.n_out;
+    const u64* out_mod = in_mod + a.n_in;
+
+    u64 y[kMaxIn];
+    u64 n_neg = 0;
+#pragma unroll
+    for (int i = 0; i < kMaxIn; i++) {
+        if (i < (int)a.n_in) {
+            u64 q = a.mq[in_mod[i]].q;
+            u64 v = shoup(in[(size_t)i * n + t], qinv[i], qinv_s[i], q);
+            n_neg += v > (q >> 1) ? 1 : 0;
+            y[i] = v;
+        }
+    }
+    for (u32 o = 0; o < a.n_out; o++) {
+        const ModQ m = a.mq[out_mod[o]];
+        u64 hi = 0, lo = 0;
+        mac128(hi, lo, n_neg, negq[o]);
+#pragma unroll
+        for (int i = 0; i < kMaxIn; i++)
+            if (i < (int)a.n_in) mac128(hi, lo, y[i], qhat[(size_t)i * a.n_out + o]);
+        u32 slot = o < a.skip_at ? o : o + a.skip_len;
+        out[(size_t)slot * n + t] = reduce128(hi, lo, m);
+    }
+}
+
+template <int MAXB>
+__global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_stride, u32 n_ct,
+                                                      const u64* key, u32 nmod, u32 level,
+                                                      u32 next, u32 beta, u32 L, u32 log_n, u32 g,
+                                                      u64* U, u64 u_stride, const ModQ* mq)
+{
+    const u32 n = 1u << log_n;
+    const u32 t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const u32 e = blockIdx.y;
+    const u32 mod = e <= level ? e : L + 1 + (e - level - 1);
+    const ModQ m = mq[mod];
+    const u32 src = g == 1 ? t : galois_src(t, g, log_n);
+    u64 kb[MAXB], ka[MAXB];
+#pragma unroll
+    for (int j = 0; j < MAXB; j++) {
+        if (j < (int)beta) {
+            kb[j] = key[((size_t)(2 * j) * nmod + mod) * n + t];
+            ka[j] = key[((size_t)(2 * j + 1) * nmod + mod) * n + t];
+        }
+    }
+    for (u32 c = 0; c < n_ct; c++) {
+        const u64* x = X + (size_t)c * x_stride + (size_t)e * n + src;
+        u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+#pragma unroll
+        for (int j = 0; j < MAXB; j++) {
+            if (j < (int)beta) {
+                u64 xv = x[(size_t)j * next * n];
+                mac128(h0, l0, xv, kb[j]);
+                mac128(h1, l1, xv, ka[j]);
+            }
+        }
+        u64* u = U + (size_t)c * u_stride + (size_t)e * n + t;
+        u[0] = reduce128(h0, l0, m);
+        u[(size_t)next * n] = reduce128(h1, l1, m);
+    }
+}
+
+// out_k = (U_k - Y_k) * P^-1 (+ add_k), k = 0, 1; limb i < nq
+__global__ __launch_bounds__(kThreads) void k_moddown_finish(
+    const u64* U, u64 u_stride, const u64* Y, u32 nq, u32 next, u32 log_n, u64* out0, u64* out1,
+    u64 out_stride, const u64* add0, u32 add0_g, const u64* add1, u64 add_stride, const ModQ* mq)
+{
+    const u32 n = 1u << log_n;
+    const u32 t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const u32 i = blockIdx.y % nq;
+    const u32 c = blockIdx.y / nq;
+    const ModQ m = mq[i];
+    const u64 q = m.q;
+    const u64* u = U + (size_t)c * u_stride + (size_t)i * n + t;
+    const u64* y = Y + ((size_t)c * 2 * nq + i) * n + t;
+    u64 r0 = shoup(u[0] + q - y[0], m.pinv, m.pinv_s, q);
+    u64 r1 = shoup(u[(size_t)next * n] + q - y[(size_t)nq * n], m.pinv, m.pinv_s, q);
+    if (add0) {
+        u32 src = add0_g == 1 ? t : galois_src(t, add0_g, log_n);
+        r0 = add_mod(r0, add0[(size_t)c * add_stride + (size_t)i * n + src], q);
+    }
+    if (add1) r1 = add_mod(r1, add1[(size_t)c * add_stride + (size_t)i * n + t], q);
+    out0[(size_t)c * out_stride + (size_t)i * n + t] = r0;
+    out1[(size_t)c * out_stride + (size_t)i * n + t] = r1;
+}
+
+u64 powmod_h(u64 b, u64 e, u64 q)
+{
+    u64 r = 1 % q;
+    b %= q;
+    while (e) {
+        if (e & 1) r = (u64)((u128)r * b % q);
+        b = (u64)((u128)b * b % q);
+        e >>= 1;
+    }
+    return r;
+}
+
+// Builds the constant table for converting from moduli `in` to moduli `out`
+// (indices into ctx->mod).
+ConvTable build_table(vr_context* ctx, const std::vector<u32>& in, const std::vector<u32>& out)
+{
+    ConvTable tb;
+    tb.n_in = (u32)in.size();
+    tb.n_out = (u32)out.size();
+    if (tb.n_in > (u32)kMaxIn) throw Error(VR_EINVAL, "base conversion: too many input moduli");
+    std::vector<u64> h;
+    h.resize(2 * tb.n_in + (size_t)tb.n_in * tb.n_out + tb.n_out + tb.n_in + tb.n_out);
+    u64* qinv = h.data();
+    u64* qinv_s = qinv + tb.n_in;
+    u64* qhat = qinv_s + tb.n_in;
+    u64* negq = qhat + (size_t)tb.n_in * tb.n_out;
+    u64* in_mod = negq + tb.n_out;
+    u64* out_mod = in_mod + tb.n_in;
+    for (u32 i = 0; i < tb.n_in; i++) {
+        u64 qi = ctx->mod[in[i]];
+        u64 prod = 1;
+        for (u32 k = 0; k < tb.n_in; k++)
+            if (k != i) prod = (u64)((u128)prod * (ctx->mod[in[k]] % qi) % qi);
+        qinv[i] = powmod_h(prod, qi - 2, qi);
+        qinv_s[i] = shoup_companion(qinv[i], qi);
+        for (u32 o = 0; o < tb.n_out; o++) {
+            u64 to = ctx->mod[out[o]];
+            u64 p = 1;
+            for (u32 k = 0; k < tb.n_in; k++)
+                if (k != i) p = (u64)((u128)p * (ctx->mod[in[k]] % to) % to);
+            qhat[(size_t)i * tb.n_out + o] = p;
+        }
+        in_mod[i] = in[i];
+    }
+    for (u32 o = 0; o < tb.n_out; o++) {
+        u64 to = ctx->mod[out[o]];
+        u64 p = 1;
+        for (u32 k = 0; k < tb.n_in; k++) p = (u64)((u128)p * (ctx->mod[in[k]] % to) % to);
+        negq[o] = p ? to - p : 0;
+        out_mod[o] = out[o];
+    }
+    tb.words = h.size();
+    VR_HIP(hipMalloc(&tb.dev, tb.words * sizeof(u64)));
+    VR_HIP(hipMemcpy(tb.dev, h.data(), tb.words * sizeof(u64), hipMemcpyHostToDevice));
+    return tb;
+}
+
+const ConvTable& modup_table(vr_context* ctx, u32 level, u32 j)
+{
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto key = std::make_pair((int)level, (int)j);
+    auto it = ctx->modup_tables.find(key);
+    if (it != ctx->modup_tables.end()) return it->second;
+    u32 lo = j * ctx->alpha, hi = std::min((j + 1) * ctx->alpha, level + 1);
+    std::vector<u32> in, out;
+    for (u32 i = lo; i < hi; i++) in.push_back(i);
+    u32 next = level + 1 + ctx->K;
+    for (u32 e = 0; e < next; e++)
+        if (e < lo || e >= hi) out.push_back(ctx->ext_mod(e, level));
+    return ctx->modup_tables[key] = build_table(ctx, in, out);
+}
+
+const ConvTable& moddown_table(vr_context* ctx, u32 level)
+{
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto it = ctx->moddown_tables.find((int)level);
+    if (it != ctx->moddown_tables.end()) return it->second;
+    std::vector<u32> in, out;
+    for (u32 k = 0; k < ctx->K; k++) in.push_back(ctx->L + 1 + k);
+    for (u32 i = 0; i <= level; i++) out.push_back(i);
+    return ctx->moddown_tables[(int)level] = build_table(ctx, in, out);
+}
+
+void launch_convert(vr_context* ctx, const ConvArgs& a, u32 n_polys, hipStream_t s)
+{
+    dim3 grid((ctx->n + kThreads - 1) / kThreads, n_polys);
+    hipLaunchKernelGGL(k_base_convert, grid, dim3(kThreads), 0, s, a);
+    VR_CHECK_LAUNCH();
+}
+
+}  // namespace
+
+KsShape ks_shape(vr_context* ctx, u32 level)
+{
+    KsShape k;
+    k.level = level;
+    k.nq = level + 1;
+    k.next = level + 1 + ctx->K;
+    k.beta = (level + 1 + ctx->alpha - 1) / ctx->alpha;
+    return k;
+}
+
+size_t keyswitch_modup_scratch(vr_context* ctx, u32 level)
+{
+    KsShape k = ks_shape(ctx, level);
+    return ((size_t)k.beta * k.next + k.nq) * ctx->n;
+}
+
+size_t keyswitch_moddown_scratch(vr_context* ctx, u32 level, u32 n_ct)
+{
+    KsShape k = ks_shape(ctx, level);
+    return (size_t)n_ct * 2 * (ctx->K + k.nq) * ctx->n;
+}
+
+// d_c = d + c * d_stride: [nq][N] evaluation domain, c < n_ct.
+// X_c = X + c * beta * next * N: [beta][next][N].  coef: [n_ct][nq][N] scratch.
+void keyswitch_modup_batch(vr_context* ctx, const u64* d, u64 d_stride, u32 n_ct, u32 level,
+                           u64* X, u64* coef, hipStream_t s)
+{
+    KsShape k = ks_shape(ctx, level);
+    const u32 n = ctx->n;
+    const u64 xs = (u64)k.beta * k.next * n;
+    // coefficient form of every d_c
+    LimbSet ls = poly_limbs(const_cast<u64*>(d), coef, n_ct, k.nq, d_stride, (int)level);
+    ls.out_dense = 1;
+    ntt_inverse(ctx, ls, s);
+    for (u32 j = 0; j < k.beta; j++) {
+        u32 lo = j * ctx->alpha, hi = std::min((j + 1) * ctx->alpha, k.nq);
+        const ConvTable& tb = modup_table(ctx, level, j);
+        ConvArgs a;
+        a.in = coef + (size_t)lo * n;
+        a.in_stride = (u64)k.nq * n;
+        a.out = X + (size_t)j * k.next * n;
+        a.out_stride = xs;
+        a.skip_at = lo;
+        a.skip_len = hi - lo;
+        a.tab = tb.dev;
+        a.n_in = tb.n_in;
+        a.n_out = tb.n_out;
+        a.log_n = ctx->log_n;
+        a.mq = ctx->d_modq;
+        launch_convert(ctx, a, n_ct, s);
+        // the digit's own limbs are d itself (already in the evaluation domain)
+        launch_copy_rows(X + ((size_t)j * k.next + lo) * n, xs, d + (size_t)lo * n, d_stride,
+                         (u64)(hi - lo) * n, n_ct, s);
+    }
+    // every converted limb of every digit to the evaluation domain: per digit
+    // all limbs except the digit's own (digit_skip), the uniform count being
+    // next - alpha; a short last digit leaves alpha - last more limbs.
+    LimbSet t = poly_limbs(X, X, n_ct * k.beta, k.next - ctx->alpha, (u64)k.next * n, (int)level);
+    t.digit_skip = 1;
+    t.alpha = ctx->alpha;
+    t.beta = k.beta;
+    t.nq = k.nq;
+    ntt_forward(ctx, t, s);
+    u32 last = k.nq - (k.beta - 1) * ctx->alpha;
+    if (last < ctx->alpha) {
+        LimbSet r = poly_limbs(X + (size_t)(k.beta - 1) * k.next * n, nullptr, n_ct,
+                               ctx->alpha - last, xs, (int)level);
+        r.out = r.in;
+        r.slot0 = k.next - ctx->alpha + last;
+        ntt_forward(ctx, r, s);
+    }
+}
+
+void keyswitch_modup(vr_context* ctx, const u64* d, u32 level, u64* X, u64* coef, hipStream_t s)
+{
+    keyswitch_modup_batch(ctx, d, (u64)(level + 1) * ctx->n, 1, level, X, coef, s);
+}
+
+void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, u32 n_ct, const u64* key,
+                           u32 level, u32 g, u64* U, u64 u_stride, hipStream_t s)
+{
+    KsShape k = ks_shape(ctx, level);
+    dim3 grid((ctx->n + kThreads - 1) / kThreads, k.next);
+    if (k.beta <= 4)
+        hipLaunchKernelGGL((k_ks_inner<4>), grid, dim3(kThreads), 0, s, X, x_stride, n_ct, key,
+                           ctx->nmod(), level, k.next, k.beta, ctx->L, ctx->log_n, g, U, u_stride,
+                           ctx->d_modq);
+    else if (k.beta <= 8)
+        hipLaunchKernelGGL((k_ks_inner<8>), grid, dim3(kThreads), 0, s, X, x_stride, n_ct, key,
+                           ctx->nmod(), level, k.next, k.beta, ctx->L, ctx->log_n, g, U, u_stride,
+                           ctx->d_modq);
+    else if (k.beta <= 16)
+        hipLaunchKernelGGL((k_ks_inner<16>), grid, dim3(kThreads), 0, s, X, x_stride, n_ct, key,
+                           ctx->nmod(), level, k.next, k.beta, ctx->L, ctx->log_n, g, U, u_stride,
+                           ctx->d_modq);
+    else
+        throw Error(VR_EINVAL, "key switching: more than 16 digits");
+    VR_CHECK_LAUNCH();
+}
+
+void keyswitch_inner(vr_context* ctx, const u64* X, const u64* key, u32 level, u32 g, u64* U,
+                     hipStream_t s)
+{
+    KsShape k = ks_shape(ctx, level);
+    keyswitch_inner_batch(ctx, X, (u64)k.beta * k.next * ctx->n, 1, key, level, g, U,
+                          (u64)2 * k.next * ctx->n, s);
+}
+
+void keyswitch_moddown_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u32 level,
+                             u64* out0, u64* out1, u64 out_stride, const u64* add0, u32 add0_g,
+                             const u64* add1, u64 add_stride, u64* scratch, hipStream_t s)
+{
+    KsShape k = ks_shape(ctx, level);
+    const u32 n = ctx->n, K = ctx->K;
+    if (u_stride != (u64)2 * k.next * n) throw Error(VR_EINVAL, "moddown: U blocks must be dense");
+    u64* pcoef = scratch;                                   // [n_ct*2][K][N]
+    u64* Y = scratch + (size_t)n_ct * 2 * K * n;            // [n_ct*2][nq][N]
+    // special-prime limbs to the coefficient domain
+    LimbSet ls = poly_limbs(U, pcoef, n_ct * 2, K, (u64)k.next * n, (int)level);
+    ls.slot0 = k.nq;
+    ls.out_dense = 1;
+    ntt_inverse(ctx, ls, s);
+    const ConvTable& tb = moddown_table(ctx, level);
+    ConvArgs a;
+    a.in = pcoef;
+    a.in_stride = (u64)K * n;
+    a.out = Y;
+    a.out_stride = (u64)k.nq * n;
+    a.skip_at = 0xffffffffu;
+    a.skip_len = 0;
+    a.tab = tb.dev;
+    a.n_in = tb.n_in;
+    a.n_out = tb.n_out;
+    a.log_n = ctx->log_n;
+    a.mq = ctx->d_modq;
+    launch_convert(ctx, a, n_ct * 2, s);
+    ntt_forward(ctx, poly_limbs(Y, Y, n_ct * 2, k.nq, (u64)k.nq * n, (int)level), s);
+    dim3 grid((n + kThreads - 1) / kThreads, n_ct * k.nq);
+    hipLaunchKernelGGL(k_moddown_finish, grid, dim3(kThreads), 0, s, U, u_stride, Y, k.nq, k.next,
+                       ctx->log_n, out0, out1, out_stride, add0, add0_g, add1, add_stride,
+                       ctx->d_modq);
+    VR_CHECK_LAUNCH();
+}
+
+void keyswitch_moddown(vr_context* ctx, u64* U, u32 level, u64* out0, u64* out1, const u64* add0,
+                       u32 add0_g, const u64* add1, u64* scratch, hipStream_t s)
+{
+    KsShape k = ks_shape(ctx, level);
+    keyswitch_moddown_batch(ctx, U, (u64)2 * k.next * ctx->n, 1, level, out0, out1, 0, add0,
+                            add0_g, add1, 0, scratch, s);
+}
+
+}  // namespace vr

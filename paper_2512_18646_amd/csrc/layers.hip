@@ -1,0 +1,672 @@
+// Column-wise encodings and layer schedules, executed in batched form.
+//
+// The paper gives the column-wise method only as an idea (abstract and
+// contributions: an A(m x n).B(n x p) product with each operand as n
+// ciphertexts; an h x w image as w column ciphertexts of h slots) plus the
+// linearity argument of "Parallelized Matrix Multiplication" and the
+// per-channel sums of "Parallelized Convolution Operation".  The schedules:
+//
+//   matmul  C[idx] = Rescale(Relin(sum_k A_k * Rot(Bbar_k, idx))), idx < P'
+//           (RowShifter of "Homomorphic Matrix Multiplication" is a single
+//           rotation because P' divides M'; SumColVec becomes the sum over k)
+//   conv    Y(c', j') = Rescale(sum_{c,u,v} MulConst(Rot(col(c, s j'+v-pad), u),
+//                                K[c'][c][u][v], q_l) + AddConst(bias[c']))
+//   square  Rescale(Relin(Tensor(Y, Y)))
+//   fc      Z_o = Rescale(sum_{c,j'} MulPlain(Y, W_o,c,j')); Z_o += Rot(Z_o, 2^t);
+//           + bias
+//
+// Batched execution (the same integers as one call per operation):
+//   - all ciphertexts of a layer live in one slab [n][ncomp][level+1][N], so
+//     every kernel runs once over the whole layer;
+//   - one ModUp per input ciphertext is shared by all its rotations
+//     (hoisting), and one launch of the inner product per rotation step
+//     streams that step's key once for every ciphertext rotated by it;
+//   - the MulConst/AddConst accumulation of a whole conv layer is one kernel
+//     (each output reads its k*k*C_in rotated inputs, weights held as Shoup
+//     pairs), and so is the tensor-accumulate of the matmul and the
+//     MulPlain-accumulate of the FC layer.
+#include <cmath>
+#include <cstring>
+
+#include "eval.h"
+
+namespace vr {
+
+namespace {
+
+constexpr int kThreads = 256;
+
+// A slab of ciphertexts with uniform stride.
+struct Slab {
+    BufPtr buf;
+    u64* base = nullptr;
+    u32 n = 0, ncomp = 2, level = 0;
+    u64 stride = 0;   // words between ciphertexts
+    double scale = 1.0;
+    u64* ct(u32 i) const { return base + (size_t)i * stride; }
+};
+
+Slab new_slab(vr_context* ctx, u32 n, u32 ncomp, u32 level, double scale, hipStream_t s)
+{
+    Slab sl;
+    sl.n = n;
+    sl.ncomp = ncomp;
+    sl.level = level;
+    sl.scale = scale;
+    sl.stride = (u64)ncomp * (level + 1) * ctx->n;
+    sl.buf = dev_alloc(ctx, std::max<size_t>(1, (size_t)n * sl.stride) * sizeof(u64), s);
+    sl.base = as_u64(sl.buf);
+    return sl;
+}
+
+// Uses the ciphertexts in place when they already form a slab, else copies.
+Slab gather(vr_context* ctx, const vr_ciphertext* const* cts, u32 n, hipStream_t s)
+{
+    if (n == 0) throw Error(VR_EINVAL, "empty ciphertext list");
+    const vr_ciphertext* c0 = cts[0];
+    for (u32 i = 0; i < n; i++) {
+        if (!cts[i]) throw Error(VR_EINVAL, "null ciphertext");
+        if (cts[i]->level != c0->level) throw Error(VR_ELEVEL, "inputs at different levels");
+        if (cts[i]->scale != c0->scale) throw Error(VR_ESCALE, "inputs at different scales");
+        if (cts[i]->ncomp != c0->ncomp) throw Error(VR_EINVAL, "inputs with different sizes");
+    }
+    Slab sl;
+    sl.n = n;
+    sl.ncomp = c0->ncomp;
+    sl.level = c0->level;
+    sl.scale = c0->scale;
+    sl.stride = (u64)c0->ncomp * (c0->level + 1) * ctx->n;
+    bool contiguous = true;
+    for (u32 i = 1; i < n && contiguous; i++) contiguous = cts[i]->data == c0->data + (size_t)i * sl.stride;
+    if (contiguous) {
+        sl.buf = c0->buf;
+        sl.base = c0->data;
+        return sl;
+    }
+    sl.buf = dev_alloc(ctx, (size_t)n * sl.stride * sizeof(u64), s);
+    sl.base = as_u64(sl.buf);
+    for (u32 i = 0; i < n; i++)
+        VR_HIP(hipMemcpyAsync(sl.ct(i), cts[i]->data, sl.stride * sizeof(u64), hipMemcpyDeviceToDevice, s));
+    return sl;
+}
+
+void to_handles(vr_context* ctx, const Slab& sl, vr_ciphertext** out)
+{
+    for (u32 i = 0; i < sl.n; i++) out[i] = view_ct(ctx, sl.buf, sl.ct(i), sl.ncomp, sl.level, sl.scale);
+}
+
+// ------------------------------------------------------------- kernels
+
+struct Term {
+    u32 in_idx;   // input ciphertext (pointer table index)
+    u32 w_idx;    // weight row
+};
+
+// out[o] = sum_{terms of o} w * in  (+ bias on component 0), 2 components
+__global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride,
+                                                      const u64* const* in_ptrs, const Term* terms,
+                                                      const u32* term_off, const u64* w,
+                                                      const u64* ws, const u64* bias, u32 nl,
+                                                      u32 log_n, const ModQ* mq)
+{
+    const u32 n = 1u << log_n;
+    const u32 t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const u32 row = blockIdx.y % (2 * nl);   // component * nl + limb
+    const u32 o = blockIdx.y / (2 * nl);
+    const u32 l = row % nl;
+    const u64 q = mq[l].q, q2 = 2 * q;
+    u64 acc = 0;
+    const u32 a = term_off[o], b = term_off[o + 1];
+    for (u32 k = a; k < b; k++) {
+        Term tm = terms[k];
+        u64 x = in_ptrs[tm.in_idx][(size_t)row * n + t];
+        acc += shoup_lazy(x, w[(size_t)tm.w_idx * nl + l], ws[(size_t)tm.w_idx * nl + l], q);
+        acc = acc >= q2 ? acc - q2 : acc;
+    }
+    if (bias && row < nl) acc += bias[(size_t)o * nl + l];
+    acc = acc >= q2 ? acc - q2 : acc;
+    acc = acc >= q ? acc - q : acc;
+    out[(size_t)o * out_stride + (size_t)row * n + t] = acc;
+}
+
+// T = sum_k A_k (x) R_k: 3-component tensor accumulate over n_terms pairs
+__global__ __launch_bounds__(kThreads) void k_tensor_acc(u64* T, const u64* A, u64 a_stride,
+                                                         const u64* R, u64 r_stride, u32 n_terms,
+                                                         u32 nl, u32 log_n, const ModQ* mq)
+{
+    const u32 n = 1u << log_n;
+    const u32 t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const u32 l = blockIdx.y;
+    const ModQ m = mq[l];
+    const size_t poly = (size_t)nl * n, off = (size_t)l * n + t;
+    u64 d0 = 0, d1 = 0, d2 = 0;
+    for (u32 k = 0; k < n_terms; k++) {
+        const u64* a = A + (size_t)k * a_stride + off;
+        const u64* r = R + (size_t)k * r_stride + off;
+        u64 a0 = a[0], a1 = a[poly], b0 = r[0], b1 = r[poly];
+        d0 = add_mod(d0, mul_mod(a0, b0, m), m.q);
+        d1 = add_mod(d1, add_mod(mul_mod(a0, b1, m), mul_mod(a1, b0, m), m.q), m.q);
+        d2 = add_mod(d2, mul_mod(a1, b1, m), m.q);
+    }
+    T[off] = d0;
+    T[poly + off] = d1;
+    T[2 * poly + off] = d2;
+}
+
+// out_c (3 comps) = tensor(a_c, b_c) for n_ct ciphertext pairs
+__global__ __launch_bounds__(kThreads) void k_tensor_batch(u64* out, const u64* a, const u64* b,
+                                                           u64 in_stride, u32 nl, u32 log_n,
+                                                           const ModQ* mq)
+{
+    const u32 n = 1u << log_n;
+    const u32 t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const u32 l = blockIdx.y % nl, c = blockIdx.y / nl;
+    const ModQ m = mq[l];
+    const size_t poly = (size_t)nl * n, off = (size_t)l * n + t;
+    const u64* x = a + (size_t)c * in_stride + off;
+    const u64* y = b + (size_t)c * in_stride + off;
+    u64* o = out + (size_t)c * 3 * poly + off;
+    u64 a0 = x[0], a1 = x[poly], b0 = y[0], b1 = y[poly];
+    o[0] = mul_mod(a0, b0, m);
+    o[poly] = add_mod(mul_mod(a0, b1, m), mul_mod(a1, b0, m), m.q);
+    o[2 * poly] = mul_mod(a1, b1, m);
+}
+
+// out[o] = sum_i Y_i * P[o][i] (2 components), P plaintexts [nl_pt][N] each
+__global__ __launch_bounds__(kThreads) void k_mulplain_acc(u64* out, u64 out_stride,
+                                                           const u64* Y, u64 y_stride, u32 n_in,
+                                                           const u64* const* pts, u32 nl,
+                                                           u32 log_n, const ModQ* mq)
+{
+    const u32 n = 1u << log_n;
+    const u32 t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const u32 row = blockIdx.y % (2 * nl);
+    const u32 o = blockIdx.y / (2 * nl);
+    const u32 l = row % nl;
+    const ModQ m = mq[l];
+    u64 hi = 0, lo = 0;
+    for (u32 i = 0; i < n_in; i++) {
+        u64 y = Y[(size_t)i * y_stride + (size_t)row * n + t];
+        u64 p = pts[(size_t)o * n_in + i][(size_t)l * n + t];
+        mac128(hi, lo, y, p);
+        if ((i & 31) == 31) {   // keep the 128-bit sum below 2^127
+            lo = reduce128(hi, lo, m);
+            hi = 0;
+        }
+    }
+    out[(size_t)o * out_stride + (size_t)row * n + t] = reduce128(hi, lo, m);
+}
+
+template <class T>
+T* upload_async(vr_context* ctx, const std::vector<T>& h, BufPtr& holder, hipStream_t s)
+{
+    holder = dev_alloc(ctx, std::max<size_t>(1, h.size()) * sizeof(T), s);
+    if (!h.empty())
+        VR_HIP(hipMemcpyAsync(holder->ptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
+    return (T*)holder->ptr;
+}
+
+// Rotations of every ciphertext of `in` by every step; out[si] is a slab of
+// in.n rotated ciphertexts (step si).  One ModUp per input (hoisting), one
+// inner-product launch per step.
+void rotate_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in,
+                 const std::vector<int32_t>& steps, std::vector<Slab>& out, hipStream_t s)
+{
+    const u32 level = in.level, n_ct = in.n;
+    const size_t n = ctx->n;
+    KsShape k = ks_shape(ctx, level);
+    std::vector<u32> gs;
+    for (int32_t st : steps) {
+        u32 g = galois_element(ctx, st);
+        if (g != 1) (void)rot_key(ek, g);
+        gs.push_back(g);
+    }
+    const u64 xs = (u64)k.beta * k.next * n;
+    BufPtr xbuf = dev_alloc(ctx, ((size_t)n_ct * xs + (size_t)n_ct * k.nq * n) * sizeof(u64), s);
+    u64* X = as_u64(xbuf);
+    u64* coef = X + (size_t)n_ct * xs;
+    keyswitch_modup_batch(ctx, in.base + (size_t)k.nq * n, in.stride, n_ct, level, X, coef, s);
+    const u64 us = (u64)2 * k.next * n;
+    BufPtr ubuf = dev_alloc(ctx, ((size_t)n_ct * us + keyswitch_moddown_scratch(ctx, level, n_ct)) * sizeof(u64), s);
+    u64* U = as_u64(ubuf);
+    u64* md = U + (size_t)n_ct * us;
+    out.clear();
+    for (size_t si = 0; si < steps.size(); si++) {
+        Slab r = new_slab(ctx, n_ct, 2, level, in.scale, s);
+        if (gs[si] == 1) {
+            VR_HIP(hipMemcpyAsync(r.base, in.base, (size_t)n_ct * in.stride * sizeof(u64),
+                                  hipMemcpyDeviceToDevice, s));
+        } else {
+            keyswitch_inner_batch(ctx, X, xs, n_ct, rot_key(ek, gs[si]).data, level, gs[si], U, us, s);
+            keyswitch_moddown_batch(ctx, U, us, n_ct, level, r.base, r.base + (size_t)k.nq * n,
+                                    r.stride, in.base, gs[si], nullptr, in.stride, md, s);
+        }
+        out.push_back(r);
+    }
+}
+
+// relinearise a slab of 3-component ciphertexts into 2-component ones
+Slab relin_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& T, hipStream_t s)
+{
+    const u32 level = T.level, n_ct = T.n;
+    const size_t n = ctx->n;
+    KsShape k = ks_shape(ctx, level);
+    const u64 xs = (u64)k.beta * k.next * n, us = (u64)2 * k.next * n;
+    BufPtr xbuf = dev_alloc(ctx, ((size_t)n_ct * xs + (size_t)n_ct * k.nq * n) * sizeof(u64), s);
+    u64* X = as_u64(xbuf);
+    keyswitch_modup_batch(ctx, T.base + (size_t)2 * k.nq * n, T.stride, n_ct, level, X,
+                          X + (size_t)n_ct * xs, s);
+    BufPtr ubuf = dev_alloc(ctx, ((size_t)n_ct * us + keyswitch_moddown_scratch(ctx, level, n_ct)) * sizeof(u64), s);
+    u64* U = as_u64(ubuf);
+    keyswitch_inner_batch(ctx, X, xs, n_ct, ek->rlk.data, level, 1, U, us, s);
+    Slab out = new_slab(ctx, n_ct, 2, level, T.scale, s);
+    keyswitch_moddown_batch(ctx, U, us, n_ct, level, out.base, out.base + (size_t)k.nq * n,
+                            out.stride, T.base, 1, T.base + (size_t)k.nq * n, T.stride,
+                            U + (size_t)n_ct * us, s);
+    return out;
+}
+
+Slab rescale_slab(vr_context* ctx, const Slab& in, hipStream_t s)
+{
+    if (in.level == 0) throw Error(VR_ELEVEL, "no limb left to rescale by");
+    Slab out = new_slab(ctx, in.n, in.ncomp, in.level - 1, in.scale / (double)ctx->mod[in.level], s);
+    rescale_dense(ctx, in.base, out.base, in.n * in.ncomp, in.level, s);
+    return out;
+}
+
+Slab square_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipStream_t s)
+{
+    if (in.ncomp != 2) throw Error(VR_EINVAL, "square needs 2-component inputs");
+    const u32 nl = in.level + 1;
+    Slab T = new_slab(ctx, in.n, 3, in.level, in.scale * in.scale, s);
+    dim3 grid((ctx->n + kThreads - 1) / kThreads, in.n * nl);
+    hipLaunchKernelGGL(k_tensor_batch, grid, dim3(kThreads), 0, s, T.base, in.base, in.base,
+                       in.stride, nl, ctx->log_n, ctx->d_modq);
+    VR_CHECK_LAUNCH();
+    Slab R = relin_slab(ctx, ek, T, s);
+    return rescale_slab(ctx, R, s);
+}
+
+u32 pow2ceil(u32 x)
+{
+    u32 p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------- encodings
+
+vr_ciphertext** encrypt_slots_batch(vr_context* ctx, const vr_eval_keys* ek,
+                                    const std::vector<double>& slots, u32 n_ct, u32 level,
+                                    u64 seed, u64 first_id, vr_ciphertext** out, hipStream_t s)
+{
+    // encode every vector in one batched FFT, then encrypt each into one slab
+    const size_t n = ctx->n, S = ctx->slots;
+    const u32 nl = level + 1;
+    BufPtr xd = dev_alloc(ctx, slots.size() * sizeof(double), s);
+    VR_HIP(hipMemcpyAsync(xd->ptr, slots.data(), slots.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    BufPtr mb = dev_alloc(ctx, (size_t)n_ct * nl * n * sizeof(u64), s);
+    encode_to_limbs(ctx, (const double*)xd->ptr, (u32)S, n_ct, S, ctx->scale, as_u64(mb), nl,
+                    (u64)nl * n, s);
+    ntt_forward(ctx, poly_limbs(as_u64(mb), as_u64(mb), n_ct, nl, (u64)nl * n, (int)level), s);
+    Slab sl = new_slab(ctx, n_ct, 2, level, ctx->scale, s);
+    BufPtr ints = dev_alloc(ctx, 3 * n * sizeof(i64), s);
+    BufPtr limbs = dev_alloc(ctx, (size_t)3 * nl * n * sizeof(u64), s);
+    i64* vi = (i64*)ints->ptr;
+    u64* L3 = as_u64(limbs);
+    std::vector<u32> mods(nl);
+    for (u32 l = 0; l < nl; l++) mods[l] = l;
+    for (u32 c = 0; c < n_ct; c++) {
+        u64 id = first_id + c;
+        launch_sample_ternary(ctx, vi, seed, kPurEncV, id, s);
+        launch_sample_gauss(ctx, vi + n, seed, kPurEncE0, id, s);
+        launch_sample_gauss(ctx, vi + 2 * n, seed, kPurEncE1, id, s);
+        for (int k = 0; k < 3; k++) launch_int_to_limbs(ctx, L3 + (size_t)k * nl * n, vi + k * n, mods.data(), nl, s);
+        ntt_forward(ctx, poly_limbs(L3, L3, 3, nl, (u64)nl * n, (int)level), s);
+        launch_encrypt_combine(ctx, sl.ct(c), L3, L3 + (size_t)nl * n, L3 + (size_t)2 * nl * n,
+                               ek->pk, as_u64(mb) + (size_t)c * nl * n, nl, s);
+    }
+    to_handles(ctx, sl, out);
+    return out;
+}
+
+}  // namespace vr
+
+using namespace vr;
+
+#define API_BEGIN try {
+#define API_END                                                  \
+    }                                                            \
+    catch (const vr::Error& e)                                   \
+    {                                                            \
+        set_last_error(e.what());                                \
+        return e.code;                                           \
+    }                                                            \
+    catch (const std::bad_alloc&)                                \
+    {                                                            \
+        set_last_error("host allocation failed");                \
+        return VR_ENOMEM;                                        \
+    }                                                            \
+    catch (const std::exception& e)                              \
+    {                                                            \
+        set_last_error(e.what());                                \
+        return VR_EINVAL;                                        \
+    }                                                            \
+    return VR_OK;
+
+#define REQUIRE(cond, msg) \
+    if (!(cond)) throw Error(VR_EINVAL, msg)
+
+extern "C" {
+
+vr_status vr_encrypt_columns(vr_context* ctx, const vr_eval_keys* ek, const double* x, uint32_t B,
+                             uint32_t C, uint32_t h, uint32_t w, uint32_t pad, uint32_t level,
+                             uint64_t seed, uint64_t first_ct_id, vr_ciphertext** cols)
+{
+    if (cols)
+        for (size_t i = 0; i < (size_t)C * w; i++) cols[i] = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && x && cols, "null argument");
+    REQUIRE(B >= 1 && C >= 1 && h >= 1 && w >= 1, "empty image batch");
+    REQUIRE(level <= ctx->L, "level above the modulus chain");
+    const u32 Hp = pow2ceil(h + 2 * pad);
+    REQUIRE((size_t)B * Hp <= ctx->slots, "B * pow2(h + 2 pad) exceeds the slot count");
+    const size_t S = ctx->slots;
+    std::vector<double> slots((size_t)C * w * S, 0.0);
+    for (u32 c = 0; c < C; c++)
+        for (u32 j = 0; j < w; j++) {
+            double* z = &slots[((size_t)c * w + j) * S];
+            for (u32 b = 0; b < B; b++)
+                for (u32 i = 0; i < h; i++)
+                    z[(size_t)b * Hp + pad + i] = x[(((size_t)b * C + c) * h + i) * w + j];
+        }
+    encrypt_slots_batch(ctx, ek, slots, C * w, level, seed, first_ct_id, cols, ctx->stream);
+    VR_HIP(hipStreamSynchronize(ctx->stream));
+    API_END
+}
+
+vr_status vr_encrypt_matrix_columns(vr_context* ctx, const vr_eval_keys* ek, const double* M,
+                                    uint32_t rows, uint32_t cols, uint32_t role, uint32_t m,
+                                    uint32_t p, uint32_t level, uint64_t seed,
+                                    uint64_t first_ct_id, vr_ciphertext** out)
+{
+    const u32 n_ct = role == 0 ? cols : rows;
+    if (out)
+        for (u32 i = 0; i < n_ct; i++) out[i] = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && M && out, "null argument");
+    REQUIRE(role <= 1, "role must be 0 (A) or 1 (B)");
+    REQUIRE(rows >= 1 && cols >= 1, "empty matrix");
+    REQUIRE(role == 0 ? rows == m : cols == p, "matrix shape does not match m / p");
+    REQUIRE(level <= ctx->L, "level above the modulus chain");
+    const u32 Mp = pow2ceil(m), Pp = pow2ceil(p);
+    REQUIRE(Mp <= ctx->slots && Pp <= ctx->slots, "matrix dimension exceeds the slot count");
+    const size_t S = ctx->slots;
+    std::vector<double> slots((size_t)n_ct * S, 0.0);
+    for (u32 k = 0; k < n_ct; k++) {
+        double* z = &slots[(size_t)k * S];
+        for (size_t s = 0; s < S; s++) {
+            if (role == 0) {
+                u32 r = (u32)(s % Mp);
+                z[s] = r < m ? M[(size_t)r * cols + k] : 0.0;
+            } else {
+                u32 r = (u32)(s % Pp);
+                z[s] = r < p ? M[(size_t)k * cols + r] : 0.0;
+            }
+        }
+    }
+    encrypt_slots_batch(ctx, ek, slots, n_ct, level, seed, first_ct_id, out, ctx->stream);
+    VR_HIP(hipStreamSynchronize(ctx->stream));
+    API_END
+}
+
+vr_status vr_matmul(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* const* A,
+                    const vr_ciphertext* const* Bbar, uint32_t m, uint32_t n, uint32_t p,
+                    vr_ciphertext** C, void* stream)
+{
+    const u32 Pp = p ? pow2ceil(p) : 0;
+    if (C)
+        for (u32 i = 0; i < Pp; i++) C[i] = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && A && Bbar && C, "null argument");
+    REQUIRE(m >= 1 && n >= 1 && p >= 1, "empty matrix");
+    REQUIRE(m >= p, "matmul schedule needs m >= p (multiply the transposes)");
+    hipStream_t s = pick_stream(ctx, stream);
+    Slab sa = gather(ctx, A, n, s);
+    Slab sb = gather(ctx, Bbar, n, s);
+    REQUIRE(sa.ncomp == 2 && sb.ncomp == 2, "matmul inputs must be 2-component");
+    if (sa.level != sb.level) throw Error(VR_ELEVEL, "A and B at different levels");
+    const u32 level = sa.level, nl = level + 1;
+    std::vector<int32_t> steps;
+    for (u32 i = 1; i < Pp; i++) steps.push_back((int32_t)i);
+    for (int32_t st : steps) (void)rot_key(ek, galois_element(ctx, st));
+    Slab T = new_slab(ctx, Pp, 3, level, sa.scale * sb.scale, s);
+    // idx = 0: no rotation
+    dim3 grid((ctx->n + kThreads - 1) / kThreads, nl);
+    hipLaunchKernelGGL(k_tensor_acc, grid, dim3(kThreads), 0, s, T.ct(0), sa.base, sa.stride,
+                       sb.base, sb.stride, n, nl, ctx->log_n, ctx->d_modq);
+    VR_CHECK_LAUNCH();
+    if (Pp > 1) {
+        // hoisted ModUp of every Bbar_k, then per step one batched key switch
+        const size_t N = ctx->n;
+        KsShape k = ks_shape(ctx, level);
+        const u64 xs = (u64)k.beta * k.next * N, us = (u64)2 * k.next * N;
+        BufPtr xbuf = dev_alloc(ctx, ((size_t)n * xs + (size_t)n * k.nq * N) * sizeof(u64), s);
+        u64* X = as_u64(xbuf);
+        keyswitch_modup_batch(ctx, sb.base + (size_t)k.nq * N, sb.stride, n, level, X,
+                              X + (size_t)n * xs, s);
+        BufPtr ubuf = dev_alloc(ctx, ((size_t)n * us + keyswitch_moddown_scratch(ctx, level, n)) * sizeof(u64), s);
+        u64* U = as_u64(ubuf);
+        Slab R = new_slab(ctx, n, 2, level, sb.scale, s);
+        for (u32 idx = 1; idx < Pp; idx++) {
+            u32 g = galois_element(ctx, (int32_t)idx);
+            keyswitch_inner_batch(ctx, X, xs, n, rot_key(ek, g).data, level, g, U, us, s);
+            keyswitch_moddown_batch(ctx, U, us, n, level, R.base, R.base + (size_t)k.nq * N, R.stride,
+                                    sb.base, g, nullptr, sb.stride, U + (size_t)n * us, s);
+            hipLaunchKernelGGL(k_tensor_acc, grid, dim3(kThreads), 0, s, T.ct(idx), sa.base,
+                               sa.stride, R.base, R.stride, n, nl, ctx->log_n, ctx->d_modq);
+            VR_CHECK_LAUNCH();
+        }
+    }
+    Slab out = rescale_slab(ctx, relin_slab(ctx, ek, T, s), s);
+    to_handles(ctx, out, C);
+    API_END
+}
+
+vr_status vr_conv2d(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* const* in,
+                    uint32_t C_in, uint32_t h, uint32_t w, uint32_t pad, const double* K,
+                    const double* bias, uint32_t C_out, uint32_t k, uint32_t stride,
+                    vr_ciphertext** out, void* stream)
+{
+    const u32 wo = (k >= 1 && stride >= 1 && w + 2 * pad >= k) ? (w + 2 * pad - k) / stride + 1 : 0;
+    if (out)
+        for (size_t i = 0; i < (size_t)C_out * wo; i++) out[i] = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && in && K && bias && out, "null argument");
+    REQUIRE(C_in >= 1 && C_out >= 1 && k >= 1 && stride >= 1, "bad conv shape");
+    REQUIRE(w + 2 * pad >= k && h + 2 * pad >= k, "kernel larger than the padded image");
+    REQUIRE(pad < k, "padding must be smaller than the kernel");
+    hipStream_t s = pick_stream(ctx, stream);
+    Slab x = gather(ctx, in, C_in * w, s);
+    REQUIRE(x.ncomp == 2, "conv inputs must be 2-component");
+    REQUIRE(x.level >= 1, "conv needs a level to rescale");
+    const u32 level = x.level, nl = level + 1;
+    // rotations by 1..k-1 of every column (step 0 is the input itself)
+    std::vector<int32_t> steps;
+    for (u32 u = 1; u < k; u++) steps.push_back((int32_t)u);
+    std::vector<Slab> rot;
+    if (!steps.empty()) rotate_slab(ctx, ek, x, steps, rot, s);
+    // pointer table: input (u, c, j) at index u * C_in * w + c * w + j
+    std::vector<const u64*> ptrs((size_t)k * C_in * w);
+    for (u32 u = 0; u < k; u++)
+        for (u32 c = 0; c < C_in; c++)
+            for (u32 j = 0; j < w; j++)
+                ptrs[((size_t)u * C_in + c) * w + j] = u == 0 ? x.ct(c * w + j) : rot[u - 1].ct(c * w + j);
+    // weights as [RHA(K q_l)]_{q_i}, one row per (c', c, u, v)
+    const double dq = (double)ctx->mod[level];
+    const size_t nw = (size_t)C_out * C_in * k * k;
+    std::vector<u64> wv(nw * nl), wsv(nw * nl), bv((size_t)C_out * wo * nl);
+    for (size_t r = 0; r < nw; r++)
+        for (u32 l = 0; l < nl; l++) {
+            wv[r * nl + l] = double_to_mod(K[r] * dq, ctx->mod[l]);
+            wsv[r * nl + l] = shoup_companion(wv[r * nl + l], ctx->mod[l]);
+        }
+    const double out_scale = x.scale * dq;
+    // one bias row per output ciphertext (c', j')
+    for (u32 co = 0; co < C_out; co++)
+        for (u32 l = 0; l < nl; l++) {
+            u64 b = double_to_mod(bias[co] * out_scale, ctx->mod[l]);
+            for (u32 jo = 0; jo < wo; jo++) bv[((size_t)co * wo + jo) * nl + l] = b;
+        }
+    std::vector<Term> terms;
+    std::vector<u32> off(1, 0);
+    for (u32 co = 0; co < C_out; co++)
+        for (u32 jo = 0; jo < wo; jo++) {
+            for (u32 c = 0; c < C_in; c++)
+                for (u32 v = 0; v < k; v++) {
+                    int jj = (int)(stride * jo + v) - (int)pad;
+                    if (jj < 0 || jj >= (int)w) continue;
+                    for (u32 u = 0; u < k; u++)
+                        terms.push_back({(u32)(((size_t)u * C_in + c) * w + jj),
+                                         (u32)((((size_t)co * C_in + c) * k + u) * k + v)});
+                }
+            off.push_back((u32)terms.size());
+        }
+    BufPtr hp, ht, ho, hw, hws, hb;
+    const u64* const* dptrs = upload_async(ctx, ptrs, hp, s);
+    const Term* dterms = upload_async(ctx, terms, ht, s);
+    const u32* doff = upload_async(ctx, off, ho, s);
+    const u64* dw = upload_async(ctx, wv, hw, s);
+    const u64* dws = upload_async(ctx, wsv, hws, s);
+    const u64* db = upload_async(ctx, bv, hb, s);
+    const u32 n_out = C_out * wo;
+    Slab acc = new_slab(ctx, n_out, 2, level, out_scale, s);
+    dim3 grid((ctx->n + kThreads - 1) / kThreads, n_out * 2 * nl);
+    hipLaunchKernelGGL(k_lincomb, grid, dim3(kThreads), 0, s, acc.base, acc.stride, dptrs, dterms,
+                       doff, dw, dws, db, nl, ctx->log_n, ctx->d_modq);
+    VR_CHECK_LAUNCH();
+    Slab y = rescale_slab(ctx, acc, s);
+    // host staging vectors must outlive the async copies
+    VR_HIP(hipStreamSynchronize(s));
+    to_handles(ctx, y, out);
+    API_END
+}
+
+vr_status vr_square(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* const* in,
+                    size_t n, vr_ciphertext** out, void* stream)
+{
+    if (out)
+        for (size_t i = 0; i < n; i++) out[i] = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && in && out, "null argument");
+    REQUIRE(n >= 1, "empty input");
+    hipStream_t s = pick_stream(ctx, stream);
+    Slab x = gather(ctx, in, (u32)n, s);
+    Slab y = square_slab(ctx, ek, x, s);
+    to_handles(ctx, y, out);
+    API_END
+}
+
+vr_status vr_encode_fc_weights(vr_context* ctx, const double* W, uint32_t n_out, uint32_t C,
+                               uint32_t h_out, uint32_t w_out, uint32_t stride, uint32_t block,
+                               uint32_t level, vr_plaintext** W_pt)
+{
+    const size_t total = (size_t)n_out * C * w_out;
+    if (W_pt)
+        for (size_t i = 0; i < total; i++) W_pt[i] = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && W && W_pt, "null argument");
+    REQUIRE(n_out >= 1 && C >= 1 && h_out >= 1 && w_out >= 1 && stride >= 1, "empty FC layer");
+    REQUIRE(block >= 1 && (block & (block - 1)) == 0 && block <= ctx->slots, "block must be a power of two <= S");
+    REQUIRE((size_t)stride * (h_out - 1) < block, "rows do not fit the block");
+    REQUIRE(level <= ctx->L, "level above the modulus chain");
+    hipStream_t s = ctx->stream;
+    const size_t S = ctx->slots, N = ctx->n;
+    const u32 nl = level + 1;
+    const u32 nb = (u32)(S / block);
+    std::vector<double> slots(total * S, 0.0);
+    for (u32 o = 0; o < n_out; o++)
+        for (u32 c = 0; c < C; c++)
+            for (u32 jo = 0; jo < w_out; jo++) {
+                double* z = &slots[(((size_t)o * C + c) * w_out + jo) * S];
+                for (u32 b = 0; b < nb; b++)
+                    for (u32 i = 0; i < h_out; i++)
+                        z[(size_t)b * block + (size_t)stride * i] = W[(((size_t)o * C + c) * h_out + i) * w_out + jo];
+            }
+    const double sc = (double)ctx->mod[level];
+    BufPtr xd = dev_alloc(ctx, slots.size() * sizeof(double), s);
+    VR_HIP(hipMemcpyAsync(xd->ptr, slots.data(), slots.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    BufPtr mb = dev_alloc(ctx, total * nl * N * sizeof(u64), s);
+    encode_to_limbs(ctx, (const double*)xd->ptr, (u32)S, (u32)total, S, sc, as_u64(mb), nl,
+                    (u64)nl * N, s);
+    ntt_forward(ctx, poly_limbs(as_u64(mb), as_u64(mb), (u32)total, nl, (u64)nl * N, (int)level), s);
+    for (size_t i = 0; i < total; i++) {
+        auto* pt = new vr_plaintext;
+        pt->ctx = ctx;
+        pt->buf = mb;
+        pt->data = as_u64(mb) + i * nl * N;
+        pt->level = level;
+        pt->scale = sc;
+        W_pt[i] = pt;
+    }
+    VR_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
+vr_status vr_fc(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* const* Y, uint32_t C,
+                uint32_t w_out, const vr_plaintext* const* W_pt, const double* bias, uint32_t n_out,
+                uint32_t block, vr_ciphertext** out, void* stream)
+{
+    if (out)
+        for (u32 i = 0; i < n_out; i++) out[i] = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && Y && W_pt && bias && out, "null argument");
+    REQUIRE(C >= 1 && w_out >= 1 && n_out >= 1, "empty FC layer");
+    REQUIRE(block >= 1 && (block & (block - 1)) == 0 && block <= ctx->slots, "block must be a power of two <= S");
+    hipStream_t s = pick_stream(ctx, stream);
+    const u32 n_in = C * w_out;
+    Slab y = gather(ctx, Y, n_in, s);
+    REQUIRE(y.ncomp == 2, "FC inputs must be 2-component");
+    REQUIRE(y.level >= 1, "FC needs a level to rescale");
+    const u32 level = y.level, nl = level + 1;
+    std::vector<const u64*> pts((size_t)n_out * n_in);
+    double pscale = 0;
+    for (size_t i = 0; i < pts.size(); i++) {
+        REQUIRE(W_pt[i], "null plaintext");
+        if (W_pt[i]->level < level) throw Error(VR_ELEVEL, "weight plaintext below the input level");
+        if (i == 0) pscale = W_pt[i]->scale;
+        if (W_pt[i]->scale != pscale) throw Error(VR_ESCALE, "weight plaintexts at different scales");
+        pts[i] = W_pt[i]->data;
+    }
+    BufPtr hp;
+    const u64* const* dp = upload_async(ctx, pts, hp, s);
+    Slab acc = new_slab(ctx, n_out, 2, level, y.scale * pscale, s);
+    dim3 grid((ctx->n + kThreads - 1) / kThreads, n_out * 2 * nl);
+    hipLaunchKernelGGL(k_mulplain_acc, grid, dim3(kThreads), 0, s, acc.base, acc.stride, y.base,
+                       y.stride, n_in, dp, nl, ctx->log_n, ctx->d_modq);
+    VR_CHECK_LAUNCH();
+    Slab z = rescale_slab(ctx, acc, s);
+    // rotate-and-sum inside each block: z += Rot(z, 2^t)
+    for (u32 st = 1; st < block; st <<= 1) {
+        std::vector<Slab> r;
+        rotate_slab(ctx, ek, z, {(int32_t)st}, r, s);
+        launch_addsub(ctx, z.base, z.base, r[0].base, z.n * 2, z.level + 1, false, s);
+    }
+    // bias on the constant coefficient of c0 (every evaluation slot)
+    for (u32 o = 0; o < n_out; o++) {
+        LimbConsts kc;
+        for (u32 l = 0; l <= z.level; l++) kc.c[l] = double_to_mod(bias[o] * z.scale, ctx->mod[l]);
+        launch_add_scalar(ctx, z.ct(o), z.ct(o), z.level + 1, kc, s);
+    }
+    VR_HIP(hipStreamSynchronize(s));
+    to_handles(ctx, z, out);
+    API_END
+}
+
+}  // extern "C"

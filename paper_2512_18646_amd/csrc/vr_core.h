@@ -1,0 +1,276 @@
+// Internal header of the HIP library: device modular arithmetic, context and
+// object layouts, and the launchers every translation unit shares.
+//
+// Data layout in HBM (all uint64, limb-major, coefficient index fastest so
+// every wavefront reads 64 consecutive words of one limb):
+//   ciphertext   [ncomp][level+1][N]   evaluation (NTT) domain
+//   plaintext    [level+1][N]          evaluation domain
+//   switch key   [dnum][2][L+1+K][N]   (b_j then a_j; limbs q_0..q_L, p_0..p_{K-1})
+//   public key   [2][L+1][N]
+// Modulus index m: 0..L are the Q chain, L+1..L+K the special primes.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "../../include/vr.h"
+
+namespace vr {
+
+typedef uint64_t u64;
+typedef int64_t i64;
+typedef uint32_t u32;
+typedef unsigned __int128 u128;
+
+// Moduli per context (Q chain + special primes).  Per-limb constant tables
+// passed by value to kernels are sized by it; keep them well under the
+// kernel-argument budget (2 x 40 x 8 = 640 bytes).
+constexpr int kMaxMod = 40;
+
+// --------------------------------------------------------------- errors
+
+struct Error : std::runtime_error {
+    vr_status code;
+    Error(vr_status c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+void set_last_error(const std::string& msg);
+
+#define VR_HIP(call)                                                                       \
+    do {                                                                                   \
+        hipError_t e_ = (call);                                                            \
+        if (e_ != hipSuccess)                                                              \
+            throw ::vr::Error(VR_EDEVICE, std::string(#call " failed: ") + hipGetErrorString(e_)); \
+    } while (0)
+
+#define VR_CHECK_LAUNCH() VR_HIP(hipGetLastError())
+
+// ------------------------------------------------- per-modulus constants
+
+// Everything a kernel needs to reduce modulo one prime q < 2^61.
+struct ModQ {
+    u64 q;
+    u64 mu;      // floor(2^(2k) / q), Barrett constant for products < q^2
+    u64 r64;     // 2^64 mod q
+    u64 r64_s;   // floor(r64 * 2^64 / q)  (Shoup companion)
+    u64 one_s;   // floor(2^64 / q)
+    u64 ninv;    // N^-1 mod q
+    u64 ninv_s;
+    u64 pmod;    // P = prod of the special primes, mod q
+    u64 pmod_s;
+    u64 pinv;    // P^-1 mod q (Q-chain moduli only)
+    u64 pinv_s;
+    u32 k;       // bit length of q
+    u32 pad_;
+};
+
+__host__ __device__ inline u64 shoup_companion(u64 w, u64 q)
+{
+    return (u64)(((u128)w << 64) / q);
+}
+
+#if defined(__HIP_DEVICE_COMPILE__) || defined(__HIPCC__)
+__device__ __forceinline__ u64 mulhi64(u64 a, u64 b) { return __umul64hi(a, b); }
+
+// x * w mod q in [0, 2q) for any x < 2^64, w < q, ws = floor(w 2^64 / q).
+__device__ __forceinline__ u64 shoup_lazy(u64 x, u64 w, u64 ws, u64 q)
+{
+    return x * w - mulhi64(x, ws) * q;
+}
+
+__device__ __forceinline__ u64 csub(u64 x, u64 q) { return x >= q ? x - q : x; }
+
+__device__ __forceinline__ u64 shoup(u64 x, u64 w, u64 ws, u64 q)
+{
+    return csub(shoup_lazy(x, w, ws, q), q);
+}
+
+__device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) { return csub(a + b, q); }
+__device__ __forceinline__ u64 neg_mod(u64 a, u64 q) { return a ? q - a : 0; }
+__device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
+
+// a * b mod q for a, b < q (Barrett with k-bit shifts; remainder < 3q before
+// the two corrections).
+__device__ __forceinline__ u64 mul_mod(u64 a, u64 b, const ModQ& m)
+{
+    u64 lo = a * b;
+    u64 hi = mulhi64(a, b);
+    u32 k = m.k;
+    u64 x1 = (hi << (65 - k)) | (lo >> (k - 1));
+    u64 plo = x1 * m.mu;
+    u64 phi = mulhi64(x1, m.mu);
+    u64 q1 = (phi << (63 - k)) | (plo >> (k + 1));
+    u64 r = lo - q1 * m.q;
+    r = csub(r, m.q);
+    return csub(r, m.q);
+}
+
+// (hi 2^64 + lo) mod q for any 128-bit value: hi * (2^64 mod q) + lo, each
+// reduced with a Shoup product.
+__device__ __forceinline__ u64 reduce128(u64 hi, u64 lo, const ModQ& m)
+{
+    u64 r = shoup_lazy(hi, m.r64, m.r64_s, m.q) + shoup_lazy(lo, 1, m.one_s, m.q);
+    r = csub(r, 2 * m.q);
+    return csub(r, m.q);
+}
+
+// any 64-bit value mod q
+__device__ __forceinline__ u64 red64(u64 x, const ModQ& m)
+{
+    return csub(shoup_lazy(x, 1, m.one_s, m.q), m.q);
+}
+
+// 128-bit accumulator helpers
+__device__ __forceinline__ void mac128(u64& hi, u64& lo, u64 a, u64 b)
+{
+    u64 plo = a * b;
+    u64 phi = mulhi64(a, b);
+    lo += plo;
+    hi += phi + (lo < plo ? 1 : 0);
+}
+#endif
+
+// ----------------------------------------------------------- context
+
+// Device memory owned through shared pointers (ciphertext views into one slab
+// keep the slab alive).  Freed stream-ordered on the stream it was allocated
+// on, by the allocator that made it.
+struct DevBuf {
+    void* ptr = nullptr;
+    size_t bytes = 0;
+    hipStream_t stream = nullptr;
+    void (*free_fn)(void*, void*, void*) = nullptr;
+    void* free_user = nullptr;
+    ~DevBuf();
+};
+typedef std::shared_ptr<DevBuf> BufPtr;
+
+// Base-conversion constants for one (input set -> output set) conversion.
+struct ConvTable {
+    u32 n_in = 0, n_out = 0;
+    u64* dev = nullptr;    // device: [n_in] qhat_inv, [n_in] qhat_inv_s, [n_in][n_out] qhat mod t,
+                           //         [n_out] (-Q) mod t, then u32 in_mod[n_in], out_mod[n_out]
+    size_t words = 0;
+};
+
+}  // namespace vr
+
+struct vr_context {
+    int device = 0;
+    vr::u32 log_n = 0, n = 0, slots = 0;
+    vr::u32 L = 0, K = 0, dnum = 0, alpha = 0;
+    double scale = 1.0;
+    bool secure = false;
+    std::vector<vr::u64> mod;         // q_0..q_L, p_0..p_{K-1}
+    std::vector<vr::ModQ> modq;       // host copy
+    vr::ModQ* d_modq = nullptr;
+    vr::u64* d_tw = nullptr;          // [nmod][N] psi^brev(k)
+    vr::u64* d_tw_s = nullptr;
+    vr::u64* d_itw = nullptr;         // [nmod][N] psi^-brev(k)
+    vr::u64* d_itw_s = nullptr;
+    double* d_fft_tw = nullptr;       // [N] complex e^{-2 pi i k / 2N}
+    int* d_gexp = nullptr;            // [S] 5^j mod 2N
+    vr::u64 cdt[20];
+    std::map<std::pair<int, int>, vr::ConvTable> modup_tables;   // (level, digit)
+    std::map<int, vr::ConvTable> moddown_tables;                 // level
+    std::mutex mu;
+    hipStream_t stream = nullptr;     // used when a call passes stream = NULL
+    void* (*alloc_fn)(size_t, void*, void*) = nullptr;
+    void (*free_fn)(void*, void*, void*) = nullptr;
+    void* alloc_user = nullptr;
+
+    vr::u32 nmod() const { return L + 1 + K; }
+    // modulus index of extended limb e at level lv (limbs q_0..q_lv, p_0..)
+    vr::u32 ext_mod(vr::u32 e, vr::u32 lv) const { return e <= lv ? e : L + 1 + (e - lv - 1); }
+};
+
+struct vr_ciphertext {
+    vr_context* ctx = nullptr;
+    vr::BufPtr buf;
+    vr::u64* data = nullptr;     // [ncomp][level+1][N]
+    vr::u32 ncomp = 2, level = 0;
+    double scale = 1.0;
+};
+
+struct vr_plaintext {
+    vr_context* ctx = nullptr;
+    vr::BufPtr buf;
+    vr::u64* data = nullptr;     // [level+1][N]
+    vr::u32 level = 0;
+    double scale = 1.0;
+};
+
+struct vr_secret_key {
+    vr_context* ctx = nullptr;
+    vr::BufPtr buf;
+    vr::u64* s = nullptr;        // [L+1+K][N] evaluation domain
+};
+
+struct vr_switch_key {
+    vr::BufPtr buf;
+    vr::u64* data = nullptr;     // [dnum][2][L+1+K][N]
+};
+
+struct vr_eval_keys {
+    vr_context* ctx = nullptr;
+    vr::BufPtr pk_buf;
+    vr::u64* pk = nullptr;       // [2][L+1][N]  (b, a)
+    vr_switch_key rlk;
+    std::map<vr::u32, vr_switch_key> rot;   // Galois element -> key
+};
+
+namespace vr {
+
+// ----------------------------------------------------------- memory
+
+BufPtr dev_alloc(vr_context* ctx, size_t bytes, hipStream_t s);
+inline u64* as_u64(const BufPtr& b) { return (u64*)b->ptr; }
+
+// ----------------------------------------------------------- launchers
+
+// A set of limbs to transform: limb r (0 <= r < per_poly * n_polys) belongs
+// to poly r / per_poly and sits at slot
+//   slot = slot0 + (l < skip_at ? l : l + skip_len),   l = r % per_poly,
+// i.e. at in + poly * poly_stride + slot * N, with modulus index
+//   slot <= level ? slot : L + 1 + slot - level - 1
+// (level = -1 puts every slot on the special primes).  With digit_skip the
+// skipped range is the Q limbs of digit (poly % beta) (ModUp targets).  The
+// output goes to the same place in `out`, or densely to out + r * N when
+// out_dense is set.
+struct LimbSet {
+    u64* in = nullptr;
+    u64* out = nullptr;          // may equal in
+    u64 poly_stride = 0;         // elements
+    u32 per_poly = 0;            // limbs transformed per poly
+    u32 n_polys = 0;
+    int level = 0;
+    u32 slot0 = 0;
+    u32 skip_at = 0xffffffffu, skip_len = 0;
+    u32 digit_skip = 0, alpha = 0, beta = 0, nq = 0;
+    u32 out_dense = 0;
+};
+
+void ntt_forward(vr_context* ctx, const LimbSet& ls, hipStream_t s);
+void ntt_inverse(vr_context* ctx, const LimbSet& ls, hipStream_t s);
+
+inline LimbSet poly_limbs(u64* in, u64* out, u32 n_polys, u32 per_poly, u64 poly_stride, int level)
+{
+    LimbSet ls;
+    ls.in = in;
+    ls.out = out;
+    ls.n_polys = n_polys;
+    ls.per_poly = per_poly;
+    ls.poly_stride = poly_stride;
+    ls.level = level;
+    return ls;
+}
+
+}  // namespace vr

@@ -1,0 +1,115 @@
+// Launchers for the element-wise, rescale, automorphism, base-conversion,
+// key-switching, sampling and FFT kernels.  All polynomials are in the
+// evaluation domain unless a name says "coef".  `nl` is the number of limbs
+// per polynomial (level + 1 for Q-chain polynomials); limb l of every poly
+// uses modulus index l.
+#pragma once
+
+#include "vr_core.h"
+
+namespace vr {
+
+// per-limb scalar constants with Shoup companions (kernel argument)
+struct LimbConsts {
+    u64 c[kMaxMod];
+    u64 cs[kMaxMod];
+};
+
+// out = a (+|-) b over n_polys x nl limbs (dense [n_polys][nl][N]).
+void launch_addsub(vr_context* ctx, u64* out, const u64* a, const u64* b, u32 n_polys, u32 nl,
+                   bool sub, hipStream_t s);
+// out[p][l] = a[p][l] * c[l]  (Shoup)
+void launch_mul_scalar(vr_context* ctx, u64* out, const u64* a, u32 n_polys, u32 nl,
+                       const LimbConsts& c, hipStream_t s);
+// out[l] = a[l] + c[l] on every slot of one polynomial
+void launch_add_scalar(vr_context* ctx, u64* out, const u64* a, u32 nl, const LimbConsts& c,
+                       hipStream_t s);
+// out[p][l] = a[p][l] * pt[l]
+void launch_mul_plain(vr_context* ctx, u64* out, const u64* a, const u64* pt, u32 n_polys, u32 nl,
+                      hipStream_t s);
+// out (3 polys) = (a0 b0, a0 b1 + a1 b0, a1 b1)
+void launch_tensor(vr_context* ctx, u64* out, const u64* a, const u64* b, u32 nl, hipStream_t s);
+// out[l] = a[perm_g(l slots)] : Galois automorphism X -> X^g in the evaluation domain
+void launch_automorphism(vr_context* ctx, u64* out, const u64* a, u32 n_polys, u32 nl,
+                         u64 poly_stride, u32 g, hipStream_t s);
+// coef[k] (centred modulo q_level) -> r[k][i] = [coef]_{q_i}, i < level (dense)
+void launch_rescale_spread(vr_context* ctx, u64* r, const u64* coef, u32 n_polys, u32 level,
+                           hipStream_t s);
+// out[k][i] = (c[k][i] - r[k][i]) * q_level^-1, i < level
+void launch_rescale_finish(vr_context* ctx, u64* out, const u64* c, const u64* r, u32 n_polys,
+                           u32 level, hipStream_t s);
+// rows x width words: dst + r * dst_stride <- src + r * src_stride (device to device)
+void launch_copy_rows(u64* dst, u64 dst_stride, const u64* src, u64 src_stride, u64 width, u32 rows,
+                      hipStream_t s);
+// signed integer coefficients x[N] -> limbs [n_mods][N] at modulus indices mods[]
+void launch_int_to_limbs(vr_context* ctx, u64* out, const i64* x, const u32* mods_host, u32 n_mods,
+                         hipStream_t s);
+
+// ---------------------------------------------------------- key switching
+
+// Scratch needed by one key switch at `level` (bytes).
+struct KsShape {
+    u32 level, nq, next, beta;
+};
+KsShape ks_shape(vr_context* ctx, u32 level);
+
+// ModUp of d (evaluation domain, nq limbs): X = [beta][next][N] extended digits
+// in the evaluation domain.  Uses `coef` ([nq][N]) as scratch.
+void keyswitch_modup(vr_context* ctx, const u64* d, u32 level, u64* X, u64* coef, hipStream_t s);
+// Batched ModUp: d_c = d + c*d_stride (c < n_ct), X_c = X + c*beta*next*N,
+// coef: [n_ct][nq][N] scratch.
+void keyswitch_modup_batch(vr_context* ctx, const u64* d, u64 d_stride, u32 n_ct, u32 level,
+                           u64* X, u64* coef, hipStream_t s);
+// U = [2][next][N]: sum_j sigma_g(X_j) * (b_j, a_j) (g = 1: no automorphism).
+void keyswitch_inner(vr_context* ctx, const u64* X, const u64* key, u32 level, u32 g, u64* U,
+                     hipStream_t s);
+// Batched inner product: n_ct digit sets X + c*x_stride share one key read.
+void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, u32 n_ct, const u64* key,
+                           u32 level, u32 g, u64* U, u64 u_stride, hipStream_t s);
+// ModDown of U ([2][next][N]) to out0/out1 (nq limbs each, may be strided),
+// adding add0 (optionally through sigma_g) and add1 when non-null.
+void keyswitch_moddown(vr_context* ctx, u64* U, u32 level, u64* out0, u64* out1, const u64* add0,
+                       u32 add0_g, const u64* add1, u64* scratch, hipStream_t s);
+// Batched ModDown: n_ct independent U blocks (u_stride apart), outputs out0 +
+// c*out_stride etc.
+void keyswitch_moddown_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u32 level,
+                             u64* out0, u64* out1, u64 out_stride, const u64* add0, u32 add0_g,
+                             const u64* add1, u64 add_stride, u64* scratch, hipStream_t s);
+// scratch sizes in u64 words
+size_t keyswitch_modup_scratch(vr_context* ctx, u32 level);     // X + coef
+size_t keyswitch_moddown_scratch(vr_context* ctx, u32 level, u32 n_ct);
+
+// ---------------------------------------------------------- sampling
+
+enum Purpose : u32 {
+    kPurSk = 1, kPurPkA = 2, kPurPkE = 3, kPurSwkA = 4, kPurSwkE = 5,
+    kPurEncV = 6, kPurEncE0 = 7, kPurEncE1 = 8
+};
+void launch_sample_ternary(vr_context* ctx, i64* out, u64 seed, u32 purpose, u64 obj, hipStream_t s);
+void launch_sample_gauss(vr_context* ctx, i64* out, u64 seed, u32 purpose, u64 obj, hipStream_t s);
+// limbs [n][N] (coefficient domain): limb i uses stream limb index limb_index[i]
+// and modulus index mods[i]
+void launch_sample_uniform(vr_context* ctx, u64* out, u64 seed, u32 purpose, u64 obj,
+                           const u32* limb_index_host, const u32* mods_host, u32 n, hipStream_t s);
+
+// keygen / encryption combiners (evaluation domain)
+// b = -a*s + e (+ [P]_q * sp on limbs in [dlo, dhi)); limb l is modulus index l
+void launch_key_combine(vr_context* ctx, u64* b, const u64* a, const u64* e, const u64* s_all,
+                        const u64* sp_all, u32 n, u32 dlo, u32 dhi, hipStream_t st);
+// c0 = v*pk_b + e0 + m, c1 = v*pk_a + e1 over nl limbs
+void launch_encrypt_combine(vr_context* ctx, u64* ct, const u64* v, const u64* e0, const u64* e1,
+                            const u64* pk, const u64* m, u32 nl, hipStream_t s);
+// m = c0 + c1 s (+ c2 s^2)
+void launch_decrypt_combine(vr_context* ctx, u64* m, const u64* ct, u32 ncomp, const u64* s_all,
+                            u32 nl, hipStream_t s);
+
+// ---------------------------------------------------------- encode / decode
+
+// slots x[n] (n <= S) at `scale` -> integer coefficients reduced into nl limbs (coefficient domain)
+void encode_to_limbs(vr_context* ctx, const double* x_dev, u32 n, u32 n_vec, u64 vec_stride_x,
+                     double scale, u64* limbs, u32 nl, u64 limbs_stride, hipStream_t s);
+// limb q_0 coefficients (coefficient domain) -> slots out[n] / scale
+void decode_from_limb0(vr_context* ctx, const u64* coef0, double scale, double* out_dev, u32 n,
+                       hipStream_t s);
+
+}  // namespace vr

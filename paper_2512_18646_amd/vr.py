@@ -1,0 +1,409 @@
+"""Thin ctypes binding of include/vr.h (argument marshalling only).
+
+Every operation runs in libvr.so's HIP kernels; this module converts numpy
+arrays and Python numbers to C arguments and wraps handles so that they are
+freed with the matching vr_free_* call.  There is no CPU fallback: without the
+built library (python -m paper_2512_18646_amd.build) or without a gfx950
+device, loading or creating a context raises.
+
+PyTorch, when importable, is imported before the library so the process holds
+a single HIP runtime, and torch's current stream can be passed as `stream`.
+"""
+import ctypes
+import os
+
+import numpy as np
+
+try:  # one HIP runtime per process: torch's, when torch is present
+    import torch  # noqa: F401
+    _HAVE_TORCH = True
+except Exception:  # pragma: no cover
+    _HAVE_TORCH = False
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libvr.so")
+
+VR_OK, VR_EINVAL, VR_ESECURITY, VR_ELEVEL, VR_ESCALE, VR_ENOKEY, VR_ENOMEM, VR_EDEVICE, VR_EBUSY, \
+    VR_ECANCELED = 0, -1, -2, -3, -4, -5, -6, -7, -8, -9
+_NAMES = {VR_EINVAL: "EINVAL", VR_ESECURITY: "ESECURITY", VR_ELEVEL: "ELEVEL", VR_ESCALE: "ESCALE",
+          VR_ENOKEY: "ENOKEY", VR_ENOMEM: "ENOMEM", VR_EDEVICE: "EDEVICE", VR_EBUSY: "EBUSY",
+          VR_ECANCELED: "ECANCELED"}
+
+
+class VRError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("%s (%d): %s" % (_NAMES.get(code, "?"), code, msg))
+        self.code = code
+
+
+class vr_params(ctypes.Structure):
+    _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("n_p", ctypes.c_uint32),
+                ("dnum", ctypes.c_uint32), ("q_bits", ctypes.POINTER(ctypes.c_uint32)),
+                ("p_bits", ctypes.POINTER(ctypes.c_uint32)), ("log2_scale", ctypes.c_double),
+                ("sigma", ctypes.c_double), ("allow_insecure", ctypes.c_uint32)]
+
+
+P = ctypes.c_void_p
+PP = ctypes.POINTER(ctypes.c_void_p)
+U32, U64, I32, DBL, SZ = ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int32, ctypes.c_double, ctypes.c_size_t
+
+# name -> argument types (all return vr_status unless listed in _VOID)
+_SIGS = {
+    "vr_context_create": [ctypes.POINTER(vr_params), ctypes.c_int, PP],
+    "vr_context_moduli": [P, P, SZ],
+    "vr_context_info": [P, P, ctypes.POINTER(DBL)],
+    "vr_context_set_stream": [P, P],
+    "vr_context_set_allocator": [P, P, P, P],
+    "vr_keygen": [P, U64, P, SZ, PP, PP],
+    "vr_keys_add_rotations": [P, P, P, U64, P, SZ],
+    "vr_encode": [P, P, SZ, U32, DBL, PP],
+    "vr_encrypt": [P, P, P, U64, U64, PP],
+    "vr_encrypt_columns": [P, P, P, U32, U32, U32, U32, U32, U32, U64, U64, PP],
+    "vr_encrypt_matrix_columns": [P, P, P, U32, U32, U32, U32, U32, U32, U64, U64, PP],
+    "vr_decrypt": [P, P, P, PP],
+    "vr_decode": [P, P, P, SZ],
+    "vr_add": [P, P, P, PP, P],
+    "vr_sub": [P, P, P, PP, P],
+    "vr_mul_const": [P, P, DBL, DBL, PP, P],
+    "vr_add_const": [P, P, DBL, PP, P],
+    "vr_mul_plain": [P, P, P, PP, P],
+    "vr_tensor": [P, P, P, PP, P],
+    "vr_relinearize": [P, P, P, PP, P],
+    "vr_mul": [P, P, P, P, PP, P],
+    "vr_rescale": [P, P, PP, P],
+    "vr_mod_drop": [P, P, U32, PP, P],
+    "vr_rotate": [P, P, P, I32, PP, P],
+    "vr_rotate_many": [P, P, P, P, SZ, PP, P],
+    "vr_matmul": [P, P, PP, PP, U32, U32, U32, PP, P],
+    "vr_conv2d": [P, P, PP, U32, U32, U32, U32, P, P, U32, U32, U32, PP, P],
+    "vr_square": [P, P, PP, SZ, PP, P],
+    "vr_fc": [P, P, PP, U32, U32, PP, P, U32, U32, PP, P],
+    "vr_encode_fc_weights": [P, P, U32, U32, U32, U32, U32, U32, U32, PP],
+    "vr_ct_export": [P, P, P, SZ, P, P, P],
+    "vr_ct_import": [P, P, U32, U32, DBL, PP],
+    "vr_pt_export": [P, P, P, SZ, P, P],
+    "vr_pt_import": [P, P, U32, DBL, PP],
+    "vr_sk_export": [P, P, P, SZ],
+    "vr_ct_meta": [P, P, P, P],
+    "vr_swk_export": [P, P, U32, P, SZ],
+    "vr_ntt": [P, P, U32, P, ctypes.c_int, P],
+    "vr_context_destroy": [P],
+    "vr_free_ciphertext": [P],
+    "vr_free_plaintext": [P],
+    "vr_free_keys": [P, P],
+    "vr_last_error": [],
+}
+_VOID = {"vr_context_destroy", "vr_free_ciphertext", "vr_free_plaintext", "vr_free_keys"}
+
+
+def _load():
+    if not os.path.exists(_LIB_PATH):
+        raise ImportError("libvr.so is not built: run `python -m paper_2512_18646_amd.build` "
+                          "(the product path has no CPU fallback)")
+    lib = ctypes.CDLL(_LIB_PATH)
+    for name, args in _SIGS.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = None if name in _VOID else (ctypes.c_char_p if name == "vr_last_error" else ctypes.c_int)
+    return lib
+
+
+lib = _load()
+
+
+def exported_symbols():
+    return sorted(_SIGS)
+
+
+def _check(rc):
+    if rc != VR_OK:
+        raise VRError(rc, (lib.vr_last_error() or b"").decode())
+
+
+def _stream(stream):
+    if stream is None:
+        return None
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream   # torch.cuda.Stream
+
+
+def _ptr_array(handles):
+    arr = (ctypes.c_void_p * max(1, len(handles)))()
+    for i, h in enumerate(handles):
+        arr[i] = h.h if hasattr(h, "h") else h
+    return arr
+
+
+def _f64(x):
+    return np.ascontiguousarray(np.asarray(x, dtype=np.float64))
+
+
+# ------------------------------------------------------------------ handles
+
+class Ciphertext:
+    __slots__ = ("h", "ctx")
+
+    def __init__(self, h, ctx):
+        self.h, self.ctx = h, ctx
+
+    def __del__(self):
+        if self.h:
+            lib.vr_free_ciphertext(self.h)
+            self.h = None
+
+    @property
+    def meta(self):
+        nc, lv, sc = U32(), U32(), DBL()
+        _check(lib.vr_ct_meta(self.h, ctypes.byref(nc), ctypes.byref(lv), ctypes.byref(sc)))
+        return nc.value, lv.value, sc.value
+
+    @property
+    def level(self):
+        return self.meta[1]
+
+    @property
+    def scale(self):
+        return self.meta[2]
+
+    def export(self):
+        """Coefficient-domain limbs, uint64 [ncomp][level+1][N] (synchronises)."""
+        nc, lv, _ = self.meta
+        out = np.empty((nc, lv + 1, self.ctx.n), dtype=np.uint64)
+        _check(lib.vr_ct_export(self.ctx.h, self.h, out.ctypes.data, out.size, None, None, None))
+        return out
+
+
+class Plaintext:
+    __slots__ = ("h", "ctx", "level", "scale")
+
+    def __init__(self, h, ctx, level, scale):
+        self.h, self.ctx, self.level, self.scale = h, ctx, level, scale
+
+    def __del__(self):
+        if self.h:
+            lib.vr_free_plaintext(self.h)
+            self.h = None
+
+    def export(self):
+        out = np.empty((self.level + 1, self.ctx.n), dtype=np.uint64)
+        _check(lib.vr_pt_export(self.ctx.h, self.h, out.ctypes.data, out.size, None, None))
+        return out
+
+
+class Keys:
+    def __init__(self, sk, ek, ctx):
+        self.sk, self.ek, self.ctx = sk, ek, ctx
+
+    def __del__(self):
+        if self.sk or self.ek:
+            lib.vr_free_keys(self.sk, self.ek)
+            self.sk = self.ek = None
+
+    def secret_coeffs(self):
+        out = np.empty(self.ctx.n, dtype=np.int8)
+        _check(lib.vr_sk_export(self.ctx.h, self.sk, out.ctypes.data, self.ctx.n))
+        return out
+
+    def switching_key(self, galois=0):
+        """Coefficient-domain key [dnum][2][n_q + n_p][N] (galois 0: relinearisation)."""
+        c = self.ctx
+        out = np.empty((c.dnum, 2, len(c.q) + len(c.p), c.n), dtype=np.uint64)
+        _check(lib.vr_swk_export(c.h, self.ek, galois, out.ctypes.data, out.size))
+        return out
+
+    def add_rotations(self, seed, steps):
+        st = np.ascontiguousarray(np.asarray(steps, dtype=np.int32))
+        _check(lib.vr_keys_add_rotations(self.ctx.h, self.sk, self.ek, seed, st.ctypes.data, st.size))
+
+
+class Context:
+    """RNS-CKKS context on one GPU (see vr_context_create)."""
+
+    def __init__(self, log_n, q_bits, p_bits, dnum, log2_scale, sigma=3.2, allow_insecure=False,
+                 device=0):
+        qb = (U32 * len(q_bits))(*q_bits)
+        pb = (U32 * len(p_bits))(*p_bits)
+        prm = vr_params(log_n, len(q_bits), len(p_bits), dnum, qb, pb, log2_scale, sigma,
+                        1 if allow_insecure else 0)
+        h = ctypes.c_void_p()
+        _check(lib.vr_context_create(ctypes.byref(prm), device, ctypes.byref(h)))
+        self.h = h.value
+        info = (U32 * 8)()
+        sc = DBL()
+        _check(lib.vr_context_info(self.h, info, ctypes.byref(sc)))
+        self.log_n, self.slots, n_q, n_p, self.dnum, self.alpha, secure, self.total_bits = list(info)
+        self.n = 1 << self.log_n
+        self.secure = bool(secure)
+        self.scale = sc.value
+        mods = np.zeros(n_q + n_p, dtype=np.uint64)
+        _check(lib.vr_context_moduli(self.h, mods.ctypes.data, mods.size))
+        self.q = [int(x) for x in mods[:n_q]]
+        self.p = [int(x) for x in mods[n_q:]]
+        self.L = n_q - 1
+
+    @classmethod
+    def from_params(cls, p, device=0):
+        """From any object with log_n, q_bits, p_bits, dnum, log2_scale, allow_insecure."""
+        return cls(p.log_n, list(p.q_bits), list(p.p_bits), p.dnum, p.log2_scale,
+                   allow_insecure=getattr(p, "allow_insecure", False), device=device)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            lib.vr_context_destroy(self.h)
+            self.h = None
+
+    def set_stream(self, stream):
+        _check(lib.vr_context_set_stream(self.h, _stream(stream)))
+
+    # ------------------------------------------------------------ client
+    def keygen(self, seed, rot_steps=()):
+        st = np.ascontiguousarray(np.asarray(list(rot_steps), dtype=np.int32))
+        sk, ek = ctypes.c_void_p(), ctypes.c_void_p()
+        _check(lib.vr_keygen(self.h, seed, st.ctypes.data if st.size else None, st.size,
+                             ctypes.byref(sk), ctypes.byref(ek)))
+        return Keys(sk.value, ek.value, self)
+
+    def encode(self, x, level, scale=None):
+        x = _f64(x)
+        scale = self.scale if scale is None else float(scale)
+        h = ctypes.c_void_p()
+        _check(lib.vr_encode(self.h, x.ctypes.data if x.size else None, x.size, level, scale, ctypes.byref(h)))
+        return Plaintext(h.value, self, level, scale)
+
+    def encrypt(self, keys, pt, seed, ct_id):
+        h = ctypes.c_void_p()
+        _check(lib.vr_encrypt(self.h, keys.ek, pt.h, seed, ct_id, ctypes.byref(h)))
+        return Ciphertext(h.value, self)
+
+    def encrypt_columns(self, keys, X, pad, level, seed, first_ct_id):
+        X = _f64(X)
+        B, C, h, w = X.shape
+        arr = (ctypes.c_void_p * (C * w))()
+        _check(lib.vr_encrypt_columns(self.h, keys.ek, X.ctypes.data, B, C, h, w, pad, level, seed,
+                                      first_ct_id, arr))
+        return [Ciphertext(arr[i], self) for i in range(C * w)]
+
+    def encrypt_matrix_columns(self, keys, M, role, m, p, level, seed, first_ct_id):
+        M = _f64(M)
+        rows, cols = M.shape
+        n = cols if role == 0 else rows
+        arr = (ctypes.c_void_p * n)()
+        _check(lib.vr_encrypt_matrix_columns(self.h, keys.ek, M.ctypes.data, rows, cols, role, m, p,
+                                             level, seed, first_ct_id, arr))
+        return [Ciphertext(arr[i], self) for i in range(n)]
+
+    def decrypt(self, keys, ct):
+        h = ctypes.c_void_p()
+        _check(lib.vr_decrypt(self.h, keys.sk, ct.h, ctypes.byref(h)))
+        _, lv, sc = ct.meta
+        return Plaintext(h.value, self, lv, sc)
+
+    def decode(self, pt, n=None):
+        n = self.slots if n is None else n
+        out = np.empty(n, dtype=np.float64)
+        _check(lib.vr_decode(self.h, pt.h, out.ctypes.data, n))
+        return out
+
+    # ------------------------------------------------------------ server
+    def _unary(self, fn, *args, stream=None):
+        h = ctypes.c_void_p()
+        _check(fn(self.h, *args, ctypes.byref(h), _stream(stream)))
+        return Ciphertext(h.value, self)
+
+    def add(self, a, b, stream=None):
+        return self._unary(lib.vr_add, a.h, b.h, stream=stream)
+
+    def sub(self, a, b, stream=None):
+        return self._unary(lib.vr_sub, a.h, b.h, stream=stream)
+
+    def mul_const(self, a, c, c_scale, stream=None):
+        return self._unary(lib.vr_mul_const, a.h, float(c), float(c_scale), stream=stream)
+
+    def add_const(self, a, c, stream=None):
+        return self._unary(lib.vr_add_const, a.h, float(c), stream=stream)
+
+    def mul_plain(self, a, pt, stream=None):
+        return self._unary(lib.vr_mul_plain, a.h, pt.h, stream=stream)
+
+    def tensor(self, a, b, stream=None):
+        return self._unary(lib.vr_tensor, a.h, b.h, stream=stream)
+
+    def relinearize(self, keys, a, stream=None):
+        return self._unary(lib.vr_relinearize, keys.ek, a.h, stream=stream)
+
+    def mul(self, keys, a, b, stream=None):
+        return self._unary(lib.vr_mul, keys.ek, a.h, b.h, stream=stream)
+
+    def rescale(self, a, stream=None):
+        return self._unary(lib.vr_rescale, a.h, stream=stream)
+
+    def mod_drop(self, a, level, stream=None):
+        return self._unary(lib.vr_mod_drop, a.h, level, stream=stream)
+
+    def rotate(self, keys, a, step, stream=None):
+        return self._unary(lib.vr_rotate, keys.ek, a.h, int(step), stream=stream)
+
+    def rotate_many(self, keys, a, steps, stream=None):
+        st = np.ascontiguousarray(np.asarray(list(steps), dtype=np.int32))
+        arr = (ctypes.c_void_p * max(1, st.size))()
+        _check(lib.vr_rotate_many(self.h, keys.ek, a.h, st.ctypes.data, st.size, arr, _stream(stream)))
+        return [Ciphertext(arr[i], self) for i in range(st.size)]
+
+    # ------------------------------------------------------------ layers
+    def matmul(self, keys, A, Bbar, m, n, p, stream=None):
+        Pp = 1
+        while Pp < p:
+            Pp *= 2
+        arr = (ctypes.c_void_p * Pp)()
+        _check(lib.vr_matmul(self.h, keys.ek, _ptr_array(A), _ptr_array(Bbar), m, n, p, arr,
+                             _stream(stream)))
+        return [Ciphertext(arr[i], self) for i in range(Pp)]
+
+    def conv2d(self, keys, cols, C_in, h, w, pad, K, bias, stride, stream=None):
+        K = _f64(K)
+        bias = _f64(bias)
+        C_out, _, k, _ = K.shape
+        wo = (w + 2 * pad - k) // stride + 1
+        arr = (ctypes.c_void_p * (C_out * wo))()
+        _check(lib.vr_conv2d(self.h, keys.ek, _ptr_array(cols), C_in, h, w, pad, K.ctypes.data,
+                             bias.ctypes.data, C_out, k, stride, arr, _stream(stream)))
+        return [Ciphertext(arr[i], self) for i in range(C_out * wo)]
+
+    def square(self, keys, cts, stream=None):
+        arr = (ctypes.c_void_p * len(cts))()
+        _check(lib.vr_square(self.h, keys.ek, _ptr_array(cts), len(cts), arr, _stream(stream)))
+        return [Ciphertext(arr[i], self) for i in range(len(cts))]
+
+    def encode_fc_weights(self, W, stride, block, level):
+        W = _f64(W)
+        n_out, C, ho, wo = W.shape
+        total = n_out * C * wo
+        arr = (ctypes.c_void_p * total)()
+        _check(lib.vr_encode_fc_weights(self.h, W.ctypes.data, n_out, C, ho, wo, stride, block, level, arr))
+        sc = float(self.q[level])
+        return [Plaintext(arr[i], self, level, sc) for i in range(total)]
+
+    def fc(self, keys, Y, C, w_out, W_pt, bias, block, stream=None):
+        bias = _f64(bias)
+        n_out = bias.size
+        arr = (ctypes.c_void_p * n_out)()
+        _check(lib.vr_fc(self.h, keys.ek, _ptr_array(Y), C, w_out, _ptr_array(W_pt), bias.ctypes.data,
+                         n_out, block, arr, _stream(stream)))
+        return [Ciphertext(arr[i], self) for i in range(n_out)]
+
+    # ------------------------------------------------------------ parity
+    def ct_import(self, limbs, level, scale):
+        a = np.ascontiguousarray(np.asarray(limbs, dtype=np.uint64))
+        h = ctypes.c_void_p()
+        _check(lib.vr_ct_import(self.h, a.ctypes.data, a.shape[0], level, float(scale), ctypes.byref(h)))
+        return Ciphertext(h.value, self)
+
+    def pt_import(self, limbs, level, scale):
+        a = np.ascontiguousarray(np.asarray(limbs, dtype=np.uint64))
+        h = ctypes.c_void_p()
+        _check(lib.vr_pt_import(self.h, a.ctypes.data, level, float(scale), ctypes.byref(h)))
+        return Plaintext(h.value, self, level, float(scale))
+
+    def ntt_device(self, ptr, n_limbs, mod_index, inverse=False, stream=None):
+        mi = np.ascontiguousarray(np.asarray(mod_index, dtype=np.uint32))
+        _check(lib.vr_ntt(self.h, ptr, n_limbs, mi.ctypes.data, 1 if inverse else 0, _stream(stream)))

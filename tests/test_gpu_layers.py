@@ -1,0 +1,199 @@
+"""GPU parity of the column-wise layers (matmul, conv, x^2, FC) against the
+oracle, limb for limb, plus the decoded FP64 bar (2^-20 normwise relative,
+max |y - ref| / max |ref|), batched-versus-per-op identity, and the
+full-size workloads on sampled output columns."""
+import numpy as np
+import pytest
+
+import synthetic_inputs as SI
+from oracle import layers as Ly
+from oracle import Params, Context as OracleContext
+from tests.gpu_helpers import pair, to_gpu, assert_same, gpu_ctx, SEED_KEYS
+
+pytestmark = pytest.mark.gpu
+EPS = 2.0 ** -20
+
+
+def gpu_matmul_decode(g, gk, D, m, p):
+    Pp = len(D)
+    C = np.full((m, p), np.nan)
+    for idx, ct in enumerate(D):
+        z = g.decode(g.decrypt(gk, ct), m)
+        for i in range(m):
+            if (i + idx) % Pp < p:
+                C[i, (i + idx) % Pp] = z[i]
+    return C
+
+
+def gpu_conv_decode(g, gk, Y, B, C_out, h, pad, k, stride, w):
+    Hp = Ly.image_block(h, pad)
+    ho, wo = Ly.conv_out_size(h, pad, k, stride), Ly.conv_out_size(w, pad, k, stride)
+    out = np.zeros((B, C_out, ho, wo))
+    for co in range(C_out):
+        for jo in range(wo):
+            z = g.decode(g.decrypt(gk, Y[co * wo + jo]))
+            for b in range(B):
+                out[b, co, :, jo] = z[b * Hp + stride * np.arange(ho)]
+    return out
+
+
+@pytest.fixture(scope="module")
+def c1mm():
+    return pair("C1", rot_steps=tuple(range(1, 16)))
+
+
+def test_matmul_16x16_bit_exact(c1mm):
+    o, ok, g, gk = c1mm
+    seed, m, n, p = SI.MATMUL_16
+    A, B = SI.matmul_operands(seed, m, n, p)
+    Ac = Ly.encrypt_matrix_columns(o, ok, A, 0, m, p, 3, 1001, 0)
+    Bc = Ly.encrypt_matrix_columns(o, ok, B, 1, m, p, 3, 1001, 100)
+    D = Ly.matmul(o, ok, Ac, Bc, m, n, p)
+    gD = g.matmul(gk, [to_gpu(g, c) for c in Ac], [to_gpu(g, c) for c in Bc], m, n, p)
+    assert len(gD) == len(D) == 16
+    for i, (x, y) in enumerate(zip(gD, D)):
+        assert_same(x, y, "C[%d]" % i)
+    assert Ly.rel_error(gpu_matmul_decode(g, gk, gD, m, p), A @ B) < EPS
+
+
+def test_matmul_gpu_encrypt_end_to_end(c1mm):
+    """GPU encode/encrypt of the columns, GPU product, GPU decrypt/decode."""
+    o, ok, g, gk = c1mm
+    seed, m, n, p = SI.MATMUL_16
+    A, B = SI.matmul_operands(seed, m, n, p)
+    gA = g.encrypt_matrix_columns(gk, A, 0, m, p, 3, 1001, 0)
+    gB = g.encrypt_matrix_columns(gk, B, 1, m, p, 3, 1001, 100)
+    gD = g.matmul(gk, gA, gB, m, n, p)
+    assert gD[0].level == 2
+    assert Ly.rel_error(gpu_matmul_decode(g, gk, gD, m, p), A @ B) < EPS
+
+
+def test_matmul_ragged_identity_and_per_op(c1mm):
+    o, ok, g, gk = c1mm
+    m, n, p = 12, 5, 5
+    A = np.random.default_rng(2).uniform(-1, 1, (m, n))
+    Ac = Ly.encrypt_matrix_columns(o, ok, A, 0, m, p, 3, 7, 0)
+    Bc = Ly.encrypt_matrix_columns(o, ok, np.eye(n), 1, m, p, 3, 7, 100)
+    D = Ly.matmul(o, ok, Ac, Bc, m, n, p)
+    gA, gB = [to_gpu(g, c) for c in Ac], [to_gpu(g, c) for c in Bc]
+    gD = g.matmul(gk, gA, gB, m, n, p)
+    for i, (x, y) in enumerate(zip(gD, D)):
+        assert_same(x, y, "C[%d]" % i)
+    from paper_2512_18646_amd import perop
+    for i, (x, y) in enumerate(zip(perop.matmul(g, gk, gA, gB, m, n, p), D)):
+        assert_same(x, y, "per-op C[%d]" % i)
+    assert Ly.rel_error(gpu_matmul_decode(g, gk, gD, m, p), A) < EPS
+
+
+def test_matmul_rejects_m_below_p(c1mm):
+    from paper_2512_18646_amd import vr
+    o, ok, g, gk = c1mm
+    A = g.encrypt_matrix_columns(gk, np.ones((4, 3)), 0, 4, 8, 3, 1, 0)
+    B = g.encrypt_matrix_columns(gk, np.ones((3, 8)), 1, 4, 8, 3, 1, 10)
+    with pytest.raises(vr.VRError) as e:
+        g.matmul(gk, A, B, 4, 3, 8)
+    assert e.value.code == vr.VR_EINVAL
+
+
+@pytest.fixture(scope="module")
+def small_cnn():
+    """N = 2^10 on the 49/40/40/40 chain: rotations for conv (1, 2) and FC blocks."""
+    return pair("C1", rot_steps=(1, 2, 4, 8), log_n=10)
+
+
+def test_conv_square_fc_bit_exact_small(small_cnn):
+    o, ok, g, gk = small_cnn
+    B, Ci, h, w, Co, k, s, pad = 8, 2, 10, 9, 3, 3, 2, 1
+    rng = np.random.default_rng(3)
+    X = rng.uniform(0, 1, (B, Ci, h, w))
+    K = rng.normal(0, 0.1, (Co, Ci, k, k))
+    bias = rng.normal(0, 0.1, Co)
+    cts = Ly.encrypt_image_columns(o, ok, X, pad, 3, 3, 0)
+    gcts = [to_gpu(g, c) for c in cts]
+    Y = Ly.conv2d(o, ok, cts, Ci, h, w, pad, K, bias, Co, k, s)
+    gY = g.conv2d(gk, gcts, Ci, h, w, pad, K, bias, s)
+    for i, (x, y) in enumerate(zip(gY, Y)):
+        assert_same(x, y, "conv %d" % i)
+    from paper_2512_18646_amd import perop
+    for i, (x, y) in enumerate(zip(perop.conv2d(g, gk, gcts, Ci, h, w, pad, K, bias, s), Y)):
+        assert_same(x, y, "per-op conv %d" % i)
+    Y2 = [Ly.square(o, ok, y) for y in Y]
+    gY2 = g.square(gk, gY)
+    for i, (x, y) in enumerate(zip(gY2, Y2)):
+        assert_same(x, y, "square %d" % i)
+    ref = Ly.ref_conv(X, K, bias, s, pad)
+    got = gpu_conv_decode(g, gk, gY2, B, Co, h, pad, k, s, w)
+    assert Ly.rel_error(got, ref ** 2) < EPS
+    Hp = Ly.image_block(h, pad)
+    ho, wo = ref.shape[2], ref.shape[3]
+    W = rng.normal(0, 0.05, (4, Co, ho, wo))
+    fb = rng.normal(0, 0.05, 4)
+    pts = Ly.fc_plaintexts(o, W, Co, ho, wo, s, Hp, Y2[0].level)
+    Z = Ly.fc(o, ok, Y2, pts, fb, Hp)
+    gpts = [g.pt_import(pt.m, pt.level, pt.scale) for row in pts for pt in row]
+    gZ = g.fc(gk, gY2, Co, wo, gpts, fb, Hp)
+    for i, (x, y) in enumerate(zip(gZ, Z)):
+        assert_same(x, y, "fc %d" % i)
+    # GPU-encoded weights: decoded logits still within the bar
+    gpts2 = g.encode_fc_weights(W, s, Hp, Y2[0].level)
+    gZ2 = g.fc(gk, gY2, Co, wo, gpts2, fb, Hp)
+    logits = np.zeros((B, 4))
+    for oi, z in enumerate(gZ2):
+        logits[:, oi] = g.decode(g.decrypt(gk, z))[np.arange(B) * Hp]
+    assert Ly.rel_error(logits, Ly.ref_fc(ref ** 2, W, fb)) < EPS
+
+
+def test_conv_edge_shapes(small_cnn):
+    """k = 1 (no rotation), stride 1 with padding, one image, ragged block."""
+    o, ok, g, gk = small_cnn
+    rng = np.random.default_rng(4)
+    for (B, Ci, h, w, Co, k, s, pad) in [(1, 1, 5, 4, 2, 1, 1, 0), (3, 1, 7, 6, 1, 3, 1, 1),
+                                         (2, 2, 12, 5, 2, 2, 2, 0)]:
+        X = rng.uniform(0, 1, (B, Ci, h, w))
+        K = rng.normal(0, 0.1, (Co, Ci, k, k))
+        bias = rng.normal(0, 0.1, Co)
+        cts = Ly.encrypt_image_columns(o, ok, X, pad, 2, 5, 0)
+        Y = Ly.conv2d(o, ok, cts, Ci, h, w, pad, K, bias, Co, k, s)
+        gY = g.conv2d(gk, [to_gpu(g, c) for c in cts], Ci, h, w, pad, K, bias, s)
+        for i, (x, y) in enumerate(zip(gY, Y)):
+            assert_same(x, y, "conv %s %d" % ((B, Ci, h, w, Co, k, s, pad), i))
+
+
+@pytest.mark.parametrize("level", [2, 7])
+def test_conv28_full_size_sampled(level):
+    """The 28x28 conv layer at N = 2^14, L = 7 on a full set of 256 images:
+    GPU layer on every column, oracle on output columns 0, 6 and 12."""
+    W = SI.CONV_28
+    o, ok, g, gk = pair("C2", rot_steps=(1, 2, 3))
+    X, K, bias = W.draw()
+    cts = Ly.encrypt_image_columns(o, ok, X, W.pad, level, 2002, 0)
+    gY = g.conv2d(gk, [to_gpu(g, c) for c in cts], 1, W.h, W.w, W.pad, K, bias, W.stride)
+    cols = {0, 6, 12}
+    Y = Ly.conv2d(o, ok, cts, 1, W.h, W.w, W.pad, K, bias, W.c_out, W.k, W.stride, only_cols=cols)
+    wo = Ly.conv_out_size(W.w, W.pad, W.k, W.stride)
+    assert len(gY) == W.c_out * wo == 65
+    checked = 0
+    for i, y in enumerate(Y):
+        if y is not None:
+            assert_same(gY[i], y, "conv28 out %d" % i)
+            checked += 1
+    assert checked == 15
+    gY2 = g.square(gk, gY)
+    i0 = 0 * wo + 6
+    assert_same(gY2[i0], Ly.square(o, ok, Y[i0]), "square")
+    ref = Ly.ref_conv(X, K, bias, W.stride, W.pad)
+    got = gpu_conv_decode(g, gk, gY2, W.batch, W.c_out, W.h, W.pad, W.k, W.stride, W.w)
+    assert Ly.rel_error(got, ref ** 2) < EPS
+
+
+def test_conv28_gpu_only_end_to_end():
+    """GPU encryption of the columns, GPU conv + x^2, GPU decryption: FP64 bar."""
+    W = SI.CONV_28
+    o, ok, g, gk = pair("C2", rot_steps=(1, 2, 3))
+    X, K, bias = W.draw()
+    gcts = g.encrypt_columns(gk, X, W.pad, 7, 2002, 0)
+    gY2 = g.square(gk, g.conv2d(gk, gcts, 1, W.h, W.w, W.pad, K, bias, W.stride))
+    ref = Ly.ref_conv(X, K, bias, W.stride, W.pad)
+    got = gpu_conv_decode(g, gk, gY2, W.batch, W.c_out, W.h, W.pad, W.k, W.stride, W.w)
+    assert gY2[0].level == 5
+    assert Ly.rel_error(got, ref ** 2) < EPS

@@ -1,0 +1,204 @@
+"""GPU parity of every RNS-CKKS primitive against the oracle, limb for limb.
+
+Inputs are oracle ciphertexts imported through vr_ct_import (coefficient
+domain), outputs are exported through vr_ct_export; both sides hold keys from
+the same seed.  Bar: bit-exact on every limb (integer arithmetic)."""
+import numpy as np
+import pytest
+
+from oracle import Params, PRESETS, Context as OracleContext
+from tests.gpu_helpers import pair, to_gpu, assert_same, gpu_ctx
+
+pytestmark = pytest.mark.gpu
+
+
+def test_moduli_match_oracle():
+    for name in ("C1", "C2", "C3"):
+        o = OracleContext(PRESETS[name])
+        g = gpu_ctx(PRESETS[name])
+        assert g.q == o.q and g.p == o.p, name
+        assert g.secure
+
+
+@pytest.mark.parametrize("log_n", [6, 13, 14, 15, 16])
+def test_ntt_matches_oracle(log_n):
+    import torch
+    p = Params(log_n, [60, 50, 40], [51], 1, 30.0, allow_insecure=True)
+    o = OracleContext(p)
+    g = gpu_ctx(p)
+    mods = o.q + o.p
+    rng = np.random.default_rng(log_n)
+    reps = 3
+    host = np.stack([rng.integers(0, mods[i % 4], o.n, dtype=np.uint64) for i in range(4 * reps)])
+    host[0, :8] = [0, 1, mods[0] - 1, 2, 3, mods[0] - 2, 0, 1]
+    mi = [i % 4 for i in range(4 * reps)]
+    dev = torch.from_numpy(host.view(np.int64).copy()).cuda()
+    g.ntt_device(dev.data_ptr(), 4 * reps, mi)
+    torch.cuda.synchronize()
+    fwd = dev.cpu().numpy().view(np.uint64)
+    for r in range(4 * reps):
+        assert np.array_equal(fwd[r], o.ntt(host[r], mods[mi[r]])), r
+    g.ntt_device(dev.data_ptr(), 4 * reps, mi, inverse=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(dev.cpu().numpy().view(np.uint64), host)
+
+
+def test_secret_and_public_key_match():
+    o, ok, g, gk = pair("C1")
+    assert np.array_equal(gk.secret_coeffs().astype(np.int64), ok.s)
+    # the public key shows through an encryption of an imported plaintext
+    pt = o.encode(np.linspace(-1, 1, 100), 3, o.scale)
+    gpt = g.pt_import(pt.m, 3, pt.scale)
+    assert_same(g.encrypt(gk, gpt, 77, 5), o.encrypt(ok, pt, 77, 5), "encrypt")
+
+
+@pytest.mark.parametrize("name,level", [("C1", 3), ("C1", 0), ("C2", 7)])
+def test_encrypt_decrypt_match(name, level):
+    o, ok, g, gk = pair(name)
+    z = np.random.default_rng(1).uniform(-1, 1, o.slots)
+    pt = o.encode(z, level, o.scale)
+    ct = o.encrypt(ok, pt, 3, 11)
+    gct = g.encrypt(gk, g.pt_import(pt.m, level, pt.scale), 3, 11)
+    assert_same(gct, ct, "encrypt")
+    gpt = g.decrypt(gk, gct)
+    assert np.array_equal(gpt.export(), o.decrypt(ok, ct).m)
+    assert np.max(np.abs(g.decode(gpt) - z)) < 2.0 ** -20
+
+
+def test_encode_within_one_of_oracle():
+    for name in ("C1", "C3"):
+        o, ok, g, gk = pair(name)
+        z = np.random.default_rng(2).uniform(-1, 1, o.slots)
+        gpt = g.encode(z, 1)
+        mo = o.encode(z, 1, o.scale).m
+        mg = gpt.export()
+        q = np.array(o.q[:2], dtype=np.uint64)[:, None]
+        d = (mg.astype(np.int64) - mo.astype(np.int64))
+        d = np.where(d > (q // 2).astype(np.int64), d - q.astype(np.int64), d)
+        d = np.where(d < -(q // 2).astype(np.int64), d + q.astype(np.int64), d)
+        assert np.abs(d).max() <= 1, name
+        assert np.max(np.abs(g.decode(gpt) - z)) < 2.0 ** -30
+
+
+@pytest.fixture(scope="module")
+def c1():
+    return pair("C1", rot_steps=(1, 2, 3, 5, -1, 4096 - 3))
+
+
+def _fresh(o, ok, seed, level=3, n=None):
+    z = np.random.default_rng(seed).uniform(-1, 1, n or o.slots)
+    return o.encrypt(ok, o.encode(z, level, o.scale), 5, seed)
+
+
+def test_add_sub_match(c1):
+    o, ok, g, gk = c1
+    a, b = _fresh(o, ok, 1), _fresh(o, ok, 2)
+    assert_same(g.add(to_gpu(g, a), to_gpu(g, b)), o.add(a, b), "add")
+    assert_same(g.sub(to_gpu(g, a), to_gpu(g, b)), o.sub(a, b), "sub")
+
+
+@pytest.mark.parametrize("c", [0.37, -0.9, 0.0, 1e-3])
+def test_mul_const_add_const_match(c1, c):
+    o, ok, g, gk = c1
+    a = _fresh(o, ok, 3)
+    dq = float(o.q[3])
+    assert_same(g.mul_const(to_gpu(g, a), c, dq), o.mul_const(a, c, dq), "mul_const")
+    assert_same(g.add_const(to_gpu(g, a), c), o.add_const(a, c), "add_const")
+    # constants beyond 2^63 (c * scale at the product scale)
+    big = o.mul_const(a, 0.5, dq)
+    assert_same(g.add_const(to_gpu(g, big), -0.7), o.add_const(big, -0.7), "add_const big")
+
+
+def test_mul_plain_tensor_relin_match(c1):
+    o, ok, g, gk = c1
+    a, b = _fresh(o, ok, 4), _fresh(o, ok, 5)
+    pt = o.encode(np.random.default_rng(9).uniform(-1, 1, o.slots), 3, float(o.q[3]))
+    gpt = g.pt_import(pt.m, 3, pt.scale)
+    assert_same(g.mul_plain(to_gpu(g, a), gpt), o.mul_plain(a, pt), "mul_plain")
+    t = o.tensor(a, b)
+    gt = g.tensor(to_gpu(g, a), to_gpu(g, b))
+    assert_same(gt, t, "tensor")
+    assert_same(g.relinearize(gk, gt), o.relinearize(t, ok), "relin")
+    assert_same(g.mul(gk, to_gpu(g, a), to_gpu(g, b)), o.mul(a, b, ok), "mul")
+
+
+@pytest.mark.parametrize("level", [3, 2, 1])
+def test_rescale_and_mod_drop_match(c1, level):
+    o, ok, g, gk = c1
+    a = _fresh(o, ok, 6, level=level)
+    assert_same(g.rescale(to_gpu(g, a)), o.rescale(a), "rescale")
+    t = o.tensor(a, a)
+    assert_same(g.rescale(to_gpu(g, t)), o.rescale(t), "rescale 3 comps")
+    assert_same(g.mod_drop(to_gpu(g, a), 0), o.mod_drop(a, 0), "mod_drop")
+
+
+@pytest.mark.parametrize("level", [3, 0])
+def test_rotate_match(c1, level):
+    o, ok, g, gk = c1
+    a = _fresh(o, ok, 7, level=level)
+    ga = to_gpu(g, a)
+    for step in (1, 5, -1, 4096 - 3, 0):
+        assert_same(g.rotate(gk, ga, step), o.rotate(a, step, ok), "rotate %d" % step)
+    many = g.rotate_many(gk, ga, [1, 2, 3, 0])
+    for st, m in zip([1, 2, 3, 0], many):
+        assert_same(m, o.rotate(a, st, ok), "hoisted %d" % st)
+
+
+@pytest.mark.parametrize("name", ["C1", "C2", "C3"])
+def test_switching_keys_match(name):
+    """Relinearisation and rotation keys, limb for limb (coefficient domain)."""
+    o, ok, g, gk = pair(name, rot_steps=(1, 3))
+    keys = [(0, ok.rlk)] + [(gal, k) for gal, k in sorted(ok.rot.items())]
+    for gal, key in keys:
+        got = gk.switching_key(gal)
+        for j in range(o.dnum):
+            for comp, want in ((0, key.b[j]), (1, key.a[j])):
+                if not np.array_equal(got[j, comp], want):
+                    limbs = sorted({int(l) for l, _ in np.argwhere(got[j, comp] != want)})
+                    raise AssertionError("%s key g=%d digit %d comp %d differs on limbs %s"
+                                         % (name, gal, j, comp, limbs[:10]))
+
+
+def test_rotation_decrypts_on_gpu():
+    o, ok, g, gk = pair("C2", rot_steps=(1, 3))
+    z = np.random.default_rng(4).uniform(-1, 1, o.slots)
+    ct = g.encrypt(gk, g.encode(z, 7), 1, 2)
+    for st in (1, 3):
+        d = g.decode(g.decrypt(gk, g.rotate(gk, ct, st)))
+        assert np.max(np.abs(d - np.roll(z, -st))) < 2.0 ** -20, st
+
+
+@pytest.mark.parametrize("name,level", [("C2", 2), ("C2", 7), ("C3", 3), ("C3", 24), ("C3", 20)])
+def test_keyswitch_match_other_chains(name, level):
+    """Rotation and relinearisation with 60-bit q_0 / special primes (C2) and
+    9-prime digits with a short last digit (C3 at levels 3 and 20)."""
+    o, ok, g, gk = pair(name, rot_steps=(1, 3))
+    z = np.random.default_rng(level).uniform(-1, 1, o.slots)
+    a = o.encrypt(ok, o.encode(z, level, o.scale), 9, level)
+    ga = to_gpu(g, a)
+    assert_same(g.rotate(gk, ga, 1), o.rotate(a, 1, ok), "%s rotate l=%d" % (name, level))
+    many = g.rotate_many(gk, ga, [3, 1])
+    assert_same(many[0], o.rotate(a, 3, ok), "%s hoisted 3" % name)
+    t = o.tensor(a, a)
+    assert_same(g.relinearize(gk, to_gpu(g, t)), o.relinearize(t, ok), "%s relin" % name)
+
+
+def test_error_paths(c1):
+    from paper_2512_18646_amd import vr
+    o, ok, g, gk = c1
+    a = to_gpu(g, _fresh(o, ok, 8, level=3))
+    b = to_gpu(g, _fresh(o, ok, 9, level=2))
+    with pytest.raises(vr.VRError) as e:
+        g.add(a, b)
+    assert e.value.code == vr.VR_ELEVEL
+    c = g.mul_const(a, 1.0, 2.0)
+    with pytest.raises(vr.VRError) as e:
+        g.add(a, c)
+    assert e.value.code == vr.VR_ESCALE
+    with pytest.raises(vr.VRError) as e:
+        g.rotate(gk, a, 7)
+    assert e.value.code == vr.VR_ENOKEY
+    z = to_gpu(g, _fresh(o, ok, 10, level=0))
+    with pytest.raises(vr.VRError) as e:
+        g.rescale(z)
+    assert e.value.code == vr.VR_ELEVEL
