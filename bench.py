@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the encrypted column-wise conv layer on one MI355X.
+
+Workload (one step): the 28x28 single-channel conv layer with x^2 activation
+on `--sets` full ciphertext sets of 256 images each (images in 32-slot blocks
+of the 28 column ciphertexts at N = 2^14, L = 7, 60/40-bit primes), 5 filters
+4x4 stride 2, followed by the square activation: per set 84 rotations, 1,040
+MulConst, 65 rescales, 65 tensor + relinearise + rescale.  Inputs are
+encrypted before the timed region and stay resident in HBM; the timed region
+is the server-side evaluation only.
+
+The JSON line adds the plain per-operation path (one C-ABI call per HE
+operation), HE rotations/s at N = 2^16 (L = 24 and a 4-limb level, batched
+with a shared key versus per operation), per-step latency percentiles, the
+live roofline of the dominant kernel (HIP events around its launches inside
+the timed region) and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "encrypted images/s, HE-rotations/s (N=2^16) batched vs per-op; p99 latency"
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def percentile(xs, p):
+    return float(np.percentile(np.asarray(xs), p)) if xs else None
+
+
+def conv_setup(vr, level, sets):
+    import synthetic_inputs as SI
+    W = SI.CONV_28
+    ctx = vr.Context(14, [60] + [40] * 7, [60], 8, 40.0)
+    keys = ctx.keygen(1002, rot_steps=[1, 2, 3])
+    _, K, bias = W.draw()
+    cols = []
+    for s in range(sets):
+        X = SI.images(W.seed + 1000 * s, W.batch, W.channels, W.h, W.w)
+        cols.append(ctx.encrypt_columns(keys, X, W.pad, level, 1002, 10000 * s))
+    return W, ctx, keys, K, bias, cols
+
+
+def step_batched(ctx, keys, W, K, bias, cols):
+    return [ctx.square(keys, ctx.conv2d(keys, c, W.channels, W.h, W.w, W.pad, K, bias, W.stride))
+            for c in cols]
+
+
+def sync():
+    import torch
+    torch.cuda.synchronize()
+
+
+def rotations_bench(vr, level, n_ct, reps):
+    """HE rotations/s at N = 2^16: n_ct ciphertexts rotated by one step."""
+    ctx = vr.Context(16, [60] + [50] * 24, [51] * 9, 3, 50.0)
+    keys = ctx.keygen(1003, rot_steps=[1])
+    z = np.random.default_rng(3).uniform(-1, 1, ctx.slots)
+    cts = [ctx.encrypt(keys, ctx.encode(z, level), 1003, i) for i in range(n_ct)]
+    out = {}
+    ctx.rotate_batch(keys, cts, 1)
+    sync()
+    t = time.perf_counter()
+    for _ in range(reps):
+        r = ctx.rotate_batch(keys, cts, 1)
+    sync()
+    out["batched"] = n_ct * reps / (time.perf_counter() - t)
+    ctx.rotate(keys, cts[0], 1)
+    sync()
+    t = time.perf_counter()
+    for _ in range(reps):
+        r1 = [ctx.rotate(keys, c, 1) for c in cts]
+    sync()
+    out["per_op"] = n_ct * reps / (time.perf_counter() - t)
+    out["identical"] = bool(np.array_equal(r[0].export(), r1[0].export()))
+    return out
+
+
+def cpu_baseline(level):
+    """The oracle on a bounded sample of the same layer: every operation
+    that output column j' = 6 needs (input columns 12..15 rotated by 1..3,
+    5 filters of 16 MulConst + AddConst + Rescale, then x^2 of the 5
+    outputs), timed per operation class and scaled by the layer's operation
+    counts (84 rotations, 13 output columns) to images/s."""
+    import synthetic_inputs as SI
+    from oracle import Context, PRESETS
+    from oracle import layers as Ly
+    W = SI.CONV_28
+    o = Context(PRESETS["C2"])
+    ok = o.keygen(1002, rot_steps=[1, 2, 3])
+    X, K, bias = W.draw()
+    cols = [o.encrypt(ok, o.encode(Ly.image_column_slots(o, X, 0, j, W.pad), level, o.scale), 1002, j)
+            for j in range(12, 16)]
+    t0 = time.perf_counter()
+    rots = [[c] + o.rotate_many(c, [1, 2, 3], ok) for c in cols]
+    t_rot = (time.perf_counter() - t0) / 12
+    t0 = time.perf_counter()
+    dq = float(o.q[level])
+    ys = []
+    for co in range(W.c_out):
+        acc = None
+        for v in range(W.k):
+            for u in range(W.k):
+                t = o.mul_const(rots[v][u], K[co, 0, u, v], dq)
+                acc = t if acc is None else o.add(acc, t)
+        ys.append(o.rescale(o.add_const(acc, float(bias[co]))))
+    for y in ys:
+        Ly.square(o, ok, y)
+    t_col = time.perf_counter() - t0
+    wo = Ly.conv_out_size(W.w, W.pad, W.k, W.stride)
+    t_layer = 84 * t_rot + wo * t_col
+    return {"value": W.batch / t_layer, "unit": "images/s", "cores": 1, "kind": "oracle",
+            "sample": "one output column of one 256-image set (12 rotations, 80 MulConst, 5 rescales, "
+                      "5 x^2) timed at level %d, scaled to the layer's 84 rotations and %d output "
+                      "columns; measured %.1f s" % (level, wo, 12 * t_rot + t_col)}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--sets", type=int, default=4, help="256-image ciphertext sets per step")
+    ap.add_argument("--level", type=int, default=7, help="level of the fresh ciphertexts (7 = full)")
+    ap.add_argument("--profile-class", default="ntt")
+    ap.add_argument("--no-extra", action="store_true", help="skip per-op, rotation and CPU legs")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the path runs on a single MI355X "
+              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    from paper_2512_18646_amd import vr, perop
+    log("setup: encrypting %d sets of 256 images at level %d" % (args.sets, args.level))
+    W, ctx, keys, K, bias, cols = conv_setup(vr, args.level, args.sets)
+    images = W.batch * args.sets
+
+    for i in range(args.warmup):
+        step_batched(ctx, keys, W, K, bias, cols)
+        sync()
+        log("warmup %d done" % i)
+    lat = []
+    ctx.profile_start(args.profile_class, 1 << 18)
+    sync()
+    t_all = time.perf_counter()
+    for i in range(args.steps):
+        t = time.perf_counter()
+        outs = step_batched(ctx, keys, W, K, bias, cols)
+        sync()
+        lat.append((time.perf_counter() - t) * 1e3)
+        del outs
+    sync()
+    total = time.perf_counter() - t_all
+    prof_ms, prof_launches, prof_units, dropped = ctx.profile_stop()
+    log("timed %d steps: %.2f ms/step" % (args.steps, total / args.steps * 1e3))
+    value = images * args.steps / total
+
+    n = 1 << 14
+    bytes_per_unit = {"ntt": 16 * n}.get(args.profile_class)
+    roofline = None
+    if bytes_per_unit and prof_ms > 0:
+        achieved = bytes_per_unit * prof_units / (prof_ms / 1e3) / 1e9
+        roofline = {"bound": "hbm", "kernel": args.profile_class, "achieved": round(achieved, 1),
+                    "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                    "traffic": None, "avg_launch_us": round(prof_ms / max(prof_launches, 1) * 1e3, 2),
+                    "launches": prof_launches, "units": prof_units,
+                    "share_of_step": round(prof_ms / (total * 1e3), 3), "dropped": dropped}
+
+    out = {"metric": METRIC, "value": round(value, 2), "unit": "images/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total / args.steps * 1e3, 3),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+           "data": "synthetic",
+           "config": {"workload": "conv 28x28 4x4/2 x5 + x^2, 256 images per set, N=2^14 L=7 (60+7x40, P 60, dnum 8)",
+                      "sets_per_step": args.sets, "images_per_step": images, "level_in": args.level,
+                      "path": "batched layer calls"},
+           "latency_ms_p50": round(percentile(lat, 50), 3), "latency_ms_p99": round(percentile(lat, 99), 3),
+           "roofline": roofline}
+
+    if not args.no_extra:
+        log("per-op path (one set)")
+        perop.square(ctx, keys, perop.conv2d(ctx, keys, cols[0], W.channels, W.h, W.w, W.pad, K, bias, W.stride))
+        sync()
+        t = time.perf_counter()
+        ys = perop.square(ctx, keys, perop.conv2d(ctx, keys, cols[0], W.channels, W.h, W.w, W.pad, K, bias,
+                                                  W.stride))
+        sync()
+        t_per_op = time.perf_counter() - t
+        ref = step_batched(ctx, keys, W, K, bias, cols[:1])[0]
+        out["per_op_images_per_s"] = round(W.batch / t_per_op, 2)
+        out["per_op_identical"] = bool(all(np.array_equal(ys[i].export(), ref[i].export()) for i in (0, 33, 64)))
+        out["batched_over_per_op"] = round((W.batch * args.sets / (total / args.steps)) / (W.batch / t_per_op), 2)
+        del ys, ref
+        log("rotations at N=2^16")
+        out["rotations_per_s_n16"] = {"level24": rotations_bench(vr, 24, 8, 3),
+                                      "level3": rotations_bench(vr, 3, 32, 3)}
+        for v in out["rotations_per_s_n16"].values():
+            v["batched"], v["per_op"] = round(v["batched"], 1), round(v["per_op"], 1)
+
+    if not args.no_extra and not args.no_cpu_baseline:
+        log("cpu baseline (oracle sample)")
+        out["cpu_baseline"] = cpu_baseline(args.level)
+        out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 4)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -187,6 +187,12 @@ vr_status vr_rotate(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext
 vr_status vr_rotate_many(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *a,
                          const int32_t *steps, size_t k, vr_ciphertext **outs, void *stream);
 
+/* n ciphertexts (same level and scale) each rotated by the same step, in one
+ * batched key switch: the rotation key streams from HBM once for all of them.
+ * Bit-identical to n vr_rotate calls.  outs receives n handles. */
+vr_status vr_rotate_batch(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *in,
+                          size_t n, int32_t step, vr_ciphertext **outs, void *stream);
+
 /* Column-split matrix product (abstract and contributions; "Homomorphic
  * Matrix Multiplication" with RowShifter reduced to one rotation and the
  * ciphertext-pair split of "Parallelized Matrix Multiplication"): from A_k,
@@ -257,6 +263,19 @@ vr_status vr_ct_meta(const vr_ciphertext *ct, uint32_t *ncomp, uint32_t *level, 
  * psi^((2 brev(i) + 1) t).  For kernel tests and benchmarks. */
 vr_status vr_ntt(vr_context *ctx, uint64_t *data, uint32_t n_limbs, const uint32_t *mod_index,
                  int inverse, void *stream);
+
+/* Device-side timing of one kernel class: while started, every launch of that
+ * class (on whatever stream it runs) is bracketed by HIP events.  Classes:
+ * "ntt" (one forward/inverse NTT call; units = limbs), "ks_inner" (key-switch
+ * inner product; units = ciphertexts x extended limbs), "base_convert" (units
+ * = output limbs), "lincomb" (fused MulConst/AddConst accumulation; units =
+ * output limbs), "moddown" (ModDown combine; units = output limbs), "tensor"
+ * (units = input limbs).  At most max_launches launches are recorded. */
+vr_status vr_profile_start(vr_context *ctx, const char *kernel_class, size_t max_launches);
+/* Synchronises the device and returns the summed event time, launch count,
+ * unit count and whether launches were dropped; profiling stops. */
+vr_status vr_profile_stop(vr_context *ctx, double *total_ms, uint64_t *launches, uint64_t *units,
+                          uint32_t *dropped);
 
 void vr_free_ciphertext(vr_ciphertext *ct);
 void vr_free_plaintext(vr_plaintext *pt);

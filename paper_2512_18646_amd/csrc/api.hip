@@ -115,6 +115,7 @@ void vr_context_destroy(vr_context* ctx)
     if (!ctx) return;
     (void)hipDeviceSynchronize();
     destroy_context_tables(ctx);
+    for (hipEvent_t e : ctx->prof.ev) (void)hipEventDestroy(e);
     delete ctx;
 }
 
@@ -557,6 +558,52 @@ vr_status vr_ntt(vr_context* ctx, uint64_t* data, uint32_t n_limbs, const uint32
             ntt_forward(ctx, ls, st);
         i += reps * period;
     }
+    API_END
+}
+
+vr_status vr_profile_start(vr_context* ctx, const char* kernel_class, size_t max_launches)
+{
+    API_BEGIN
+    REQUIRE(ctx && kernel_class, "null argument");
+    static const char* names[kProfClasses] = {"ntt", "ks_inner", "base_convert", "lincomb", "moddown",
+                                              "tensor"};
+    int cls = -1;
+    for (int i = 0; i < kProfClasses; i++)
+        if (strcmp(kernel_class, names[i]) == 0) cls = i;
+    REQUIRE(cls >= 0, "unknown kernel class");
+    REQUIRE(max_launches >= 1 && max_launches <= (1u << 20), "max_launches out of range");
+    Profiler& p = ctx->prof;
+    while (p.ev.size() < 2 * max_launches) {
+        hipEvent_t e;
+        VR_HIP(hipEventCreate(&e));
+        p.ev.push_back(e);
+    }
+    p.cls = cls;
+    p.used = 0;
+    p.units = p.launches = 0;
+    p.overflow = false;
+    API_END
+}
+
+vr_status vr_profile_stop(vr_context* ctx, double* total_ms, uint64_t* launches, uint64_t* units,
+                          uint32_t* dropped)
+{
+    API_BEGIN
+    REQUIRE(ctx, "null context");
+    Profiler& p = ctx->prof;
+    p.cls = -1;
+    VR_HIP(hipDeviceSynchronize());
+    double tot = 0;
+    for (size_t i = 0; i + 1 < p.used; i += 2) {
+        float ms = 0;
+        VR_HIP(hipEventElapsedTime(&ms, p.ev[i], p.ev[i + 1]));
+        tot += ms;
+    }
+    if (total_ms) *total_ms = tot;
+    if (launches) *launches = p.launches;
+    if (units) *units = p.units;
+    if (dropped) *dropped = p.overflow ? 1 : 0;
+    p.used = 0;
     API_END
 }
 

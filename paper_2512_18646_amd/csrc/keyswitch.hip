@@ -232,6 +232,7 @@ const ConvTable& moddown_table(vr_context* ctx, u32 level)
 void launch_convert(vr_context* ctx, const ConvArgs& a, u32 n_polys, hipStream_t s)
 {
     dim3 grid((ctx->n + kThreads - 1) / kThreads, n_polys);
+    ProfScope prof(ctx, kProfBaseConv, s, (u64)n_polys * a.n_out);
     hipLaunchKernelGGL(k_base_convert, grid, dim3(kThreads), 0, s, a);
     VR_CHECK_LAUNCH();
 }
@@ -321,6 +322,7 @@ void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, u32 n_ct
 {
     KsShape k = ks_shape(ctx, level);
     dim3 grid((ctx->n + kThreads - 1) / kThreads, k.next);
+    ProfScope prof(ctx, kProfKsInner, s, (u64)n_ct * k.next);
     if (k.beta <= 4)
         hipLaunchKernelGGL((k_ks_inner<4>), grid, dim3(kThreads), 0, s, X, x_stride, n_ct, key,
                            ctx->nmod(), level, k.next, k.beta, ctx->L, ctx->log_n, g, U, u_stride,
@@ -376,6 +378,7 @@ void keyswitch_moddown_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u3
     launch_convert(ctx, a, n_ct * 2, s);
     ntt_forward(ctx, poly_limbs(Y, Y, n_ct * 2, k.nq, (u64)k.nq * n, (int)level), s);
     dim3 grid((n + kThreads - 1) / kThreads, n_ct * k.nq);
+    ProfScope prof(ctx, kProfModDown, s, (u64)n_ct * 2 * k.nq);
     hipLaunchKernelGGL(k_moddown_finish, grid, dim3(kThreads), 0, s, U, u_stride, Y, k.nq, k.next,
                        ctx->log_n, out0, out1, out_stride, add0, add0_g, add1, add_stride,
                        ctx->d_modq);

@@ -284,6 +284,7 @@ Slab square_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipStr
     const u32 nl = in.level + 1;
     Slab T = new_slab(ctx, in.n, 3, in.level, in.scale * in.scale, s);
     dim3 grid((ctx->n + kThreads - 1) / kThreads, in.n * nl);
+    ProfScope prof(ctx, kProfTensor, s, (u64)in.n * 2 * nl);
     hipLaunchKernelGGL(k_tensor_batch, grid, dim3(kThreads), 0, s, T.base, in.base, in.base,
                        in.stride, nl, ctx->log_n, ctx->d_modq);
     VR_CHECK_LAUNCH();
@@ -426,6 +427,23 @@ vr_status vr_encrypt_matrix_columns(vr_context* ctx, const vr_eval_keys* ek, con
     API_END
 }
 
+vr_status vr_rotate_batch(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* const* in,
+                          size_t n, int32_t step, vr_ciphertext** outs, void* stream)
+{
+    if (outs)
+        for (size_t i = 0; i < n; i++) outs[i] = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && in && outs, "null argument");
+    REQUIRE(n >= 1, "empty input");
+    hipStream_t s = pick_stream(ctx, stream);
+    Slab x = gather(ctx, in, (u32)n, s);
+    REQUIRE(x.ncomp == 2, "rotation needs 2-component ciphertexts");
+    std::vector<Slab> r;
+    rotate_slab(ctx, ek, x, {step}, r, s);
+    to_handles(ctx, r[0], outs);
+    API_END
+}
+
 vr_status vr_matmul(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* const* A,
                     const vr_ciphertext* const* Bbar, uint32_t m, uint32_t n, uint32_t p,
                     vr_ciphertext** C, void* stream)
@@ -548,6 +566,7 @@ vr_status vr_conv2d(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext
     const u32 n_out = C_out * wo;
     Slab acc = new_slab(ctx, n_out, 2, level, out_scale, s);
     dim3 grid((ctx->n + kThreads - 1) / kThreads, n_out * 2 * nl);
+    ProfScope prof(ctx, kProfLincomb, s, (u64)n_out * 2 * nl);
     hipLaunchKernelGGL(k_lincomb, grid, dim3(kThreads), 0, s, acc.base, acc.stride, dptrs, dterms,
                        doff, dw, dws, db, nl, ctx->log_n, ctx->d_modq);
     VR_CHECK_LAUNCH();

@@ -198,6 +198,7 @@ void run(vr_context* ctx, const LimbSet& ls, hipStream_t s)
 {
     u32 n_limbs = ls.per_poly * ls.n_polys;
     if (n_limbs == 0) return;
+    ProfScope prof(ctx, kProfNtt, s, n_limbs);
     auto passes = plan(ctx->log_n);
     NttPass p;
     p.ls = ls;

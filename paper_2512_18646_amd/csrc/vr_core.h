@@ -153,6 +153,25 @@ struct DevBuf {
 };
 typedef std::shared_ptr<DevBuf> BufPtr;
 
+// Kernel classes the event profiler can bracket.
+enum ProfClass : int {
+    kProfNtt = 0,       // one forward/inverse NTT call (all its passes); units = limbs
+    kProfKsInner,       // key-switch inner product; units = ciphertext x extended limb
+    kProfBaseConv,      // fast base conversion; units = output limbs
+    kProfLincomb,       // fused MulConst/AddConst accumulation; units = output limbs
+    kProfModDown,       // ModDown combine; units = output limbs
+    kProfTensor,        // tensor products; units = input limbs
+    kProfClasses
+};
+
+struct Profiler {
+    int cls = -1;
+    std::vector<hipEvent_t> ev;   // start/stop pairs
+    size_t used = 0;
+    u64 units = 0, launches = 0;
+    bool overflow = false;
+};
+
 // Base-conversion constants for one (input set -> output set) conversion.
 struct ConvTable {
     u32 n_in = 0, n_out = 0;
@@ -183,6 +202,7 @@ struct vr_context {
     std::map<int, vr::ConvTable> moddown_tables;                 // level
     std::mutex mu;
     hipStream_t stream = nullptr;     // used when a call passes stream = NULL
+    vr::Profiler prof;
     void* (*alloc_fn)(size_t, void*, void*) = nullptr;
     void (*free_fn)(void*, void*, void*) = nullptr;
     void* alloc_user = nullptr;
@@ -233,6 +253,32 @@ namespace vr {
 
 BufPtr dev_alloc(vr_context* ctx, size_t bytes, hipStream_t s);
 inline u64* as_u64(const BufPtr& b) { return (u64*)b->ptr; }
+
+// Brackets the launches made in its scope with HIP events on `s` when the
+// context profiles class `cls` (see vr_profile_start).
+struct ProfScope {
+    vr_context* ctx;
+    hipStream_t s;
+    long idx = -1;
+    ProfScope(vr_context* c, int cls, hipStream_t st, u64 units) : ctx(c), s(st)
+    {
+        Profiler& p = c->prof;
+        if (p.cls != cls) return;
+        if (p.used + 2 > p.ev.size()) {
+            p.overflow = true;
+            return;
+        }
+        idx = (long)p.used;
+        p.used += 2;
+        p.units += units;
+        p.launches++;
+        (void)hipEventRecord(p.ev[idx], s);
+    }
+    ~ProfScope()
+    {
+        if (idx >= 0) (void)hipEventRecord(ctx->prof.ev[idx + 1], s);
+    }
+};
 
 // ----------------------------------------------------------- launchers
 

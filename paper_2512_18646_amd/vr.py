@@ -73,6 +73,7 @@ _SIGS = {
     "vr_mod_drop": [P, P, U32, PP, P],
     "vr_rotate": [P, P, P, I32, PP, P],
     "vr_rotate_many": [P, P, P, P, SZ, PP, P],
+    "vr_rotate_batch": [P, P, PP, SZ, I32, PP, P],
     "vr_matmul": [P, P, PP, PP, U32, U32, U32, PP, P],
     "vr_conv2d": [P, P, PP, U32, U32, U32, U32, P, P, U32, U32, U32, PP, P],
     "vr_square": [P, P, PP, SZ, PP, P],
@@ -86,6 +87,9 @@ _SIGS = {
     "vr_ct_meta": [P, P, P, P],
     "vr_swk_export": [P, P, U32, P, SZ],
     "vr_ntt": [P, P, U32, P, ctypes.c_int, P],
+    "vr_profile_start": [P, ctypes.c_char_p, SZ],
+    "vr_profile_stop": [P, ctypes.POINTER(DBL), ctypes.POINTER(U64), ctypes.POINTER(U64),
+                        ctypes.POINTER(U32)],
     "vr_context_destroy": [P],
     "vr_free_ciphertext": [P],
     "vr_free_plaintext": [P],
@@ -255,6 +259,16 @@ class Context:
     def set_stream(self, stream):
         _check(lib.vr_context_set_stream(self.h, _stream(stream)))
 
+    def profile_start(self, kernel_class, max_launches=65536):
+        _check(lib.vr_profile_start(self.h, kernel_class.encode(), max_launches))
+
+    def profile_stop(self):
+        """(total_ms, launches, units, dropped) of the profiled kernel class."""
+        ms, la, un, dr = DBL(), U64(), U64(), U32()
+        _check(lib.vr_profile_stop(self.h, ctypes.byref(ms), ctypes.byref(la), ctypes.byref(un),
+                                   ctypes.byref(dr)))
+        return ms.value, la.value, un.value, bool(dr.value)
+
     # ------------------------------------------------------------ client
     def keygen(self, seed, rot_steps=()):
         st = np.ascontiguousarray(np.asarray(list(rot_steps), dtype=np.int32))
@@ -348,6 +362,12 @@ class Context:
         arr = (ctypes.c_void_p * max(1, st.size))()
         _check(lib.vr_rotate_many(self.h, keys.ek, a.h, st.ctypes.data, st.size, arr, _stream(stream)))
         return [Ciphertext(arr[i], self) for i in range(st.size)]
+
+    def rotate_batch(self, keys, cts, step, stream=None):
+        arr = (ctypes.c_void_p * len(cts))()
+        _check(lib.vr_rotate_batch(self.h, keys.ek, _ptr_array(cts), len(cts), int(step), arr,
+                                   _stream(stream)))
+        return [Ciphertext(arr[i], self) for i in range(len(cts))]
 
     # ------------------------------------------------------------ layers
     def matmul(self, keys, A, Bbar, m, n, p, stream=None):
