@@ -45,20 +45,40 @@ struct ConvArgs {
     const ModQ* mq;
 };
 
+constexpr int kMaxOut = 48;
+
+// Constants are staged in LDS per block (qhat [n_out][n_in] transposed so one
+// output's row is contiguous, plus q, 2^64 mod q and the Shoup companions of
+// each target), then every thread converts one coefficient.
 __global__ __launch_bounds__(kThreads) void k_base_convert(ConvArgs a)
 {
+    __shared__ u64 s_qhat[kMaxIn * kMaxOut];
+    __shared__ u64 s_out[kMaxOut * 5];   // q, r64, r64_s, one_s, negq
     const u32 n = 1u << a.log_n;
-    const u32 t = blockIdx.x * kThreads + threadIdx.x;
-    if (t >= n) return;
     const u32 poly = blockIdx.y;
-    const u64* in = a.in + (size_t)poly * a.in_stride;
-    u64* out = a.out + (size_t)poly * a.out_stride;
     const u64* qinv = a.tab;
     const u64* qinv_s = a.tab + a.n_in;
     const u64* qhat = a.tab + 2 * a.n_in;
     const u64* negq = qhat + (size_t)a.n_in * a.n_out;
     const u64* in_mod = negq + a.n_out;
     const u64* out_mod = in_mod + a.n_in;
+    for (u32 e = threadIdx.x; e < a.n_in * a.n_out; e += kThreads) {
+        u32 i = e / a.n_out, o = e - i * a.n_out;
+        s_qhat[o * a.n_in + i] = qhat[e];
+    }
+    for (u32 o = threadIdx.x; o < a.n_out; o += kThreads) {
+        const ModQ& m = a.mq[out_mod[o]];
+        s_out[5 * o] = m.q;
+        s_out[5 * o + 1] = m.r64;
+        s_out[5 * o + 2] = m.r64_s;
+        s_out[5 * o + 3] = m.one_s;
+        s_out[5 * o + 4] = negq[o];
+    }
+    __syncthreads();
+    const u32 t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const u64* in = a.in + (size_t)poly * a.in_stride;
+    u64* out = a.out + (size_t)poly * a.out_stride;
 
     u64 y[kMaxIn];
     u64 n_neg = 0;
@@ -71,46 +91,71 @@ __global__ __launch_bounds__(kThreads) void k_base_convert(ConvArgs a)
             y[i] = v;
         }
     }
+#pragma unroll 2
     for (u32 o = 0; o < a.n_out; o++) {
-        const ModQ m = a.mq[out_mod[o]];
+        const u64* c = s_out + 5 * o;
         u64 hi = 0, lo = 0;
-        mac128(hi, lo, n_neg, negq[o]);
+        mac128(hi, lo, n_neg, c[4]);
+        const u64* qh = s_qhat + o * a.n_in;
 #pragma unroll
         for (int i = 0; i < kMaxIn; i++)
-            if (i < (int)a.n_in) mac128(hi, lo, y[i], qhat[(size_t)i * a.n_out + o]);
+            if (i < (int)a.n_in) mac128(hi, lo, y[i], qh[i]);
+        const u64 q = c[0];
+        u64 r = shoup_lazy(hi, c[1], c[2], q) + shoup_lazy(lo, 1, c[3], q);
+        r = csub(r, 2 * q);
         u32 slot = o < a.skip_at ? o : o + a.skip_len;
-        out[(size_t)slot * n + t] = reduce128(hi, lo, m);
+        out[(size_t)slot * n + t] = csub(r, q);
     }
 }
 
+// One block = 256 consecutive outputs of extended limb e.  With a Galois
+// element g != 1 the block's sources form one contiguous 256-word chunk of
+// every digit (the top index bits of the bit-reversed order map among
+// themselves under X -> X^g), which the block stages in LDS with coalesced
+// loads before the per-thread gather (for N < 256 the chunk is the limb).
 template <int MAXB>
 __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_stride, u32 n_ct,
                                                       const u64* key, u32 nmod, u32 level,
                                                       u32 next, u32 beta, u32 L, u32 log_n, u32 g,
                                                       u64* U, u64 u_stride, const ModQ* mq)
 {
+    __shared__ u64 stage[MAXB * kThreads];
     const u32 n = 1u << log_n;
+    const u32 csize = n < (u32)kThreads ? n : (u32)kThreads;
     const u32 t = blockIdx.x * kThreads + threadIdx.x;
-    if (t >= n) return;
+    const bool active = t < n;
     const u32 e = blockIdx.y;
     const u32 mod = e <= level ? e : L + 1 + (e - level - 1);
     const ModQ m = mq[mod];
-    const u32 src = g == 1 ? t : galois_src(t, g, log_n);
+    const bool perm = g != 1;
+    const u32 src = perm && active ? galois_src(t, g, log_n) : t;
+    const u32 chunk = perm ? (galois_src(blockIdx.x * kThreads, g, log_n) & ~(csize - 1)) : 0;
     u64 kb[MAXB], ka[MAXB];
 #pragma unroll
     for (int j = 0; j < MAXB; j++) {
-        if (j < (int)beta) {
+        if (j < (int)beta && active) {
             kb[j] = key[((size_t)(2 * j) * nmod + mod) * n + t];
             ka[j] = key[((size_t)(2 * j + 1) * nmod + mod) * n + t];
         }
     }
     for (u32 c = 0; c < n_ct; c++) {
-        const u64* x = X + (size_t)c * x_stride + (size_t)e * n + src;
+        const u64* xc = X + (size_t)c * x_stride + (size_t)e * n;
+        if (perm) {
+            __syncthreads();
+            if (threadIdx.x < csize) {
+#pragma unroll
+                for (int j = 0; j < MAXB; j++)
+                    if (j < (int)beta)
+                        stage[j * kThreads + threadIdx.x] = xc[(size_t)j * next * n + chunk + threadIdx.x];
+            }
+            __syncthreads();
+        }
+        if (!active) continue;
         u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
 #pragma unroll
         for (int j = 0; j < MAXB; j++) {
             if (j < (int)beta) {
-                u64 xv = x[(size_t)j * next * n];
+                u64 xv = perm ? stage[j * kThreads + (src - chunk)] : xc[(size_t)j * next * n + t];
                 mac128(h0, l0, xv, kb[j]);
                 mac128(h1, l1, xv, ka[j]);
             }
@@ -166,6 +211,7 @@ ConvTable build_table(vr_context* ctx, const std::vector<u32>& in, const std::ve
     tb.n_in = (u32)in.size();
     tb.n_out = (u32)out.size();
     if (tb.n_in > (u32)kMaxIn) throw Error(VR_EINVAL, "base conversion: too many input moduli");
+    if (tb.n_out > (u32)kMaxOut) throw Error(VR_EINVAL, "base conversion: too many output moduli");
     std::vector<u64> h;
     h.resize(2 * tb.n_in + (size_t)tb.n_in * tb.n_out + tb.n_out + tb.n_in + tb.n_out);
     u64* qinv = h.data();

@@ -102,12 +102,14 @@ struct Term {
     u32 w_idx;    // weight row
 };
 
-// out[o] = sum_{terms of o} w * in  (+ bias on component 0), 2 components
-__global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride,
-                                                      const u64* const* in_ptrs, const Term* terms,
-                                                      const u32* term_off, const u64* w,
-                                                      const u64* ws, const u64* bias, u32 nl,
-                                                      u32 log_n, const ModQ* mq)
+// out[o] = sum_{terms of o} w * in  (+ bias on component 0), 2 components.
+// Input index i: ciphertext i of slab x when i < n_x, else ciphertext i - n_x
+// of slab r (both with stride `stride`).
+__global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, const u64* x,
+                                                      const u64* r, u32 n_x, u64 stride,
+                                                      const Term* terms, const u32* term_off,
+                                                      const u64* w, const u64* ws, const u64* bias,
+                                                      u32 nl, u32 log_n, const ModQ* mq)
 {
     const u32 n = 1u << log_n;
     const u32 t = blockIdx.x * kThreads + threadIdx.x;
@@ -120,8 +122,10 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride,
     const u32 a = term_off[o], b = term_off[o + 1];
     for (u32 k = a; k < b; k++) {
         Term tm = terms[k];
-        u64 x = in_ptrs[tm.in_idx][(size_t)row * n + t];
-        acc += shoup_lazy(x, w[(size_t)tm.w_idx * nl + l], ws[(size_t)tm.w_idx * nl + l], q);
+        const u64* src = tm.in_idx < n_x ? x + (size_t)tm.in_idx * stride
+                                         : r + (size_t)(tm.in_idx - n_x) * stride;
+        u64 xv = src[(size_t)row * n + t];
+        acc += shoup_lazy(xv, w[(size_t)tm.w_idx * nl + l], ws[(size_t)tm.w_idx * nl + l], q);
         acc = acc >= q2 ? acc - q2 : acc;
     }
     if (bias && row < nl) acc += bias[(size_t)o * nl + l];
@@ -235,8 +239,12 @@ void rotate_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in,
     u64* U = as_u64(ubuf);
     u64* md = U + (size_t)n_ct * us;
     out.clear();
+    // every step's output in one allocation: step si at all.base + si * n_ct * stride
+    Slab all = new_slab(ctx, n_ct * (u32)steps.size(), 2, level, in.scale, s);
     for (size_t si = 0; si < steps.size(); si++) {
-        Slab r = new_slab(ctx, n_ct, 2, level, in.scale, s);
+        Slab r = all;
+        r.n = n_ct;
+        r.base = all.base + si * n_ct * all.stride;
         if (gs[si] == 1) {
             VR_HIP(hipMemcpyAsync(r.base, in.base, (size_t)n_ct * in.stride * sizeof(u64),
                                   hipMemcpyDeviceToDevice, s));
@@ -297,6 +305,82 @@ u32 pow2ceil(u32 x)
     u32 p = 1;
     while (p < x) p <<= 1;
     return p;
+}
+
+// Device-resident constants of one conv layer call: weights [RHA(K q_l)]_{q_i}
+// with Shoup companions (one row per (c', c, u, v)), the AddConst value per
+// output and limb, and the term list (input index, weight row) per output.
+// Input (u, c, j) has index u * C_in * w + c * w + j.
+struct ConvPlan {
+    BufPtr buf;
+    const Term* terms = nullptr;
+    const u32* off = nullptr;
+    const u64 *w = nullptr, *ws = nullptr, *bias = nullptr;
+};
+
+const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const double* K,
+                          const double* bias, u32 C_out, u32 k, u32 stride, u32 level, double out_scale)
+{
+    const u32 wo = (w + 2 * pad - k) / stride + 1, nl = level + 1;
+    const size_t nw = (size_t)C_out * C_in * k * k;
+    std::string key = "conv:";
+    u32 shape[7] = {C_in, w, pad, C_out, k, stride, level};
+    key.append((const char*)shape, sizeof shape);
+    key.append((const char*)&out_scale, sizeof out_scale);
+    key.append((const char*)K, nw * sizeof(double));
+    key.append((const char*)bias, C_out * sizeof(double));
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto it = ctx->plans.find(key);
+    if (it != ctx->plans.end()) return *(const ConvPlan*)it->second.get();
+
+    const double dq = (double)ctx->mod[level];
+    std::vector<u64> wv(nw * nl), wsv(nw * nl), bv((size_t)C_out * wo * nl);
+    for (size_t r = 0; r < nw; r++)
+        for (u32 l = 0; l < nl; l++) {
+            wv[r * nl + l] = double_to_mod(K[r] * dq, ctx->mod[l]);
+            wsv[r * nl + l] = shoup_companion(wv[r * nl + l], ctx->mod[l]);
+        }
+    for (u32 co = 0; co < C_out; co++)
+        for (u32 l = 0; l < nl; l++) {
+            u64 b = double_to_mod(bias[co] * out_scale, ctx->mod[l]);
+            for (u32 jo = 0; jo < wo; jo++) bv[((size_t)co * wo + jo) * nl + l] = b;
+        }
+    std::vector<Term> terms;
+    std::vector<u32> off(1, 0);
+    for (u32 co = 0; co < C_out; co++)
+        for (u32 jo = 0; jo < wo; jo++) {
+            for (u32 c = 0; c < C_in; c++)
+                for (u32 v = 0; v < k; v++) {
+                    int jj = (int)(stride * jo + v) - (int)pad;
+                    if (jj < 0 || jj >= (int)w) continue;
+                    for (u32 u = 0; u < k; u++)
+                        terms.push_back({(u32)(((size_t)u * C_in + c) * w + jj),
+                                         (u32)((((size_t)co * C_in + c) * k + u) * k + v)});
+                }
+            off.push_back((u32)terms.size());
+        }
+    // one device buffer: terms | off | w | ws | bias (8-byte aligned parts)
+    size_t b_terms = terms.size() * sizeof(Term), b_off = ((off.size() * 4 + 7) / 8) * 8;
+    size_t total = b_terms + b_off + (wv.size() + wsv.size() + bv.size()) * 8;
+    auto plan = std::make_shared<ConvPlan>();
+    VR_HIP(hipDeviceSynchronize());
+    plan->buf = dev_alloc(ctx, total, nullptr);
+    char* base = (char*)plan->buf->ptr;
+    std::vector<char> h(total, 0);
+    memcpy(h.data(), terms.data(), b_terms);
+    memcpy(h.data() + b_terms, off.data(), off.size() * 4);
+    size_t o = b_terms + b_off;
+    memcpy(h.data() + o, wv.data(), wv.size() * 8);
+    memcpy(h.data() + o + wv.size() * 8, wsv.data(), wsv.size() * 8);
+    memcpy(h.data() + o + (wv.size() + wsv.size()) * 8, bv.data(), bv.size() * 8);
+    VR_HIP(hipMemcpy(base, h.data(), total, hipMemcpyHostToDevice));
+    plan->terms = (const Term*)base;
+    plan->off = (const u32*)(base + b_terms);
+    plan->w = (const u64*)(base + o);
+    plan->ws = plan->w + wv.size();
+    plan->bias = plan->ws + wsv.size();
+    ctx->plans[key] = plan;
+    return *plan;
 }
 
 }  // namespace
@@ -520,59 +604,21 @@ vr_status vr_conv2d(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext
     for (u32 u = 1; u < k; u++) steps.push_back((int32_t)u);
     std::vector<Slab> rot;
     if (!steps.empty()) rotate_slab(ctx, ek, x, steps, rot, s);
-    // pointer table: input (u, c, j) at index u * C_in * w + c * w + j
-    std::vector<const u64*> ptrs((size_t)k * C_in * w);
-    for (u32 u = 0; u < k; u++)
-        for (u32 c = 0; c < C_in; c++)
-            for (u32 j = 0; j < w; j++)
-                ptrs[((size_t)u * C_in + c) * w + j] = u == 0 ? x.ct(c * w + j) : rot[u - 1].ct(c * w + j);
-    // weights as [RHA(K q_l)]_{q_i}, one row per (c', c, u, v)
     const double dq = (double)ctx->mod[level];
-    const size_t nw = (size_t)C_out * C_in * k * k;
-    std::vector<u64> wv(nw * nl), wsv(nw * nl), bv((size_t)C_out * wo * nl);
-    for (size_t r = 0; r < nw; r++)
-        for (u32 l = 0; l < nl; l++) {
-            wv[r * nl + l] = double_to_mod(K[r] * dq, ctx->mod[l]);
-            wsv[r * nl + l] = shoup_companion(wv[r * nl + l], ctx->mod[l]);
-        }
     const double out_scale = x.scale * dq;
-    // one bias row per output ciphertext (c', j')
-    for (u32 co = 0; co < C_out; co++)
-        for (u32 l = 0; l < nl; l++) {
-            u64 b = double_to_mod(bias[co] * out_scale, ctx->mod[l]);
-            for (u32 jo = 0; jo < wo; jo++) bv[((size_t)co * wo + jo) * nl + l] = b;
-        }
-    std::vector<Term> terms;
-    std::vector<u32> off(1, 0);
-    for (u32 co = 0; co < C_out; co++)
-        for (u32 jo = 0; jo < wo; jo++) {
-            for (u32 c = 0; c < C_in; c++)
-                for (u32 v = 0; v < k; v++) {
-                    int jj = (int)(stride * jo + v) - (int)pad;
-                    if (jj < 0 || jj >= (int)w) continue;
-                    for (u32 u = 0; u < k; u++)
-                        terms.push_back({(u32)(((size_t)u * C_in + c) * w + jj),
-                                         (u32)((((size_t)co * C_in + c) * k + u) * k + v)});
-                }
-            off.push_back((u32)terms.size());
-        }
-    BufPtr hp, ht, ho, hw, hws, hb;
-    const u64* const* dptrs = upload_async(ctx, ptrs, hp, s);
-    const Term* dterms = upload_async(ctx, terms, ht, s);
-    const u32* doff = upload_async(ctx, off, ho, s);
-    const u64* dw = upload_async(ctx, wv, hw, s);
-    const u64* dws = upload_async(ctx, wsv, hws, s);
-    const u64* db = upload_async(ctx, bv, hb, s);
+    const ConvPlan& plan = conv_plan(ctx, C_in, w, pad, K, bias, C_out, k, stride, level, out_scale);
     const u32 n_out = C_out * wo;
     Slab acc = new_slab(ctx, n_out, 2, level, out_scale, s);
     dim3 grid((ctx->n + kThreads - 1) / kThreads, n_out * 2 * nl);
-    ProfScope prof(ctx, kProfLincomb, s, (u64)n_out * 2 * nl);
-    hipLaunchKernelGGL(k_lincomb, grid, dim3(kThreads), 0, s, acc.base, acc.stride, dptrs, dterms,
-                       doff, dw, dws, db, nl, ctx->log_n, ctx->d_modq);
-    VR_CHECK_LAUNCH();
+    {
+        ProfScope prof(ctx, kProfLincomb, s, (u64)n_out * 2 * nl);
+        // inputs: (u = 0) the columns themselves, (u >= 1) the rotation slabs
+        hipLaunchKernelGGL(k_lincomb, grid, dim3(kThreads), 0, s, acc.base, acc.stride, x.base,
+                           rot.empty() ? x.base : rot[0].base, C_in * w, x.stride, plan.terms,
+                           plan.off, plan.w, plan.ws, plan.bias, nl, ctx->log_n, ctx->d_modq);
+        VR_CHECK_LAUNCH();
+    }
     Slab y = rescale_slab(ctx, acc, s);
-    // host staging vectors must outlive the async copies
-    VR_HIP(hipStreamSynchronize(s));
     to_handles(ctx, y, out);
     API_END
 }

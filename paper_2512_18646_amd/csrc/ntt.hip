@@ -1,20 +1,27 @@
 // Negacyclic NTT / inverse NTT on gfx950.
 //
 // Transform: out[i] = sum_t a_t psi^((2 brev(i) + 1) t) mod q (bit-reversed
-// evaluation order), computed as the radix-2 Cooley-Tukey network with merged
-// psi twiddles; the inverse is the Gentleman-Sande network with inverse
-// twiddles followed by N^-1.
+// evaluation order), the radix-2 Cooley-Tukey network with merged psi
+// twiddles; the inverse is the Gentleman-Sande network with inverse twiddles
+// followed by N^-1.
 //
-// A limb is N uint64 (64 KiB at N = 2^13, 128 KiB at 2^14, 512 KiB at 2^16).
-// Up to 2^14 one workgroup holds a whole limb in LDS (160 KiB per CU) and runs
-// every stage there: one HBM read and one write per limb.  At 2^15 and 2^16 the
-// limb does not fit, so the stages split in two passes over groups of
-// 2^log_g elements: the first pass works on strided groups (the high index bits
-// vary) with 16-32 consecutive groups per workgroup so every row read is a
-// coalesced 128-256 byte segment; the second pass on contiguous blocks.
-// Butterflies use Shoup products with precomputed twiddle companions and lazy
-// reduction (forward values in [0, 4q), inverse in [0, 2q); Harvey 2014),
-// reduced to [0, q) only when the last pass stores.
+// Layout.  A limb is N uint64 (64 KiB at N = 2^13, 128 KiB at 2^14, 512 KiB at
+// 2^16).  Up to 2^14 one workgroup holds a whole limb in LDS (160 KiB per CU)
+// and runs every stage there: one HBM read and one write per limb.  At 2^15
+// and 2^16 the stages split in two passes over groups of 2^7-2^8 elements; the
+// first pass works on strided groups with 16-32 consecutive groups per
+// workgroup so each row read is a coalesced 128-256 byte segment, the second
+// on contiguous blocks.
+//
+// Compute.  Inside a pass the stages run in rounds of up to four: each thread
+// pulls a 16-element group (elements that differ only in the four index bits
+// those stages touch) from LDS into registers, issues the 15 twiddle loads of
+// the round at once (16-byte (w, w') pairs, w' = floor(w 2^64 / q)), runs the
+// 32 butterflies, and writes the group back: one LDS round trip and one
+// barrier per four stages.  LDS rows are padded by one word every 16 so the
+// stride-16 group reads of the last round do not collide on banks.  Shoup
+// products with lazy reduction keep forward values in [0, 4q) and inverse
+// values in [0, 2q) (Harvey 2014); the last pass stores [0, q).
 #include "vr_core.h"
 
 namespace vr {
@@ -22,8 +29,7 @@ namespace vr {
 struct NttPass {
     LimbSet ls;
     const ModQ* mq;
-    const u64* tw;      // [nmod][N]
-    const u64* tw_s;
+    const u64* tw;      // [nmod][N][2]
     u32 log_n, L;
     u32 s0, log_g, log_c;
     u32 first, last;
@@ -48,6 +54,90 @@ __device__ __forceinline__ void limb_addr(const LimbSet& ls, u32 r, u32 n, u32 L
     *out = ls.out_dense ? ls.out + (size_t)r * n : ls.out + off;
 }
 
+__device__ __forceinline__ u32 pad(u32 i) { return i + (i >> 4); }
+
+// One round of R stages (local stages sg0 .. sg0+R-1 of the pass) over every
+// 2^R-element group of the tile.
+template <int R, bool INV, int THREADS>
+__device__ __forceinline__ void ntt_round(u64* lds, const u64* tw, u64 q, u32 log_g, u32 log_c,
+                                          u32 sg0, u32 s_pass, u32 g0, u32 lo_bits)
+{
+    constexpr int E = 1 << R;
+    const u32 G = 1u << log_g;
+    const u32 low_bits = log_g - sg0 - R;
+    const u32 ngroups = (G >> R) << log_c;
+    const u64 q2 = 2 * q;
+    for (u32 f = threadIdx.x; f < ngroups; f += THREADS) {
+        const u32 c = f >> (log_g - R);
+        const u32 gid = f & ((G >> R) - 1);
+        const u32 hi = gid >> low_bits;
+        const u32 lo = gid & ((1u << low_bits) - 1);
+        const u32 base = c * G + (hi << (log_g - sg0)) + lo;
+        const u32 H = (g0 + c) >> lo_bits;
+        const u32 hprefix = (H << sg0) | hi;
+        // stage k of the round uses the 2^k consecutive twiddles starting at
+        // 2^(s_pass + sg0 + k) + (hprefix << k)
+        const ulonglong2* twp = (const ulonglong2*)tw;
+        u64 x[E];
+#pragma unroll
+        for (int m = 0; m < E; m++) x[m] = lds[pad(base + ((u32)m << low_bits))];
+        if (!INV) {
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                const int half = 1 << (R - 1 - k);
+                const u32 tb = (1u << (s_pass + sg0 + k)) + (hprefix << k);
+#pragma unroll
+                for (int j = 0; j < (1 << k); j++) {
+                    const ulonglong2 t = twp[tb + j];
+                    const u64 wv = t.x, wsv = t.y;
+#pragma unroll
+                    for (int i = 0; i < half; i++) {
+                        const int m1 = (j << (R - k)) + i, m2 = m1 + half;
+                        u64 X = x[m1];
+                        X = X >= q2 ? X - q2 : X;
+                        u64 T = shoup_lazy(x[m2], wv, wsv, q);
+                        x[m1] = X + T;
+                        x[m2] = X + q2 - T;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = R - 1; k >= 0; k--) {
+                const int half = 1 << (R - 1 - k);
+                const u32 tb = (1u << (s_pass + sg0 + k)) + (hprefix << k);
+#pragma unroll
+                for (int j = 0; j < (1 << k); j++) {
+                    const ulonglong2 t = twp[tb + j];
+                    const u64 wv = t.x, wsv = t.y;
+#pragma unroll
+                    for (int i = 0; i < half; i++) {
+                        const int m1 = (j << (R - k)) + i, m2 = m1 + half;
+                        u64 X = x[m1], Y = x[m2];
+                        u64 S = X + Y;
+                        x[m1] = S >= q2 ? S - q2 : S;
+                        x[m2] = shoup_lazy(X + q2 - Y, wv, wsv, q);
+                    }
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < E; m++) lds[pad(base + ((u32)m << low_bits))] = x[m];
+    }
+}
+
+template <bool INV, int THREADS>
+__device__ __forceinline__ void run_round(u32 r, u64* lds, const u64* tw, u64 q, u32 log_g,
+                                          u32 log_c, u32 sg0, u32 s_pass, u32 g0, u32 lo_bits)
+{
+    switch (r) {
+    case 4: ntt_round<4, INV, THREADS>(lds, tw, q, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
+    case 3: ntt_round<3, INV, THREADS>(lds, tw, q, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
+    case 2: ntt_round<2, INV, THREADS>(lds, tw, q, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
+    default: ntt_round<1, INV, THREADS>(lds, tw, q, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
+    }
+}
+
 template <int THREADS, bool INV>
 __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
 {
@@ -68,8 +158,7 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
     if (!p.first) src = dst;
     const ModQ m = p.mq[mod];
     const u64 q = m.q, q2 = 2 * m.q;
-    const u64* tw = p.tw + (size_t)mod * n;
-    const u64* tws = p.tw_s + (size_t)mod * n;
+    const u64* tw = p.tw + (size_t)mod * n * 2;
 
     // coalesced load: consecutive threads take consecutive addresses
     const bool strided = lo_bits > 0;
@@ -80,49 +169,22 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
         u32 g = g0 + c;
         u32 H = g >> lo_bits, Lo = g & ((1u << lo_bits) - 1);
         size_t idx = ((size_t)H << (p.log_n - p.s0)) + ((size_t)v << lo_bits) + Lo;
-        lds[c * G + v] = src[idx];
+        lds[pad(c * G + v)] = src[idx];
     }
     __syncthreads();
 
-    const u32 half = tile >> 1;
     if (!INV) {
-        for (u32 sg = 0; sg < p.log_g; sg++) {
-            const u32 t = G >> (sg + 1);
-            const u32 s = p.s0 + sg;
-            for (u32 b = threadIdx.x; b < half; b += THREADS) {
-                u32 c = b >> (p.log_g - 1);
-                u32 k = b & ((G >> 1) - 1);
-                u32 v1 = ((k & ~(t - 1)) << 1) | (k & (t - 1));
-                u32 H = (g0 + c) >> lo_bits;
-                u32 ti = (1u << s) + (H << sg) + (v1 >> (p.log_g - sg));
-                u64 w = tw[ti], ws = tws[ti];
-                u64 X = lds[c * G + v1];
-                u64 Y = lds[c * G + v1 + t];
-                X = X >= q2 ? X - q2 : X;
-                u64 T = shoup_lazy(Y, w, ws, q);
-                lds[c * G + v1] = X + T;
-                lds[c * G + v1 + t] = X + q2 - T;
-            }
+        for (u32 sg0 = 0; sg0 < p.log_g;) {
+            u32 rr = p.log_g - sg0 < 4 ? p.log_g - sg0 : 4;
+            run_round<false, THREADS>(rr, lds, tw, q, p.log_g, p.log_c, sg0, p.s0, g0, lo_bits);
+            sg0 += rr;
             __syncthreads();
         }
     } else {
-        for (int sg = (int)p.log_g - 1; sg >= 0; sg--) {
-            const u32 t = G >> (sg + 1);
-            const u32 s = p.s0 + sg;
-            for (u32 b = threadIdx.x; b < half; b += THREADS) {
-                u32 c = b >> (p.log_g - 1);
-                u32 k = b & ((G >> 1) - 1);
-                u32 v1 = ((k & ~(t - 1)) << 1) | (k & (t - 1));
-                u32 H = (g0 + c) >> lo_bits;
-                u32 ti = (1u << s) + (H << sg) + (v1 >> (p.log_g - sg));
-                u64 w = tw[ti], ws = tws[ti];
-                u64 X = lds[c * G + v1];
-                u64 Y = lds[c * G + v1 + t];
-                u64 S = X + Y;
-                S = S >= q2 ? S - q2 : S;
-                lds[c * G + v1] = S;
-                lds[c * G + v1 + t] = shoup_lazy(X + q2 - Y, w, ws, q);
-            }
+        for (u32 top = p.log_g; top > 0;) {
+            u32 rr = top < 4 ? top : 4;
+            run_round<true, THREADS>(rr, lds, tw, q, p.log_g, p.log_c, top - rr, p.s0, g0, lo_bits);
+            top -= rr;
             __syncthreads();
         }
     }
@@ -134,7 +196,7 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
         u32 g = g0 + c;
         u32 H = g >> lo_bits, Lo = g & ((1u << lo_bits) - 1);
         size_t idx = ((size_t)H << (p.log_n - p.s0)) + ((size_t)v << lo_bits) + Lo;
-        u64 x = lds[c * G + v];
+        u64 x = lds[pad(c * G + v)];
         if (p.last) {
             if (!INV) {
                 x = x >= q2 ? x - q2 : x;
@@ -168,7 +230,7 @@ void launch_pass(const NttPass& p, u32 n_limbs, hipStream_t s)
     if (threads < 64) threads = 64;
     if (threads > 1024) threads = 1024;
     u32 blocks = n_limbs * ((1u << (p.log_n - p.log_g - p.log_c)));
-    size_t shmem = (size_t)tile * sizeof(u64);
+    size_t shmem = (size_t)(tile + tile / 16) * sizeof(u64);
     switch (threads) {
 #define VR_NTT_CASE(T)                                                                          \
     case T: {                                                                                   \
@@ -204,7 +266,6 @@ void run(vr_context* ctx, const LimbSet& ls, hipStream_t s)
     p.ls = ls;
     p.mq = ctx->d_modq;
     p.tw = INV ? ctx->d_itw : ctx->d_tw;
-    p.tw_s = INV ? ctx->d_itw_s : ctx->d_tw_s;
     p.log_n = ctx->log_n;
     p.L = ctx->L;
     size_t np = passes.size();

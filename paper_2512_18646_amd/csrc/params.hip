@@ -156,8 +156,7 @@ void build_context(vr_context* ctx, const vr_params* p, int device)
 
     const u32 n = ctx->n, nmod = ctx->nmod();
     ctx->modq.resize(nmod);
-    std::vector<u64> tw((size_t)nmod * n), tws((size_t)nmod * n), itw((size_t)nmod * n),
-        itws((size_t)nmod * n);
+    std::vector<u64> tw((size_t)nmod * n * 2), itw((size_t)nmod * n * 2);
     std::vector<u64> pw(n), ipw(n);
     for (u32 m = 0; m < nmod; m++) {
         u64 q = ctx->mod[m];
@@ -188,18 +187,16 @@ void build_context(vr_context* ctx, const vr_params* p, int device)
         }
         for (u32 k = 0; k < n; k++) {
             u32 e = bitrev(k, p->log_n);
-            size_t at = (size_t)m * n + k;
+            size_t at = 2 * ((size_t)m * n + k);
             tw[at] = pw[e];
-            tws[at] = shoup_companion(pw[e], q);
+            tw[at + 1] = shoup_companion(pw[e], q);
             itw[at] = ipw[e];
-            itws[at] = shoup_companion(ipw[e], q);
+            itw[at + 1] = shoup_companion(ipw[e], q);
         }
     }
     ctx->d_modq = upload(ctx->modq);
     ctx->d_tw = upload(tw);
-    ctx->d_tw_s = upload(tws);
     ctx->d_itw = upload(itw);
-    ctx->d_itw_s = upload(itws);
 
     // FFT twiddles e^{-2 pi i k / 2N}, k < N, as (re, im) pairs
     std::vector<double> ft(2 * (size_t)n);
@@ -223,9 +220,7 @@ void destroy_context_tables(vr_context* ctx)
 {
     (void)hipFree(ctx->d_modq);
     (void)hipFree(ctx->d_tw);
-    (void)hipFree(ctx->d_tw_s);
     (void)hipFree(ctx->d_itw);
-    (void)hipFree(ctx->d_itw_s);
     (void)hipFree(ctx->d_fft_tw);
     (void)hipFree(ctx->d_gexp);
     for (auto& kv : ctx->modup_tables) (void)hipFree(kv.second.dev);

@@ -191,15 +191,16 @@ struct vr_context {
     std::vector<vr::u64> mod;         // q_0..q_L, p_0..p_{K-1}
     std::vector<vr::ModQ> modq;       // host copy
     vr::ModQ* d_modq = nullptr;
-    vr::u64* d_tw = nullptr;          // [nmod][N] psi^brev(k)
-    vr::u64* d_tw_s = nullptr;
-    vr::u64* d_itw = nullptr;         // [nmod][N] psi^-brev(k)
-    vr::u64* d_itw_s = nullptr;
+    vr::u64* d_tw = nullptr;          // [nmod][N][2] (psi^brev(k), Shoup companion)
+    vr::u64* d_itw = nullptr;         // [nmod][N][2] (psi^-brev(k), Shoup companion)
     double* d_fft_tw = nullptr;       // [N] complex e^{-2 pi i k / 2N}
     int* d_gexp = nullptr;            // [S] 5^j mod 2N
     vr::u64 cdt[20];
     std::map<std::pair<int, int>, vr::ConvTable> modup_tables;   // (level, digit)
     std::map<int, vr::ConvTable> moddown_tables;                 // level
+    // device-resident constants of layer calls (weights, term lists), keyed by
+    // the call's shape and weight bytes, so repeated calls upload nothing
+    std::map<std::string, std::shared_ptr<void>> plans;
     std::mutex mu;
     hipStream_t stream = nullptr;     // used when a call passes stream = NULL
     vr::Profiler prof;
