@@ -52,8 +52,71 @@ def conv_setup(vr, level, sets):
 
 
 def step_batched(ctx, keys, W, K, bias, cols):
-    return [ctx.square(keys, ctx.conv2d(keys, c, W.channels, W.h, W.w, W.pad, K, bias, W.stride))
-            for c in cols]
+    """All sets in one multi-set conv call, then x^2 over every output."""
+    flat = [c for cs in cols for c in cs]
+    y = ctx.conv2d_sets(keys, flat, len(cols), W.channels, W.h, W.w, W.pad, K, bias, W.stride)
+    return ctx.square(keys, y)
+
+
+SERVE_MIX = (("28x28", 28, 0.5), ("64x64", 64, 0.3), ("128x128", 128, 0.2))
+
+
+def serving_bench(vr, ctx, keys, n_req, load, level, seed=7):
+    """Poisson arrivals of single-set requests with the 5:3:2 image-size mix
+    (conv 4x4/2 x5 + x^2, one ciphertext set per request) through the
+    continuous-batching server; latency is submit-to-completion."""
+    import synthetic_inputs as SI
+    _, K, bias = SI.CONV_28.draw()
+    srv = vr.Server(ctx, 200 << 30, max_batch=4)
+    sid = srv.register_session(keys)
+    kinds = []
+    for name, hw, _ in SERVE_MIX:
+        mid = srv.register_conv_model(1, hw, hw, 0, K, bias, 2, square=True)
+        B = ctx.slots // (1 << (hw - 1).bit_length())
+        cols = ctx.encrypt_columns(keys, SI.images(seed + hw, B, 1, hw, hw), 0, level, 3000 + hw, 0)
+        kinds.append((name, mid, cols, B))
+    # service time of each kind alone (also warms the cached layer constants)
+    alone_ms, alone_out = [], []
+    for name, mid, cols, B in kinds:
+        srv.poll(srv.submit(sid, mid, cols, B), mid)
+        t = time.perf_counter()
+        alone_out.append(srv.poll(srv.submit(sid, mid, cols, B), mid))
+        alone_ms.append((time.perf_counter() - t) * 1e3)
+    probs = np.array([p for _, _, p in SERVE_MIX])
+    mean_ms = float(np.dot(probs, alone_ms))
+    rate = load * 1e3 / mean_ms          # requests/s offered
+    srv.close()
+    srv = vr.Server(ctx, 200 << 30, max_batch=4)
+    sid = srv.register_session(keys)
+    for name, hw, _ in SERVE_MIX:
+        srv.register_conv_model(1, hw, hw, 0, K, bias, 2, square=True)
+    rng = np.random.default_rng(seed)
+    which = rng.choice(len(kinds), size=n_req, p=probs)
+    gaps = rng.exponential(1.0 / rate, size=n_req)
+    tickets = []
+    t0 = time.perf_counter()
+    due = t0
+    for i in range(n_req):
+        due += gaps[i]
+        delay = due - time.perf_counter()
+        if delay > 0:
+            time.sleep(delay)
+        name, mid, cols, B = kinds[which[i]]
+        tickets.append((srv.submit(sid, mid, cols, B), which[i]))
+    outs = {}
+    for t, k in tickets:
+        outs.setdefault(k, srv.poll(t, kinds[k][1]))
+    st = srv.stats()
+    srv.close()
+    same = all(np.array_equal(outs[k][j].export(), alone_out[k][j].export())
+               for k in outs for j in (0, len(outs[k]) - 1))
+    return {"mix": "5:3:2 of 28x28 (256 img), 64x64 (128 img), 128x128 (64 img) per request, "
+                   "N=2^14 L=7", "requests": n_req, "offered_load": load,
+            "offered_req_per_s": round(rate, 2), "alone_ms": [round(x, 2) for x in alone_ms],
+            "images_per_s": round(st["images_per_s"], 1), "latency_ms_p50": round(st["p50_ms"], 2),
+            "latency_ms_p99": round(st["p99_ms"], 2), "waves": st["waves"],
+            "requests_per_wave": round(st["batched"] / max(st["waves"], 1), 2),
+            "identical_to_alone": bool(same)}
 
 
 def sync():
@@ -135,6 +198,12 @@ def main():
     ap.add_argument("--profile-class", default="ntt")
     ap.add_argument("--no-extra", action="store_true", help="skip per-op, rotation and CPU legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--serve-load", default="0.8,2.0",
+                    help="offered loads, as fractions of the one-request-at-a-time service rate")
+    ap.add_argument("--breakdown", action="store_true",
+                    help="one extra step per kernel class, reporting its device time per step")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X "
@@ -183,9 +252,18 @@ def main():
            "data": "synthetic",
            "config": {"workload": "conv 28x28 4x4/2 x5 + x^2, 256 images per set, N=2^14 L=7 (60+7x40, P 60, dnum 8)",
                       "sets_per_step": args.sets, "images_per_step": images, "level_in": args.level,
-                      "path": "batched layer calls"},
+                      "path": "multi-set conv call + batched x^2"},
            "latency_ms_p50": round(percentile(lat, 50), 3), "latency_ms_p99": round(percentile(lat, 99), 3),
            "roofline": roofline}
+
+    if args.breakdown:
+        bd = {}
+        for cls in ("ntt", "ks_inner", "base_convert", "lincomb", "moddown", "tensor"):
+            ctx.profile_start(cls, 1 << 16)
+            step_batched(ctx, keys, W, K, bias, cols)
+            ms, la, un, _ = ctx.profile_stop()
+            bd[cls] = {"ms": round(ms, 3), "launches": la, "units": un}
+        out["breakdown_per_step"] = bd
 
     if not args.no_extra:
         log("per-op path (one set)")
@@ -196,7 +274,7 @@ def main():
                                                   W.stride))
         sync()
         t_per_op = time.perf_counter() - t
-        ref = step_batched(ctx, keys, W, K, bias, cols[:1])[0]
+        ref = step_batched(ctx, keys, W, K, bias, cols[:1])
         out["per_op_images_per_s"] = round(W.batch / t_per_op, 2)
         out["per_op_identical"] = bool(all(np.array_equal(ys[i].export(), ref[i].export()) for i in (0, 33, 64)))
         out["batched_over_per_op"] = round((W.batch * args.sets / (total / args.steps)) / (W.batch / t_per_op), 2)
@@ -206,6 +284,12 @@ def main():
                                       "level3": rotations_bench(vr, 3, 32, 3)}
         for v in out["rotations_per_s_n16"].values():
             v["batched"], v["per_op"] = round(v["batched"], 1), round(v["per_op"], 1)
+
+    if not args.no_extra and not args.no_serve:
+        log("serving (Poisson arrivals, image-size mix)")
+        out["serving"] = [serving_bench(vr, ctx, keys, args.serve_requests, float(x), args.level)
+                          for x in args.serve_load.split(",")]
+        log("serving done")
 
     if not args.no_extra and not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")

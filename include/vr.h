@@ -19,8 +19,8 @@
  *    returns is new and must be released with the matching vr_free_*.
  *    Inputs are never modified.
  *  - Host pointers (double*, uint64_t*, int32_t*) are read or written before
- *    the call returns.  Device memory behind handles is allocated by the
- *    context (stream-ordered) unless an allocator hook is installed.
+ *    the call returns.  Device memory behind handles comes from the
+ *    context's caching allocator (stream-ordered) unless a hook is set.
  *  - `stream` is a hipStream_t; NULL means the context's stream (the null
  *    stream unless vr_context_set_stream was called).  Server calls only
  *    enqueue work; vr_ct_export, vr_pt_export, vr_decode and the serving poll
@@ -94,11 +94,21 @@ vr_status vr_context_info(const vr_context *ctx, uint32_t *info8, double *defaul
 vr_status vr_context_set_stream(vr_context *ctx, void *stream);
 /* Optional device allocator (e.g. a framework's caching allocator).  Both
  * functions receive the stream the memory is used on and `user`.  NULL
- * restores the built-in stream-ordered pool (hipMallocAsync). */
+ * restores the built-in caching allocator: blocks from hipMalloc are kept
+ * after their handles are freed and reused, stream-ordered, by later calls;
+ * they return to the runtime on vr_context_trim, on a failed hipMalloc, and
+ * when the context and every handle from it are gone.  A handle must be
+ * freed before the stream it was produced on is destroyed. */
 vr_status vr_context_set_allocator(vr_context *ctx,
                                    void *(*alloc_fn)(size_t bytes, void *stream, void *user),
                                    void (*free_fn)(void *ptr, void *stream, void *user),
                                    void *user);
+/* Built-in allocator: bytes held from the runtime and bytes behind live
+ * handles and in-flight work. */
+vr_status vr_context_mem_info(vr_context *ctx, size_t *reserved, size_t *in_use);
+/* Synchronises the device and returns the built-in allocator's cached free
+ * blocks to the runtime. */
+vr_status vr_context_trim(vr_context *ctx);
 const char *vr_last_error(void);
 
 /* ------------------------------------------------------------ client side */
@@ -215,6 +225,14 @@ vr_status vr_conv2d(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext
                     uint32_t C_in, uint32_t h, uint32_t w, uint32_t pad, const double *K,
                     const double *bias, uint32_t C_out, uint32_t k, uint32_t stride,
                     vr_ciphertext **out, void *stream);
+/* The same layer on n_sets independent image sets (mini-batches of the
+ * paper's "Secure Inference" section, each its own C_in*w column set) in one
+ * batched evaluation: in[s*C_in*w + c*w + j], out[s*C_out*w_out + c'*w_out + j'].
+ * Identical limbs to n_sets vr_conv2d calls. */
+vr_status vr_conv2d_sets(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *in,
+                         uint32_t n_sets, uint32_t C_in, uint32_t h, uint32_t w, uint32_t pad,
+                         const double *K, const double *bias, uint32_t C_out, uint32_t k,
+                         uint32_t stride, vr_ciphertext **out, void *stream);
 /* x^2 activation on n ciphertexts: Rescale(Relin(Tensor(y, y))). */
 vr_status vr_square(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *in,
                     size_t n, vr_ciphertext **out, void *stream);
@@ -276,6 +294,59 @@ vr_status vr_profile_start(vr_context *ctx, const char *kernel_class, size_t max
  * unit count and whether launches were dropped; profiling stops. */
 vr_status vr_profile_stop(vr_context *ctx, double *total_ms, uint64_t *launches, uint64_t *units,
                           uint32_t *dropped);
+
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of encrypted inference requests ("Secure Inference":
+ * a model owner evaluates a client's encrypted mini-batches).  A request is
+ * one image set (the C_in*w column ciphertexts of up to B' images, from
+ * vr_encrypt_columns) for a registered model under a session whose keys stay
+ * resident.  A worker thread forms waves: the oldest pending request plus
+ * later pending requests of the same session, model, level and scale, up to
+ * max_batch, while the estimated device bytes of the in-flight waves stay
+ * within the budget.  A wave is one batched multi-set evaluation (as
+ * vr_conv2d_sets, then vr_square when the model has the activation); up to
+ * two waves are in flight, on two streams of their own.  Every request's
+ * output limbs are identical to evaluating it alone.  While a server runs,
+ * the context's other calls may be used from the submitting thread; the
+ * kernel profiler (vr_profile_*) must not be. */
+
+/* hbm_budget_bytes bounds resident session keys plus in-flight requests.
+ * Starts the worker thread.  *out owned by the caller (vr_srv_destroy). */
+vr_status vr_srv_create(vr_context *ctx, size_t hbm_budget_bytes, uint32_t max_batch,
+                        vr_server **out);
+/* Finishes every submitted request, stops the worker, frees the server
+ * (handles already returned by vr_srv_poll stay valid). */
+void vr_srv_destroy(vr_server *srv);
+/* Makes ek's keys resident for later requests (ek must outlive the server).
+ * VR_EBUSY if the keys do not fit the budget. */
+vr_status vr_srv_register_session(vr_server *srv, const vr_eval_keys *ek, uint64_t *session_id);
+/* A conv layer (arguments as vr_conv2d; weights copied) followed by x^2 when
+ * square != 0.  *model_id indexes it for vr_srv_submit. */
+vr_status vr_srv_register_conv_model(vr_server *srv, uint32_t C_in, uint32_t h, uint32_t w,
+                                     uint32_t pad, const double *K, const double *bias,
+                                     uint32_t C_out, uint32_t k, uint32_t stride, uint32_t square,
+                                     uint32_t *model_id);
+/* Queues one request: in[c*w + j] (n_in = C_in*w), n_images images (for the
+ * throughput figure).  The inputs are read after the work already queued on
+ * the context's stream; the caller may free its handles at once.  VR_EBUSY
+ * if the request alone can never fit the budget, VR_ELEVEL if it has too few
+ * levels.  *ticket identifies it. */
+vr_status vr_srv_submit(vr_server *srv, uint64_t session_id, uint32_t model_id,
+                        const vr_ciphertext *const *in, size_t n_in, uint32_t n_images,
+                        uint64_t *ticket);
+/* Removes a request that has not started; VR_EINVAL if it already has.  Its
+ * poll then returns VR_ECANCELED. */
+vr_status vr_srv_cancel(vr_server *srv, uint64_t ticket);
+/* *ready = 1 and out[0..*n_out) = the C_out*w_out output handles (caller
+ * frees) once the request is done (wait != 0 blocks until then); the ticket
+ * is then consumed.  A failed or cancelled request returns its error code. */
+vr_status vr_srv_poll(vr_server *srv, uint64_t ticket, int wait, vr_ciphertext **out, size_t cap,
+                      size_t *n_out, int *ready);
+/* Submit-to-completion latency percentiles (nearest rank) over completed
+ * requests, images per second between the first submit and the last
+ * completion, request and wave counts (batched = requests run in waves). */
+vr_status vr_srv_stats(vr_server *srv, double *p50_ms, double *p99_ms, double *images_per_s,
+                       uint64_t *completed, uint64_t *waves, uint64_t *batched);
 
 void vr_free_ciphertext(vr_ciphertext *ct);
 void vr_free_plaintext(vr_plaintext *pt);

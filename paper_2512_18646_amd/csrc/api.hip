@@ -161,6 +161,22 @@ vr_status vr_context_set_allocator(vr_context* ctx, void* (*alloc_fn)(size_t, vo
     API_END
 }
 
+vr_status vr_context_mem_info(vr_context* ctx, size_t* reserved, size_t* in_use)
+{
+    API_BEGIN
+    REQUIRE(ctx && reserved && in_use, "null argument");
+    ctx->arena->usage(reserved, in_use);
+    API_END
+}
+
+vr_status vr_context_trim(vr_context* ctx)
+{
+    API_BEGIN
+    REQUIRE(ctx, "null context");
+    ctx->arena->trim();
+    API_END
+}
+
 // ------------------------------------------------------------------ client
 
 vr_status vr_keygen(vr_context* ctx, uint64_t seed, const int32_t* rot_steps, size_t n_steps,

@@ -14,8 +14,8 @@ DevBuf::~DevBuf()
     if (!ptr) return;
     if (free_fn)
         free_fn(ptr, (void*)stream, free_user);
-    else
-        (void)hipFreeAsync(ptr, stream);
+    else if (arena)
+        arena->release(ptr, stream);
 }
 
 BufPtr dev_alloc(vr_context* ctx, size_t bytes, hipStream_t s)
@@ -30,12 +30,9 @@ BufPtr dev_alloc(vr_context* ctx, size_t bytes, hipStream_t s)
         b->free_fn = ctx->free_fn;
         b->free_user = ctx->alloc_user;
     } else {
-        hipError_t e = hipMallocAsync(&b->ptr, bytes, s);
-        if (e != hipSuccess) {
-            b->ptr = nullptr;
-            (void)hipGetLastError();
-            throw Error(VR_ENOMEM, std::string("device allocation failed: ") + hipGetErrorString(e));
-        }
+        b->ptr = ctx->arena->alloc(bytes, s);
+        if (!b->ptr) throw Error(VR_ENOMEM, "device allocation failed");
+        b->arena = ctx->arena;
     }
     return b;
 }

@@ -138,7 +138,10 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
             ka[j] = key[((size_t)(2 * j + 1) * nmod + mod) * n + t];
         }
     }
-    for (u32 c = 0; c < n_ct; c++) {
+    // blockIdx.z splits the ciphertexts into groups so small rings still fill the chip
+    const u32 per = (n_ct + gridDim.z - 1) / gridDim.z;
+    const u32 c_lo = blockIdx.z * per, c_hi = min(n_ct, c_lo + per);
+    for (u32 c = c_lo; c < c_hi; c++) {
         const u64* xc = X + (size_t)c * x_stride + (size_t)e * n;
         if (perm) {
             __syncthreads();
@@ -367,7 +370,12 @@ void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, u32 n_ct
                            u32 level, u32 g, u64* U, u64 u_stride, hipStream_t s)
 {
     KsShape k = ks_shape(ctx, level);
-    dim3 grid((ctx->n + kThreads - 1) / kThreads, k.next);
+    // at least ~4096 blocks: split the ciphertexts (each group re-reads the key)
+    u32 bxy = ((ctx->n + kThreads - 1) / kThreads) * k.next;
+    u32 groups = (4096 + bxy - 1) / bxy;
+    if (groups > n_ct) groups = n_ct;
+    if (groups < 1) groups = 1;
+    dim3 grid((ctx->n + kThreads - 1) / kThreads, k.next, groups);
     ProfScope prof(ctx, kProfKsInner, s, (u64)n_ct * k.next);
     if (k.beta <= 4)
         hipLaunchKernelGGL((k_ks_inner<4>), grid, dim3(kThreads), 0, s, X, x_stride, n_ct, key,

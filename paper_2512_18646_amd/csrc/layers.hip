@@ -28,23 +28,13 @@
 #include <cmath>
 #include <cstring>
 
-#include "eval.h"
+#include "slab.h"
 
 namespace vr {
 
 namespace {
-
 constexpr int kThreads = 256;
-
-// A slab of ciphertexts with uniform stride.
-struct Slab {
-    BufPtr buf;
-    u64* base = nullptr;
-    u32 n = 0, ncomp = 2, level = 0;
-    u64 stride = 0;   // words between ciphertexts
-    double scale = 1.0;
-    u64* ct(u32 i) const { return base + (size_t)i * stride; }
-};
+}  // namespace
 
 Slab new_slab(vr_context* ctx, u32 n, u32 ncomp, u32 level, double scale, hipStream_t s)
 {
@@ -95,6 +85,8 @@ void to_handles(vr_context* ctx, const Slab& sl, vr_ciphertext** out)
     for (u32 i = 0; i < sl.n; i++) out[i] = view_ct(ctx, sl.buf, sl.ct(i), sl.ncomp, sl.level, sl.scale);
 }
 
+namespace {
+
 // ------------------------------------------------------------- kernels
 
 struct Term {
@@ -102,28 +94,44 @@ struct Term {
     u32 w_idx;    // weight row
 };
 
-// out[o] = sum_{terms of o} w * in  (+ bias on component 0), 2 components.
-// Input index i: ciphertext i of slab x when i < n_x, else ciphertext i - n_x
-// of slab r (both with stride `stride`).
+// For each of n_sets independent image sets s and each output o:
+// out[s][o] = sum_{terms of o} w * in (+ bias on component 0), 2 components.
+// Term input index i = u * n_x + j: for u = 0 ciphertext s * n_x + j of slab x,
+// for u >= 1 ciphertext (u - 1) * n_x * n_sets + s * n_x + j of slab r (the
+// rotations by u of every column of every set), all with stride `stride`.
+//
+// Launch order: the logical block id runs over outputs fastest, then sets,
+// then rows, then 256-coefficient chunks, so the outputs that read the same
+// input chunk (neighbouring columns, every filter) run back to back; the
+// logical ids are dealt to the 8 XCDs in contiguous ranges (hardware hands
+// block b to XCD b mod 8), so those blocks share one L2.
 __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, const u64* x,
-                                                      const u64* r, u32 n_x, u64 stride,
+                                                      const u64* r, u32 n_x, u32 n_sets, u64 stride,
                                                       const Term* terms, const u32* term_off,
                                                       const u64* w, const u64* ws, const u64* bias,
-                                                      u32 nl, u32 log_n, const ModQ* mq)
+                                                      u32 nl, u32 log_n, const ModQ* mq, u32 n_out,
+                                                      u32 total, u32 per_xcd)
 {
+    const u32 logical = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (logical >= total) return;
     const u32 n = 1u << log_n;
-    const u32 t = blockIdx.x * kThreads + threadIdx.x;
+    const u32 o = logical % n_out;
+    u32 rest = logical / n_out;
+    const u32 set = rest % n_sets;
+    rest /= n_sets;
+    const u32 row = rest % (2 * nl);   // component * nl + limb
+    const u32 chunk = rest / (2 * nl);
+    const u32 t = chunk * kThreads + threadIdx.x;
     if (t >= n) return;
-    const u32 row = blockIdx.y % (2 * nl);   // component * nl + limb
-    const u32 o = blockIdx.y / (2 * nl);
     const u32 l = row % nl;
     const u64 q = mq[l].q, q2 = 2 * q;
     u64 acc = 0;
     const u32 a = term_off[o], b = term_off[o + 1];
     for (u32 k = a; k < b; k++) {
         Term tm = terms[k];
-        const u64* src = tm.in_idx < n_x ? x + (size_t)tm.in_idx * stride
-                                         : r + (size_t)(tm.in_idx - n_x) * stride;
+        const u32 u = tm.in_idx / n_x, j = tm.in_idx - u * n_x;
+        const u64* src = u == 0 ? x + (size_t)(set * n_x + j) * stride
+                                : r + ((size_t)(u - 1) * n_x * n_sets + set * n_x + j) * stride;
         u64 xv = src[(size_t)row * n + t];
         acc += shoup_lazy(xv, w[(size_t)tm.w_idx * nl + l], ws[(size_t)tm.w_idx * nl + l], q);
         acc = acc >= q2 ? acc - q2 : acc;
@@ -131,7 +139,7 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
     if (bias && row < nl) acc += bias[(size_t)o * nl + l];
     acc = acc >= q2 ? acc - q2 : acc;
     acc = acc >= q ? acc - q : acc;
-    out[(size_t)o * out_stride + (size_t)row * n + t] = acc;
+    out[(size_t)(set * n_out + o) * out_stride + (size_t)row * n + t] = acc;
 }
 
 // T = sum_k A_k (x) R_k: 3-component tensor accumulate over n_terms pairs
@@ -292,10 +300,12 @@ Slab square_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipStr
     const u32 nl = in.level + 1;
     Slab T = new_slab(ctx, in.n, 3, in.level, in.scale * in.scale, s);
     dim3 grid((ctx->n + kThreads - 1) / kThreads, in.n * nl);
-    ProfScope prof(ctx, kProfTensor, s, (u64)in.n * 2 * nl);
-    hipLaunchKernelGGL(k_tensor_batch, grid, dim3(kThreads), 0, s, T.base, in.base, in.base,
-                       in.stride, nl, ctx->log_n, ctx->d_modq);
-    VR_CHECK_LAUNCH();
+    {
+        ProfScope prof(ctx, kProfTensor, s, (u64)in.n * 2 * nl);
+        hipLaunchKernelGGL(k_tensor_batch, grid, dim3(kThreads), 0, s, T.base, in.base, in.base,
+                           in.stride, nl, ctx->log_n, ctx->d_modq);
+        VR_CHECK_LAUNCH();
+    }
     Slab R = relin_slab(ctx, ek, T, s);
     return rescale_slab(ctx, R, s);
 }
@@ -385,6 +395,11 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
 
 }  // namespace
 
+Slab layer_square(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipStream_t s)
+{
+    return square_slab(ctx, ek, in, s);
+}
+
 // ------------------------------------------------------------- encodings
 
 vr_ciphertext** encrypt_slots_batch(vr_context* ctx, const vr_eval_keys* ek,
@@ -419,6 +434,42 @@ vr_ciphertext** encrypt_slots_batch(vr_context* ctx, const vr_eval_keys* ek,
     }
     to_handles(ctx, sl, out);
     return out;
+}
+
+// Conv layer over n_sets image sets laid out in one slab (set s occupies
+// ciphertexts s * C_in * w .. (s + 1) * C_in * w - 1): one hoisted ModUp per
+// column, one shared-key inner-product launch per rotation step for every
+// column of every set, one fused MulConst/AddConst launch, one rescale.
+Slab conv_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& x, u32 n_sets, u32 C_in, u32 w,
+               u32 pad, const double* K, const double* bias, u32 C_out, u32 k, u32 stride,
+               hipStream_t s)
+{
+    if (x.ncomp != 2) throw Error(VR_EINVAL, "conv inputs must be 2-component");
+    if (x.level < 1) throw Error(VR_ELEVEL, "conv needs a level to rescale");
+    const u32 wo = (w + 2 * pad - k) / stride + 1;
+    const u32 level = x.level, nl = level + 1;
+    // rotations by 1..k-1 of every column (step 0 is the input itself)
+    std::vector<int32_t> steps;
+    for (u32 u = 1; u < k; u++) steps.push_back((int32_t)u);
+    std::vector<Slab> rot;
+    if (!steps.empty()) rotate_slab(ctx, ek, x, steps, rot, s);
+    const double dq = (double)ctx->mod[level];
+    const double out_scale = x.scale * dq;
+    const ConvPlan& plan = conv_plan(ctx, C_in, w, pad, K, bias, C_out, k, stride, level, out_scale);
+    const u32 n_out = C_out * wo;
+    Slab acc = new_slab(ctx, n_sets * n_out, 2, level, out_scale, s);
+    {
+        const u32 chunks = (ctx->n + kThreads - 1) / kThreads;
+        const u32 total = chunks * 2 * nl * n_sets * n_out;
+        const u32 per_xcd = (total + 7) / 8;
+        ProfScope prof(ctx, kProfLincomb, s, (u64)n_sets * n_out * 2 * nl);
+        hipLaunchKernelGGL(k_lincomb, dim3(8 * per_xcd), dim3(kThreads), 0, s, acc.base, acc.stride,
+                           x.base, rot.empty() ? x.base : rot[0].base, C_in * w, n_sets, x.stride,
+                           plan.terms, plan.off, plan.w, plan.ws, plan.bias, nl, ctx->log_n,
+                           ctx->d_modq, n_out, total, per_xcd);
+        VR_CHECK_LAUNCH();
+    }
+    return rescale_slab(ctx, acc, s);
 }
 
 }  // namespace vr
@@ -586,39 +637,26 @@ vr_status vr_conv2d(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext
                     const double* bias, uint32_t C_out, uint32_t k, uint32_t stride,
                     vr_ciphertext** out, void* stream)
 {
+    return vr_conv2d_sets(ctx, ek, in, 1, C_in, h, w, pad, K, bias, C_out, k, stride, out, stream);
+}
+
+vr_status vr_conv2d_sets(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* const* in,
+                         uint32_t n_sets, uint32_t C_in, uint32_t h, uint32_t w, uint32_t pad,
+                         const double* K, const double* bias, uint32_t C_out, uint32_t k,
+                         uint32_t stride, vr_ciphertext** out, void* stream)
+{
     const u32 wo = (k >= 1 && stride >= 1 && w + 2 * pad >= k) ? (w + 2 * pad - k) / stride + 1 : 0;
     if (out)
-        for (size_t i = 0; i < (size_t)C_out * wo; i++) out[i] = nullptr;
+        for (size_t i = 0; i < (size_t)n_sets * C_out * wo; i++) out[i] = nullptr;
     API_BEGIN
     REQUIRE(ctx && ek && in && K && bias && out, "null argument");
+    REQUIRE(n_sets >= 1, "no image set");
     REQUIRE(C_in >= 1 && C_out >= 1 && k >= 1 && stride >= 1, "bad conv shape");
     REQUIRE(w + 2 * pad >= k && h + 2 * pad >= k, "kernel larger than the padded image");
     REQUIRE(pad < k, "padding must be smaller than the kernel");
     hipStream_t s = pick_stream(ctx, stream);
-    Slab x = gather(ctx, in, C_in * w, s);
-    REQUIRE(x.ncomp == 2, "conv inputs must be 2-component");
-    REQUIRE(x.level >= 1, "conv needs a level to rescale");
-    const u32 level = x.level, nl = level + 1;
-    // rotations by 1..k-1 of every column (step 0 is the input itself)
-    std::vector<int32_t> steps;
-    for (u32 u = 1; u < k; u++) steps.push_back((int32_t)u);
-    std::vector<Slab> rot;
-    if (!steps.empty()) rotate_slab(ctx, ek, x, steps, rot, s);
-    const double dq = (double)ctx->mod[level];
-    const double out_scale = x.scale * dq;
-    const ConvPlan& plan = conv_plan(ctx, C_in, w, pad, K, bias, C_out, k, stride, level, out_scale);
-    const u32 n_out = C_out * wo;
-    Slab acc = new_slab(ctx, n_out, 2, level, out_scale, s);
-    dim3 grid((ctx->n + kThreads - 1) / kThreads, n_out * 2 * nl);
-    {
-        ProfScope prof(ctx, kProfLincomb, s, (u64)n_out * 2 * nl);
-        // inputs: (u = 0) the columns themselves, (u >= 1) the rotation slabs
-        hipLaunchKernelGGL(k_lincomb, grid, dim3(kThreads), 0, s, acc.base, acc.stride, x.base,
-                           rot.empty() ? x.base : rot[0].base, C_in * w, x.stride, plan.terms,
-                           plan.off, plan.w, plan.ws, plan.bias, nl, ctx->log_n, ctx->d_modq);
-        VR_CHECK_LAUNCH();
-    }
-    Slab y = rescale_slab(ctx, acc, s);
+    Slab x = gather(ctx, in, n_sets * C_in * w, s);
+    Slab y = conv_slab(ctx, ek, x, n_sets, C_in, w, pad, K, bias, C_out, k, stride, s);
     to_handles(ctx, y, out);
     API_END
 }

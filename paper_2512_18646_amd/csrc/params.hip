@@ -130,6 +130,7 @@ void build_context(vr_context* ctx, const vr_params* p, int device)
         if (b < 20 || b > 60) throw Error(VR_EINVAL, "prime sizes must be in [20, 60] bits");
 
     ctx->device = device;
+    ctx->arena = std::make_shared<DeviceArena>(device);
     ctx->log_n = p->log_n;
     ctx->n = 1u << p->log_n;
     ctx->slots = ctx->n / 2;

@@ -1,0 +1,31 @@
+// Slabs: a layer's ciphertexts in one allocation, so one kernel launch covers
+// all of them.  Shared by the layer calls and the serving loop.
+#pragma once
+
+#include "eval.h"
+
+namespace vr {
+
+struct Slab {
+    BufPtr buf;
+    u64* base = nullptr;
+    u32 n = 0, ncomp = 2, level = 0;
+    u64 stride = 0;   // words between ciphertexts
+    double scale = 1.0;
+    u64* ct(u32 i) const { return base + (size_t)i * stride; }
+};
+
+Slab new_slab(vr_context* ctx, u32 n, u32 ncomp, u32 level, double scale, hipStream_t s);
+// the ciphertexts in place when they already form a slab, else a copy
+Slab gather(vr_context* ctx, const vr_ciphertext* const* cts, u32 n, hipStream_t s);
+// new handles viewing the slab's ciphertexts (they share its allocation)
+void to_handles(vr_context* ctx, const Slab& sl, vr_ciphertext** out);
+
+// conv layer over n_sets image sets (set s: ciphertexts s*C_in*w ...)
+Slab conv_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& x, u32 n_sets, u32 C_in, u32 w,
+               u32 pad, const double* K, const double* bias, u32 C_out, u32 k, u32 stride,
+               hipStream_t s);
+// x^2 of every ciphertext: Rescale(Relin(Tensor(y, y)))
+Slab layer_square(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipStream_t s);
+
+}  // namespace vr

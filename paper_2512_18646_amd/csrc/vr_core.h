@@ -22,6 +22,7 @@
 #include <vector>
 
 #include "../../include/vr.h"
+#include "alloc.h"
 
 namespace vr {
 
@@ -149,6 +150,7 @@ struct DevBuf {
     hipStream_t stream = nullptr;
     void (*free_fn)(void*, void*, void*) = nullptr;
     void* free_user = nullptr;
+    std::shared_ptr<DeviceArena> arena;   // built-in allocator (kept alive by its blocks)
     ~DevBuf();
 };
 typedef std::shared_ptr<DevBuf> BufPtr;
@@ -203,6 +205,7 @@ struct vr_context {
     std::map<std::string, std::shared_ptr<void>> plans;
     std::mutex mu;
     hipStream_t stream = nullptr;     // used when a call passes stream = NULL
+    std::shared_ptr<vr::DeviceArena> arena;
     vr::Profiler prof;
     void* (*alloc_fn)(size_t, void*, void*) = nullptr;
     void (*free_fn)(void*, void*, void*) = nullptr;

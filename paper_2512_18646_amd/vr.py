@@ -53,6 +53,8 @@ _SIGS = {
     "vr_context_info": [P, P, ctypes.POINTER(DBL)],
     "vr_context_set_stream": [P, P],
     "vr_context_set_allocator": [P, P, P, P],
+    "vr_context_mem_info": [P, ctypes.POINTER(SZ), ctypes.POINTER(SZ)],
+    "vr_context_trim": [P],
     "vr_keygen": [P, U64, P, SZ, PP, PP],
     "vr_keys_add_rotations": [P, P, P, U64, P, SZ],
     "vr_encode": [P, P, SZ, U32, DBL, PP],
@@ -76,6 +78,7 @@ _SIGS = {
     "vr_rotate_batch": [P, P, PP, SZ, I32, PP, P],
     "vr_matmul": [P, P, PP, PP, U32, U32, U32, PP, P],
     "vr_conv2d": [P, P, PP, U32, U32, U32, U32, P, P, U32, U32, U32, PP, P],
+    "vr_conv2d_sets": [P, P, PP, U32, U32, U32, U32, U32, P, P, U32, U32, U32, PP, P],
     "vr_square": [P, P, PP, SZ, PP, P],
     "vr_fc": [P, P, PP, U32, U32, PP, P, U32, U32, PP, P],
     "vr_encode_fc_weights": [P, P, U32, U32, U32, U32, U32, U32, U32, PP],
@@ -90,13 +93,23 @@ _SIGS = {
     "vr_profile_start": [P, ctypes.c_char_p, SZ],
     "vr_profile_stop": [P, ctypes.POINTER(DBL), ctypes.POINTER(U64), ctypes.POINTER(U64),
                         ctypes.POINTER(U32)],
+    "vr_srv_create": [P, SZ, U32, PP],
+    "vr_srv_destroy": [P],
+    "vr_srv_register_session": [P, P, ctypes.POINTER(U64)],
+    "vr_srv_register_conv_model": [P, U32, U32, U32, U32, P, P, U32, U32, U32, U32,
+                                   ctypes.POINTER(U32)],
+    "vr_srv_submit": [P, U64, U32, PP, SZ, U32, ctypes.POINTER(U64)],
+    "vr_srv_cancel": [P, U64],
+    "vr_srv_poll": [P, U64, ctypes.c_int, PP, SZ, ctypes.POINTER(SZ), ctypes.POINTER(ctypes.c_int)],
+    "vr_srv_stats": [P, ctypes.POINTER(DBL), ctypes.POINTER(DBL), ctypes.POINTER(DBL),
+                     ctypes.POINTER(U64), ctypes.POINTER(U64), ctypes.POINTER(U64)],
     "vr_context_destroy": [P],
     "vr_free_ciphertext": [P],
     "vr_free_plaintext": [P],
     "vr_free_keys": [P, P],
     "vr_last_error": [],
 }
-_VOID = {"vr_context_destroy", "vr_free_ciphertext", "vr_free_plaintext", "vr_free_keys"}
+_VOID = {"vr_context_destroy", "vr_srv_destroy", "vr_free_ciphertext", "vr_free_plaintext", "vr_free_keys"}
 
 
 def _load():
@@ -259,6 +272,15 @@ class Context:
     def set_stream(self, stream):
         _check(lib.vr_context_set_stream(self.h, _stream(stream)))
 
+    def mem_info(self):
+        """(reserved, in_use) bytes of the built-in caching allocator."""
+        r, u = SZ(), SZ()
+        _check(lib.vr_context_mem_info(self.h, ctypes.byref(r), ctypes.byref(u)))
+        return r.value, u.value
+
+    def trim(self):
+        _check(lib.vr_context_trim(self.h))
+
     def profile_start(self, kernel_class, max_launches=65536):
         _check(lib.vr_profile_start(self.h, kernel_class.encode(), max_launches))
 
@@ -389,6 +411,18 @@ class Context:
                              bias.ctypes.data, C_out, k, stride, arr, _stream(stream)))
         return [Ciphertext(arr[i], self) for i in range(C_out * wo)]
 
+    def conv2d_sets(self, keys, cols, n_sets, C_in, h, w, pad, K, bias, stride, stream=None):
+        """cols = every set's C_in*w columns, set after set."""
+        K = _f64(K)
+        bias = _f64(bias)
+        C_out, _, k, _ = K.shape
+        wo = (w + 2 * pad - k) // stride + 1
+        arr = (ctypes.c_void_p * (n_sets * C_out * wo))()
+        _check(lib.vr_conv2d_sets(self.h, keys.ek, _ptr_array(cols), n_sets, C_in, h, w, pad,
+                                  K.ctypes.data, bias.ctypes.data, C_out, k, stride, arr,
+                                  _stream(stream)))
+        return [Ciphertext(arr[i], self) for i in range(n_sets * C_out * wo)]
+
     def square(self, keys, cts, stream=None):
         arr = (ctypes.c_void_p * len(cts))()
         _check(lib.vr_square(self.h, keys.ek, _ptr_array(cts), len(cts), arr, _stream(stream)))
@@ -427,3 +461,70 @@ class Context:
     def ntt_device(self, ptr, n_limbs, mod_index, inverse=False, stream=None):
         mi = np.ascontiguousarray(np.asarray(mod_index, dtype=np.uint32))
         _check(lib.vr_ntt(self.h, ptr, n_limbs, mi.ctypes.data, 1 if inverse else 0, _stream(stream)))
+
+
+class Server:
+    """Continuous-batching server over one context (vr_srv_*)."""
+
+    def __init__(self, ctx, hbm_budget_bytes, max_batch=8):
+        self.ctx = ctx
+        self._keys = []
+        self._models = {}
+        h = ctypes.c_void_p()
+        _check(lib.vr_srv_create(ctx.h, int(hbm_budget_bytes), int(max_batch), ctypes.byref(h)))
+        self.h = h.value
+
+    def close(self):
+        if self.h:
+            lib.vr_srv_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def register_session(self, keys):
+        sid = U64()
+        _check(lib.vr_srv_register_session(self.h, keys.ek, ctypes.byref(sid)))
+        self._keys.append(keys)   # keys outlive the server
+        return sid.value
+
+    def register_conv_model(self, C_in, h, w, pad, K, bias, stride, square=True):
+        K = _f64(K)
+        bias = _f64(bias)
+        C_out, _, k, _ = K.shape
+        mid = U32()
+        _check(lib.vr_srv_register_conv_model(self.h, C_in, h, w, pad, K.ctypes.data, bias.ctypes.data,
+                                              C_out, k, stride, 1 if square else 0, ctypes.byref(mid)))
+        self._models[mid.value] = C_out * ((w + 2 * pad - k) // stride + 1)
+        return mid.value
+
+    def submit(self, session, model, cols, n_images):
+        t = U64()
+        _check(lib.vr_srv_submit(self.h, session, model, _ptr_array(cols), len(cols), n_images,
+                                 ctypes.byref(t)))
+        return t.value
+
+    def cancel(self, ticket):
+        _check(lib.vr_srv_cancel(self.h, ticket))
+
+    def poll(self, ticket, model, wait=True):
+        """Output ciphertexts once done, else None."""
+        cap = self._models[model]
+        arr = (ctypes.c_void_p * cap)()
+        n, ready = SZ(), ctypes.c_int()
+        _check(lib.vr_srv_poll(self.h, ticket, 1 if wait else 0, arr, cap, ctypes.byref(n),
+                               ctypes.byref(ready)))
+        if not ready.value:
+            return None
+        return [Ciphertext(arr[i], self.ctx) for i in range(n.value)]
+
+    def stats(self):
+        p50, p99, ips = DBL(), DBL(), DBL()
+        done, waves, batched = U64(), U64(), U64()
+        _check(lib.vr_srv_stats(self.h, ctypes.byref(p50), ctypes.byref(p99), ctypes.byref(ips),
+                                ctypes.byref(done), ctypes.byref(waves), ctypes.byref(batched)))
+        return {"p50_ms": p50.value, "p99_ms": p99.value, "images_per_s": ips.value,
+                "completed": done.value, "waves": waves.value, "batched": batched.value}

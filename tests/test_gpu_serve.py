@@ -1,0 +1,178 @@
+"""Multi-set conv and the continuous-batching server: a request's output limbs
+are the same whether it is evaluated alone, in a batched multi-set call or in
+a server wave mixed with other requests, sessions and models; admission by
+memory, cancellation and level errors."""
+import numpy as np
+import pytest
+
+from oracle import layers as Ly
+from tests.gpu_helpers import pair, to_gpu, assert_same
+
+pytestmark = pytest.mark.gpu
+
+SHAPE = dict(B=8, Ci=2, h=10, w=9, k=3, s=2, pad=1)
+
+
+@pytest.fixture(scope="module")
+def small():
+    return pair("C1", rot_steps=(1, 2, 4, 8), log_n=10)
+
+
+def draw(rng, co=3):
+    S = SHAPE
+    X = rng.uniform(0, 1, (S["B"], S["Ci"], S["h"], S["w"]))
+    K = rng.normal(0, 0.1, (co, S["Ci"], S["k"], S["k"]))
+    bias = rng.normal(0, 0.1, co)
+    return X, K, bias
+
+
+def same_limbs(a, b, what):
+    assert a.meta == b.meta, what
+    assert np.array_equal(a.export(), b.export()), what
+
+
+def test_conv2d_sets_matches_single_set_calls(small):
+    o, ok, g, gk = small
+    S = SHAPE
+    rng = np.random.default_rng(11)
+    _, K, bias = draw(rng)
+    sets = [g.encrypt_columns(gk, rng.uniform(0, 1, (S["B"], S["Ci"], S["h"], S["w"])), S["pad"], 3,
+                              77, 100 * i) for i in range(3)]
+    flat = [c for st in sets for c in st]
+    Y = g.conv2d_sets(gk, flat, 3, S["Ci"], S["h"], S["w"], S["pad"], K, bias, S["s"])
+    per = len(Y) // 3
+    for i, st in enumerate(sets):
+        one = g.conv2d(gk, st, S["Ci"], S["h"], S["w"], S["pad"], K, bias, S["s"])
+        assert len(one) == per
+        for j in range(per):
+            same_limbs(Y[i * per + j], one[j], "set %d out %d" % (i, j))
+    # one set against the oracle
+    X, _, _ = draw(np.random.default_rng(12))
+    cts = Ly.encrypt_image_columns(o, ok, X, S["pad"], 3, 5, 0)
+    ref = Ly.conv2d(o, ok, cts, S["Ci"], S["h"], S["w"], S["pad"], K, bias, 3, S["k"], S["s"])
+    gc = [to_gpu(g, c) for c in cts]
+    Y2 = g.conv2d_sets(gk, flat[:S["Ci"] * S["w"]] + gc, 2, S["Ci"], S["h"], S["w"], S["pad"], K,
+                       bias, S["s"])
+    for j in range(per):
+        assert_same(Y2[per + j], ref[j], "oracle set out %d" % j)
+
+
+def alone(g, keys, cols, K, bias, square):
+    S = SHAPE
+    y = g.conv2d(keys, cols, S["Ci"], S["h"], S["w"], S["pad"], K, bias, S["s"])
+    return g.square(keys, y) if square else y
+
+
+def test_server_mixed_requests_identical_to_alone(small):
+    from paper_2512_18646_amd import vr
+    o, ok, g, gk = small
+    S = SHAPE
+    gk2 = g.keygen(2024, rot_steps=[1, 2])
+    rng = np.random.default_rng(21)
+    _, K1, b1 = draw(rng, 3)
+    _, K2, b2 = draw(rng, 2)
+    srv = vr.Server(g, 8 << 30, max_batch=4)
+    s1, s2 = srv.register_session(gk), srv.register_session(gk2)
+    m1 = srv.register_conv_model(S["Ci"], S["h"], S["w"], S["pad"], K1, b1, S["s"], square=True)
+    m2 = srv.register_conv_model(S["Ci"], S["h"], S["w"], S["pad"], K2, b2, S["s"], square=False)
+    plan = [(s1, gk, m1, K1, b1, True)] * 5 + [(s2, gk2, m1, K1, b1, True)] * 2 + \
+           [(s1, gk, m2, K2, b2, False)] * 3
+    order = np.random.default_rng(5).permutation(len(plan))
+    # the first request carries the oracle's encryption, to anchor the served limbs
+    X0 = rng.uniform(0, 1, (S["B"], S["Ci"], S["h"], S["w"]))
+    ocols = Ly.encrypt_image_columns(o, ok, X0, S["pad"], 3, 800, 0)
+    batch = [(s1, gk, m1, K1, b1, True, [to_gpu(g, c) for c in ocols])]
+    for n, i in enumerate(order):
+        sess, keys, model, K, bias, sq = plan[i]
+        X = rng.uniform(0, 1, (S["B"], S["Ci"], S["h"], S["w"]))
+        batch.append((sess, keys, model, K, bias, sq, g.encrypt_columns(keys, X, S["pad"], 3, 900 + n, 0)))
+    # submitted in a burst, so that later requests queue behind the first waves
+    reqs = [(srv.submit(sess, model, cols, S["B"]), keys, model, K, bias, sq, cols)
+            for sess, keys, model, K, bias, sq, cols in batch]
+    outs = [srv.poll(r[0], r[2]) for r in reqs]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs) and st["batched"] == len(reqs)
+    assert st["waves"] < len(reqs), st          # some waves held several requests
+    assert 0 < st["p50_ms"] <= st["p99_ms"]
+    for (t, keys, model, K, bias, sq, cols), got in zip(reqs, outs):
+        ref = alone(g, keys, cols, K, bias, sq)
+        assert len(got) == len(ref)
+        for j, (a, b) in enumerate(zip(got, ref)):
+            same_limbs(a, b, "ticket %d out %d" % (t, j))
+    Y = Ly.conv2d(o, ok, ocols, S["Ci"], S["h"], S["w"], S["pad"], K1, b1, 3, S["k"], S["s"])
+    for j, y in enumerate(Y):
+        assert_same(outs[0][j], Ly.square(o, ok, y), "served vs oracle %d" % j)
+
+
+def test_server_admission_cancel_and_levels(small):
+    from paper_2512_18646_amd import vr
+    o, ok, g, gk = small
+    S = SHAPE
+    rng = np.random.default_rng(31)
+    X, K, bias = draw(rng)
+    with pytest.raises(vr.VRError) as e:
+        vr.Server(g, 1 << 16).register_session(gk)     # keys alone exceed the budget
+    assert e.value.code == vr.VR_EBUSY
+    tight = vr.Server(g, 12 << 20)
+    sid = tight.register_session(gk)
+    mid = tight.register_conv_model(S["Ci"], S["h"], S["w"], S["pad"], K, bias, S["s"])
+    cols = g.encrypt_columns(gk, X, S["pad"], 3, 1, 0)
+    with pytest.raises(vr.VRError) as e:
+        tight.submit(sid, mid, cols, S["B"])           # the request can never fit
+    assert e.value.code == vr.VR_EBUSY
+    tight.close()
+
+    srv = vr.Server(g, 8 << 30, max_batch=2)
+    sid = srv.register_session(gk)
+    mid = srv.register_conv_model(S["Ci"], S["h"], S["w"], S["pad"], K, bias, S["s"])
+    low = g.encrypt_columns(gk, X, S["pad"], 1, 2, 0)
+    with pytest.raises(vr.VRError) as e:
+        srv.submit(sid, mid, low, S["B"])              # conv + x^2 needs two levels
+    assert e.value.code == vr.VR_ELEVEL
+    with pytest.raises(vr.VRError) as e:
+        srv.submit(sid, mid, cols[:-1], S["B"])
+    assert e.value.code == vr.VR_EINVAL
+    tickets = [srv.submit(sid, mid, cols, S["B"]) for _ in range(8)]
+    try:
+        srv.cancel(tickets[-1])
+        cancelled = True
+    except vr.VRError as err:                         # it had already started
+        assert err.code == vr.VR_EINVAL
+        cancelled = False
+    ref = alone(g, gk, cols, K, bias, True)
+    for t in tickets[:-1]:
+        for a, b in zip(srv.poll(t, mid), ref):
+            same_limbs(a, b, "ticket %d" % t)
+    if cancelled:
+        with pytest.raises(vr.VRError) as e:
+            srv.poll(tickets[-1], mid)
+        assert e.value.code == vr.VR_ECANCELED
+    else:
+        srv.poll(tickets[-1], mid)
+    with pytest.raises(vr.VRError):
+        srv.poll(tickets[0], mid)                      # ticket already consumed
+    srv.close()
+
+
+def test_caching_allocator_steady_state(small):
+    """Repeated identical layer calls reuse cached blocks: nothing new is
+    reserved after the first call, freed outputs return their bytes, and trim
+    hands every free block back."""
+    o, ok, g, gk = small
+    S = SHAPE
+    X, K, bias = draw(np.random.default_rng(41))
+    cols = g.encrypt_columns(gk, X, S["pad"], 3, 3, 0)
+    reserved, used = [], []
+    for _ in range(3):
+        y = alone(g, gk, cols, K, bias, True)
+        y[0].export()                                  # synchronises
+        reserved.append(g.mem_info()[0])
+        del y
+        used.append(g.mem_info()[1])
+    # the first call also caches the layer's constants (weights, term lists)
+    assert reserved[1] == reserved[2] == reserved[0], reserved
+    assert used[0] == used[1] == used[2], used
+    g.trim()
+    r, u = g.mem_info()
+    assert r == u == used[0]
