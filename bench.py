@@ -58,6 +58,74 @@ def step_batched(ctx, keys, W, K, bias, cols):
     return ctx.square(keys, y)
 
 
+def plain_conv_sq_fc(X, K, bias, stride, pad, Wfc, bfc):
+    """FP64 plaintext network (conv, x^2, FC) for the decoded-error check."""
+    B, C, h, w = X.shape
+    Co, _, k, _ = K.shape
+    Xp = np.pad(X, ((0, 0), (0, 0), (pad, pad), (pad, pad)))
+    ho, wo = (h + 2 * pad - k) // stride + 1, (w + 2 * pad - k) // stride + 1
+    Y = np.zeros((B, Co, ho, wo)) + bias[None, :, None, None]
+    for u in range(k):
+        for v in range(k):
+            patch = Xp[:, :, u:u + stride * ho:stride, v:v + stride * wo:stride]
+            Y += np.einsum("bchw,oc->bohw", patch, K[:, :, u, v])
+    Y = Y ** 2
+    return Y.reshape(B, -1) @ Wfc.reshape(Wfc.shape[0], -1).T + bfc[None, :]
+
+
+def cnn128_bench(vr, level_in, sets, reps):
+    """The 3x128x128 CNN (conv 3x3/2 pad 1 x8, x^2, FC 8*64*64 -> 10) at
+    N = 2^16, L = 24 (60 + 24x50, P 9x51, dnum 3), 128 images per set (one
+    set = 384 column ciphertexts), sets evaluated one after another."""
+    import synthetic_inputs as SI
+    W = SI.CNN_128
+    ctx = vr.Context(16, [60] + [50] * 24, [51] * 9, 3, 50.0)
+    Hp = 1 << (W.h + 2 * W.pad - 1).bit_length()
+    steps = sorted(set(range(1, W.k)) | {1 << t for t in range(Hp.bit_length() - 1)})
+    t = time.perf_counter()
+    keys = ctx.keygen(1003, rot_steps=steps)
+    X0, K, bias = W.draw()
+    Wfc, bfc = W.draw_fc()
+    Xs = [X0] + [SI.images(W.seed + 1000 * i, W.batch, W.channels, W.h, W.w) for i in range(1, sets)]
+    cols = [ctx.encrypt_columns(keys, X, W.pad, level_in, 1003, 10000 * i) for i, X in enumerate(Xs)]
+    wo = (W.w + 2 * W.pad - W.k) // W.stride + 1
+    W_pt = ctx.encode_fc_weights(Wfc, W.stride, Hp, level_in - 2)
+    sync()
+    setup_s = time.perf_counter() - t
+
+    def network(c):
+        y = ctx.conv2d(keys, c, W.channels, W.h, W.w, W.pad, K, bias, W.stride)
+        y2 = ctx.square(keys, y)
+        del y
+        return ctx.fc(keys, y2, W.c_out, wo, W_pt, bfc, Hp)
+
+    z = network(cols[0])
+    logits = np.zeros((W.batch, len(z)))
+    for o, ct in enumerate(z):
+        logits[:, o] = ctx.decode(ctx.decrypt(keys, ct))[np.arange(W.batch) * Hp]
+    ref = plain_conv_sq_fc(X0, K, bias, W.stride, W.pad, Wfc, bfc)
+    err = float(np.max(np.abs(logits - ref)) / np.max(np.abs(ref)))
+    del z
+    sync()
+    lat = []
+    t_all = time.perf_counter()
+    for r in range(reps):
+        for c in cols:
+            t = time.perf_counter()
+            z = network(c)
+            sync()
+            lat.append((time.perf_counter() - t) * 1e3)
+            del z
+    total = time.perf_counter() - t_all
+    reserved, _ = ctx.mem_info()
+    return {"workload": "3x128x128 images, conv 3x3/2 pad 1 x8 + x^2 + FC 32768->10, N=2^16 L=24, "
+                        "128 images per set", "level_in": level_in, "sets": sets, "reps": reps,
+            "images_per_s": round(W.batch * sets * reps / total, 2),
+            "ms_per_set_p50": round(percentile(lat, 50), 2), "ms_per_set_p99": round(percentile(lat, 99), 2),
+            "decoded_rel_error": err, "setup_s": round(setup_s, 1),
+            "device_gib_reserved": round(reserved / 2 ** 30, 1)}
+
+
 SERVE_MIX = (("28x28", 28, 0.5), ("64x64", 64, 0.3), ("128x128", 128, 0.2))
 
 
@@ -199,6 +267,9 @@ def main():
     ap.add_argument("--no-extra", action="store_true", help="skip per-op, rotation and CPU legs")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-cnn", action="store_true")
+    ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--cnn-sets", type=int, default=2)
     ap.add_argument("--serve-requests", type=int, default=60)
     ap.add_argument("--serve-load", default="0.8,2.0",
                     help="offered loads, as fractions of the one-request-at-a-time service rate")
@@ -256,6 +327,33 @@ def main():
            "latency_ms_p50": round(percentile(lat, 50), 3), "latency_ms_p99": round(percentile(lat, 99), 3),
            "roofline": roofline}
 
+    if not args.no_graph:
+        log("graph capture of the step")
+        net = vr.CNN(W.channels, W.h, W.w, W.pad, K, bias, W.stride, square=True)
+        flat = [c for cs in cols for c in cs]
+        gr = vr.Graph(ctx, keys, net, flat, n_sets=len(cols))
+        for _ in range(args.warmup):
+            gr.launch()
+        sync()
+        glat = []
+        t_g = time.perf_counter()
+        for i in range(args.steps):
+            t = time.perf_counter()
+            gr.launch()
+            sync()
+            glat.append((time.perf_counter() - t) * 1e3)
+        g_total = time.perf_counter() - t_g
+        ref = step_batched(ctx, keys, W, K, bias, cols[:1])
+        gout = gr.outputs()
+        out["graph"] = {"images_per_s": round(images * args.steps / g_total, 2),
+                        "ms_per_step": round(g_total / args.steps * 1e3, 3),
+                        "latency_ms_p50": round(percentile(glat, 50), 3),
+                        "latency_ms_p99": round(percentile(glat, 99), 3),
+                        "identical": bool(all(np.array_equal(gout[i].export(), ref[i].export())
+                                              for i in (0, 33, 64)))}
+        gr.close()
+        del gout, ref
+
     if args.breakdown:
         bd = {}
         for cls in ("ntt", "ks_inner", "base_convert", "lincomb", "moddown", "tensor"):
@@ -284,6 +382,11 @@ def main():
                                       "level3": rotations_bench(vr, 3, 32, 3)}
         for v in out["rotations_per_s_n16"].values():
             v["batched"], v["per_op"] = round(v["batched"], 1), round(v["per_op"], 1)
+
+    if not args.no_extra and not args.no_cnn:
+        for lv, sets in ((3, args.cnn_sets), (24, 1)):
+            log("cnn128 at level %d" % lv)
+            out.setdefault("cnn128_n16", []).append(cnn128_bench(vr, lv, sets, 2))
 
     if not args.no_extra and not args.no_serve:
         log("serving (Poisson arrivals, image-size mix)")

@@ -295,6 +295,46 @@ vr_status vr_profile_start(vr_context *ctx, const char *kernel_class, size_t max
 vr_status vr_profile_stop(vr_context *ctx, double *total_ms, uint64_t *launches, uint64_t *units,
                           uint32_t *dropped);
 
+/* ------------------------------------------------------- whole networks
+ * The encrypted CNN of "Convolutional Neural Networks" with the column-wise
+ * layout: conv (as vr_conv2d), then x^2 when square != 0, then the FC layer
+ * (as vr_fc) when fc_w != NULL.  fc_w holds fc_out * C_out * w_out weight
+ * plaintexts in vr_fc's order, at a level >= the FC input level. */
+typedef struct {
+    uint32_t C_in, h, w, pad, C_out, k, stride;
+    const double *K;                  /* [C_out][C_in][k][k] */
+    const double *bias;               /* [C_out] */
+    uint32_t square;
+    const vr_plaintext *const *fc_w;  /* NULL: no FC layer */
+    const double *fc_bias;            /* [fc_out] */
+    uint32_t fc_out, fc_block;        /* fc_block: slot block H' of the images */
+} vr_cnn_desc;
+typedef struct vr_graph vr_graph;
+
+/* The network on n_sets image sets (in[s*C_in*w + c*w + j]) in one call:
+ * out receives n_sets * (fc_w ? fc_out : C_out*w_out) handles, set after
+ * set.  Identical limbs to the per-layer calls. */
+vr_status vr_cnn_forward(vr_context *ctx, const vr_eval_keys *ek, const vr_cnn_desc *desc,
+                         const vr_ciphertext *const *in, uint32_t n_sets, vr_ciphertext **out,
+                         void *stream);
+/* Captures the same schedule into a HIP graph: copies `in` into the graph's
+ * own input slab, runs the network once eagerly (building every cached
+ * constant), then records it on a private stream.  The graph owns its
+ * intermediate and output memory until vr_graph_destroy.  Needs the built-in
+ * allocator and the profiler stopped.  Synchronises. */
+vr_status vr_graph_create(vr_context *ctx, const vr_eval_keys *ek, const vr_cnn_desc *desc,
+                          const vr_ciphertext *const *in, uint32_t n_sets, vr_graph **out);
+/* Copies new inputs (same count, level and scale) into the graph's input
+ * slab on `stream`. */
+vr_status vr_graph_set_inputs(vr_graph *g, const vr_ciphertext *const *in, size_t n, void *stream);
+/* One replay on `stream`: rewrites the output slab from the input slab. */
+vr_status vr_graph_launch(vr_graph *g, void *stream);
+/* New handles viewing the graph's outputs (valid after a launch completes;
+ * the next launch rewrites them). */
+vr_status vr_graph_outputs(vr_graph *g, vr_ciphertext **out, size_t cap, size_t *n_out);
+/* Synchronises the device and frees the graph (output handles stay valid). */
+void vr_graph_destroy(vr_graph *g);
+
 /* ---------------------------------------------------------------- serving
  * Continuous batching of encrypted inference requests ("Secure Inference":
  * a model owner evaluates a client's encrypted mini-batches).  A request is

@@ -4,8 +4,11 @@
 // of about the same size reuses it (at once on the same stream; behind a wait
 // on that event on another).  Steady-state layer calls therefore make no
 // runtime allocation at all, and blocks are never returned to the runtime
-// while the context lives, except when hipMalloc fails: then the cache is
-// released (after a device synchronisation) and the allocation retried.
+// while the context lives.  Near the device's capacity (a new block would take
+// the held total past 90 % of its memory) a larger cached block is reused
+// instead, or else the largest cached blocks are released (after a device
+// synchronisation) until the new one fits; a failed hipMalloc releases the
+// whole cache and retries.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -20,7 +23,7 @@ namespace vr {
 
 class DeviceArena {
 public:
-    explicit DeviceArena(int device) : device_(device) {}
+    explicit DeviceArena(int device);
     ~DeviceArena();
     DeviceArena(const DeviceArena&) = delete;
     DeviceArena& operator=(const DeviceArena&) = delete;
@@ -28,6 +31,9 @@ public:
     // Memory usable by work queued on s after this call; nullptr when the
     // device is out of memory even with the cache released.
     void* alloc(size_t bytes, hipStream_t s);
+    // A block straight from the runtime, bypassing the cache (for memory a
+    // captured graph will own: no stream dependency may be recorded then).
+    void* alloc_fresh(size_t bytes);
     // Stream-ordered free: the block may be reused once the work queued on s
     // before this call has finished.
     void release(void* p, hipStream_t s);
@@ -45,6 +51,7 @@ private:
         hipEvent_t ev;
     };
     hipEvent_t take_event();
+    void* take(std::multimap<size_t, Block>::iterator it, hipStream_t s);
     void trim_locked();
 
     int device_;
@@ -52,7 +59,7 @@ private:
     std::multimap<size_t, Block> free_;
     std::unordered_map<void*, size_t> live_;
     std::vector<hipEvent_t> events_;
-    size_t reserved_ = 0, in_use_ = 0;
+    size_t reserved_ = 0, in_use_ = 0, soft_limit_ = 0;
 };
 
 }  // namespace vr

@@ -10,6 +10,13 @@ size_t DeviceArena::round_size(size_t bytes)
     return (bytes + large - 1) / large * large;
 }
 
+DeviceArena::DeviceArena(int device) : device_(device)
+{
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) == hipSuccess) soft_limit_ = total_b / 10 * 9;
+    (void)hipGetLastError();
+}
+
 DeviceArena::~DeviceArena()
 {
     std::lock_guard<std::mutex> g(mu_);
@@ -29,6 +36,19 @@ hipEvent_t DeviceArena::take_event()
     return e;
 }
 
+void* DeviceArena::take(std::multimap<size_t, Block>::iterator it, hipStream_t s)
+{
+    Block b = it->second;
+    free_.erase(it);
+    if (b.ev) {
+        if (b.stream != s) (void)hipStreamWaitEvent(s, b.ev, 0);
+        events_.push_back(b.ev);
+    }
+    live_[b.p] = b.size;
+    in_use_ += b.size;
+    return b.p;
+}
+
 void* DeviceArena::alloc(size_t bytes, hipStream_t s)
 {
     const size_t want = round_size(bytes);
@@ -42,16 +62,21 @@ void* DeviceArena::alloc(size_t bytes, hipStream_t s)
         }
         if (best == free_.end()) best = it;
     }
-    if (best != free_.end()) {
-        Block b = best->second;
-        free_.erase(best);
-        if (b.ev) {
-            if (b.stream != s) (void)hipStreamWaitEvent(s, b.ev, 0);
-            events_.push_back(b.ev);
+    if (best != free_.end()) return take(best, s);
+    const bool over = soft_limit_ && reserved_ + want > soft_limit_;
+    if (over) {
+        // near the device's capacity: any larger cached block beats a new one
+        auto it = free_.lower_bound(want);
+        if (it != free_.end()) return take(it, s);
+        // else return the largest cached blocks until the new one fits
+        (void)hipDeviceSynchronize();
+        while (!free_.empty() && reserved_ + want > soft_limit_) {
+            auto last = std::prev(free_.end());
+            (void)hipFree(last->second.p);
+            reserved_ -= last->second.size;
+            if (last->second.ev) events_.push_back(last->second.ev);
+            free_.erase(last);
         }
-        live_[b.p] = b.size;
-        in_use_ += b.size;
-        return b.p;
     }
     void* p = nullptr;
     if (hipMalloc(&p, want) != hipSuccess) {
@@ -62,6 +87,21 @@ void* DeviceArena::alloc(size_t bytes, hipStream_t s)
             (void)hipGetLastError();
             return nullptr;
         }
+    }
+    reserved_ += want;
+    in_use_ += want;
+    live_[p] = want;
+    return p;
+}
+
+void* DeviceArena::alloc_fresh(size_t bytes)
+{
+    const size_t want = round_size(bytes);
+    std::lock_guard<std::mutex> g(mu_);
+    void* p = nullptr;
+    if (hipMalloc(&p, want) != hipSuccess) {
+        (void)hipGetLastError();
+        return nullptr;
     }
     reserved_ += want;
     in_use_ += want;

@@ -18,13 +18,20 @@ DevBuf::~DevBuf()
         arena->release(ptr, stream);
 }
 
+thread_local CaptureKeep* g_capture = nullptr;
+
 BufPtr dev_alloc(vr_context* ctx, size_t bytes, hipStream_t s)
 {
     auto b = std::make_shared<DevBuf>();
     b->bytes = bytes;
     b->stream = s;
     if (bytes == 0) return b;
-    if (ctx->alloc_fn) {
+    if (g_capture) {
+        b->ptr = ctx->arena->alloc_fresh(bytes);
+        if (!b->ptr) throw Error(VR_ENOMEM, "device allocation failed");
+        b->arena = ctx->arena;
+        g_capture->bufs.push_back(b);
+    } else if (ctx->alloc_fn) {
         b->ptr = ctx->alloc_fn(bytes, (void*)s, ctx->alloc_user);
         if (!b->ptr) throw Error(VR_ENOMEM, "allocator hook returned NULL");
         b->free_fn = ctx->free_fn;

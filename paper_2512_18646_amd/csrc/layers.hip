@@ -187,39 +187,57 @@ __global__ __launch_bounds__(kThreads) void k_tensor_batch(u64* out, const u64* 
     o[2 * poly] = mul_mod(a1, b1, m);
 }
 
-// out[o] = sum_i Y_i * P[o][i] (2 components), P plaintexts [nl_pt][N] each
+// out[o] = sum_i Y_i * P[o][i] for outputs o0 .. o0 + kFcGroup - 1 (o0 =
+// blockIdx.z * kFcGroup): one thread per (limb, coefficient) accumulates both
+// components of every output of its group, so each plaintext word is read
+// once and each input word once per group.  Plaintext (o, i) starts at
+// P + (o * n_in + i) * p_stride, limbs [N] each.
+constexpr int kFcGroup = 8;
+
 __global__ __launch_bounds__(kThreads) void k_mulplain_acc(u64* out, u64 out_stride,
                                                            const u64* Y, u64 y_stride, u32 n_in,
-                                                           const u64* const* pts, u32 nl,
-                                                           u32 log_n, const ModQ* mq)
+                                                           const u64* P, u64 p_stride, u32 n_out,
+                                                           u32 nl, u32 log_n, const ModQ* mq)
 {
     const u32 n = 1u << log_n;
     const u32 t = blockIdx.x * kThreads + threadIdx.x;
     if (t >= n) return;
-    const u32 row = blockIdx.y % (2 * nl);
-    const u32 o = blockIdx.y / (2 * nl);
-    const u32 l = row % nl;
+    const u32 l = blockIdx.y;
+    const u32 o0 = blockIdx.z * kFcGroup;
+    const u32 cnt = min((u32)kFcGroup, n_out - o0);
     const ModQ m = mq[l];
-    u64 hi = 0, lo = 0;
+    u64 h0[kFcGroup], l0[kFcGroup], h1[kFcGroup], l1[kFcGroup];
+#pragma unroll
+    for (int g = 0; g < kFcGroup; g++) h0[g] = l0[g] = h1[g] = l1[g] = 0;
+    const size_t off0 = (size_t)l * n + t, off1 = (size_t)(nl + l) * n + t;
     for (u32 i = 0; i < n_in; i++) {
-        u64 y = Y[(size_t)i * y_stride + (size_t)row * n + t];
-        u64 p = pts[(size_t)o * n_in + i][(size_t)l * n + t];
-        mac128(hi, lo, y, p);
-        if ((i & 31) == 31) {   // keep the 128-bit sum below 2^127
-            lo = reduce128(hi, lo, m);
-            hi = 0;
+        const u64 y0 = Y[(size_t)i * y_stride + off0];
+        const u64 y1 = Y[(size_t)i * y_stride + off1];
+#pragma unroll
+        for (int g = 0; g < kFcGroup; g++) {
+            if (g < (int)cnt) {
+                const u64 p = P[((size_t)(o0 + g) * n_in + i) * p_stride + off0];
+                mac128(h0[g], l0[g], y0, p);
+                mac128(h1[g], l1[g], y1, p);
+            }
+        }
+        if ((i & 31) == 31) {   // keep every 128-bit sum below 2^127
+#pragma unroll
+            for (int g = 0; g < kFcGroup; g++) {
+                l0[g] = reduce128(h0[g], l0[g], m);
+                l1[g] = reduce128(h1[g], l1[g], m);
+                h0[g] = h1[g] = 0;
+            }
         }
     }
-    out[(size_t)o * out_stride + (size_t)row * n + t] = reduce128(hi, lo, m);
-}
-
-template <class T>
-T* upload_async(vr_context* ctx, const std::vector<T>& h, BufPtr& holder, hipStream_t s)
-{
-    holder = dev_alloc(ctx, std::max<size_t>(1, h.size()) * sizeof(T), s);
-    if (!h.empty())
-        VR_HIP(hipMemcpyAsync(holder->ptr, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
-    return (T*)holder->ptr;
+#pragma unroll
+    for (int g = 0; g < kFcGroup; g++) {
+        if (g < (int)cnt) {
+            u64* o = out + (size_t)(o0 + g) * out_stride;
+            o[off0] = reduce128(h0[g], l0[g], m);
+            o[off1] = reduce128(h1[g], l1[g], m);
+        }
+    }
 }
 
 // Rotations of every ciphertext of `in` by every step; out[si] is a slab of
@@ -398,6 +416,62 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
 Slab layer_square(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipStream_t s)
 {
     return square_slab(ctx, ek, in, s);
+}
+
+Slab fc_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& y, const u64* P, u64 p_stride,
+             double p_scale, u32 n_out, const double* bias, u32 block, hipStream_t s)
+{
+    if (y.ncomp != 2) throw Error(VR_EINVAL, "FC inputs must be 2-component");
+    if (y.level < 1) throw Error(VR_ELEVEL, "FC needs a level to rescale");
+    const u32 nl = y.level + 1;
+    Slab acc = new_slab(ctx, n_out, 2, y.level, y.scale * p_scale, s);
+    dim3 grid((ctx->n + kThreads - 1) / kThreads, nl, (n_out + kFcGroup - 1) / kFcGroup);
+    hipLaunchKernelGGL(k_mulplain_acc, grid, dim3(kThreads), 0, s, acc.base, acc.stride, y.base,
+                       y.stride, y.n, P, p_stride, n_out, nl, ctx->log_n, ctx->d_modq);
+    VR_CHECK_LAUNCH();
+    Slab z = rescale_slab(ctx, acc, s);
+    // rotate-and-sum inside each block: z += Rot(z, 2^t)
+    for (u32 st = 1; st < block; st <<= 1) {
+        std::vector<Slab> r;
+        rotate_slab(ctx, ek, z, {(int32_t)st}, r, s);
+        launch_addsub(ctx, z.base, z.base, r[0].base, z.n * 2, z.level + 1, false, s);
+    }
+    // bias on the constant coefficient of c0 (every evaluation slot)
+    for (u32 o = 0; o < n_out; o++) {
+        LimbConsts kc;
+        for (u32 l = 0; l <= z.level; l++) kc.c[l] = double_to_mod(bias[o] * z.scale, ctx->mod[l]);
+        launch_add_scalar(ctx, z.ct(o), z.ct(o), z.level + 1, kc, s);
+    }
+    return z;
+}
+
+// Weight plaintexts as one [n_out * n_in][>= nl][N] array: in place when the
+// handles already form one (as vr_encode_fc_weights returns them), else a copy.
+const u64* fc_weights(vr_context* ctx, const vr_plaintext* const* W_pt, size_t count, u32 nl,
+                      u64* p_stride, double* p_scale, BufPtr& holder, hipStream_t s)
+{
+    const vr_plaintext* p0 = W_pt[0];
+    if (!p0) throw Error(VR_EINVAL, "null plaintext");
+    const u64 stride = (u64)(p0->level + 1) * ctx->n;
+    bool contiguous = true;
+    for (size_t i = 0; i < count; i++) {
+        if (!W_pt[i]) throw Error(VR_EINVAL, "null plaintext");
+        if (W_pt[i]->level + 1 < nl) throw Error(VR_ELEVEL, "weight plaintext below the input level");
+        if (W_pt[i]->scale != p0->scale) throw Error(VR_ESCALE, "weight plaintexts at different scales");
+        contiguous = contiguous && W_pt[i]->level == p0->level && W_pt[i]->data == p0->data + i * stride;
+    }
+    *p_scale = p0->scale;
+    if (contiguous) {
+        *p_stride = stride;
+        return p0->data;
+    }
+    const u64 ws = (u64)nl * ctx->n;
+    holder = dev_alloc(ctx, count * ws * sizeof(u64), s);
+    for (size_t i = 0; i < count; i++)
+        VR_HIP(hipMemcpyAsync(as_u64(holder) + i * ws, W_pt[i]->data, ws * sizeof(u64),
+                              hipMemcpyDeviceToDevice, s));
+    *p_stride = ws;
+    return as_u64(holder);
 }
 
 // ------------------------------------------------------------- encodings
@@ -736,38 +810,11 @@ vr_status vr_fc(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* co
     const u32 n_in = C * w_out;
     Slab y = gather(ctx, Y, n_in, s);
     REQUIRE(y.ncomp == 2, "FC inputs must be 2-component");
-    REQUIRE(y.level >= 1, "FC needs a level to rescale");
-    const u32 level = y.level, nl = level + 1;
-    std::vector<const u64*> pts((size_t)n_out * n_in);
-    double pscale = 0;
-    for (size_t i = 0; i < pts.size(); i++) {
-        REQUIRE(W_pt[i], "null plaintext");
-        if (W_pt[i]->level < level) throw Error(VR_ELEVEL, "weight plaintext below the input level");
-        if (i == 0) pscale = W_pt[i]->scale;
-        if (W_pt[i]->scale != pscale) throw Error(VR_ESCALE, "weight plaintexts at different scales");
-        pts[i] = W_pt[i]->data;
-    }
-    BufPtr hp;
-    const u64* const* dp = upload_async(ctx, pts, hp, s);
-    Slab acc = new_slab(ctx, n_out, 2, level, y.scale * pscale, s);
-    dim3 grid((ctx->n + kThreads - 1) / kThreads, n_out * 2 * nl);
-    hipLaunchKernelGGL(k_mulplain_acc, grid, dim3(kThreads), 0, s, acc.base, acc.stride, y.base,
-                       y.stride, n_in, dp, nl, ctx->log_n, ctx->d_modq);
-    VR_CHECK_LAUNCH();
-    Slab z = rescale_slab(ctx, acc, s);
-    // rotate-and-sum inside each block: z += Rot(z, 2^t)
-    for (u32 st = 1; st < block; st <<= 1) {
-        std::vector<Slab> r;
-        rotate_slab(ctx, ek, z, {(int32_t)st}, r, s);
-        launch_addsub(ctx, z.base, z.base, r[0].base, z.n * 2, z.level + 1, false, s);
-    }
-    // bias on the constant coefficient of c0 (every evaluation slot)
-    for (u32 o = 0; o < n_out; o++) {
-        LimbConsts kc;
-        for (u32 l = 0; l <= z.level; l++) kc.c[l] = double_to_mod(bias[o] * z.scale, ctx->mod[l]);
-        launch_add_scalar(ctx, z.ct(o), z.ct(o), z.level + 1, kc, s);
-    }
-    VR_HIP(hipStreamSynchronize(s));
+    BufPtr hold;
+    u64 p_stride = 0;
+    double p_scale = 0;
+    const u64* P = fc_weights(ctx, W_pt, (size_t)n_out * n_in, y.level + 1, &p_stride, &p_scale, hold, s);
+    Slab z = fc_slab(ctx, ek, y, P, p_stride, p_scale, n_out, bias, block, s);
     to_handles(ctx, z, out);
     API_END
 }

@@ -130,7 +130,6 @@ void build_context(vr_context* ctx, const vr_params* p, int device)
         if (b < 20 || b > 60) throw Error(VR_EINVAL, "prime sizes must be in [20, 60] bits");
 
     ctx->device = device;
-    ctx->arena = std::make_shared<DeviceArena>(device);
     ctx->log_n = p->log_n;
     ctx->n = 1u << p->log_n;
     ctx->slots = ctx->n / 2;
@@ -154,6 +153,7 @@ void build_context(vr_context* ctx, const vr_params* p, int device)
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= device)
         throw Error(VR_EDEVICE, "no HIP device available");
     VR_HIP(hipSetDevice(device));
+    ctx->arena = std::make_shared<DeviceArena>(device);
 
     const u32 n = ctx->n, nmod = ctx->nmod();
     ctx->modq.resize(nmod);

@@ -27,5 +27,11 @@ Slab conv_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& x, u32 n_set
                hipStream_t s);
 // x^2 of every ciphertext: Rescale(Relin(Tensor(y, y)))
 Slab layer_square(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipStream_t s);
+// FC layer: Z_o = RotSum_block(Rescale(sum_i y_i * P[o][i])) + bias_o with the
+// weight plaintexts P[o][i] at P + (o * y.n + i) * p_stride
+Slab fc_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& y, const u64* P, u64 p_stride,
+             double p_scale, u32 n_out, const double* bias, u32 block, hipStream_t s);
+const u64* fc_weights(vr_context* ctx, const vr_plaintext* const* W_pt, size_t count, u32 nl,
+                      u64* p_stride, double* p_scale, BufPtr& holder, hipStream_t s);
 
 }  // namespace vr

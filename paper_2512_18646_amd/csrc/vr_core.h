@@ -155,6 +155,14 @@ struct DevBuf {
 };
 typedef std::shared_ptr<DevBuf> BufPtr;
 
+// Set on a thread while it captures a graph: every allocation it makes is
+// taken fresh from the runtime and held here, so no block is released (and
+// handed to other work) while the graph may still use it.
+struct CaptureKeep {
+    std::vector<BufPtr> bufs;
+};
+extern thread_local CaptureKeep* g_capture;
+
 // Kernel classes the event profiler can bracket.
 enum ProfClass : int {
     kProfNtt = 0,       // one forward/inverse NTT call (all its passes); units = limbs

@@ -35,6 +35,14 @@ class VRError(RuntimeError):
         self.code = code
 
 
+class vr_cnn_desc(ctypes.Structure):
+    _fields_ = [("C_in", ctypes.c_uint32), ("h", ctypes.c_uint32), ("w", ctypes.c_uint32),
+                ("pad", ctypes.c_uint32), ("C_out", ctypes.c_uint32), ("k", ctypes.c_uint32),
+                ("stride", ctypes.c_uint32), ("K", ctypes.c_void_p), ("bias", ctypes.c_void_p),
+                ("square", ctypes.c_uint32), ("fc_w", ctypes.c_void_p), ("fc_bias", ctypes.c_void_p),
+                ("fc_out", ctypes.c_uint32), ("fc_block", ctypes.c_uint32)]
+
+
 class vr_params(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("n_p", ctypes.c_uint32),
                 ("dnum", ctypes.c_uint32), ("q_bits", ctypes.POINTER(ctypes.c_uint32)),
@@ -93,6 +101,12 @@ _SIGS = {
     "vr_profile_start": [P, ctypes.c_char_p, SZ],
     "vr_profile_stop": [P, ctypes.POINTER(DBL), ctypes.POINTER(U64), ctypes.POINTER(U64),
                         ctypes.POINTER(U32)],
+    "vr_cnn_forward": [P, P, P, PP, U32, PP, P],
+    "vr_graph_create": [P, P, P, PP, U32, PP],
+    "vr_graph_set_inputs": [P, PP, SZ, P],
+    "vr_graph_launch": [P, P],
+    "vr_graph_outputs": [P, PP, SZ, ctypes.POINTER(SZ)],
+    "vr_graph_destroy": [P],
     "vr_srv_create": [P, SZ, U32, PP],
     "vr_srv_destroy": [P],
     "vr_srv_register_session": [P, P, ctypes.POINTER(U64)],
@@ -109,7 +123,7 @@ _SIGS = {
     "vr_free_keys": [P, P],
     "vr_last_error": [],
 }
-_VOID = {"vr_context_destroy", "vr_srv_destroy", "vr_free_ciphertext", "vr_free_plaintext", "vr_free_keys"}
+_VOID = {"vr_context_destroy", "vr_srv_destroy", "vr_graph_destroy", "vr_free_ciphertext", "vr_free_plaintext", "vr_free_keys"}
 
 
 def _load():
@@ -528,3 +542,68 @@ class Server:
                                 ctypes.byref(done), ctypes.byref(waves), ctypes.byref(batched)))
         return {"p50_ms": p50.value, "p99_ms": p99.value, "images_per_s": ips.value,
                 "completed": done.value, "waves": waves.value, "batched": batched.value}
+
+
+class CNN:
+    """Network description (vr_cnn_desc): conv, optional x^2, optional FC."""
+
+    def __init__(self, C_in, h, w, pad, K, bias, stride, square=True, fc_w=None, fc_bias=None,
+                 fc_block=0):
+        self.K, self.bias = _f64(K), _f64(bias)
+        self.C_out, _, self.k, _ = self.K.shape
+        self.C_in, self.h, self.w, self.pad, self.stride = C_in, h, w, pad, stride
+        self.w_out = (w + 2 * pad - self.k) // stride + 1
+        self.fc_w = list(fc_w) if fc_w is not None else None
+        self.fc_bias = _f64(fc_bias) if fc_bias is not None else None
+        self._fc_arr = _ptr_array(self.fc_w) if self.fc_w else None
+        self.desc = vr_cnn_desc(C_in, h, w, pad, self.C_out, self.k, stride, self.K.ctypes.data,
+                                self.bias.ctypes.data, 1 if square else 0,
+                                ctypes.cast(self._fc_arr, ctypes.c_void_p) if self.fc_w else None,
+                                self.fc_bias.ctypes.data if self.fc_w else None,
+                                self.fc_bias.size if self.fc_w else 0, fc_block)
+
+    def outputs_per_set(self):
+        return self.fc_bias.size if self.fc_w else self.C_out * self.w_out
+
+    def forward(self, ctx, keys, cols, n_sets=1, stream=None):
+        n = n_sets * self.outputs_per_set()
+        arr = (ctypes.c_void_p * n)()
+        _check(lib.vr_cnn_forward(ctx.h, keys.ek, ctypes.byref(self.desc), _ptr_array(cols), n_sets, arr,
+                                  _stream(stream)))
+        return [Ciphertext(arr[i], ctx) for i in range(n)]
+
+
+class Graph:
+    """A network captured into a HIP graph (vr_graph_*)."""
+
+    def __init__(self, ctx, keys, net, cols, n_sets=1):
+        self.ctx, self.keys, self.net, self.n_sets = ctx, keys, net, n_sets
+        h = ctypes.c_void_p()
+        _check(lib.vr_graph_create(ctx.h, keys.ek, ctypes.byref(net.desc), _ptr_array(cols), n_sets,
+                                   ctypes.byref(h)))
+        self.h = h.value
+        self.n_in = len(cols)
+
+    def set_inputs(self, cols, stream=None):
+        _check(lib.vr_graph_set_inputs(self.h, _ptr_array(cols), len(cols), _stream(stream)))
+
+    def launch(self, stream=None):
+        _check(lib.vr_graph_launch(self.h, _stream(stream)))
+
+    def outputs(self):
+        cap = self.n_sets * self.net.outputs_per_set()
+        arr = (ctypes.c_void_p * cap)()
+        n = SZ()
+        _check(lib.vr_graph_outputs(self.h, arr, cap, ctypes.byref(n)))
+        return [Ciphertext(arr[i], self.ctx) for i in range(n.value)]
+
+    def close(self):
+        if self.h:
+            lib.vr_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,88 @@
+"""The whole-network call and its HIP-graph capture: identical limbs to the
+per-layer calls, on every replay, with eager work and synchronisations
+between replays and after new inputs are copied in."""
+import numpy as np
+import pytest
+
+from oracle import layers as Ly
+from tests.gpu_helpers import pair
+
+pytestmark = pytest.mark.gpu
+
+B, CI, H, W_, CO, K_, S_, PAD = 8, 2, 10, 9, 3, 3, 2, 1
+
+
+@pytest.fixture(scope="module")
+def net():
+    from paper_2512_18646_amd import vr
+    o, ok, g, gk = pair("C1", rot_steps=(1, 2, 4, 8), log_n=10)
+    rng = np.random.default_rng(51)
+    K = rng.normal(0, 0.1, (CO, CI, K_, K_))
+    bias = rng.normal(0, 0.1, CO)
+    Hp = Ly.image_block(H, PAD)
+    wo = Ly.conv_out_size(W_, PAD, K_, S_)
+    ho = Ly.conv_out_size(H, PAD, K_, S_)
+    Wfc = rng.normal(0, 0.05, (4, CO, ho, wo))
+    fb = rng.normal(0, 0.05, 4)
+    pts = g.encode_fc_weights(Wfc, S_, Hp, 1)
+    full = vr.CNN(CI, H, W_, PAD, K, bias, S_, square=True, fc_w=pts, fc_bias=fb, fc_block=Hp)
+    conv_sq = vr.CNN(CI, H, W_, PAD, K, bias, S_, square=True)
+    sets = [g.encrypt_columns(gk, rng.uniform(0, 1, (B, CI, H, W_)), PAD, 3, 61, 100 * i)
+            for i in range(4)]
+    return g, gk, full, conv_sq, sets, (K, bias, Wfc, fb, pts, Hp, wo)
+
+
+def layers_ref(g, gk, cols, params, fc=True):
+    K, bias, Wfc, fb, pts, Hp, wo = params
+    y = g.square(gk, g.conv2d(gk, cols, CI, H, W_, PAD, K, bias, S_))
+    return g.fc(gk, y, CO, wo, pts, fb, Hp) if fc else y
+
+
+def limbs(cts):
+    return [c.export() for c in cts]
+
+
+def check(got, ref, what):
+    assert len(got) == len(ref), what
+    for i, (a, b) in enumerate(zip(got, ref)):
+        assert a.meta == b.meta, (what, i)
+        assert np.array_equal(a.export(), b.export()), "%s: output %d differs" % (what, i)
+
+
+def test_cnn_forward_matches_layer_calls(net):
+    g, gk, full, conv_sq, sets, params = net
+    out = full.forward(g, gk, sets[0] + sets[1], n_sets=2)
+    check(out[:4], layers_ref(g, gk, sets[0], params), "set 0")
+    check(out[4:], layers_ref(g, gk, sets[1], params), "set 1")
+    out2 = conv_sq.forward(g, gk, sets[2], n_sets=1)
+    check(out2, layers_ref(g, gk, sets[2], params, fc=False), "conv + x^2")
+
+
+def test_graph_replays_match_eager(net):
+    from paper_2512_18646_amd import vr
+    g, gk, full, conv_sq, sets, params = net
+    ref01 = [layers_ref(g, gk, sets[i], params) for i in (0, 1)]
+    ref23 = [layers_ref(g, gk, sets[i], params) for i in (2, 3)]
+    gr = vr.Graph(g, gk, full, sets[0] + sets[1], n_sets=2)
+    for rep in range(3):
+        gr.launch()
+        out = gr.outputs()
+        check(out[:4], ref01[0], "replay %d set 0" % rep)
+        check(out[4:], ref01[1], "replay %d set 1" % rep)
+        layers_ref(g, gk, sets[3], params)          # eager work between replays
+    gr.set_inputs(sets[2] + sets[3])
+    for rep in range(2):
+        gr.launch()
+        out = gr.outputs()
+        check(out[:4], ref23[0], "new inputs replay %d set 0" % rep)
+        check(out[4:], ref23[1], "new inputs replay %d set 1" % rep)
+        conv_sq.forward(g, gk, sets[0])[0].export()
+    kept = limbs(out)
+    gr.close()
+    assert all(np.array_equal(a, b.export()) for a, b in zip(kept, out))   # handles outlive the graph
+    g2 = vr.Graph(g, gk, conv_sq, sets[1])
+    ref = layers_ref(g, gk, sets[1], params, fc=False)
+    for rep in range(3):
+        g2.launch()
+        check(g2.outputs(), ref, "conv + x^2 graph replay %d" % rep)
+    g2.close()

@@ -197,3 +197,41 @@ def test_conv28_gpu_only_end_to_end():
     got = gpu_conv_decode(g, gk, gY2, W.batch, W.c_out, W.h, W.pad, W.k, W.stride, W.w)
     assert gY2[0].level == 5
     assert Ly.rel_error(got, ref ** 2) < EPS
+
+
+def test_cnn128_trimmed_sampled():
+    """The 3x128x128 network at N = 2^16 (L = 24 chain, dnum 3, 9-prime
+    digits) on one 128-image set entering at level 3: GPU conv on all 384
+    columns, oracle on output column 0 of every filter (inputs 0 and 1 of each
+    channel encrypted by the oracle), x^2 of one output, then the GPU FC on
+    the whole set against the FP64 network."""
+    W = SI.CNN_128
+    o, ok, g, gk = pair("C3", rot_steps=(1, 2))
+    X, K, bias = W.draw()
+    Hp = Ly.image_block(W.h, W.pad)
+    gcols = g.encrypt_columns(gk, X, W.pad, 3, 3003, 0)
+    ocols = [None] * (W.channels * W.w)
+    for c in range(W.channels):
+        for j in (0, 1):
+            slots = Ly.image_column_slots(o, X, c, j, W.pad)
+            ocols[c * W.w + j] = o.encrypt(ok, o.encode(slots, 3, o.scale), 3003, c * W.w + j)
+            gcols[c * W.w + j] = to_gpu(g, ocols[c * W.w + j])
+    gY = g.conv2d(gk, gcols, W.channels, W.h, W.w, W.pad, K, bias, W.stride)
+    wo = Ly.conv_out_size(W.w, W.pad, W.k, W.stride)
+    assert len(gY) == W.c_out * wo == 512
+    Y = Ly.conv2d(o, ok, ocols, W.channels, W.h, W.w, W.pad, K, bias, W.c_out, W.k, W.stride,
+                  only_cols={0})
+    for co in range(W.c_out):
+        assert_same(gY[co * wo], Y[co * wo], "cnn128 conv out (%d, 0)" % co)
+    gY2 = g.square(gk, gY)
+    assert_same(gY2[3 * wo], Ly.square(o, ok, Y[3 * wo]), "cnn128 square")
+    Wfc, bfc = W.draw_fc()
+    gk.add_rotations(SEED_KEYS, [1 << t for t in range(2, Hp.bit_length() - 1)])   # FC rotate-and-sum
+    pts = g.encode_fc_weights(Wfc, W.stride, Hp, gY2[0].meta[1])
+    gZ = g.fc(gk, gY2, W.c_out, wo, pts, bfc, Hp)
+    logits = np.zeros((W.batch, W.fc_out))
+    for oi, z in enumerate(gZ):
+        logits[:, oi] = g.decode(g.decrypt(gk, z))[np.arange(W.batch) * Hp]
+    ref = Ly.ref_fc(Ly.ref_conv(X, K, bias, W.stride, W.pad) ** 2, Wfc, bfc)
+    assert gZ[0].meta[1] == 0
+    assert Ly.rel_error(logits, ref) < EPS
