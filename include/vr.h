@@ -109,6 +109,12 @@ vr_status vr_context_mem_info(vr_context *ctx, size_t *reserved, size_t *in_use)
 /* Synchronises the device and returns the built-in allocator's cached free
  * blocks to the runtime. */
 vr_status vr_context_trim(vr_context *ctx);
+/* Kernel choices.  Knob "base_convert": "auto" (default: each base-conversion
+ * table times the vector-ALU and the INT8-split MFMA kernel on its first call
+ * and keeps the faster; both give identical words), "alu" or "mfma". */
+vr_status vr_context_set_tuning(vr_context *ctx, const char *knob, const char *value);
+/* One line per base-conversion table built so far: shape and kernel chosen. */
+vr_status vr_context_tuning_report(vr_context *ctx, char *buf, size_t cap);
 const char *vr_last_error(void);
 
 /* ------------------------------------------------------------ client side */

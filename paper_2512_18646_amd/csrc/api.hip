@@ -169,6 +169,39 @@ vr_status vr_context_mem_info(vr_context* ctx, size_t* reserved, size_t* in_use)
     API_END
 }
 
+vr_status vr_context_set_tuning(vr_context* ctx, const char* knob, const char* value)
+{
+    API_BEGIN
+    REQUIRE(ctx && knob && value, "null argument");
+    std::string k(knob), v(value);
+    REQUIRE(k == "base_convert", "unknown tuning knob");
+    int mode = v == "auto" ? 0 : v == "alu" ? 1 : v == "mfma" ? 2 : -1;
+    REQUIRE(mode >= 0, "base_convert takes auto, alu or mfma");
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->tuning[k] = mode;
+    API_END
+}
+
+vr_status vr_context_tuning_report(vr_context* ctx, char* buf, size_t cap)
+{
+    API_BEGIN
+    REQUIRE(ctx && buf && cap > 0, "null argument");
+    std::string r;
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto name = [](int c) { return c < 0 ? "untimed" : c == 1 ? "mfma" : "alu"; };
+    for (auto& kv : ctx->modup_tables)
+        r += "modup l" + std::to_string(kv.first.first) + " d" + std::to_string(kv.first.second) + " " +
+             std::to_string(kv.second.n_in) + "->" + std::to_string(kv.second.n_out) + ": " +
+             name(kv.second.choice ? kv.second.choice->load() : -1) + "\n";
+    for (auto& kv : ctx->moddown_tables)
+        r += "moddown l" + std::to_string(kv.first) + " " + std::to_string(kv.second.n_in) + "->" +
+             std::to_string(kv.second.n_out) + ": " +
+             name(kv.second.choice ? kv.second.choice->load() : -1) + "\n";
+    REQUIRE(r.size() < cap, "report buffer too small");
+    memcpy(buf, r.c_str(), r.size() + 1);
+    API_END
+}
+
 vr_status vr_context_trim(vr_context* ctx)
 {
     API_BEGIN

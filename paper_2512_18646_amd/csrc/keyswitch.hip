@@ -11,6 +11,16 @@
 // keeps the <= 16 inputs in registers and streams the targets; the 128-bit
 // dot product is reduced once per target.
 //
+// The same contraction on the matrix cores, exactly: every y_i (< 2^60) and
+// every constant W (< 2^61) is written in balanced base 256, eight signed
+// digits in [-128, 127], so that sum_i y_i W = sum_c 2^(8c) S_c with
+// S_c = sum_{i, a + b = c} y_{i,a} W_{i,b} an int8 dot product (|S_c| < 2^21).
+// One v_mfma_i32_16x16x32_i8 takes 4 inputs x 8 digits on K, 16 coefficients
+// on N and (4 targets x 4 values of c) on M; four such tiles give a lane all
+// sixteen S_c of one (target, coefficient), which it shifts into the exact
+// 128-bit sum and reduces once.  The n_neg term rides along as one more input
+// whose only digit is n_neg.  Which kernel runs is timed once per table.
+//
 // Inner product: every extended limb e reads the beta digits of X (through the
 // Galois permutation for rotations) and the key limbs b_j, a_j once; the
 // batched form keeps the key values in registers and loops over ciphertexts
@@ -31,6 +41,16 @@ __device__ __forceinline__ u32 galois_src(u32 i, u32 g, u32 log_n)
     u32 mask = (2u << log_n) - 1;
     u32 e = (u32)(((u64)g * (2 * brev_n(i, log_n) + 1)) & mask);
     return brev_n((e - 1) >> 1, log_n);
+}
+
+typedef int v4i __attribute__((ext_vector_type(4)));
+
+// balanced base-256 digits of x < 2^63 as eight signed bytes:
+// x = sum_a d_a 256^a with byte a = d_a
+__host__ __device__ __forceinline__ u64 balanced_bytes(u64 x)
+{
+    const u64 h = 0x8080808080808080ull;
+    return (x + h) ^ h;
 }
 
 struct ConvArgs {
@@ -105,6 +125,80 @@ __global__ __launch_bounds__(kThreads) void k_base_convert(ConvArgs a)
         r = csub(r, 2 * q);
         u32 slot = o < a.skip_at ? o : o + a.skip_len;
         out[(size_t)slot * n + t] = csub(r, q);
+    }
+}
+
+constexpr u32 kMfmaCoef = 256;    // coefficients per block: 4 waves x 4 tiles of 16
+constexpr u32 kDigitRow = 264;    // LDS row pitch of the digit words (padded)
+
+__global__ __launch_bounds__(256) void k_base_convert_mfma(ConvArgs a, const u64* wt, u32 steps,
+                                                            u32 groups, u32 n_polys)
+{
+    extern __shared__ u64 lds[];
+    const u32 tw = groups * 4 * steps * 64;
+    u64* s_wt = lds;                  // [groups][4][steps][64]
+    u64* s_d = lds + tw;              // [4 * steps][kDigitRow]
+    for (u32 e = threadIdx.x; e < tw; e += 256) s_wt[e] = wt[e];
+    const u32 n = 1u << a.log_n;
+    const u64* qinv = a.tab;
+    const u64* qinv_s = a.tab + a.n_in;
+    const u64* in_mod = a.tab + 2 * a.n_in + (size_t)a.n_in * a.n_out + a.n_out;
+    const u64* out_mod = in_mod + a.n_in;
+    const u32 base = blockIdx.x * kMfmaCoef;
+    const u32 lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const u32 g = lane >> 4, col = lane & 15;
+    for (u32 poly = blockIdx.y; poly < n_polys; poly += gridDim.y) {
+        // digit words of this block's coefficients: row i = input i, row n_in = n_neg
+        const u64* in = a.in + (size_t)poly * a.in_stride;
+        const u32 t = base + threadIdx.x;
+        u32 n_neg = 0;
+        for (u32 i = 0; i < 4 * steps; i++) {
+            u64 w = 0;
+            if (i < a.n_in && t < n) {
+                const u64 q = a.mq[in_mod[i]].q;
+                const u64 v = shoup(in[(size_t)i * n + t], qinv[i], qinv_s[i], q);
+                n_neg += v > (q >> 1) ? 1 : 0;
+                w = balanced_bytes(v);
+            }
+            s_d[i * kDigitRow + threadIdx.x] = w;
+        }
+        s_d[a.n_in * kDigitRow + threadIdx.x] = n_neg;
+        __syncthreads();
+        u64* out = a.out + (size_t)poly * a.out_stride;
+        for (u32 u = 0; u < 4; u++) {
+            const u32 nl = wave * 64 + u * 16 + col;
+            const u32 coef = base + nl;
+            long b[4];
+#pragma unroll
+            for (u32 s = 0; s < 4; s++) b[s] = s < steps ? (long)s_d[(4 * s + g) * kDigitRow + nl] : 0;
+            for (u32 G = 0; G < groups; G++) {
+                i64 P[4];
+#pragma unroll
+                for (u32 m = 0; m < 4; m++) {
+                    v4i acc = {0, 0, 0, 0};
+                    const u64* w = s_wt + (size_t)(G * 4 + m) * steps * 64 + lane;
+#pragma unroll
+                    for (u32 s = 0; s < 4; s++)
+                        if (s < steps)
+                            acc = __builtin_amdgcn_mfma_i32_16x16x32_i8((long)w[s * 64], b[s], acc, 0, 0, 0);
+                    // rows 4g + r of tile m are c = 4m + r of target 4G + g
+                    P[m] = (i64)acc[0] + ((i64)acc[1] << 8) + ((i64)acc[2] << 16) + ((i64)acc[3] << 24);
+                }
+                // V = sum_m P[m] 2^(32 m), exact in two's complement 128 bits
+                u64 lo = (u64)P[0], hi = (u64)(P[0] >> 63);
+                const u64 x1 = (u64)P[1] << 32;
+                lo += x1;
+                hi += (u64)(P[1] >> 32) + (lo < x1 ? 1 : 0);
+                hi += (u64)P[2] + ((u64)P[3] << 32);
+                const u32 o = G * 4 + g;
+                if (o < a.n_out && coef < n) {
+                    const ModQ& mq = a.mq[out_mod[o]];
+                    const u32 slot = o < a.skip_at ? o : o + a.skip_len;
+                    out[(size_t)slot * n + coef] = reduce128(hi, lo, mq);
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -249,6 +343,31 @@ ConvTable build_table(vr_context* ctx, const std::vector<u32>& in, const std::ve
     tb.words = h.size();
     VR_HIP(hipMalloc(&tb.dev, tb.words * sizeof(u64)));
     VR_HIP(hipMemcpy(tb.dev, h.data(), tb.words * sizeof(u64), hipMemcpyHostToDevice));
+    // matrix-core table: lane l of (group G, tile m, step s) holds row
+    // rho = l % 16 (target 4G + rho / 4, c = 4m + rho % 4) and inputs
+    // i = 4s + l / 16; byte a is digit c - a of that input's constant
+    tb.steps = (tb.n_in + 1 + 3) / 4;
+    tb.groups = (tb.n_out + 3) / 4;
+    std::vector<u64> wt((size_t)tb.groups * 4 * tb.steps * 64, 0);
+    for (u32 G = 0; G < tb.groups; G++)
+        for (u32 m = 0; m < 4; m++)
+            for (u32 s = 0; s < tb.steps; s++)
+                for (u32 l = 0; l < 64; l++) {
+                    const u32 rho = l & 15, o = 4 * G + (rho >> 2), c = 4 * m + (rho & 3);
+                    const u32 i = 4 * s + (l >> 4);
+                    if (o >= tb.n_out || i > tb.n_in) continue;
+                    const u64 W = i < tb.n_in ? qhat[(size_t)i * tb.n_out + o] : negq[o];
+                    const u64 e = balanced_bytes(W);
+                    u64 word = 0;
+                    for (u32 aa = 0; aa < 8; aa++) {
+                        const int b = (int)c - (int)aa;
+                        if (b >= 0 && b < 8) word |= ((e >> (8 * b)) & 0xff) << (8 * aa);
+                    }
+                    wt[(((size_t)G * 4 + m) * tb.steps + s) * 64 + l] = word;
+                }
+    VR_HIP(hipMalloc(&tb.wt, wt.size() * sizeof(u64)));
+    VR_HIP(hipMemcpy(tb.wt, wt.data(), wt.size() * sizeof(u64), hipMemcpyHostToDevice));
+    tb.choice = std::make_shared<std::atomic<int>>(-1);
     return tb;
 }
 
@@ -278,12 +397,69 @@ const ConvTable& moddown_table(vr_context* ctx, u32 level)
     return ctx->moddown_tables[(int)level] = build_table(ctx, in, out);
 }
 
-void launch_convert(vr_context* ctx, const ConvArgs& a, u32 n_polys, hipStream_t s)
+void launch_alu(vr_context* ctx, const ConvArgs& a, u32 n_polys, hipStream_t s)
 {
     dim3 grid((ctx->n + kThreads - 1) / kThreads, n_polys);
-    ProfScope prof(ctx, kProfBaseConv, s, (u64)n_polys * a.n_out);
     hipLaunchKernelGGL(k_base_convert, grid, dim3(kThreads), 0, s, a);
     VR_CHECK_LAUNCH();
+}
+
+void launch_mfma(vr_context* ctx, const ConvArgs& a, const ConvTable& tb, u32 n_polys, hipStream_t s)
+{
+    static std::once_flag attr;
+    std::call_once(attr, [] {
+        (void)hipFuncSetAttribute((const void*)k_base_convert_mfma,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    });
+    const size_t shmem = ((size_t)tb.groups * 4 * tb.steps * 64 + (size_t)4 * tb.steps * kDigitRow) * 8;
+    // a few polynomials per block so the constant table is staged into LDS
+    // about 4k times per call, not once per 256 coefficients of every poly
+    const u32 xblocks = ctx->n / kMfmaCoef;
+    const u32 ypolys = std::max(1u, std::min(n_polys, (4096 + xblocks - 1) / xblocks));
+    hipLaunchKernelGGL(k_base_convert_mfma, dim3(xblocks, ypolys), dim3(256), shmem, s, a, tb.wt,
+                       tb.steps, tb.groups, n_polys);
+    VR_CHECK_LAUNCH();
+}
+
+bool mfma_usable(vr_context* ctx, const ConvTable& tb)
+{
+    const size_t shmem = ((size_t)tb.groups * 4 * tb.steps * 64 + (size_t)4 * tb.steps * kDigitRow) * 8;
+    return ctx->n >= kMfmaCoef && tb.wt && shmem <= 160 * 1024;
+}
+
+// Both kernels give the same words, so the first call of a table runs each
+// once on the real operands under events and keeps the faster.
+void launch_convert(vr_context* ctx, const ConvArgs& a, const ConvTable& tb, u32 n_polys,
+                    hipStream_t s)
+{
+    ProfScope prof(ctx, kProfBaseConv, s, (u64)n_polys * a.n_out);
+    int mode = 0;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->tuning.find("base_convert");
+        if (it != ctx->tuning.end()) mode = it->second;
+    }
+    if (!mfma_usable(ctx, tb) || mode == 1) return launch_alu(ctx, a, n_polys, s);
+    if (mode == 2) return launch_mfma(ctx, a, tb, n_polys, s);
+    int c = tb.choice->load();
+    if (c < 0 && !g_capture && ctx->prof.cls < 0) {
+        hipEvent_t ev[3];
+        for (auto& e : ev) VR_HIP(hipEventCreate(&e));
+        VR_HIP(hipEventRecord(ev[0], s));
+        launch_alu(ctx, a, n_polys, s);
+        VR_HIP(hipEventRecord(ev[1], s));
+        launch_mfma(ctx, a, tb, n_polys, s);
+        VR_HIP(hipEventRecord(ev[2], s));
+        VR_HIP(hipEventSynchronize(ev[2]));
+        float t_alu = 0, t_mfma = 0;
+        VR_HIP(hipEventElapsedTime(&t_alu, ev[0], ev[1]));
+        VR_HIP(hipEventElapsedTime(&t_mfma, ev[1], ev[2]));
+        for (auto& e : ev) (void)hipEventDestroy(e);
+        tb.choice->store(t_mfma < t_alu ? 1 : 0);
+        return;
+    }
+    if (c == 1) return launch_mfma(ctx, a, tb, n_polys, s);
+    launch_alu(ctx, a, n_polys, s);
 }
 
 }  // namespace
@@ -337,7 +513,7 @@ void keyswitch_modup_batch(vr_context* ctx, const u64* d, u64 d_stride, u32 n_ct
         a.n_out = tb.n_out;
         a.log_n = ctx->log_n;
         a.mq = ctx->d_modq;
-        launch_convert(ctx, a, n_ct, s);
+        launch_convert(ctx, a, tb, n_ct, s);
         // the digit's own limbs are d itself (already in the evaluation domain)
         launch_copy_rows(X + ((size_t)j * k.next + lo) * n, xs, d + (size_t)lo * n, d_stride,
                          (u64)(hi - lo) * n, n_ct, s);
@@ -429,7 +605,7 @@ void keyswitch_moddown_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u3
     a.n_out = tb.n_out;
     a.log_n = ctx->log_n;
     a.mq = ctx->d_modq;
-    launch_convert(ctx, a, n_ct * 2, s);
+    launch_convert(ctx, a, tb, n_ct * 2, s);
     ntt_forward(ctx, poly_limbs(Y, Y, n_ct * 2, k.nq, (u64)k.nq * n, (int)level), s);
     dim3 grid((n + kThreads - 1) / kThreads, n_ct * k.nq);
     ProfScope prof(ctx, kProfModDown, s, (u64)n_ct * 2 * k.nq);

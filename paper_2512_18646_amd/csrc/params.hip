@@ -224,8 +224,8 @@ void destroy_context_tables(vr_context* ctx)
     (void)hipFree(ctx->d_itw);
     (void)hipFree(ctx->d_fft_tw);
     (void)hipFree(ctx->d_gexp);
-    for (auto& kv : ctx->modup_tables) (void)hipFree(kv.second.dev);
-    for (auto& kv : ctx->moddown_tables) (void)hipFree(kv.second.dev);
+    for (auto& kv : ctx->modup_tables) (void)hipFree(kv.second.dev), (void)hipFree(kv.second.wt);
+    for (auto& kv : ctx->moddown_tables) (void)hipFree(kv.second.dev), (void)hipFree(kv.second.wt);
 }
 
 }  // namespace vr

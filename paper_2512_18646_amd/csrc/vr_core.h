@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <atomic>
 #include <cstdint>
 #include <map>
 #include <memory>
@@ -188,6 +189,12 @@ struct ConvTable {
     u64* dev = nullptr;    // device: [n_in] qhat_inv, [n_in] qhat_inv_s, [n_in][n_out] qhat mod t,
                            //         [n_out] (-Q) mod t, then u32 in_mod[n_in], out_mod[n_out]
     size_t words = 0;
+    // matrix-core form: balanced base-256 digit words of the same constants,
+    // [groups][4][steps][64] (one 64-bit A operand per lane and instruction)
+    u64* wt = nullptr;
+    u32 steps = 0, groups = 0;
+    // kernel chosen for this table: -1 not yet timed, 0 vector ALU, 1 MFMA
+    std::shared_ptr<std::atomic<int>> choice;
 };
 
 }  // namespace vr
@@ -211,6 +218,8 @@ struct vr_context {
     // device-resident constants of layer calls (weights, term lists), keyed by
     // the call's shape and weight bytes, so repeated calls upload nothing
     std::map<std::string, std::shared_ptr<void>> plans;
+    // kernel choices: "base_convert" = 0 autotune, 1 vector ALU, 2 MFMA
+    std::map<std::string, int> tuning;
     std::mutex mu;
     hipStream_t stream = nullptr;     // used when a call passes stream = NULL
     std::shared_ptr<vr::DeviceArena> arena;

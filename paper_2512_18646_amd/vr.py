@@ -63,6 +63,8 @@ _SIGS = {
     "vr_context_set_allocator": [P, P, P, P],
     "vr_context_mem_info": [P, ctypes.POINTER(SZ), ctypes.POINTER(SZ)],
     "vr_context_trim": [P],
+    "vr_context_set_tuning": [P, ctypes.c_char_p, ctypes.c_char_p],
+    "vr_context_tuning_report": [P, ctypes.c_char_p, SZ],
     "vr_keygen": [P, U64, P, SZ, PP, PP],
     "vr_keys_add_rotations": [P, P, P, U64, P, SZ],
     "vr_encode": [P, P, SZ, U32, DBL, PP],
@@ -294,6 +296,14 @@ class Context:
 
     def trim(self):
         _check(lib.vr_context_trim(self.h))
+
+    def set_tuning(self, knob, value):
+        _check(lib.vr_context_set_tuning(self.h, knob.encode(), value.encode()))
+
+    def tuning_report(self):
+        buf = ctypes.create_string_buffer(1 << 16)
+        _check(lib.vr_context_tuning_report(self.h, buf, len(buf)))
+        return buf.value.decode()
 
     def profile_start(self, kernel_class, max_launches=65536):
         _check(lib.vr_profile_start(self.h, kernel_class.encode(), max_launches))

@@ -168,19 +168,29 @@ def test_rotation_decrypts_on_gpu():
         assert np.max(np.abs(d - np.roll(z, -st))) < 2.0 ** -20, st
 
 
+@pytest.mark.parametrize("mode", ["alu", "mfma", "auto"])
 @pytest.mark.parametrize("name,level", [("C2", 2), ("C2", 7), ("C3", 3), ("C3", 24), ("C3", 20)])
-def test_keyswitch_match_other_chains(name, level):
+def test_keyswitch_match_other_chains(name, level, mode):
     """Rotation and relinearisation with 60-bit q_0 / special primes (C2) and
-    9-prime digits with a short last digit (C3 at levels 3 and 20)."""
+    9-prime digits with a short last digit (C3 at levels 3 and 20), with the
+    base conversions on the vector ALU, on the INT8 matrix cores, and as the
+    autotuner picks (its first call runs both kernels)."""
     o, ok, g, gk = pair(name, rot_steps=(1, 3))
     z = np.random.default_rng(level).uniform(-1, 1, o.slots)
     a = o.encrypt(ok, o.encode(z, level, o.scale), 9, level)
     ga = to_gpu(g, a)
-    assert_same(g.rotate(gk, ga, 1), o.rotate(a, 1, ok), "%s rotate l=%d" % (name, level))
-    many = g.rotate_many(gk, ga, [3, 1])
-    assert_same(many[0], o.rotate(a, 3, ok), "%s hoisted 3" % name)
-    t = o.tensor(a, a)
-    assert_same(g.relinearize(gk, to_gpu(g, t)), o.relinearize(t, ok), "%s relin" % name)
+    g.set_tuning("base_convert", mode)
+    try:
+        assert_same(g.rotate(gk, ga, 1), o.rotate(a, 1, ok), "%s rotate l=%d %s" % (name, level, mode))
+        many = g.rotate_many(gk, ga, [3, 1])
+        assert_same(many[0], o.rotate(a, 3, ok), "%s hoisted 3 %s" % (name, mode))
+        t = o.tensor(a, a)
+        assert_same(g.relinearize(gk, to_gpu(g, t)), o.relinearize(t, ok), "%s relin %s" % (name, mode))
+        if mode == "auto":
+            rep = g.tuning_report()
+            assert "modup l%d d0" % level in rep and "untimed" not in rep.split("modup l%d d0" % level)[1].split("\n")[0]
+    finally:
+        g.set_tuning("base_convert", "auto")
 
 
 def test_error_paths(c1):
