@@ -214,7 +214,49 @@ def rotations_bench(vr, level, n_ct, reps):
     sync()
     out["per_op"] = n_ct * reps / (time.perf_counter() - t)
     out["identical"] = bool(np.array_equal(r[0].export(), r1[0].export()))
+    out["base_convert"] = convert_compare(ctx, keys, cts, level, reps)
     return out
+
+
+def mfma_instructions(log_n, level, n_ct, alpha=9, K=9):
+    """v_mfma_i32_16x16x32_i8 issued by one rotate_batch of n_ct ciphertexts
+    (ModUp of every digit, ModDown of both halves)."""
+    n16 = (1 << log_n) // 16
+    nq, nxt = level + 1, level + 1 + K
+
+    def conv(n_in, n_out, polys):
+        return polys * n16 * ((n_out + 3) // 4) * 4 * ((n_in + 1 + 3) // 4)
+
+    total = 0
+    for j in range((nq + alpha - 1) // alpha):
+        n_in = min(alpha, nq - j * alpha)
+        total += conv(n_in, nxt - n_in, n_ct)
+    return total + conv(K, nq, 2 * n_ct)
+
+
+def convert_compare(ctx, keys, cts, level, reps):
+    """Base-conversion device time per rotation with each kernel forced."""
+    res = {}
+    for mode in ("alu", "mfma"):
+        ctx.set_tuning("base_convert", mode)
+        ctx.rotate_batch(keys, cts, 1)
+        sync()
+        ctx.profile_start("base_convert", 1 << 14)
+        for _ in range(reps):
+            ctx.rotate_batch(keys, cts, 1)
+        ms, launches, _, _ = ctx.profile_stop()
+        res[mode + "_us_per_rotation"] = round(ms * 1e3 / (reps * len(cts)), 2)
+        if mode == "mfma":
+            ops = mfma_instructions(16, level, len(cts)) * reps * 16 * 16 * 32 * 2
+            tops = ops / (ms / 1e3) / 1e12
+            res["mfma_int8_tops"] = round(tops, 1)
+            res["mfma_util_of_5000_tops"] = round(tops / 5000.0, 4)
+    ctx.set_tuning("base_convert", "auto")
+    ctx.rotate_batch(keys, cts, 1)
+    sync()
+    res["autotuned"] = sorted(set(line.split(": ")[1] for line in ctx.tuning_report().splitlines()
+                                  if ": " in line))
+    return res
 
 
 def cpu_baseline(level):

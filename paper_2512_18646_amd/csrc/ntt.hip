@@ -22,6 +22,17 @@
 // stride-16 group reads of the last round do not collide on banks.  Shoup
 // products with lazy reduction keep forward values in [0, 4q) and inverse
 // values in [0, 2q) (Harvey 2014); the last pass stores [0, q).
+//
+// Moduli below 2^51 take an FP64 path instead (one branch per workgroup, as
+// a workgroup holds one limb): values are integers held exactly in doubles in
+// balanced form, a product y w mod q is p = y w, e = fma(y, w, -p) (the exact
+// low part), t = rint(p / q), r = fma(-t, q, p) + e -- six FP64 operations,
+// all exact while |values| < 2^53 -- and the butterflies add and subtract
+// without any correction.  A balanced reduction x - q rint(x / q) after every
+// four forward stages (two when q >= 2^50, and two for the inverse, whose sums
+// double) keeps |values| below 2^52.7 (bounds in the design notes).  Between
+// the passes of a two-pass transform the balanced doubles themselves go
+// through memory; the last pass stores the canonical uint64.
 #include "vr_core.h"
 
 namespace vr {
@@ -30,6 +41,7 @@ struct NttPass {
     LimbSet ls;
     const ModQ* mq;
     const u64* tw;      // [nmod][N][2]
+    const double* twf;  // [nmod][N] balanced
     u32 log_n, L;
     u32 s0, log_g, log_c;
     u32 first, last;
@@ -126,6 +138,105 @@ __device__ __forceinline__ void ntt_round(u64* lds, const u64* tw, u64 q, u32 lo
     }
 }
 
+#pragma clang fp contract(off)
+// y w mod q as an exact integer in about (-1.4 q, 1.4 q), for |y w| < 2^104
+__device__ __forceinline__ double fmulmod(double y, double w, double q, double qinv)
+{
+    const double p = y * w;
+    const double e = __fma_rn(y, w, -p);
+    const double t = rint(p * qinv);
+    return __fma_rn(-t, q, p) + e;
+}
+
+// x - q rint(x / q): balanced representative, |result| <= q/2 + 1
+__device__ __forceinline__ double fbal(double x, double q, double qinv)
+{
+    return __fma_rn(-rint(x * qinv), q, x);
+}
+#pragma clang fp contract(on)
+
+template <int R, bool INV, int THREADS>
+__device__ __forceinline__ void ntt_round_fp(double* lds, const double* tw, double q, double qinv,
+                                             bool every2, u32 log_g, u32 log_c, u32 sg0,
+                                             u32 s_pass, u32 g0, u32 lo_bits)
+{
+    constexpr int E = 1 << R;
+    const u32 G = 1u << log_g;
+    const u32 low_bits = log_g - sg0 - R;
+    const u32 ngroups = (G >> R) << log_c;
+    for (u32 f = threadIdx.x; f < ngroups; f += THREADS) {
+        const u32 c = f >> (log_g - R);
+        const u32 gid = f & ((G >> R) - 1);
+        const u32 hi = gid >> low_bits;
+        const u32 lo = gid & ((1u << low_bits) - 1);
+        const u32 base = c * G + (hi << (log_g - sg0)) + lo;
+        const u32 H = (g0 + c) >> lo_bits;
+        const u32 hprefix = (H << sg0) | hi;
+        double x[E];
+#pragma unroll
+        for (int m = 0; m < E; m++) x[m] = lds[pad(base + ((u32)m << low_bits))];
+        if (!INV) {
+#pragma unroll
+            for (int k = 0; k < R; k++) {
+                const int half = 1 << (R - 1 - k);
+                const u32 tb = (1u << (s_pass + sg0 + k)) + (hprefix << k);
+#pragma unroll
+                for (int j = 0; j < (1 << k); j++) {
+                    const double w = tw[tb + j];
+#pragma unroll
+                    for (int i = 0; i < half; i++) {
+                        const int m1 = (j << (R - k)) + i, m2 = m1 + half;
+                        const double X = x[m1];
+                        const double T = fmulmod(x[m2], w, q, qinv);
+                        x[m1] = X + T;
+                        x[m2] = X - T;
+                    }
+                }
+                if (every2 && (k & 1) && k != R - 1) {
+#pragma unroll
+                    for (int m = 0; m < E; m++) x[m] = fbal(x[m], q, qinv);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int k = R - 1; k >= 0; k--) {
+                const int half = 1 << (R - 1 - k);
+                const u32 tb = (1u << (s_pass + sg0 + k)) + (hprefix << k);
+#pragma unroll
+                for (int j = 0; j < (1 << k); j++) {
+                    const double w = tw[tb + j];
+#pragma unroll
+                    for (int i = 0; i < half; i++) {
+                        const int m1 = (j << (R - k)) + i, m2 = m1 + half;
+                        const double X = x[m1], Y = x[m2];
+                        x[m1] = X + Y;
+                        x[m2] = fmulmod(X - Y, w, q, qinv);
+                    }
+                }
+                if (((R - k) & 1) == 0 && k != 0) {
+#pragma unroll
+                    for (int m = 0; m < E; m++) x[m] = fbal(x[m], q, qinv);
+                }
+            }
+        }
+#pragma unroll
+        for (int m = 0; m < E; m++) lds[pad(base + ((u32)m << low_bits))] = fbal(x[m], q, qinv);
+    }
+}
+
+template <bool INV, int THREADS>
+__device__ __forceinline__ void run_round_fp(u32 r, double* lds, const double* tw, double q,
+                                             double qinv, bool every2, u32 log_g, u32 log_c,
+                                             u32 sg0, u32 s_pass, u32 g0, u32 lo_bits)
+{
+    switch (r) {
+    case 4: ntt_round_fp<4, INV, THREADS>(lds, tw, q, qinv, every2, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
+    case 3: ntt_round_fp<3, INV, THREADS>(lds, tw, q, qinv, every2, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
+    case 2: ntt_round_fp<2, INV, THREADS>(lds, tw, q, qinv, every2, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
+    default: ntt_round_fp<1, INV, THREADS>(lds, tw, q, qinv, every2, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
+    }
+}
+
 template <bool INV, int THREADS>
 __device__ __forceinline__ void run_round(u32 r, u64* lds, const u64* tw, u64 q, u32 log_g,
                                           u32 log_c, u32 sg0, u32 s_pass, u32 g0, u32 lo_bits)
@@ -158,7 +269,8 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
     if (!p.first) src = dst;
     const ModQ m = p.mq[mod];
     const u64 q = m.q, q2 = 2 * m.q;
-    const u64* tw = p.tw + (size_t)mod * n * 2;
+    const bool fp = q < (1ull << 51);   // uniform over the workgroup (one limb)
+    const double qd = (double)q, qinv = 1.0 / qd;
 
     // coalesced load: consecutive threads take consecutive addresses
     const bool strided = lo_bits > 0;
@@ -169,26 +281,55 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
         u32 g = g0 + c;
         u32 H = g >> lo_bits, Lo = g & ((1u << lo_bits) - 1);
         size_t idx = ((size_t)H << (p.log_n - p.s0)) + ((size_t)v << lo_bits) + Lo;
-        lds[pad(c * G + v)] = src[idx];
+        u64 x = src[idx];
+        // first pass of the FP64 path: canonical uint64 -> balanced double;
+        // later passes read the balanced doubles the previous pass stored
+        if (fp && p.first) x = __double_as_longlong(x > q / 2 ? -(double)(q - x) : (double)x);
+        lds[pad(c * G + v)] = x;
     }
     __syncthreads();
 
-    if (!INV) {
-        for (u32 sg0 = 0; sg0 < p.log_g;) {
-            u32 rr = p.log_g - sg0 < 4 ? p.log_g - sg0 : 4;
-            run_round<false, THREADS>(rr, lds, tw, q, p.log_g, p.log_c, sg0, p.s0, g0, lo_bits);
-            sg0 += rr;
-            __syncthreads();
+    if (fp) {
+        double* ldf = (double*)lds;
+        const double* twf = p.twf + (size_t)mod * n;
+        const bool every2 = q >= (1ull << 50);
+        if (!INV) {
+            for (u32 sg0 = 0; sg0 < p.log_g;) {
+                u32 rr = p.log_g - sg0 < 4 ? p.log_g - sg0 : 4;
+                run_round_fp<false, THREADS>(rr, ldf, twf, qd, qinv, every2, p.log_g, p.log_c, sg0,
+                                             p.s0, g0, lo_bits);
+                sg0 += rr;
+                __syncthreads();
+            }
+        } else {
+            for (u32 top = p.log_g; top > 0;) {
+                u32 rr = top < 4 ? top : 4;
+                run_round_fp<true, THREADS>(rr, ldf, twf, qd, qinv, true, p.log_g, p.log_c, top - rr,
+                                            p.s0, g0, lo_bits);
+                top -= rr;
+                __syncthreads();
+            }
         }
     } else {
-        for (u32 top = p.log_g; top > 0;) {
-            u32 rr = top < 4 ? top : 4;
-            run_round<true, THREADS>(rr, lds, tw, q, p.log_g, p.log_c, top - rr, p.s0, g0, lo_bits);
-            top -= rr;
-            __syncthreads();
+        const u64* tw = p.tw + (size_t)mod * n * 2;
+        if (!INV) {
+            for (u32 sg0 = 0; sg0 < p.log_g;) {
+                u32 rr = p.log_g - sg0 < 4 ? p.log_g - sg0 : 4;
+                run_round<false, THREADS>(rr, lds, tw, q, p.log_g, p.log_c, sg0, p.s0, g0, lo_bits);
+                sg0 += rr;
+                __syncthreads();
+            }
+        } else {
+            for (u32 top = p.log_g; top > 0;) {
+                u32 rr = top < 4 ? top : 4;
+                run_round<true, THREADS>(rr, lds, tw, q, p.log_g, p.log_c, top - rr, p.s0, g0, lo_bits);
+                top -= rr;
+                __syncthreads();
+            }
         }
     }
 
+    const double ninv_f = m.ninv > q / 2 ? -(double)(q - m.ninv) : (double)m.ninv;
     for (u32 e = threadIdx.x; e < tile; e += THREADS) {
         u32 c, v;
         if (strided) { v = e >> p.log_c; c = e & (C - 1); }
@@ -197,7 +338,15 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
         u32 H = g >> lo_bits, Lo = g & ((1u << lo_bits) - 1);
         size_t idx = ((size_t)H << (p.log_n - p.s0)) + ((size_t)v << lo_bits) + Lo;
         u64 x = lds[pad(c * G + v)];
-        if (p.last) {
+        if (fp) {
+            if (p.last) {
+                double y = __longlong_as_double(x);
+                if (INV) y = fbal(fmulmod(y, ninv_f, qd, qinv), qd, qinv);
+                y = y < 0.0 ? y + qd : y;
+                x = (u64)y;
+                x = x >= q ? x - q : x;
+            }
+        } else if (p.last) {
             if (!INV) {
                 x = x >= q2 ? x - q2 : x;
                 x = x >= q ? x - q : x;
@@ -266,6 +415,7 @@ void run(vr_context* ctx, const LimbSet& ls, hipStream_t s)
     p.ls = ls;
     p.mq = ctx->d_modq;
     p.tw = INV ? ctx->d_itw : ctx->d_tw;
+    p.twf = INV ? ctx->d_itwf : ctx->d_twf;
     p.log_n = ctx->log_n;
     p.L = ctx->L;
     size_t np = passes.size();

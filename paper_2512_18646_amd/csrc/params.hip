@@ -158,6 +158,7 @@ void build_context(vr_context* ctx, const vr_params* p, int device)
     const u32 n = ctx->n, nmod = ctx->nmod();
     ctx->modq.resize(nmod);
     std::vector<u64> tw((size_t)nmod * n * 2), itw((size_t)nmod * n * 2);
+    std::vector<double> twf((size_t)nmod * n), itwf((size_t)nmod * n);
     std::vector<u64> pw(n), ipw(n);
     for (u32 m = 0; m < nmod; m++) {
         u64 q = ctx->mod[m];
@@ -193,11 +194,16 @@ void build_context(vr_context* ctx, const vr_params* p, int device)
             tw[at + 1] = shoup_companion(pw[e], q);
             itw[at] = ipw[e];
             itw[at + 1] = shoup_companion(ipw[e], q);
+            // balanced (-q/2, q/2] copies for the FP64 butterflies (exact below 2^53)
+            twf[(size_t)m * n + k] = pw[e] > q / 2 ? -(double)(q - pw[e]) : (double)pw[e];
+            itwf[(size_t)m * n + k] = ipw[e] > q / 2 ? -(double)(q - ipw[e]) : (double)ipw[e];
         }
     }
     ctx->d_modq = upload(ctx->modq);
     ctx->d_tw = upload(tw);
     ctx->d_itw = upload(itw);
+    ctx->d_twf = upload(twf);
+    ctx->d_itwf = upload(itwf);
 
     // FFT twiddles e^{-2 pi i k / 2N}, k < N, as (re, im) pairs
     std::vector<double> ft(2 * (size_t)n);
@@ -222,6 +228,8 @@ void destroy_context_tables(vr_context* ctx)
     (void)hipFree(ctx->d_modq);
     (void)hipFree(ctx->d_tw);
     (void)hipFree(ctx->d_itw);
+    (void)hipFree(ctx->d_twf);
+    (void)hipFree(ctx->d_itwf);
     (void)hipFree(ctx->d_fft_tw);
     (void)hipFree(ctx->d_gexp);
     for (auto& kv : ctx->modup_tables) (void)hipFree(kv.second.dev), (void)hipFree(kv.second.wt);

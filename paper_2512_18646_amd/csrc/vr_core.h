@@ -210,6 +210,8 @@ struct vr_context {
     vr::ModQ* d_modq = nullptr;
     vr::u64* d_tw = nullptr;          // [nmod][N][2] (psi^brev(k), Shoup companion)
     vr::u64* d_itw = nullptr;         // [nmod][N][2] (psi^-brev(k), Shoup companion)
+    double* d_twf = nullptr;          // [nmod][N] psi^brev(k) in (-q/2, q/2] (FP64 butterflies)
+    double* d_itwf = nullptr;         // [nmod][N] psi^-brev(k) likewise
     double* d_fft_tw = nullptr;       // [N] complex e^{-2 pi i k / 2N}
     int* d_gexp = nullptr;            // [S] 5^j mod 2N
     vr::u64 cdt[20];
