@@ -369,6 +369,8 @@ def main():
            "latency_ms_p50": round(percentile(lat, 50), 3), "latency_ms_p99": round(percentile(lat, 99), 3),
            "roofline": roofline}
 
+    out["autotuned"] = ctx.tuning_report().splitlines()
+
     if not args.no_graph:
         log("graph capture of the step")
         net = vr.CNN(W.channels, W.h, W.w, W.pad, K, bias, W.stride, square=True)

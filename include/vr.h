@@ -111,9 +111,16 @@ vr_status vr_context_mem_info(vr_context *ctx, size_t *reserved, size_t *in_use)
 vr_status vr_context_trim(vr_context *ctx);
 /* Kernel choices.  Knob "base_convert": "auto" (default: each base-conversion
  * table times the vector-ALU and the INT8-split MFMA kernel on its first call
- * and keeps the faster; both give identical words), "alu" or "mfma". */
+ * and keeps the faster; both give identical words), "alu" or "mfma".  Knob
+ * "ntt": "auto" (default: the first transform in each direction times the
+ * candidate pass plans -- one LDS-resident pass, or two passes with every
+ * split of log N and 8..128 groups per workgroup -- on 256 scratch limbs and
+ * keeps the fastest), "fixed" (the built-in plan) or "cand:<i>" (candidate i,
+ * for tests; VR_EINVAL at the next transform if there is none).  Tuning synchronises
+ * once; the transform is the same exact map under every plan. */
 vr_status vr_context_set_tuning(vr_context *ctx, const char *knob, const char *value);
-/* One line per base-conversion table built so far: shape and kernel chosen. */
+/* One line per base-conversion table built so far (shape, kernel chosen) and
+ * per tuned NTT direction (passes as {first stage, stages, log groups}). */
 vr_status vr_context_tuning_report(vr_context *ctx, char *buf, size_t cap);
 const char *vr_last_error(void);
 

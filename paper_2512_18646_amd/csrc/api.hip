@@ -174,9 +174,14 @@ vr_status vr_context_set_tuning(vr_context* ctx, const char* knob, const char* v
     API_BEGIN
     REQUIRE(ctx && knob && value, "null argument");
     std::string k(knob), v(value);
-    REQUIRE(k == "base_convert", "unknown tuning knob");
-    int mode = v == "auto" ? 0 : v == "alu" ? 1 : v == "mfma" ? 2 : -1;
-    REQUIRE(mode >= 0, "base_convert takes auto, alu or mfma");
+    int mode = -1;
+    if (k == "base_convert") mode = v == "auto" ? 0 : v == "alu" ? 1 : v == "mfma" ? 2 : -1;
+    else if (k == "ntt") {
+        mode = v == "auto" ? 0 : v == "fixed" ? 1 : -1;
+        if (v.compare(0, 5, "cand:") == 0) mode = 2 + std::stoi(v.substr(5));
+    }
+    else throw Error(VR_EINVAL, "unknown tuning knob");
+    REQUIRE(mode >= 0, "base_convert takes auto, alu or mfma; ntt takes auto or fixed");
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->tuning[k] = mode;
     API_END
@@ -197,6 +202,14 @@ vr_status vr_context_tuning_report(vr_context* ctx, char* buf, size_t cap)
         r += "moddown l" + std::to_string(kv.first) + " " + std::to_string(kv.second.n_in) + "->" +
              std::to_string(kv.second.n_out) + ": " +
              name(kv.second.choice ? kv.second.choice->load() : -1) + "\n";
+    for (int d = 0; d < 2; d++) {
+        if (ctx->ntt_plan[d].empty()) continue;
+        r += std::string("ntt N=2^") + std::to_string(ctx->log_n) + (d ? " inverse:" : " forward:");
+        for (auto& c : ctx->ntt_plan[d])
+            r += " {" + std::to_string(c[0]) + "," + std::to_string(c[1]) + "," + std::to_string(c[2]) +
+                 (c[3] ? ",direct" : "") + ",/" + std::to_string(c[4]) + "}";
+        r += "\n";
+    }
     REQUIRE(r.size() < cap, "report buffer too small");
     memcpy(buf, r.c_str(), r.size() + 1);
     API_END

@@ -68,12 +68,25 @@ __device__ __forceinline__ void limb_addr(const LimbSet& ls, u32 r, u32 n, u32 L
 
 __device__ __forceinline__ u32 pad(u32 i) { return i + (i >> 4); }
 
+// Where a round reads and writes.  A pass that holds the whole limb takes its
+// first round straight from global memory (element e at gsrc[e]: the groups
+// of the first forward round are strided so consecutive threads read
+// consecutive words) and writes its last round straight back in final form,
+// saving two LDS round trips and letting each wave start and finish on its
+// own instead of at a barrier.
+struct RoundIO {
+    const u64* gsrc = nullptr;   // canonical uint64 input
+    u64* gdst = nullptr;         // canonical uint64 output
+};
+
 // One round of R stages (local stages sg0 .. sg0+R-1 of the pass) over every
 // 2^R-element group of the tile.
 template <int R, bool INV, int THREADS>
-__device__ __forceinline__ void ntt_round(u64* lds, const u64* tw, u64 q, u32 log_g, u32 log_c,
-                                          u32 sg0, u32 s_pass, u32 g0, u32 lo_bits)
+__device__ __forceinline__ void ntt_round(u64* lds, const u64* tw, const ModQ& mq, u32 log_g,
+                                          u32 log_c, u32 sg0, u32 s_pass, u32 g0, u32 lo_bits,
+                                          RoundIO io)
 {
+    const u64 q = mq.q;
     constexpr int E = 1 << R;
     const u32 G = 1u << log_g;
     const u32 low_bits = log_g - sg0 - R;
@@ -91,8 +104,13 @@ __device__ __forceinline__ void ntt_round(u64* lds, const u64* tw, u64 q, u32 lo
         // 2^(s_pass + sg0 + k) + (hprefix << k)
         const ulonglong2* twp = (const ulonglong2*)tw;
         u64 x[E];
+        if (io.gsrc) {
 #pragma unroll
-        for (int m = 0; m < E; m++) x[m] = lds[pad(base + ((u32)m << low_bits))];
+            for (int m = 0; m < E; m++) x[m] = io.gsrc[base + ((u32)m << low_bits)];
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; m++) x[m] = lds[pad(base + ((u32)m << low_bits))];
+        }
         if (!INV) {
 #pragma unroll
             for (int k = 0; k < R; k++) {
@@ -133,8 +151,22 @@ __device__ __forceinline__ void ntt_round(u64* lds, const u64* tw, u64 q, u32 lo
                 }
             }
         }
+        if (io.gdst) {
 #pragma unroll
-        for (int m = 0; m < E; m++) lds[pad(base + ((u32)m << low_bits))] = x[m];
+            for (int m = 0; m < E; m++) {
+                u64 v = x[m];
+                if (!INV) {
+                    v = v >= q2 ? v - q2 : v;
+                    v = v >= q ? v - q : v;
+                } else {
+                    v = shoup(v, mq.ninv, mq.ninv_s, q);
+                }
+                io.gdst[base + ((u32)m << low_bits)] = v;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; m++) lds[pad(base + ((u32)m << low_bits))] = x[m];
+        }
     }
 }
 
@@ -158,8 +190,10 @@ __device__ __forceinline__ double fbal(double x, double q, double qinv)
 template <int R, bool INV, int THREADS>
 __device__ __forceinline__ void ntt_round_fp(double* lds, const double* tw, double q, double qinv,
                                              bool every2, u32 log_g, u32 log_c, u32 sg0,
-                                             u32 s_pass, u32 g0, u32 lo_bits)
+                                             u32 s_pass, u32 g0, u32 lo_bits, RoundIO io,
+                                             double ninv_f)
 {
+    const u64 qi = (u64)q;
     constexpr int E = 1 << R;
     const u32 G = 1u << log_g;
     const u32 low_bits = log_g - sg0 - R;
@@ -173,8 +207,16 @@ __device__ __forceinline__ void ntt_round_fp(double* lds, const double* tw, doub
         const u32 H = (g0 + c) >> lo_bits;
         const u32 hprefix = (H << sg0) | hi;
         double x[E];
+        if (io.gsrc) {
 #pragma unroll
-        for (int m = 0; m < E; m++) x[m] = lds[pad(base + ((u32)m << low_bits))];
+            for (int m = 0; m < E; m++) {
+                const u64 v = io.gsrc[base + ((u32)m << low_bits)];
+                x[m] = v > qi / 2 ? -(double)(qi - v) : (double)v;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; m++) x[m] = lds[pad(base + ((u32)m << low_bits))];
+        }
         if (!INV) {
 #pragma unroll
             for (int k = 0; k < R; k++) {
@@ -219,37 +261,53 @@ __device__ __forceinline__ void ntt_round_fp(double* lds, const double* tw, doub
                 }
             }
         }
+        if (io.gdst) {
 #pragma unroll
-        for (int m = 0; m < E; m++) lds[pad(base + ((u32)m << low_bits))] = fbal(x[m], q, qinv);
+            for (int m = 0; m < E; m++) {
+                double y = INV ? fbal(fmulmod(x[m], ninv_f, q, qinv), q, qinv) : fbal(x[m], q, qinv);
+                y = y < 0.0 ? y + q : y;
+                const u64 v = (u64)y;
+                io.gdst[base + ((u32)m << low_bits)] = v >= qi ? v - qi : v;
+            }
+        } else {
+#pragma unroll
+            for (int m = 0; m < E; m++) lds[pad(base + ((u32)m << low_bits))] = fbal(x[m], q, qinv);
+        }
     }
 }
 
 template <bool INV, int THREADS>
 __device__ __forceinline__ void run_round_fp(u32 r, double* lds, const double* tw, double q,
                                              double qinv, bool every2, u32 log_g, u32 log_c,
-                                             u32 sg0, u32 s_pass, u32 g0, u32 lo_bits)
+                                             u32 sg0, u32 s_pass, u32 g0, u32 lo_bits, RoundIO io,
+                                             double ninv_f)
 {
+#define VR_FP_ROUND(RR)                                                                              \
+    ntt_round_fp<RR, INV, THREADS>(lds, tw, q, qinv, every2, log_g, log_c, sg0, s_pass, g0, lo_bits, \
+                                   io, ninv_f)
     switch (r) {
-    case 4: ntt_round_fp<4, INV, THREADS>(lds, tw, q, qinv, every2, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
-    case 3: ntt_round_fp<3, INV, THREADS>(lds, tw, q, qinv, every2, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
-    case 2: ntt_round_fp<2, INV, THREADS>(lds, tw, q, qinv, every2, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
-    default: ntt_round_fp<1, INV, THREADS>(lds, tw, q, qinv, every2, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
+    case 4: VR_FP_ROUND(4); break;
+    case 3: VR_FP_ROUND(3); break;
+    case 2: VR_FP_ROUND(2); break;
+    default: VR_FP_ROUND(1); break;
     }
+#undef VR_FP_ROUND
 }
 
 template <bool INV, int THREADS>
-__device__ __forceinline__ void run_round(u32 r, u64* lds, const u64* tw, u64 q, u32 log_g,
-                                          u32 log_c, u32 sg0, u32 s_pass, u32 g0, u32 lo_bits)
+__device__ __forceinline__ void run_round(u32 r, u64* lds, const u64* tw, const ModQ& mq, u32 log_g,
+                                          u32 log_c, u32 sg0, u32 s_pass, u32 g0, u32 lo_bits,
+                                          RoundIO io)
 {
     switch (r) {
-    case 4: ntt_round<4, INV, THREADS>(lds, tw, q, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
-    case 3: ntt_round<3, INV, THREADS>(lds, tw, q, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
-    case 2: ntt_round<2, INV, THREADS>(lds, tw, q, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
-    default: ntt_round<1, INV, THREADS>(lds, tw, q, log_g, log_c, sg0, s_pass, g0, lo_bits); break;
+    case 4: ntt_round<4, INV, THREADS>(lds, tw, mq, log_g, log_c, sg0, s_pass, g0, lo_bits, io); break;
+    case 3: ntt_round<3, INV, THREADS>(lds, tw, mq, log_g, log_c, sg0, s_pass, g0, lo_bits, io); break;
+    case 2: ntt_round<2, INV, THREADS>(lds, tw, mq, log_g, log_c, sg0, s_pass, g0, lo_bits, io); break;
+    default: ntt_round<1, INV, THREADS>(lds, tw, mq, log_g, log_c, sg0, s_pass, g0, lo_bits, io); break;
     }
 }
 
-template <int THREADS, bool INV>
+template <int THREADS, bool INV, bool DIRECT>
 __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
 {
     extern __shared__ u64 lds[];
@@ -272,22 +330,27 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
     const bool fp = q < (1ull << 51);   // uniform over the workgroup (one limb)
     const double qd = (double)q, qinv = 1.0 / qd;
 
-    // coalesced load: consecutive threads take consecutive addresses
+    // a pass over the whole limb reads and writes global memory in its first
+    // and last round; other passes stage the tile through LDS with coalesced loads
+    const bool direct = DIRECT;   // launched only for a single pass over the whole limb
     const bool strided = lo_bits > 0;
-    for (u32 e = threadIdx.x; e < tile; e += THREADS) {
-        u32 c, v;
-        if (strided) { v = e >> p.log_c; c = e & (C - 1); }
-        else { c = e >> p.log_g; v = e & (G - 1); }
-        u32 g = g0 + c;
-        u32 H = g >> lo_bits, Lo = g & ((1u << lo_bits) - 1);
-        size_t idx = ((size_t)H << (p.log_n - p.s0)) + ((size_t)v << lo_bits) + Lo;
-        u64 x = src[idx];
-        // first pass of the FP64 path: canonical uint64 -> balanced double;
-        // later passes read the balanced doubles the previous pass stored
-        if (fp && p.first) x = __double_as_longlong(x > q / 2 ? -(double)(q - x) : (double)x);
-        lds[pad(c * G + v)] = x;
+    if (!direct) {
+        for (u32 e = threadIdx.x; e < tile; e += THREADS) {
+            u32 c, v;
+            if (strided) { v = e >> p.log_c; c = e & (C - 1); }
+            else { c = e >> p.log_g; v = e & (G - 1); }
+            u32 g = g0 + c;
+            u32 H = g >> lo_bits, Lo = g & ((1u << lo_bits) - 1);
+            size_t idx = ((size_t)H << (p.log_n - p.s0)) + ((size_t)v << lo_bits) + Lo;
+            u64 x = src[idx];
+            // first pass of the FP64 path: canonical uint64 -> balanced double;
+            // later passes read the balanced doubles the previous pass stored
+            if (fp && p.first) x = __double_as_longlong(x > q / 2 ? -(double)(q - x) : (double)x);
+            lds[pad(c * G + v)] = x;
+        }
+        __syncthreads();
     }
-    __syncthreads();
+    const double ninv_f = m.ninv > q / 2 ? -(double)(q - m.ninv) : (double)m.ninv;
 
     if (fp) {
         double* ldf = (double*)lds;
@@ -296,16 +359,22 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
         if (!INV) {
             for (u32 sg0 = 0; sg0 < p.log_g;) {
                 u32 rr = p.log_g - sg0 < 4 ? p.log_g - sg0 : 4;
+                RoundIO io;
+                if (direct && sg0 == 0) io.gsrc = src;
+                if (direct && sg0 + rr == p.log_g) io.gdst = dst;
                 run_round_fp<false, THREADS>(rr, ldf, twf, qd, qinv, every2, p.log_g, p.log_c, sg0,
-                                             p.s0, g0, lo_bits);
+                                             p.s0, g0, lo_bits, io, ninv_f);
                 sg0 += rr;
                 __syncthreads();
             }
         } else {
             for (u32 top = p.log_g; top > 0;) {
                 u32 rr = top < 4 ? top : 4;
+                RoundIO io;
+                if (direct && top == p.log_g) io.gsrc = src;
+                if (direct && top == rr) io.gdst = dst;
                 run_round_fp<true, THREADS>(rr, ldf, twf, qd, qinv, true, p.log_g, p.log_c, top - rr,
-                                            p.s0, g0, lo_bits);
+                                            p.s0, g0, lo_bits, io, ninv_f);
                 top -= rr;
                 __syncthreads();
             }
@@ -315,21 +384,28 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
         if (!INV) {
             for (u32 sg0 = 0; sg0 < p.log_g;) {
                 u32 rr = p.log_g - sg0 < 4 ? p.log_g - sg0 : 4;
-                run_round<false, THREADS>(rr, lds, tw, q, p.log_g, p.log_c, sg0, p.s0, g0, lo_bits);
+                RoundIO io;
+                if (direct && sg0 == 0) io.gsrc = src;
+                if (direct && sg0 + rr == p.log_g) io.gdst = dst;
+                run_round<false, THREADS>(rr, lds, tw, m, p.log_g, p.log_c, sg0, p.s0, g0, lo_bits, io);
                 sg0 += rr;
                 __syncthreads();
             }
         } else {
             for (u32 top = p.log_g; top > 0;) {
                 u32 rr = top < 4 ? top : 4;
-                run_round<true, THREADS>(rr, lds, tw, q, p.log_g, p.log_c, top - rr, p.s0, g0, lo_bits);
+                RoundIO io;
+                if (direct && top == p.log_g) io.gsrc = src;
+                if (direct && top == rr) io.gdst = dst;
+                run_round<true, THREADS>(rr, lds, tw, m, p.log_g, p.log_c, top - rr, p.s0, g0, lo_bits,
+                                         io);
                 top -= rr;
                 __syncthreads();
             }
         }
     }
+    if (direct) return;
 
-    const double ninv_f = m.ninv > q / 2 ? -(double)(q - m.ninv) : (double)m.ninv;
     for (u32 e = threadIdx.x; e < tile; e += THREADS) {
         u32 c, v;
         if (strided) { v = e >> p.log_c; c = e & (C - 1); }
@@ -362,55 +438,80 @@ namespace {
 
 struct PassCfg {
     u32 s0, log_g, log_c;
+    u32 direct = 0;    // whole-limb pass with global first/last rounds
+    u32 div = 16;      // tile words per thread
 };
 
-std::vector<PassCfg> plan(u32 log_n)
+std::vector<PassCfg> default_plan(u32 log_n)
 {
     if (log_n <= 14) return {{0, log_n, 0}};
     if (log_n == 15) return {{0, 7, 5}, {7, 8, 4}};
     return {{0, 8, 4}, {8, 8, 4}};   // 2^16
 }
 
+// Plans the autotuner times: the single LDS-resident pass where the limb
+// fits, and two-pass splits a + b = log N with 2^(3..7) groups per workgroup
+// (tiles of 2^10 .. 2^14 words).
+std::vector<std::vector<PassCfg>> candidates(u32 log_n)
+{
+    std::vector<std::vector<PassCfg>> out;
+    if (log_n <= 14) {
+        out.push_back({{0, log_n, 0}});
+        if (log_n >= 10) {
+            if (log_n <= 13) out.push_back({{0, log_n, 0, 1, 16}});
+            out.push_back({{0, log_n, 0, 1, 32}});
+        }
+    }
+    if (log_n < 10) return out;
+    for (u32 a = log_n / 2 - 1; a <= (log_n + 1) / 2 + 1; a++) {
+        const u32 b = log_n - a;
+        for (u32 c = 3; c <= 7; c++) {
+            const u32 c1 = c, c2 = c;
+            if (a + c1 < 10 || a + c1 > 14 || b + c2 < 10 || b + c2 > 14) continue;
+            if (c1 > log_n - a || c2 > log_n - b) continue;
+            out.push_back({{0, a, c1}, {a, b, c2}});
+        }
+    }
+    return out;
+}
+
+template <int T, bool INV, bool DIRECT>
+void launch_kernel(const NttPass& p, u32 blocks, size_t shmem, hipStream_t s)
+{
+    static std::once_flag attr;
+    std::call_once(attr, [] {
+        (void)hipFuncSetAttribute((const void*)k_ntt_pass<T, INV, DIRECT>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+    });
+    hipLaunchKernelGGL((k_ntt_pass<T, INV, DIRECT>), dim3(blocks), dim3(T), shmem, s, p);
+}
+
 template <bool INV>
-void launch_pass(const NttPass& p, u32 n_limbs, hipStream_t s)
+void launch_pass(const NttPass& p, const PassCfg& c, u32 n_limbs, hipStream_t s)
 {
     u32 tile = 1u << (p.log_g + p.log_c);
-    u32 threads = tile / 16;
+    u32 threads = tile / c.div;
     if (threads < 64) threads = 64;
-    if (threads > 1024) threads = 1024;
+    if (threads > 1024) throw Error(VR_EINVAL, "ntt: tile too large");
+    const bool direct = c.direct && p.log_c == 0 && p.log_g == p.log_n;
+    if (direct && threads > 512) throw Error(VR_EINVAL, "ntt: whole-limb pass needs <= 512 threads");
     u32 blocks = n_limbs * ((1u << (p.log_n - p.log_g - p.log_c)));
     size_t shmem = (size_t)(tile + tile / 16) * sizeof(u64);
     switch (threads) {
-#define VR_NTT_CASE(T)                                                                          \
-    case T: {                                                                                   \
-        static bool attr = false;                                                               \
-        if (!attr) {                                                                            \
-            VR_HIP(hipFuncSetAttribute((const void*)k_ntt_pass<T, INV>,                         \
-                                       hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024)); \
-            attr = true;                                                                        \
-        }                                                                                       \
-        hipLaunchKernelGGL((k_ntt_pass<T, INV>), dim3(blocks), dim3(T), shmem, s, p);           \
-        break;                                                                                  \
-    }
-        VR_NTT_CASE(64)
-        VR_NTT_CASE(128)
-        VR_NTT_CASE(256)
-        VR_NTT_CASE(512)
-        VR_NTT_CASE(1024)
-#undef VR_NTT_CASE
-    default:
-        throw Error(VR_EINVAL, "ntt: unsupported tile");
+    case 64: direct ? launch_kernel<64, INV, true>(p, blocks, shmem, s) : launch_kernel<64, INV, false>(p, blocks, shmem, s); break;
+    case 128: direct ? launch_kernel<128, INV, true>(p, blocks, shmem, s) : launch_kernel<128, INV, false>(p, blocks, shmem, s); break;
+    case 256: direct ? launch_kernel<256, INV, true>(p, blocks, shmem, s) : launch_kernel<256, INV, false>(p, blocks, shmem, s); break;
+    case 512: direct ? launch_kernel<512, INV, true>(p, blocks, shmem, s) : launch_kernel<512, INV, false>(p, blocks, shmem, s); break;
+    case 1024: launch_kernel<1024, INV, false>(p, blocks, shmem, s); break;
+    default: throw Error(VR_EINVAL, "ntt: unsupported tile");
     }
     VR_CHECK_LAUNCH();
 }
 
 template <bool INV>
-void run(vr_context* ctx, const LimbSet& ls, hipStream_t s)
+void run_plan(vr_context* ctx, const LimbSet& ls, const std::vector<PassCfg>& passes, hipStream_t s)
 {
     u32 n_limbs = ls.per_poly * ls.n_polys;
-    if (n_limbs == 0) return;
-    ProfScope prof(ctx, kProfNtt, s, n_limbs);
-    auto passes = plan(ctx->log_n);
     NttPass p;
     p.ls = ls;
     p.mq = ctx->d_modq;
@@ -427,8 +528,79 @@ void run(vr_context* ctx, const LimbSet& ls, hipStream_t s)
         p.log_c = c.log_c;
         p.first = (i == 0);
         p.last = (i == np - 1);
-        launch_pass<INV>(p, n_limbs, s);
+        launch_pass<INV>(p, c, n_limbs, s);
     }
+}
+
+// Times every candidate plan on 256 scratch limbs of the Q chain (three runs
+// each after a warm-up) and keeps the fastest.
+template <bool INV>
+std::vector<PassCfg> tune(vr_context* ctx, hipStream_t s)
+{
+    auto cands = candidates(ctx->log_n);
+    if (cands.size() < 2) return cands.empty() ? default_plan(ctx->log_n) : cands[0];
+    const u32 per = ctx->L + 1, polys = (256 + per - 1) / per;
+    const size_t words = (size_t)per * polys * ctx->n;
+    void* buf = ctx->arena->alloc(words * sizeof(u64), s);
+    if (!buf) return default_plan(ctx->log_n);
+    VR_HIP(hipMemsetAsync(buf, 0, words * sizeof(u64), s));
+    LimbSet ls = poly_limbs((u64*)buf, (u64*)buf, polys, per, (u64)per * ctx->n, (int)ctx->L);
+    hipEvent_t a, b;
+    VR_HIP(hipEventCreate(&a));
+    VR_HIP(hipEventCreate(&b));
+    float best = 1e30f;
+    size_t pick = 0;
+    for (size_t i = 0; i < cands.size(); i++) {
+        run_plan<INV>(ctx, ls, cands[i], s);
+        VR_HIP(hipEventRecord(a, s));
+        for (int r = 0; r < 3; r++) run_plan<INV>(ctx, ls, cands[i], s);
+        VR_HIP(hipEventRecord(b, s));
+        VR_HIP(hipEventSynchronize(b));
+        float ms = 0;
+        VR_HIP(hipEventElapsedTime(&ms, a, b));
+        if (ms < best) best = ms, pick = i;
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    ctx->arena->release(buf, s);
+    return cands[pick];
+}
+
+template <bool INV>
+std::vector<PassCfg> plan_for(vr_context* ctx, hipStream_t s)
+{
+    int mode = 0;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->tuning.find("ntt");
+        if (it != ctx->tuning.end()) mode = it->second;
+        if (mode == 0 && !ctx->ntt_plan[INV].empty()) {
+            std::vector<PassCfg> p;
+            for (auto& c : ctx->ntt_plan[INV]) p.push_back({c[0], c[1], c[2], c[3], c[4]});
+            return p;
+        }
+    }
+    if (mode >= 2) {
+        auto cands = candidates(ctx->log_n);
+        if ((size_t)(mode - 2) >= cands.size()) throw Error(VR_EINVAL, "ntt: no such candidate plan");
+        return cands[mode - 2];
+    }
+    if (mode == 1 || g_capture) return default_plan(ctx->log_n);
+    std::vector<PassCfg> p = tune<INV>(ctx, s);
+    std::lock_guard<std::mutex> g(ctx->mu);
+    ctx->ntt_plan[INV].clear();
+    for (auto& c : p) ctx->ntt_plan[INV].push_back({c.s0, c.log_g, c.log_c, c.direct, c.div});
+    return p;
+}
+
+template <bool INV>
+void run(vr_context* ctx, const LimbSet& ls, hipStream_t s)
+{
+    u32 n_limbs = ls.per_poly * ls.n_polys;
+    if (n_limbs == 0) return;
+    std::vector<PassCfg> passes = plan_for<INV>(ctx, s);
+    ProfScope prof(ctx, kProfNtt, s, n_limbs);
+    run_plan<INV>(ctx, ls, passes, s);
 }
 
 }  // namespace

@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstddef>
+#include <array>
 #include <atomic>
 #include <cstdint>
 #include <map>
@@ -220,8 +221,12 @@ struct vr_context {
     // device-resident constants of layer calls (weights, term lists), keyed by
     // the call's shape and weight bytes, so repeated calls upload nothing
     std::map<std::string, std::shared_ptr<void>> plans;
-    // kernel choices: "base_convert" = 0 autotune, 1 vector ALU, 2 MFMA
+    // kernel choices: "base_convert" = 0 autotune, 1 vector ALU, 2 MFMA;
+    // "ntt" = 0 autotune, 1 the fixed default pass plan
     std::map<std::string, int> tuning;
+    // NTT pass plans picked by the autotuner, per direction, per pass:
+    // {first stage, stages, log groups per workgroup, whole-limb direct, words per thread}
+    std::vector<std::array<vr::u32, 5>> ntt_plan[2];
     std::mutex mu;
     hipStream_t stream = nullptr;     // used when a call passes stream = NULL
     std::shared_ptr<vr::DeviceArena> arena;

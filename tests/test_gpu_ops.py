@@ -22,13 +22,35 @@ def test_moduli_match_oracle():
 
 @pytest.mark.parametrize("log_n", [6, 13, 14, 15, 16])
 def test_ntt_matches_oracle(log_n):
-    import torch
     p = Params(log_n, [60, 50, 40], [51], 1, 30.0, allow_insecure=True)
-    o = OracleContext(p)
-    g = gpu_ctx(p)
+    check_ntt(OracleContext(p), gpu_ctx(p), log_n)
+
+
+@pytest.mark.parametrize("log_n", [13, 14, 15, 16])
+def test_ntt_every_candidate_plan(log_n):
+    """Each pass plan the autotuner may pick gives the exact transform (both
+    the FP64 path, 40/50/51-bit moduli, and the integer path, 60-bit)."""
+    from paper_2512_18646_amd import vr
+    p = Params(log_n, [60, 50, 40], [51], 1, 30.0, allow_insecure=True)
+    o, g = OracleContext(p), gpu_ctx(p)
+    tried = 0
+    while True:
+        g.set_tuning("ntt", "cand:%d" % tried)
+        try:
+            check_ntt(o, g, log_n, reps=1)
+        except vr.VRError as e:
+            assert e.code == vr.VR_EINVAL and tried >= 1
+            break
+        tried += 1
+    g.set_tuning("ntt", "auto")
+    check_ntt(o, g, log_n, reps=1)
+    assert "ntt N=2^%d forward" % log_n in g.tuning_report()
+
+
+def check_ntt(o, g, log_n, reps=3):
+    import torch
     mods = o.q + o.p
     rng = np.random.default_rng(log_n)
-    reps = 3
     host = np.stack([rng.integers(0, mods[i % 4], o.n, dtype=np.uint64) for i in range(4 * reps)])
     host[0, :8] = [0, 1, mods[0] - 1, 2, 3, mods[0] - 2, 0, 1]
     mi = [i % 4 for i in range(4 * reps)]
