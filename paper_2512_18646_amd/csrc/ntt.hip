@@ -28,11 +28,14 @@
 // balanced form, a product y w mod q is p = y w, e = fma(y, w, -p) (the exact
 // low part), t = rint(p / q), r = fma(-t, q, p) + e -- six FP64 operations,
 // all exact while |values| < 2^53 -- and the butterflies add and subtract
-// without any correction.  A balanced reduction x - q rint(x / q) after every
-// four forward stages (two when q >= 2^50, and two for the inverse, whose sums
-// double) keeps |values| below 2^52.7 (bounds in the design notes).  Between
-// the passes of a two-pass transform the balanced doubles themselves go
-// through memory; the last pass stores the canonical uint64.
+// without any correction.  Bounds: from |x| <= q/2, a product is off the
+// nearest multiple by at most q/2 plus the rounding of p / q (< 0.7 q while
+// |p| < 1.4 q^2) plus |e| (< q/4), so each forward stage adds < 1.44 q; four
+// stages stay below 6.2 q < 2^52.7 for q < 2^50, two stages below 3.4 q for
+// q < 2^51, and two inverse stages (whose sums double) below 2.9 q.  A
+// balanced reduction x - q rint(x / q) follows every such group of stages.
+// Between the passes of a two-pass transform the balanced doubles themselves
+// go through memory; the last pass stores the canonical uint64.
 #include "vr_core.h"
 
 namespace vr {
