@@ -348,6 +348,38 @@ vr_status vr_graph_outputs(vr_graph *g, vr_ciphertext **out, size_t cap, size_t 
 /* Synchronises the device and frees the graph (output handles stay valid). */
 void vr_graph_destroy(vr_graph *g);
 
+/* An uneven batch in one launch graph: requests of different kinds and sizes
+ * (networks as vr_cnn_desc over their own image sets, column-split products
+ * as vr_matmul).  Networks with the same description, input level and scale
+ * run as one multi-set evaluation; products at one level and scale share one
+ * hoisted ModUp and, per rotation step, one shared-key inner product and one
+ * ModDown for every request still needing that step.  Inputs are copied into
+ * the batch when added.  Every request's output limbs are identical to its
+ * own vr_cnn_forward / vr_matmul call. */
+typedef struct vr_batch vr_batch;
+vr_status vr_batch_create(vr_context *ctx, const vr_eval_keys *ek, vr_batch **out);
+/* *req_id indexes the request for vr_batch_outputs. */
+vr_status vr_batch_add_cnn(vr_batch *b, const vr_cnn_desc *desc, const vr_ciphertext *const *in,
+                           uint32_t n_sets, uint32_t *req_id);
+vr_status vr_batch_add_matmul(vr_batch *b, const vr_ciphertext *const *A,
+                              const vr_ciphertext *const *Bbar, uint32_t m, uint32_t n, uint32_t p,
+                              uint32_t *req_id);
+/* Evaluates every request eagerly on `stream` (no graph). */
+vr_status vr_batch_run(vr_batch *b, void *stream);
+/* Runs the batch once eagerly (building and tuning every cached constant),
+ * then captures it into one HIP graph that owns the intermediate and output
+ * memory.  No request can be added afterwards.  Synchronises. */
+vr_status vr_batch_capture(vr_batch *b);
+/* One replay of the captured graph on `stream`. */
+vr_status vr_batch_launch(vr_batch *b, void *stream);
+/* New handles viewing request req_id's outputs (after a run or a completed
+ * launch; the next one rewrites them): a network's n_sets * (fc_out or
+ * C_out*w_out) outputs, or a product's P' ciphertexts. */
+vr_status vr_batch_outputs(vr_batch *b, uint32_t req_id, vr_ciphertext **out, size_t cap,
+                           size_t *n_out);
+/* Synchronises the device and frees the batch (output handles stay valid). */
+void vr_batch_destroy(vr_batch *b);
+
 /* ---------------------------------------------------------------- serving
  * Continuous batching of encrypted inference requests ("Secure Inference":
  * a model owner evaluates a client's encrypted mini-batches).  A request is

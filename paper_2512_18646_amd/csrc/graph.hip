@@ -88,6 +88,76 @@ struct CaptureGuard {
     ~CaptureGuard() { g_capture = nullptr; }
 };
 
+bool same_net(const CnnDesc& a, const CnnDesc& b)
+{
+    return a.C_in == b.C_in && a.h == b.h && a.w == b.w && a.pad == b.pad && a.C_out == b.C_out &&
+           a.k == b.k && a.stride == b.stride && a.square == b.square && a.K == b.K && a.bias == b.bias &&
+           a.fc_P == b.fc_P && a.fc_stride == b.fc_stride && a.fc_out == b.fc_out &&
+           a.fc_block == b.fc_block && a.fc_bias == b.fc_bias;
+}
+
+// One request of a batch: a network over its own image sets, or a product.
+struct BatchReq {
+    bool cnn = true;
+    CnnDesc desc;
+    u32 n_sets = 1;
+    u32 m = 0, n = 0, p = 0;
+    Slab a, b;        // inputs, owned by the batch (b: the Bbar columns)
+    Slab out;
+};
+
+// Runs every request: networks with the same description and input level
+// and scale as one multi-set evaluation, products at one level and scale as
+// one merged schedule.
+void run_batch(vr_context* ctx, const vr_eval_keys* ek, std::vector<BatchReq>& reqs, hipStream_t s)
+{
+    std::vector<bool> done(reqs.size(), false);
+    for (size_t i = 0; i < reqs.size(); i++) {
+        if (done[i] || !reqs[i].cnn) continue;
+        std::vector<size_t> grp;
+        for (size_t j = i; j < reqs.size(); j++)
+            if (!done[j] && reqs[j].cnn && same_net(reqs[i].desc, reqs[j].desc) &&
+                reqs[j].a.level == reqs[i].a.level && reqs[j].a.scale == reqs[i].a.scale)
+                grp.push_back(j), done[j] = true;
+        u32 sets = 0;
+        for (size_t j : grp) sets += reqs[j].n_sets;
+        const u32 per_in = reqs[i].desc.n_in(), per_out = reqs[i].desc.n_out();
+        Slab x = reqs[i].a;
+        if (grp.size() > 1) {
+            x = new_slab(ctx, sets * per_in, 2, reqs[i].a.level, reqs[i].a.scale, s);
+            u32 at = 0;
+            for (size_t j : grp) {
+                VR_HIP(hipMemcpyAsync(x.ct(at), reqs[j].a.base, (size_t)reqs[j].a.n * x.stride * sizeof(u64),
+                                      hipMemcpyDeviceToDevice, s));
+                at += reqs[j].a.n;
+            }
+        }
+        Slab y = run_cnn(ctx, ek, reqs[i].desc, x, sets, s);
+        u32 at = 0;
+        for (size_t j : grp) {
+            reqs[j].out = y;
+            reqs[j].out.n = reqs[j].n_sets * per_out;
+            reqs[j].out.base = y.ct(at);
+            at += reqs[j].n_sets * per_out;
+        }
+    }
+    for (size_t i = 0; i < reqs.size(); i++) {
+        if (done[i]) continue;
+        std::vector<size_t> grp;
+        std::vector<MatReq> mr;
+        for (size_t j = i; j < reqs.size(); j++)
+            if (!done[j] && !reqs[j].cnn && reqs[j].a.level == reqs[i].a.level &&
+                reqs[j].a.scale * reqs[j].b.scale == reqs[i].a.scale * reqs[i].b.scale) {
+                grp.push_back(j), done[j] = true;
+                MatReq q;
+                q.A = reqs[j].a, q.B = reqs[j].b, q.m = reqs[j].m, q.n = reqs[j].n, q.p = reqs[j].p;
+                mr.push_back(q);
+            }
+        std::vector<Slab> outs = matmul_multi(ctx, ek, mr, s);
+        for (size_t g = 0; g < grp.size(); g++) reqs[grp[g]].out = outs[g];
+    }
+}
+
 }  // namespace
 
 }  // namespace vr
@@ -98,6 +168,16 @@ struct vr_graph {
     vr::CnnDesc desc;
     vr::u32 n_sets = 0;
     vr::Slab in, out;
+    std::vector<vr::BufPtr> keep;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+struct vr_batch {
+    vr_context* ctx = nullptr;
+    const vr_eval_keys* ek = nullptr;
+    std::vector<vr::BatchReq> reqs;
     std::vector<vr::BufPtr> keep;
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
@@ -260,6 +340,144 @@ vr_status vr_graph_outputs(vr_graph* g, vr_ciphertext** out, size_t cap, size_t*
 void vr_graph_destroy(vr_graph* g)
 {
     if (g) release_graph(g);
+}
+
+vr_status vr_batch_create(vr_context* ctx, const vr_eval_keys* ek, vr_batch** out)
+{
+    if (out) *out = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && out, "null argument");
+    vr_batch* b = new vr_batch;
+    b->ctx = ctx;
+    b->ek = ek;
+    *out = b;
+    API_END
+}
+
+vr_status vr_batch_add_cnn(vr_batch* b, const vr_cnn_desc* desc, const vr_ciphertext* const* in,
+                           uint32_t n_sets, uint32_t* req_id)
+{
+    if (req_id) *req_id = 0;
+    API_BEGIN
+    REQUIRE(b && desc && in && req_id, "null argument");
+    REQUIRE(!b->exec, "batch already captured");
+    REQUIRE(n_sets >= 1 && in[0], "no image set");
+    hipStream_t s = b->ctx->stream;
+    BatchReq r;
+    r.cnn = true;
+    r.desc = make_desc(b->ctx, desc, in[0]->level, s);
+    r.n_sets = n_sets;
+    const u32 n = n_sets * r.desc.n_in();
+    r.a = new_slab(b->ctx, n, 2, in[0]->level, in[0]->scale, s);
+    copy_inputs(b->ctx, r.a, in, n, s);
+    b->reqs.push_back(std::move(r));
+    *req_id = (uint32_t)b->reqs.size() - 1;
+    API_END
+}
+
+vr_status vr_batch_add_matmul(vr_batch* b, const vr_ciphertext* const* A, const vr_ciphertext* const* Bbar,
+                              uint32_t m, uint32_t n, uint32_t p, uint32_t* req_id)
+{
+    if (req_id) *req_id = 0;
+    API_BEGIN
+    REQUIRE(b && A && Bbar && req_id, "null argument");
+    REQUIRE(!b->exec, "batch already captured");
+    REQUIRE(m >= 1 && n >= 1 && p >= 1 && A[0] && Bbar[0], "empty matrix");
+    REQUIRE(m >= p, "matmul schedule needs m >= p (multiply the transposes)");
+    hipStream_t s = b->ctx->stream;
+    BatchReq r;
+    r.cnn = false;
+    r.m = m, r.n = n, r.p = p;
+    r.a = new_slab(b->ctx, n, 2, A[0]->level, A[0]->scale, s);
+    copy_inputs(b->ctx, r.a, A, n, s);
+    r.b = new_slab(b->ctx, n, 2, Bbar[0]->level, Bbar[0]->scale, s);
+    copy_inputs(b->ctx, r.b, Bbar, n, s);
+    b->reqs.push_back(std::move(r));
+    *req_id = (uint32_t)b->reqs.size() - 1;
+    API_END
+}
+
+vr_status vr_batch_run(vr_batch* b, void* stream)
+{
+    API_BEGIN
+    REQUIRE(b, "null batch");
+    REQUIRE(!b->exec, "batch captured: use vr_batch_launch");
+    run_batch(b->ctx, b->ek, b->reqs, stream ? (hipStream_t)stream : b->ctx->stream);
+    API_END
+}
+
+vr_status vr_batch_capture(vr_batch* b)
+{
+    API_BEGIN
+    REQUIRE(b, "null batch");
+    REQUIRE(!b->exec, "batch already captured");
+    REQUIRE(!b->reqs.empty(), "empty batch");
+    REQUIRE(!b->ctx->alloc_fn, "graphs need the built-in allocator");
+    REQUIRE(b->ctx->prof.cls < 0, "stop the kernel profiler before capturing a graph");
+    VR_HIP(hipStreamCreateWithFlags(&b->cap, hipStreamNonBlocking));
+    VR_HIP(hipStreamSynchronize(b->ctx->stream));
+    run_batch(b->ctx, b->ek, b->reqs, b->cap);   // eager: builds and tunes every cached constant
+    VR_HIP(hipStreamSynchronize(b->cap));
+    // release the eager outputs now: nothing allocated before the capture may
+    // be freed while it records
+    for (auto& r : b->reqs) r.out = Slab();
+    {
+        CaptureGuard guard;
+        VR_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
+        try {
+            run_batch(b->ctx, b->ek, b->reqs, b->cap);
+        } catch (...) {
+            hipGraph_t partial = nullptr;
+            (void)hipStreamEndCapture(b->cap, &partial);
+            if (partial) (void)hipGraphDestroy(partial);
+            b->keep = std::move(guard.keep.bufs);
+            throw;
+        }
+        VR_HIP(hipStreamEndCapture(b->cap, &b->graph));
+        b->keep = std::move(guard.keep.bufs);
+    }
+    VR_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
+    API_END
+}
+
+vr_status vr_batch_launch(vr_batch* b, void* stream)
+{
+    API_BEGIN
+    REQUIRE(b && b->exec, "batch not captured");
+    VR_HIP(hipGraphLaunch(b->exec, stream ? (hipStream_t)stream : b->ctx->stream));
+    API_END
+}
+
+vr_status vr_batch_outputs(vr_batch* b, uint32_t req_id, vr_ciphertext** out, size_t cap, size_t* n_out)
+{
+    if (n_out) *n_out = 0;
+    API_BEGIN
+    REQUIRE(b && out && n_out, "null argument");
+    REQUIRE(req_id < b->reqs.size(), "unknown request");
+    const Slab& o = b->reqs[req_id].out;
+    REQUIRE(o.base, "batch not run yet");
+    REQUIRE(cap >= o.n, "output capacity too small");
+    to_handles(b->ctx, o, out);
+    *n_out = o.n;
+    API_END
+}
+
+void vr_batch_destroy(vr_batch* b)
+{
+    if (!b) return;
+    (void)hipDeviceSynchronize();
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    for (auto& k : b->keep) k->stream = b->ctx->stream;
+    for (auto& r : b->reqs) {
+        if (r.out.buf) r.out.buf->stream = b->ctx->stream;
+        if (r.a.buf) r.a.buf->stream = b->ctx->stream;
+        if (r.b.buf) r.b.buf->stream = b->ctx->stream;
+    }
+    b->keep.clear();
+    b->reqs.clear();
+    if (b->cap) (void)hipStreamDestroy(b->cap);
+    delete b;
 }
 
 }  // extern "C"

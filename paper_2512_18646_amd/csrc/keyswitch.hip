@@ -498,22 +498,27 @@ void keyswitch_modup_batch(vr_context* ctx, const u64* d, u64 d_stride, u32 n_ct
     LimbSet ls = poly_limbs(const_cast<u64*>(d), coef, n_ct, k.nq, d_stride, (int)level);
     ls.out_dense = 1;
     ntt_inverse(ctx, ls, s);
+    // one-limb digits: the conversion is a centred reduction, done by the
+    // NTT as it loads each limb (below); wider digits convert first
+    const bool fused = ctx->alpha == 1;
     for (u32 j = 0; j < k.beta; j++) {
         u32 lo = j * ctx->alpha, hi = std::min((j + 1) * ctx->alpha, k.nq);
-        const ConvTable& tb = modup_table(ctx, level, j);
-        ConvArgs a;
-        a.in = coef + (size_t)lo * n;
-        a.in_stride = (u64)k.nq * n;
-        a.out = X + (size_t)j * k.next * n;
-        a.out_stride = xs;
-        a.skip_at = lo;
-        a.skip_len = hi - lo;
-        a.tab = tb.dev;
-        a.n_in = tb.n_in;
-        a.n_out = tb.n_out;
-        a.log_n = ctx->log_n;
-        a.mq = ctx->d_modq;
-        launch_convert(ctx, a, tb, n_ct, s);
+        if (!fused) {
+            const ConvTable& tb = modup_table(ctx, level, j);
+            ConvArgs a;
+            a.in = coef + (size_t)lo * n;
+            a.in_stride = (u64)k.nq * n;
+            a.out = X + (size_t)j * k.next * n;
+            a.out_stride = xs;
+            a.skip_at = lo;
+            a.skip_len = hi - lo;
+            a.tab = tb.dev;
+            a.n_in = tb.n_in;
+            a.n_out = tb.n_out;
+            a.log_n = ctx->log_n;
+            a.mq = ctx->d_modq;
+            launch_convert(ctx, a, tb, n_ct, s);
+        }
         // the digit's own limbs are d itself (already in the evaluation domain)
         launch_copy_rows(X + ((size_t)j * k.next + lo) * n, xs, d + (size_t)lo * n, d_stride,
                          (u64)(hi - lo) * n, n_ct, s);
@@ -526,6 +531,12 @@ void keyswitch_modup_batch(vr_context* ctx, const u64* d, u64 d_stride, u32 n_ct
     t.alpha = ctx->alpha;
     t.beta = k.beta;
     t.nq = k.nq;
+    if (fused) {
+        t.cv_src = coef;             // digit j of ciphertext c: coef + c * nq * N + j * N
+        t.cv_ct_stride = (u64)k.nq * n;
+        t.cv_beta = k.beta;
+        t.cv_mod0 = 0;
+    }
     ntt_forward(ctx, t, s);
     u32 last = k.nq - (k.beta - 1) * ctx->alpha;
     if (last < ctx->alpha) {
@@ -592,21 +603,31 @@ void keyswitch_moddown_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u3
     ls.slot0 = k.nq;
     ls.out_dense = 1;
     ntt_inverse(ctx, ls, s);
-    const ConvTable& tb = moddown_table(ctx, level);
-    ConvArgs a;
-    a.in = pcoef;
-    a.in_stride = (u64)K * n;
-    a.out = Y;
-    a.out_stride = (u64)k.nq * n;
-    a.skip_at = 0xffffffffu;
-    a.skip_len = 0;
-    a.tab = tb.dev;
-    a.n_in = tb.n_in;
-    a.n_out = tb.n_out;
-    a.log_n = ctx->log_n;
-    a.mq = ctx->d_modq;
-    launch_convert(ctx, a, tb, n_ct * 2, s);
-    ntt_forward(ctx, poly_limbs(Y, Y, n_ct * 2, k.nq, (u64)k.nq * n, (int)level), s);
+    LimbSet ly = poly_limbs(Y, Y, n_ct * 2, k.nq, (u64)k.nq * n, (int)level);
+    if (K == 1) {
+        // one special prime: the conversion is a centred reduction done by the
+        // NTT as it loads each limb
+        ly.cv_src = pcoef;
+        ly.cv_ct_stride = n;
+        ly.cv_beta = 1;
+        ly.cv_mod0 = ctx->L + 1;
+    } else {
+        const ConvTable& tb = moddown_table(ctx, level);
+        ConvArgs a;
+        a.in = pcoef;
+        a.in_stride = (u64)K * n;
+        a.out = Y;
+        a.out_stride = (u64)k.nq * n;
+        a.skip_at = 0xffffffffu;
+        a.skip_len = 0;
+        a.tab = tb.dev;
+        a.n_in = tb.n_in;
+        a.n_out = tb.n_out;
+        a.log_n = ctx->log_n;
+        a.mq = ctx->d_modq;
+        launch_convert(ctx, a, tb, n_ct * 2, s);
+    }
+    ntt_forward(ctx, ly, s);
     dim3 grid((n + kThreads - 1) / kThreads, n_ct * k.nq);
     ProfScope prof(ctx, kProfModDown, s, (u64)n_ct * 2 * k.nq);
     hipLaunchKernelGGL(k_moddown_finish, grid, dim3(kThreads), 0, s, U, u_stride, Y, k.nq, k.next,

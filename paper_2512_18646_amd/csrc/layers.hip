@@ -67,7 +67,10 @@ Slab gather(vr_context* ctx, const vr_ciphertext* const* cts, u32 n, hipStream_t
     sl.scale = c0->scale;
     sl.stride = (u64)c0->ncomp * (c0->level + 1) * ctx->n;
     bool contiguous = true;
-    for (u32 i = 1; i < n && contiguous; i++) contiguous = cts[i]->data == c0->data + (size_t)i * sl.stride;
+    // in place only within one allocation: separate blocks can sit back to
+    // back in the address space, and copies must not span allocations
+    for (u32 i = 1; i < n && contiguous; i++)
+        contiguous = cts[i]->buf == c0->buf && cts[i]->data == c0->data + (size_t)i * sl.stride;
     if (contiguous) {
         sl.buf = c0->buf;
         sl.base = c0->data;
@@ -94,29 +97,35 @@ struct Term {
     u32 w_idx;    // weight row
 };
 
-// For each of n_sets independent image sets s and each output o:
-// out[s][o] = sum_{terms of o} w * in (+ bias on component 0), 2 components.
-// Term input index i = u * n_x + j: for u = 0 ciphertext s * n_x + j of slab x,
-// for u >= 1 ciphertext (u - 1) * n_x * n_sets + s * n_x + j of slab r (the
-// rotations by u of every column of every set), all with stride `stride`.
+// For each of n_sets independent image sets s and each output column j':
+// out[s][f][j'] = sum_{terms of j'} w_f * in (+ bias on component 0) for every
+// filter f, 2 components.  The filters of one column read the same inputs, so
+// a block keeps all filters' sums in registers and reads each input word
+// once.  Term input index i = u * n_x + j: for u = 0 ciphertext s * n_x + j
+// of slab x, for u >= 1 ciphertext (u - 1) * n_x * n_sets + s * n_x + j of
+// slab r (the rotations by u of every column of every set), all with stride
+// `stride`.  Term weight row for filter f: w_row + f * w_fstride.
 //
-// Launch order: the logical block id runs over outputs fastest, then sets,
-// then rows, then 256-coefficient chunks, so the outputs that read the same
-// input chunk (neighbouring columns, every filter) run back to back; the
-// logical ids are dealt to the 8 XCDs in contiguous ranges (hardware hands
-// block b to XCD b mod 8), so those blocks share one L2.
+// Launch order: the logical block id runs over output columns fastest, then
+// sets, then rows, then 256-coefficient chunks, so the columns that read the
+// same input chunk run back to back; the logical ids are dealt to the 8 XCDs
+// in contiguous ranges (hardware hands block b to XCD b mod 8), so those
+// blocks share one L2.
+constexpr int kMaxFilters = 8;
+
 __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, const u64* x,
                                                       const u64* r, u32 n_x, u32 n_sets, u64 stride,
                                                       const Term* terms, const u32* term_off,
-                                                      const u64* w, const u64* ws, const u64* bias,
-                                                      u32 nl, u32 log_n, const ModQ* mq, u32 n_out,
+                                                      const u64* w, const u64* ws, u32 w_fstride,
+                                                      const u64* bias, u32 nl, u32 log_n,
+                                                      const ModQ* mq, u32 wo, u32 n_filters,
                                                       u32 total, u32 per_xcd)
 {
     const u32 logical = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
     if (logical >= total) return;
     const u32 n = 1u << log_n;
-    const u32 o = logical % n_out;
-    u32 rest = logical / n_out;
+    const u32 jo = logical % wo;
+    u32 rest = logical / wo;
     const u32 set = rest % n_sets;
     rest /= n_sets;
     const u32 row = rest % (2 * nl);   // component * nl + limb
@@ -125,21 +134,40 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
     if (t >= n) return;
     const u32 l = row % nl;
     const u64 q = mq[l].q, q2 = 2 * q;
-    u64 acc = 0;
-    const u32 a = term_off[o], b = term_off[o + 1];
-    for (u32 k = a; k < b; k++) {
-        Term tm = terms[k];
-        const u32 u = tm.in_idx / n_x, j = tm.in_idx - u * n_x;
-        const u64* src = u == 0 ? x + (size_t)(set * n_x + j) * stride
-                                : r + ((size_t)(u - 1) * n_x * n_sets + set * n_x + j) * stride;
-        u64 xv = src[(size_t)row * n + t];
-        acc += shoup_lazy(xv, w[(size_t)tm.w_idx * nl + l], ws[(size_t)tm.w_idx * nl + l], q);
-        acc = acc >= q2 ? acc - q2 : acc;
+    const u32 a = term_off[jo], b = term_off[jo + 1];
+    const u32 n_out = n_filters * wo;
+    for (u32 f0 = 0; f0 < n_filters; f0 += kMaxFilters) {
+        const u32 nf = min((u32)kMaxFilters, n_filters - f0);
+        u64 acc[kMaxFilters];
+#pragma unroll
+        for (int f = 0; f < kMaxFilters; f++) acc[f] = 0;
+        for (u32 k = a; k < b; k++) {
+            const Term tm = terms[k];
+            const u32 u = tm.in_idx / n_x, j = tm.in_idx - u * n_x;
+            const u64* src = u == 0 ? x + (size_t)(set * n_x + j) * stride
+                                    : r + ((size_t)(u - 1) * n_x * n_sets + set * n_x + j) * stride;
+            const u64 xv = src[(size_t)row * n + t];
+#pragma unroll
+            for (int f = 0; f < kMaxFilters; f++) {
+                if (f < (int)nf) {
+                    const size_t wi = (size_t)(tm.w_idx + (f0 + f) * w_fstride) * nl + l;
+                    u64 v = acc[f] + shoup_lazy(xv, w[wi], ws[wi], q);
+                    acc[f] = v >= q2 ? v - q2 : v;
+                }
+            }
+        }
+#pragma unroll
+        for (int f = 0; f < kMaxFilters; f++) {
+            if (f < (int)nf) {
+                const u32 o = (f0 + f) * wo + jo;
+                u64 v = acc[f];
+                if (bias && row < nl) v += bias[(size_t)o * nl + l];
+                v = v >= q2 ? v - q2 : v;
+                v = v >= q ? v - q : v;
+                out[(size_t)(set * n_out + o) * out_stride + (size_t)row * n + t] = v;
+            }
+        }
     }
-    if (bias && row < nl) acc += bias[(size_t)o * nl + l];
-    acc = acc >= q2 ? acc - q2 : acc;
-    acc = acc >= q ? acc - q : acc;
-    out[(size_t)(set * n_out + o) * out_stride + (size_t)row * n + t] = acc;
 }
 
 // T = sum_k A_k (x) R_k: 3-component tensor accumulate over n_terms pairs
@@ -337,8 +365,8 @@ u32 pow2ceil(u32 x)
 
 // Device-resident constants of one conv layer call: weights [RHA(K q_l)]_{q_i}
 // with Shoup companions (one row per (c', c, u, v)), the AddConst value per
-// output and limb, and the term list (input index, weight row) per output.
-// Input (u, c, j) has index u * C_in * w + c * w + j.
+// output and limb, and the term list (input index, weight row of filter 0)
+// per output column.  Input (u, c, j) has index u * C_in * w + c * w + j.
 struct ConvPlan {
     BufPtr buf;
     const Term* terms = nullptr;
@@ -373,20 +401,21 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
             u64 b = double_to_mod(bias[co] * out_scale, ctx->mod[l]);
             for (u32 jo = 0; jo < wo; jo++) bv[((size_t)co * wo + jo) * nl + l] = b;
         }
+    // one term list per output column, weight rows of filter 0 (filter c'
+    // adds c' * C_in * k * k)
     std::vector<Term> terms;
     std::vector<u32> off(1, 0);
-    for (u32 co = 0; co < C_out; co++)
-        for (u32 jo = 0; jo < wo; jo++) {
-            for (u32 c = 0; c < C_in; c++)
-                for (u32 v = 0; v < k; v++) {
-                    int jj = (int)(stride * jo + v) - (int)pad;
-                    if (jj < 0 || jj >= (int)w) continue;
-                    for (u32 u = 0; u < k; u++)
-                        terms.push_back({(u32)(((size_t)u * C_in + c) * w + jj),
-                                         (u32)((((size_t)co * C_in + c) * k + u) * k + v)});
-                }
-            off.push_back((u32)terms.size());
-        }
+    for (u32 jo = 0; jo < wo; jo++) {
+        for (u32 c = 0; c < C_in; c++)
+            for (u32 v = 0; v < k; v++) {
+                int jj = (int)(stride * jo + v) - (int)pad;
+                if (jj < 0 || jj >= (int)w) continue;
+                for (u32 u = 0; u < k; u++)
+                    terms.push_back({(u32)(((size_t)u * C_in + c) * w + jj),
+                                     (u32)(((size_t)c * k + u) * k + v)});
+            }
+        off.push_back((u32)terms.size());
+    }
     // one device buffer: terms | off | w | ws | bias (8-byte aligned parts)
     size_t b_terms = terms.size() * sizeof(Term), b_off = ((off.size() * 4 + 7) / 8) * 8;
     size_t total = b_terms + b_off + (wv.size() + wsv.size() + bv.size()) * 8;
@@ -534,16 +563,98 @@ Slab conv_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& x, u32 n_set
     Slab acc = new_slab(ctx, n_sets * n_out, 2, level, out_scale, s);
     {
         const u32 chunks = (ctx->n + kThreads - 1) / kThreads;
-        const u32 total = chunks * 2 * nl * n_sets * n_out;
+        const u32 total = chunks * 2 * nl * n_sets * wo;
         const u32 per_xcd = (total + 7) / 8;
         ProfScope prof(ctx, kProfLincomb, s, (u64)n_sets * n_out * 2 * nl);
         hipLaunchKernelGGL(k_lincomb, dim3(8 * per_xcd), dim3(kThreads), 0, s, acc.base, acc.stride,
                            x.base, rot.empty() ? x.base : rot[0].base, C_in * w, n_sets, x.stride,
-                           plan.terms, plan.off, plan.w, plan.ws, plan.bias, nl, ctx->log_n,
-                           ctx->d_modq, n_out, total, per_xcd);
+                           plan.terms, plan.off, plan.w, plan.ws, C_in * k * k, plan.bias, nl,
+                           ctx->log_n, ctx->d_modq, wo, C_out, total, per_xcd);
         VR_CHECK_LAUNCH();
     }
     return rescale_slab(ctx, acc, s);
+}
+
+// Several column-split products at one level and scale in one schedule
+// (S-MM of the abstract and "Homomorphic Matrix Multiplication" per request):
+// the Bbar columns of every request share one hoisted ModUp; requests are
+// ordered by P' (largest first) so that for each rotation step idx the
+// ciphertexts still needing it form a prefix, rotated by one shared-key
+// inner product and one ModDown; the tensor accumulations stay per request,
+// and every request's P' products are relinearised and rescaled together.
+std::vector<Slab> matmul_multi(vr_context* ctx, const vr_eval_keys* ek, const std::vector<MatReq>& reqs,
+                               hipStream_t s)
+{
+    const u32 nr = (u32)reqs.size();
+    if (nr == 0) return {};
+    const u32 level = reqs[0].A.level, nl = level + 1;
+    const double scale_ab = reqs[0].A.scale * reqs[0].B.scale;
+    std::vector<u32> order(nr), Pp(nr);
+    for (u32 r = 0; r < nr; r++) {
+        const MatReq& q = reqs[r];
+        if (q.A.level != level || q.B.level != level) throw Error(VR_ELEVEL, "matmul inputs at different levels");
+        if (q.A.scale * q.B.scale != scale_ab) throw Error(VR_ESCALE, "matmul inputs at different scales");
+        if (q.A.ncomp != 2 || q.B.ncomp != 2) throw Error(VR_EINVAL, "matmul inputs must be 2-component");
+        if (q.m < q.p) throw Error(VR_EINVAL, "matmul schedule needs m >= p (multiply the transposes)");
+        Pp[r] = pow2ceil(q.p);
+        order[r] = r;
+        for (u32 i = 1; i < Pp[r]; i++) (void)rot_key(ek, galois_element(ctx, (int32_t)i));
+    }
+    std::stable_sort(order.begin(), order.end(), [&](u32 a, u32 b) { return Pp[a] > Pp[b]; });
+    const size_t N = ctx->n;
+    // every request's Bbar columns in one slab, in that order; products slab
+    u32 n_tot = 0, p_tot = 0;
+    std::vector<u32> b_off(nr), t_off(nr);
+    for (u32 r : order) b_off[r] = n_tot, n_tot += reqs[r].n;
+    for (u32 r = 0; r < nr; r++) t_off[r] = p_tot, p_tot += Pp[r];
+    Slab SB = new_slab(ctx, n_tot, 2, level, reqs[0].B.scale, s);
+    for (u32 r = 0; r < nr; r++)
+        VR_HIP(hipMemcpyAsync(SB.ct(b_off[r]), reqs[r].B.base, (size_t)reqs[r].n * SB.stride * sizeof(u64),
+                              hipMemcpyDeviceToDevice, s));
+    Slab T = new_slab(ctx, p_tot, 3, level, scale_ab, s);
+    dim3 grid((ctx->n + kThreads - 1) / kThreads, nl);
+    for (u32 r = 0; r < nr; r++) {   // idx = 0: no rotation
+        hipLaunchKernelGGL(k_tensor_acc, grid, dim3(kThreads), 0, s, T.ct(t_off[r]), reqs[r].A.base,
+                           reqs[r].A.stride, SB.ct(b_off[r]), SB.stride, reqs[r].n, nl, ctx->log_n,
+                           ctx->d_modq);
+        VR_CHECK_LAUNCH();
+    }
+    const u32 max_p = Pp[order[0]];
+    if (max_p > 1) {
+        KsShape k = ks_shape(ctx, level);
+        const u64 xs = (u64)k.beta * k.next * N, us = (u64)2 * k.next * N;
+        BufPtr xbuf = dev_alloc(ctx, ((size_t)n_tot * xs + (size_t)n_tot * k.nq * N) * sizeof(u64), s);
+        u64* X = as_u64(xbuf);
+        keyswitch_modup_batch(ctx, SB.base + (size_t)k.nq * N, SB.stride, n_tot, level, X,
+                              X + (size_t)n_tot * xs, s);
+        BufPtr ubuf = dev_alloc(ctx, ((size_t)n_tot * us + keyswitch_moddown_scratch(ctx, level, n_tot)) * sizeof(u64), s);
+        u64* U = as_u64(ubuf);
+        Slab R = new_slab(ctx, n_tot, 2, level, SB.scale, s);
+        for (u32 idx = 1; idx < max_p; idx++) {
+            u32 n_act = 0;   // prefix of columns whose request still needs step idx
+            for (u32 r : order)
+                if (Pp[r] > idx) n_act = b_off[r] + reqs[r].n;
+            const u32 g = galois_element(ctx, (int32_t)idx);
+            keyswitch_inner_batch(ctx, X, xs, n_act, rot_key(ek, g).data, level, g, U, us, s);
+            keyswitch_moddown_batch(ctx, U, us, n_act, level, R.base, R.base + (size_t)k.nq * N, R.stride,
+                                    SB.base, g, nullptr, SB.stride, U + (size_t)n_act * us, s);
+            for (u32 r : order) {
+                if (Pp[r] <= idx) continue;
+                hipLaunchKernelGGL(k_tensor_acc, grid, dim3(kThreads), 0, s, T.ct(t_off[r] + idx),
+                                   reqs[r].A.base, reqs[r].A.stride, R.ct(b_off[r]), R.stride, reqs[r].n,
+                                   nl, ctx->log_n, ctx->d_modq);
+                VR_CHECK_LAUNCH();
+            }
+        }
+    }
+    Slab out = rescale_slab(ctx, relin_slab(ctx, ek, T, s), s);
+    std::vector<Slab> res(nr);
+    for (u32 r = 0; r < nr; r++) {
+        res[r] = out;
+        res[r].n = Pp[r];
+        res[r].base = out.ct(t_off[r]);
+    }
+    return res;
 }
 
 }  // namespace vr
@@ -665,44 +776,12 @@ vr_status vr_matmul(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext
     REQUIRE(m >= 1 && n >= 1 && p >= 1, "empty matrix");
     REQUIRE(m >= p, "matmul schedule needs m >= p (multiply the transposes)");
     hipStream_t s = pick_stream(ctx, stream);
-    Slab sa = gather(ctx, A, n, s);
-    Slab sb = gather(ctx, Bbar, n, s);
-    REQUIRE(sa.ncomp == 2 && sb.ncomp == 2, "matmul inputs must be 2-component");
-    if (sa.level != sb.level) throw Error(VR_ELEVEL, "A and B at different levels");
-    const u32 level = sa.level, nl = level + 1;
-    std::vector<int32_t> steps;
-    for (u32 i = 1; i < Pp; i++) steps.push_back((int32_t)i);
-    for (int32_t st : steps) (void)rot_key(ek, galois_element(ctx, st));
-    Slab T = new_slab(ctx, Pp, 3, level, sa.scale * sb.scale, s);
-    // idx = 0: no rotation
-    dim3 grid((ctx->n + kThreads - 1) / kThreads, nl);
-    hipLaunchKernelGGL(k_tensor_acc, grid, dim3(kThreads), 0, s, T.ct(0), sa.base, sa.stride,
-                       sb.base, sb.stride, n, nl, ctx->log_n, ctx->d_modq);
-    VR_CHECK_LAUNCH();
-    if (Pp > 1) {
-        // hoisted ModUp of every Bbar_k, then per step one batched key switch
-        const size_t N = ctx->n;
-        KsShape k = ks_shape(ctx, level);
-        const u64 xs = (u64)k.beta * k.next * N, us = (u64)2 * k.next * N;
-        BufPtr xbuf = dev_alloc(ctx, ((size_t)n * xs + (size_t)n * k.nq * N) * sizeof(u64), s);
-        u64* X = as_u64(xbuf);
-        keyswitch_modup_batch(ctx, sb.base + (size_t)k.nq * N, sb.stride, n, level, X,
-                              X + (size_t)n * xs, s);
-        BufPtr ubuf = dev_alloc(ctx, ((size_t)n * us + keyswitch_moddown_scratch(ctx, level, n)) * sizeof(u64), s);
-        u64* U = as_u64(ubuf);
-        Slab R = new_slab(ctx, n, 2, level, sb.scale, s);
-        for (u32 idx = 1; idx < Pp; idx++) {
-            u32 g = galois_element(ctx, (int32_t)idx);
-            keyswitch_inner_batch(ctx, X, xs, n, rot_key(ek, g).data, level, g, U, us, s);
-            keyswitch_moddown_batch(ctx, U, us, n, level, R.base, R.base + (size_t)k.nq * N, R.stride,
-                                    sb.base, g, nullptr, sb.stride, U + (size_t)n * us, s);
-            hipLaunchKernelGGL(k_tensor_acc, grid, dim3(kThreads), 0, s, T.ct(idx), sa.base,
-                               sa.stride, R.base, R.stride, n, nl, ctx->log_n, ctx->d_modq);
-            VR_CHECK_LAUNCH();
-        }
-    }
-    Slab out = rescale_slab(ctx, relin_slab(ctx, ek, T, s), s);
-    to_handles(ctx, out, C);
+    MatReq rq;
+    rq.A = gather(ctx, A, n, s);
+    rq.B = gather(ctx, Bbar, n, s);
+    rq.m = m, rq.n = n, rq.p = p;
+    std::vector<Slab> out = matmul_multi(ctx, ek, {rq}, s);
+    to_handles(ctx, out[0], C);
     API_END
 }
 

@@ -80,7 +80,18 @@ __device__ __forceinline__ u32 pad(u32 i) { return i + (i >> 4); }
 struct RoundIO {
     const u64* gsrc = nullptr;   // canonical uint64 input
     u64* gdst = nullptr;         // canonical uint64 output
+    u64 cq = 0;                  // != 0: gsrc holds residues mod cq, converted on the load
+    u64 t_one_s = 0;             // floor(2^64 / q) of the limb's own modulus
 };
+
+// centred residue v mod cq as a residue mod q (one-limb fast base conversion)
+__device__ __forceinline__ u64 conv_one(u64 v, u64 cq, u64 q, u64 one_s)
+{
+    const bool neg = v > (cq >> 1);
+    u64 x = neg ? cq - v : v;
+    x = csub(shoup_lazy(x, 1, one_s, q), q);
+    return neg ? neg_mod(x, q) : x;
+}
 
 // One round of R stages (local stages sg0 .. sg0+R-1 of the pass) over every
 // 2^R-element group of the tile.
@@ -109,7 +120,10 @@ __device__ __forceinline__ void ntt_round(u64* lds, const u64* tw, const ModQ& m
         u64 x[E];
         if (io.gsrc) {
 #pragma unroll
-            for (int m = 0; m < E; m++) x[m] = io.gsrc[base + ((u32)m << low_bits)];
+            for (int m = 0; m < E; m++) {
+                x[m] = io.gsrc[base + ((u32)m << low_bits)];
+                if (io.cq) x[m] = conv_one(x[m], io.cq, q, io.t_one_s);
+            }
         } else {
 #pragma unroll
             for (int m = 0; m < E; m++) x[m] = lds[pad(base + ((u32)m << low_bits))];
@@ -213,7 +227,8 @@ __device__ __forceinline__ void ntt_round_fp(double* lds, const double* tw, doub
         if (io.gsrc) {
 #pragma unroll
             for (int m = 0; m < E; m++) {
-                const u64 v = io.gsrc[base + ((u32)m << low_bits)];
+                u64 v = io.gsrc[base + ((u32)m << low_bits)];
+                if (io.cq) v = conv_one(v, io.cq, qi, io.t_one_s);
                 x[m] = v > qi / 2 ? -(double)(qi - v) : (double)v;
             }
         } else {
@@ -332,6 +347,14 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
     const u64 q = m.q, q2 = 2 * m.q;
     const bool fp = q < (1ull << 51);   // uniform over the workgroup (one limb)
     const double qd = (double)q, qinv = 1.0 / qd;
+    // fused one-limb base conversion: this limb's source and its modulus
+    u64 cq = 0;
+    if (!INV && p.first && p.ls.cv_src) {
+        const u32 poly = r / p.ls.per_poly;
+        const u32 ct = poly / p.ls.cv_beta, d = poly - ct * p.ls.cv_beta;
+        src = p.ls.cv_src + (size_t)ct * p.ls.cv_ct_stride + (size_t)d * n;
+        cq = p.mq[p.ls.cv_mod0 + d].q;
+    }
 
     // a pass over the whole limb reads and writes global memory in its first
     // and last round; other passes stage the tile through LDS with coalesced loads
@@ -346,6 +369,7 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
             u32 H = g >> lo_bits, Lo = g & ((1u << lo_bits) - 1);
             size_t idx = ((size_t)H << (p.log_n - p.s0)) + ((size_t)v << lo_bits) + Lo;
             u64 x = src[idx];
+            if (cq) x = conv_one(x, cq, q, m.one_s);
             // first pass of the FP64 path: canonical uint64 -> balanced double;
             // later passes read the balanced doubles the previous pass stored
             if (fp && p.first) x = __double_as_longlong(x > q / 2 ? -(double)(q - x) : (double)x);
@@ -363,7 +387,7 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
             for (u32 sg0 = 0; sg0 < p.log_g;) {
                 u32 rr = p.log_g - sg0 < 4 ? p.log_g - sg0 : 4;
                 RoundIO io;
-                if (direct && sg0 == 0) io.gsrc = src;
+                if (direct && sg0 == 0) io.gsrc = src, io.cq = cq, io.t_one_s = m.one_s;
                 if (direct && sg0 + rr == p.log_g) io.gdst = dst;
                 run_round_fp<false, THREADS>(rr, ldf, twf, qd, qinv, every2, p.log_g, p.log_c, sg0,
                                              p.s0, g0, lo_bits, io, ninv_f);
@@ -388,7 +412,7 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
             for (u32 sg0 = 0; sg0 < p.log_g;) {
                 u32 rr = p.log_g - sg0 < 4 ? p.log_g - sg0 : 4;
                 RoundIO io;
-                if (direct && sg0 == 0) io.gsrc = src;
+                if (direct && sg0 == 0) io.gsrc = src, io.cq = cq, io.t_one_s = m.one_s;
                 if (direct && sg0 + rr == p.log_g) io.gdst = dst;
                 run_round<false, THREADS>(rr, lds, tw, m, p.log_g, p.log_c, sg0, p.s0, g0, lo_bits, io);
                 sg0 += rr;

@@ -31,6 +31,15 @@ Slab layer_square(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipSt
 // weight plaintexts P[o][i] at P + (o * y.n + i) * p_stride
 Slab fc_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& y, const u64* P, u64 p_stride,
              double p_scale, u32 n_out, const double* bias, u32 block, hipStream_t s);
+// One column-split product C = A B (A_k, Bbar_k column slabs of n each).
+struct MatReq {
+    Slab A, B;
+    u32 m = 0, n = 0, p = 0;
+};
+// Products of several requests at one level and scale, sharing the hoisted
+// ModUp and each rotation step's key; result r holds P'_r ciphertexts.
+std::vector<Slab> matmul_multi(vr_context* ctx, const vr_eval_keys* ek, const std::vector<MatReq>& reqs,
+                               hipStream_t s);
 const u64* fc_weights(vr_context* ctx, const vr_plaintext* const* W_pt, size_t count, u32 nl,
                       u64* p_stride, double* p_scale, BufPtr& holder, hipStream_t s);
 

@@ -330,6 +330,14 @@ struct LimbSet {
     u32 skip_at = 0xffffffffu, skip_len = 0;
     u32 digit_skip = 0, alpha = 0, beta = 0, nq = 0;
     u32 out_dense = 0;
+    // forward only: the first pass reads, instead of each limb, the one-limb
+    // source it is the fast base conversion of (digits of one modulus): poly
+    // p takes limb cv_src + (p / cv_beta) * cv_ct_stride + (p % cv_beta) * N,
+    // modulo modulus cv_mod0 + p % cv_beta, centred and reduced to the limb's
+    // own modulus on the load
+    const u64* cv_src = nullptr;
+    u64 cv_ct_stride = 0;
+    u32 cv_beta = 1, cv_mod0 = 0;
 };
 
 void ntt_forward(vr_context* ctx, const LimbSet& ls, hipStream_t s);

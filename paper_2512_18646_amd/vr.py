@@ -109,6 +109,14 @@ _SIGS = {
     "vr_graph_launch": [P, P],
     "vr_graph_outputs": [P, PP, SZ, ctypes.POINTER(SZ)],
     "vr_graph_destroy": [P],
+    "vr_batch_create": [P, P, PP],
+    "vr_batch_add_cnn": [P, P, PP, U32, ctypes.POINTER(U32)],
+    "vr_batch_add_matmul": [P, PP, PP, U32, U32, U32, ctypes.POINTER(U32)],
+    "vr_batch_run": [P, P],
+    "vr_batch_capture": [P],
+    "vr_batch_launch": [P, P],
+    "vr_batch_outputs": [P, U32, PP, SZ, ctypes.POINTER(SZ)],
+    "vr_batch_destroy": [P],
     "vr_srv_create": [P, SZ, U32, PP],
     "vr_srv_destroy": [P],
     "vr_srv_register_session": [P, P, ctypes.POINTER(U64)],
@@ -125,7 +133,7 @@ _SIGS = {
     "vr_free_keys": [P, P],
     "vr_last_error": [],
 }
-_VOID = {"vr_context_destroy", "vr_srv_destroy", "vr_graph_destroy", "vr_free_ciphertext", "vr_free_plaintext", "vr_free_keys"}
+_VOID = {"vr_context_destroy", "vr_srv_destroy", "vr_graph_destroy", "vr_batch_destroy", "vr_free_ciphertext", "vr_free_plaintext", "vr_free_keys"}
 
 
 def _load():
@@ -610,6 +618,61 @@ class Graph:
     def close(self):
         if self.h:
             lib.vr_graph_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Uneven batch of networks and products, run eagerly or as one HIP graph (vr_batch_*)."""
+
+    def __init__(self, ctx, keys):
+        self.ctx, self.keys = ctx, keys
+        self._nets = []
+        self._cap = []
+        h = ctypes.c_void_p()
+        _check(lib.vr_batch_create(ctx.h, keys.ek, ctypes.byref(h)))
+        self.h = h.value
+
+    def add_cnn(self, net, cols, n_sets=1):
+        rid = U32()
+        _check(lib.vr_batch_add_cnn(self.h, ctypes.byref(net.desc), _ptr_array(cols), n_sets, ctypes.byref(rid)))
+        self._nets.append(net)          # the description's arrays must outlive the batch
+        self._cap.append(n_sets * net.outputs_per_set())
+        return rid.value
+
+    def add_matmul(self, A, Bbar, m, n, p):
+        rid = U32()
+        _check(lib.vr_batch_add_matmul(self.h, _ptr_array(A), _ptr_array(Bbar), m, n, p, ctypes.byref(rid)))
+        pp = 1
+        while pp < p:
+            pp <<= 1
+        self._cap.append(pp)
+        return rid.value
+
+    def run(self, stream=None):
+        _check(lib.vr_batch_run(self.h, _stream(stream)))
+
+    def capture(self):
+        _check(lib.vr_batch_capture(self.h))
+
+    def launch(self, stream=None):
+        _check(lib.vr_batch_launch(self.h, _stream(stream)))
+
+    def outputs(self, rid):
+        cap = self._cap[rid]
+        arr = (ctypes.c_void_p * cap)()
+        n = SZ()
+        _check(lib.vr_batch_outputs(self.h, rid, arr, cap, ctypes.byref(n)))
+        return [Ciphertext(arr[i], self.ctx) for i in range(n.value)]
+
+    def close(self):
+        if self.h:
+            lib.vr_batch_destroy(self.h)
             self.h = None
 
     def __del__(self):

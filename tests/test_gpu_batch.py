@@ -1,0 +1,73 @@
+"""Uneven batches (vr_batch_*): products of different shapes sharing rotation
+keys, networks merged into multi-set evaluations, run eagerly and as one
+captured graph -- every request's limbs identical to its own call, on every
+replay."""
+import numpy as np
+import pytest
+
+from oracle import layers as Ly
+from tests.gpu_helpers import pair, to_gpu, assert_same
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    return pair("C1", rot_steps=tuple(range(1, 16)), log_n=10)
+
+
+def same(a_list, b_list, what):
+    assert len(a_list) == len(b_list), what
+    for i, (a, b) in enumerate(zip(a_list, b_list)):
+        assert a.meta == b.meta, (what, i)
+        assert np.array_equal(a.export(), b.export()), "%s: output %d differs" % (what, i)
+
+
+def test_uneven_batch_eager_and_graph(ctx):
+    from paper_2512_18646_amd import vr
+    o, ok, g, gk = ctx
+    rng = np.random.default_rng(71)
+    mm = []
+    for i, (m, n, p) in enumerate([(8, 6, 8), (16, 5, 4), (8, 8, 3), (16, 3, 16)]):
+        A, B = rng.uniform(-1, 1, (m, n)), rng.uniform(-1, 1, (n, p))
+        if i == 0:   # the oracle's encryption, to anchor the batched limbs
+            Ac = [to_gpu(g, c) for c in Ly.encrypt_matrix_columns(o, ok, A, 0, m, p, 3, 81, 0)]
+            Bc = [to_gpu(g, c) for c in Ly.encrypt_matrix_columns(o, ok, B, 1, m, p, 3, 81, 100)]
+        else:
+            Ac = g.encrypt_matrix_columns(gk, A, 0, m, p, 3, 82 + i, 0)
+            Bc = g.encrypt_matrix_columns(gk, B, 1, m, p, 3, 82 + i, 100)
+        mm.append((A, B, Ac, Bc, m, n, p))
+    K1, b1 = rng.normal(0, 0.1, (3, 2, 3, 3)), rng.normal(0, 0.1, 3)
+    K2, b2 = rng.normal(0, 0.1, (2, 1, 2, 2)), rng.normal(0, 0.1, 2)
+    net1 = vr.CNN(2, 10, 9, 1, K1, b1, 2, square=True)
+    net2 = vr.CNN(1, 7, 6, 0, K2, b2, 1, square=False)
+    def cols(seed, X, pad):
+        return g.encrypt_columns(gk, X, pad, 3, seed, 0)
+
+    nets = [(net1, cols(90, rng.uniform(0, 1, (8, 2, 10, 9)), 1), 1),
+            (net1, cols(95, rng.uniform(0, 1, (8, 2, 10, 9)), 1) + cols(96, rng.uniform(0, 1, (8, 2, 10, 9)), 1), 2),
+            (net2, cols(99, rng.uniform(0, 1, (4, 1, 7, 6)), 0), 1)]
+    b = vr.Batch(g, gk)
+    ids, refs = [], []
+    for A, B, Ac, Bc, m, n, p in mm:
+        ids.append(b.add_matmul(Ac, Bc, m, n, p))
+        refs.append(g.matmul(gk, Ac, Bc, m, n, p))
+    for net, flat, sets in nets:
+        ids.append(b.add_cnn(net, flat, sets))
+        refs.append(net.forward(g, gk, flat, sets))
+    b.run()
+    for i, r in zip(ids, refs):
+        same(b.outputs(i), r, "eager request %d" % i)
+    # the anchored product against the oracle
+    A, B, Ac, Bc, m, n, p = mm[0]
+    D = Ly.matmul(o, ok, Ly.encrypt_matrix_columns(o, ok, A, 0, m, p, 3, 81, 0),
+                  Ly.encrypt_matrix_columns(o, ok, B, 1, m, p, 3, 81, 100), m, n, p)
+    for j, (x, y) in enumerate(zip(b.outputs(ids[0]), D)):
+        assert_same(x, y, "batched product %d" % j)
+    b.capture()
+    for rep in range(3):
+        b.launch()
+        for i, r in zip(ids, refs):
+            same(b.outputs(i), r, "replay %d request %d" % (rep, i))
+        net2.forward(g, gk, nets[2][1])[0].export()     # eager work between replays
+    b.close()

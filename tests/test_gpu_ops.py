@@ -196,7 +196,8 @@ def test_keyswitch_match_other_chains(name, level, mode):
     """Rotation and relinearisation with 60-bit q_0 / special primes (C2) and
     9-prime digits with a short last digit (C3 at levels 3 and 20), with the
     base conversions on the vector ALU, on the INT8 matrix cores, and as the
-    autotuner picks (its first call runs both kernels)."""
+    autotuner picks (its first call runs both kernels); one-limb digits (C2)
+    convert inside the NTT's first load whatever the mode."""
     o, ok, g, gk = pair(name, rot_steps=(1, 3))
     z = np.random.default_rng(level).uniform(-1, 1, o.slots)
     a = o.encrypt(ok, o.encode(z, level, o.scale), 9, level)
@@ -208,7 +209,7 @@ def test_keyswitch_match_other_chains(name, level, mode):
         assert_same(many[0], o.rotate(a, 3, ok), "%s hoisted 3 %s" % (name, mode))
         t = o.tensor(a, a)
         assert_same(g.relinearize(gk, to_gpu(g, t)), o.relinearize(t, ok), "%s relin %s" % (name, mode))
-        if mode == "auto":
+        if mode == "auto" and name == "C3":   # one-limb digits (C2) convert inside the NTT
             rep = g.tuning_report()
             assert "modup l%d d0" % level in rep and "untimed" not in rep.split("modup l%d d0" % level)[1].split("\n")[0]
     finally:
