@@ -163,6 +163,97 @@ def cnn128_bench(vr, level_in, sets, reps):
             "device_gib_reserved": round(reserved / 2 ** 30, 1)}
 
 
+def uneven_bench(vr, n_req, level, reps, seed=4):
+    """64 mixed requests at N = 2^16 (L = 24 chain, entering at `level`):
+    products with m, n, p in 8..32 and 3x3/2 convolutions (8 filters, x^2)
+    on 32x32 or 64x64 images, one full ciphertext set each.  Per-request calls
+    versus one eager batch versus the batch captured as one HIP graph."""
+    import synthetic_inputs as SI
+    reqs = SI.uneven_requests(seed, n_req)
+    ctx = vr.Context(16, [60] + [50] * 24, [51] * 9, 3, 50.0)
+    max_p = max(1 << (r[1][2] - 1).bit_length() for r in reqs if r[0] == "matmul")
+    keys = ctx.keygen(1004, rot_steps=list(range(1, max(max_p, 3))))
+    nets, items = {}, []
+    images = 0
+    for i, (kind, shape, rs) in enumerate(reqs):
+        if kind == "matmul":
+            m, n, p = shape
+            A, B = SI.matmul_operands(rs, m, n, p)
+            items.append(("matmul", ctx.encrypt_matrix_columns(keys, A, 0, m, p, level, 1004, 1000 * i),
+                          ctx.encrypt_matrix_columns(keys, B, 1, m, p, level, 1004, 1000 * i + 500),
+                          (m, n, p), (A, B)))
+        else:
+            side = shape
+            if side not in nets:
+                K, bias = SI.conv_weights(seed + side, 8, 1, 3, 0.05)
+                nets[side] = vr.CNN(1, side, side, 1, K, bias, 2, square=True)
+            hp = 1 << (side + 1).bit_length()
+            B = ctx.slots // hp
+            X = SI.images(rs, B, 1, side, side)
+            items.append(("conv", ctx.encrypt_columns(keys, X, 1, level, 1004, 1000 * i), side, B))
+            images += B
+
+    def per_request():
+        outs = []
+        for it in items:
+            if it[0] == "matmul":
+                m, n, p = it[3]
+                outs.append(ctx.matmul(keys, it[1], it[2], m, n, p))
+            else:
+                outs.append(nets[it[2]].forward(ctx, keys, it[1]))
+        return outs
+
+    ref = per_request()
+    sync()
+    t = time.perf_counter()
+    for _ in range(reps):
+        per_request()
+    sync()
+    t_per = (time.perf_counter() - t) / reps
+    batch = vr.Batch(ctx, keys)
+    ids = [batch.add_matmul(it[1], it[2], *it[3]) if it[0] == "matmul" else batch.add_cnn(nets[it[2]], it[1])
+           for it in items]
+    batch.run()
+    sync()
+    t = time.perf_counter()
+    for _ in range(reps):
+        batch.run()
+    sync()
+    t_batch = (time.perf_counter() - t) / reps
+    same_eager = all(np.array_equal(batch.outputs(ids[i])[0].export(), ref[i][0].export()) for i in (0, 1, 2, 3))
+    batch.capture()
+    batch.launch()
+    sync()
+    t = time.perf_counter()
+    for _ in range(reps):
+        batch.launch()
+    sync()
+    t_graph = (time.perf_counter() - t) / reps
+    same_graph = all(np.array_equal(batch.outputs(ids[i])[-1].export(), ref[i][-1].export()) for i in range(len(ids)))
+    # decoded check of the first product
+    m, n, p = items[0][3]
+    A, B = items[0][4]
+    outs = batch.outputs(ids[0])
+    Pp = len(outs)
+    C = np.full((m, p), np.nan)
+    for idx, ct in enumerate(outs):
+        z = ctx.decode(ctx.decrypt(keys, ct), m)
+        for r in range(m):
+            if (r + idx) % Pp < p:
+                C[r, (r + idx) % Pp] = z[r]
+    err = float(np.nanmax(np.abs(C - A @ B)) / np.max(np.abs(A @ B)))
+    batch.close()
+    n_mm = sum(1 for it in items if it[0] == "matmul")
+    return {"workload": "%d requests: %d products (m, n, p in 8..32), %d 3x3/2 x8 + x^2 convolutions on "
+                        "32x32 / 64x64 images (full sets), N=2^16 L=24 chain at level %d"
+                        % (n_req, n_mm, n_req - n_mm, level),
+            "requests_per_s": {"per_request": round(n_req / t_per, 1), "batch": round(n_req / t_batch, 1),
+                               "graph": round(n_req / t_graph, 1)},
+            "conv_images_per_s": {"per_request": round(images / t_per, 1), "batch": round(images / t_batch, 1),
+                                  "graph": round(images / t_graph, 1)},
+            "identical_to_per_request": bool(same_eager and same_graph), "product_rel_error": err}
+
+
 SERVE_MIX = (("28x28", 28, 0.5), ("64x64", 64, 0.3), ("128x128", 128, 0.2))
 
 
@@ -354,6 +445,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cnn", action="store_true")
     ap.add_argument("--no-graph", action="store_true")
+    ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration)")
     ap.add_argument("--cnn-sets", type=int, default=2)
@@ -478,6 +570,10 @@ def main():
         for lv, sets in ((3, args.cnn_sets), (24, 1)):
             log("cnn128 at level %d" % lv)
             out.setdefault("cnn128_n16", []).append(cnn128_bench(vr, lv, sets, 2))
+
+    if not args.no_extra and not args.no_uneven:
+        log("uneven batch at N=2^16")
+        out["uneven_batch_n16"] = uneven_bench(vr, 64, 3, 2)
 
     if not args.no_extra and not args.no_serve:
         log("serving (Poisson arrivals, image-size mix)")

@@ -116,7 +116,10 @@ vr_status vr_context_trim(vr_context *ctx);
  * candidate pass plans -- one LDS-resident pass, or two passes with every
  * split of log N and 8..128 groups per workgroup -- on 256 scratch limbs and
  * keeps the fastest), "fixed" (the built-in plan) or "cand:<i>" (candidate i,
- * for tests; VR_EINVAL at the next transform if there is none).  Tuning synchronises
+ * for tests; VR_EINVAL at the next transform if there is none).  Knob
+ * "switch_chunk": "<k>" key-switches at most k ciphertexts per launch in the
+ * layer calls ("0": as many as 16 GiB of scratch allows, the default).
+ * Tuning synchronises
  * once; the transform is the same exact map under every plan. */
 vr_status vr_context_set_tuning(vr_context *ctx, const char *knob, const char *value);
 /* One line per base-conversion table built so far (shape, kernel chosen) and

@@ -12,13 +12,43 @@ namespace vr {
 DevBuf::~DevBuf()
 {
     if (!ptr) return;
-    if (free_fn)
+    if (cap)
+        cap->give_back(ptr);
+    else if (free_fn)
         free_fn(ptr, (void*)stream, free_user);
     else if (arena)
         arena->release(ptr, stream);
 }
 
-thread_local CaptureKeep* g_capture = nullptr;
+thread_local std::shared_ptr<CaptureKeep> g_capture;
+
+void* CaptureKeep::take(size_t bytes)
+{
+    const size_t want = DeviceArena::round_size(bytes);
+    std::lock_guard<std::mutex> g(mu);
+    auto it = free.lower_bound(want);
+    if (it != free.end() && it->first <= want + want / 4 + 4096) {
+        void* p = it->second;
+        free.erase(it);
+        return p;
+    }
+    void* p = arena->alloc_fresh(bytes);
+    if (p) size[p] = want;
+    return p;
+}
+
+void CaptureKeep::give_back(void* p)
+{
+    std::lock_guard<std::mutex> g(mu);
+    free.insert({size.at(p), p});
+}
+
+CaptureKeep::~CaptureKeep()
+{
+    // the graph is gone (its owner synchronised the device); later frees
+    // follow the context's stream
+    for (auto& kv : size) arena->release(kv.first, release_stream);
+}
 
 BufPtr dev_alloc(vr_context* ctx, size_t bytes, hipStream_t s)
 {
@@ -27,10 +57,9 @@ BufPtr dev_alloc(vr_context* ctx, size_t bytes, hipStream_t s)
     b->stream = s;
     if (bytes == 0) return b;
     if (g_capture) {
-        b->ptr = ctx->arena->alloc_fresh(bytes);
+        b->ptr = g_capture->take(bytes);
         if (!b->ptr) throw Error(VR_ENOMEM, "device allocation failed");
-        b->arena = ctx->arena;
-        g_capture->bufs.push_back(b);
+        b->cap = g_capture;
     } else if (ctx->alloc_fn) {
         b->ptr = ctx->alloc_fn(bytes, (void*)s, ctx->alloc_user);
         if (!b->ptr) throw Error(VR_ENOMEM, "allocator hook returned NULL");

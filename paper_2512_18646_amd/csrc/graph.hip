@@ -82,10 +82,19 @@ Slab run_cnn(vr_context* ctx, const vr_eval_keys* ek, const CnnDesc& d, const Sl
     return z;
 }
 
+// Sets the thread's capture pool for the guard's lifetime.  The context's
+// cache is emptied first so the graph's blocks have the device to themselves.
 struct CaptureGuard {
-    CaptureKeep keep;
-    CaptureGuard() { g_capture = &keep; }
-    ~CaptureGuard() { g_capture = nullptr; }
+    std::shared_ptr<CaptureKeep> keep;
+    explicit CaptureGuard(vr_context* ctx)
+    {
+        ctx->arena->trim();
+        keep = std::make_shared<CaptureKeep>();
+        keep->arena = ctx->arena;
+        keep->release_stream = ctx->stream;
+        g_capture = keep;
+    }
+    ~CaptureGuard() { g_capture.reset(); }
 };
 
 bool same_net(const CnnDesc& a, const CnnDesc& b)
@@ -168,7 +177,7 @@ struct vr_graph {
     vr::CnnDesc desc;
     vr::u32 n_sets = 0;
     vr::Slab in, out;
-    std::vector<vr::BufPtr> keep;
+    std::shared_ptr<vr::CaptureKeep> keep;   // the graph's memory
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -178,7 +187,7 @@ struct vr_batch {
     vr_context* ctx = nullptr;
     const vr_eval_keys* ek = nullptr;
     std::vector<vr::BatchReq> reqs;
-    std::vector<vr::BufPtr> keep;
+    std::shared_ptr<vr::CaptureKeep> keep;   // the graph's memory
     hipStream_t cap = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -231,11 +240,10 @@ void release_graph(vr_graph* g)
     (void)hipDeviceSynchronize();
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
-    // later frees of what the graph held (and of output handles) follow the context's stream
-    for (auto& b : g->keep) b->stream = g->ctx->stream;
-    if (g->out.buf) g->out.buf->stream = g->ctx->stream;
+    // later frees of the input slab follow the context's stream; the graph's
+    // own blocks return when the last handle into them is gone
     if (g->in.buf) g->in.buf->stream = g->ctx->stream;
-    g->keep.clear();
+    g->keep.reset();
     g->out = Slab();
     g->in = Slab();
     if (g->cap) (void)hipStreamDestroy(g->cap);
@@ -286,7 +294,8 @@ vr_status vr_graph_create(vr_context* ctx, const vr_eval_keys* ek, const vr_cnn_
         (void)run_cnn(ctx, ek, g->desc, g->in, n_sets, g->cap);
         VR_HIP(hipStreamSynchronize(g->cap));
         {
-            CaptureGuard guard;
+            CaptureGuard guard(ctx);
+            g->keep = guard.keep;
             VR_HIP(hipStreamBeginCapture(g->cap, hipStreamCaptureModeRelaxed));
             try {
                 g->out = run_cnn(ctx, ek, g->desc, g->in, n_sets, g->cap);
@@ -294,11 +303,9 @@ vr_status vr_graph_create(vr_context* ctx, const vr_eval_keys* ek, const vr_cnn_
                 hipGraph_t partial = nullptr;
                 (void)hipStreamEndCapture(g->cap, &partial);
                 if (partial) (void)hipGraphDestroy(partial);
-                g->keep = std::move(guard.keep.bufs);
                 throw;
             }
             VR_HIP(hipStreamEndCapture(g->cap, &g->graph));
-            g->keep = std::move(guard.keep.bufs);
         }
         VR_HIP(hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0));
     } catch (...) {
@@ -422,7 +429,8 @@ vr_status vr_batch_capture(vr_batch* b)
     // be freed while it records
     for (auto& r : b->reqs) r.out = Slab();
     {
-        CaptureGuard guard;
+        CaptureGuard guard(b->ctx);
+        b->keep = guard.keep;
         VR_HIP(hipStreamBeginCapture(b->cap, hipStreamCaptureModeRelaxed));
         try {
             run_batch(b->ctx, b->ek, b->reqs, b->cap);
@@ -430,11 +438,9 @@ vr_status vr_batch_capture(vr_batch* b)
             hipGraph_t partial = nullptr;
             (void)hipStreamEndCapture(b->cap, &partial);
             if (partial) (void)hipGraphDestroy(partial);
-            b->keep = std::move(guard.keep.bufs);
             throw;
         }
         VR_HIP(hipStreamEndCapture(b->cap, &b->graph));
-        b->keep = std::move(guard.keep.bufs);
     }
     VR_HIP(hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0));
     API_END
@@ -468,14 +474,13 @@ void vr_batch_destroy(vr_batch* b)
     (void)hipDeviceSynchronize();
     if (b->exec) (void)hipGraphExecDestroy(b->exec);
     if (b->graph) (void)hipGraphDestroy(b->graph);
-    for (auto& k : b->keep) k->stream = b->ctx->stream;
     for (auto& r : b->reqs) {
-        if (r.out.buf) r.out.buf->stream = b->ctx->stream;
+        if (r.out.buf && !r.out.buf->cap) r.out.buf->stream = b->ctx->stream;
         if (r.a.buf) r.a.buf->stream = b->ctx->stream;
         if (r.b.buf) r.b.buf->stream = b->ctx->stream;
     }
-    b->keep.clear();
     b->reqs.clear();
+    b->keep.reset();
     if (b->cap) (void)hipStreamDestroy(b->cap);
     delete b;
 }

@@ -268,9 +268,28 @@ __global__ __launch_bounds__(kThreads) void k_mulplain_acc(u64* out, u64 out_str
     }
 }
 
+// Key-switching scratch per ciphertext (ModUp digits, coefficient copy,
+// inner-product sums, ModDown scratch); layer calls switch at most
+// kSwitchBudget bytes' worth of ciphertexts at a time so that a layer of any
+// size runs in bounded memory (at N = 2^16, l = 24 that is ~120 ciphertexts).
+constexpr size_t kSwitchBudget = size_t(16) << 30;
+
+u32 switch_chunk(vr_context* ctx, u32 level, u32 n_ct)
+{
+    KsShape k = ks_shape(ctx, level);
+    const size_t per = ((size_t)k.beta * k.next + k.nq + 2 * k.next + 2 * (ctx->K + k.nq)) * ctx->n * 8;
+    size_t c = std::max<size_t>(1, kSwitchBudget / per);
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->tuning.find("switch_chunk");
+        if (it != ctx->tuning.end() && it->second > 0) c = (size_t)it->second;
+    }
+    return (u32)std::min<size_t>(c, n_ct);
+}
+
 // Rotations of every ciphertext of `in` by every step; out[si] is a slab of
 // in.n rotated ciphertexts (step si).  One ModUp per input (hoisting), one
-// inner-product launch per step.
+// inner-product launch per step and chunk of inputs.
 void rotate_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in,
                  const std::vector<int32_t>& steps, std::vector<Slab>& out, hipStream_t s)
 {
@@ -283,15 +302,14 @@ void rotate_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in,
         if (g != 1) (void)rot_key(ek, g);
         gs.push_back(g);
     }
-    const u64 xs = (u64)k.beta * k.next * n;
-    BufPtr xbuf = dev_alloc(ctx, ((size_t)n_ct * xs + (size_t)n_ct * k.nq * n) * sizeof(u64), s);
+    const u32 cs = switch_chunk(ctx, level, n_ct);
+    const u64 xs = (u64)k.beta * k.next * n, us = (u64)2 * k.next * n;
+    BufPtr xbuf = dev_alloc(ctx, ((size_t)cs * xs + (size_t)cs * k.nq * n) * sizeof(u64), s);
     u64* X = as_u64(xbuf);
-    u64* coef = X + (size_t)n_ct * xs;
-    keyswitch_modup_batch(ctx, in.base + (size_t)k.nq * n, in.stride, n_ct, level, X, coef, s);
-    const u64 us = (u64)2 * k.next * n;
-    BufPtr ubuf = dev_alloc(ctx, ((size_t)n_ct * us + keyswitch_moddown_scratch(ctx, level, n_ct)) * sizeof(u64), s);
+    u64* coef = X + (size_t)cs * xs;
+    BufPtr ubuf = dev_alloc(ctx, ((size_t)cs * us + keyswitch_moddown_scratch(ctx, level, cs)) * sizeof(u64), s);
     u64* U = as_u64(ubuf);
-    u64* md = U + (size_t)n_ct * us;
+    u64* md = U + (size_t)cs * us;
     out.clear();
     // every step's output in one allocation: step si at all.base + si * n_ct * stride
     Slab all = new_slab(ctx, n_ct * (u32)steps.size(), 2, level, in.scale, s);
@@ -299,15 +317,22 @@ void rotate_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in,
         Slab r = all;
         r.n = n_ct;
         r.base = all.base + si * n_ct * all.stride;
-        if (gs[si] == 1) {
-            VR_HIP(hipMemcpyAsync(r.base, in.base, (size_t)n_ct * in.stride * sizeof(u64),
-                                  hipMemcpyDeviceToDevice, s));
-        } else {
-            keyswitch_inner_batch(ctx, X, xs, n_ct, rot_key(ek, gs[si]).data, level, gs[si], U, us, s);
-            keyswitch_moddown_batch(ctx, U, us, n_ct, level, r.base, r.base + (size_t)k.nq * n,
-                                    r.stride, in.base, gs[si], nullptr, in.stride, md, s);
-        }
         out.push_back(r);
+    }
+    for (u32 c0 = 0; c0 < n_ct; c0 += cs) {
+        const u32 nc = std::min(cs, n_ct - c0);
+        const u64* src = in.ct(c0);
+        keyswitch_modup_batch(ctx, src + (size_t)k.nq * n, in.stride, nc, level, X, coef, s);
+        for (size_t si = 0; si < steps.size(); si++) {
+            u64* dst = out[si].ct(c0);
+            if (gs[si] == 1) {
+                VR_HIP(hipMemcpyAsync(dst, src, (size_t)nc * in.stride * sizeof(u64), hipMemcpyDeviceToDevice, s));
+            } else {
+                keyswitch_inner_batch(ctx, X, xs, nc, rot_key(ek, gs[si]).data, level, gs[si], U, us, s);
+                keyswitch_moddown_batch(ctx, U, us, nc, level, dst, dst + (size_t)k.nq * n, all.stride, src,
+                                        gs[si], nullptr, in.stride, md, s);
+            }
+        }
     }
 }
 
@@ -317,18 +342,22 @@ Slab relin_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& T, hipStrea
     const u32 level = T.level, n_ct = T.n;
     const size_t n = ctx->n;
     KsShape k = ks_shape(ctx, level);
+    const u32 cs = switch_chunk(ctx, level, n_ct);
     const u64 xs = (u64)k.beta * k.next * n, us = (u64)2 * k.next * n;
-    BufPtr xbuf = dev_alloc(ctx, ((size_t)n_ct * xs + (size_t)n_ct * k.nq * n) * sizeof(u64), s);
+    BufPtr xbuf = dev_alloc(ctx, ((size_t)cs * xs + (size_t)cs * k.nq * n) * sizeof(u64), s);
     u64* X = as_u64(xbuf);
-    keyswitch_modup_batch(ctx, T.base + (size_t)2 * k.nq * n, T.stride, n_ct, level, X,
-                          X + (size_t)n_ct * xs, s);
-    BufPtr ubuf = dev_alloc(ctx, ((size_t)n_ct * us + keyswitch_moddown_scratch(ctx, level, n_ct)) * sizeof(u64), s);
+    BufPtr ubuf = dev_alloc(ctx, ((size_t)cs * us + keyswitch_moddown_scratch(ctx, level, cs)) * sizeof(u64), s);
     u64* U = as_u64(ubuf);
-    keyswitch_inner_batch(ctx, X, xs, n_ct, ek->rlk.data, level, 1, U, us, s);
     Slab out = new_slab(ctx, n_ct, 2, level, T.scale, s);
-    keyswitch_moddown_batch(ctx, U, us, n_ct, level, out.base, out.base + (size_t)k.nq * n,
-                            out.stride, T.base, 1, T.base + (size_t)k.nq * n, T.stride,
-                            U + (size_t)n_ct * us, s);
+    for (u32 c0 = 0; c0 < n_ct; c0 += cs) {
+        const u32 nc = std::min(cs, n_ct - c0);
+        const u64* t = T.ct(c0);
+        keyswitch_modup_batch(ctx, t + (size_t)2 * k.nq * n, T.stride, nc, level, X, X + (size_t)cs * xs, s);
+        keyswitch_inner_batch(ctx, X, xs, nc, ek->rlk.data, level, 1, U, us, s);
+        u64* o = out.ct(c0);
+        keyswitch_moddown_batch(ctx, U, us, nc, level, o, o + (size_t)k.nq * n, out.stride, t, 1,
+                                t + (size_t)k.nq * n, T.stride, U + (size_t)cs * us, s);
+    }
     return out;
 }
 

@@ -146,6 +146,8 @@ __device__ __forceinline__ void mac128(u64& hi, u64& lo, u64 a, u64 b)
 // Device memory owned through shared pointers (ciphertext views into one slab
 // keep the slab alive).  Freed stream-ordered on the stream it was allocated
 // on, by the allocator that made it.
+struct CaptureKeep;
+
 struct DevBuf {
     void* ptr = nullptr;
     size_t bytes = 0;
@@ -153,17 +155,29 @@ struct DevBuf {
     void (*free_fn)(void*, void*, void*) = nullptr;
     void* free_user = nullptr;
     std::shared_ptr<DeviceArena> arena;   // built-in allocator (kept alive by its blocks)
+    std::shared_ptr<CaptureKeep> cap;     // allocated while a graph was being captured
     ~DevBuf();
 };
 typedef std::shared_ptr<DevBuf> BufPtr;
 
-// Set on a thread while it captures a graph: every allocation it makes is
-// taken fresh from the runtime and held here, so no block is released (and
-// handed to other work) while the graph may still use it.
+// Memory of one captured graph.  While a thread captures (g_capture set),
+// every allocation comes from here: a block released during the capture goes
+// back to this pool and later allocations of the same capture reuse it -- the
+// captured work is one stream-ordered chain, so the reuse is safe on every
+// replay -- and no block is recorded in or returned to the context's cache
+// while the graph may run.  The blocks go back to the context's allocator
+// when the graph and every handle into its memory are gone.
 struct CaptureKeep {
-    std::vector<BufPtr> bufs;
+    std::shared_ptr<DeviceArena> arena;
+    hipStream_t release_stream = nullptr;
+    std::mutex mu;
+    std::multimap<size_t, void*> free;             // by block size
+    std::map<void*, size_t> size;                  // every block it owns
+    void* take(size_t bytes);
+    void give_back(void* p);
+    ~CaptureKeep();
 };
-extern thread_local CaptureKeep* g_capture;
+extern thread_local std::shared_ptr<CaptureKeep> g_capture;
 
 // Kernel classes the event profiler can bracket.
 enum ProfClass : int {

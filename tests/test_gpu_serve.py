@@ -176,3 +176,20 @@ def test_caching_allocator_steady_state(small):
     g.trim()
     r, u = g.mem_info()
     assert r == u == used[0]
+
+
+def test_chunked_key_switching_identical(small):
+    """Layers key-switch in chunks when the scratch would exceed its budget;
+    forcing tiny chunks gives the same limbs."""
+    o, ok, g, gk = small
+    S = SHAPE
+    X, K, bias = draw(np.random.default_rng(61))
+    cols = g.encrypt_columns(gk, X, S["pad"], 3, 6, 0)
+    ref = alone(g, gk, cols, K, bias, True)
+    g.set_tuning("switch_chunk", "4")
+    try:
+        got = alone(g, gk, cols, K, bias, True)
+    finally:
+        g.set_tuning("switch_chunk", "0")
+    for j, (a, b) in enumerate(zip(got, ref)):
+        same_limbs(a, b, "chunked out %d" % j)
