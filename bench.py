@@ -254,6 +254,87 @@ def uneven_bench(vr, n_req, level, reps, seed=4):
             "identical_to_per_request": bool(same_eager and same_graph), "product_rel_error": err}
 
 
+def serving_n16_bench(vr, level=3, n_sessions=8, n_warm=20, n_meas=100, loads=(0.25, 0.5, 0.75, 0.9),
+                      seed=5):
+    """Serving at N = 2^16 (L = 24 chain, requests entering at `level`): 8
+    sessions with resident keys, Poisson arrivals of 28x28 (1 channel),
+    64x64 and 128x128 (3 channels) requests in a 5:3:2 mix, each carrying
+    b ~ U{1..B'} images, through the 3x3/2 x8 conv + x^2 + FC 8(s/2)^2 -> 10
+    network adapted to the size.  Offered load swept as fractions of the
+    saturating request rate measured first on a burst."""
+    import synthetic_inputs as SI
+    ctx = vr.Context(16, [60] + [50] * 24, [51] * 9, 3, 50.0)
+    steps = [1, 2] + [1 << t for t in range(2, 8)]
+    sessions = [ctx.keygen(2000 + i, rot_steps=steps) for i in range(n_sessions)]
+    kinds = []
+    for side, ch, frac in ((28, 1, 0.5), (64, 3, 0.3), (128, 3, 0.2)):
+        K, bias = SI.conv_weights(seed + side, 8, ch, 3, 0.05)
+        hp = 1 << (side + 1).bit_length()
+        wo = (side + 2 - 3) // 2 + 1
+        Wfc, bfc = SI.fc_weights(seed + 7 * side, 10, 8, wo, wo, 0.05)
+        pts = ctx.encode_fc_weights(Wfc, 2, hp, level - 2)
+        net = vr.CNN(ch, side, side, 1, K, bias, 2, square=True, fc_w=pts, fc_bias=bfc, fc_block=hp)
+        bmax = ctx.slots // hp
+        cols = [ctx.encrypt_columns(keys, SI.images(seed + 31 * i + side, bmax, ch, side, side), 1, level,
+                                    3000 + i, 100000 * side) for i, keys in enumerate(sessions)]
+        kinds.append({"side": side, "net": net, "bmax": bmax, "cols": cols, "frac": frac})
+    probs = np.array([k["frac"] for k in kinds])
+    free, total = __import__("torch").cuda.mem_get_info()
+    srv = vr.Server(ctx, int(total * 0.9), max_batch=4)
+    sids = [srv.register_session(k) for k in sessions]
+    for k in kinds:
+        k["mid"] = srv.register_model(k["net"])
+    rng = np.random.default_rng(seed)
+
+    def draw_request():
+        ki = int(rng.choice(len(kinds), p=probs))
+        si = int(rng.integers(n_sessions))
+        k = kinds[ki]
+        return ki, si, int(rng.integers(1, k["bmax"] + 1))
+
+    def run(n, rate):
+        tickets = []
+        t0 = time.perf_counter()
+        due = t0
+        for _ in range(n):
+            ki, si, b = draw_request()
+            if rate:
+                due += rng.exponential(1.0 / rate)
+                delay = due - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+            k = kinds[ki]
+            tickets.append((srv.submit(sids[si], k["mid"], k["cols"][si], b), k["mid"]))
+        for t, mid in tickets:
+            srv.poll(t, mid)
+
+    for k in kinds:                              # warm the cached constants of every network
+        srv.poll(srv.submit(sids[0], k["mid"], k["cols"][0], 1), k["mid"])
+    t0 = time.perf_counter()                     # saturation: a burst
+    srv.reset_stats()
+    run(24, 0)
+    burst_s = time.perf_counter() - t0
+    sat = srv.stats()
+    sat_req_s = 24 / burst_s
+    levels = []
+    for load in loads:
+        run(n_warm, load * sat_req_s)
+        srv.reset_stats()
+        run(n_meas, load * sat_req_s)
+        st = srv.stats()
+        levels.append({"offered_load": load, "offered_req_per_s": round(load * sat_req_s, 2),
+                       "images_per_s": round(st["images_per_s"], 1), "latency_ms_p50": round(st["p50_ms"], 2),
+                       "latency_ms_p99": round(st["p99_ms"], 2),
+                       "requests_per_wave": round(st["batched"] / max(st["waves"], 1), 2)})
+    srv.close()
+    return {"workload": "5:3:2 of 28x28x1 / 64x64x3 / 128x128x3 requests, b ~ U{1..B'} images each "
+                        "(B' = 1024 / 256 / 128), conv 3x3/2 x8 + x^2 + FC -> 10, %d sessions, N=2^16 L=24 "
+                        "chain at level %d, %d measured requests per load" % (n_sessions, level, n_meas),
+            "saturation": {"req_per_s": round(sat_req_s, 2), "images_per_s": round(sat["images_per_s"], 1),
+                           "latency_ms_p50": round(sat["p50_ms"], 2), "latency_ms_p99": round(sat["p99_ms"], 2)},
+            "loads": levels}
+
+
 SERVE_MIX = (("28x28", 28, 0.5), ("64x64", 64, 0.3), ("128x128", 128, 0.2))
 
 
@@ -579,6 +660,8 @@ def main():
         log("serving (Poisson arrivals, image-size mix)")
         out["serving"] = [serving_bench(vr, ctx, keys, args.serve_requests, float(x), args.level)
                           for x in args.serve_load.split(",")]
+        log("serving at N=2^16")
+        out["serving_n16"] = serving_n16_bench(vr)
         log("serving done")
 
     if not args.no_extra and not args.no_cpu_baseline:

@@ -414,6 +414,9 @@ vr_status vr_srv_register_conv_model(vr_server *srv, uint32_t C_in, uint32_t h, 
                                      uint32_t pad, const double *K, const double *bias,
                                      uint32_t C_out, uint32_t k, uint32_t stride, uint32_t square,
                                      uint32_t *model_id);
+/* Any network of vr_cnn_desc (conv, x^2, FC); the weights are copied, the FC
+ * weight plaintexts must outlive the server. */
+vr_status vr_srv_register_model(vr_server *srv, const vr_cnn_desc *desc, uint32_t *model_id);
 /* Queues one request: in[c*w + j] (n_in = C_in*w), n_images images (for the
  * throughput figure).  The inputs are read after the work already queued on
  * the context's stream; the caller may free its handles at once.  VR_EBUSY
@@ -425,14 +428,17 @@ vr_status vr_srv_submit(vr_server *srv, uint64_t session_id, uint32_t model_id,
 /* Removes a request that has not started; VR_EINVAL if it already has.  Its
  * poll then returns VR_ECANCELED. */
 vr_status vr_srv_cancel(vr_server *srv, uint64_t ticket);
-/* *ready = 1 and out[0..*n_out) = the C_out*w_out output handles (caller
+/* *ready = 1 and out[0..*n_out) = the model's output handles (C_out*w_out, or fc_out; caller
  * frees) once the request is done (wait != 0 blocks until then); the ticket
  * is then consumed.  A failed or cancelled request returns its error code. */
 vr_status vr_srv_poll(vr_server *srv, uint64_t ticket, int wait, vr_ciphertext **out, size_t cap,
                       size_t *n_out, int *ready);
-/* Submit-to-completion latency percentiles (nearest rank) over completed
- * requests, images per second between the first submit and the last
- * completion, request and wave counts (batched = requests run in waves). */
+/* Submit-to-completion latency percentiles (nearest rank) over the requests
+ * completed since creation or the last reset, images per second between the
+ * first submit and the last completion among them, request and wave counts
+ * (batched = requests run in waves). */
+/* Forgets the completed requests counted so far (e.g. after a warm-up). */
+vr_status vr_srv_reset_stats(vr_server *srv);
 vr_status vr_srv_stats(vr_server *srv, double *p50_ms, double *p99_ms, double *images_per_s,
                        uint64_t *completed, uint64_t *waves, uint64_t *batched);
 

@@ -9,21 +9,6 @@
 
 namespace vr {
 
-namespace {
-
-struct CnnDesc {
-    u32 C_in, h, w, pad, C_out, k, stride, square;
-    std::vector<double> K, bias, fc_bias;
-    std::vector<BufPtr> fc_hold;     // keeps the weight plaintexts alive
-    const u64* fc_P = nullptr;
-    u64 fc_stride = 0;
-    double fc_scale = 0;
-    u32 fc_out = 0, fc_block = 0;
-    u32 w_out() const { return (w + 2 * pad - k) / stride + 1; }
-    u32 n_in() const { return C_in * w; }
-    u32 n_out() const { return fc_out ? fc_out : C_out * w_out(); }
-};
-
 CnnDesc make_desc(vr_context* ctx, const vr_cnn_desc* d, u32 level_in, hipStream_t s)
 {
     if (d->C_in < 1 || d->C_out < 1 || d->k < 1 || d->stride < 1 || d->pad >= d->k)
@@ -84,6 +69,8 @@ Slab run_cnn(vr_context* ctx, const vr_eval_keys* ek, const CnnDesc& d, const Sl
 
 // Sets the thread's capture pool for the guard's lifetime.  The context's
 // cache is emptied first so the graph's blocks have the device to themselves.
+namespace {
+
 struct CaptureGuard {
     std::shared_ptr<CaptureKeep> keep;
     explicit CaptureGuard(vr_context* ctx)

@@ -32,13 +32,28 @@ double now_ms()
     return duration<double, std::milli>(steady_clock::now().time_since_epoch()).count();
 }
 
+// A registered network: its description with owned copies of the weights
+// (the FC weight plaintexts are the caller's and must outlive the server).
 struct Model {
     u32 C_in, h, w, pad, C_out, k, stride;
     bool square;
-    std::vector<double> K, bias;
+    std::vector<double> K, bias, fc_bias;
+    std::vector<const vr_plaintext*> fc_w;
+    u32 fc_out = 0, fc_block = 0;
     u32 n_cols() const { return C_in * w; }
     u32 w_out() const { return (w + 2 * pad - k) / stride + 1; }
-    u32 n_out() const { return C_out * w_out(); }
+    u32 n_out() const { return fc_out ? fc_out : C_out * w_out(); }
+    u32 levels() const { return 1 + (square ? 1 : 0) + (fc_out ? 1 : 0); }
+    vr_cnn_desc desc() const
+    {
+        vr_cnn_desc d;
+        d.C_in = C_in, d.h = h, d.w = w, d.pad = pad, d.C_out = C_out, d.k = k, d.stride = stride;
+        d.K = K.data(), d.bias = bias.data(), d.square = square ? 1 : 0;
+        d.fc_w = fc_out ? fc_w.data() : nullptr;
+        d.fc_bias = fc_out ? fc_bias.data() : nullptr;
+        d.fc_out = fc_out, d.fc_block = fc_block;
+        return d;
+    }
 };
 
 struct Request {
@@ -107,9 +122,11 @@ size_t request_bytes(vr_context* ctx, const Model& m, u32 level)
         return ((size_t)k.beta * k.next + k.nq + 2 * k.next + 2 * (ctx->K + k.nq)) * N * 8;
     };
     const size_t ct = (size_t)2 * (level + 1) * N * 8;
+    const size_t conv_out = (size_t)m.C_out * m.w_out();
     size_t b = (size_t)m.n_cols() * (ct * (m.k + 1) + ks(level));
-    b += (size_t)m.n_out() * ct * 2;
-    if (m.square) b += (size_t)m.n_out() * (ct * 4 + ks(level - 1));
+    b += conv_out * ct * 2;
+    if (m.square) b += conv_out * (ct * 4 + ks(level - 1));
+    if (m.fc_out) b += (size_t)m.fc_out * (ct * 2 + ks(level - 2));
     return b;
 }
 
@@ -124,11 +141,10 @@ void run_wave(vr_server* srv, Wave& wv, const Model& m, const vr_eval_keys* ek, 
         for (u32 c = 0; c < ncols; c++)
             VR_HIP(hipMemcpyAsync(x.ct(i * ncols + c), wv.reqs[i]->data[c], x.stride * sizeof(u64),
                                   hipMemcpyDeviceToDevice, s));
-    Slab y = conv_slab(ctx, ek, x, nsets, m.C_in, m.w, m.pad, m.K.data(), m.bias.data(), m.C_out,
-                       m.k, m.stride, s);
-    if (m.square) y = layer_square(ctx, ek, y, s);
-    wv.y = y;
-    wv.per_req = m.n_out();
+    const vr_cnn_desc dd = m.desc();
+    CnnDesc d = make_desc(ctx, &dd, r0->level, s);
+    wv.y = run_cnn(ctx, ek, d, x, nsets, s);
+    wv.per_req = d.n_out();
     VR_HIP(hipEventCreateWithFlags(&wv.done, hipEventDisableTiming));
     VR_HIP(hipEventRecord(wv.done, s));
 }
@@ -163,6 +179,7 @@ void retire(vr_server* srv)
             r->ready = nullptr;
             srv->lat_ms.push_back(t - r->t_submit);
             srv->images_done += r->images;
+            if (srv->t_first < 0 || r->t_submit < srv->t_first) srv->t_first = r->t_submit;
             srv->t_last = t;
         }
         (void)hipEventDestroy(wv.done);
@@ -355,9 +372,40 @@ vr_status vr_srv_register_conv_model(vr_server* srv, uint32_t C_in, uint32_t h, 
     REQUIRE(srv && K && bias && model_id, "null argument");
     REQUIRE(C_in >= 1 && C_out >= 1 && k >= 1 && stride >= 1 && pad < k, "bad conv shape");
     REQUIRE(w + 2 * pad >= k && h + 2 * pad >= k, "kernel larger than the padded image");
-    Model m{C_in, h, w, pad, C_out, k, stride, square != 0, {}, {}};
+    Model m;
+    m.C_in = C_in, m.h = h, m.w = w, m.pad = pad, m.C_out = C_out, m.k = k, m.stride = stride;
+    m.square = square != 0;
     m.K.assign(K, K + (size_t)C_out * C_in * k * k);
     m.bias.assign(bias, bias + C_out);
+    std::lock_guard<std::mutex> g(srv->mu);
+    srv->models.push_back(m);
+    *model_id = (u32)srv->models.size() - 1;
+    API_END
+}
+
+vr_status vr_srv_register_model(vr_server* srv, const vr_cnn_desc* d, uint32_t* model_id)
+{
+    if (model_id) *model_id = 0;
+    API_BEGIN
+    REQUIRE(srv && d && model_id && d->K && d->bias, "null argument");
+    REQUIRE(d->C_in >= 1 && d->C_out >= 1 && d->k >= 1 && d->stride >= 1 && d->pad < d->k, "bad conv shape");
+    REQUIRE(d->w + 2 * d->pad >= d->k && d->h + 2 * d->pad >= d->k, "kernel larger than the padded image");
+    Model m;
+    m.C_in = d->C_in, m.h = d->h, m.w = d->w, m.pad = d->pad, m.C_out = d->C_out, m.k = d->k;
+    m.stride = d->stride, m.square = d->square != 0;
+    m.K.assign(d->K, d->K + (size_t)d->C_out * d->C_in * d->k * d->k);
+    m.bias.assign(d->bias, d->bias + d->C_out);
+    if (d->fc_w) {
+        REQUIRE(d->fc_bias && d->fc_out >= 1, "FC needs weights, bias and outputs");
+        REQUIRE(d->fc_block >= 1 && (d->fc_block & (d->fc_block - 1)) == 0 && d->fc_block <= srv->ctx->slots,
+                "FC block must be a power of two <= S");
+        const size_t count = (size_t)d->fc_out * d->C_out * m.w_out();
+        for (size_t i = 0; i < count; i++) REQUIRE(d->fc_w[i], "null weight plaintext");
+        m.fc_w.assign(d->fc_w, d->fc_w + count);
+        m.fc_bias.assign(d->fc_bias, d->fc_bias + d->fc_out);
+        m.fc_out = d->fc_out;
+        m.fc_block = d->fc_block;
+    }
     std::lock_guard<std::mutex> g(srv->mu);
     srv->models.push_back(m);
     *model_id = (u32)srv->models.size() - 1;
@@ -386,7 +434,7 @@ vr_status vr_srv_submit(vr_server* srv, uint64_t session_id, uint32_t model_id,
     }
     r->level = in[0]->level;
     r->scale = in[0]->scale;
-    if (r->level < (m.square ? 2u : 1u)) throw Error(VR_ELEVEL, "not enough levels for the model");
+    if (r->level < m.levels()) throw Error(VR_ELEVEL, "not enough levels for the model");
     r->bytes = request_bytes(srv->ctx, m, r->level);
     if (srv->resident > srv->budget || r->bytes > srv->budget - srv->resident)
         throw Error(VR_EBUSY, "request can never fit the memory budget");
@@ -397,7 +445,6 @@ vr_status vr_srv_submit(vr_server* srv, uint64_t session_id, uint32_t model_id,
     VR_HIP(hipEventCreateWithFlags(&r->ready, hipEventDisableTiming));
     VR_HIP(hipEventRecord(r->ready, srv->ctx->stream));
     r->t_submit = now_ms();
-    if (srv->t_first < 0) srv->t_first = r->t_submit;
     *ticket = r->ticket;
     srv->pending.push_back(r.get());
     srv->reqs[r->ticket] = std::move(r);
@@ -452,6 +499,20 @@ vr_status vr_srv_poll(vr_server* srv, uint64_t ticket, int wait, vr_ciphertext**
     *n_out = r->out.n;
     *ready = 1;
     srv->reqs.erase(it);
+    API_END
+}
+
+vr_status vr_srv_reset_stats(vr_server* srv)
+{
+    API_BEGIN
+    REQUIRE(srv, "null server");
+    std::lock_guard<std::mutex> g(srv->mu);
+    srv->lat_ms.clear();
+    srv->images_done = 0;
+    srv->t_first = -1;
+    srv->t_last = 0;
+    srv->waves = 0;
+    srv->batched_requests = 0;
     API_END
 }
 

@@ -31,6 +31,25 @@ Slab layer_square(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipSt
 // weight plaintexts P[o][i] at P + (o * y.n + i) * p_stride
 Slab fc_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& y, const u64* P, u64 p_stride,
              double p_scale, u32 n_out, const double* bias, u32 block, hipStream_t s);
+// A network (conv, optional x^2, optional FC) with its constants resolved.
+struct CnnDesc {
+    u32 C_in, h, w, pad, C_out, k, stride, square;
+    std::vector<double> K, bias, fc_bias;
+    std::vector<BufPtr> fc_hold;     // keeps the weight plaintexts alive
+    const u64* fc_P = nullptr;
+    u64 fc_stride = 0;
+    double fc_scale = 0;
+    u32 fc_out = 0, fc_block = 0;
+    u32 w_out() const { return (w + 2 * pad - k) / stride + 1; }
+    u32 n_in() const { return C_in * w; }
+    u32 n_out() const { return fc_out ? fc_out : C_out * w_out(); }
+    u32 levels() const { return 1 + square + (fc_out ? 1 : 0); }
+};
+CnnDesc make_desc(vr_context* ctx, const vr_cnn_desc* d, u32 level_in, hipStream_t s);
+// the network on n_sets image sets (slab x, set after set); outputs set after set
+Slab run_cnn(vr_context* ctx, const vr_eval_keys* ek, const CnnDesc& d, const Slab& x, u32 n_sets,
+             hipStream_t s);
+
 // One column-split product C = A B (A_k, Bbar_k column slabs of n each).
 struct MatReq {
     Slab A, B;

@@ -122,8 +122,10 @@ _SIGS = {
     "vr_srv_register_session": [P, P, ctypes.POINTER(U64)],
     "vr_srv_register_conv_model": [P, U32, U32, U32, U32, P, P, U32, U32, U32, U32,
                                    ctypes.POINTER(U32)],
+    "vr_srv_register_model": [P, P, ctypes.POINTER(U32)],
     "vr_srv_submit": [P, U64, U32, PP, SZ, U32, ctypes.POINTER(U64)],
     "vr_srv_cancel": [P, U64],
+    "vr_srv_reset_stats": [P],
     "vr_srv_poll": [P, U64, ctypes.c_int, PP, SZ, ctypes.POINTER(SZ), ctypes.POINTER(ctypes.c_int)],
     "vr_srv_stats": [P, ctypes.POINTER(DBL), ctypes.POINTER(DBL), ctypes.POINTER(DBL),
                      ctypes.POINTER(U64), ctypes.POINTER(U64), ctypes.POINTER(U64)],
@@ -533,6 +535,14 @@ class Server:
         self._models[mid.value] = C_out * ((w + 2 * pad - k) // stride + 1)
         return mid.value
 
+    def register_model(self, net):
+        """A vr.CNN network (conv, x^2, FC); the network object is kept alive."""
+        mid = U32()
+        _check(lib.vr_srv_register_model(self.h, ctypes.byref(net.desc), ctypes.byref(mid)))
+        self._models[mid.value] = net.outputs_per_set()
+        self._nets = getattr(self, "_nets", []) + [net]
+        return mid.value
+
     def submit(self, session, model, cols, n_images):
         t = U64()
         _check(lib.vr_srv_submit(self.h, session, model, _ptr_array(cols), len(cols), n_images,
@@ -552,6 +562,9 @@ class Server:
         if not ready.value:
             return None
         return [Ciphertext(arr[i], self.ctx) for i in range(n.value)]
+
+    def reset_stats(self):
+        _check(lib.vr_srv_reset_stats(self.h))
 
     def stats(self):
         p50, p99, ips = DBL(), DBL(), DBL()

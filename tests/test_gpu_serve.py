@@ -193,3 +193,36 @@ def test_chunked_key_switching_identical(small):
         g.set_tuning("switch_chunk", "0")
     for j, (a, b) in enumerate(zip(got, ref)):
         same_limbs(a, b, "chunked out %d" % j)
+
+
+def test_server_full_network_model(small):
+    """A registered conv + x^2 + FC network: served results identical to the
+    whole-network call on each request alone."""
+    from paper_2512_18646_amd import vr
+    o, ok, g, gk = small
+    S = SHAPE
+    rng = np.random.default_rng(81)
+    _, K, bias = draw(rng)
+    Hp = Ly.image_block(S["h"], S["pad"])
+    wo = Ly.conv_out_size(S["w"], S["pad"], S["k"], S["s"])
+    ho = Ly.conv_out_size(S["h"], S["pad"], S["k"], S["s"])
+    pts = g.encode_fc_weights(rng.normal(0, 0.05, (4, 3, ho, wo)), S["s"], Hp, 1)
+    net = vr.CNN(S["Ci"], S["h"], S["w"], S["pad"], K, bias, S["s"], square=True, fc_w=pts,
+                 fc_bias=rng.normal(0, 0.05, 4), fc_block=Hp)
+    srv = vr.Server(g, 8 << 30, max_batch=4)
+    sid = srv.register_session(gk)
+    mid = srv.register_model(net)
+    inputs = [g.encrypt_columns(gk, rng.uniform(0, 1, (S["B"], S["Ci"], S["h"], S["w"])), S["pad"], 3,
+                                400 + i, 0) for i in range(5)]
+    tickets = [srv.submit(sid, mid, c, S["B"]) for c in inputs]
+    outs = [srv.poll(t, mid) for t in tickets]
+    low = g.encrypt_columns(gk, rng.uniform(0, 1, (S["B"], S["Ci"], S["h"], S["w"])), S["pad"], 2, 499, 0)
+    with pytest.raises(vr.VRError) as e:
+        srv.submit(sid, mid, low, S["B"])             # conv, x^2 and FC need three levels
+    assert e.value.code == vr.VR_ELEVEL
+    srv.close()
+    for i, (c, got) in enumerate(zip(inputs, outs)):
+        ref = net.forward(g, gk, c)
+        assert len(got) == len(ref) == 4
+        for j, (a, b) in enumerate(zip(got, ref)):
+            same_limbs(a, b, "request %d logit %d" % (i, j))
