@@ -202,32 +202,31 @@ __global__ __launch_bounds__(256) void k_base_convert_mfma(ConvArgs a, const u64
     }
 }
 
-// One block = 256 consecutive outputs of extended limb e.  With a Galois
-// element g != 1 the block's sources form one contiguous 256-word chunk of
-// every digit (the top index bits of the bit-reversed order map among
-// themselves under X -> X^g), which the block stages in LDS with coalesced
-// loads before the per-thread gather (for N < 256 the chunk is the limb).
+// One block = 256 consecutive source words of extended limb e.  With a Galois
+// element g != 1 output t reads source sigma(t); the block's sources form one
+// aligned 256-word chunk whose outputs t = sigma^-1(s) (g_inv = g^-1 mod 2N)
+// form another (the top index bits of the bit-reversed order map among
+// themselves under X -> X^g).  So each thread loads its source words
+// coalesced, takes the key at its output index (loaded once per block, the
+// key being shared by every ciphertext of the batch), and writes its output
+// within that chunk: no staging and no barrier per ciphertext.
 template <int MAXB>
 __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_stride, u32 n_ct,
                                                       const u64* key, u32 nmod, u32 level,
-                                                      u32 next, u32 beta, u32 L, u32 log_n, u32 g,
+                                                      u32 next, u32 beta, u32 L, u32 log_n, u32 g_inv,
                                                       u64* U, u64 u_stride, const ModQ* mq)
 {
-    __shared__ u64 stage[MAXB * kThreads];
     const u32 n = 1u << log_n;
-    const u32 csize = n < (u32)kThreads ? n : (u32)kThreads;
-    const u32 t = blockIdx.x * kThreads + threadIdx.x;
-    const bool active = t < n;
+    const u32 s = blockIdx.x * kThreads + threadIdx.x;
+    if (s >= n) return;
     const u32 e = blockIdx.y;
     const u32 mod = e <= level ? e : L + 1 + (e - level - 1);
     const ModQ m = mq[mod];
-    const bool perm = g != 1;
-    const u32 src = perm && active ? galois_src(t, g, log_n) : t;
-    const u32 chunk = perm ? (galois_src(blockIdx.x * kThreads, g, log_n) & ~(csize - 1)) : 0;
+    const u32 t = g_inv != 1 ? galois_src(s, g_inv, log_n) : s;
     u64 kb[MAXB], ka[MAXB];
 #pragma unroll
     for (int j = 0; j < MAXB; j++) {
-        if (j < (int)beta && active) {
+        if (j < (int)beta) {
             kb[j] = key[((size_t)(2 * j) * nmod + mod) * n + t];
             ka[j] = key[((size_t)(2 * j + 1) * nmod + mod) * n + t];
         }
@@ -236,23 +235,12 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
     const u32 per = (n_ct + gridDim.z - 1) / gridDim.z;
     const u32 c_lo = blockIdx.z * per, c_hi = min(n_ct, c_lo + per);
     for (u32 c = c_lo; c < c_hi; c++) {
-        const u64* xc = X + (size_t)c * x_stride + (size_t)e * n;
-        if (perm) {
-            __syncthreads();
-            if (threadIdx.x < csize) {
-#pragma unroll
-                for (int j = 0; j < MAXB; j++)
-                    if (j < (int)beta)
-                        stage[j * kThreads + threadIdx.x] = xc[(size_t)j * next * n + chunk + threadIdx.x];
-            }
-            __syncthreads();
-        }
-        if (!active) continue;
+        const u64* xc = X + (size_t)c * x_stride + (size_t)e * n + s;
         u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
 #pragma unroll
         for (int j = 0; j < MAXB; j++) {
             if (j < (int)beta) {
-                u64 xv = perm ? stage[j * kThreads + (src - chunk)] : xc[(size_t)j * next * n + t];
+                const u64 xv = xc[(size_t)j * next * n];
                 mac128(h0, l0, xv, kb[j]);
                 mac128(h1, l1, xv, ka[j]);
             }
@@ -563,18 +551,29 @@ void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, u32 n_ct
     if (groups > n_ct) groups = n_ct;
     if (groups < 1) groups = 1;
     dim3 grid((ctx->n + kThreads - 1) / kThreads, k.next, groups);
+    // inverse of g modulo 2N: the odd residues mod 2N = 2^(log N + 1) have
+    // exponent N/2, so g^-1 = g^(N/2 - 1)
+    const u64 two_n = 2ull * ctx->n;
+    u32 g_inv = 1;
+    if (g != 1) {
+        u64 r = 1;
+        for (u64 x = g % two_n, ee = two_n / 4 - 1; ee; ee >>= 1, x = x * x % two_n)
+            if (ee & 1) r = r * x % two_n;
+        if (r * g % two_n != 1) throw Error(VR_EINVAL, "key switching: no inverse Galois element");
+        g_inv = (u32)r;
+    }
     ProfScope prof(ctx, kProfKsInner, s, (u64)n_ct * k.next);
     if (k.beta <= 4)
         hipLaunchKernelGGL((k_ks_inner<4>), grid, dim3(kThreads), 0, s, X, x_stride, n_ct, key,
-                           ctx->nmod(), level, k.next, k.beta, ctx->L, ctx->log_n, g, U, u_stride,
+                           ctx->nmod(), level, k.next, k.beta, ctx->L, ctx->log_n, g_inv, U, u_stride,
                            ctx->d_modq);
     else if (k.beta <= 8)
         hipLaunchKernelGGL((k_ks_inner<8>), grid, dim3(kThreads), 0, s, X, x_stride, n_ct, key,
-                           ctx->nmod(), level, k.next, k.beta, ctx->L, ctx->log_n, g, U, u_stride,
+                           ctx->nmod(), level, k.next, k.beta, ctx->L, ctx->log_n, g_inv, U, u_stride,
                            ctx->d_modq);
     else if (k.beta <= 16)
         hipLaunchKernelGGL((k_ks_inner<16>), grid, dim3(kThreads), 0, s, X, x_stride, n_ct, key,
-                           ctx->nmod(), level, k.next, k.beta, ctx->L, ctx->log_n, g, U, u_stride,
+                           ctx->nmod(), level, k.next, k.beta, ctx->L, ctx->log_n, g_inv, U, u_stride,
                            ctx->d_modq);
     else
         throw Error(VR_EINVAL, "key switching: more than 16 digits");

@@ -93,6 +93,66 @@ __device__ __forceinline__ u64 conv_one(u64 v, u64 cq, u64 q, u64 one_s)
     return neg ? neg_mod(x, q) : x;
 }
 
+// Whether every lane of a wave has the same twiddle prefix in a round: the
+// group's block index H is common when the strided groups of a workgroup do
+// not cross a row (lo_bits >= log_c) or a wave stays in one group column
+// (log_g - R >= 6), and the in-group prefix hi is common when a wave's 64
+// lanes differ only below it (low_bits >= 6) or it is empty (sg0 = 0).
+// Then the twiddles are loaded once per wave through the scalar cache.
+__device__ __forceinline__ bool wave_uniform_prefix(u32 lo_bits, u32 log_c, u32 log_g, u32 R,
+                                                    u32 low_bits, u32 sg0)
+{
+    return (lo_bits >= log_c || log_g - R >= 6) && (low_bits >= 6 || sg0 == 0);
+}
+
+template <int R, bool INV, bool UNI>
+__device__ __forceinline__ void int_butterflies(u64 (&x)[1 << R], const ulonglong2* twp, u32 hprefix,
+                                                u32 s_pass, u32 sg0, u64 q)
+{
+    if (UNI) hprefix = __builtin_amdgcn_readfirstlane(hprefix);
+    const u64 q2 = 2 * q;
+    if (!INV) {
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            const int half = 1 << (R - 1 - k);
+            const u32 tb = (1u << (s_pass + sg0 + k)) + (hprefix << k);
+#pragma unroll
+            for (int j = 0; j < (1 << k); j++) {
+                const ulonglong2 t = twp[tb + j];
+                const u64 wv = t.x, wsv = t.y;
+#pragma unroll
+                for (int i = 0; i < half; i++) {
+                    const int m1 = (j << (R - k)) + i, m2 = m1 + half;
+                    u64 X = x[m1];
+                    X = X >= q2 ? X - q2 : X;
+                    u64 T = shoup_lazy(x[m2], wv, wsv, q);
+                    x[m1] = X + T;
+                    x[m2] = X + q2 - T;
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = R - 1; k >= 0; k--) {
+            const int half = 1 << (R - 1 - k);
+            const u32 tb = (1u << (s_pass + sg0 + k)) + (hprefix << k);
+#pragma unroll
+            for (int j = 0; j < (1 << k); j++) {
+                const ulonglong2 t = twp[tb + j];
+                const u64 wv = t.x, wsv = t.y;
+#pragma unroll
+                for (int i = 0; i < half; i++) {
+                    const int m1 = (j << (R - k)) + i, m2 = m1 + half;
+                    u64 X = x[m1], Y = x[m2];
+                    u64 S = X + Y;
+                    x[m1] = S >= q2 ? S - q2 : S;
+                    x[m2] = shoup_lazy(X + q2 - Y, wv, wsv, q);
+                }
+            }
+        }
+    }
+}
+
 // One round of R stages (local stages sg0 .. sg0+R-1 of the pass) over every
 // 2^R-element group of the tile.
 template <int R, bool INV, int THREADS>
@@ -117,6 +177,7 @@ __device__ __forceinline__ void ntt_round(u64* lds, const u64* tw, const ModQ& m
         // stage k of the round uses the 2^k consecutive twiddles starting at
         // 2^(s_pass + sg0 + k) + (hprefix << k)
         const ulonglong2* twp = (const ulonglong2*)tw;
+        const bool uni = wave_uniform_prefix(lo_bits, log_c, log_g, R, low_bits, sg0);
         u64 x[E];
         if (io.gsrc) {
 #pragma unroll
@@ -128,46 +189,10 @@ __device__ __forceinline__ void ntt_round(u64* lds, const u64* tw, const ModQ& m
 #pragma unroll
             for (int m = 0; m < E; m++) x[m] = lds[pad(base + ((u32)m << low_bits))];
         }
-        if (!INV) {
-#pragma unroll
-            for (int k = 0; k < R; k++) {
-                const int half = 1 << (R - 1 - k);
-                const u32 tb = (1u << (s_pass + sg0 + k)) + (hprefix << k);
-#pragma unroll
-                for (int j = 0; j < (1 << k); j++) {
-                    const ulonglong2 t = twp[tb + j];
-                    const u64 wv = t.x, wsv = t.y;
-#pragma unroll
-                    for (int i = 0; i < half; i++) {
-                        const int m1 = (j << (R - k)) + i, m2 = m1 + half;
-                        u64 X = x[m1];
-                        X = X >= q2 ? X - q2 : X;
-                        u64 T = shoup_lazy(x[m2], wv, wsv, q);
-                        x[m1] = X + T;
-                        x[m2] = X + q2 - T;
-                    }
-                }
-            }
-        } else {
-#pragma unroll
-            for (int k = R - 1; k >= 0; k--) {
-                const int half = 1 << (R - 1 - k);
-                const u32 tb = (1u << (s_pass + sg0 + k)) + (hprefix << k);
-#pragma unroll
-                for (int j = 0; j < (1 << k); j++) {
-                    const ulonglong2 t = twp[tb + j];
-                    const u64 wv = t.x, wsv = t.y;
-#pragma unroll
-                    for (int i = 0; i < half; i++) {
-                        const int m1 = (j << (R - k)) + i, m2 = m1 + half;
-                        u64 X = x[m1], Y = x[m2];
-                        u64 S = X + Y;
-                        x[m1] = S >= q2 ? S - q2 : S;
-                        x[m2] = shoup_lazy(X + q2 - Y, wv, wsv, q);
-                    }
-                }
-            }
-        }
+        if (uni)
+            int_butterflies<R, INV, true>(x, twp, hprefix, s_pass, sg0, q);
+        else
+            int_butterflies<R, INV, false>(x, twp, hprefix, s_pass, sg0, q);
         if (io.gdst) {
 #pragma unroll
             for (int m = 0; m < E; m++) {
@@ -204,6 +229,58 @@ __device__ __forceinline__ double fbal(double x, double q, double qinv)
 }
 #pragma clang fp contract(on)
 
+template <int R, bool INV, bool UNI>
+__device__ __forceinline__ void fp_butterflies(double (&x)[1 << R], const double* tw, u32 hprefix,
+                                               u32 s_pass, u32 sg0, double q, double qinv, bool every2)
+{
+    constexpr int E = 1 << R;
+    if (UNI) hprefix = __builtin_amdgcn_readfirstlane(hprefix);
+    if (!INV) {
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            const int half = 1 << (R - 1 - k);
+            const u32 tb = (1u << (s_pass + sg0 + k)) + (hprefix << k);
+#pragma unroll
+            for (int j = 0; j < (1 << k); j++) {
+                const double w = tw[tb + j];
+#pragma unroll
+                for (int i = 0; i < half; i++) {
+                    const int m1 = (j << (R - k)) + i, m2 = m1 + half;
+                    const double X = x[m1];
+                    const double T = fmulmod(x[m2], w, q, qinv);
+                    x[m1] = X + T;
+                    x[m2] = X - T;
+                }
+            }
+            if (every2 && (k & 1) && k != R - 1) {
+#pragma unroll
+                for (int m = 0; m < E; m++) x[m] = fbal(x[m], q, qinv);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = R - 1; k >= 0; k--) {
+            const int half = 1 << (R - 1 - k);
+            const u32 tb = (1u << (s_pass + sg0 + k)) + (hprefix << k);
+#pragma unroll
+            for (int j = 0; j < (1 << k); j++) {
+                const double w = tw[tb + j];
+#pragma unroll
+                for (int i = 0; i < half; i++) {
+                    const int m1 = (j << (R - k)) + i, m2 = m1 + half;
+                    const double X = x[m1], Y = x[m2];
+                    x[m1] = X + Y;
+                    x[m2] = fmulmod(X - Y, w, q, qinv);
+                }
+            }
+            if (((R - k) & 1) == 0 && k != 0) {
+#pragma unroll
+                for (int m = 0; m < E; m++) x[m] = fbal(x[m], q, qinv);
+            }
+        }
+    }
+}
+
 template <int R, bool INV, int THREADS>
 __device__ __forceinline__ void ntt_round_fp(double* lds, const double* tw, double q, double qinv,
                                              bool every2, u32 log_g, u32 log_c, u32 sg0,
@@ -223,6 +300,7 @@ __device__ __forceinline__ void ntt_round_fp(double* lds, const double* tw, doub
         const u32 base = c * G + (hi << (log_g - sg0)) + lo;
         const u32 H = (g0 + c) >> lo_bits;
         const u32 hprefix = (H << sg0) | hi;
+        const bool uni = wave_uniform_prefix(lo_bits, log_c, log_g, R, low_bits, sg0);
         double x[E];
         if (io.gsrc) {
 #pragma unroll
@@ -235,50 +313,10 @@ __device__ __forceinline__ void ntt_round_fp(double* lds, const double* tw, doub
 #pragma unroll
             for (int m = 0; m < E; m++) x[m] = lds[pad(base + ((u32)m << low_bits))];
         }
-        if (!INV) {
-#pragma unroll
-            for (int k = 0; k < R; k++) {
-                const int half = 1 << (R - 1 - k);
-                const u32 tb = (1u << (s_pass + sg0 + k)) + (hprefix << k);
-#pragma unroll
-                for (int j = 0; j < (1 << k); j++) {
-                    const double w = tw[tb + j];
-#pragma unroll
-                    for (int i = 0; i < half; i++) {
-                        const int m1 = (j << (R - k)) + i, m2 = m1 + half;
-                        const double X = x[m1];
-                        const double T = fmulmod(x[m2], w, q, qinv);
-                        x[m1] = X + T;
-                        x[m2] = X - T;
-                    }
-                }
-                if (every2 && (k & 1) && k != R - 1) {
-#pragma unroll
-                    for (int m = 0; m < E; m++) x[m] = fbal(x[m], q, qinv);
-                }
-            }
-        } else {
-#pragma unroll
-            for (int k = R - 1; k >= 0; k--) {
-                const int half = 1 << (R - 1 - k);
-                const u32 tb = (1u << (s_pass + sg0 + k)) + (hprefix << k);
-#pragma unroll
-                for (int j = 0; j < (1 << k); j++) {
-                    const double w = tw[tb + j];
-#pragma unroll
-                    for (int i = 0; i < half; i++) {
-                        const int m1 = (j << (R - k)) + i, m2 = m1 + half;
-                        const double X = x[m1], Y = x[m2];
-                        x[m1] = X + Y;
-                        x[m2] = fmulmod(X - Y, w, q, qinv);
-                    }
-                }
-                if (((R - k) & 1) == 0 && k != 0) {
-#pragma unroll
-                    for (int m = 0; m < E; m++) x[m] = fbal(x[m], q, qinv);
-                }
-            }
-        }
+        if (uni)
+            fp_butterflies<R, INV, true>(x, tw, hprefix, s_pass, sg0, q, qinv, every2);
+        else
+            fp_butterflies<R, INV, false>(x, tw, hprefix, s_pass, sg0, q, qinv, every2);
         if (io.gdst) {
 #pragma unroll
             for (int m = 0; m < E; m++) {
