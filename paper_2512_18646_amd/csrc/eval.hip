@@ -279,8 +279,13 @@ void rescale_dense(vr_context* ctx, const u64* in, u64* out, u32 n_polys, u32 le
     ls.slot0 = level;
     ls.out_dense = 1;
     ntt_inverse(ctx, ls, s);
-    launch_rescale_spread(ctx, r, last, n_polys, level, s);
-    ntt_forward(ctx, poly_limbs(r, r, n_polys, level, (u64)level * n, (int)level), s);
+    // centred last limb reduced to every other modulus, as the NTT loads it
+    LimbSet lr = poly_limbs(r, r, n_polys, level, (u64)level * n, (int)level);
+    lr.cv_src = last;
+    lr.cv_ct_stride = n;
+    lr.cv_beta = 1;
+    lr.cv_mod0 = level;
+    ntt_forward(ctx, lr, s);
     launch_rescale_finish(ctx, out, in, r, n_polys, level, s);
 }
 

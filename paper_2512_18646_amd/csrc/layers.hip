@@ -141,18 +141,33 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
         u64 acc[kMaxFilters];
 #pragma unroll
         for (int f = 0; f < kMaxFilters; f++) acc[f] = 0;
-        for (u32 k = a; k < b; k++) {
-            const Term tm = terms[k];
-            const u32 u = tm.in_idx / n_x, j = tm.in_idx - u * n_x;
-            const u64* src = u == 0 ? x + (size_t)(set * n_x + j) * stride
-                                    : r + ((size_t)(u - 1) * n_x * n_sets + set * n_x + j) * stride;
-            const u64 xv = src[(size_t)row * n + t];
+        // eight terms at a time: their input words are loaded together so the
+        // loads overlap instead of each waiting on the previous one
+        for (u32 k0 = a; k0 < b; k0 += 8) {
+            u64 xv[8];
+            u32 wrow[8];
 #pragma unroll
-            for (int f = 0; f < kMaxFilters; f++) {
-                if (f < (int)nf) {
-                    const size_t wi = (size_t)(tm.w_idx + (f0 + f) * w_fstride) * nl + l;
-                    u64 v = acc[f] + shoup_lazy(xv, w[wi], ws[wi], q);
-                    acc[f] = v >= q2 ? v - q2 : v;
+            for (int i = 0; i < 8; i++) {
+                if (k0 + i < b) {
+                    const Term tm = terms[k0 + i];
+                    const u32 u = tm.in_idx / n_x, j = tm.in_idx - u * n_x;
+                    const u64* src = u == 0 ? x + (size_t)(set * n_x + j) * stride
+                                            : r + ((size_t)(u - 1) * n_x * n_sets + set * n_x + j) * stride;
+                    xv[i] = src[(size_t)row * n + t];
+                    wrow[i] = tm.w_idx;
+                }
+            }
+#pragma unroll
+            for (int i = 0; i < 8; i++) {
+                if (k0 + i < b) {
+#pragma unroll
+                    for (int f = 0; f < kMaxFilters; f++) {
+                        if (f < (int)nf) {
+                            const size_t wi = (size_t)(wrow[i] + (f0 + f) * w_fstride) * nl + l;
+                            u64 v = acc[f] + shoup_lazy(xv[i], w[wi], ws[wi], q);
+                            acc[f] = v >= q2 ? v - q2 : v;
+                        }
+                    }
                 }
             }
         }
