@@ -312,10 +312,10 @@ def serving_n16_bench(vr, level=3, n_sessions=8, n_warm=20, n_meas=100, loads=(0
         srv.poll(srv.submit(sids[0], k["mid"], k["cols"][0], 1), k["mid"])
     t0 = time.perf_counter()                     # saturation: a burst
     srv.reset_stats()
-    run(24, 0)
+    run(48, 0)
     burst_s = time.perf_counter() - t0
     sat = srv.stats()
-    sat_req_s = 24 / burst_s
+    sat_req_s = 48 / burst_s
     levels = []
     for load in loads:
         run(n_warm, load * sat_req_s)
