@@ -48,6 +48,7 @@ struct NttPass {
     u32 log_n, L;
     u32 s0, log_g, log_c;
     u32 first, last;
+    u32 max_r;          // stages per round (4, or 5 with 32 elements per thread)
 };
 
 __device__ __forceinline__ void limb_addr(const LimbSet& ls, u32 r, u32 n, u32 L,
@@ -227,6 +228,34 @@ __device__ __forceinline__ double fbal(double x, double q, double qinv)
 {
     return __fma_rn(-rint(x * qinv), q, x);
 }
+
+// Exact conversions between integers below 2^52 and doubles through the
+// mantissa of 2^52 + v (one add and one bit operation instead of the generic
+// conversion sequences).
+constexpr double kTwo52 = 4503599627370496.0;
+__device__ __forceinline__ double u2f(u64 v)
+{
+    return __longlong_as_double((long long)(v | 0x4330000000000000ull)) - kTwo52;
+}
+__device__ __forceinline__ u64 f2u(double y)   // y an integer in [0, 2^52)
+{
+    return (u64)__double_as_longlong(y + kTwo52) & 0xFFFFFFFFFFFFFull;
+}
+
+// canonical residue in [0, q) -> balanced double in (-q/2, q/2]
+__device__ __forceinline__ double to_bal(u64 v, u64 q, double qd)
+{
+    const double d = u2f(v);
+    return v > (q >> 1) ? d - qd : d;
+}
+
+// balanced double (any |x| < 2^52.7) -> canonical residue in [0, q)
+__device__ __forceinline__ u64 to_canon(double x, double q, double qinv)
+{
+    const u64 v = f2u(fbal(x, q, qinv) + q);   // in [q/2 - 1, 3q/2 + 1]
+    const u64 qi = f2u(q);
+    return v >= qi ? v - qi : v;
+}
 #pragma clang fp contract(on)
 
 template <int R, bool INV, bool UNI>
@@ -307,7 +336,7 @@ __device__ __forceinline__ void ntt_round_fp(double* lds, const double* tw, doub
             for (int m = 0; m < E; m++) {
                 u64 v = io.gsrc[base + ((u32)m << low_bits)];
                 if (io.cq) v = conv_one(v, io.cq, qi, io.t_one_s);
-                x[m] = v > qi / 2 ? -(double)(qi - v) : (double)v;
+                x[m] = to_bal(v, qi, q);
             }
         } else {
 #pragma unroll
@@ -320,10 +349,8 @@ __device__ __forceinline__ void ntt_round_fp(double* lds, const double* tw, doub
         if (io.gdst) {
 #pragma unroll
             for (int m = 0; m < E; m++) {
-                double y = INV ? fbal(fmulmod(x[m], ninv_f, q, qinv), q, qinv) : fbal(x[m], q, qinv);
-                y = y < 0.0 ? y + q : y;
-                const u64 v = (u64)y;
-                io.gdst[base + ((u32)m << low_bits)] = v >= qi ? v - qi : v;
+                const double y = INV ? fmulmod(x[m], ninv_f, q, qinv) : x[m];
+                io.gdst[base + ((u32)m << low_bits)] = to_canon(y, q, qinv);
             }
         } else {
 #pragma unroll
@@ -332,7 +359,7 @@ __device__ __forceinline__ void ntt_round_fp(double* lds, const double* tw, doub
     }
 }
 
-template <bool INV, int THREADS>
+template <bool INV, int THREADS, bool R5>
 __device__ __forceinline__ void run_round_fp(u32 r, double* lds, const double* tw, double q,
                                              double qinv, bool every2, u32 log_g, u32 log_c,
                                              u32 sg0, u32 s_pass, u32 g0, u32 lo_bits, RoundIO io,
@@ -342,6 +369,9 @@ __device__ __forceinline__ void run_round_fp(u32 r, double* lds, const double* t
     ntt_round_fp<RR, INV, THREADS>(lds, tw, q, qinv, every2, log_g, log_c, sg0, s_pass, g0, lo_bits, \
                                    io, ninv_f)
     switch (r) {
+    case 5:
+        if constexpr (R5) VR_FP_ROUND(5);
+        break;
     case 4: VR_FP_ROUND(4); break;
     case 3: VR_FP_ROUND(3); break;
     case 2: VR_FP_ROUND(2); break;
@@ -350,12 +380,30 @@ __device__ __forceinline__ void run_round_fp(u32 r, double* lds, const double* t
 #undef VR_FP_ROUND
 }
 
-template <bool INV, int THREADS>
+template <bool INV, int THREADS, bool R5>
 __device__ __forceinline__ void run_round(u32 r, u64* lds, const u64* tw, const ModQ& mq, u32 log_g,
                                           u32 log_c, u32 sg0, u32 s_pass, u32 g0, u32 lo_bits,
                                           RoundIO io)
 {
     switch (r) {
+    case 5:
+        // the integer butterflies would spill with 32 words per thread: four
+        // stages, then one (the block is uniformly on this path)
+        if constexpr (R5) {
+            RoundIO a = io, b = io;
+            a.gdst = nullptr;
+            b.gsrc = nullptr;
+            if (!INV) {
+                ntt_round<4, INV, THREADS>(lds, tw, mq, log_g, log_c, sg0, s_pass, g0, lo_bits, a);
+                __syncthreads();
+                ntt_round<1, INV, THREADS>(lds, tw, mq, log_g, log_c, sg0 + 4, s_pass, g0, lo_bits, b);
+            } else {
+                ntt_round<4, INV, THREADS>(lds, tw, mq, log_g, log_c, sg0 + 1, s_pass, g0, lo_bits, a);
+                __syncthreads();
+                ntt_round<1, INV, THREADS>(lds, tw, mq, log_g, log_c, sg0, s_pass, g0, lo_bits, b);
+            }
+        }
+        break;
     case 4: ntt_round<4, INV, THREADS>(lds, tw, mq, log_g, log_c, sg0, s_pass, g0, lo_bits, io); break;
     case 3: ntt_round<3, INV, THREADS>(lds, tw, mq, log_g, log_c, sg0, s_pass, g0, lo_bits, io); break;
     case 2: ntt_round<2, INV, THREADS>(lds, tw, mq, log_g, log_c, sg0, s_pass, g0, lo_bits, io); break;
@@ -363,7 +411,7 @@ __device__ __forceinline__ void run_round(u32 r, u64* lds, const u64* tw, const 
     }
 }
 
-template <int THREADS, bool INV, bool DIRECT>
+template <int THREADS, bool INV, bool DIRECT, bool R5>
 __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
 {
     extern __shared__ u64 lds[];
@@ -410,7 +458,7 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
             if (cq) x = conv_one(x, cq, q, m.one_s);
             // first pass of the FP64 path: canonical uint64 -> balanced double;
             // later passes read the balanced doubles the previous pass stored
-            if (fp && p.first) x = __double_as_longlong(x > q / 2 ? -(double)(q - x) : (double)x);
+            if (fp && p.first) x = __double_as_longlong(to_bal(x, q, qd));
             lds[pad(c * G + v)] = x;
         }
         __syncthreads();
@@ -423,22 +471,22 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
         const bool every2 = q >= (1ull << 50);
         if (!INV) {
             for (u32 sg0 = 0; sg0 < p.log_g;) {
-                u32 rr = p.log_g - sg0 < 4 ? p.log_g - sg0 : 4;
+                u32 rr = p.log_g - sg0 < p.max_r ? p.log_g - sg0 : p.max_r;
                 RoundIO io;
                 if (direct && sg0 == 0) io.gsrc = src, io.cq = cq, io.t_one_s = m.one_s;
                 if (direct && sg0 + rr == p.log_g) io.gdst = dst;
-                run_round_fp<false, THREADS>(rr, ldf, twf, qd, qinv, every2, p.log_g, p.log_c, sg0,
+                run_round_fp<false, THREADS, R5>(rr, ldf, twf, qd, qinv, every2, p.log_g, p.log_c, sg0,
                                              p.s0, g0, lo_bits, io, ninv_f);
                 sg0 += rr;
                 __syncthreads();
             }
         } else {
             for (u32 top = p.log_g; top > 0;) {
-                u32 rr = top < 4 ? top : 4;
+                u32 rr = top < p.max_r ? top : p.max_r;
                 RoundIO io;
                 if (direct && top == p.log_g) io.gsrc = src;
                 if (direct && top == rr) io.gdst = dst;
-                run_round_fp<true, THREADS>(rr, ldf, twf, qd, qinv, true, p.log_g, p.log_c, top - rr,
+                run_round_fp<true, THREADS, R5>(rr, ldf, twf, qd, qinv, true, p.log_g, p.log_c, top - rr,
                                             p.s0, g0, lo_bits, io, ninv_f);
                 top -= rr;
                 __syncthreads();
@@ -448,21 +496,21 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
         const u64* tw = p.tw + (size_t)mod * n * 2;
         if (!INV) {
             for (u32 sg0 = 0; sg0 < p.log_g;) {
-                u32 rr = p.log_g - sg0 < 4 ? p.log_g - sg0 : 4;
+                u32 rr = p.log_g - sg0 < p.max_r ? p.log_g - sg0 : p.max_r;
                 RoundIO io;
                 if (direct && sg0 == 0) io.gsrc = src, io.cq = cq, io.t_one_s = m.one_s;
                 if (direct && sg0 + rr == p.log_g) io.gdst = dst;
-                run_round<false, THREADS>(rr, lds, tw, m, p.log_g, p.log_c, sg0, p.s0, g0, lo_bits, io);
+                run_round<false, THREADS, R5>(rr, lds, tw, m, p.log_g, p.log_c, sg0, p.s0, g0, lo_bits, io);
                 sg0 += rr;
                 __syncthreads();
             }
         } else {
             for (u32 top = p.log_g; top > 0;) {
-                u32 rr = top < 4 ? top : 4;
+                u32 rr = top < p.max_r ? top : p.max_r;
                 RoundIO io;
                 if (direct && top == p.log_g) io.gsrc = src;
                 if (direct && top == rr) io.gdst = dst;
-                run_round<true, THREADS>(rr, lds, tw, m, p.log_g, p.log_c, top - rr, p.s0, g0, lo_bits,
+                run_round<true, THREADS, R5>(rr, lds, tw, m, p.log_g, p.log_c, top - rr, p.s0, g0, lo_bits,
                                          io);
                 top -= rr;
                 __syncthreads();
@@ -482,10 +530,8 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
         if (fp) {
             if (p.last) {
                 double y = __longlong_as_double(x);
-                if (INV) y = fbal(fmulmod(y, ninv_f, qd, qinv), qd, qinv);
-                y = y < 0.0 ? y + qd : y;
-                x = (u64)y;
-                x = x >= q ? x - q : x;
+                if (INV) y = fmulmod(y, ninv_f, qd, qinv);
+                x = to_canon(y, qd, qinv);
             }
         } else if (p.last) {
             if (!INV) {
@@ -505,6 +551,7 @@ struct PassCfg {
     u32 s0, log_g, log_c;
     u32 direct = 0;    // whole-limb pass with global first/last rounds
     u32 div = 16;      // tile words per thread
+    u32 max_r = 4;     // stages per round
 };
 
 std::vector<PassCfg> default_plan(u32 log_n)
@@ -525,6 +572,7 @@ std::vector<std::vector<PassCfg>> candidates(u32 log_n)
         if (log_n >= 10) {
             if (log_n <= 13) out.push_back({{0, log_n, 0, 1, 16}});
             out.push_back({{0, log_n, 0, 1, 32}});
+            if (log_n >= 13) out.push_back({{0, log_n, 0, 1, 32, 5}});   // rounds of five stages
         }
     }
     if (log_n < 10) return out;
@@ -540,15 +588,15 @@ std::vector<std::vector<PassCfg>> candidates(u32 log_n)
     return out;
 }
 
-template <int T, bool INV, bool DIRECT>
+template <int T, bool INV, bool DIRECT, bool R5 = false>
 void launch_kernel(const NttPass& p, u32 blocks, size_t shmem, hipStream_t s)
 {
     static std::once_flag attr;
     std::call_once(attr, [] {
-        (void)hipFuncSetAttribute((const void*)k_ntt_pass<T, INV, DIRECT>,
+        (void)hipFuncSetAttribute((const void*)k_ntt_pass<T, INV, DIRECT, R5>,
                                   hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
     });
-    hipLaunchKernelGGL((k_ntt_pass<T, INV, DIRECT>), dim3(blocks), dim3(T), shmem, s, p);
+    hipLaunchKernelGGL((k_ntt_pass<T, INV, DIRECT, R5>), dim3(blocks), dim3(T), shmem, s, p);
 }
 
 template <bool INV>
@@ -562,6 +610,17 @@ void launch_pass(const NttPass& p, const PassCfg& c, u32 n_limbs, hipStream_t s)
     if (direct && threads > 512) throw Error(VR_EINVAL, "ntt: whole-limb pass needs <= 512 threads");
     u32 blocks = n_limbs * ((1u << (p.log_n - p.log_g - p.log_c)));
     size_t shmem = (size_t)(tile + tile / 16) * sizeof(u64);
+    if (p.max_r == 5) {
+        // five-stage rounds: whole-limb passes with 32 words per thread only
+        if (!direct || c.div != 32) throw Error(VR_EINVAL, "ntt: five-stage rounds need a direct pass");
+        switch (threads) {
+        case 256: launch_kernel<256, INV, true, true>(p, blocks, shmem, s); break;
+        case 512: launch_kernel<512, INV, true, true>(p, blocks, shmem, s); break;
+        default: throw Error(VR_EINVAL, "ntt: unsupported tile for five-stage rounds");
+        }
+        VR_CHECK_LAUNCH();
+        return;
+    }
     switch (threads) {
     case 64: direct ? launch_kernel<64, INV, true>(p, blocks, shmem, s) : launch_kernel<64, INV, false>(p, blocks, shmem, s); break;
     case 128: direct ? launch_kernel<128, INV, true>(p, blocks, shmem, s) : launch_kernel<128, INV, false>(p, blocks, shmem, s); break;
@@ -593,6 +652,7 @@ void run_plan(vr_context* ctx, const LimbSet& ls, const std::vector<PassCfg>& pa
         p.log_c = c.log_c;
         p.first = (i == 0);
         p.last = (i == np - 1);
+        p.max_r = c.max_r;
         launch_pass<INV>(p, c, n_limbs, s);
     }
 }
@@ -643,7 +703,7 @@ std::vector<PassCfg> plan_for(vr_context* ctx, hipStream_t s)
         if (it != ctx->tuning.end()) mode = it->second;
         if (mode == 0 && !ctx->ntt_plan[INV].empty()) {
             std::vector<PassCfg> p;
-            for (auto& c : ctx->ntt_plan[INV]) p.push_back({c[0], c[1], c[2], c[3], c[4]});
+            for (auto& c : ctx->ntt_plan[INV]) p.push_back({c[0], c[1], c[2], c[3], c[4], c[5]});
             return p;
         }
     }
@@ -656,7 +716,7 @@ std::vector<PassCfg> plan_for(vr_context* ctx, hipStream_t s)
     std::vector<PassCfg> p = tune<INV>(ctx, s);
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->ntt_plan[INV].clear();
-    for (auto& c : p) ctx->ntt_plan[INV].push_back({c.s0, c.log_g, c.log_c, c.direct, c.div});
+    for (auto& c : p) ctx->ntt_plan[INV].push_back({c.s0, c.log_g, c.log_c, c.direct, c.div, c.max_r});
     return p;
 }
 

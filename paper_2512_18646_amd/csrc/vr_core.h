@@ -239,8 +239,9 @@ struct vr_context {
     // "ntt" = 0 autotune, 1 the fixed default pass plan
     std::map<std::string, int> tuning;
     // NTT pass plans picked by the autotuner, per direction, per pass:
-    // {first stage, stages, log groups per workgroup, whole-limb direct, words per thread}
-    std::vector<std::array<vr::u32, 5>> ntt_plan[2];
+    // {first stage, stages, log groups per workgroup, whole-limb direct, words per
+    // thread, stages per round}
+    std::vector<std::array<vr::u32, 6>> ntt_plan[2];
     std::mutex mu;
     hipStream_t stream = nullptr;     // used when a call passes stream = NULL
     std::shared_ptr<vr::DeviceArena> arena;
