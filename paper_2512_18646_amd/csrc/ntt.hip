@@ -72,6 +72,10 @@ __device__ __forceinline__ void limb_addr(const LimbSet& ls, u32 r, u32 n, u32 L
 
 __device__ __forceinline__ u32 pad(u32 i) { return i + (i >> 4); }
 
+// words per thread moved between global memory and LDS with their loads all
+// issued before the first is used
+constexpr int kBatch = 16;
+
 // Where a round reads and writes.  A pass that holds the whole limb takes its
 // first round straight from global memory (element e at gsrc[e]: the groups
 // of the first forward round are strided so consecutive threads read
@@ -446,20 +450,37 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
     // and last round; other passes stage the tile through LDS with coalesced loads
     const bool direct = DIRECT;   // launched only for a single pass over the whole limb
     const bool strided = lo_bits > 0;
+    // tile word e <-> (column c, row v) and its global index
+    auto locate = [&](u32 e, u32* slot) -> size_t {
+        u32 c, v;
+        if (strided) { v = e >> p.log_c; c = e & (C - 1); }
+        else { c = e >> p.log_g; v = e & (G - 1); }
+        const u32 g = g0 + c;
+        const u32 H = g >> lo_bits, Lo = g & ((1u << lo_bits) - 1);
+        *slot = pad(c * G + v);
+        return ((size_t)H << (p.log_n - p.s0)) + ((size_t)v << lo_bits) + Lo;
+    };
     if (!direct) {
-        for (u32 e = threadIdx.x; e < tile; e += THREADS) {
-            u32 c, v;
-            if (strided) { v = e >> p.log_c; c = e & (C - 1); }
-            else { c = e >> p.log_g; v = e & (G - 1); }
-            u32 g = g0 + c;
-            u32 H = g >> lo_bits, Lo = g & ((1u << lo_bits) - 1);
-            size_t idx = ((size_t)H << (p.log_n - p.s0)) + ((size_t)v << lo_bits) + Lo;
-            u64 x = src[idx];
-            if (cq) x = conv_one(x, cq, q, m.one_s);
-            // first pass of the FP64 path: canonical uint64 -> balanced double;
-            // later passes read the balanced doubles the previous pass stored
-            if (fp && p.first) x = __double_as_longlong(to_bal(x, q, qd));
-            lds[pad(c * G + v)] = x;
+        // kBatch loads in flight per thread before the first one is consumed
+        for (u32 e0 = threadIdx.x; e0 < tile; e0 += kBatch * THREADS) {
+            u64 x[kBatch];
+            u32 slot[kBatch];
+#pragma unroll
+            for (int j = 0; j < kBatch; j++) {
+                const u32 e = e0 + j * THREADS;
+                const size_t idx = locate(e < tile ? e : e0, &slot[j]);
+                x[j] = e < tile ? src[idx] : 0;
+            }
+#pragma unroll
+            for (int j = 0; j < kBatch; j++) {
+                if (e0 + j * THREADS >= tile) break;
+                u64 v = x[j];
+                if (cq) v = conv_one(v, cq, q, m.one_s);
+                // first pass of the FP64 path: canonical uint64 -> balanced double;
+                // later passes read the balanced doubles the previous pass stored
+                if (fp && p.first) v = __double_as_longlong(to_bal(v, q, qd));
+                lds[slot[j]] = v;
+            }
         }
         __syncthreads();
     }
@@ -519,29 +540,349 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
     }
     if (direct) return;
 
-    for (u32 e = threadIdx.x; e < tile; e += THREADS) {
-        u32 c, v;
-        if (strided) { v = e >> p.log_c; c = e & (C - 1); }
-        else { c = e >> p.log_g; v = e & (G - 1); }
-        u32 g = g0 + c;
-        u32 H = g >> lo_bits, Lo = g & ((1u << lo_bits) - 1);
-        size_t idx = ((size_t)H << (p.log_n - p.s0)) + ((size_t)v << lo_bits) + Lo;
-        u64 x = lds[pad(c * G + v)];
-        if (fp) {
-            if (p.last) {
-                double y = __longlong_as_double(x);
-                if (INV) y = fmulmod(y, ninv_f, qd, qinv);
-                x = to_canon(y, qd, qinv);
+    for (u32 e0 = threadIdx.x; e0 < tile; e0 += kBatch * THREADS) {
+        u64 xs[kBatch];
+        size_t gi[kBatch];
+#pragma unroll
+        for (int j = 0; j < kBatch; j++) {
+            const u32 e = e0 + j * THREADS;
+            u32 slot;
+            gi[j] = locate(e < tile ? e : e0, &slot);
+            xs[j] = lds[slot];
+        }
+#pragma unroll
+        for (int j = 0; j < kBatch; j++) {
+            if (e0 + j * THREADS >= tile) break;
+            const size_t idx = gi[j];
+            u64 x = xs[j];
+            if (fp) {
+                if (p.last) {
+                    double y = __longlong_as_double(x);
+                    if (INV) y = fmulmod(y, ninv_f, qd, qinv);
+                    x = to_canon(y, qd, qinv);
+                }
+            } else if (p.last) {
+                if (!INV) {
+                    x = x >= q2 ? x - q2 : x;
+                    x = x >= q ? x - q : x;
+                } else {
+                    x = shoup(x, m.ninv, m.ninv_s, q);
+                }
             }
-        } else if (p.last) {
-            if (!INV) {
-                x = x >= q2 ? x - q2 : x;
-                x = x >= q ? x - q : x;
-            } else {
-                x = shoup(x, m.ninv, m.ninv_s, q);
+            dst[idx] = x;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Whole-limb transform with the round geometry fixed at compile time.
+//
+// One workgroup of 2^(LOGN - LOGE) threads transforms one limb of 2^LOGN
+// words, each thread holding 2^LOGE words per round.  The rounds (LOGE stages
+// each, the last one taking the remainder) are unrolled at compile time, so
+// every shift, mask and offset is a constant: the words of a group differ
+// only in index bits [lb, lb + R), which the group's base leaves clear, hence
+// pad(base | m << lb) = pad(base) + pad(m << lb) and each word's LDS address
+// is one per-group register plus an immediate.  The first round reads global
+// memory and the last writes it, so LDS is only visited between rounds.
+//
+// FP64 limbs (q < 2^51) reduce no more often than their bounds require (the
+// bounds are those of the general kernel above: a product is within about
+// q + |e| of zero, e the exact low part, |e| < q / 16 in every case below):
+//   forward  q < 2^44: never before the final store (16 stages from |x| <=
+//            q/2 stay below 26 q < 2^49); q < 2^50: every 4 stages; else 2;
+//   inverse  q < 2^46: every 4 stages (sums at most double per stage: below
+//            8.8 q); else every 2.
+// The inverse's N^-1 is folded into its last stage, whose single twiddle w1
+// becomes the two constants N^-1 and w1 N^-1 (one product per output word
+// instead of a product for the stage and one for the scaling).
+
+constexpr u32 padc(u32 i) { return i + (i >> 4); }
+
+template <int LOGN, int LOGE>
+struct LimbShape {
+    static constexpr int T_LOG = LOGN - LOGE;
+    static constexpr u32 T = 1u << T_LOG;
+    static constexpr int NR = (LOGN + LOGE - 1) / LOGE;
+    // forward round i covers stages [i LOGE, i LOGE + R(i))
+    static constexpr int R(int i) { return (i + 1) * LOGE <= LOGN ? LOGE : LOGN - i * LOGE; }
+};
+
+// Forward FP64 butterflies of one group: global stages SG0 .. SG0 + R - 1,
+// reducing after each stage s with (s + 1) % RED == 0 (RED = 0: never).
+template <int LOGN, int R, int SG0, int RED, bool UNI>
+__device__ __forceinline__ void limb_fp_fwd(double (&x)[1 << R], const double* tw, u32 hi, double q,
+                                            double qinv)
+{
+    constexpr int E = 1 << R;
+    if (UNI) hi = __builtin_amdgcn_readfirstlane(hi);
+#pragma unroll
+    for (int k = 0; k < R; k++) {
+        const int half = 1 << (R - 1 - k);
+        const double* twk = tw + (1u << (SG0 + k)) + (hi << k);
+#pragma unroll
+        for (int j = 0; j < (1 << k); j++) {
+            const double w = twk[j];
+#pragma unroll
+            for (int i = 0; i < half; i++) {
+                const int m1 = (j << (R - k)) + i, m2 = m1 + half;
+                const double X = x[m1];
+                const double T = fmulmod(x[m2], w, q, qinv);
+                x[m1] = X + T;
+                x[m2] = X - T;
             }
         }
-        dst[idx] = x;
+        const int s = SG0 + k;
+        if (RED && (s + 1) % (RED ? RED : 1) == 0 && s != LOGN - 1) {
+#pragma unroll
+            for (int m = 0; m < E; m++) x[m] = fbal(x[m], q, qinv);
+        }
+    }
+}
+
+// Inverse FP64 butterflies: stages SG0 + R - 1 down to SG0; stage 0 takes
+// the folded constants (n1 = N^-1, w1n = w1 N^-1).
+template <int LOGN, int R, int SG0, int RED, bool UNI>
+__device__ __forceinline__ void limb_fp_inv(double (&x)[1 << R], const double* tw, u32 hi, double q,
+                                            double qinv, double n1, double w1n)
+{
+    constexpr int E = 1 << R;
+    if (UNI) hi = __builtin_amdgcn_readfirstlane(hi);
+#pragma unroll
+    for (int k = R - 1; k >= 0; k--) {
+        const int half = 1 << (R - 1 - k);
+        const int s = SG0 + k;
+        const double* twk = tw + (1u << s) + (hi << k);
+#pragma unroll
+        for (int j = 0; j < (1 << k); j++) {
+#pragma unroll
+            for (int i = 0; i < half; i++) {
+                const int m1 = (j << (R - k)) + i, m2 = m1 + half;
+                const double X = x[m1], Y = x[m2];
+                if (s == 0) {
+                    x[m1] = fmulmod(X + Y, n1, q, qinv);
+                    x[m2] = fmulmod(X - Y, w1n, q, qinv);
+                } else {
+                    x[m1] = X + Y;
+                    x[m2] = fmulmod(X - Y, twk[j], q, qinv);
+                }
+            }
+        }
+        if (RED && (LOGN - s) % (RED ? RED : 1) == 0 && s != 0) {
+#pragma unroll
+            for (int m = 0; m < E; m++) x[m] = fbal(x[m], q, qinv);
+        }
+    }
+}
+
+// Integer (Shoup, lazy) butterflies with the same compile-time geometry:
+// forward values in [0, 4q), inverse in [0, 2q); stage 0 of the inverse
+// takes the folded constants as (w, w') pairs.
+template <int R, int SG0, bool INV, bool UNI>
+__device__ __forceinline__ void limb_int(u64 (&x)[1 << R], const ulonglong2* tw, u32 hi, u64 q,
+                                         ulonglong2 n1, ulonglong2 w1n)
+{
+    if (UNI) hi = __builtin_amdgcn_readfirstlane(hi);
+    const u64 q2 = 2 * q;
+    if (!INV) {
+#pragma unroll
+        for (int k = 0; k < R; k++) {
+            const int half = 1 << (R - 1 - k);
+            const ulonglong2* twk = tw + (1u << (SG0 + k)) + (hi << k);
+#pragma unroll
+            for (int j = 0; j < (1 << k); j++) {
+                const ulonglong2 t = twk[j];
+#pragma unroll
+                for (int i = 0; i < half; i++) {
+                    const int m1 = (j << (R - k)) + i, m2 = m1 + half;
+                    u64 X = x[m1];
+                    X = X >= q2 ? X - q2 : X;
+                    const u64 T = shoup_lazy(x[m2], t.x, t.y, q);
+                    x[m1] = X + T;
+                    x[m2] = X + q2 - T;
+                }
+            }
+        }
+    } else {
+#pragma unroll
+        for (int k = R - 1; k >= 0; k--) {
+            const int half = 1 << (R - 1 - k);
+            const int s = SG0 + k;
+            const ulonglong2* twk = tw + (1u << s) + (hi << k);
+#pragma unroll
+            for (int j = 0; j < (1 << k); j++) {
+#pragma unroll
+                for (int i = 0; i < half; i++) {
+                    const int m1 = (j << (R - k)) + i, m2 = m1 + half;
+                    const u64 X = x[m1], Y = x[m2];
+                    if (s == 0) {
+                        x[m1] = shoup_lazy(X + Y, n1.x, n1.y, q);
+                        x[m2] = shoup_lazy(X + q2 - Y, w1n.x, w1n.y, q);
+                    } else {
+                        const ulonglong2 t = twk[j];
+                        const u64 S = X + Y;
+                        x[m1] = S >= q2 ? S - q2 : S;
+                        x[m2] = shoup_lazy(X + q2 - Y, t.x, t.y, q);
+                    }
+                }
+            }
+        }
+    }
+}
+
+// Per-limb constants of the whole-limb kernel.
+struct LimbK {
+    const u64* src;
+    u64* dst;
+    u64 q, cq, one_s;
+    double qd, qinv, n1f, w1nf;
+    ulonglong2 n1, w1n;
+};
+
+// Forward round i (or inverse round i, walking the forward rounds from the
+// last) over the thread's groups.  FP = the limb is on the FP64 path.
+template <int LOGN, int LOGE, int I, bool INV, bool FP, int RED>
+__device__ __forceinline__ void limb_round(u64* lds, const u64* tw64, const double* twf, const LimbK& c)
+{
+    using S = LimbShape<LOGN, LOGE>;
+    constexpr int R = S::R(I);
+    constexpr int SG0 = I * LOGE;
+    constexpr int E = 1 << R;
+    constexpr int LB = LOGN - SG0 - R;
+    constexpr int GPT = 1 << (LOGE - R);
+    constexpr bool UNI = LB >= 6;
+    // the forward transform's first round and the inverse's last face the
+    // canonical limb in global memory; so do the forward's last and the
+    // inverse's first
+    constexpr bool FROM_G = INV ? (I == S::NR - 1) : (I == 0);
+    constexpr bool TO_G = INV ? (I == 0) : (I == S::NR - 1);
+    double* ldf = (double*)lds;
+#pragma unroll
+    for (int g = 0; g < GPT; g++) {
+        const u32 gid = threadIdx.x + (u32)g * S::T;
+        const u32 hi = gid >> LB, lo = gid & ((1u << LB) - 1);
+        const u32 base = (hi << (LB + R)) | lo;
+        const u32 pb = pad(base);
+        if constexpr (FP) {
+            double x[E];
+            if (FROM_G) {
+                u64 v[E];
+#pragma unroll
+                for (int m = 0; m < E; m++) v[m] = c.src[base + ((u32)m << LB)];
+#pragma unroll
+                for (int m = 0; m < E; m++) {
+                    u64 t = v[m];
+                    if (!INV && c.cq) t = conv_one(t, c.cq, c.q, c.one_s);
+                    x[m] = to_bal(t, c.q, c.qd);
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < E; m++) x[m] = ldf[pb + padc((u32)m << LB)];
+            }
+            if constexpr (INV)
+                limb_fp_inv<LOGN, R, SG0, RED, UNI>(x, twf, hi, c.qd, c.qinv, c.n1f, c.w1nf);
+            else
+                limb_fp_fwd<LOGN, R, SG0, RED, UNI>(x, twf, hi, c.qd, c.qinv);
+            if (TO_G) {
+#pragma unroll
+                for (int m = 0; m < E; m++) c.dst[base + ((u32)m << LB)] = to_canon(x[m], c.qd, c.qinv);
+            } else {
+#pragma unroll
+                for (int m = 0; m < E; m++) ldf[pb + padc((u32)m << LB)] = x[m];
+            }
+        } else {
+            const u64 q = c.q, q2 = 2 * q;
+            u64 x[E];
+            if (FROM_G) {
+#pragma unroll
+                for (int m = 0; m < E; m++) x[m] = c.src[base + ((u32)m << LB)];
+                if (!INV && c.cq) {
+#pragma unroll
+                    for (int m = 0; m < E; m++) x[m] = conv_one(x[m], c.cq, q, c.one_s);
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < E; m++) x[m] = lds[pb + padc((u32)m << LB)];
+            }
+            limb_int<R, SG0, INV, UNI>(x, (const ulonglong2*)tw64, hi, q, c.n1, c.w1n);
+            if (TO_G) {
+#pragma unroll
+                for (int m = 0; m < E; m++) {
+                    u64 v = x[m];
+                    if (!INV) v = v >= q2 ? v - q2 : v;
+                    c.dst[base + ((u32)m << LB)] = v >= q ? v - q : v;
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < E; m++) lds[pb + padc((u32)m << LB)] = x[m];
+            }
+        }
+    }
+}
+
+template <int LOGN, int LOGE, bool INV, bool FP, int RED, int I>
+__device__ __forceinline__ void limb_rounds(u64* lds, const u64* tw64, const double* twf, const LimbK& c)
+{
+    using S = LimbShape<LOGN, LOGE>;
+    if constexpr (I >= 0 && I < S::NR) {
+        limb_round<LOGN, LOGE, I, INV, FP, RED>(lds, tw64, twf, c);
+        constexpr int NEXT = INV ? I - 1 : I + 1;
+        if constexpr (NEXT >= 0 && NEXT < S::NR) {
+            __syncthreads();
+            limb_rounds<LOGN, LOGE, INV, FP, RED, NEXT>(lds, tw64, twf, c);
+        }
+    }
+}
+
+template <int LOGN, int LOGE, bool INV>
+__global__ __launch_bounds__(1u << (LOGN - LOGE)) void k_ntt_limb(NttPass p)
+{
+    extern __shared__ u64 lds[];
+    using S = LimbShape<LOGN, LOGE>;
+    constexpr u32 n = 1u << LOGN;
+    constexpr int I0 = INV ? S::NR - 1 : 0;
+    const u32 r = blockIdx.x;
+    const u64* src;
+    u64* dst;
+    u32 mod;
+    limb_addr(p.ls, r, n, p.L, &src, &dst, &mod);
+    const ModQ& mq = p.mq[mod];
+    LimbK c;
+    c.src = src;
+    c.dst = dst;
+    c.q = mq.q;
+    c.cq = 0;
+    c.one_s = mq.one_s;
+    if (!INV && p.ls.cv_src) {
+        const u32 poly = r / p.ls.per_poly;
+        const u32 ct = poly / p.ls.cv_beta, d = poly - ct * p.ls.cv_beta;
+        c.src = p.ls.cv_src + (size_t)ct * p.ls.cv_ct_stride + (size_t)d * n;
+        c.cq = p.mq[p.ls.cv_mod0 + d].q;
+    }
+    const u64* tw64 = p.tw + (size_t)mod * n * 2;
+    const double* twf = p.twf + (size_t)mod * n;
+    c.n1 = make_ulonglong2(mq.ninv, mq.ninv_s);
+    c.w1n = make_ulonglong2(mq.inw1, mq.inw1_s);
+    if (c.q < (1ull << 51)) {
+        c.qd = (double)c.q;
+        c.qinv = 1.0 / c.qd;
+        c.n1f = to_bal(mq.ninv, c.q, c.qd);
+        c.w1nf = to_bal(mq.inw1, c.q, c.qd);
+        if (!INV) {
+            if (c.q < (1ull << 44))
+                limb_rounds<LOGN, LOGE, INV, true, 0, I0>(lds, tw64, twf, c);
+            else if (c.q < (1ull << 50))
+                limb_rounds<LOGN, LOGE, INV, true, 4, I0>(lds, tw64, twf, c);
+            else
+                limb_rounds<LOGN, LOGE, INV, true, 2, I0>(lds, tw64, twf, c);
+        } else {
+            if (c.q < (1ull << 46))
+                limb_rounds<LOGN, LOGE, INV, true, 4, I0>(lds, tw64, twf, c);
+            else
+                limb_rounds<LOGN, LOGE, INV, true, 2, I0>(lds, tw64, twf, c);
+        }
+    } else {
+        limb_rounds<LOGN, LOGE, INV, false, 4, I0>(lds, tw64, twf, c);
     }
 }
 
@@ -549,7 +890,8 @@ namespace {
 
 struct PassCfg {
     u32 s0, log_g, log_c;
-    u32 direct = 0;    // whole-limb pass with global first/last rounds
+    u32 direct = 0;    // 1: whole-limb pass with global first/last rounds; 2: the same
+                       // with the round geometry fixed at compile time
     u32 div = 16;      // tile words per thread
     u32 max_r = 4;     // stages per round
 };
@@ -573,6 +915,11 @@ std::vector<std::vector<PassCfg>> candidates(u32 log_n)
             if (log_n <= 13) out.push_back({{0, log_n, 0, 1, 16}});
             out.push_back({{0, log_n, 0, 1, 32}});
             if (log_n >= 13) out.push_back({{0, log_n, 0, 1, 32, 5}});   // rounds of five stages
+            if (log_n >= 13) {
+                // compile-time whole-limb kernels, 16 or 32 words per thread
+                out.push_back({{0, log_n, 0, 2, 16}});
+                out.push_back({{0, log_n, 0, 2, 32}});
+            }
         }
     }
     if (log_n < 10) return out;
@@ -599,9 +946,34 @@ void launch_kernel(const NttPass& p, u32 blocks, size_t shmem, hipStream_t s)
     hipLaunchKernelGGL((k_ntt_pass<T, INV, DIRECT, R5>), dim3(blocks), dim3(T), shmem, s, p);
 }
 
+template <int LOGN, int LOGE, bool INV>
+void launch_limb(const NttPass& p, u32 n_limbs, hipStream_t s)
+{
+    static std::once_flag attr;
+    const size_t shmem = (size_t)padc(1u << LOGN) * sizeof(u64);
+    std::call_once(attr, [&] {
+        (void)hipFuncSetAttribute((const void*)k_ntt_limb<LOGN, LOGE, INV>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    });
+    hipLaunchKernelGGL((k_ntt_limb<LOGN, LOGE, INV>), dim3(n_limbs), dim3(1u << (LOGN - LOGE)), shmem, s, p);
+}
+
 template <bool INV>
 void launch_pass(const NttPass& p, const PassCfg& c, u32 n_limbs, hipStream_t s)
 {
+    if (c.direct == 2) {
+        // whole-limb kernel with the geometry fixed at compile time
+        const u32 key = p.log_n * 100 + c.div;
+        switch (key) {
+        case 1316: launch_limb<13, 4, INV>(p, n_limbs, s); break;
+        case 1332: launch_limb<13, 5, INV>(p, n_limbs, s); break;
+        case 1416: launch_limb<14, 4, INV>(p, n_limbs, s); break;
+        case 1432: launch_limb<14, 5, INV>(p, n_limbs, s); break;
+        default: throw Error(VR_EINVAL, "ntt: no whole-limb kernel for this size");
+        }
+        VR_CHECK_LAUNCH();
+        return;
+    }
     u32 tile = 1u << (p.log_g + p.log_c);
     u32 threads = tile / c.div;
     if (threads < 64) threads = 64;

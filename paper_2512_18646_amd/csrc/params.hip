@@ -187,6 +187,9 @@ void build_context(vr_context* ctx, const vr_params* p, int device)
             pw[k] = mulmod_h(pw[k - 1], psi, q);
             ipw[k] = mulmod_h(ipw[k - 1], ipsi, q);
         }
+        // the inverse's last stage has the single twiddle ipsi^(N/2)
+        mq.inw1 = mulmod_h(ipw[n / 2], mq.ninv, q);
+        mq.inw1_s = shoup_companion(mq.inw1, q);
         for (u32 k = 0; k < n; k++) {
             u32 e = bitrev(k, p->log_n);
             size_t at = 2 * ((size_t)m * n + k);

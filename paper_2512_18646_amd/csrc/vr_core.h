@@ -67,6 +67,8 @@ struct ModQ {
     u64 one_s;   // floor(2^64 / q)
     u64 ninv;    // N^-1 mod q
     u64 ninv_s;
+    u64 inw1;    // N^-1 times the inverse transform's last-stage twiddle, mod q
+    u64 inw1_s;
     u64 pmod;    // P = prod of the special primes, mod q
     u64 pmod_s;
     u64 pinv;    // P^-1 mod q (Q-chain moduli only)

@@ -47,12 +47,38 @@ def test_ntt_every_candidate_plan(log_n):
     assert "ntt N=2^%d forward" % log_n in g.tuning_report()
 
 
+@pytest.mark.parametrize("log_n", [13, 14])
+def test_ntt_every_plan_reduction_bands(log_n):
+    """FP64 moduli in each band of the reduction schedule (45 and 49 bits:
+    forward every four stages; 45: inverse every four, 49: every two) under
+    every plan, with rows of extreme balanced inputs (all (q-1)/2, all
+    (q+1)/2, alternating)."""
+    from paper_2512_18646_amd import vr
+    p = Params(log_n, [49, 45, 40], [45], 1, 30.0, allow_insecure=True)
+    o, g = OracleContext(p), gpu_ctx(p)
+    tried = 0
+    while True:
+        g.set_tuning("ntt", "cand:%d" % tried)
+        try:
+            check_ntt(o, g, log_n, reps=2)
+        except vr.VRError as e:
+            assert e.code == vr.VR_EINVAL and tried >= 1
+            break
+        tried += 1
+
+
 def check_ntt(o, g, log_n, reps=3):
     import torch
     mods = o.q + o.p
     rng = np.random.default_rng(log_n)
     host = np.stack([rng.integers(0, mods[i % 4], o.n, dtype=np.uint64) for i in range(4 * reps)])
     host[0, :8] = [0, 1, mods[0] - 1, 2, 3, mods[0] - 2, 0, 1]
+    # largest balanced magnitudes: (q-1)/2 and (q+1)/2 = -(q-1)/2
+    half = [(int(q) - 1) // 2 for q in mods[:4]]
+    host[1] = half[1]
+    host[2] = half[2] + 1
+    host[3, 0::2] = half[3]
+    host[3, 1::2] = half[3] + 1
     mi = [i % 4 for i in range(4 * reps)]
     dev = torch.from_numpy(host.view(np.int64).copy()).cuda()
     g.ntt_device(dev.data_ptr(), 4 * reps, mi)
