@@ -234,6 +234,44 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
     // blockIdx.z splits the ciphertexts into groups so small rings still fill the chip
     const u32 per = (n_ct + gridDim.z - 1) / gridDim.z;
     const u32 c_lo = blockIdx.z * per, c_hi = min(n_ct, c_lo + per);
+    if (m.q < (1ull << 51)) {
+        // FP64 products (one modulus per block): key and inputs balanced,
+        // each product within 0.75 q, the sums reduced every four digits
+        // (below 3.5 q < 2^53)
+        const double qd = (double)m.q, qinv = 1.0 / qd;
+        double fb[MAXB], fa[MAXB];
+#pragma unroll
+        for (int j = 0; j < MAXB; j++) {
+            if (j < (int)beta) {
+                fb[j] = to_bal(kb[j], m.q, qd);
+                fa[j] = to_bal(ka[j], m.q, qd);
+            }
+        }
+        for (u32 c = c_lo; c < c_hi; c++) {
+            const u64* xc = X + (size_t)c * x_stride + (size_t)e * n + s;
+            u64 xv[MAXB];
+#pragma unroll
+            for (int j = 0; j < MAXB; j++)
+                if (j < (int)beta) xv[j] = xc[(size_t)j * next * n];
+            double s0 = 0, s1 = 0;
+#pragma unroll
+            for (int j = 0; j < MAXB; j++) {
+                if (j < (int)beta) {
+                    const double x = to_bal(xv[j], m.q, qd);
+                    s0 += fmulmod(x, fb[j], qd, qinv);
+                    s1 += fmulmod(x, fa[j], qd, qinv);
+                    if ((j & 3) == 3) {
+                        s0 = fbal(s0, qd, qinv);
+                        s1 = fbal(s1, qd, qinv);
+                    }
+                }
+            }
+            u64* u = U + (size_t)c * u_stride + (size_t)e * n + t;
+            u[0] = to_canon(s0, qd, qinv);
+            u[(size_t)next * n] = to_canon(s1, qd, qinv);
+        }
+        return;
+    }
     for (u32 c = c_lo; c < c_hi; c++) {
         const u64* xc = X + (size_t)c * x_stride + (size_t)e * n + s;
         u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;

@@ -116,7 +116,8 @@ constexpr int kMaxFilters = 8;
 __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, const u64* x,
                                                       const u64* r, u32 n_x, u32 n_sets, u64 stride,
                                                       const Term* terms, const u32* term_off,
-                                                      const u64* w, const u64* ws, u32 w_fstride,
+                                                      const u64* w, const u64* ws, const double* wf,
+                                                      u32 w_fstride,
                                                       const u64* bias, u32 nl, u32 log_n,
                                                       const ModQ* mq, u32 wo, u32 n_filters,
                                                       u32 total, u32 per_xcd)
@@ -136,6 +137,60 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
     const u64 q = mq[l].q, q2 = 2 * q;
     const u32 a = term_off[jo], b = term_off[jo + 1];
     const u32 n_out = n_filters * wo;
+    if (q < (1ull << 51)) {
+        // FP64 products (the block's limb has one modulus): inputs and
+        // weights balanced, each product within 0.75 q, the sums reduced
+        // every four terms (below 3.5 q < 2^53)
+        const double qd = (double)q, qinv = 1.0 / qd;
+        for (u32 f0 = 0; f0 < n_filters; f0 += kMaxFilters) {
+            const u32 nf = min((u32)kMaxFilters, n_filters - f0);
+            double acc[kMaxFilters];
+#pragma unroll
+            for (int f = 0; f < kMaxFilters; f++) acc[f] = 0;
+            for (u32 k0 = a; k0 < b; k0 += 8) {
+                u64 xv[8];
+                u32 wrow[8];
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    if (k0 + i < b) {
+                        const Term tm = terms[k0 + i];
+                        const u32 u = tm.in_idx / n_x, j = tm.in_idx - u * n_x;
+                        const u64* src = u == 0 ? x + (size_t)(set * n_x + j) * stride
+                                                : r + ((size_t)(u - 1) * n_x * n_sets + set * n_x + j) * stride;
+                        xv[i] = src[(size_t)row * n + t];
+                        wrow[i] = tm.w_idx;
+                    }
+                }
+#pragma unroll
+                for (int i = 0; i < 8; i++) {
+                    if (k0 + i < b) {
+                        const double xf = to_bal(xv[i], q, qd);
+#pragma unroll
+                        for (int f = 0; f < kMaxFilters; f++) {
+                            if (f < (int)nf) {
+                                const size_t wi = (size_t)(wrow[i] + (f0 + f) * w_fstride) * nl + l;
+                                acc[f] += fmulmod(xf, wf[wi], qd, qinv);
+                            }
+                        }
+                    }
+                    if ((i & 3) == 3) {
+#pragma unroll
+                        for (int f = 0; f < kMaxFilters; f++) acc[f] = fbal(acc[f], qd, qinv);
+                    }
+                }
+            }
+#pragma unroll
+            for (int f = 0; f < kMaxFilters; f++) {
+                if (f < (int)nf) {
+                    const u32 o = (f0 + f) * wo + jo;
+                    double v = acc[f];
+                    if (bias && row < nl) v += to_bal(bias[(size_t)o * nl + l], q, qd);
+                    out[(size_t)(set * n_out + o) * out_stride + (size_t)row * n + t] = to_canon(v, qd, qinv);
+                }
+            }
+        }
+        return;
+    }
     for (u32 f0 = 0; f0 < n_filters; f0 += kMaxFilters) {
         const u32 nf = min((u32)kMaxFilters, n_filters - f0);
         u64 acc[kMaxFilters];
@@ -416,6 +471,7 @@ struct ConvPlan {
     const Term* terms = nullptr;
     const u32* off = nullptr;
     const u64 *w = nullptr, *ws = nullptr, *bias = nullptr;
+    const double* wf = nullptr;   // the weights as balanced doubles (moduli below 2^51)
 };
 
 const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const double* K,
@@ -435,10 +491,13 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
 
     const double dq = (double)ctx->mod[level];
     std::vector<u64> wv(nw * nl), wsv(nw * nl), bv((size_t)C_out * wo * nl);
+    std::vector<double> wfv(nw * nl);
     for (size_t r = 0; r < nw; r++)
         for (u32 l = 0; l < nl; l++) {
-            wv[r * nl + l] = double_to_mod(K[r] * dq, ctx->mod[l]);
-            wsv[r * nl + l] = shoup_companion(wv[r * nl + l], ctx->mod[l]);
+            const u64 q = ctx->mod[l], v = double_to_mod(K[r] * dq, q);
+            wv[r * nl + l] = v;
+            wsv[r * nl + l] = shoup_companion(v, q);
+            wfv[r * nl + l] = v > q / 2 ? -(double)(q - v) : (double)v;
         }
     for (u32 co = 0; co < C_out; co++)
         for (u32 l = 0; l < nl; l++) {
@@ -460,9 +519,9 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
             }
         off.push_back((u32)terms.size());
     }
-    // one device buffer: terms | off | w | ws | bias (8-byte aligned parts)
+    // one device buffer: terms | off | w | ws | bias | wf (8-byte aligned parts)
     size_t b_terms = terms.size() * sizeof(Term), b_off = ((off.size() * 4 + 7) / 8) * 8;
-    size_t total = b_terms + b_off + (wv.size() + wsv.size() + bv.size()) * 8;
+    size_t total = b_terms + b_off + (wv.size() + wsv.size() + bv.size() + wfv.size()) * 8;
     auto plan = std::make_shared<ConvPlan>();
     VR_HIP(hipDeviceSynchronize());
     plan->buf = dev_alloc(ctx, total, nullptr);
@@ -474,12 +533,14 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
     memcpy(h.data() + o, wv.data(), wv.size() * 8);
     memcpy(h.data() + o + wv.size() * 8, wsv.data(), wsv.size() * 8);
     memcpy(h.data() + o + (wv.size() + wsv.size()) * 8, bv.data(), bv.size() * 8);
+    memcpy(h.data() + o + (wv.size() + wsv.size() + bv.size()) * 8, wfv.data(), wfv.size() * 8);
     VR_HIP(hipMemcpy(base, h.data(), total, hipMemcpyHostToDevice));
     plan->terms = (const Term*)base;
     plan->off = (const u32*)(base + b_terms);
     plan->w = (const u64*)(base + o);
     plan->ws = plan->w + wv.size();
     plan->bias = plan->ws + wsv.size();
+    plan->wf = (const double*)(plan->bias + bv.size());
     ctx->plans[key] = plan;
     return *plan;
 }
@@ -612,7 +673,7 @@ Slab conv_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& x, u32 n_set
         ProfScope prof(ctx, kProfLincomb, s, (u64)n_sets * n_out * 2 * nl);
         hipLaunchKernelGGL(k_lincomb, dim3(8 * per_xcd), dim3(kThreads), 0, s, acc.base, acc.stride,
                            x.base, rot.empty() ? x.base : rot[0].base, C_in * w, n_sets, x.stride,
-                           plan.terms, plan.off, plan.w, plan.ws, C_in * k * k, plan.bias, nl,
+                           plan.terms, plan.off, plan.w, plan.ws, plan.wf, C_in * k * k, plan.bias, nl,
                            ctx->log_n, ctx->d_modq, wo, C_out, total, per_xcd);
         VR_CHECK_LAUNCH();
     }

@@ -217,50 +217,6 @@ __device__ __forceinline__ void ntt_round(u64* lds, const u64* tw, const ModQ& m
     }
 }
 
-#pragma clang fp contract(off)
-// y w mod q as an exact integer in about (-1.4 q, 1.4 q), for |y w| < 2^104
-__device__ __forceinline__ double fmulmod(double y, double w, double q, double qinv)
-{
-    const double p = y * w;
-    const double e = __fma_rn(y, w, -p);
-    const double t = rint(p * qinv);
-    return __fma_rn(-t, q, p) + e;
-}
-
-// x - q rint(x / q): balanced representative, |result| <= q/2 + 1
-__device__ __forceinline__ double fbal(double x, double q, double qinv)
-{
-    return __fma_rn(-rint(x * qinv), q, x);
-}
-
-// Exact conversions between integers below 2^52 and doubles through the
-// mantissa of 2^52 + v (one add and one bit operation instead of the generic
-// conversion sequences).
-constexpr double kTwo52 = 4503599627370496.0;
-__device__ __forceinline__ double u2f(u64 v)
-{
-    return __longlong_as_double((long long)(v | 0x4330000000000000ull)) - kTwo52;
-}
-__device__ __forceinline__ u64 f2u(double y)   // y an integer in [0, 2^52)
-{
-    return (u64)__double_as_longlong(y + kTwo52) & 0xFFFFFFFFFFFFFull;
-}
-
-// canonical residue in [0, q) -> balanced double in (-q/2, q/2]
-__device__ __forceinline__ double to_bal(u64 v, u64 q, double qd)
-{
-    const double d = u2f(v);
-    return v > (q >> 1) ? d - qd : d;
-}
-
-// balanced double (any |x| < 2^52.7) -> canonical residue in [0, q)
-__device__ __forceinline__ u64 to_canon(double x, double q, double qinv)
-{
-    const u64 v = f2u(fbal(x, q, qinv) + q);   // in [q/2 - 1, 3q/2 + 1]
-    const u64 qi = f2u(q);
-    return v >= qi ? v - qi : v;
-}
-#pragma clang fp contract(on)
 
 template <int R, bool INV, bool UNI>
 __device__ __forceinline__ void fp_butterflies(double (&x)[1 << R], const double* tw, u32 hprefix,
@@ -732,34 +688,85 @@ __device__ __forceinline__ void limb_int(u64 (&x)[1 << R], const ulonglong2* tw,
 
 // Per-limb constants of the whole-limb kernel.
 struct LimbK {
+    u32 tid;    // threadIdx.x
     const u64* src;
     u64* dst;
+    const u64* tw64;
+    const double* twf;
     u64 q, cq, one_s;
     double qd, qinv, n1f, w1nf;
     ulonglong2 n1, w1n;
 };
 
-// Forward round i (or inverse round i, walking the forward rounds from the
+// Where limb r's input comes from: the limb itself, or (forward, fused
+// conversion) the one-limb source it is converted from, modulo *cq.
+template <int LOGN, bool INV>
+__device__ __forceinline__ const u64* limb_src(const NttPass& p, u32 r, u64** dst, u32* mod, u64* cq)
+{
+    constexpr u32 n = 1u << LOGN;
+    const u64* src;
+    limb_addr(p.ls, r, n, p.L, &src, dst, mod);
+    *cq = 0;
+    if (!INV && p.ls.cv_src) {
+        const u32 poly = r / p.ls.per_poly;
+        const u32 ct = poly / p.ls.cv_beta, d = poly - ct * p.ls.cv_beta;
+        src = p.ls.cv_src + (size_t)ct * p.ls.cv_ct_stride + (size_t)d * n;
+        *cq = p.mq[p.ls.cv_mod0 + d].q;
+    }
+    return src;
+}
+
+template <int LOGN, bool INV>
+__device__ __forceinline__ LimbK limb_consts(const NttPass& p, u32 r)
+{
+    constexpr u32 n = 1u << LOGN;
+    LimbK c;
+    u32 mod;
+    c.src = limb_src<LOGN, INV>(p, r, &c.dst, &mod, &c.cq);
+    const ModQ& mq = p.mq[mod];
+    c.q = mq.q;
+    c.one_s = mq.one_s;
+    c.tw64 = p.tw + (size_t)mod * n * 2;
+    c.twf = p.twf + (size_t)mod * n;
+    c.n1 = make_ulonglong2(mq.ninv, mq.ninv_s);
+    c.w1n = make_ulonglong2(mq.inw1, mq.inw1_s);
+    c.qd = (double)c.q;
+    c.qinv = 1.0 / c.qd;
+    c.n1f = to_bal(mq.ninv, c.q, c.qd);
+    c.w1nf = to_bal(mq.inw1, c.q, c.qd);
+    return c;
+}
+
+// Round i's geometry: R stages from global stage SG0, groups of 2^R words at
+// index stride 2^LB, GPT groups per thread.
+template <int LOGN, int LOGE, int I>
+struct RoundShape {
+    using S = LimbShape<LOGN, LOGE>;
+    static constexpr int R = S::R(I);
+    static constexpr int SG0 = I * LOGE;
+    static constexpr int E = 1 << R;
+    static constexpr int LB = LOGN - SG0 - R;
+    static constexpr int GPT = 1 << (LOGE - R);
+};
+
+// Forward round I (or inverse round I, walking the forward rounds from the
 // last) over the thread's groups.  FP = the limb is on the FP64 path.
 template <int LOGN, int LOGE, int I, bool INV, bool FP, int RED>
-__device__ __forceinline__ void limb_round(u64* lds, const u64* tw64, const double* twf, const LimbK& c)
+__device__ __forceinline__ void limb_round(u64* lds, const LimbK& c)
 {
     using S = LimbShape<LOGN, LOGE>;
-    constexpr int R = S::R(I);
-    constexpr int SG0 = I * LOGE;
-    constexpr int E = 1 << R;
-    constexpr int LB = LOGN - SG0 - R;
-    constexpr int GPT = 1 << (LOGE - R);
+    using G = RoundShape<LOGN, LOGE, I>;
+    constexpr int R = G::R, SG0 = G::SG0, E = G::E, LB = G::LB, GPT = G::GPT;
     constexpr bool UNI = LB >= 6;
     // the forward transform's first round and the inverse's last face the
-    // canonical limb in global memory; so do the forward's last and the
+    // limb's coefficients in global memory; so do the forward's last and the
     // inverse's first
     constexpr bool FROM_G = INV ? (I == S::NR - 1) : (I == 0);
     constexpr bool TO_G = INV ? (I == 0) : (I == S::NR - 1);
     double* ldf = (double*)lds;
 #pragma unroll
     for (int g = 0; g < GPT; g++) {
-        const u32 gid = threadIdx.x + (u32)g * S::T;
+        const u32 gid = c.tid + (u32)g * S::T;
         const u32 hi = gid >> LB, lo = gid & ((1u << LB) - 1);
         const u32 base = (hi << (LB + R)) | lo;
         const u32 pb = pad(base);
@@ -780,9 +787,9 @@ __device__ __forceinline__ void limb_round(u64* lds, const u64* tw64, const doub
                 for (int m = 0; m < E; m++) x[m] = ldf[pb + padc((u32)m << LB)];
             }
             if constexpr (INV)
-                limb_fp_inv<LOGN, R, SG0, RED, UNI>(x, twf, hi, c.qd, c.qinv, c.n1f, c.w1nf);
+                limb_fp_inv<LOGN, R, SG0, RED, UNI>(x, c.twf, hi, c.qd, c.qinv, c.n1f, c.w1nf);
             else
-                limb_fp_fwd<LOGN, R, SG0, RED, UNI>(x, twf, hi, c.qd, c.qinv);
+                limb_fp_fwd<LOGN, R, SG0, RED, UNI>(x, c.twf, hi, c.qd, c.qinv);
             if (TO_G) {
 #pragma unroll
                 for (int m = 0; m < E; m++) c.dst[base + ((u32)m << LB)] = to_canon(x[m], c.qd, c.qinv);
@@ -804,13 +811,13 @@ __device__ __forceinline__ void limb_round(u64* lds, const u64* tw64, const doub
 #pragma unroll
                 for (int m = 0; m < E; m++) x[m] = lds[pb + padc((u32)m << LB)];
             }
-            limb_int<R, SG0, INV, UNI>(x, (const ulonglong2*)tw64, hi, q, c.n1, c.w1n);
+            limb_int<R, SG0, INV, UNI>(x, (const ulonglong2*)c.tw64, hi, q, c.n1, c.w1n);
             if (TO_G) {
 #pragma unroll
                 for (int m = 0; m < E; m++) {
-                    u64 v = x[m];
-                    if (!INV) v = v >= q2 ? v - q2 : v;
-                    c.dst[base + ((u32)m << LB)] = v >= q ? v - q : v;
+                    u64 y = x[m];
+                    if (!INV) y = y >= q2 ? y - q2 : y;
+                    c.dst[base + ((u32)m << LB)] = y >= q ? y - q : y;
                 }
             } else {
 #pragma unroll
@@ -820,70 +827,56 @@ __device__ __forceinline__ void limb_round(u64* lds, const u64* tw64, const doub
     }
 }
 
+// Rounds I, I+1, ... (inverse: I, I-1, ...) with a barrier between rounds.
 template <int LOGN, int LOGE, bool INV, bool FP, int RED, int I>
-__device__ __forceinline__ void limb_rounds(u64* lds, const u64* tw64, const double* twf, const LimbK& c)
+__device__ __forceinline__ void limb_rounds(u64* lds, const LimbK& c)
 {
     using S = LimbShape<LOGN, LOGE>;
+    static_assert(S::NR >= 2, "whole-limb kernel needs two rounds or more");
     if constexpr (I >= 0 && I < S::NR) {
-        limb_round<LOGN, LOGE, I, INV, FP, RED>(lds, tw64, twf, c);
+        limb_round<LOGN, LOGE, I, INV, FP, RED>(lds, c);
         constexpr int NEXT = INV ? I - 1 : I + 1;
         if constexpr (NEXT >= 0 && NEXT < S::NR) {
             __syncthreads();
-            limb_rounds<LOGN, LOGE, INV, FP, RED, NEXT>(lds, tw64, twf, c);
+            limb_rounds<LOGN, LOGE, INV, FP, RED, NEXT>(lds, c);
         }
     }
 }
 
 template <int LOGN, int LOGE, bool INV>
+__device__ __forceinline__ void limb_transform(u64* lds, const LimbK& c)
+{
+    constexpr int I0 = INV ? LimbShape<LOGN, LOGE>::NR - 1 : 0;
+    if (c.q < (1ull << 51)) {
+        if (!INV) {
+            if (c.q < (1ull << 44))
+                limb_rounds<LOGN, LOGE, INV, true, 0, I0>(lds, c);
+            else if (c.q < (1ull << 50))
+                limb_rounds<LOGN, LOGE, INV, true, 4, I0>(lds, c);
+            else
+                limb_rounds<LOGN, LOGE, INV, true, 2, I0>(lds, c);
+        } else {
+            if (c.q < (1ull << 46))
+                limb_rounds<LOGN, LOGE, INV, true, 4, I0>(lds, c);
+            else
+                limb_rounds<LOGN, LOGE, INV, true, 2, I0>(lds, c);
+        }
+    } else {
+        limb_rounds<LOGN, LOGE, INV, false, 4, I0>(lds, c);
+    }
+}
+
+// One workgroup per limb.  (A persistent variant, one workgroup per CU
+// walking the limbs and pulling the next one into cache during the last
+// round, measured slower: the hardware already starts the next workgroup as
+// soon as the previous one frees the CU's LDS.)
+template <int LOGN, int LOGE, bool INV>
 __global__ __launch_bounds__(1u << (LOGN - LOGE)) void k_ntt_limb(NttPass p)
 {
     extern __shared__ u64 lds[];
-    using S = LimbShape<LOGN, LOGE>;
-    constexpr u32 n = 1u << LOGN;
-    constexpr int I0 = INV ? S::NR - 1 : 0;
-    const u32 r = blockIdx.x;
-    const u64* src;
-    u64* dst;
-    u32 mod;
-    limb_addr(p.ls, r, n, p.L, &src, &dst, &mod);
-    const ModQ& mq = p.mq[mod];
-    LimbK c;
-    c.src = src;
-    c.dst = dst;
-    c.q = mq.q;
-    c.cq = 0;
-    c.one_s = mq.one_s;
-    if (!INV && p.ls.cv_src) {
-        const u32 poly = r / p.ls.per_poly;
-        const u32 ct = poly / p.ls.cv_beta, d = poly - ct * p.ls.cv_beta;
-        c.src = p.ls.cv_src + (size_t)ct * p.ls.cv_ct_stride + (size_t)d * n;
-        c.cq = p.mq[p.ls.cv_mod0 + d].q;
-    }
-    const u64* tw64 = p.tw + (size_t)mod * n * 2;
-    const double* twf = p.twf + (size_t)mod * n;
-    c.n1 = make_ulonglong2(mq.ninv, mq.ninv_s);
-    c.w1n = make_ulonglong2(mq.inw1, mq.inw1_s);
-    if (c.q < (1ull << 51)) {
-        c.qd = (double)c.q;
-        c.qinv = 1.0 / c.qd;
-        c.n1f = to_bal(mq.ninv, c.q, c.qd);
-        c.w1nf = to_bal(mq.inw1, c.q, c.qd);
-        if (!INV) {
-            if (c.q < (1ull << 44))
-                limb_rounds<LOGN, LOGE, INV, true, 0, I0>(lds, tw64, twf, c);
-            else if (c.q < (1ull << 50))
-                limb_rounds<LOGN, LOGE, INV, true, 4, I0>(lds, tw64, twf, c);
-            else
-                limb_rounds<LOGN, LOGE, INV, true, 2, I0>(lds, tw64, twf, c);
-        } else {
-            if (c.q < (1ull << 46))
-                limb_rounds<LOGN, LOGE, INV, true, 4, I0>(lds, tw64, twf, c);
-            else
-                limb_rounds<LOGN, LOGE, INV, true, 2, I0>(lds, tw64, twf, c);
-        }
-    } else {
-        limb_rounds<LOGN, LOGE, INV, false, 4, I0>(lds, tw64, twf, c);
-    }
+    LimbK c = limb_consts<LOGN, INV>(p, blockIdx.x);
+    c.tid = threadIdx.x;
+    limb_transform<LOGN, LOGE, INV>(lds, c);
 }
 
 namespace {
@@ -963,8 +956,7 @@ void launch_pass(const NttPass& p, const PassCfg& c, u32 n_limbs, hipStream_t s)
 {
     if (c.direct == 2) {
         // whole-limb kernel with the geometry fixed at compile time
-        const u32 key = p.log_n * 100 + c.div;
-        switch (key) {
+        switch (p.log_n * 100 + c.div) {
         case 1316: launch_limb<13, 4, INV>(p, n_limbs, s); break;
         case 1332: launch_limb<13, 5, INV>(p, n_limbs, s); break;
         case 1416: launch_limb<14, 4, INV>(p, n_limbs, s); break;
@@ -1029,7 +1021,7 @@ void run_plan(vr_context* ctx, const LimbSet& ls, const std::vector<PassCfg>& pa
     }
 }
 
-// Times every candidate plan on 256 scratch limbs of the Q chain (five runs
+// Times every candidate plan on 256-2048 scratch limbs of the Q chain (five runs
 // each after a warm-up) and keeps the fastest; a later candidate replaces an
 // earlier one only when it is more than 8 % faster, so that plans within the
 // timing noise of each other do not flip from run to run.
@@ -1038,7 +1030,9 @@ std::vector<PassCfg> tune(vr_context* ctx, hipStream_t s)
 {
     auto cands = candidates(ctx->log_n);
     if (cands.size() < 2) return cands.empty() ? default_plan(ctx->log_n) : cands[0];
-    const u32 per = ctx->L + 1, polys = (256 + per - 1) / per;
+    // several limbs per CU, as in a layer's launches, within 256 MiB
+    const u32 want = std::max(256u, std::min(2048u, (u32)((256u << 20) / (8ull * ctx->n))));
+    const u32 per = ctx->L + 1, polys = (want + per - 1) / per;
     const size_t words = (size_t)per * polys * ctx->n;
     void* buf = ctx->arena->alloc(words * sizeof(u64), s);
     if (!buf) return default_plan(ctx->log_n);

@@ -98,6 +98,67 @@ __device__ __forceinline__ u64 shoup(u64 x, u64 w, u64 ws, u64 q)
     return csub(shoup_lazy(x, w, ws, q), q);
 }
 
+
+// ---------------------------------------------- exact modular FP64 arithmetic
+//
+// For q < 2^51 residues and constants are integers held exactly in doubles,
+// in balanced form |x| <= q/2.  A product y w mod q is p = y w with its exact
+// low part e = fma(y, w, -p), t = rint(p / q) and r = fma(-t, q, p) + e: an
+// exact integer congruent to y w, within q + |e| of zero while |p / q| stays
+// well below 2^52 (|e| <= ulp(p) / 2).  Sums of such values stay exact below
+// 2^53.  No contraction may merge these operations (the split of y w into
+// p + e relies on p being the rounded product), hence the per-function
+// pragma.
+
+// y w mod q as an exact integer in about (-1.4 q, 1.4 q), for |y w| < 2^104
+__device__ __forceinline__ double fmulmod(double y, double w, double q, double qinv)
+{
+#pragma clang fp contract(off)
+    const double p = y * w;
+    const double e = __fma_rn(y, w, -p);
+    const double t = rint(p * qinv);
+    return __fma_rn(-t, q, p) + e;
+}
+
+// x - q rint(x / q): balanced representative, |result| <= q/2 + 1
+__device__ __forceinline__ double fbal(double x, double q, double qinv)
+{
+#pragma clang fp contract(off)
+    return __fma_rn(-rint(x * qinv), q, x);
+}
+
+// Exact conversions between integers below 2^52 and doubles through the
+// mantissa of 2^52 + v (one add and one bit operation instead of the generic
+// conversion sequences).
+constexpr double kTwo52 = 4503599627370496.0;
+__device__ __forceinline__ double u2f(u64 v)
+{
+#pragma clang fp contract(off)
+    return __longlong_as_double((long long)(v | 0x4330000000000000ull)) - kTwo52;
+}
+__device__ __forceinline__ u64 f2u(double y)   // y an integer in [0, 2^52)
+{
+#pragma clang fp contract(off)
+    return (u64)__double_as_longlong(y + kTwo52) & 0xFFFFFFFFFFFFFull;
+}
+
+// canonical residue in [0, q) -> balanced double in (-q/2, q/2]
+__device__ __forceinline__ double to_bal(u64 v, u64 q, double qd)
+{
+#pragma clang fp contract(off)
+    const double d = u2f(v);
+    return v > (q >> 1) ? d - qd : d;
+}
+
+// balanced double (any |x| < 2^52.7) -> canonical residue in [0, q)
+__device__ __forceinline__ u64 to_canon(double x, double q, double qinv)
+{
+#pragma clang fp contract(off)
+    const u64 v = f2u(fbal(x, q, qinv) + q);   // in [q/2 - 1, 3q/2 + 1]
+    const u64 qi = f2u(q);
+    return v >= qi ? v - qi : v;
+}
+
 __device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) { return csub(a + b, q); }
 __device__ __forceinline__ u64 neg_mod(u64 a, u64 q) { return a ? q - a : 0; }
 __device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }

@@ -67,6 +67,41 @@ def test_ntt_every_plan_reduction_bands(log_n):
         tried += 1
 
 
+@pytest.mark.parametrize("log_n", [13, 14])
+def test_ntt_every_plan_many_limbs(log_n):
+    """600 limbs in one launch (more than one per CU, so persistent plans walk
+    several limbs per workgroup): sampled limbs, including ones a workgroup
+    reaches on a later iteration, against the oracle, and the exact round
+    trip for all, under every plan."""
+    import torch
+    from paper_2512_18646_amd import vr
+    p = Params(log_n, [60, 50, 40], [51], 1, 30.0, allow_insecure=True)
+    o, g = OracleContext(p), gpu_ctx(p)
+    mods = o.q + o.p
+    count = 600
+    rng = np.random.default_rng(100 + log_n)
+    host = np.stack([rng.integers(0, mods[i % 4], o.n, dtype=np.uint64) for i in range(count)])
+    mi = [i % 4 for i in range(count)]
+    sample = [0, 1, 255, 256, 257, 300, 511, 512, 513, 599]
+    tried = 0
+    while True:
+        g.set_tuning("ntt", "cand:%d" % tried)
+        dev = torch.from_numpy(host.view(np.int64).copy()).cuda()
+        try:
+            g.ntt_device(dev.data_ptr(), count, mi)
+        except vr.VRError as e:
+            assert e.code == vr.VR_EINVAL and tried >= 1
+            break
+        torch.cuda.synchronize()
+        fwd = dev.cpu().numpy().view(np.uint64)
+        for r in sample:
+            assert np.array_equal(fwd[r], o.ntt(host[r], mods[mi[r]])), (tried, r)
+        g.ntt_device(dev.data_ptr(), count, mi, inverse=True)
+        torch.cuda.synchronize()
+        assert np.array_equal(dev.cpu().numpy().view(np.uint64), host), tried
+        tried += 1
+
+
 def check_ntt(o, g, log_n, reps=3):
     import torch
     mods = o.q + o.p
