@@ -209,50 +209,50 @@ __global__ __launch_bounds__(256) void k_base_convert_mfma(ConvArgs a, const u64
 // themselves under X -> X^g).  So each thread loads its source words
 // coalesced, takes the key at its output index (loaded once per block, the
 // key being shared by every ciphertext of the batch), and writes its output
-// within that chunk: no staging and no barrier per ciphertext.
-template <int MAXB>
+// within that chunk: no staging and no barrier per ciphertext.  The next
+// ciphertext's digits are loaded while the current one is summed.
+//
+// FP = the launch covers limbs whose moduli are below 2^51: FP64 products
+// with key and inputs balanced, each product within 0.75 q, the sums reduced
+// every four digits (below 3.5 q < 2^53).  Otherwise 128-bit integer sums.
+// Limbs e0 .. e0 + gridDim.y - 1 of the extended basis.
+template <int MAXB, bool FP>
 __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_stride, u32 n_ct,
                                                       const u64* key, u32 nmod, u32 level,
                                                       u32 next, u32 beta, u32 L, u32 log_n, u32 g_inv,
-                                                      u64* U, u64 u_stride, const ModQ* mq)
+                                                      u64* U, u64 u_stride, const ModQ* mq, u32 e0)
 {
     const u32 n = 1u << log_n;
     const u32 s = blockIdx.x * kThreads + threadIdx.x;
     if (s >= n) return;
-    const u32 e = blockIdx.y;
+    const u32 e = e0 + blockIdx.y;
     const u32 mod = e <= level ? e : L + 1 + (e - level - 1);
     const ModQ m = mq[mod];
     const u32 t = g_inv != 1 ? galois_src(s, g_inv, log_n) : s;
-    u64 kb[MAXB], ka[MAXB];
-#pragma unroll
-    for (int j = 0; j < MAXB; j++) {
-        if (j < (int)beta) {
-            kb[j] = key[((size_t)(2 * j) * nmod + mod) * n + t];
-            ka[j] = key[((size_t)(2 * j + 1) * nmod + mod) * n + t];
-        }
-    }
     // blockIdx.z splits the ciphertexts into groups so small rings still fill the chip
     const u32 per = (n_ct + gridDim.z - 1) / gridDim.z;
     const u32 c_lo = blockIdx.z * per, c_hi = min(n_ct, c_lo + per);
-    if (m.q < (1ull << 51)) {
-        // FP64 products (one modulus per block): key and inputs balanced,
-        // each product within 0.75 q, the sums reduced every four digits
-        // (below 3.5 q < 2^53)
+    if (c_lo >= c_hi) return;
+    auto load = [&](u32 c, u64 (&xv)[MAXB]) {
+        const u64* xc = X + (size_t)c * x_stride + (size_t)e * n + s;
+#pragma unroll
+        for (int j = 0; j < MAXB; j++)
+            if (j < (int)beta) xv[j] = xc[(size_t)j * next * n];
+    };
+    if constexpr (FP) {
         const double qd = (double)m.q, qinv = 1.0 / qd;
         double fb[MAXB], fa[MAXB];
 #pragma unroll
         for (int j = 0; j < MAXB; j++) {
             if (j < (int)beta) {
-                fb[j] = to_bal(kb[j], m.q, qd);
-                fa[j] = to_bal(ka[j], m.q, qd);
+                fb[j] = to_bal(key[((size_t)(2 * j) * nmod + mod) * n + t], m.q, qd);
+                fa[j] = to_bal(key[((size_t)(2 * j + 1) * nmod + mod) * n + t], m.q, qd);
             }
         }
+        u64 xv[MAXB], xn[MAXB];
+        load(c_lo, xv);
         for (u32 c = c_lo; c < c_hi; c++) {
-            const u64* xc = X + (size_t)c * x_stride + (size_t)e * n + s;
-            u64 xv[MAXB];
-#pragma unroll
-            for (int j = 0; j < MAXB; j++)
-                if (j < (int)beta) xv[j] = xc[(size_t)j * next * n];
+            if (c + 1 < c_hi) load(c + 1, xn);
             double s0 = 0, s1 = 0;
 #pragma unroll
             for (int j = 0; j < MAXB; j++) {
@@ -269,23 +269,33 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
             u64* u = U + (size_t)c * u_stride + (size_t)e * n + t;
             u[0] = to_canon(s0, qd, qinv);
             u[(size_t)next * n] = to_canon(s1, qd, qinv);
+#pragma unroll
+            for (int j = 0; j < MAXB; j++) xv[j] = xn[j];
         }
-        return;
-    }
-    for (u32 c = c_lo; c < c_hi; c++) {
-        const u64* xc = X + (size_t)c * x_stride + (size_t)e * n + s;
-        u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+    } else {
+        u64 kb[MAXB], ka[MAXB];
 #pragma unroll
         for (int j = 0; j < MAXB; j++) {
             if (j < (int)beta) {
-                const u64 xv = xc[(size_t)j * next * n];
-                mac128(h0, l0, xv, kb[j]);
-                mac128(h1, l1, xv, ka[j]);
+                kb[j] = key[((size_t)(2 * j) * nmod + mod) * n + t];
+                ka[j] = key[((size_t)(2 * j + 1) * nmod + mod) * n + t];
             }
         }
-        u64* u = U + (size_t)c * u_stride + (size_t)e * n + t;
-        u[0] = reduce128(h0, l0, m);
-        u[(size_t)next * n] = reduce128(h1, l1, m);
+        for (u32 c = c_lo; c < c_hi; c++) {
+            u64 xv[MAXB];
+            load(c, xv);
+            u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+#pragma unroll
+            for (int j = 0; j < MAXB; j++) {
+                if (j < (int)beta) {
+                    mac128(h0, l0, xv[j], kb[j]);
+                    mac128(h1, l1, xv[j], ka[j]);
+                }
+            }
+            u64* u = U + (size_t)c * u_stride + (size_t)e * n + t;
+            u[0] = reduce128(h0, l0, m);
+            u[(size_t)next * n] = reduce128(h1, l1, m);
+        }
     }
 }
 
@@ -601,22 +611,40 @@ void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, u32 n_ct
         g_inv = (u32)r;
     }
     ProfScope prof(ctx, kProfKsInner, s, (u64)n_ct * k.next);
-    if (k.beta <= 4)
-        hipLaunchKernelGGL((k_ks_inner<4>), grid, dim3(kThreads), 0, s, X, x_stride, n_ct, key,
-                           ctx->nmod(), level, k.next, k.beta, ctx->L, ctx->log_n, g_inv, U, u_stride,
-                           ctx->d_modq);
-    else if (k.beta <= 8)
-        hipLaunchKernelGGL((k_ks_inner<8>), grid, dim3(kThreads), 0, s, X, x_stride, n_ct, key,
-                           ctx->nmod(), level, k.next, k.beta, ctx->L, ctx->log_n, g_inv, U, u_stride,
-                           ctx->d_modq);
-    else if (k.beta <= 16)
-        hipLaunchKernelGGL((k_ks_inner<16>), grid, dim3(kThreads), 0, s, X, x_stride, n_ct, key,
-                           ctx->nmod(), level, k.next, k.beta, ctx->L, ctx->log_n, g_inv, U, u_stride,
-                           ctx->d_modq);
-    else
-        throw Error(VR_EINVAL, "key switching: more than 16 digits");
-    VR_CHECK_LAUNCH();
+    if (k.beta > 16) throw Error(VR_EINVAL, "key switching: more than 16 digits");
+    // one launch per run of consecutive extended limbs on the same path
+    // (FP64 below 2^51, else integer), so each kernel gets its own registers
+    u32 e_begin = 0;
+    while (e_begin < k.next) {
+        const bool fp = ctx->modq[ctx->ext_mod(e_begin, level)].q < (1ull << 51);
+        u32 e_end = e_begin + 1;
+        while (e_end < k.next && (ctx->modq[ctx->ext_mod(e_end, level)].q < (1ull << 51)) == fp) e_end++;
+        dim3 g2(grid.x, e_end - e_begin, grid.z);
+#define VR_KS_INNER(B, F)                                                                             \
+    hipLaunchKernelGGL((k_ks_inner<B, F>), g2, dim3(kThreads), 0, s, X, x_stride, n_ct, key, ctx->nmod(), \
+                       level, k.next, k.beta, ctx->L, ctx->log_n, g_inv, U, u_stride, ctx->d_modq, e_begin)
+        if (k.beta <= 4) {
+            if (fp)
+                VR_KS_INNER(4, true);
+            else
+                VR_KS_INNER(4, false);
+        } else if (k.beta <= 8) {
+            if (fp)
+                VR_KS_INNER(8, true);
+            else
+                VR_KS_INNER(8, false);
+        } else {
+            if (fp)
+                VR_KS_INNER(16, true);
+            else
+                VR_KS_INNER(16, false);
+        }
+#undef VR_KS_INNER
+        VR_CHECK_LAUNCH();
+        e_begin = e_end;
+    }
 }
+
 
 void keyswitch_inner(vr_context* ctx, const u64* X, const u64* key, u32 level, u32 g, u64* U,
                      hipStream_t s)
