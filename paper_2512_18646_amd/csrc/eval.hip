@@ -285,8 +285,16 @@ void rescale_dense(vr_context* ctx, const u64* in, u64* out, u32 n_polys, u32 le
     lr.cv_ct_stride = n;
     lr.cv_beta = 1;
     lr.cv_mod0 = level;
-    ntt_forward(ctx, lr, s);
-    launch_rescale_finish(ctx, out, in, r, n_polys, level, s);
+    // (c - r) q_l^-1 in the transform's last round where the plan allows
+    NttEpilogue& ep = lr.epi;
+    ep.a = in;
+    ep.a_ct = (u64)2 * (level + 1) * n;
+    ep.a_comp = (u64)(level + 1) * n;
+    ep.out0 = out;
+    ep.out1 = out + (size_t)level * n;
+    ep.out_ct = (u64)2 * level * n;
+    ep.cmul = ctx->d_rinv_tab + (size_t)level * ctx->nmod();
+    if (!ntt_forward(ctx, lr, s)) launch_rescale_finish(ctx, out, in, r, n_polys, level, s);
 }
 
 vr_ciphertext* ev_rescale(vr_context* ctx, const vr_ciphertext* a, hipStream_t s)

@@ -34,14 +34,6 @@ namespace {
 constexpr int kThreads = 256;
 constexpr int kMaxIn = 16;
 
-__device__ __forceinline__ u32 brev_n(u32 x, u32 log_n) { return __brev(x) >> (32 - log_n); }
-
-__device__ __forceinline__ u32 galois_src(u32 i, u32 g, u32 log_n)
-{
-    u32 mask = (2u << log_n) - 1;
-    u32 e = (u32)(((u64)g * (2 * brev_n(i, log_n) + 1)) & mask);
-    return brev_n((e - 1) >> 1, log_n);
-}
 
 typedef int v4i __attribute__((ext_vector_type(4)));
 
@@ -692,7 +684,21 @@ void keyswitch_moddown_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u3
         a.mq = ctx->d_modq;
         launch_convert(ctx, a, tb, n_ct * 2, s);
     }
-    ntt_forward(ctx, ly, s);
+    // (U - Y) P^-1 (+ add) in the forward transform's last round where the
+    // plan allows, else by the finish kernel
+    NttEpilogue& ep = ly.epi;
+    ep.a = U;
+    ep.a_ct = u_stride;
+    ep.a_comp = (u64)k.next * n;
+    ep.out0 = out0;
+    ep.out1 = out1;
+    ep.out_ct = out_stride;
+    ep.add0 = add0;
+    ep.add1 = add1;
+    ep.add_ct = add_stride;
+    ep.add0_g = add0_g;
+    ep.cmul = ctx->d_pinv_tab;
+    if (ntt_forward(ctx, ly, s)) return;
     dim3 grid((n + kThreads - 1) / kThreads, n_ct * k.nq);
     ProfScope prof(ctx, kProfModDown, s, (u64)n_ct * 2 * k.nq);
     hipLaunchKernelGGL(k_moddown_finish, grid, dim3(kThreads), 0, s, U, u_stride, Y, k.nq, k.next,

@@ -696,6 +696,14 @@ struct LimbK {
     u64 q, cq, one_s;
     double qd, qinv, n1f, w1nf;
     ulonglong2 n1, w1n;
+    // forward epilogue (ea != null): this limb's rows of A, of the output and
+    // of B (eb_g: Galois element B is read through), and its scaling
+    const u64* ea;
+    u64* eo;
+    const u64* eb;
+    u32 eb_g;
+    ulonglong2 ec;
+    double ecf;
 };
 
 // Where limb r's input comes from: the limb itself, or (forward, fused
@@ -734,6 +742,19 @@ __device__ __forceinline__ LimbK limb_consts(const NttPass& p, u32 r)
     c.qinv = 1.0 / c.qd;
     c.n1f = to_bal(mq.ninv, c.q, c.qd);
     c.w1nf = to_bal(mq.inw1, c.q, c.qd);
+    c.ea = nullptr;
+    if (!INV && p.ls.epi.a) {
+        const NttEpilogue& ep = p.ls.epi;
+        const u32 poly = r / p.ls.per_poly, i = r - poly * p.ls.per_poly;
+        const u32 k = poly >> 1, j = poly & 1;
+        c.ea = ep.a + k * ep.a_ct + j * ep.a_comp + (size_t)i * n;
+        c.eo = (j ? ep.out1 : ep.out0) + k * ep.out_ct + (size_t)i * n;
+        const u64* add = j ? ep.add1 : ep.add0;
+        c.eb = add ? add + k * ep.add_ct + (size_t)i * n : nullptr;
+        c.eb_g = j ? 1 : ep.add0_g;
+        c.ec = ep.cmul[mod];
+        c.ecf = to_bal(c.ec.x, c.q, c.qd);
+    }
     return c;
 }
 
@@ -790,7 +811,23 @@ __device__ __forceinline__ void limb_round(u64* lds, const LimbK& c)
                 limb_fp_inv<LOGN, R, SG0, RED, UNI>(x, c.twf, hi, c.qd, c.qinv, c.n1f, c.w1nf);
             else
                 limb_fp_fwd<LOGN, R, SG0, RED, UNI>(x, c.twf, hi, c.qd, c.qinv);
-            if (TO_G) {
+            if (TO_G && !INV && c.ea) {
+                // (A - y) c (+ B): |A - y| < 27 q, the product within 1.5 q
+                // (3 q when q >= 2^50), reduced before B is added
+                u64 av[E], bv[E];
+#pragma unroll
+                for (int m = 0; m < E; m++) {
+                    const u32 idx = base + ((u32)m << LB);
+                    av[m] = c.ea[idx];
+                    if (c.eb) bv[m] = c.eb[c.eb_g != 1 ? galois_src(idx, c.eb_g, LOGN) : idx];
+                }
+#pragma unroll
+                for (int m = 0; m < E; m++) {
+                    double v = fbal(fmulmod(to_bal(av[m], c.q, c.qd) - x[m], c.ecf, c.qd, c.qinv), c.qd, c.qinv);
+                    if (c.eb) v += to_bal(bv[m], c.q, c.qd);
+                    c.eo[base + ((u32)m << LB)] = to_canon(v, c.qd, c.qinv);
+                }
+            } else if (TO_G) {
 #pragma unroll
                 for (int m = 0; m < E; m++) c.dst[base + ((u32)m << LB)] = to_canon(x[m], c.qd, c.qinv);
             } else {
@@ -812,7 +849,24 @@ __device__ __forceinline__ void limb_round(u64* lds, const LimbK& c)
                 for (int m = 0; m < E; m++) x[m] = lds[pb + padc((u32)m << LB)];
             }
             limb_int<R, SG0, INV, UNI>(x, (const ulonglong2*)c.tw64, hi, q, c.n1, c.w1n);
-            if (TO_G) {
+            if (TO_G && !INV && c.ea) {
+                u64 av[E], bv[E];
+#pragma unroll
+                for (int m = 0; m < E; m++) {
+                    const u32 idx = base + ((u32)m << LB);
+                    av[m] = c.ea[idx];
+                    if (c.eb) bv[m] = c.eb[c.eb_g != 1 ? galois_src(idx, c.eb_g, LOGN) : idx];
+                }
+#pragma unroll
+                for (int m = 0; m < E; m++) {
+                    u64 y = x[m];
+                    y = y >= q2 ? y - q2 : y;
+                    y = y >= q ? y - q : y;
+                    u64 v = shoup(av[m] + q - y, c.ec.x, c.ec.y, q);
+                    if (c.eb) v = add_mod(v, bv[m], q);
+                    c.eo[base + ((u32)m << LB)] = v;
+                }
+            } else if (TO_G) {
 #pragma unroll
                 for (int m = 0; m < E; m++) {
                     u64 y = x[m];
@@ -1086,19 +1140,29 @@ std::vector<PassCfg> plan_for(vr_context* ctx, hipStream_t s)
     return p;
 }
 
+// Runs the transform; a forward epilogue is applied when the plan is one
+// whole-limb pass, else dropped (the transform is stored) and false returned.
 template <bool INV>
-void run(vr_context* ctx, const LimbSet& ls, hipStream_t s)
+bool run(vr_context* ctx, const LimbSet& ls, hipStream_t s)
 {
     u32 n_limbs = ls.per_poly * ls.n_polys;
-    if (n_limbs == 0) return;
     std::vector<PassCfg> passes = plan_for<INV>(ctx, s);
+    const bool fuse = !INV && ls.epi.a && passes.size() == 1 && passes[0].direct == 2;
+    if (n_limbs == 0) return fuse;
     ProfScope prof(ctx, kProfNtt, s, n_limbs);
-    run_plan<INV>(ctx, ls, passes, s);
+    if (fuse || !ls.epi.a) {
+        run_plan<INV>(ctx, ls, passes, s);
+    } else {
+        LimbSet plain = ls;
+        plain.epi = NttEpilogue();
+        run_plan<INV>(ctx, plain, passes, s);
+    }
+    return fuse;
 }
 
 }  // namespace
 
-void ntt_forward(vr_context* ctx, const LimbSet& ls, hipStream_t s) { run<false>(ctx, ls, s); }
-void ntt_inverse(vr_context* ctx, const LimbSet& ls, hipStream_t s) { run<true>(ctx, ls, s); }
+bool ntt_forward(vr_context* ctx, const LimbSet& ls, hipStream_t s) { return run<false>(ctx, ls, s); }
+void ntt_inverse(vr_context* ctx, const LimbSet& ls, hipStream_t s) { (void)run<true>(ctx, ls, s); }
 
 }  // namespace vr

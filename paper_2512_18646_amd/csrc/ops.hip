@@ -19,16 +19,6 @@ inline dim3 grid_for(size_t elems)
     return dim3((unsigned)((pairs + kThreads - 1) / kThreads));
 }
 
-__device__ __forceinline__ u32 brev_n(u32 x, u32 log_n) { return __brev(x) >> (32 - log_n); }
-
-// index in the evaluation domain that sigma_g reads for output slot i:
-// out[i] = in[brev((g (2 brev(i) + 1) mod 2N - 1) / 2)]
-__device__ __forceinline__ u32 galois_src(u32 i, u32 g, u32 log_n)
-{
-    u32 two_n_mask = (2u << log_n) - 1;
-    u32 e = (u32)(((u64)g * (2 * brev_n(i, log_n) + 1)) & two_n_mask);
-    return brev_n((e - 1) >> 1, log_n);
-}
 
 __global__ void k_addsub(u64* out, const u64* a, const u64* b, size_t elems, u32 log_n, u32 nl,
                          const ModQ* mq, int sub)

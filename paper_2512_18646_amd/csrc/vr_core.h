@@ -159,6 +159,17 @@ __device__ __forceinline__ u64 to_canon(double x, double q, double qinv)
     return v >= qi ? v - qi : v;
 }
 
+__device__ __forceinline__ u32 brev_n(u32 x, u32 log_n) { return __brev(x) >> (32 - log_n); }
+
+// index in the evaluation domain that sigma_g reads for output slot i:
+// out[i] = in[brev((g (2 brev(i) + 1) mod 2N - 1) / 2)]
+__device__ __forceinline__ u32 galois_src(u32 i, u32 g, u32 log_n)
+{
+    const u32 two_n_mask = (2u << log_n) - 1;
+    const u32 e = (u32)(((u64)g * (2 * brev_n(i, log_n) + 1)) & two_n_mask);
+    return brev_n((e - 1) >> 1, log_n);
+}
+
 __device__ __forceinline__ u64 add_mod(u64 a, u64 b, u64 q) { return csub(a + b, q); }
 __device__ __forceinline__ u64 neg_mod(u64 a, u64 q) { return a ? q - a : 0; }
 __device__ __forceinline__ u64 sub_mod(u64 a, u64 b, u64 q) { return a >= b ? a - b : a + q - b; }
@@ -291,6 +302,10 @@ struct vr_context {
     double* d_twf = nullptr;          // [nmod][N] psi^brev(k) in (-q/2, q/2] (FP64 butterflies)
     double* d_itwf = nullptr;         // [nmod][N] psi^-brev(k) likewise
     double* d_fft_tw = nullptr;       // [N] complex e^{-2 pi i k / 2N}
+    // (c, Shoup companion) per modulus: P^-1 mod q_i (Q chain), and for each
+    // level l, q_l^-1 mod q_i at [l][i] (i < l): the ModDown and rescale scalings
+    ulonglong2* d_pinv_tab = nullptr;  // [nmod]
+    ulonglong2* d_rinv_tab = nullptr;  // [L + 1][nmod]
     int* d_gexp = nullptr;            // [S] 5^j mod 2N
     vr::u64 cdt[20];
     std::map<std::pair<int, int>, vr::ConvTable> modup_tables;   // (level, digit)
@@ -397,6 +412,27 @@ struct ProfScope {
 // skipped range is the Q limbs of digit (poly % beta) (ModUp targets).  The
 // output goes to the same place in `out`, or densely to out + r * N when
 // out_dense is set.
+// Finish of a forward transform (ModDown, rescale): instead of the transform
+// y of limb i of poly p = 2 k + j (ciphertext k, component j), store
+// (A - y) c (+ B) mod q, with A(p, i) = a + k a_ct + j a_comp + i N,
+// out(p, i) = out_j + k out_ct + i N, B(p, i) = add_j + k add_ct + i N
+// (component 0 read through sigma_g when add0_g != 1, a null add_j adds
+// nothing) and (c, floor(c 2^64 / q)) = cmul[modulus of the limb].  The
+// limbs of each poly are its first per_poly ones (no skip).  Applied only by
+// the whole-limb transform; ntt_forward reports whether it was.
+struct NttEpilogue {
+    const u64* a = nullptr;        // non-null: the epilogue is requested
+    u64 a_ct = 0, a_comp = 0;
+    u64* out0 = nullptr;
+    u64* out1 = nullptr;
+    u64 out_ct = 0;
+    const u64* add0 = nullptr;
+    const u64* add1 = nullptr;
+    u64 add_ct = 0;
+    u32 add0_g = 1;
+    const ulonglong2* cmul = nullptr;
+};
+
 struct LimbSet {
     u64* in = nullptr;
     u64* out = nullptr;          // may equal in
@@ -416,9 +452,12 @@ struct LimbSet {
     const u64* cv_src = nullptr;
     u64 cv_ct_stride = 0;
     u32 cv_beta = 1, cv_mod0 = 0;
+    NttEpilogue epi;   // forward only, see NttEpilogue
 };
 
-void ntt_forward(vr_context* ctx, const LimbSet& ls, hipStream_t s);
+// Returns whether ls.epi was applied (false when it is unset or the plan
+// for this ring has no whole-limb pass: then the transform is stored).
+bool ntt_forward(vr_context* ctx, const LimbSet& ls, hipStream_t s);
 void ntt_inverse(vr_context* ctx, const LimbSet& ls, hipStream_t s);
 
 inline LimbSet poly_limbs(u64* in, u64* out, u32 n_polys, u32 per_poly, u64 poly_stride, int level)

@@ -277,6 +277,31 @@ def test_keyswitch_match_other_chains(name, level, mode):
         g.set_tuning("base_convert", "auto")
 
 
+@pytest.mark.parametrize("plan", ["auto", "cand:0"])
+@pytest.mark.parametrize("name,level", [("C1", 3), ("C2", 7), ("C2", 1)])
+def test_finish_in_transform_and_separate_match(name, level, plan):
+    """ModDown's (U - Y) P^-1 (+ the Galois-mapped c_0 of a rotation) and
+    rescale's (c - r) q_l^-1 run in the forward transform's last round under
+    the whole-limb plan the autotuner keeps at N = 2^13 and 2^14, and in their
+    own kernels under a plan without a whole-limb pass (cand:0): both against
+    the oracle."""
+    o, ok, g, gk = pair(name, rot_steps=(1, 3))
+    z = np.random.default_rng(40 + level).uniform(-1, 1, o.slots)
+    a = o.encrypt(ok, o.encode(z, level, o.scale), 11, level)
+    ga = to_gpu(g, a)
+    g.set_tuning("ntt", plan)
+    try:
+        assert_same(g.rotate(gk, ga, 1), o.rotate(a, 1, ok), "%s rotate %s" % (name, plan))
+        many = g.rotate_many(gk, ga, [3, 1])
+        assert_same(many[0], o.rotate(a, 3, ok), "%s hoisted 3 %s" % (name, plan))
+        t = o.tensor(a, a)
+        assert_same(g.relinearize(gk, to_gpu(g, t)), o.relinearize(t, ok), "%s relin %s" % (name, plan))
+        assert_same(g.rescale(ga), o.rescale(a), "%s rescale %s" % (name, plan))
+        assert_same(g.rescale(to_gpu(g, t)), o.rescale(t), "%s rescale 3 comps %s" % (name, plan))
+    finally:
+        g.set_tuning("ntt", "auto")
+
+
 def test_error_paths(c1):
     from paper_2512_18646_amd import vr
     o, ok, g, gk = c1
