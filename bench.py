@@ -75,10 +75,12 @@ def percentile(xs, p):
     return float(np.percentile(np.asarray(xs), p)) if xs else None
 
 
-def conv_setup(vr, level, sets):
+def conv_setup(vr, level, sets, ntt_plan="auto"):
     import synthetic_inputs as SI
     W = SI.CONV_28
     ctx = vr.Context(14, [60] + [40] * 7, [60], 8, 40.0)
+    if ntt_plan != "auto":
+        ctx.set_tuning("ntt", ntt_plan)
     keys = ctx.keygen(1002, rot_steps=[1, 2, 3])
     _, K, bias = W.draw()
     cols = []
@@ -533,6 +535,9 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=60)
     ap.add_argument("--serve-load", default="0.8,2.0",
                     help="offered loads, as fractions of the one-request-at-a-time service rate")
+    ap.add_argument("--ntt-plan", default="auto",
+                    help="NTT pass plan of the main workload: auto (autotuned), fixed, or cand:i "
+                         "(pins the plan, e.g. for counter runs)")
     ap.add_argument("--breakdown", action="store_true",
                     help="one extra step per kernel class, reporting its device time per step")
     args = ap.parse_args()
@@ -552,7 +557,7 @@ def main():
         sync()
         del src, dst
     log("setup: encrypting %d sets of 256 images at level %d" % (args.sets, args.level))
-    W, ctx, keys, K, bias, cols = conv_setup(vr, args.level, args.sets)
+    W, ctx, keys, K, bias, cols = conv_setup(vr, args.level, args.sets, args.ntt_plan)
     images = W.batch * args.sets
 
     for i in range(args.warmup):
