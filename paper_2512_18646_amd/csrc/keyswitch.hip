@@ -207,17 +207,25 @@ __global__ __launch_bounds__(256) void k_base_convert_mfma(ConvArgs a, const u64
 // FP = the launch covers limbs whose moduli are below 2^51: FP64 products
 // with key and inputs balanced, each product within 0.75 q, the sums reduced
 // every four digits (below 3.5 q < 2^53).  Otherwise 128-bit integer sums.
-// Limbs e0 .. e0 + gridDim.y - 1 of the extended basis.
+// The launch covers the extended limbs of up to kMaxRuns runs [b, b + len),
+// blockIdx.y enumerating them in order.
+constexpr int kMaxRuns = 4;
+struct LimbRuns {
+    u32 b[kMaxRuns], len[kMaxRuns];
+};
+
 template <int MAXB, bool FP>
 __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_stride, u32 n_ct,
                                                       const u64* key, u32 nmod, u32 level,
                                                       u32 next, u32 beta, u32 L, u32 log_n, u32 g_inv,
-                                                      u64* U, u64 u_stride, const ModQ* mq, u32 e0)
+                                                      u64* U, u64 u_stride, const ModQ* mq, LimbRuns runs)
 {
     const u32 n = 1u << log_n;
     const u32 s = blockIdx.x * kThreads + threadIdx.x;
     if (s >= n) return;
-    const u32 e = e0 + blockIdx.y;
+    u32 e = blockIdx.y, r = 0;
+    while (r + 1 < kMaxRuns && e >= runs.len[r]) e -= runs.len[r++];
+    e += runs.b[r];
     const u32 mod = e <= level ? e : L + 1 + (e - level - 1);
     const ModQ m = mq[mod];
     const u32 t = g_inv != 1 ? galois_src(s, g_inv, log_n) : s;
@@ -289,6 +297,19 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
             u[(size_t)next * n] = reduce128(h1, l1, m);
         }
     }
+}
+
+// X_c row (i / alpha) next + i <- limb i of d_c (i = blockIdx.y, c = blockIdx.z),
+// as 16-byte pairs
+__global__ __launch_bounds__(kThreads) void k_own_limbs(u64* X, u64 xs, const u64* d, u64 d_stride,
+                                                       u32 next, u32 alpha, u32 n)
+{
+    const u32 k = blockIdx.x * kThreads + threadIdx.x;
+    if (k >= n / 2) return;
+    const u32 i = blockIdx.y, c = blockIdx.z;
+    const ulonglong2* src = (const ulonglong2*)(d + (size_t)c * d_stride + (size_t)i * n);
+    ulonglong2* dst = (ulonglong2*)(X + (size_t)c * xs + ((size_t)(i / alpha) * next + i) * n);
+    dst[k] = src[k];
 }
 
 // out_k = (U_k - Y_k) * P^-1 (+ add_k), k = 0, 1; limb i < nq
@@ -547,9 +568,14 @@ void keyswitch_modup_batch(vr_context* ctx, const u64* d, u64 d_stride, u32 n_ct
             a.mq = ctx->d_modq;
             launch_convert(ctx, a, tb, n_ct, s);
         }
-        // the digit's own limbs are d itself (already in the evaluation domain)
-        launch_copy_rows(X + ((size_t)j * k.next + lo) * n, xs, d + (size_t)lo * n, d_stride,
-                         (u64)(hi - lo) * n, n_ct, s);
+    }
+    // each digit's own limbs are d itself (already in the evaluation domain):
+    // one launch places limb i of every d_c at row (i / alpha) next + i of X_c
+    {
+        dim3 grid((n / 2 + kThreads - 1) / kThreads, k.nq, n_ct);
+        hipLaunchKernelGGL(k_own_limbs, grid, dim3(kThreads), 0, s, X, xs, d, d_stride, k.next,
+                           ctx->alpha, n);
+        VR_CHECK_LAUNCH();
     }
     // every converted limb of every digit to the evaluation domain: per digit
     // all limbs except the digit's own (digit_skip), the uniform count being
@@ -604,36 +630,49 @@ void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, u32 n_ct
     }
     ProfScope prof(ctx, kProfKsInner, s, (u64)n_ct * k.next);
     if (k.beta > 16) throw Error(VR_EINVAL, "key switching: more than 16 digits");
-    // one launch per run of consecutive extended limbs on the same path
-    // (FP64 below 2^51, else integer), so each kernel gets its own registers
-    u32 e_begin = 0;
-    while (e_begin < k.next) {
-        const bool fp = ctx->modq[ctx->ext_mod(e_begin, level)].q < (1ull << 51);
-        u32 e_end = e_begin + 1;
-        while (e_end < k.next && (ctx->modq[ctx->ext_mod(e_end, level)].q < (1ull << 51)) == fp) e_end++;
-        dim3 g2(grid.x, e_end - e_begin, grid.z);
+    // one launch per path (FP64 below 2^51, else integer) over its runs of
+    // consecutive extended limbs, so each kernel gets its own registers
+    for (int pass = 0; pass < 2; pass++) {
+        const bool fp = pass == 0;
+        std::vector<std::pair<u32, u32>> runs;   // (begin, length)
+        for (u32 e = 0; e < k.next; e++) {
+            if ((ctx->modq[ctx->ext_mod(e, level)].q < (1ull << 51)) != fp) continue;
+            if (!runs.empty() && runs.back().first + runs.back().second == e)
+                runs.back().second++;
+            else
+                runs.push_back({e, 1});
+        }
+        for (size_t r0 = 0; r0 < runs.size(); r0 += kMaxRuns) {
+            LimbRuns lr = {};
+            u32 rows = 0;
+            for (size_t r = r0; r < std::min(runs.size(), r0 + kMaxRuns); r++) {
+                lr.b[r - r0] = runs[r].first;
+                lr.len[r - r0] = runs[r].second;
+                rows += runs[r].second;
+            }
+            dim3 g2(grid.x, rows, grid.z);
 #define VR_KS_INNER(B, F)                                                                             \
     hipLaunchKernelGGL((k_ks_inner<B, F>), g2, dim3(kThreads), 0, s, X, x_stride, n_ct, key, ctx->nmod(), \
-                       level, k.next, k.beta, ctx->L, ctx->log_n, g_inv, U, u_stride, ctx->d_modq, e_begin)
-        if (k.beta <= 4) {
-            if (fp)
-                VR_KS_INNER(4, true);
-            else
-                VR_KS_INNER(4, false);
-        } else if (k.beta <= 8) {
-            if (fp)
-                VR_KS_INNER(8, true);
-            else
-                VR_KS_INNER(8, false);
-        } else {
-            if (fp)
-                VR_KS_INNER(16, true);
-            else
-                VR_KS_INNER(16, false);
-        }
+                       level, k.next, k.beta, ctx->L, ctx->log_n, g_inv, U, u_stride, ctx->d_modq, lr)
+            if (k.beta <= 4) {
+                if (fp)
+                    VR_KS_INNER(4, true);
+                else
+                    VR_KS_INNER(4, false);
+            } else if (k.beta <= 8) {
+                if (fp)
+                    VR_KS_INNER(8, true);
+                else
+                    VR_KS_INNER(8, false);
+            } else {
+                if (fp)
+                    VR_KS_INNER(16, true);
+                else
+                    VR_KS_INNER(16, false);
+            }
 #undef VR_KS_INNER
-        VR_CHECK_LAUNCH();
-        e_begin = e_end;
+            VR_CHECK_LAUNCH();
+        }
     }
 }
 

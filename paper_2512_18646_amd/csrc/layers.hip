@@ -49,6 +49,20 @@ Slab new_slab(vr_context* ctx, u32 n, u32 ncomp, u32 level, double scale, hipStr
     return sl;
 }
 
+constexpr u32 kGatherMax = 64;
+struct GatherTable {
+    const u64* src[kGatherMax];
+};
+
+// dst + i * stride <- src[i], i < gridDim.y, as 16-byte pairs
+__global__ __launch_bounds__(kThreads) void k_gather_cts(u64* dst, u64 stride, GatherTable t, u32 pairs)
+{
+    const u32 k = blockIdx.x * kThreads + threadIdx.x;
+    if (k >= pairs) return;
+    const ulonglong2* src = (const ulonglong2*)t.src[blockIdx.y];
+    ((ulonglong2*)(dst + (size_t)blockIdx.y * stride))[k] = src[k];
+}
+
 // Uses the ciphertexts in place when they already form a slab, else copies.
 Slab gather(vr_context* ctx, const vr_ciphertext* const* cts, u32 n, hipStream_t s)
 {
@@ -78,8 +92,17 @@ Slab gather(vr_context* ctx, const vr_ciphertext* const* cts, u32 n, hipStream_t
     }
     sl.buf = dev_alloc(ctx, (size_t)n * sl.stride * sizeof(u64), s);
     sl.base = as_u64(sl.buf);
-    for (u32 i = 0; i < n; i++)
-        VR_HIP(hipMemcpyAsync(sl.ct(i), cts[i]->data, sl.stride * sizeof(u64), hipMemcpyDeviceToDevice, s));
+    // one copy kernel per kGatherMax ciphertexts (their addresses in the
+    // arguments) instead of one copy call per ciphertext
+    const u32 pairs = (u32)(sl.stride / 2);   // stride is a multiple of N: even
+    for (u32 i0 = 0; i0 < n; i0 += kGatherMax) {
+        GatherTable t;
+        const u32 cnt = std::min(kGatherMax, n - i0);
+        for (u32 i = 0; i < cnt; i++) t.src[i] = cts[i0 + i]->data;
+        dim3 grid((pairs + kThreads - 1) / kThreads, cnt);
+        hipLaunchKernelGGL(k_gather_cts, grid, dim3(kThreads), 0, s, sl.ct(i0), sl.stride, t, pairs);
+        VR_CHECK_LAUNCH();
+    }
     return sl;
 }
 
