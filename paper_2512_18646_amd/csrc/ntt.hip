@@ -881,42 +881,67 @@ __device__ __forceinline__ void limb_round(u64* lds, const LimbK& c)
     }
 }
 
+// One word of each 128-byte line of a limb row per thread (2^LOGN / 16 lines).
+template <int LOGN, int LOGE>
+struct LinePrefetch {
+    static constexpr u32 LINES = (1u << LOGN) / 16;
+    static constexpr u32 PER = LINES > LimbShape<LOGN, LOGE>::T ? LINES / LimbShape<LOGN, LOGE>::T : 1;
+    u64 a[PER], b[PER];
+};
+
 // Rounds I, I+1, ... (inverse: I, I-1, ...) with a barrier between rounds.
+// A fused finish reads its operands in the last round; after the first
+// round every thread loads one word of each of their 128-byte lines, so
+// that the operands are in cache by then (the words are consumed at the
+// kernel's end).
 template <int LOGN, int LOGE, bool INV, bool FP, int RED, int I>
-__device__ __forceinline__ void limb_rounds(u64* lds, const LimbK& c)
+__device__ __forceinline__ void limb_rounds(u64* lds, const LimbK& c, LinePrefetch<LOGN, LOGE>& pf)
 {
     using S = LimbShape<LOGN, LOGE>;
+    using PF = LinePrefetch<LOGN, LOGE>;
     static_assert(S::NR >= 2, "whole-limb kernel needs two rounds or more");
     if constexpr (I >= 0 && I < S::NR) {
+        if constexpr (!INV && I == 1) {
+            if (c.ea) {
+#pragma unroll
+                for (u32 k = 0; k < PF::PER; k++) {
+                    const u32 line = c.tid + k * S::T;
+                    if (line < PF::LINES) {
+                        pf.a[k] = c.ea[line * 16];
+                        if (c.eb) pf.b[k] = c.eb[line * 16];
+                    }
+                }
+            }
+        }
         limb_round<LOGN, LOGE, I, INV, FP, RED>(lds, c);
         constexpr int NEXT = INV ? I - 1 : I + 1;
         if constexpr (NEXT >= 0 && NEXT < S::NR) {
             __syncthreads();
-            limb_rounds<LOGN, LOGE, INV, FP, RED, NEXT>(lds, c);
+            limb_rounds<LOGN, LOGE, INV, FP, RED, NEXT>(lds, c, pf);
         }
     }
 }
 
 template <int LOGN, int LOGE, bool INV>
-__device__ __forceinline__ void limb_transform(u64* lds, const LimbK& c)
+__device__ __forceinline__ void limb_transform(u64* lds, const LimbK& c, LinePrefetch<LOGN, LOGE>& pf)
 {
     constexpr int I0 = INV ? LimbShape<LOGN, LOGE>::NR - 1 : 0;
     if (c.q < (1ull << 51)) {
         if (!INV) {
             if (c.q < (1ull << 44))
-                limb_rounds<LOGN, LOGE, INV, true, 0, I0>(lds, c);
+                limb_rounds<LOGN, LOGE, INV, true, 0, I0>(lds, c, pf);
             else if (c.q < (1ull << 50))
-                limb_rounds<LOGN, LOGE, INV, true, 4, I0>(lds, c);
+                limb_rounds<LOGN, LOGE, INV, true, 4, I0>(lds, c, pf);
             else
-                limb_rounds<LOGN, LOGE, INV, true, 2, I0>(lds, c);
+                limb_rounds<LOGN, LOGE, INV, true, 2, I0>(lds, c, pf);
         } else {
             if (c.q < (1ull << 46))
-                limb_rounds<LOGN, LOGE, INV, true, 4, I0>(lds, c);
+                limb_rounds<LOGN, LOGE, INV, true, 4, I0>(lds, c, pf);
             else
-                limb_rounds<LOGN, LOGE, INV, true, 2, I0>(lds, c);
+                limb_rounds<LOGN, LOGE, INV, true, 2, I0>(lds, c, pf);
         }
     } else {
-        limb_rounds<LOGN, LOGE, INV, false, 4, I0>(lds, c);
+        limb_rounds<LOGN, LOGE, INV, false, 4, I0>(lds, c, pf);
     }
 }
 
@@ -930,7 +955,17 @@ __global__ __launch_bounds__(1u << (LOGN - LOGE)) void k_ntt_limb(NttPass p)
     extern __shared__ u64 lds[];
     LimbK c = limb_consts<LOGN, INV>(p, blockIdx.x);
     c.tid = threadIdx.x;
-    limb_transform<LOGN, LOGE, INV>(lds, c);
+    LinePrefetch<LOGN, LOGE> pf;
+    limb_transform<LOGN, LOGE, INV>(lds, c, pf);
+    if (!INV && c.ea) {
+#pragma unroll
+        for (u32 k = 0; k < LinePrefetch<LOGN, LOGE>::PER; k++) {
+            if (c.tid + k * LimbShape<LOGN, LOGE>::T < LinePrefetch<LOGN, LOGE>::LINES) {
+                asm volatile("" ::"v"(pf.a[k]));
+                if (c.eb) asm volatile("" ::"v"(pf.b[k]));
+            }
+        }
+    }
 }
 
 namespace {
