@@ -208,7 +208,7 @@ vr_status vr_context_tuning_report(vr_context* ctx, char* buf, size_t cap)
         r += std::string("ntt N=2^") + std::to_string(ctx->log_n) + (d ? " inverse:" : " forward:");
         for (auto& c : ctx->ntt_plan[d])
             r += " {" + std::to_string(c[0]) + "," + std::to_string(c[1]) + "," + std::to_string(c[2]) +
-                 (c[3] == 2 ? ",limb" : c[3] ? ",direct" : "") + ",/" + std::to_string(c[4]) + (c[5] == 5 ? ",r32" : "") + "}";
+                 (c[3] == 3 ? ",split" : c[3] == 2 ? ",limb" : c[3] ? ",direct" : "") + ",/" + std::to_string(c[4]) + (c[5] == 5 ? ",r32" : "") + "}";
         r += "\n";
     }
     REQUIRE(r.size() < cap, "report buffer too small");

@@ -758,6 +758,37 @@ __device__ __forceinline__ LimbK limb_consts(const NttPass& p, u32 r)
     return c;
 }
 
+// LDS words written by lanes of this wave are visible to its other lanes
+// (LDS executes one wave's instructions in order; the fences keep the
+// compiler from moving the accesses across).
+__device__ __forceinline__ void wave_lds_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The finish of a forward transform on one word: (A - y) c (+ B) with B read
+// through the Galois map, FP64 path (|A - y| < 27 q, the product within 1.5 q,
+// 3 q when q >= 2^50, reduced before B is added) or integer path (y lazy in
+// [0, 4q)).
+__device__ __forceinline__ u64 finish_fp(const LimbK& c, u64 a, u64 b, double y)
+{
+    double v = fbal(fmulmod(to_bal(a, c.q, c.qd) - y, c.ecf, c.qd, c.qinv), c.qd, c.qinv);
+    if (c.eb) v += to_bal(b, c.q, c.qd);
+    return to_canon(v, c.qd, c.qinv);
+}
+
+__device__ __forceinline__ u64 finish_int(const LimbK& c, u64 a, u64 b, u64 y)
+{
+    const u64 q = c.q, q2 = 2 * q;
+    y = y >= q2 ? y - q2 : y;
+    y = y >= q ? y - q : y;
+    u64 v = shoup(a + q - y, c.ec.x, c.ec.y, q);
+    if (c.eb) v = add_mod(v, b, q);
+    return v;
+}
+
 // Round i's geometry: R stages from global stage SG0, groups of 2^R words at
 // index stride 2^LB, GPT groups per thread.
 template <int LOGN, int LOGE, int I>
@@ -784,6 +815,11 @@ __device__ __forceinline__ void limb_round(u64* lds, const LimbK& c)
     // inverse's first
     constexpr bool FROM_G = INV ? (I == S::NR - 1) : (I == 0);
     constexpr bool TO_G = INV ? (I == 0) : (I == S::NR - 1);
+    // groups of consecutive words (the forward's last round, the inverse's
+    // first): global memory is accessed across lanes instead, each wave
+    // staging its own 64 groups through their LDS words
+    constexpr bool XPOSE = LB == 0;
+    const u32 lane = c.tid & 63;
     double* ldf = (double*)lds;
 #pragma unroll
     for (int g = 0; g < GPT; g++) {
@@ -791,17 +827,27 @@ __device__ __forceinline__ void limb_round(u64* lds, const LimbK& c)
         const u32 hi = gid >> LB, lo = gid & ((1u << LB) - 1);
         const u32 base = (hi << (LB + R)) | lo;
         const u32 pb = pad(base);
+        const u32 rb = (gid - lane) * E;   // this wave's words when XPOSE
+        // limb word of the m-th global access
+        auto gword = [&](int m) -> u32 { return XPOSE ? rb + (u32)m * 64 + lane : base + ((u32)m << LB); };
         if constexpr (FP) {
             double x[E];
             if (FROM_G) {
                 u64 v[E];
 #pragma unroll
-                for (int m = 0; m < E; m++) v[m] = c.src[base + ((u32)m << LB)];
+                for (int m = 0; m < E; m++) v[m] = c.src[gword(m)];
 #pragma unroll
                 for (int m = 0; m < E; m++) {
                     u64 t = v[m];
                     if (!INV && c.cq) t = conv_one(t, c.cq, c.q, c.one_s);
                     x[m] = to_bal(t, c.q, c.qd);
+                }
+                if constexpr (XPOSE) {
+#pragma unroll
+                    for (int m = 0; m < E; m++) ldf[pad(gword(m))] = x[m];
+                    wave_lds_sync();
+#pragma unroll
+                    for (int m = 0; m < E; m++) x[m] = ldf[pb + m];
                 }
             } else {
 #pragma unroll
@@ -811,25 +857,28 @@ __device__ __forceinline__ void limb_round(u64* lds, const LimbK& c)
                 limb_fp_inv<LOGN, R, SG0, RED, UNI>(x, c.twf, hi, c.qd, c.qinv, c.n1f, c.w1nf);
             else
                 limb_fp_fwd<LOGN, R, SG0, RED, UNI>(x, c.twf, hi, c.qd, c.qinv);
-            if (TO_G && !INV && c.ea) {
-                // (A - y) c (+ B): |A - y| < 27 q, the product within 1.5 q
-                // (3 q when q >= 2^50), reduced before B is added
-                u64 av[E], bv[E];
+            if constexpr (TO_G) {
+                if constexpr (XPOSE) {
 #pragma unroll
-                for (int m = 0; m < E; m++) {
-                    const u32 idx = base + ((u32)m << LB);
-                    av[m] = c.ea[idx];
-                    if (c.eb) bv[m] = c.eb[c.eb_g != 1 ? galois_src(idx, c.eb_g, LOGN) : idx];
+                    for (int m = 0; m < E; m++) ldf[pb + m] = x[m];
+                    wave_lds_sync();
+#pragma unroll
+                    for (int m = 0; m < E; m++) x[m] = ldf[pad(gword(m))];
                 }
+                if (!INV && c.ea) {
+                    u64 av[E], bv[E];
 #pragma unroll
-                for (int m = 0; m < E; m++) {
-                    double v = fbal(fmulmod(to_bal(av[m], c.q, c.qd) - x[m], c.ecf, c.qd, c.qinv), c.qd, c.qinv);
-                    if (c.eb) v += to_bal(bv[m], c.q, c.qd);
-                    c.eo[base + ((u32)m << LB)] = to_canon(v, c.qd, c.qinv);
+                    for (int m = 0; m < E; m++) {
+                        const u32 idx = gword(m);
+                        av[m] = c.ea[idx];
+                        if (c.eb) bv[m] = c.eb[c.eb_g != 1 ? galois_src(idx, c.eb_g, LOGN) : idx];
+                    }
+#pragma unroll
+                    for (int m = 0; m < E; m++) c.eo[gword(m)] = finish_fp(c, av[m], bv[m], x[m]);
+                } else {
+#pragma unroll
+                    for (int m = 0; m < E; m++) c.dst[gword(m)] = to_canon(x[m], c.qd, c.qinv);
                 }
-            } else if (TO_G) {
-#pragma unroll
-                for (int m = 0; m < E; m++) c.dst[base + ((u32)m << LB)] = to_canon(x[m], c.qd, c.qinv);
             } else {
 #pragma unroll
                 for (int m = 0; m < E; m++) ldf[pb + padc((u32)m << LB)] = x[m];
@@ -839,39 +888,48 @@ __device__ __forceinline__ void limb_round(u64* lds, const LimbK& c)
             u64 x[E];
             if (FROM_G) {
 #pragma unroll
-                for (int m = 0; m < E; m++) x[m] = c.src[base + ((u32)m << LB)];
+                for (int m = 0; m < E; m++) x[m] = c.src[gword(m)];
                 if (!INV && c.cq) {
 #pragma unroll
                     for (int m = 0; m < E; m++) x[m] = conv_one(x[m], c.cq, q, c.one_s);
+                }
+                if constexpr (XPOSE) {
+#pragma unroll
+                    for (int m = 0; m < E; m++) lds[pad(gword(m))] = x[m];
+                    wave_lds_sync();
+#pragma unroll
+                    for (int m = 0; m < E; m++) x[m] = lds[pb + m];
                 }
             } else {
 #pragma unroll
                 for (int m = 0; m < E; m++) x[m] = lds[pb + padc((u32)m << LB)];
             }
             limb_int<R, SG0, INV, UNI>(x, (const ulonglong2*)c.tw64, hi, q, c.n1, c.w1n);
-            if (TO_G && !INV && c.ea) {
-                u64 av[E], bv[E];
+            if constexpr (TO_G) {
+                if constexpr (XPOSE) {
 #pragma unroll
-                for (int m = 0; m < E; m++) {
-                    const u32 idx = base + ((u32)m << LB);
-                    av[m] = c.ea[idx];
-                    if (c.eb) bv[m] = c.eb[c.eb_g != 1 ? galois_src(idx, c.eb_g, LOGN) : idx];
+                    for (int m = 0; m < E; m++) lds[pb + m] = x[m];
+                    wave_lds_sync();
+#pragma unroll
+                    for (int m = 0; m < E; m++) x[m] = lds[pad(gword(m))];
                 }
+                if (!INV && c.ea) {
+                    u64 av[E], bv[E];
 #pragma unroll
-                for (int m = 0; m < E; m++) {
-                    u64 y = x[m];
-                    y = y >= q2 ? y - q2 : y;
-                    y = y >= q ? y - q : y;
-                    u64 v = shoup(av[m] + q - y, c.ec.x, c.ec.y, q);
-                    if (c.eb) v = add_mod(v, bv[m], q);
-                    c.eo[base + ((u32)m << LB)] = v;
-                }
-            } else if (TO_G) {
+                    for (int m = 0; m < E; m++) {
+                        const u32 idx = gword(m);
+                        av[m] = c.ea[idx];
+                        if (c.eb) bv[m] = c.eb[c.eb_g != 1 ? galois_src(idx, c.eb_g, LOGN) : idx];
+                    }
 #pragma unroll
-                for (int m = 0; m < E; m++) {
-                    u64 y = x[m];
-                    if (!INV) y = y >= q2 ? y - q2 : y;
-                    c.dst[base + ((u32)m << LB)] = y >= q ? y - q : y;
+                    for (int m = 0; m < E; m++) c.eo[gword(m)] = finish_int(c, av[m], bv[m], x[m]);
+                } else {
+#pragma unroll
+                    for (int m = 0; m < E; m++) {
+                        u64 y = x[m];
+                        if (!INV) y = y >= q2 ? y - q2 : y;
+                        c.dst[gword(m)] = y >= q ? y - q : y;
+                    }
                 }
             } else {
 #pragma unroll
@@ -968,12 +1026,261 @@ __global__ __launch_bounds__(1u << (LOGN - LOGE)) void k_ntt_limb(NttPass p)
     }
 }
 
+// ---------------------------------------------------------------------------
+// Two-pass transform with the round geometry fixed at compile time, for rings
+// whose limb does not fit in one CU's LDS (N = 2^15, 2^16).
+//
+// Pass 0 runs global stages [0, A) on tiles of 2^LC consecutive columns: tile
+// word e = v 2^LC + c is coefficient v 2^(LOGN - A) + col0 + c (v < 2^A), so
+// each of a thread's loads and stores covers 2^LC consecutive words across
+// neighbouring lanes.  Pass 1 runs stages [A, LOGN) on 2^LC consecutive
+// blocks of 2^(LOGN - A) words: tile word e is coefficient tile0 + e.  Inside
+// a pass the rounds are those of the whole-limb kernel (16 words per thread,
+// four stages per round, the last taking the remainder): the first round
+// reads global memory, the last writes it, and LDS is visited only between
+// rounds.  A tile is 2^(P + LC) words (P = the pass's stages), small enough
+// for several workgroups per CU, so that one workgroup's global loads and
+// stores overlap the butterflies of another.
+//
+// Twiddle prefixes: at global stage s a butterfly's twiddle is indexed by its
+// coefficient index >> (LOGN - s).  In pass 0 that is v >> (A - s), which is
+// the group's hi below; in pass 1 it is (tile0 + e) >> (LOGN - s), i.e. hi
+// plus tile0 >> (LOGN - s).  Between the passes the FP64 path stores its
+// balanced doubles (exact integers, bounded as in a single pass since the
+// reduction schedule follows the global stage), the integer path its lazy
+// residues; only the transform's own input and output are canonical.
+template <int LOGN, int A, int LC, int PASS>
+struct SplitShape {
+    static constexpr int P = PASS == 0 ? A : LOGN - A;   // stages in the pass
+    static constexpr int LOGT = P + LC;                  // tile words (log)
+    static constexpr u32 T = 1u << (LOGT - 4);           // 16 words per thread
+    static constexpr int TOP = PASS == 0 ? LOGT : P;     // the pass pairs tile bits below TOP
+    static constexpr int S0 = PASS == 0 ? 0 : A;         // global stage of the pass's first
+    static constexpr int NR = (P + 3) / 4;
+    static constexpr int R(int i) { return (i + 1) * 4 <= P ? 4 : P - i * 4; }
+    static constexpr int WG_LOG = LOGN - LOGT;           // workgroups per limb (log)
+};
+
+// coefficient index of tile word e in tile wg
+template <int LOGN, int A, int LC, int PASS>
+__device__ __forceinline__ u32 split_addr(u32 e, u32 wg)
+{
+    if constexpr (PASS == 0)
+        return ((e >> LC) << (LOGN - A)) + (wg << LC) + (e & ((1u << LC) - 1));
+    else
+        return (wg << (LOGN - A + LC)) + e;
+}
+
+template <int LOGN, int A, int LC, int PASS, int I, bool INV, bool FP, int RED>
+__device__ __forceinline__ void split_round(u64* lds, const LimbK& c, u32 wg)
+{
+    using S = SplitShape<LOGN, A, LC, PASS>;
+    constexpr int R = S::R(I), SGL = 4 * I, SG0 = S::S0 + SGL, E = 1 << R;
+    constexpr int LB = S::TOP - SGL - R, GPT = 1 << (4 - R);
+    constexpr bool UNI = LB >= 6;
+    constexpr bool FROM_G = INV ? (I == S::NR - 1) : (I == 0);
+    constexpr bool TO_G = INV ? (I == 0) : (I == S::NR - 1);
+    // the pass launched first reads the canonical input, the second writes
+    // the canonical output; in between the intermediate form
+    constexpr bool FIRST = INV ? PASS == 1 : PASS == 0;
+    // groups of consecutive words (pass 1's last forward round, first
+    // inverse one): global memory is accessed across lanes instead, each
+    // wave staging its own 64 groups through their LDS words
+    constexpr bool XPOSE = LB == 0;
+    const u32 hoff = PASS == 1 ? wg << (LC + SGL) : 0u;
+    const u32 lane = c.tid & 63;
+    double* ldf = (double*)lds;
+#pragma unroll
+    for (int g = 0; g < GPT; g++) {
+        const u32 gid = c.tid + (u32)g * S::T;
+        const u32 hi = gid >> LB, lo = gid & ((1u << LB) - 1);
+        const u32 base = (hi << (LB + R)) | lo;
+        const u32 pb = pad(base);
+        const u32 rb = (gid - lane) * E;   // this wave's words when XPOSE
+        // tile word of the m-th global access
+        auto gword = [&](int m) -> u32 { return XPOSE ? rb + (u32)m * 64 + lane : base + ((u32)m << LB); };
+        if constexpr (FP) {
+            double x[E];
+            if constexpr (FROM_G) {
+                u64 v[E];
+#pragma unroll
+                for (int m = 0; m < E; m++) v[m] = c.src[split_addr<LOGN, A, LC, PASS>(gword(m), wg)];
+#pragma unroll
+                for (int m = 0; m < E; m++) {
+                    if constexpr (FIRST) {
+                        u64 t = v[m];
+                        if (!INV && c.cq) t = conv_one(t, c.cq, c.q, c.one_s);
+                        x[m] = to_bal(t, c.q, c.qd);
+                    } else {
+                        x[m] = __longlong_as_double(v[m]);
+                    }
+                }
+                if constexpr (XPOSE) {
+#pragma unroll
+                    for (int m = 0; m < E; m++) ldf[pad(gword(m))] = x[m];
+                    wave_lds_sync();
+#pragma unroll
+                    for (int m = 0; m < E; m++) x[m] = ldf[pb + m];
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < E; m++) x[m] = ldf[pb + padc((u32)m << LB)];
+            }
+            if constexpr (INV)
+                limb_fp_inv<LOGN, R, SG0, RED, UNI>(x, c.twf, hi + hoff, c.qd, c.qinv, c.n1f, c.w1nf);
+            else
+                limb_fp_fwd<LOGN, R, SG0, RED, UNI>(x, c.twf, hi + hoff, c.qd, c.qinv);
+            if constexpr (TO_G) {
+                if constexpr (XPOSE) {
+#pragma unroll
+                    for (int m = 0; m < E; m++) ldf[pb + m] = x[m];
+                    wave_lds_sync();
+#pragma unroll
+                    for (int m = 0; m < E; m++) x[m] = ldf[pad(gword(m))];
+                }
+                if constexpr (FIRST) {
+#pragma unroll
+                    for (int m = 0; m < E; m++)
+                        c.dst[split_addr<LOGN, A, LC, PASS>(gword(m), wg)] = __double_as_longlong(x[m]);
+                } else if (!INV && c.ea) {
+                    u64 av[E], bv[E];
+#pragma unroll
+                    for (int m = 0; m < E; m++) {
+                        const u32 idx = split_addr<LOGN, A, LC, PASS>(gword(m), wg);
+                        av[m] = c.ea[idx];
+                        if (c.eb) bv[m] = c.eb[c.eb_g != 1 ? galois_src(idx, c.eb_g, LOGN) : idx];
+                    }
+#pragma unroll
+                    for (int m = 0; m < E; m++) {
+                        const u32 idx = split_addr<LOGN, A, LC, PASS>(gword(m), wg);
+                        c.eo[idx] = finish_fp(c, av[m], bv[m], x[m]);
+                    }
+                } else {
+#pragma unroll
+                    for (int m = 0; m < E; m++)
+                        c.dst[split_addr<LOGN, A, LC, PASS>(gword(m), wg)] = to_canon(x[m], c.qd, c.qinv);
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < E; m++) ldf[pb + padc((u32)m << LB)] = x[m];
+            }
+        } else {
+            const u64 q = c.q, q2 = 2 * q;
+            u64 x[E];
+            if constexpr (FROM_G) {
+#pragma unroll
+                for (int m = 0; m < E; m++) x[m] = c.src[split_addr<LOGN, A, LC, PASS>(gword(m), wg)];
+                if (FIRST && !INV && c.cq) {
+#pragma unroll
+                    for (int m = 0; m < E; m++) x[m] = conv_one(x[m], c.cq, q, c.one_s);
+                }
+                if constexpr (XPOSE) {
+#pragma unroll
+                    for (int m = 0; m < E; m++) lds[pad(gword(m))] = x[m];
+                    wave_lds_sync();
+#pragma unroll
+                    for (int m = 0; m < E; m++) x[m] = lds[pb + m];
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < E; m++) x[m] = lds[pb + padc((u32)m << LB)];
+            }
+            limb_int<R, SG0, INV, UNI>(x, (const ulonglong2*)c.tw64, hi + hoff, q, c.n1, c.w1n);
+            if constexpr (TO_G) {
+                if constexpr (XPOSE) {
+#pragma unroll
+                    for (int m = 0; m < E; m++) lds[pb + m] = x[m];
+                    wave_lds_sync();
+#pragma unroll
+                    for (int m = 0; m < E; m++) x[m] = lds[pad(gword(m))];
+                }
+                if constexpr (FIRST) {
+#pragma unroll
+                    for (int m = 0; m < E; m++) c.dst[split_addr<LOGN, A, LC, PASS>(gword(m), wg)] = x[m];
+                } else if (!INV && c.ea) {
+                    u64 av[E], bv[E];
+#pragma unroll
+                    for (int m = 0; m < E; m++) {
+                        const u32 idx = split_addr<LOGN, A, LC, PASS>(gword(m), wg);
+                        av[m] = c.ea[idx];
+                        if (c.eb) bv[m] = c.eb[c.eb_g != 1 ? galois_src(idx, c.eb_g, LOGN) : idx];
+                    }
+#pragma unroll
+                    for (int m = 0; m < E; m++)
+                        c.eo[split_addr<LOGN, A, LC, PASS>(gword(m), wg)] = finish_int(c, av[m], bv[m], x[m]);
+                } else {
+#pragma unroll
+                    for (int m = 0; m < E; m++) {
+                        u64 y = x[m];
+                        if (!INV) y = y >= q2 ? y - q2 : y;
+                        c.dst[split_addr<LOGN, A, LC, PASS>(gword(m), wg)] = y >= q ? y - q : y;
+                    }
+                }
+            } else {
+#pragma unroll
+                for (int m = 0; m < E; m++) lds[pb + padc((u32)m << LB)] = x[m];
+            }
+        }
+    }
+}
+
+template <int LOGN, int A, int LC, int PASS, bool INV, bool FP, int RED, int I>
+__device__ __forceinline__ void split_rounds(u64* lds, const LimbK& c, u32 wg)
+{
+    using S = SplitShape<LOGN, A, LC, PASS>;
+    if constexpr (I >= 0 && I < S::NR) {
+        split_round<LOGN, A, LC, PASS, I, INV, FP, RED>(lds, c, wg);
+        constexpr int NEXT = INV ? I - 1 : I + 1;
+        if constexpr (NEXT >= 0 && NEXT < S::NR) {
+            __syncthreads();
+            split_rounds<LOGN, A, LC, PASS, INV, FP, RED, NEXT>(lds, c, wg);
+        }
+    }
+}
+
+// One workgroup per tile; the reduction schedule of the whole-limb kernel
+// (its bounds cover 16 stages).
+template <int LOGN, int A, int LC, int PASS, bool INV>
+__global__ __launch_bounds__((SplitShape<LOGN, A, LC, PASS>::T)) void k_ntt_split(NttPass p)
+{
+    using S = SplitShape<LOGN, A, LC, PASS>;
+    extern __shared__ u64 lds[];
+    const u32 r = blockIdx.x >> S::WG_LOG, wg = blockIdx.x & ((1u << S::WG_LOG) - 1);
+    LimbK c = limb_consts<LOGN, INV>(p, r);
+    c.tid = threadIdx.x;
+    constexpr bool FIRST = INV ? PASS == 1 : PASS == 0;
+    if (!FIRST) {
+        c.src = c.dst;
+        c.cq = 0;
+    }
+    if (INV || PASS == 0) c.ea = nullptr;
+    constexpr int I0 = INV ? S::NR - 1 : 0;
+    if (c.q < (1ull << 51)) {
+        if (!INV) {
+            if (c.q < (1ull << 44))
+                split_rounds<LOGN, A, LC, PASS, INV, true, 0, I0>(lds, c, wg);
+            else if (c.q < (1ull << 50))
+                split_rounds<LOGN, A, LC, PASS, INV, true, 4, I0>(lds, c, wg);
+            else
+                split_rounds<LOGN, A, LC, PASS, INV, true, 2, I0>(lds, c, wg);
+        } else {
+            if (c.q < (1ull << 46))
+                split_rounds<LOGN, A, LC, PASS, INV, true, 4, I0>(lds, c, wg);
+            else
+                split_rounds<LOGN, A, LC, PASS, INV, true, 2, I0>(lds, c, wg);
+        }
+    } else {
+        split_rounds<LOGN, A, LC, PASS, INV, false, 4, I0>(lds, c, wg);
+    }
+}
+
 namespace {
 
 struct PassCfg {
     u32 s0, log_g, log_c;
     u32 direct = 0;    // 1: whole-limb pass with global first/last rounds; 2: the same
-                       // with the round geometry fixed at compile time
+                       // with the round geometry fixed at compile time; 3: a pass of
+                       // the compile-time two-pass kernels
     u32 div = 16;      // tile words per thread
     u32 max_r = 4;     // stages per round
 };
@@ -986,8 +1293,9 @@ std::vector<PassCfg> default_plan(u32 log_n)
 }
 
 // Plans the autotuner times: the single LDS-resident pass where the limb
-// fits, and two-pass splits a + b = log N with 2^(3..7) groups per workgroup
-// (tiles of 2^10 .. 2^14 words).
+// fits, two-pass splits a + b = log N with 2^(3..7) groups per workgroup
+// (tiles of 2^10 .. 2^14 words), and at 2^15 and 2^16 the compile-time
+// two-pass kernels (listed last, so they are kept only when clearly faster).
 std::vector<std::vector<PassCfg>> candidates(u32 log_n)
 {
     std::vector<std::vector<PassCfg>> out;
@@ -1013,6 +1321,13 @@ std::vector<std::vector<PassCfg>> candidates(u32 log_n)
             if (c1 > log_n - a || c2 > log_n - b) continue;
             out.push_back({{0, a, c1}, {a, b, c2}});
         }
+    }
+    if (log_n == 15 || log_n == 16) {
+        // compile-time two-pass kernels: stages split a + b, 2^lc columns
+        // (pass 0) or blocks (pass 1) per workgroup
+        for (u32 a = log_n / 2; a <= (log_n + 1) / 2; a++)
+            for (u32 lc = (log_n == 16 ? 3 : 4); lc <= 5; lc++)
+                out.push_back({{0, a, lc, 3, 16}, {a, log_n - a, lc, 3, 16}});
     }
     return out;
 }
@@ -1040,9 +1355,49 @@ void launch_limb(const NttPass& p, u32 n_limbs, hipStream_t s)
     hipLaunchKernelGGL((k_ntt_limb<LOGN, LOGE, INV>), dim3(n_limbs), dim3(1u << (LOGN - LOGE)), shmem, s, p);
 }
 
+template <int LOGN, int A, int LC, int PASS, bool INV>
+void launch_split(const NttPass& p, u32 n_limbs, hipStream_t s)
+{
+    using S = SplitShape<LOGN, A, LC, PASS>;
+    static std::once_flag attr;
+    const size_t shmem = (size_t)padc(1u << S::LOGT) * sizeof(u64);
+    std::call_once(attr, [&] {
+        (void)hipFuncSetAttribute((const void*)k_ntt_split<LOGN, A, LC, PASS, INV>,
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)shmem);
+    });
+    hipLaunchKernelGGL((k_ntt_split<LOGN, A, LC, PASS, INV>), dim3(n_limbs << S::WG_LOG), dim3(S::T), shmem,
+                       s, p);
+}
+
 template <bool INV>
 void launch_pass(const NttPass& p, const PassCfg& c, u32 n_limbs, hipStream_t s)
 {
+    if (c.direct == 3) {
+        // pass 0 starts at stage 0 and runs a = log_g stages; pass 1 starts at a
+        const u32 pass = c.s0 == 0 ? 0 : 1;
+        const u32 a = pass == 0 ? c.log_g : c.s0;
+        if (c.div != 16 || (pass == 1 && a + c.log_g != p.log_n))
+            throw Error(VR_EINVAL, "ntt: malformed two-pass plan");
+        switch (p.log_n * 1000 + a * 100 + c.log_c * 10 + pass) {
+        case 16830: launch_split<16, 8, 3, 0, INV>(p, n_limbs, s); break;
+        case 16831: launch_split<16, 8, 3, 1, INV>(p, n_limbs, s); break;
+        case 16840: launch_split<16, 8, 4, 0, INV>(p, n_limbs, s); break;
+        case 16841: launch_split<16, 8, 4, 1, INV>(p, n_limbs, s); break;
+        case 16850: launch_split<16, 8, 5, 0, INV>(p, n_limbs, s); break;
+        case 16851: launch_split<16, 8, 5, 1, INV>(p, n_limbs, s); break;
+        case 15740: launch_split<15, 7, 4, 0, INV>(p, n_limbs, s); break;
+        case 15741: launch_split<15, 7, 4, 1, INV>(p, n_limbs, s); break;
+        case 15750: launch_split<15, 7, 5, 0, INV>(p, n_limbs, s); break;
+        case 15751: launch_split<15, 7, 5, 1, INV>(p, n_limbs, s); break;
+        case 15840: launch_split<15, 8, 4, 0, INV>(p, n_limbs, s); break;
+        case 15841: launch_split<15, 8, 4, 1, INV>(p, n_limbs, s); break;
+        case 15850: launch_split<15, 8, 5, 0, INV>(p, n_limbs, s); break;
+        case 15851: launch_split<15, 8, 5, 1, INV>(p, n_limbs, s); break;
+        default: throw Error(VR_EINVAL, "ntt: no two-pass kernel for this split");
+        }
+        VR_CHECK_LAUNCH();
+        return;
+    }
     if (c.direct == 2) {
         // whole-limb kernel with the geometry fixed at compile time
         switch (p.log_n * 100 + c.div) {
@@ -1176,13 +1531,16 @@ std::vector<PassCfg> plan_for(vr_context* ctx, hipStream_t s)
 }
 
 // Runs the transform; a forward epilogue is applied when the plan is one
-// whole-limb pass, else dropped (the transform is stored) and false returned.
+// whole-limb pass or ends with a compile-time two-pass kernel, else dropped
+// (the transform is stored) and false returned.
 template <bool INV>
 bool run(vr_context* ctx, const LimbSet& ls, hipStream_t s)
 {
     u32 n_limbs = ls.per_poly * ls.n_polys;
     std::vector<PassCfg> passes = plan_for<INV>(ctx, s);
-    const bool fuse = !INV && ls.epi.a && passes.size() == 1 && passes[0].direct == 2;
+    const bool fuse = !INV && ls.epi.a &&
+                      ((passes.size() == 1 && passes[0].direct == 2) ||
+                       (passes.size() == 2 && passes[1].direct == 3));
     if (n_limbs == 0) return fuse;
     ProfScope prof(ctx, kProfNtt, s, n_limbs);
     if (fuse || !ls.epi.a) {

@@ -456,7 +456,8 @@ struct LimbSet {
 };
 
 // Returns whether ls.epi was applied (false when it is unset or the plan
-// for this ring has no whole-limb pass: then the transform is stored).
+// for this ring has neither a whole-limb pass nor the compile-time two-pass
+// kernels: then the transform is stored).
 bool ntt_forward(vr_context* ctx, const LimbSet& ls, hipStream_t s);
 void ntt_inverse(vr_context* ctx, const LimbSet& ls, hipStream_t s);
 

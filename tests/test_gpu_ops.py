@@ -47,7 +47,7 @@ def test_ntt_every_candidate_plan(log_n):
     assert "ntt N=2^%d forward" % log_n in g.tuning_report()
 
 
-@pytest.mark.parametrize("log_n", [13, 14])
+@pytest.mark.parametrize("log_n", [13, 14, 16])
 def test_ntt_every_plan_reduction_bands(log_n):
     """FP64 moduli in each band of the reduction schedule (45 and 49 bits:
     forward every four stages; 45: inverse every four, 49: every two) under
@@ -300,6 +300,39 @@ def test_finish_in_transform_and_separate_match(name, level, plan):
         assert_same(g.rescale(to_gpu(g, t)), o.rescale(t), "%s rescale 3 comps %s" % (name, plan))
     finally:
         g.set_tuning("ntt", "auto")
+
+
+def test_finish_every_plan_n16():
+    """At N = 2^16 (C3, level 3: 50-bit Q limbs and 51-bit special primes)
+    under every candidate plan: the compile-time two-pass plans run ModDown's
+    and rescale's finish in the forward transform's last pass, the others in
+    their own kernels; rotation, hoisted rotation, relinearisation and
+    rescale against the oracle."""
+    from paper_2512_18646_amd import vr
+    o, ok, g, gk = pair("C3", rot_steps=(1, 3))
+    z = np.random.default_rng(44).uniform(-1, 1, o.slots)
+    a = o.encrypt(ok, o.encode(z, 3, o.scale), 12, 3)
+    t = o.tensor(a, a)
+    want = [o.rotate(a, 1, ok), o.rotate(a, 3, ok), o.relinearize(t, ok), o.rescale(a), o.rescale(t)]
+    ga, gt = to_gpu(g, a), to_gpu(g, t)
+    tried = 0
+    try:
+        while True:
+            g.set_tuning("ntt", "cand:%d" % tried)
+            try:
+                got = g.rotate(gk, ga, 1)
+            except vr.VRError as e:
+                assert e.code == vr.VR_EINVAL and tried >= 1
+                break
+            assert_same(got, want[0], "rotate cand:%d" % tried)
+            assert_same(g.rotate_many(gk, ga, [3, 1])[0], want[1], "hoisted 3 cand:%d" % tried)
+            assert_same(g.relinearize(gk, gt), want[2], "relin cand:%d" % tried)
+            assert_same(g.rescale(ga), want[3], "rescale cand:%d" % tried)
+            assert_same(g.rescale(gt), want[4], "rescale 3 comps cand:%d" % tried)
+            tried += 1
+    finally:
+        g.set_tuning("ntt", "auto")
+    assert tried >= 4
 
 
 def test_error_paths(c1):
