@@ -448,7 +448,7 @@ def mfma_instructions(log_n, level, n_ct, alpha=9, K=9):
 def convert_compare(ctx, keys, cts, level, reps):
     """Base-conversion device time per rotation with each kernel forced."""
     res = {}
-    for mode in ("alu", "mfma"):
+    for mode in ("alu", "fp64", "mfma"):
         ctx.set_tuning("base_convert", mode)
         ctx.rotate_batch(keys, cts, 1)
         sync()

@@ -110,12 +110,14 @@ vr_status vr_context_mem_info(vr_context *ctx, size_t *reserved, size_t *in_use)
  * blocks to the runtime. */
 vr_status vr_context_trim(vr_context *ctx);
 /* Kernel choices.  Knob "base_convert": "auto" (default: each base-conversion
- * table times the vector-ALU and the INT8-split MFMA kernel on its first call
- * and keeps the faster; both give identical words), "alu" or "mfma".  Knob
+ * table times the 128-bit vector-ALU kernel, the exact FP64 kernel and the
+ * INT8-split MFMA kernel on its first call and keeps the fastest; all give
+ * identical words), "alu", "fp64" or "mfma".  Knob
  * "ntt": "auto" (default: the first transform in each direction times the
- * candidate pass plans -- one LDS-resident pass, or two passes with every
- * split of log N and 8..128 groups per workgroup -- on 256 scratch limbs and
- * keeps the fastest), "fixed" (the built-in plan) or "cand:<i>" (candidate i,
+ * candidate pass plans -- one LDS-resident pass, two passes with every split
+ * of log N and 8..128 groups per workgroup, and at N = 2^15, 2^16 the
+ * compile-time two-pass kernels -- on 256 scratch limbs and keeps the
+ * fastest), "fixed" (the built-in plan) or "cand:<i>" (candidate i,
  * for tests; VR_EINVAL at the next transform if there is none).  Knob
  * "switch_chunk": "<k>" key-switches at most k ciphertexts per launch in the
  * layer calls ("0": as many as 16 GiB of scratch allows, the default).

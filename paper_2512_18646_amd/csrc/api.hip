@@ -175,14 +175,15 @@ vr_status vr_context_set_tuning(vr_context* ctx, const char* knob, const char* v
     REQUIRE(ctx && knob && value, "null argument");
     std::string k(knob), v(value);
     int mode = -1;
-    if (k == "base_convert") mode = v == "auto" ? 0 : v == "alu" ? 1 : v == "mfma" ? 2 : -1;
+    if (k == "base_convert")
+        mode = v == "auto" ? 0 : v == "alu" ? 1 : v == "mfma" ? 2 : v == "fp64" ? 3 : -1;
     else if (k == "ntt") {
         mode = v == "auto" ? 0 : v == "fixed" ? 1 : -1;
         if (v.compare(0, 5, "cand:") == 0) mode = 2 + std::stoi(v.substr(5));
     }
     else if (k == "switch_chunk") mode = std::stoi(v);
     else throw Error(VR_EINVAL, "unknown tuning knob");
-    REQUIRE(mode >= 0, "base_convert takes auto, alu or mfma; ntt takes auto or fixed");
+    REQUIRE(mode >= 0, "base_convert takes auto, alu, mfma or fp64; ntt takes auto, fixed or cand:k");
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->tuning[k] = mode;
     API_END
@@ -194,7 +195,7 @@ vr_status vr_context_tuning_report(vr_context* ctx, char* buf, size_t cap)
     REQUIRE(ctx && buf && cap > 0, "null argument");
     std::string r;
     std::lock_guard<std::mutex> g(ctx->mu);
-    auto name = [](int c) { return c < 0 ? "untimed" : c == 1 ? "mfma" : "alu"; };
+    auto name = [](int c) { return c < 0 ? "untimed" : c == 1 ? "mfma" : c == 2 ? "fp64" : "alu"; };
     for (auto& kv : ctx->modup_tables)
         r += "modup l" + std::to_string(kv.first.first) + " d" + std::to_string(kv.first.second) + " " +
              std::to_string(kv.second.n_in) + "->" + std::to_string(kv.second.n_out) + ": " +

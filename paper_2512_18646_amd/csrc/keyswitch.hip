@@ -120,6 +120,101 @@ __global__ __launch_bounds__(kThreads) void k_base_convert(ConvArgs a)
     }
 }
 
+// The same conversion in FP64 for targets t < 2^51 (the 128-bit integer form
+// above for wider targets): y_i centred, held exactly as a double when
+// q_i < 2^51; a 60-bit first input (q_0 in digit 0) is held as halves
+// y = yh 2^30 + yl (yl in [0, 2^30)).  The constants are balanced mod t,
+// [Qhat_i]_t (and [2^30 Qhat_0]_t), in rows zero-padded to kMaxIn inputs, so
+// the product loop has no branches and its wave-uniform constant loads issue
+// together.  Each product is formed exactly (fmulmod; |y W / t| <= 2^49
+// keeps it within 0.69 t of zero) and the sum is reduced every four products,
+// staying below 3.3 t < 2^53.
+struct ConvFp {
+    const double* w;   // [n_out][kMaxIn][2]: balanced [Qhat_i]_t, [2^30 Qhat_i]_t
+    const double* t;   // [n_out][2]: t, 1 / t
+};
+
+constexpr double kTwo51 = 2251799813685248.0;
+
+template <int NI, bool W0>
+__global__ __launch_bounds__(kThreads) void k_base_convert_fp(ConvArgs a, ConvFp f)
+{
+    const u32 n = 1u << a.log_n;
+    const u32 poly = blockIdx.y;
+    const u64* qinv = a.tab;
+    const u64* qinv_s = a.tab + a.n_in;
+    const u64* qhat = a.tab + 2 * a.n_in;
+    const u64* negq = qhat + (size_t)a.n_in * a.n_out;
+    const u64* in_mod = negq + a.n_out;
+    const u64* out_mod = in_mod + a.n_in;
+    const u32 t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const u64* in = a.in + (size_t)poly * a.in_stride;
+    u64* out = a.out + (size_t)poly * a.out_stride;
+
+    u64 x[NI];
+#pragma unroll
+    for (int i = 0; i < NI; i++)
+        if (i < (int)a.n_in) x[i] = in[(size_t)i * n + t];
+    double yl[NI], yh0 = 0.0;
+#pragma unroll
+    for (int i = 0; i < NI; i++) {
+        yl[i] = 0.0;
+        if (i < (int)a.n_in) {
+            const u64 q = a.mq[in_mod[i]].q;
+            const u64 v = shoup(x[i], qinv[i], qinv_s[i], q);
+            if (W0 && i == 0) {
+                const i64 y = v > (q >> 1) ? (i64)v - (i64)q : (i64)v;
+                yh0 = (double)(int)(y >> 30);
+                yl[0] = (double)(u32)(y & ((1ll << 30) - 1));
+            } else {
+                yl[i] = to_bal(v, q, (double)q);
+            }
+        }
+    }
+    for (u32 o = 0; o < a.n_out; o++) {
+        const double td = f.t[2 * o], tinv = f.t[2 * o + 1];
+        u64 r;
+        if (td < kTwo51) {
+            const double* w = f.w + (size_t)o * kMaxIn * 2;
+            double acc = 0.0;
+            int since = 0;   // products since the last reduction (compile time)
+#pragma unroll
+            for (int i = 0; i < NI; i++) {
+                acc += fmulmod(yl[i], w[2 * i], td, tinv);
+                since++;
+                if (W0 && i == 0) {
+                    acc += fmulmod(yh0, w[1], td, tinv);
+                    since++;
+                }
+                if (since >= 4 && i + 1 < NI) {
+                    acc = fbal(acc, td, tinv);
+                    since = 0;
+                }
+            }
+            r = to_canon(acc, td, tinv);
+        } else {
+            u64 hi = 0, lo = 0, nn = 0;
+#pragma unroll
+            for (int i = 0; i < NI; i++) {
+                if (i < (int)a.n_in) {
+                    const u64 q = a.mq[in_mod[i]].q;
+                    const i64 y = (W0 && i == 0) ? ((i64)(int)yh0 << 30) + (i64)(u32)yl[0] : (i64)yl[i];
+                    nn += y < 0 ? 1 : 0;
+                    mac128(hi, lo, (u64)(y < 0 ? y + (i64)q : y), qhat[(size_t)i * a.n_out + o]);
+                }
+            }
+            mac128(hi, lo, nn, negq[o]);
+            const ModQ& m = a.mq[out_mod[o]];
+            const u64 tq = m.q;
+            r = shoup_lazy(hi, m.r64, m.r64_s, tq) + shoup_lazy(lo, 1, m.one_s, tq);
+            r = csub(csub(r, 2 * tq), tq);
+        }
+        const u32 slot = o < a.skip_at ? o : o + a.skip_len;
+        out[(size_t)slot * n + t] = r;
+    }
+}
+
 constexpr u32 kMfmaCoef = 256;    // coefficients per block: 4 waves x 4 tiles of 16
 constexpr u32 kDigitRow = 264;    // LDS row pitch of the digit words (padded)
 
@@ -416,6 +511,28 @@ ConvTable build_table(vr_context* ctx, const std::vector<u32>& in, const std::ve
                 }
     VR_HIP(hipMalloc(&tb.wt, wt.size() * sizeof(u64)));
     VR_HIP(hipMemcpy(tb.wt, wt.data(), wt.size() * sizeof(u64), hipMemcpyHostToDevice));
+    // FP64 form: balanced [Qhat_i]_t and [2^30 Qhat_i]_t per (target, input),
+    // rows padded with zeros to kMaxIn inputs, then (t, 1/t) per target;
+    // entries of targets >= 2^51 are unused
+    std::vector<double> wf((size_t)tb.n_out * kMaxIn * 2 + (size_t)tb.n_out * 2, 0.0);
+    double* wt_t = wf.data() + (size_t)tb.n_out * kMaxIn * 2;
+    tb.wide = 0;
+    for (u32 i = 0; i < tb.n_in; i++)
+        if (ctx->mod[in[i]] >= (1ull << 51)) tb.wide |= 1u << i;
+    for (u32 o = 0; o < tb.n_out; o++) {
+        const u64 to = ctx->mod[out[o]];
+        wt_t[2 * o] = (double)to;
+        wt_t[2 * o + 1] = 1.0 / (double)to;
+        if (to >= (1ull << 51)) continue;
+        auto bal = [to](u64 v) { return v > to / 2 ? -(double)(to - v) : (double)v; };
+        for (u32 i = 0; i < tb.n_in; i++) {
+            const u64 W = qhat[(size_t)i * tb.n_out + o];
+            wf[((size_t)o * kMaxIn + i) * 2] = bal(W);
+            wf[((size_t)o * kMaxIn + i) * 2 + 1] = bal((u64)(((u128)W << 30) % to));
+        }
+    }
+    VR_HIP(hipMalloc(&tb.wf, wf.size() * sizeof(double)));
+    VR_HIP(hipMemcpy(tb.wf, wf.data(), wf.size() * sizeof(double), hipMemcpyHostToDevice));
     tb.choice = std::make_shared<std::atomic<int>>(-1);
     return tb;
 }
@@ -470,14 +587,46 @@ void launch_mfma(vr_context* ctx, const ConvArgs& a, const ConvTable& tb, u32 n_
     VR_CHECK_LAUNCH();
 }
 
+// The FP64 kernel takes at most one input of 2^51 or more, and only as the
+// first (q_0 in digit 0); other tables stay on the integer kernels.
+bool fp_usable(const ConvTable& tb) { return tb.wf && (tb.wide & ~1u) == 0; }
+
+template <bool W0>
+void launch_fp_w(const ConvArgs& a, const ConvFp& f, dim3 grid, hipStream_t s)
+{
+    if (a.n_in <= 4)
+        hipLaunchKernelGGL((k_base_convert_fp<4, W0>), grid, dim3(kThreads), 0, s, a, f);
+    else if (a.n_in <= 8)
+        hipLaunchKernelGGL((k_base_convert_fp<8, W0>), grid, dim3(kThreads), 0, s, a, f);
+    else if (a.n_in == 9)   // digits of nine primes
+        hipLaunchKernelGGL((k_base_convert_fp<9, W0>), grid, dim3(kThreads), 0, s, a, f);
+    else if (a.n_in <= 12)
+        hipLaunchKernelGGL((k_base_convert_fp<12, W0>), grid, dim3(kThreads), 0, s, a, f);
+    else
+        hipLaunchKernelGGL((k_base_convert_fp<16, W0>), grid, dim3(kThreads), 0, s, a, f);
+}
+
+void launch_fp(vr_context* ctx, const ConvArgs& a, const ConvTable& tb, u32 n_polys, hipStream_t s)
+{
+    ConvFp f;
+    f.w = tb.wf;
+    f.t = tb.wf + (size_t)tb.n_out * kMaxIn * 2;
+    dim3 grid((ctx->n + kThreads - 1) / kThreads, n_polys);
+    if (tb.wide & 1)
+        launch_fp_w<true>(a, f, grid, s);
+    else
+        launch_fp_w<false>(a, f, grid, s);
+    VR_CHECK_LAUNCH();
+}
+
 bool mfma_usable(vr_context* ctx, const ConvTable& tb)
 {
     const size_t shmem = ((size_t)tb.groups * 4 * tb.steps * 64 + (size_t)4 * tb.steps * kDigitRow) * 8;
     return ctx->n >= kMfmaCoef && tb.wt && shmem <= 160 * 1024;
 }
 
-// Both kernels give the same words, so the first call of a table runs each
-// once on the real operands under events and keeps the faster.
+// The kernels give the same words, so the first call of a table runs each
+// once on the real operands under events and keeps the fastest.
 void launch_convert(vr_context* ctx, const ConvArgs& a, const ConvTable& tb, u32 n_polys,
                     hipStream_t s)
 {
@@ -488,26 +637,32 @@ void launch_convert(vr_context* ctx, const ConvArgs& a, const ConvTable& tb, u32
         auto it = ctx->tuning.find("base_convert");
         if (it != ctx->tuning.end()) mode = it->second;
     }
-    if (!mfma_usable(ctx, tb) || mode == 1) return launch_alu(ctx, a, n_polys, s);
+    const bool mfma = mfma_usable(ctx, tb), fp = fp_usable(tb);
+    if (mode == 1 || (mode == 2 && !mfma) || (mode == 3 && !fp)) return launch_alu(ctx, a, n_polys, s);
     if (mode == 2) return launch_mfma(ctx, a, tb, n_polys, s);
+    if (mode == 3) return launch_fp(ctx, a, tb, n_polys, s);
     int c = tb.choice->load();
     if (c < 0 && !g_capture && ctx->prof.cls < 0) {
-        hipEvent_t ev[3];
+        hipEvent_t ev[4];
         for (auto& e : ev) VR_HIP(hipEventCreate(&e));
         VR_HIP(hipEventRecord(ev[0], s));
         launch_alu(ctx, a, n_polys, s);
         VR_HIP(hipEventRecord(ev[1], s));
-        launch_mfma(ctx, a, tb, n_polys, s);
+        if (fp) launch_fp(ctx, a, tb, n_polys, s);
         VR_HIP(hipEventRecord(ev[2], s));
-        VR_HIP(hipEventSynchronize(ev[2]));
-        float t_alu = 0, t_mfma = 0;
-        VR_HIP(hipEventElapsedTime(&t_alu, ev[0], ev[1]));
-        VR_HIP(hipEventElapsedTime(&t_mfma, ev[1], ev[2]));
+        if (mfma) launch_mfma(ctx, a, tb, n_polys, s);
+        VR_HIP(hipEventRecord(ev[3], s));
+        VR_HIP(hipEventSynchronize(ev[3]));
+        float ms[3] = {0, 0, 0};
+        for (int k = 0; k < 3; k++) VR_HIP(hipEventElapsedTime(&ms[k], ev[k], ev[k + 1]));
         for (auto& e : ev) (void)hipEventDestroy(e);
-        tb.choice->store(t_mfma < t_alu ? 1 : 0);
+        int pick = fp && ms[1] < ms[0] ? 2 : 0;
+        if (mfma && ms[2] < ms[pick == 2 ? 1 : 0]) pick = 1;
+        tb.choice->store(pick);
         return;
     }
     if (c == 1) return launch_mfma(ctx, a, tb, n_polys, s);
+    if (c == 2) return launch_fp(ctx, a, tb, n_polys, s);
     launch_alu(ctx, a, n_polys, s);
 }
 

@@ -248,8 +248,10 @@ void destroy_context_tables(vr_context* ctx)
     (void)hipFree(ctx->d_pinv_tab);
     (void)hipFree(ctx->d_rinv_tab);
     (void)hipFree(ctx->d_gexp);
-    for (auto& kv : ctx->modup_tables) (void)hipFree(kv.second.dev), (void)hipFree(kv.second.wt);
-    for (auto& kv : ctx->moddown_tables) (void)hipFree(kv.second.dev), (void)hipFree(kv.second.wt);
+    for (auto& kv : ctx->modup_tables)
+        (void)hipFree(kv.second.dev), (void)hipFree(kv.second.wt), (void)hipFree(kv.second.wf);
+    for (auto& kv : ctx->moddown_tables)
+        (void)hipFree(kv.second.dev), (void)hipFree(kv.second.wt), (void)hipFree(kv.second.wf);
 }
 
 }  // namespace vr

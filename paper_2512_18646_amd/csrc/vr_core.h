@@ -282,7 +282,11 @@ struct ConvTable {
     // [groups][4][steps][64] (one 64-bit A operand per lane and instruction)
     u64* wt = nullptr;
     u32 steps = 0, groups = 0;
-    // kernel chosen for this table: -1 not yet timed, 0 vector ALU, 1 MFMA
+    // FP64 form: [n_out][16][2] balanced constants, then [n_out][2] (t, 1/t);
+    // bit i of wide: input modulus i is 2^51 or more
+    double* wf = nullptr;
+    u32 wide = 0;
+    // kernel chosen for this table: -1 not yet timed, 0 vector ALU, 1 MFMA, 2 FP64
     std::shared_ptr<std::atomic<int>> choice;
 };
 
@@ -313,7 +317,7 @@ struct vr_context {
     // device-resident constants of layer calls (weights, term lists), keyed by
     // the call's shape and weight bytes, so repeated calls upload nothing
     std::map<std::string, std::shared_ptr<void>> plans;
-    // kernel choices: "base_convert" = 0 autotune, 1 vector ALU, 2 MFMA;
+    // kernel choices: "base_convert" = 0 autotune, 1 vector ALU, 2 MFMA, 3 FP64;
     // "ntt" = 0 autotune, 1 the fixed default pass plan
     std::map<std::string, int> tuning;
     // NTT pass plans picked by the autotuner, per direction, per pass:

@@ -251,14 +251,16 @@ def test_rotation_decrypts_on_gpu():
         assert np.max(np.abs(d - np.roll(z, -st))) < 2.0 ** -20, st
 
 
-@pytest.mark.parametrize("mode", ["alu", "mfma", "auto"])
+@pytest.mark.parametrize("mode", ["alu", "mfma", "fp64", "auto"])
 @pytest.mark.parametrize("name,level", [("C2", 2), ("C2", 7), ("C3", 3), ("C3", 24), ("C3", 20)])
 def test_keyswitch_match_other_chains(name, level, mode):
     """Rotation and relinearisation with 60-bit q_0 / special primes (C2) and
-    9-prime digits with a short last digit (C3 at levels 3 and 20), with the
-    base conversions on the vector ALU, on the INT8 matrix cores, and as the
-    autotuner picks (its first call runs both kernels); one-limb digits (C2)
-    convert inside the NTT's first load whatever the mode."""
+    9-prime digits with a short last digit (C3 at levels 3 and 20; digit 0
+    holds the 60-bit q_0, split in halves by the FP64 kernel, and q_0 is a
+    target of the other digits and of ModDown, taking the integer form), with
+    the base conversions on the vector ALU, in FP64, on the INT8 matrix cores,
+    and as the autotuner picks (its first call runs every kernel); one-limb
+    digits (C2) convert inside the NTT's first load whatever the mode."""
     o, ok, g, gk = pair(name, rot_steps=(1, 3))
     z = np.random.default_rng(level).uniform(-1, 1, o.slots)
     a = o.encrypt(ok, o.encode(z, level, o.scale), 9, level)
