@@ -425,8 +425,45 @@ def rotations_bench(vr, level, n_ct, reps):
     sync()
     out["per_op"] = n_ct * reps / (time.perf_counter() - t)
     out["identical"] = bool(np.array_equal(r[0].export(), r1[0].export()))
+    out["hbm_roofline"] = keyswitch_roofline(ctx, keys, cts, level, reps)
     out["base_convert"] = convert_compare(ctx, keys, cts, level, reps)
     return out
+
+
+def keyswitch_roofline(ctx, keys, cts, level, reps):
+    """HBM rooflines of the batched rotation's NTT and key-switch inner
+    product, from the device time of every launch (HIP events):
+    NTT: a limb moves 16N bytes (read and write once); with two passes
+    (N = 2^16) the passes move 32N, the bytes HBM must carry.
+    Inner product: a unit (ciphertext x extended limb) reads its beta digit
+    limbs and writes two output limbs, 8N (beta + 2) bytes, plus the key's
+    2 beta limbs of that extended limb, 16N beta, read once per batch."""
+    n = ctx.n
+    beta = -(-(level + 1) // ctx.alpha)
+    res = {}
+    for cls in ("ntt", "ks_inner"):
+        ctx.profile_start(cls, 1 << 14)
+        for _ in range(reps):
+            r = ctx.rotate_batch(keys, cts, 1)
+            del r
+        ms, la, un, _ = ctx.profile_stop()
+        s_dev = ms / 1e3
+        if cls == "ntt":
+            moved = 32 * n * un if ctx.log_n > 14 else 16 * n * un
+            alg = 16 * n * un
+            res["ntt"] = {"launches_per_batch": la // reps, "limbs_per_batch": un // reps,
+                          "us_per_batch": round(ms * 1e3 / reps, 1),
+                          "pass_traffic_gbs": round(moved / s_dev / 1e9, 1),
+                          "pass_traffic_frac_of_8000": round(moved / s_dev / 1e9 / HBM_PEAK_GBS, 4),
+                          "algorithmic_gbs": round(alg / s_dev / 1e9, 1),
+                          "algorithmic_frac_of_8000": round(alg / s_dev / 1e9 / HBM_PEAK_GBS, 4)}
+        else:
+            b = 8 * n * (beta + 2) * un + 16 * n * beta * un // len(cts)
+            res["ks_inner"] = {"launches_per_batch": la // reps, "units_per_batch": un // reps,
+                               "us_per_batch": round(ms * 1e3 / reps, 1),
+                               "algorithmic_gbs": round(b / s_dev / 1e9, 1),
+                               "algorithmic_frac_of_8000": round(b / s_dev / 1e9 / HBM_PEAK_GBS, 4)}
+    return res
 
 
 def mfma_instructions(log_n, level, n_ct, alpha=9, K=9):
@@ -538,6 +575,8 @@ def main():
     ap.add_argument("--ntt-plan", default="auto",
                     help="NTT pass plan of the main workload: auto (autotuned), fixed, or cand:i "
                          "(pins the plan, e.g. for counter runs)")
+    ap.add_argument("--rotations-only", action="store_true",
+                    help="only the N=2^16 rotation leg (for profiling its kernels)")
     ap.add_argument("--breakdown", action="store_true",
                     help="one extra step per kernel class, reporting its device time per step")
     args = ap.parse_args()
@@ -547,6 +586,11 @@ def main():
         sys.exit(2)
 
     from paper_2512_18646_amd import vr, perop
+    if args.rotations_only:
+        out = {"rotations_per_s_n16": {"level24": rotations_bench(vr, 24, 8, args.steps),
+                                       "level3": rotations_bench(vr, 3, 32, args.steps)}}
+        print(json.dumps(out), flush=True)
+        return
     if args.copy_probe:
         # a plain 1 GiB device copy, cold then warm: the HBM counters' scale
         import torch
