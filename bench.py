@@ -441,6 +441,7 @@ def keyswitch_roofline(ctx, keys, cts, level, reps):
     n = ctx.n
     beta = -(-(level + 1) // ctx.alpha)
     res = {}
+    cnt = counter_file("rotations_n16_hbm_counters.json", ("ntt.hip", "keyswitch.hip"))
     for cls in ("ntt", "ks_inner"):
         ctx.profile_start(cls, 1 << 14)
         for _ in range(reps):
@@ -457,13 +458,39 @@ def keyswitch_roofline(ctx, keys, cts, level, reps):
                           "pass_traffic_frac_of_8000": round(moved / s_dev / 1e9 / HBM_PEAK_GBS, 4),
                           "algorithmic_gbs": round(alg / s_dev / 1e9, 1),
                           "algorithmic_frac_of_8000": round(alg / s_dev / 1e9 / HBM_PEAK_GBS, 4)}
+            if cnt and level == 24 and len(cts) == 8:
+                c = cnt["ntt_level24"]["bytes_per_limb"] * un / s_dev / 1e9
+                res["ntt"]["counter_gbs"] = round(c, 1)
+                res["ntt"]["counter_frac_of_8000"] = round(c / HBM_PEAK_GBS, 4)
         else:
             b = 8 * n * (beta + 2) * un + 16 * n * beta * un // len(cts)
             res["ks_inner"] = {"launches_per_batch": la // reps, "units_per_batch": un // reps,
                                "us_per_batch": round(ms * 1e3 / reps, 1),
                                "algorithmic_gbs": round(b / s_dev / 1e9, 1),
                                "algorithmic_frac_of_8000": round(b / s_dev / 1e9 / HBM_PEAK_GBS, 4)}
+            k = cnt["ks_inner"].get(str(level)) if cnt else None
+            if k and un // reps == k["units"]:
+                c = (k["read_bytes_per_unit"] + k["write_bytes_per_unit"]) * un / s_dev / 1e9
+                res["ks_inner"]["counter_gbs"] = round(c, 1)
+                res["ks_inner"]["counter_frac_of_8000"] = round(c / HBM_PEAK_GBS, 4)
     return res
+
+
+def counter_file(name, sources):
+    """Counter-derived bytes per unit from profiles/, only while every kernel
+    source it was measured on is byte-identical (else None)."""
+    import hashlib
+    try:
+        with open(os.path.join(ROOT, "profiles", name)) as f:
+            cnt = json.load(f)
+        for src in sources:
+            with open(os.path.join(ROOT, "paper_2512_18646_amd", "csrc", src), "rb") as f:
+                key = src.split(".")[0] + "_source_sha256_prefix"
+                if not hashlib.sha256(f.read()).hexdigest().startswith(cnt[key]):
+                    return None
+        return cnt
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def mfma_instructions(log_n, level, n_ct, alpha=9, K=9):
@@ -586,11 +613,6 @@ def main():
         sys.exit(2)
 
     from paper_2512_18646_amd import vr, perop
-    if args.rotations_only:
-        out = {"rotations_per_s_n16": {"level24": rotations_bench(vr, 24, 8, args.steps),
-                                       "level3": rotations_bench(vr, 3, 32, args.steps)}}
-        print(json.dumps(out), flush=True)
-        return
     if args.copy_probe:
         # a plain 1 GiB device copy, cold then warm: the HBM counters' scale
         import torch
@@ -600,6 +622,11 @@ def main():
             dst.copy_(src)
         sync()
         del src, dst
+    if args.rotations_only:
+        out = {"rotations_per_s_n16": {"level24": rotations_bench(vr, 24, 8, args.steps),
+                                       "level3": rotations_bench(vr, 3, 32, args.steps)}}
+        print(json.dumps(out), flush=True)
+        return
     log("setup: encrypting %d sets of 256 images at level %d" % (args.sets, args.level))
     W, ctx, keys, K, bias, cols = conv_setup(vr, args.level, args.sets, args.ntt_plan)
     images = W.batch * args.sets
