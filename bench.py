@@ -112,7 +112,7 @@ def plain_conv_sq_fc(X, K, bias, stride, pad, Wfc, bfc):
     return Y.reshape(B, -1) @ Wfc.reshape(Wfc.shape[0], -1).T + bfc[None, :]
 
 
-def cnn128_bench(vr, level_in, sets, reps):
+def cnn128_bench(vr, level_in, sets, reps, graph=False):
     """The 3x128x128 CNN (conv 3x3/2 pad 1 x8, x^2, FC 8*64*64 -> 10) at
     N = 2^16, L = 24 (60 + 24x50, P 9x51, dnum 3), 128 images per set (one
     set = 384 column ciphertexts), sets evaluated one after another."""
@@ -156,13 +156,50 @@ def cnn128_bench(vr, level_in, sets, reps):
             lat.append((time.perf_counter() - t) * 1e3)
             del z
     total = time.perf_counter() - t_all
+    res = {"workload": "3x128x128 images, conv 3x3/2 pad 1 x8 + x^2 + FC 32768->10, N=2^16 L=24, "
+                       "128 images per set", "level_in": level_in, "sets": sets, "reps": reps,
+           "path": "three layer calls per set (conv, x^2, FC)",
+           "images_per_s": round(W.batch * sets * reps / total, 2),
+           "ms_per_set_p50": round(percentile(lat, 50), 2), "ms_per_set_p99": round(percentile(lat, 99), 2),
+           "decoded_rel_error": err, "setup_s": round(setup_s, 1)}
+    if graph:
+        # every set in one whole-network call, and that call captured as one
+        # HIP graph and replayed; limbs against the layer calls
+        net = vr.CNN(W.channels, W.h, W.w, W.pad, K, bias, W.stride, square=True, fc_w=W_pt,
+                     fc_bias=bfc, fc_block=Hp)
+        flat = [c for cs in cols for c in cs]
+        ref = network(cols[0])
+        z = net.forward(ctx, keys, flat, n_sets=sets)
+        sync()
+        same = all(np.array_equal(z[i].export(), ref[i].export()) for i in range(len(ref)))
+        del z
+        t = time.perf_counter()
+        for r in range(reps):
+            z = net.forward(ctx, keys, flat, n_sets=sets)
+            sync()
+            del z
+        res["network_call"] = {"images_per_s": round(W.batch * sets * reps / (time.perf_counter() - t), 2),
+                               "identical": bool(same)}
+        gr = vr.Graph(ctx, keys, net, flat, n_sets=sets)
+        gr.launch()
+        sync()
+        glat = []
+        t = time.perf_counter()
+        for r in range(reps):
+            t1 = time.perf_counter()
+            gr.launch()
+            sync()
+            glat.append((time.perf_counter() - t1) * 1e3)
+        g_total = time.perf_counter() - t
+        gout = gr.outputs()
+        same = all(np.array_equal(gout[i].export(), ref[i].export()) for i in range(len(ref)))
+        res["graph"] = {"images_per_s": round(W.batch * sets * reps / g_total, 2),
+                        "ms_per_replay_p50": round(percentile(glat, 50), 2), "identical": bool(same)}
+        del gout, ref
+        gr.close()
     reserved, _ = ctx.mem_info()
-    return {"workload": "3x128x128 images, conv 3x3/2 pad 1 x8 + x^2 + FC 32768->10, N=2^16 L=24, "
-                        "128 images per set", "level_in": level_in, "sets": sets, "reps": reps,
-            "images_per_s": round(W.batch * sets * reps / total, 2),
-            "ms_per_set_p50": round(percentile(lat, 50), 2), "ms_per_set_p99": round(percentile(lat, 99), 2),
-            "decoded_rel_error": err, "setup_s": round(setup_s, 1),
-            "device_gib_reserved": round(reserved / 2 ** 30, 1)}
+    res["device_gib_reserved"] = round(reserved / 2 ** 30, 1)
+    return res
 
 
 def uneven_bench(vr, n_req, level, reps, seed=4):
@@ -726,7 +763,7 @@ def main():
     if not args.no_extra and not args.no_cnn:
         for lv, sets in ((3, args.cnn_sets), (24, 1)):
             log("cnn128 at level %d" % lv)
-            out.setdefault("cnn128_n16", []).append(cnn128_bench(vr, lv, sets, 2))
+            out.setdefault("cnn128_n16", []).append(cnn128_bench(vr, lv, sets, 2, graph=(lv == 3)))
 
     if not args.no_extra and not args.no_uneven:
         log("uneven batch at N=2^16")
