@@ -24,6 +24,17 @@ from its single-ciphertext algorithms:
           column j' sums MulConst(Rot(col(c, s j'+v-pi), u), K[c'][c][u][v]) over
           c, u, v, adds the bias and rescales; slot b H' + s i' holds output
           row i' of image b.
+  matmul (outer-product form; the rotation-free alternative to the
+          revolver above, built from the paper's observation that split
+          operands are multiplied pair-wise and summed by linearity): C is
+          tiled by R = S / P' rows per ciphertext (P' = pow2(p)); for tile t
+          and inner index k the ciphertext A'_{t,k} holds A[t R + r][k] in
+          every slot r P' + j with j < p (column k of A replicated across the
+          row), and B'_k holds B[k][j] in slot r P' + j for every r (row k of
+          B tiled down the rows).  Then
+              C_t = Rescale(Relin(sum_k A'_{t,k} * B'_k)),
+          slot r P' + j of C_t holds C[t R + r][j]: n tensors and one
+          relinearisation per tile, no rotation.
   square  Rescale(Relin(Tensor(Y, Y))).
   fc      Rescale(sum_{c',j'} MulPlain(Y(c',j'), pt_{o,c',j'})), then the
           SumColVec-style Z += Rot(Z, 2^t) over the H' block, then the bias.
@@ -127,6 +138,43 @@ def encrypt_matrix_columns(ctx: Context, keys: Keys, M, role, m, p, level, seed,
                         seed, first_ct_id + k) for k in range(n)]
 
 
+def outer_tiles(ctx: Context, m, p):
+    """(P', R, T): column padding, rows per ciphertext and row tiles of the
+    outer-product form."""
+    Pp = pow2ceil(p)
+    if Pp > ctx.slots:
+        raise ValueError("p exceeds the slot count")
+    R = ctx.slots // Pp
+    return Pp, R, -(-m // R)
+
+
+def matrix_outer_slots(ctx: Context, M, role, m, p, t, k):
+    """role 2: A'_{t,k}, slot r P' + j -> A[t R + r][k] for j < p and
+    t R + r < m; role 3: B'_k, slot r P' + j -> B[k][j] for j < p."""
+    M = np.asarray(M, np.float64)
+    Pp, R, _ = outer_tiles(ctx, m, p)
+    s = np.arange(ctx.slots)
+    r, j = s // Pp, s % Pp
+    if role == 2:
+        i = t * R + r
+        return np.where((j < p) & (i < m), M[np.minimum(i, m - 1), k], 0.0)
+    return np.where(j < p, M[k, np.minimum(j, p - 1)], 0.0)
+
+
+def encrypt_matrix_outer(ctx: Context, keys: Keys, M, role, m, p, level, seed, first_ct_id):
+    """role 2 (A, m x n): T n ciphertexts, A'_{t,k} at index t n + k; role 3
+    (B, n x p): n ciphertexts B'_k.  Ciphertext i has id first_ct_id + i."""
+    M = np.asarray(M, np.float64)
+    _, _, T = outer_tiles(ctx, m, p)
+    if role == 2:
+        n = M.shape[1]
+        idx = [(t, k) for t in range(T) for k in range(n)]
+    else:
+        idx = [(0, k) for k in range(M.shape[0])]
+    return [ctx.encrypt(keys, ctx.encode(matrix_outer_slots(ctx, M, role, m, p, t, k), level, ctx.scale),
+                        seed, first_ct_id + i) for i, (t, k) in enumerate(idx)]
+
+
 # ------------------------------------------------------------- schedules
 
 
@@ -152,6 +200,31 @@ def matmul_decode(ctx: Context, keys: Keys, D, m, p):
             col = (i + idx) % Pp
             if col < p:
                 C[i, col] = z[i]
+    return C
+
+
+def matmul_outer(ctx: Context, keys: Keys, A_cts, B_cts, m, n, p):
+    """C_t = Rescale(Relin(sum_k Tensor(A'_{t,k}, B'_k))) for every row tile t."""
+    _, _, T = outer_tiles(ctx, m, p)
+    out = []
+    for t in range(T):
+        acc = None
+        for k in range(n):
+            x = ctx.tensor(A_cts[t * n + k], B_cts[k])
+            acc = x if acc is None else ctx.add(acc, x)
+        out.append(ctx.rescale(ctx.relinearize(acc, keys)))
+    return out
+
+
+def matmul_outer_decode(ctx: Context, keys: Keys, D, m, p):
+    Pp, R, T = outer_tiles(ctx, m, p)
+    C = np.full((m, p), np.nan)
+    for t in range(T):
+        z = ctx.decode(ctx.decrypt(keys, D[t]))
+        for r in range(R):
+            i = t * R + r
+            if i < m:
+                C[i, :] = z[r * Pp:r * Pp + p]
     return C
 
 

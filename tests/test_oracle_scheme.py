@@ -179,6 +179,57 @@ def test_matmul_schedule_identity_and_ragged(ctx10):
     assert Ly.rel_error(C, A) < EPS
 
 
+def test_matmul_outer_slot_layout_brute_force():
+    """The outer-product encodings on plain slot vectors: sum_k A'_{t,k} * B'_k
+    (element-wise, exact on small integers) is tile t of A B, slot r P' + j
+    = C[t R + r][j], zeros elsewhere; brute force over ragged shapes with
+    several tiles (m not a multiple of R, p not a power of two)."""
+    ctx = small_ctx(log_n=6)   # 32 slots
+    rng = np.random.default_rng(5)
+    for m, n, p in ((5, 3, 3), (13, 4, 5), (2, 7, 8), (33, 2, 1)):
+        A = rng.integers(-9, 10, (m, n)).astype(float)
+        B = rng.integers(-9, 10, (n, p)).astype(float)
+        C = A @ B
+        Pp, R, T = Ly.outer_tiles(ctx, m, p)
+        assert Pp * R == ctx.slots and T == -(-m // R)
+        seen = np.zeros((m, p), bool)
+        for t in range(T):
+            acc = sum(Ly.matrix_outer_slots(ctx, A, 2, m, p, t, k) * Ly.matrix_outer_slots(ctx, B, 3, m, p, 0, k)
+                      for k in range(n))
+            for s in range(ctx.slots):
+                i, j = t * R + s // Pp, s % Pp
+                if i < m and j < p:
+                    assert acc[s] == C[i, j]
+                    seen[i, j] = True
+                else:
+                    assert acc[s] == 0.0
+        assert seen.all()
+
+
+def test_matmul_outer_schedule_random_and_identity(ctx10):
+    """Encrypted outer-product product against FP64 (two row tiles with a
+    ragged last one at N = 2^10: S = 512, P' = 64, R = 8, m = 12), and A = I
+    giving C = B; n tensors and one relinearisation per tile, no rotation."""
+    ctx, keys = ctx10
+    rng = np.random.default_rng(3)
+    m, n, p = 12, 7, 40
+    A, B = rng.uniform(-1, 1, (m, n)), rng.uniform(-1, 1, (n, p))
+    Ac = Ly.encrypt_matrix_outer(ctx, keys, A, 2, m, p, 3, 3, 0)
+    Bc = Ly.encrypt_matrix_outer(ctx, keys, B, 3, m, p, 3, 3, 1000)
+    assert len(Ac) == 2 * n and len(Bc) == n
+    D = Ly.matmul_outer(ctx, keys, Ac, Bc, m, n, p)
+    assert len(D) == 2 and D[0].level == 2
+    C = Ly.matmul_outer_decode(ctx, keys, D, m, p)
+    assert not np.any(np.isnan(C))
+    assert Ly.rel_error(C, A @ B) < EPS
+    m2 = n2 = 6
+    B2 = rng.uniform(-1, 1, (n2, p))
+    Ac = Ly.encrypt_matrix_outer(ctx, keys, np.eye(m2), 2, m2, p, 3, 4, 0)
+    Bc = Ly.encrypt_matrix_outer(ctx, keys, B2, 3, m2, p, 3, 4, 1000)
+    C = Ly.matmul_outer_decode(ctx, keys, Ly.matmul_outer(ctx, keys, Ac, Bc, m2, n2, p), m2, p)
+    assert Ly.rel_error(C, B2) < EPS
+
+
 def test_conv_schedule_random_square_fc(ctx10):
     ctx, keys = ctx10
     B, Ci, h, w, Co, k, s, pad = 8, 2, 10, 9, 3, 3, 2, 1
