@@ -165,7 +165,12 @@ vr_status vr_encrypt_columns(vr_context *ctx, const vr_eval_keys *ek, const doub
  * holds slot s -> A[s mod M'][k] (column k of the tau_a encoding, period
  * M' = pow2(m)).  role 1: M is B (n x p), ciphertext k holds slot s ->
  * B[k][s mod P'] (column k of the tau_b encoding, period P' = pow2(p)).
- * Zeros past m rows / p columns.  out receives n handles. */
+ * Zeros past m rows / p columns.  out receives n handles.  Outer-product
+ * operands (vr_matmul_outer): role 2: M is A (m x n), T n ciphertexts
+ * A'_{t,k} at index t n + k (T = ceil(m / R), R = S / P'), slot r P' + j ->
+ * A[t R + r][k] for j < p and t R + r < m; role 3: M is B (n x p), n
+ * ciphertexts B'_k, slot r P' + j -> B[k][j] for j < p and every r < R.
+ * Ciphertext i is encrypted with ct_id = first_ct_id + i. */
 vr_status vr_encrypt_matrix_columns(vr_context *ctx, const vr_eval_keys *ek, const double *M,
                                     uint32_t rows, uint32_t cols, uint32_t role, uint32_t m,
                                     uint32_t p, uint32_t level, uint64_t seed,
@@ -231,6 +236,21 @@ vr_status vr_rotate_batch(vr_context *ctx, const vr_eval_keys *ek, const vr_ciph
 vr_status vr_matmul(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *A,
                     const vr_ciphertext *const *Bbar, uint32_t m, uint32_t n, uint32_t p,
                     vr_ciphertext **C, void *stream);
+
+/* Outer-product matrix product, the rotation-free form of the split product
+ * (split operands are multiplied pair-wise and summed by linearity: "Secure
+ * Inference"): C is tiled by R = S / P' rows per ciphertext (P' = pow2(p),
+ * S slots), T = ceil(m / R) tiles.  A holds T n ciphertexts A'_{t,k} (index
+ * t n + k; vr_encrypt_matrix_columns role 2): slot r P' + j = A[t R + r][k]
+ * for j < p; B holds n ciphertexts B'_k (role 3): slot r P' + j = B[k][j].
+ *   C[t] = Rescale(Relin(sum_k A'_{t,k} * B'_k)),
+ * slot r P' + j of C[t] holding (A B)[t R + r][j].  No rotation and no
+ * rotation key; any m, n and p with P' <= S.  C receives T handles.
+ * VR_EINVAL for empty shapes or p above S; VR_ELEVEL / VR_ESCALE when the
+ * inputs differ in level or scale. */
+vr_status vr_matmul_outer(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *A,
+                          const vr_ciphertext *const *B, uint32_t m, uint32_t n, uint32_t p,
+                          vr_ciphertext **C, void *stream);
 /* Column convolution (conv layer of "Convolutional Neural Networks", with
  * per-channel accumulation of "Parallelized Convolution Operation"): inputs
  * in[c*w + j] from vr_encrypt_columns; K is [C_out][C_in][k][k], bias

@@ -785,6 +785,36 @@ std::vector<Slab> matmul_multi(vr_context* ctx, const vr_eval_keys* ek, const st
     return res;
 }
 
+// Outer-product product (the rotation-free form of the split product): row
+// tile t accumulates sum_k Tensor(A'_{t,k}, B'_k) (A' tile-major, t n + k),
+// then every tile is relinearised and rescaled together.  No rotation.
+Slab matmul_outer(vr_context* ctx, const vr_eval_keys* ek, const Slab& A, const Slab& B, u32 n, u32 T,
+                  hipStream_t s)
+{
+    if (A.level != B.level) throw Error(VR_ELEVEL, "matmul inputs at different levels");
+    if (A.ncomp != 2 || B.ncomp != 2) throw Error(VR_EINVAL, "matmul inputs must be 2-component");
+    if (A.n != T * n || B.n != n) throw Error(VR_EINVAL, "outer product needs T n and n ciphertexts");
+    const u32 nl = A.level + 1;
+    Slab acc = new_slab(ctx, T, 3, A.level, A.scale * B.scale, s);
+    dim3 grid((ctx->n + kThreads - 1) / kThreads, nl);
+    for (u32 t = 0; t < T; t++) {
+        hipLaunchKernelGGL(k_tensor_acc, grid, dim3(kThreads), 0, s, acc.ct(t), A.ct(t * n), A.stride, B.base,
+                           B.stride, n, nl, ctx->log_n, ctx->d_modq);
+        VR_CHECK_LAUNCH();
+    }
+    return rescale_slab(ctx, relin_slab(ctx, ek, acc, s), s);
+}
+
+// (P', R, T) of the outer-product form: column padding, rows per ciphertext,
+// row tiles
+void outer_tiles(vr_context* ctx, u32 m, u32 p, u32* Pp, u32* R, u32* T)
+{
+    *Pp = pow2ceil(p);
+    if (*Pp > ctx->slots) throw Error(VR_EINVAL, "p exceeds the slot count");
+    *R = (u32)(ctx->slots / *Pp);
+    *T = (m + *R - 1) / *R;
+}
+
 }  // namespace vr
 
 using namespace vr;
@@ -845,21 +875,41 @@ vr_status vr_encrypt_matrix_columns(vr_context* ctx, const vr_eval_keys* ek, con
                                     uint32_t p, uint32_t level, uint64_t seed,
                                     uint64_t first_ct_id, vr_ciphertext** out)
 {
-    const u32 n_ct = role == 0 ? cols : rows;
+    // outputs: role 0 cols, role 1 rows, role 2 T cols, role 3 rows
+    u32 n_ct = role == 0 || role == 2 ? cols : rows;
+    if (role == 2 && ctx && p >= 1 && p <= ctx->slots && m >= 1) {
+        const u32 R = (u32)(ctx->slots / pow2ceil(p));
+        n_ct = ((m + R - 1) / R) * cols;
+    }
     if (out)
         for (u32 i = 0; i < n_ct; i++) out[i] = nullptr;
     API_BEGIN
     REQUIRE(ctx && ek && M && out, "null argument");
-    REQUIRE(role <= 1, "role must be 0 (A) or 1 (B)");
-    REQUIRE(rows >= 1 && cols >= 1, "empty matrix");
-    REQUIRE(role == 0 ? rows == m : cols == p, "matrix shape does not match m / p");
+    REQUIRE(role <= 3, "role must be 0 (A columns), 1 (Bbar columns), 2 (A outer) or 3 (B outer)");
+    REQUIRE(rows >= 1 && cols >= 1 && m >= 1 && p >= 1, "empty matrix");
+    REQUIRE(role == 0 || role == 2 ? rows == m : cols == p, "matrix shape does not match m / p");
     REQUIRE(level <= ctx->L, "level above the modulus chain");
     const u32 Mp = pow2ceil(m), Pp = pow2ceil(p);
-    REQUIRE(Mp <= ctx->slots && Pp <= ctx->slots, "matrix dimension exceeds the slot count");
+    REQUIRE(Pp <= ctx->slots && (role >= 2 || Mp <= ctx->slots), "matrix dimension exceeds the slot count");
     const size_t S = ctx->slots;
+    const u32 R = (u32)(S / Pp);
     std::vector<double> slots((size_t)n_ct * S, 0.0);
-    for (u32 k = 0; k < n_ct; k++) {
-        double* z = &slots[(size_t)k * S];
+    for (u32 c = 0; c < n_ct; c++) {
+        double* z = &slots[(size_t)c * S];
+        if (role == 2) {
+            // A'_{t,k} (c = t cols + k): slot r P' + j -> A[t R + r][k], j < p
+            const u32 t = c / cols, k = c - t * cols;
+            for (u32 r = 0; r < R && (size_t)t * R + r < m; r++)
+                for (u32 j = 0; j < p; j++) z[(size_t)r * Pp + j] = M[((size_t)t * R + r) * cols + k];
+            continue;
+        }
+        if (role == 3) {
+            // B'_k: slot r P' + j -> B[k][j], j < p, every row r
+            for (u32 r = 0; r < R; r++)
+                for (u32 j = 0; j < p; j++) z[(size_t)r * Pp + j] = M[(size_t)c * cols + j];
+            continue;
+        }
+        const u32 k = c;
         for (size_t s = 0; s < S; s++) {
             if (role == 0) {
                 u32 r = (u32)(s % Mp);
@@ -910,6 +960,30 @@ vr_status vr_matmul(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext
     rq.m = m, rq.n = n, rq.p = p;
     std::vector<Slab> out = matmul_multi(ctx, ek, {rq}, s);
     to_handles(ctx, out[0], C);
+    API_END
+}
+
+vr_status vr_matmul_outer(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* const* A,
+                          const vr_ciphertext* const* B, uint32_t m, uint32_t n, uint32_t p,
+                          vr_ciphertext** C, void* stream)
+{
+    u32 T = 0;
+    if (ctx && m >= 1 && p >= 1 && pow2ceil(p) <= ctx->slots) {
+        const u32 R = (u32)(ctx->slots / pow2ceil(p));
+        T = (m + R - 1) / R;
+    }
+    if (C)
+        for (u32 i = 0; i < T; i++) C[i] = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && A && B && C, "null argument");
+    REQUIRE(m >= 1 && n >= 1 && p >= 1, "empty matrix");
+    u32 Pp, R, Tt;
+    outer_tiles(ctx, m, p, &Pp, &R, &Tt);
+    hipStream_t s = pick_stream(ctx, stream);
+    Slab a = gather(ctx, A, Tt * n, s);
+    Slab b = gather(ctx, B, n, s);
+    Slab out = matmul_outer(ctx, ek, a, b, n, Tt, s);
+    to_handles(ctx, out, C);
     API_END
 }
 

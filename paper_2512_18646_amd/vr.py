@@ -87,6 +87,7 @@ _SIGS = {
     "vr_rotate_many": [P, P, P, P, SZ, PP, P],
     "vr_rotate_batch": [P, P, PP, SZ, I32, PP, P],
     "vr_matmul": [P, P, PP, PP, U32, U32, U32, PP, P],
+    "vr_matmul_outer": [P, P, PP, PP, U32, U32, U32, PP, P],
     "vr_conv2d": [P, P, PP, U32, U32, U32, U32, P, P, U32, U32, U32, PP, P],
     "vr_conv2d_sets": [P, P, PP, U32, U32, U32, U32, U32, P, P, U32, U32, U32, PP, P],
     "vr_square": [P, P, PP, SZ, PP, P],
@@ -357,6 +358,8 @@ class Context:
         M = _f64(M)
         rows, cols = M.shape
         n = cols if role == 0 else rows
+        if role == 2:
+            n = self.outer_tiles(m, p)[2] * cols
         arr = (ctypes.c_void_p * n)()
         _check(lib.vr_encrypt_matrix_columns(self.h, keys.ek, M.ctypes.data, rows, cols, role, m, p,
                                              level, seed, first_ct_id, arr))
@@ -434,6 +437,22 @@ class Context:
         _check(lib.vr_matmul(self.h, keys.ek, _ptr_array(A), _ptr_array(Bbar), m, n, p, arr,
                              _stream(stream)))
         return [Ciphertext(arr[i], self) for i in range(Pp)]
+
+    def outer_tiles(self, m, p):
+        """(P', R, T) of the outer-product product: column padding, rows per
+        ciphertext, row tiles."""
+        Pp = 1
+        while Pp < p:
+            Pp *= 2
+        R = max(1, self.slots // Pp)
+        return Pp, R, -(-m // R)
+
+    def matmul_outer(self, keys, A, B, m, n, p, stream=None):
+        T = self.outer_tiles(m, p)[2]
+        arr = (ctypes.c_void_p * T)()
+        _check(lib.vr_matmul_outer(self.h, keys.ek, _ptr_array(A), _ptr_array(B), m, n, p, arr,
+                                   _stream(stream)))
+        return [Ciphertext(arr[i], self) for i in range(T)]
 
     def conv2d(self, keys, cols, C_in, h, w, pad, K, bias, stride, stream=None):
         K = _f64(K)

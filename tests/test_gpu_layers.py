@@ -85,6 +85,66 @@ def test_matmul_ragged_identity_and_per_op(c1mm):
     assert Ly.rel_error(gpu_matmul_decode(g, gk, gD, m, p), A) < EPS
 
 
+def gpu_outer_decode(g, gk, D, m, p):
+    Pp, R, T = g.outer_tiles(m, p)
+    assert len(D) == T
+    C = np.full((m, p), np.nan)
+    for t, ct in enumerate(D):
+        z = g.decode(g.decrypt(gk, ct))
+        for r in range(R):
+            if t * R + r < m:
+                C[t * R + r] = z[r * Pp:r * Pp + p]
+    return C
+
+
+def test_matmul_outer_bit_exact_ragged_tiles(c1mm):
+    """Outer-product product at N = 2^13 (S = 4096): m = 300, n = 5, p = 20
+    gives P' = 32, R = 128, three row tiles (the last one ragged); oracle
+    ciphertexts in, every limb of every tile against the oracle, decoded
+    against FP64."""
+    o, ok, g, gk = c1mm
+    m, n, p = 300, 5, 20
+    rng = np.random.default_rng(61)
+    A, B = rng.uniform(-1, 1, (m, n)), rng.uniform(-1, 1, (n, p))
+    Ac = Ly.encrypt_matrix_outer(o, ok, A, 2, m, p, 3, 1001, 0)
+    Bc = Ly.encrypt_matrix_outer(o, ok, B, 3, m, p, 3, 1001, 500)
+    D = Ly.matmul_outer(o, ok, Ac, Bc, m, n, p)
+    gD = g.matmul_outer(gk, [to_gpu(g, c) for c in Ac], [to_gpu(g, c) for c in Bc], m, n, p)
+    assert len(gD) == len(D) == 3
+    for i, (x, y) in enumerate(zip(gD, D)):
+        assert_same(x, y, "C[%d]" % i)
+    assert Ly.rel_error(gpu_outer_decode(g, gk, gD, m, p), A @ B) < EPS
+
+
+def test_matmul_outer_gpu_encrypt_end_to_end(c1mm):
+    """GPU encode/encrypt of the outer-product operands (roles 2 and 3), GPU
+    product, GPU decrypt/decode against FP64: m = 200, n = 40, p = 100 (P' =
+    128, R = 32, seven tiles), m = 1 with p = 1, and p = S (one row per tile)."""
+    o, ok, g, gk = c1mm
+    rng = np.random.default_rng(62)
+    for m, n, p in ((200, 40, 100), (1, 3, 1), (3, 2, g.slots)):
+        A, B = rng.uniform(-1, 1, (m, n)), rng.uniform(-1, 1, (n, p))
+        gA = g.encrypt_matrix_columns(gk, A, 2, m, p, 3, 7, 0)
+        gB = g.encrypt_matrix_columns(gk, B, 3, m, p, 3, 7, 100000)
+        assert len(gA) == g.outer_tiles(m, p)[2] * n and len(gB) == n
+        C = gpu_outer_decode(g, gk, g.matmul_outer(gk, gA, gB, m, n, p), m, p)
+        assert not np.any(np.isnan(C))
+        assert Ly.rel_error(C, A @ B) < EPS, (m, n, p)
+
+
+def test_matmul_outer_errors(c1mm):
+    from paper_2512_18646_amd import vr
+    o, ok, g, gk = c1mm
+    A = g.encrypt_matrix_columns(gk, np.ones((4, 2)), 2, 4, 3, 3, 1, 0)
+    B = g.encrypt_matrix_columns(gk, np.ones((2, 3)), 3, 4, 3, 2, 1, 50)
+    with pytest.raises(vr.VRError) as e:
+        g.matmul_outer(gk, A, B, 4, 2, 3)
+    assert e.value.code == vr.VR_ELEVEL
+    with pytest.raises(vr.VRError) as e:
+        g.encrypt_matrix_columns(gk, np.ones((2, 2 * g.slots)), 3, 4, 2 * g.slots, 3, 1, 0)
+    assert e.value.code == vr.VR_EINVAL
+
+
 def test_matmul_rejects_m_below_p(c1mm):
     from paper_2512_18646_amd import vr
     o, ok, g, gk = c1mm
