@@ -293,6 +293,85 @@ def uneven_bench(vr, n_req, level, reps, seed=4):
             "identical_to_per_request": bool(same_eager and same_graph), "product_rel_error": err}
 
 
+def uneven_full_bench(vr, n_req, level, reps, seed=4):
+    """The mixed batch at its full size ranges, N = 2^16 (L = 24 chain,
+    entering at `level`): products with m, n, p uniform in 16..512 through the
+    outer-product form (vr_matmul_outer: row tiles, no rotation) and 3x3/2
+    convolutions (8 filters, x^2) on 32x32 .. 256x256 images (full ciphertext
+    sets), one call per request.  Reports the rotations the column-split form
+    would have needed (n (P' - 1) per product, transposed when p > m)."""
+    import synthetic_inputs as SI
+    reqs = SI.uneven_requests(seed, n_req, dim_range=(16, 512), sides=(32, 64, 128, 256), p_le_m=False)
+    ctx = vr.Context(16, [60] + [50] * 24, [51] * 9, 3, 50.0)
+    keys = ctx.keygen(1004, rot_steps=[1, 2])
+    t0 = time.perf_counter()
+    nets, items = {}, []
+    images = rot_split = tensors = 0
+    for i, (kind, shape, rs) in enumerate(reqs):
+        if kind == "matmul":
+            m, n, p = shape
+            A, B = SI.matmul_operands(rs, m, n, p)
+            items.append(("matmul", ctx.encrypt_matrix_columns(keys, A, 2, m, p, level, 1004, 100000 * i),
+                          ctx.encrypt_matrix_columns(keys, B, 3, m, p, level, 1004, 100000 * i + 90000),
+                          (m, n, p), (A, B)))
+            lo, hi = min(m, p), max(m, p)
+            rot_split += n * ((1 << (lo - 1).bit_length()) - 1)
+            tensors += ctx.outer_tiles(m, p)[2] * n
+        else:
+            side = shape
+            if side not in nets:
+                K, bias = SI.conv_weights(seed + side, 8, 1, 3, 0.05)
+                nets[side] = vr.CNN(1, side, side, 1, K, bias, 2, square=True)
+            hp = 1 << (side + 1).bit_length()
+            B = ctx.slots // hp
+            X = SI.images(rs, B, 1, side, side)
+            items.append(("conv", ctx.encrypt_columns(keys, X, 1, level, 1004, 100000 * i), side, B))
+            images += B
+    sync()
+    setup_s = time.perf_counter() - t0
+
+    def run():
+        outs = []
+        for it in items:
+            if it[0] == "matmul":
+                outs.append(ctx.matmul_outer(keys, it[1], it[2], *it[3]))
+            else:
+                outs.append(nets[it[2]].forward(ctx, keys, it[1]))
+        return outs
+
+    outs = run()
+    sync()
+    # decoded check of every product against FP64
+    err = 0.0
+    for it, o in zip(items, outs):
+        if it[0] != "matmul":
+            continue
+        (m, n, p), (A, B) = it[3], it[4]
+        Pp, R, T = ctx.outer_tiles(m, p)
+        C = np.zeros((m, p))
+        for t, ct in enumerate(o):
+            z = ctx.decode(ctx.decrypt(keys, ct))
+            rows = min(R, m - t * R)
+            C[t * R:t * R + rows] = z[:rows * Pp].reshape(rows, Pp)[:, :p]
+        err = max(err, float(np.max(np.abs(C - A @ B)) / np.max(np.abs(A @ B))))
+    del outs
+    t = time.perf_counter()
+    for _ in range(reps):
+        o = run()
+        del o
+    sync()
+    t_run = (time.perf_counter() - t) / reps
+    n_mm = sum(1 for it in items if it[0] == "matmul")
+    reserved, _ = ctx.mem_info()
+    return {"workload": "%d requests: %d products (m, n, p in 16..512, outer-product form), %d 3x3/2 x8 + x^2 "
+                        "convolutions on 32x32 .. 256x256 images (full sets), N=2^16 L=24 chain at level %d"
+                        % (n_req, n_mm, n_req - n_mm, level),
+            "requests_per_s": round(n_req / t_run, 2), "ms_per_batch": round(t_run * 1e3, 1),
+            "conv_images_per_s": round(images / t_run, 1), "product_tensors": tensors,
+            "column_split_rotations_avoided": rot_split, "products_max_rel_error": err,
+            "setup_s": round(setup_s, 1), "device_gib_reserved": round(reserved / 2 ** 30, 1)}
+
+
 def serving_n16_bench(vr, level=3, n_sessions=8, n_warm=20, n_meas=100, loads=(0.25, 0.5, 0.75, 0.9),
                       seed=5):
     """Serving at N = 2^16 (L = 24 chain, requests entering at `level`): 8
@@ -768,6 +847,8 @@ def main():
     if not args.no_extra and not args.no_uneven:
         log("uneven batch at N=2^16")
         out["uneven_batch_n16"] = uneven_bench(vr, 64, 3, 2)
+        log("uneven batch at full size ranges (outer-product products)")
+        out["uneven_full_n16"] = uneven_full_bench(vr, 64, 3, 2)
 
     if not args.no_extra and not args.no_serve:
         log("serving (Poisson arrivals, image-size mix)")
