@@ -248,7 +248,7 @@ static void key_switch(vr_context* ctx, const u64* d, u32 level, const u64* key,
     u64* U = coef + (size_t)k.nq * n;
     u64* md = U + (size_t)2 * k.next * n;
     keyswitch_modup(ctx, d, level, X, coef, s);
-    keyswitch_inner(ctx, X, key, level, g, U, s);
+    keyswitch_inner(ctx, X, d, key, level, g, U, s);
     keyswitch_moddown(ctx, U, level, out0, out1, add0, g, add1, md, s);
 }
 
@@ -346,7 +346,7 @@ void ev_rotate_many(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext
             md = U + (size_t)2 * sh.next * n;
             keyswitch_modup(ctx, a->data + poly, level, X, coef, s);
         }
-        keyswitch_inner(ctx, X, rot_key(ek, gs[i]).data, level, gs[i], U, s);
+        keyswitch_inner(ctx, X, a->data + poly, rot_key(ek, gs[i]).data, level, gs[i], U, s);
         keyswitch_moddown(ctx, U, level, o->data, o->data + poly, a->data, gs[i], nullptr, md, s);
     }
     for (size_t i = 0; i < k; i++) outs[i] = made[i].release();

@@ -310,10 +310,11 @@ struct LimbRuns {
 };
 
 template <int MAXB, bool FP>
-__global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_stride, u32 n_ct,
-                                                      const u64* key, u32 nmod, u32 level,
-                                                      u32 next, u32 beta, u32 L, u32 log_n, u32 g_inv,
-                                                      u64* U, u64 u_stride, const ModQ* mq, LimbRuns runs)
+__global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_stride, const u64* D,
+                                                      u64 d_stride, u32 n_ct, const u64* key, u32 nmod,
+                                                      u32 level, u32 next, u32 beta, u32 alpha, u32 L,
+                                                      u32 log_n, u32 g_inv, u64* U, u64 u_stride,
+                                                      const ModQ* mq, LimbRuns runs)
 {
     const u32 n = 1u << log_n;
     const u32 s = blockIdx.x * kThreads + threadIdx.x;
@@ -328,11 +329,14 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
     const u32 per = (n_ct + gridDim.z - 1) / gridDim.z;
     const u32 c_lo = blockIdx.z * per, c_hi = min(n_ct, c_lo + per);
     if (c_lo >= c_hi) return;
+    // the digit owning limb e (a Q limb) takes it from the ModUp input
+    const u32 own = e <= level ? e / alpha : 0xffffffffu;
     auto load = [&](u32 c, u64 (&xv)[MAXB]) {
         const u64* xc = X + (size_t)c * x_stride + (size_t)e * n + s;
+        const u64* dc = D + (size_t)c * d_stride + (size_t)(e <= level ? e : 0) * n + s;
 #pragma unroll
         for (int j = 0; j < MAXB; j++)
-            if (j < (int)beta) xv[j] = xc[(size_t)j * next * n];
+            if (j < (int)beta) xv[j] = own == (u32)j ? dc[0] : xc[(size_t)j * next * n];
     };
     if constexpr (FP) {
         const double qd = (double)m.q, qinv = 1.0 / qd;
@@ -392,19 +396,6 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
             u[(size_t)next * n] = reduce128(h1, l1, m);
         }
     }
-}
-
-// X_c row (i / alpha) next + i <- limb i of d_c (i = blockIdx.y, c = blockIdx.z),
-// as 16-byte pairs
-__global__ __launch_bounds__(kThreads) void k_own_limbs(u64* X, u64 xs, const u64* d, u64 d_stride,
-                                                       u32 next, u32 alpha, u32 n)
-{
-    const u32 k = blockIdx.x * kThreads + threadIdx.x;
-    if (k >= n / 2) return;
-    const u32 i = blockIdx.y, c = blockIdx.z;
-    const ulonglong2* src = (const ulonglong2*)(d + (size_t)c * d_stride + (size_t)i * n);
-    ulonglong2* dst = (ulonglong2*)(X + (size_t)c * xs + ((size_t)(i / alpha) * next + i) * n);
-    dst[k] = src[k];
 }
 
 // out_k = (U_k - Y_k) * P^-1 (+ add_k), k = 0, 1; limb i < nq
@@ -725,13 +716,7 @@ void keyswitch_modup_batch(vr_context* ctx, const u64* d, u64 d_stride, u32 n_ct
         }
     }
     // each digit's own limbs are d itself (already in the evaluation domain):
-    // one launch places limb i of every d_c at row (i / alpha) next + i of X_c
-    {
-        dim3 grid((n / 2 + kThreads - 1) / kThreads, k.nq, n_ct);
-        hipLaunchKernelGGL(k_own_limbs, grid, dim3(kThreads), 0, s, X, xs, d, d_stride, k.next,
-                           ctx->alpha, n);
-        VR_CHECK_LAUNCH();
-    }
+    // the inner product reads them there, so they are not copied into X
     // every converted limb of every digit to the evaluation domain: per digit
     // all limbs except the digit's own (digit_skip), the uniform count being
     // next - alpha; a short last digit leaves alpha - last more limbs.
@@ -762,8 +747,9 @@ void keyswitch_modup(vr_context* ctx, const u64* d, u32 level, u64* X, u64* coef
     keyswitch_modup_batch(ctx, d, (u64)(level + 1) * ctx->n, 1, level, X, coef, s);
 }
 
-void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, u32 n_ct, const u64* key,
-                           u32 level, u32 g, u64* U, u64 u_stride, hipStream_t s)
+void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u64* d, u64 d_stride,
+                           u32 n_ct, const u64* key, u32 level, u32 g, u64* U, u64 u_stride,
+                           hipStream_t s)
 {
     KsShape k = ks_shape(ctx, level);
     // at least ~4096 blocks: split the ciphertexts (each group re-reads the key)
@@ -807,8 +793,9 @@ void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, u32 n_ct
             }
             dim3 g2(grid.x, rows, grid.z);
 #define VR_KS_INNER(B, F)                                                                             \
-    hipLaunchKernelGGL((k_ks_inner<B, F>), g2, dim3(kThreads), 0, s, X, x_stride, n_ct, key, ctx->nmod(), \
-                       level, k.next, k.beta, ctx->L, ctx->log_n, g_inv, U, u_stride, ctx->d_modq, lr)
+    hipLaunchKernelGGL((k_ks_inner<B, F>), g2, dim3(kThreads), 0, s, X, x_stride, d, d_stride, n_ct, key, \
+                       ctx->nmod(), level, k.next, k.beta, ctx->alpha, ctx->L, ctx->log_n, g_inv, U,   \
+                       u_stride, ctx->d_modq, lr)
             if (k.beta <= 4) {
                 if (fp)
                     VR_KS_INNER(4, true);
@@ -832,12 +819,12 @@ void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, u32 n_ct
 }
 
 
-void keyswitch_inner(vr_context* ctx, const u64* X, const u64* key, u32 level, u32 g, u64* U,
-                     hipStream_t s)
+void keyswitch_inner(vr_context* ctx, const u64* X, const u64* d, const u64* key, u32 level, u32 g,
+                     u64* U, hipStream_t s)
 {
     KsShape k = ks_shape(ctx, level);
-    keyswitch_inner_batch(ctx, X, (u64)k.beta * k.next * ctx->n, 1, key, level, g, U,
-                          (u64)2 * k.next * ctx->n, s);
+    keyswitch_inner_batch(ctx, X, (u64)k.beta * k.next * ctx->n, d, (u64)k.nq * ctx->n, 1, key, level, g,
+                          U, (u64)2 * k.next * ctx->n, s);
 }
 
 void keyswitch_moddown_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u32 level,

@@ -421,7 +421,8 @@ void rotate_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in,
             if (gs[si] == 1) {
                 VR_HIP(hipMemcpyAsync(dst, src, (size_t)nc * in.stride * sizeof(u64), hipMemcpyDeviceToDevice, s));
             } else {
-                keyswitch_inner_batch(ctx, X, xs, nc, rot_key(ek, gs[si]).data, level, gs[si], U, us, s);
+                keyswitch_inner_batch(ctx, X, xs, src + (size_t)k.nq * n, in.stride, nc,
+                                      rot_key(ek, gs[si]).data, level, gs[si], U, us, s);
                 keyswitch_moddown_batch(ctx, U, us, nc, level, dst, dst + (size_t)k.nq * n, all.stride, src,
                                         gs[si], nullptr, in.stride, md, s);
             }
@@ -446,7 +447,8 @@ Slab relin_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& T, hipStrea
         const u32 nc = std::min(cs, n_ct - c0);
         const u64* t = T.ct(c0);
         keyswitch_modup_batch(ctx, t + (size_t)2 * k.nq * n, T.stride, nc, level, X, X + (size_t)cs * xs, s);
-        keyswitch_inner_batch(ctx, X, xs, nc, ek->rlk.data, level, 1, U, us, s);
+        keyswitch_inner_batch(ctx, X, xs, t + (size_t)2 * k.nq * n, T.stride, nc, ek->rlk.data, level, 1,
+                              U, us, s);
         u64* o = out.ct(c0);
         keyswitch_moddown_batch(ctx, U, us, nc, level, o, o + (size_t)k.nq * n, out.stride, t, 1,
                                 t + (size_t)k.nq * n, T.stride, U + (size_t)cs * us, s);
@@ -763,7 +765,8 @@ std::vector<Slab> matmul_multi(vr_context* ctx, const vr_eval_keys* ek, const st
             for (u32 r : order)
                 if (Pp[r] > idx) n_act = b_off[r] + reqs[r].n;
             const u32 g = galois_element(ctx, (int32_t)idx);
-            keyswitch_inner_batch(ctx, X, xs, n_act, rot_key(ek, g).data, level, g, U, us, s);
+            keyswitch_inner_batch(ctx, X, xs, SB.base + (size_t)k.nq * N, SB.stride, n_act,
+                                  rot_key(ek, g).data, level, g, U, us, s);
             keyswitch_moddown_batch(ctx, U, us, n_act, level, R.base, R.base + (size_t)k.nq * N, R.stride,
                                     SB.base, g, nullptr, SB.stride, U + (size_t)n_act * us, s);
             for (u32 r : order) {

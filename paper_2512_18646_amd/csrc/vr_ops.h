@@ -54,18 +54,23 @@ struct KsShape {
 KsShape ks_shape(vr_context* ctx, u32 level);
 
 // ModUp of d (evaluation domain, nq limbs): X = [beta][next][N] extended digits
-// in the evaluation domain.  Uses `coef` ([nq][N]) as scratch.
+// in the evaluation domain, except each digit's own limbs (rows j next + i,
+// i in digit j), which are d itself and are not written: the inner product
+// reads them from d.  Uses `coef` ([nq][N]) as scratch.
 void keyswitch_modup(vr_context* ctx, const u64* d, u32 level, u64* X, u64* coef, hipStream_t s);
 // Batched ModUp: d_c = d + c*d_stride (c < n_ct), X_c = X + c*beta*next*N,
 // coef: [n_ct][nq][N] scratch.
 void keyswitch_modup_batch(vr_context* ctx, const u64* d, u64 d_stride, u32 n_ct, u32 level,
                            u64* X, u64* coef, hipStream_t s);
-// U = [2][next][N]: sum_j sigma_g(X_j) * (b_j, a_j) (g = 1: no automorphism).
-void keyswitch_inner(vr_context* ctx, const u64* X, const u64* key, u32 level, u32 g, u64* U,
-                     hipStream_t s);
-// Batched inner product: n_ct digit sets X + c*x_stride share one key read.
-void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, u32 n_ct, const u64* key,
-                           u32 level, u32 g, u64* U, u64 u_stride, hipStream_t s);
+// U = [2][next][N]: sum_j sigma_g(X_j) * (b_j, a_j) (g = 1: no automorphism);
+// d is the ModUp input (the digits' own limbs).
+void keyswitch_inner(vr_context* ctx, const u64* X, const u64* d, const u64* key, u32 level, u32 g,
+                     u64* U, hipStream_t s);
+// Batched inner product: n_ct digit sets X + c*x_stride (ModUp inputs
+// d + c*d_stride) share one key read.
+void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u64* d, u64 d_stride,
+                           u32 n_ct, const u64* key, u32 level, u32 g, u64* U, u64 u_stride,
+                           hipStream_t s);
 // ModDown of U ([2][next][N]) to out0/out1 (nq limbs each, may be strided),
 // adding add0 (optionally through sigma_g) and add1 when non-null.
 void keyswitch_moddown(vr_context* ctx, u64* U, u32 level, u64* out0, u64* out1, const u64* add0,
