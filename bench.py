@@ -67,6 +67,12 @@ def ntt_roofline(cls, prof_ms, launches, units, total_s, log_n=14):
             "share_of_step": round(prof_ms / (total_s * 1e3), 3)}
 
 
+def log_free(tag):
+    import torch
+    free, total = torch.cuda.mem_get_info()
+    log("%s: %.1f of %.1f GiB free" % (tag, free / 2 ** 30, total / 2 ** 30))
+
+
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
@@ -820,6 +826,8 @@ def main():
         out["breakdown_per_step"] = bd
 
     if not args.no_extra:
+        ctx.trim()
+        log_free("after the main step")
         log("per-op path (one set)")
         perop.square(ctx, keys, perop.conv2d(ctx, keys, cols[0], W.channels, W.h, W.w, W.pad, K, bias, W.stride))
         sync()
@@ -834,29 +842,38 @@ def main():
         out["batched_over_per_op"] = round((W.batch * args.sets / (total / args.steps)) / (W.batch / t_per_op), 2)
         del ys, ref
         log("rotations at N=2^16")
+        log_free("before this leg")
         out["rotations_per_s_n16"] = {"level24": rotations_bench(vr, 24, 8, 3),
                                       "level3": rotations_bench(vr, 3, 32, 3)}
         for v in out["rotations_per_s_n16"].values():
             v["batched"], v["per_op"] = round(v["batched"], 1), round(v["per_op"], 1)
 
-    if not args.no_extra and not args.no_cnn:
-        for lv, sets in ((3, args.cnn_sets), (24, 1)):
-            log("cnn128 at level %d" % lv)
-            out.setdefault("cnn128_n16", []).append(cnn128_bench(vr, lv, sets, 2, graph=(lv == 3)))
-
-    if not args.no_extra and not args.no_uneven:
-        log("uneven batch at N=2^16")
-        out["uneven_batch_n16"] = uneven_bench(vr, 64, 3, 2)
-        log("uneven batch at full size ranges (outer-product products)")
-        out["uneven_full_n16"] = uneven_full_bench(vr, 64, 3, 2)
-
     if not args.no_extra and not args.no_serve:
         log("serving (Poisson arrivals, image-size mix)")
         out["serving"] = [serving_bench(vr, ctx, keys, args.serve_requests, float(x), args.level)
                           for x in args.serve_load.split(",")]
+        # the N=2^14 context's allocator caches what its legs held (up to the
+        # serving budget): hand it back before the N=2^16 legs allocate
+        ctx.trim()
+        log_free("N=2^14 context trimmed")
         log("serving at N=2^16")
         out["serving_n16"] = serving_n16_bench(vr)
         log("serving done")
+
+    if not args.no_extra and not args.no_cnn:
+        for lv, sets in ((3, args.cnn_sets), (24, 1)):
+            log("cnn128 at level %d" % lv)
+            log_free("before this leg")
+            out.setdefault("cnn128_n16", []).append(cnn128_bench(vr, lv, sets, 2, graph=(lv == 3)))
+
+    if not args.no_extra and not args.no_uneven:
+        log("uneven batch at N=2^16")
+        log_free("before this leg")
+        out["uneven_batch_n16"] = uneven_bench(vr, 64, 3, 2)
+        log("uneven batch at full size ranges (outer-product products)")
+        log_free("before this leg")
+        out["uneven_full_n16"] = uneven_full_bench(vr, 64, 3, 2)
+
 
     if not args.no_extra and not args.no_cpu_baseline:
         log("cpu baseline (oracle sample)")
