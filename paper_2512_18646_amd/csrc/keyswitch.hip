@@ -172,19 +172,36 @@ __global__ __launch_bounds__(kThreads) void k_base_convert_fp(ConvArgs a, ConvFp
             }
         }
     }
+    // target o + 1's constants are loaded while target o is summed
+    double wc[NI], wh = 0.0, tc[2];
+#pragma unroll
+    for (int i = 0; i < NI; i++) wc[i] = f.w[2 * i];
+    if (W0) wh = f.w[1];
+    tc[0] = f.t[0];
+    tc[1] = f.t[1];
     for (u32 o = 0; o < a.n_out; o++) {
-        const double td = f.t[2 * o], tinv = f.t[2 * o + 1];
+        const double td = tc[0], tinv = tc[1];
+        double w[NI], w1 = wh;
+#pragma unroll
+        for (int i = 0; i < NI; i++) w[i] = wc[i];
+        if (o + 1 < a.n_out) {
+            const double* wn = f.w + (size_t)(o + 1) * kMaxIn * 2;
+#pragma unroll
+            for (int i = 0; i < NI; i++) wc[i] = wn[2 * i];
+            if (W0) wh = wn[1];
+            tc[0] = f.t[2 * (o + 1)];
+            tc[1] = f.t[2 * (o + 1) + 1];
+        }
         u64 r;
         if (td < kTwo51) {
-            const double* w = f.w + (size_t)o * kMaxIn * 2;
             double acc = 0.0;
             int since = 0;   // products since the last reduction (compile time)
 #pragma unroll
             for (int i = 0; i < NI; i++) {
-                acc += fmulmod(yl[i], w[2 * i], td, tinv);
+                acc += fmulmod(yl[i], w[i], td, tinv);
                 since++;
                 if (W0 && i == 0) {
-                    acc += fmulmod(yh0, w[1], td, tinv);
+                    acc += fmulmod(yh0, w1, td, tinv);
                     since++;
                 }
                 if (since >= 4 && i + 1 < NI) {
