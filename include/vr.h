@@ -389,6 +389,13 @@ vr_status vr_batch_add_cnn(vr_batch *b, const vr_cnn_desc *desc, const vr_cipher
 vr_status vr_batch_add_matmul(vr_batch *b, const vr_ciphertext *const *A,
                               const vr_ciphertext *const *Bbar, uint32_t m, uint32_t n, uint32_t p,
                               uint32_t *req_id);
+/* An outer-product product (operands as for vr_matmul_outer: T n and n
+ * handles).  Outer-product requests at one level and scale share one
+ * relinearisation and rescale of all their tiles; limbs identical to each
+ * request's own vr_matmul_outer call. */
+vr_status vr_batch_add_matmul_outer(vr_batch *b, const vr_ciphertext *const *A,
+                                    const vr_ciphertext *const *B, uint32_t m, uint32_t n, uint32_t p,
+                                    uint32_t *req_id);
 /* Evaluates every request eagerly on `stream` (no graph). */
 vr_status vr_batch_run(vr_batch *b, void *stream);
 /* Runs the batch once eagerly (building and tuning every cached constant),

@@ -67,7 +67,13 @@ BufPtr dev_alloc(vr_context* ctx, size_t bytes, hipStream_t s)
         b->free_user = ctx->alloc_user;
     } else {
         b->ptr = ctx->arena->alloc(bytes, s);
-        if (!b->ptr) throw Error(VR_ENOMEM, "device allocation failed");
+        if (!b->ptr) {
+            size_t reserved = 0, in_use = 0;
+            ctx->arena->usage(&reserved, &in_use);
+            throw Error(VR_ENOMEM, "device allocation of " + std::to_string(bytes >> 20) + " MiB failed (" +
+                                       std::to_string(in_use >> 20) + " MiB in use, " +
+                                       std::to_string(reserved >> 20) + " MiB reserved)");
+        }
         b->arena = ctx->arena;
     }
     return b;

@@ -92,19 +92,21 @@ bool same_net(const CnnDesc& a, const CnnDesc& b)
            a.fc_block == b.fc_block && a.fc_bias == b.fc_bias;
 }
 
-// One request of a batch: a network over its own image sets, or a product.
+// One request of a batch: a network over its own image sets, or a product
+// (column-split, or outer-product when `outer`).
 struct BatchReq {
     bool cnn = true;
+    bool outer = false;
     CnnDesc desc;
     u32 n_sets = 1;
     u32 m = 0, n = 0, p = 0;
-    Slab a, b;        // inputs, owned by the batch (b: the Bbar columns)
+    Slab a, b;        // inputs, owned by the batch (b: the Bbar columns, or B')
     Slab out;
 };
 
 // Runs every request: networks with the same description and input level
-// and scale as one multi-set evaluation, products at one level and scale as
-// one merged schedule.
+// and scale as one multi-set evaluation, products of one form at one level
+// and scale as one merged schedule.
 void run_batch(vr_context* ctx, const vr_eval_keys* ek, std::vector<BatchReq>& reqs, hipStream_t s)
 {
     std::vector<bool> done(reqs.size(), false);
@@ -142,14 +144,14 @@ void run_batch(vr_context* ctx, const vr_eval_keys* ek, std::vector<BatchReq>& r
         std::vector<size_t> grp;
         std::vector<MatReq> mr;
         for (size_t j = i; j < reqs.size(); j++)
-            if (!done[j] && !reqs[j].cnn && reqs[j].a.level == reqs[i].a.level &&
+            if (!done[j] && !reqs[j].cnn && reqs[j].outer == reqs[i].outer && reqs[j].a.level == reqs[i].a.level &&
                 reqs[j].a.scale * reqs[j].b.scale == reqs[i].a.scale * reqs[i].b.scale) {
                 grp.push_back(j), done[j] = true;
                 MatReq q;
                 q.A = reqs[j].a, q.B = reqs[j].b, q.m = reqs[j].m, q.n = reqs[j].n, q.p = reqs[j].p;
                 mr.push_back(q);
             }
-        std::vector<Slab> outs = matmul_multi(ctx, ek, mr, s);
+        std::vector<Slab> outs = reqs[i].outer ? matmul_outer_multi(ctx, ek, mr, s) : matmul_multi(ctx, ek, mr, s);
         for (size_t g = 0; g < grp.size(); g++) reqs[grp[g]].out = outs[g];
     }
 }
@@ -386,6 +388,30 @@ vr_status vr_batch_add_matmul(vr_batch* b, const vr_ciphertext* const* A, const 
     copy_inputs(b->ctx, r.a, A, n, s);
     r.b = new_slab(b->ctx, n, 2, Bbar[0]->level, Bbar[0]->scale, s);
     copy_inputs(b->ctx, r.b, Bbar, n, s);
+    b->reqs.push_back(std::move(r));
+    *req_id = (uint32_t)b->reqs.size() - 1;
+    API_END
+}
+
+vr_status vr_batch_add_matmul_outer(vr_batch* b, const vr_ciphertext* const* A, const vr_ciphertext* const* B,
+                                    uint32_t m, uint32_t n, uint32_t p, uint32_t* req_id)
+{
+    if (req_id) *req_id = 0;
+    API_BEGIN
+    REQUIRE(b && A && B && req_id, "null argument");
+    REQUIRE(!b->exec, "batch already captured");
+    REQUIRE(m >= 1 && n >= 1 && p >= 1 && A[0] && B[0], "empty matrix");
+    u32 Pp, R, T;
+    outer_tiles(b->ctx, m, p, &Pp, &R, &T);
+    hipStream_t s = b->ctx->stream;
+    BatchReq r;
+    r.cnn = false;
+    r.outer = true;
+    r.m = m, r.n = n, r.p = p;
+    r.a = new_slab(b->ctx, T * n, 2, A[0]->level, A[0]->scale, s);
+    copy_inputs(b->ctx, r.a, A, (size_t)T * n, s);
+    r.b = new_slab(b->ctx, n, 2, B[0]->level, B[0]->scale, s);
+    copy_inputs(b->ctx, r.b, B, n, s);
     b->reqs.push_back(std::move(r));
     *req_id = (uint32_t)b->reqs.size() - 1;
     API_END

@@ -788,24 +788,48 @@ std::vector<Slab> matmul_multi(vr_context* ctx, const vr_eval_keys* ek, const st
     return res;
 }
 
-// Outer-product product (the rotation-free form of the split product): row
-// tile t accumulates sum_k Tensor(A'_{t,k}, B'_k) (A' tile-major, t n + k),
-// then every tile is relinearised and rescaled together.  No rotation.
-Slab matmul_outer(vr_context* ctx, const vr_eval_keys* ek, const Slab& A, const Slab& B, u32 n, u32 T,
-                  hipStream_t s)
+// Outer-product products (the rotation-free form of the split product) of
+// several requests at one level and scale: row tile t of request r
+// accumulates sum_k Tensor(A'_{t,k}, B'_k) (A' tile-major, t n + k), then
+// every tile of every request is relinearised and rescaled together.  No
+// rotation.
+std::vector<Slab> matmul_outer_multi(vr_context* ctx, const vr_eval_keys* ek, const std::vector<MatReq>& reqs,
+                                     hipStream_t s)
 {
-    if (A.level != B.level) throw Error(VR_ELEVEL, "matmul inputs at different levels");
-    if (A.ncomp != 2 || B.ncomp != 2) throw Error(VR_EINVAL, "matmul inputs must be 2-component");
-    if (A.n != T * n || B.n != n) throw Error(VR_EINVAL, "outer product needs T n and n ciphertexts");
-    const u32 nl = A.level + 1;
-    Slab acc = new_slab(ctx, T, 3, A.level, A.scale * B.scale, s);
-    dim3 grid((ctx->n + kThreads - 1) / kThreads, nl);
-    for (u32 t = 0; t < T; t++) {
-        hipLaunchKernelGGL(k_tensor_acc, grid, dim3(kThreads), 0, s, acc.ct(t), A.ct(t * n), A.stride, B.base,
-                           B.stride, n, nl, ctx->log_n, ctx->d_modq);
-        VR_CHECK_LAUNCH();
+    const u32 nr = (u32)reqs.size();
+    if (nr == 0) return {};
+    const u32 level = reqs[0].A.level, nl = level + 1;
+    const double scale_ab = reqs[0].A.scale * reqs[0].B.scale;
+    std::vector<u32> T(nr), off(nr);
+    u32 tiles = 0;
+    for (u32 r = 0; r < nr; r++) {
+        const MatReq& q = reqs[r];
+        if (q.A.level != level || q.B.level != level) throw Error(VR_ELEVEL, "matmul inputs at different levels");
+        if (q.A.scale * q.B.scale != scale_ab) throw Error(VR_ESCALE, "matmul inputs at different scales");
+        if (q.A.ncomp != 2 || q.B.ncomp != 2) throw Error(VR_EINVAL, "matmul inputs must be 2-component");
+        u32 Pp, R;
+        outer_tiles(ctx, q.m, q.p, &Pp, &R, &T[r]);
+        if (q.A.n != T[r] * q.n || q.B.n != q.n) throw Error(VR_EINVAL, "outer product needs T n and n ciphertexts");
+        off[r] = tiles;
+        tiles += T[r];
     }
-    return rescale_slab(ctx, relin_slab(ctx, ek, acc, s), s);
+    Slab acc = new_slab(ctx, tiles, 3, level, scale_ab, s);
+    dim3 grid((ctx->n + kThreads - 1) / kThreads, nl);
+    for (u32 r = 0; r < nr; r++)
+        for (u32 t = 0; t < T[r]; t++) {
+            hipLaunchKernelGGL(k_tensor_acc, grid, dim3(kThreads), 0, s, acc.ct(off[r] + t), reqs[r].A.ct(t * reqs[r].n),
+                               reqs[r].A.stride, reqs[r].B.base, reqs[r].B.stride, reqs[r].n, nl, ctx->log_n,
+                               ctx->d_modq);
+            VR_CHECK_LAUNCH();
+        }
+    Slab out = rescale_slab(ctx, relin_slab(ctx, ek, acc, s), s);
+    std::vector<Slab> res(nr);
+    for (u32 r = 0; r < nr; r++) {
+        res[r] = out;
+        res[r].n = T[r];
+        res[r].base = out.ct(off[r]);
+    }
+    return res;
 }
 
 // (P', R, T) of the outer-product form: column padding, rows per ciphertext,
@@ -983,10 +1007,12 @@ vr_status vr_matmul_outer(vr_context* ctx, const vr_eval_keys* ek, const vr_ciph
     u32 Pp, R, Tt;
     outer_tiles(ctx, m, p, &Pp, &R, &Tt);
     hipStream_t s = pick_stream(ctx, stream);
-    Slab a = gather(ctx, A, Tt * n, s);
-    Slab b = gather(ctx, B, n, s);
-    Slab out = matmul_outer(ctx, ek, a, b, n, Tt, s);
-    to_handles(ctx, out, C);
+    MatReq rq;
+    rq.A = gather(ctx, A, Tt * n, s);
+    rq.B = gather(ctx, B, n, s);
+    rq.m = m, rq.n = n, rq.p = p;
+    std::vector<Slab> out = matmul_outer_multi(ctx, ek, {rq}, s);
+    to_handles(ctx, out[0], C);
     API_END
 }
 

@@ -59,6 +59,13 @@ struct MatReq {
 // ModUp and each rotation step's key; result r holds P'_r ciphertexts.
 std::vector<Slab> matmul_multi(vr_context* ctx, const vr_eval_keys* ek, const std::vector<MatReq>& reqs,
                                hipStream_t s);
+// Outer-product products (A: T n ciphertexts, tile-major; B: n) at one level
+// and scale: every request's tiles relinearised and rescaled together;
+// result r holds T_r ciphertexts.
+std::vector<Slab> matmul_outer_multi(vr_context* ctx, const vr_eval_keys* ek, const std::vector<MatReq>& reqs,
+                                     hipStream_t s);
+// (P', R, T) of the outer-product form: column padding, rows per ciphertext, tiles
+void outer_tiles(vr_context* ctx, u32 m, u32 p, u32* Pp, u32* R, u32* T);
 const u64* fc_weights(vr_context* ctx, const vr_plaintext* const* W_pt, size_t count, u32 nl,
                       u64* p_stride, double* p_scale, BufPtr& holder, hipStream_t s);
 

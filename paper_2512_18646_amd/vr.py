@@ -113,6 +113,7 @@ _SIGS = {
     "vr_batch_create": [P, P, PP],
     "vr_batch_add_cnn": [P, P, PP, U32, ctypes.POINTER(U32)],
     "vr_batch_add_matmul": [P, PP, PP, U32, U32, U32, ctypes.POINTER(U32)],
+    "vr_batch_add_matmul_outer": [P, PP, PP, U32, U32, U32, ctypes.POINTER(U32)],
     "vr_batch_run": [P, P],
     "vr_batch_capture": [P],
     "vr_batch_launch": [P, P],
@@ -684,6 +685,13 @@ class Batch:
         while pp < p:
             pp <<= 1
         self._cap.append(pp)
+        return rid.value
+
+    def add_matmul_outer(self, A, B, m, n, p):
+        rid = U32()
+        _check(lib.vr_batch_add_matmul_outer(self.h, _ptr_array(A), _ptr_array(B), m, n, p,
+                                             ctypes.byref(rid)))
+        self._cap.append(self.ctx.outer_tiles(m, p)[2])
         return rid.value
 
     def run(self, stream=None):

@@ -71,3 +71,54 @@ def test_uneven_batch_eager_and_graph(ctx):
             same(b.outputs(i), r, "replay %d request %d" % (rep, i))
         net2.forward(g, gk, nets[2][1])[0].export()     # eager work between replays
     b.close()
+
+
+def test_uneven_batch_outer_products(ctx):
+    """Outer-product products in a batch (ragged row tiles, two shapes at one
+    level) beside a column-split product and a network: every request's
+    limbs identical to its own call, eagerly and on three graph replays with
+    eager work between them; the first outer product against the oracle."""
+    from paper_2512_18646_amd import vr
+    o, ok, g, gk = ctx
+    rng = np.random.default_rng(72)
+    reqs = []
+    for i, (m, n, p) in enumerate([(40, 5, 12), (9, 7, 100), (3, 2, 3)]):
+        A, B = rng.uniform(-1, 1, (m, n)), rng.uniform(-1, 1, (n, p))
+        if i == 0:
+            Ac = [to_gpu(g, c) for c in Ly.encrypt_matrix_outer(o, ok, A, 2, m, p, 3, 91, 0)]
+            Bc = [to_gpu(g, c) for c in Ly.encrypt_matrix_outer(o, ok, B, 3, m, p, 3, 91, 1000)]
+        else:
+            Ac = g.encrypt_matrix_columns(gk, A, 2, m, p, 3, 92 + i, 0)
+            Bc = g.encrypt_matrix_columns(gk, B, 3, m, p, 3, 92 + i, 1000)
+        reqs.append((A, B, Ac, Bc, m, n, p))
+    A2, B2 = rng.uniform(-1, 1, (8, 4)), rng.uniform(-1, 1, (4, 8))
+    Ac2 = g.encrypt_matrix_columns(gk, A2, 0, 8, 8, 3, 97, 0)
+    Bc2 = g.encrypt_matrix_columns(gk, B2, 1, 8, 8, 3, 97, 100)
+    K, bias = rng.normal(0, 0.1, (2, 1, 3, 3)), rng.normal(0, 0.1, 2)
+    net = vr.CNN(1, 8, 8, 1, K, bias, 2, square=True)
+    cols = g.encrypt_columns(gk, rng.uniform(0, 1, (8, 1, 8, 8)), 1, 3, 98, 0)
+    b = vr.Batch(g, gk)
+    ids, refs = [], []
+    for A, B, Ac, Bc, m, n, p in reqs:
+        ids.append(b.add_matmul_outer(Ac, Bc, m, n, p))
+        refs.append(g.matmul_outer(gk, Ac, Bc, m, n, p))
+    ids.append(b.add_matmul(Ac2, Bc2, 8, 4, 8))
+    refs.append(g.matmul(gk, Ac2, Bc2, 8, 4, 8))
+    ids.append(b.add_cnn(net, cols))
+    refs.append(net.forward(g, gk, cols))
+    b.run()
+    for i, r in zip(ids, refs):
+        same(b.outputs(i), r, "eager request %d" % i)
+    A, B, _, _, m, n, p = reqs[0]
+    D = Ly.matmul_outer(o, ok, Ly.encrypt_matrix_outer(o, ok, A, 2, m, p, 3, 91, 0),
+                        Ly.encrypt_matrix_outer(o, ok, B, 3, m, p, 3, 91, 1000), m, n, p)
+    assert len(D) == len(b.outputs(ids[0])) == 2
+    for j, (x, y) in enumerate(zip(b.outputs(ids[0]), D)):
+        assert_same(x, y, "batched outer product tile %d" % j)
+    b.capture()
+    for rep in range(3):
+        b.launch()
+        for i, r in zip(ids, refs):
+            same(b.outputs(i), r, "replay %d request %d" % (rep, i))
+        net.forward(g, gk, cols)[0].export()     # eager work between replays
+    b.close()
