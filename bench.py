@@ -304,8 +304,10 @@ def uneven_full_bench(vr, n_req, level, reps, seed=4):
     entering at `level`): products with m, n, p uniform in 16..512 through the
     outer-product form (vr_matmul_outer: row tiles, no rotation) and 3x3/2
     convolutions (8 filters, x^2) on 32x32 .. 256x256 images (full ciphertext
-    sets), one call per request.  Reports the rotations the column-split form
-    would have needed (n (P' - 1) per product, transposed when p > m)."""
+    sets): one call per request, one eager uneven batch (vr_batch_*) and the
+    batch captured as one HIP graph, with limb identity of sampled requests.
+    Reports the rotations the column-split form would have needed
+    (n (P' - 1) per product, transposed when p > m)."""
     import synthetic_inputs as SI
     reqs = SI.uneven_requests(seed, n_req, dim_range=(16, 512), sides=(32, 64, 128, 256), p_le_m=False)
     ctx = vr.Context(16, [60] + [50] * 24, [51] * 9, 3, 50.0)
@@ -360,6 +362,13 @@ def uneven_full_bench(vr, n_req, level, reps, seed=4):
             rows = min(R, m - t * R)
             C[t * R:t * R + rows] = z[:rows * Pp].reshape(rows, Pp)[:, :p]
         err = max(err, float(np.max(np.abs(C - A @ B)) / np.max(np.abs(A @ B))))
+    # the batch holds its own copy of every input and evaluates equal
+    # networks as one multi-set call (three 256x256 sets take ~90 GiB of
+    # intermediates): the whole mix does not fit in the device's memory in
+    # that form, so the batch and graph forms take the first quarter
+    nb = n_req // 4
+    check = [0, 1, 2, 3, nb - 2, nb - 1]   # requests whose limbs the batch must reproduce
+    ref = {i: [c.export() for c in outs[i][:2]] for i in check}
     del outs
     t = time.perf_counter()
     for _ in range(reps):
@@ -368,14 +377,63 @@ def uneven_full_bench(vr, n_req, level, reps, seed=4):
     sync()
     t_run = (time.perf_counter() - t) / reps
     n_mm = sum(1 for it in items if it[0] == "matmul")
+    items = items[:nb]
+    t = time.perf_counter()
+    for _ in range(reps):
+        o = run()
+        del o
+    sync()
+    t_half = (time.perf_counter() - t) / reps
+    half_images = sum(it[3] for it in items if it[0] == "conv")
+    # the first quarter as one uneven batch (inputs copied into it, each caller's
+    # ciphertexts released once added), eager and captured as one graph
+    batch = vr.Batch(ctx, keys)
+    ids = []
+    for i, it in enumerate(items):
+        ids.append(batch.add_matmul_outer(it[1], it[2], *it[3]) if it[0] == "matmul"
+                   else batch.add_cnn(nets[it[2]], it[1]))
+        items[i] = None
+    items = None
+    sync()
+
+    def identical():
+        return all(np.array_equal(batch.outputs(ids[i])[k].export(), ref[i][k])
+                   for i in check for k in range(len(ref[i])))
+
+    batch.run()
+    sync()
+    same_eager = identical()
+    t = time.perf_counter()
+    for _ in range(reps):
+        batch.run()
+    sync()
+    t_batch = (time.perf_counter() - t) / reps
+    batch.capture()
+    batch.launch()
+    sync()
+    t = time.perf_counter()
+    for _ in range(reps):
+        batch.launch()
+    sync()
+    t_graph = (time.perf_counter() - t) / reps
+    same_graph = identical()
+    batch.close()
     reserved, _ = ctx.mem_info()
     return {"workload": "%d requests: %d products (m, n, p in 16..512, outer-product form), %d 3x3/2 x8 + x^2 "
                         "convolutions on 32x32 .. 256x256 images (full sets), N=2^16 L=24 chain at level %d"
                         % (n_req, n_mm, n_req - n_mm, level),
-            "requests_per_s": round(n_req / t_run, 2), "ms_per_batch": round(t_run * 1e3, 1),
-            "conv_images_per_s": round(images / t_run, 1), "product_tensors": tensors,
-            "column_split_rotations_avoided": rot_split, "products_max_rel_error": err,
-            "setup_s": round(setup_s, 1), "device_gib_reserved": round(reserved / 2 ** 30, 1)}
+            "requests_per_s": round(n_req / t_run, 2), "ms_for_all": round(t_run * 1e3, 1),
+            "conv_images_per_s": round(images / t_run, 1),
+            "first_quarter": {"requests": nb,
+                           "requests_per_s": {"per_request": round(nb / t_half, 2), "batch": round(nb / t_batch, 2),
+                                              "graph": round(nb / t_graph, 2)},
+                           "conv_images_per_s": {"per_request": round(half_images / t_half, 1),
+                                                 "batch": round(half_images / t_batch, 1),
+                                                 "graph": round(half_images / t_graph, 1)},
+                           "identical_to_per_request": bool(same_eager and same_graph)},
+            "product_tensors": tensors, "column_split_rotations_avoided": rot_split,
+            "products_max_rel_error": err, "setup_s": round(setup_s, 1),
+            "device_gib_reserved": round(reserved / 2 ** 30, 1)}
 
 
 def serving_n16_bench(vr, level=3, n_sessions=8, n_warm=20, n_meas=100, loads=(0.25, 0.5, 0.75, 0.9),
