@@ -119,6 +119,7 @@ def plain_conv_sq_fc(X, K, bias, stride, pad, Wfc, bfc):
 
 
 def cnn128_bench(vr, level_in, sets, reps, graph=False):
+    from paper_2512_18646_amd import perop
     """The 3x128x128 CNN (conv 3x3/2 pad 1 x8, x^2, FC 8*64*64 -> 10) at
     N = 2^16, L = 24 (60 + 24x50, P 9x51, dnum 3), 128 images per set (one
     set = 384 column ciphertexts), sets evaluated one after another."""
@@ -201,8 +202,17 @@ def cnn128_bench(vr, level_in, sets, reps, graph=False):
         same = all(np.array_equal(gout[i].export(), ref[i].export()) for i in range(len(ref)))
         res["graph"] = {"images_per_s": round(W.batch * sets * reps / g_total, 2),
                         "ms_per_replay_p50": round(percentile(glat, 50), 2), "identical": bool(same)}
-        del gout, ref
         gr.close()
+        # one C-ABI call per HE operation on the first set
+        t = time.perf_counter()
+        y = perop.square(ctx, keys, perop.conv2d(ctx, keys, cols[0], W.channels, W.h, W.w, W.pad, K, bias,
+                                                 W.stride))
+        zp = perop.fc(ctx, keys, y, W_pt, bfc, Hp)
+        sync()
+        t_op = time.perf_counter() - t
+        same = all(np.array_equal(zp[i].export(), ref[i].export()) for i in range(len(ref)))
+        res["per_op"] = {"images_per_s": round(W.batch / t_op, 2), "identical": bool(same)}
+        del gout, ref, y, zp
     reserved, _ = ctx.mem_info()
     res["device_gib_reserved"] = round(reserved / 2 ** 30, 1)
     return res

@@ -1,10 +1,10 @@
 """The layer schedules issued as one C-ABI call per HE operation.
 
 This is the plain per-operation path the batched layer calls (vr_conv2d,
-vr_square, vr_matmul) are measured against; it issues exactly the
+vr_square, vr_fc, vr_matmul) are measured against; it issues exactly the
 operations of the schedules (rotations hoisted per input column, MulConst,
-Add, AddConst, Rescale, Tensor, Relinearise) and therefore reaches the same
-limbs.  Every arithmetic step runs in libvr.so.
+MulPlain, Add, AddConst, Rescale, Tensor, Relinearise, Rotate) and therefore
+reaches the same limbs.  Every arithmetic step runs in libvr.so.
 """
 
 
@@ -56,3 +56,23 @@ def matmul(ctx, keys, A, Bbar, m, n, p, stream=None):
             t = ctx.tensor(A[k], rots[idx], stream=stream)
             T[idx] = t if T[idx] is None else ctx.add(T[idx], t, stream=stream)
     return [ctx.rescale(ctx.relinearize(keys, T[idx], stream=stream), stream=stream) for idx in range(Pp)]
+
+
+def fc(ctx, keys, Y, W_pt, bias, block, stream=None):
+    """Z_o = RotSum over the block of Rescale(sum_i MulPlain(Y_i, pt[o][i])), plus
+    bias[o]; W_pt is the flat list from encode_fc_weights ([o][i], i over the
+    C_out * w_out inputs)."""
+    per = len(Y)
+    out = []
+    for o in range(len(bias)):
+        acc = None
+        for i, y in enumerate(Y):
+            t = ctx.mul_plain(y, W_pt[o * per + i], stream=stream)
+            acc = t if acc is None else ctx.add(acc, t, stream=stream)
+        z = ctx.rescale(acc, stream=stream)
+        step = 1
+        while step < block:
+            z = ctx.add(z, ctx.rotate(keys, z, step, stream=stream), stream=stream)
+            step *= 2
+        out.append(ctx.add_const(z, float(bias[o]), stream=stream))
+    return out

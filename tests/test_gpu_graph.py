@@ -86,3 +86,15 @@ def test_graph_replays_match_eager(net):
         g2.launch()
         check(g2.outputs(), ref, "conv + x^2 graph replay %d" % rep)
     g2.close()
+
+
+def test_per_op_network_matches_layer_calls(net):
+    """The network as one C-ABI call per HE operation (conv: hoisted
+    rotations, MulConst, Add, AddConst, Rescale; x^2: Tensor, Relinearise,
+    Rescale; FC: MulPlain, Add, Rescale, rotations, AddConst) gives the limbs
+    of the layer calls."""
+    from paper_2512_18646_amd import perop
+    g, gk, full, conv_sq, sets, params = net
+    K, bias, Wfc, fb, pts, Hp, wo = params
+    y = perop.square(g, gk, perop.conv2d(g, gk, sets[3], CI, H, W_, PAD, K, bias, S_))
+    check(perop.fc(g, gk, y, pts, fb, Hp), layers_ref(g, gk, sets[3], params), "per-op network")
