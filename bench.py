@@ -724,6 +724,27 @@ def convert_compare(ctx, keys, cts, level, reps):
     return res
 
 
+def cpu_rotations_n16(counts=((24, 2), (3, 4))):
+    """The oracle's one-slot rotation at N = 2^16 (60 + 24x50, P 9x51, dnum 3)
+    on one host core: `count` rotations per level, timed after key
+    generation and encryption (which are not timed)."""
+    from oracle import Context as OC, PRESETS
+    o = OC(PRESETS["C3"])
+    ok = o.keygen(1003, rot_steps=[1])
+    z = np.random.default_rng(3).uniform(-1, 1, o.slots)
+    res = {}
+    for lv, count in counts:
+        cts = [o.encrypt(ok, o.encode(z, lv, o.scale), 1003, i) for i in range(count)]
+        t = time.perf_counter()
+        for c in cts:
+            o.rotate(c, 1, ok)
+        dt = time.perf_counter() - t
+        res["level%d" % lv] = {"rotations_per_s": round(count / dt, 4), "sample": "%d rotations" % count,
+                               "seconds": round(dt, 1)}
+    res["cores"] = 1
+    return res
+
+
 def cpu_baseline(level, out_cols=(0, 3, 6, 9, 12)):
     """The oracle on a bounded sample of the same layer: every operation the
     output columns j' in out_cols need (their input columns rotated by 1..3,
@@ -947,6 +968,8 @@ def main():
         log("cpu baseline (oracle sample)")
         out["cpu_baseline"] = cpu_baseline(args.level)
         out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 4)
+        log("cpu baseline: oracle rotations at N=2^16")
+        out["cpu_baseline"]["rotations_n16"] = cpu_rotations_n16()
     print(json.dumps(out), flush=True)
 
 
