@@ -593,9 +593,13 @@ def sync():
     torch.cuda.synchronize()
 
 
-def rotations_bench(vr, level, n_ct, reps):
-    """HE rotations/s at N = 2^16: n_ct ciphertexts rotated by one step."""
+def rotations_bench(vr, level, n_ct, reps, ntt_plan="auto"):
+    """HE rotations/s at N = 2^16: n_ct ciphertexts rotated by one step
+    (ntt_plan: auto, or cand:i to pin the transform plan, e.g. for counter
+    runs)."""
     ctx = vr.Context(16, [60] + [50] * 24, [51] * 9, 3, 50.0)
+    if ntt_plan != "auto":
+        ctx.set_tuning("ntt", ntt_plan)
     keys = ctx.keygen(1003, rot_steps=[1])
     z = np.random.default_rng(3).uniform(-1, 1, ctx.slots)
     cts = [ctx.encrypt(keys, ctx.encode(z, level), 1003, i) for i in range(n_ct)]
@@ -813,6 +817,9 @@ def main():
     ap.add_argument("--ntt-plan", default="auto",
                     help="NTT pass plan of the main workload: auto (autotuned), fixed, or cand:i "
                          "(pins the plan, e.g. for counter runs)")
+    ap.add_argument("--ntt-plan-n16", default="auto",
+                    help="NTT pass plan of the N=2^16 rotation legs: auto or cand:i (cand:11 = the "
+                         "compile-time two-pass kernels with 16-column tiles)")
     ap.add_argument("--rotations-only", action="store_true",
                     help="only the N=2^16 rotation leg (for profiling its kernels)")
     ap.add_argument("--breakdown", action="store_true",
@@ -834,8 +841,8 @@ def main():
         sync()
         del src, dst
     if args.rotations_only:
-        out = {"rotations_per_s_n16": {"level24": rotations_bench(vr, 24, 8, args.steps),
-                                       "level3": rotations_bench(vr, 3, 32, args.steps)}}
+        out = {"rotations_per_s_n16": {"level24": rotations_bench(vr, 24, 8, args.steps, args.ntt_plan_n16),
+                                       "level3": rotations_bench(vr, 3, 32, args.steps, args.ntt_plan_n16)}}
         print(json.dumps(out), flush=True)
         return
     log("setup: encrypting %d sets of 256 images at level %d" % (args.sets, args.level))
