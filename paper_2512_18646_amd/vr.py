@@ -192,7 +192,7 @@ class Ciphertext:
         self.h, self.ctx = h, ctx
 
     def __del__(self):
-        if self.h:
+        if self.h and lib is not None:   # lib is None once the interpreter is tearing down
             lib.vr_free_ciphertext(self.h)
             self.h = None
 
@@ -225,7 +225,7 @@ class Plaintext:
         self.h, self.ctx, self.level, self.scale = h, ctx, level, scale
 
     def __del__(self):
-        if self.h:
+        if self.h and lib is not None:
             lib.vr_free_plaintext(self.h)
             self.h = None
 
@@ -240,7 +240,7 @@ class Keys:
         self.sk, self.ek, self.ctx = sk, ek, ctx
 
     def __del__(self):
-        if self.sk or self.ek:
+        if (self.sk or self.ek) and lib is not None:
             lib.vr_free_keys(self.sk, self.ek)
             self.sk = self.ek = None
 
@@ -293,7 +293,7 @@ class Context:
                    allow_insecure=getattr(p, "allow_insecure", False), device=device)
 
     def __del__(self):
-        if getattr(self, "h", None):
+        if getattr(self, "h", None) and lib is not None:
             lib.vr_context_destroy(self.h)
             self.h = None
 
