@@ -179,6 +179,72 @@ def test_matmul_schedule_identity_and_ragged(ctx10):
     assert Ly.rel_error(C, A) < EPS
 
 
+def test_matmul_column_slot_layout_brute_force():
+    """The column-split encodings on plain slot vectors: with rotation as a
+    left cyclic shift of the slots (pinned by the automorphism test above),
+    D_idx = sum_k A_k * Rot(Bbar_k, idx) holds C[i][(i + idx) mod P'] in slot
+    i (exact on small integers), and zero there when that column is past p;
+    brute force over ragged shapes, every entry of A B reached once."""
+    ctx = small_ctx(log_n=6)   # 32 slots
+    rng = np.random.default_rng(11)
+    for m, n, p in ((4, 3, 3), (12, 5, 5), (8, 2, 8), (16, 3, 1), (32, 2, 32)):
+        A = rng.integers(-9, 10, (m, n)).astype(float)
+        B = rng.integers(-9, 10, (n, p)).astype(float)
+        C = A @ B
+        Pp = Ly.pow2ceil(p)
+        seen = np.zeros((m, p), int)
+        for idx in range(Pp):
+            D = sum(Ly.matrix_column_slots(ctx, A, k, 0, m, p) * np.roll(Ly.matrix_column_slots(ctx, B, k, 1, m, p), -idx)
+                    for k in range(n))
+            for i in range(m):
+                col = (i + idx) % Pp
+                if col < p:
+                    assert D[i] == C[i, col]
+                    seen[i, col] += 1
+                else:
+                    assert D[i] == 0.0
+        assert (seen == 1).all()
+
+
+def test_conv_column_slot_layout_brute_force():
+    """The conv's column encoding on plain slot vectors: Y(c', j') = bias +
+    sum_{c,u,v} K[c'][c][u][v] Rot(col(c, s j' + v - pad), u), with rotation
+    a left cyclic shift, holds output row i' of image b in slot b H' + s i';
+    checked exactly (small integers) against cross-correlation with zero
+    padding written out as loops, for several strides, pads and a full slot
+    vector (the last image block wraps around)."""
+    ctx = small_ctx(log_n=6)   # 32 slots
+    rng = np.random.default_rng(12)
+    for B, C_in, h, w, pad, k, stride, C_out in ((4, 2, 5, 5, 1, 3, 2, 2), (2, 1, 6, 7, 0, 4, 2, 3),
+                                                 (3, 2, 4, 4, 2, 2, 1, 1), (4, 1, 8, 3, 0, 3, 3, 2)):
+        X = rng.integers(-5, 6, (B, C_in, h, w)).astype(float)
+        K = rng.integers(-3, 4, (C_out, C_in, k, k)).astype(float)
+        bias = rng.integers(-4, 5, C_out).astype(float)
+        Hp = Ly.image_block(h, pad)
+        assert B * Hp <= ctx.slots
+        ho, wo = (h + 2 * pad - k) // stride + 1, (w + 2 * pad - k) // stride + 1
+        for co in range(C_out):
+            for jo in range(wo):
+                Y = np.full(ctx.slots, bias[co])
+                for c in range(C_in):
+                    for v in range(k):
+                        jj = stride * jo + v - pad
+                        if 0 <= jj < w:
+                            col = Ly.image_column_slots(ctx, X, c, jj, pad)
+                            for u in range(k):
+                                Y = Y + K[co, c, u, v] * np.roll(col, -u)
+                for b in range(B):
+                    for io in range(ho):
+                        want = bias[co]
+                        for c in range(C_in):
+                            for u in range(k):
+                                for v in range(k):
+                                    i, j = stride * io + u - pad, stride * jo + v - pad
+                                    if 0 <= i < h and 0 <= j < w:
+                                        want += K[co, c, u, v] * X[b, c, i, j]
+                        assert Y[b * Hp + stride * io] == want
+
+
 def test_matmul_outer_slot_layout_brute_force():
     """The outer-product encodings on plain slot vectors: sum_k A'_{t,k} * B'_k
     (element-wise, exact on small integers) is tile t of A B, slot r P' + j
