@@ -245,6 +245,42 @@ def test_conv_column_slot_layout_brute_force():
                         assert Y[b * Hp + stride * io] == want
 
 
+def test_fc_slot_layout_and_block_sum_brute_force():
+    """FC on plain slot vectors: the weight plaintexts (decoded and rounded;
+    small integer weights) times the conv-output layout, with arbitrary junk
+    in every slot that holds no output row, summed over the ciphertexts and
+    then Z += Rot(Z, 2^t) for 2^t < H', hold bias-free FC output o of image b
+    in slot b H', exactly against the dot product written out as loops."""
+    ctx = small_ctx(log_n=6)   # 32 slots
+    rng = np.random.default_rng(13)
+    for B, C, ho, wo, stride, Hp, n_out in ((4, 2, 3, 2, 2, 8, 3), (2, 1, 5, 3, 3, 16, 2), (8, 3, 2, 2, 2, 4, 2)):
+        assert B * Hp <= ctx.slots and stride * (ho - 1) < Hp
+        Yv = rng.integers(-5, 6, (B, C, ho, wo)).astype(float)
+        W = rng.integers(-3, 4, (n_out, C, ho, wo)).astype(float)
+        pts = Ly.fc_plaintexts(ctx, W.reshape(n_out, -1), C, ho, wo, stride, Hp, 3)
+        wslots = [[np.rint(ctx.decode(pt).real) for pt in row] for row in pts]
+        cts = []
+        for c in range(C):
+            for jo in range(wo):
+                z = rng.integers(-50, 51, ctx.slots).astype(float)   # junk outside the output rows
+                for b in range(B):
+                    z[b * Hp + stride * np.arange(ho)] = Yv[b, c, :, jo]
+                cts.append(z)
+        for o in range(n_out):
+            Z = sum(y * wv for y, wv in zip(cts, wslots[o]))
+            step = 1
+            while step < Hp:
+                Z = Z + np.roll(Z, -step)
+                step *= 2
+            for b in range(B):
+                want = 0.0
+                for c in range(C):
+                    for i in range(ho):
+                        for j in range(wo):
+                            want += W[o, c, i, j] * Yv[b, c, i, j]
+                assert Z[b * Hp] == want
+
+
 def test_matmul_outer_slot_layout_brute_force():
     """The outer-product encodings on plain slot vectors: sum_k A'_{t,k} * B'_k
     (element-wise, exact on small integers) is tile t of A B, slot r P' + j
