@@ -63,6 +63,8 @@ def fc(ctx, keys, Y, W_pt, bias, block, stream=None):
     bias[o]; W_pt is the flat list from encode_fc_weights ([o][i], i over the
     C_out * w_out inputs)."""
     per = len(Y)
+    if per == 0 or len(W_pt) != len(bias) * per:
+        raise ValueError("fc: %d weight plaintexts for %d outputs x %d inputs" % (len(W_pt), len(bias), per))
     out = []
     for o in range(len(bias)):
         acc = None
