@@ -827,7 +827,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X "
-              "(multi-GPU sharding is a design note, not part of this build)", file=sys.stderr)
+              "(sharding over several GPUs is not implemented)", file=sys.stderr)
         sys.exit(2)
 
     from paper_2512_18646_amd import vr, perop

@@ -4,6 +4,7 @@ import ctypes
 import os
 import re
 import subprocess
+import sys
 
 import pytest
 
@@ -71,3 +72,15 @@ def test_security_check_runs_before_device_use():
     with pytest.raises(vr.VRError) as e:
         vr.Context(13, [49, 40, 40, 40], [49], 4, 40.0, sigma=3.0)
     assert e.value.code == vr.VR_EINVAL
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus 2 (or a WORLD_SIZE above 1) exits
+    with status 2 and says so, before touching the library or a device."""
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    for args, env in ((["--gpus", "2"], {}), ([], {"WORLD_SIZE": "2"})):
+        r = subprocess.run([sys.executable, os.path.join(root, "bench.py")] + args, cwd=root,
+                           env=dict(os.environ, **env), capture_output=True, text=True, timeout=120)
+        assert r.returncode == 2
+        assert "one GPU only" in r.stderr
+        assert r.stdout == ""
