@@ -115,19 +115,25 @@ namespace {
 
 // ------------------------------------------------------------- kernels
 
+// Input (u, i) packed as u << 24 | i and the weight row pre-multiplied by
+// the limb count, so that a block decodes a term with a shift and a mask
+// (the scalar unit, not the vector ALU, limits this kernel: a division by
+// the column count per term cost more scalar instructions than the products
+// cost vector ones).
 struct Term {
-    u32 in_idx;   // input ciphertext (pointer table index)
-    u32 w_idx;    // weight row
+    u32 in_idx;   // rotation u << 24 | input column index i
+    u32 w_idx;    // weight row of filter 0 times the limb count
 };
+constexpr u32 kTermColBits = 24;
 
 // For each of n_sets independent image sets s and each output column j':
 // out[s][f][j'] = sum_{terms of j'} w_f * in (+ bias on component 0) for every
 // filter f, 2 components.  The filters of one column read the same inputs, so
 // a block keeps all filters' sums in registers and reads each input word
-// once.  Term input index i = u * n_x + j: for u = 0 ciphertext s * n_x + j
-// of slab x, for u >= 1 ciphertext (u - 1) * n_x * n_sets + s * n_x + j of
-// slab r (the rotations by u of every column of every set), all with stride
-// `stride`.  Term weight row for filter f: w_row + f * w_fstride.
+// once.  Term input (u, j): for u = 0 ciphertext s * n_x + j of slab x, for
+// u >= 1 ciphertext (u - 1) * n_x * n_sets + s * n_x + j of slab r (the
+// rotations by u of every column of every set), all with stride `stride`.
+// Term weight offset for filter f and limb l: w_idx + f * w_fstride * nl + l.
 //
 // Launch order: the logical block id runs over output columns fastest, then
 // sets, then rows, then 256-coefficient chunks, so the columns that read the
@@ -160,6 +166,12 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
     const u64 q = mq[l].q, q2 = 2 * q;
     const u32 a = term_off[jo], b = term_off[jo + 1];
     const u32 n_out = n_filters * wo;
+    const size_t tile = (size_t)row * n + t;
+    const u64* xb = x + (size_t)set * n_x * stride;
+    const u64* rb = r + (size_t)set * n_x * stride;
+    const size_t ustride = (size_t)n_x * n_sets * stride;
+    const size_t fst = (size_t)w_fstride * nl;
+    constexpr u32 kColMask = (1u << kTermColBits) - 1;
     if (q < (1ull << 51)) {
         // FP64 products (the block's limb has one modulus): inputs and
         // weights balanced, each product within 0.75 q, the sums reduced
@@ -177,10 +189,9 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
                 for (int i = 0; i < 8; i++) {
                     if (k0 + i < b) {
                         const Term tm = terms[k0 + i];
-                        const u32 u = tm.in_idx / n_x, j = tm.in_idx - u * n_x;
-                        const u64* src = u == 0 ? x + (size_t)(set * n_x + j) * stride
-                                                : r + ((size_t)(u - 1) * n_x * n_sets + set * n_x + j) * stride;
-                        xv[i] = src[(size_t)row * n + t];
+                        const u32 u = tm.in_idx >> kTermColBits, j = tm.in_idx & kColMask;
+                        const u64* src = u == 0 ? xb : rb + (u - 1) * ustride;
+                        xv[i] = src[(size_t)j * stride + tile];
                         wrow[i] = tm.w_idx;
                     }
                 }
@@ -191,7 +202,7 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
 #pragma unroll
                         for (int f = 0; f < kMaxFilters; f++) {
                             if (f < (int)nf) {
-                                const size_t wi = (size_t)(wrow[i] + (f0 + f) * w_fstride) * nl + l;
+                                const size_t wi = wrow[i] + (f0 + f) * fst + l;
                                 acc[f] += fmulmod(xf, wf[wi], qd, qinv);
                             }
                         }
@@ -228,10 +239,9 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
             for (int i = 0; i < 8; i++) {
                 if (k0 + i < b) {
                     const Term tm = terms[k0 + i];
-                    const u32 u = tm.in_idx / n_x, j = tm.in_idx - u * n_x;
-                    const u64* src = u == 0 ? x + (size_t)(set * n_x + j) * stride
-                                            : r + ((size_t)(u - 1) * n_x * n_sets + set * n_x + j) * stride;
-                    xv[i] = src[(size_t)row * n + t];
+                    const u32 u = tm.in_idx >> kTermColBits, j = tm.in_idx & kColMask;
+                    const u64* src = u == 0 ? xb : rb + (u - 1) * ustride;
+                    xv[i] = src[(size_t)j * stride + tile];
                     wrow[i] = tm.w_idx;
                 }
             }
@@ -241,7 +251,7 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
 #pragma unroll
                     for (int f = 0; f < kMaxFilters; f++) {
                         if (f < (int)nf) {
-                            const size_t wi = (size_t)(wrow[i] + (f0 + f) * w_fstride) * nl + l;
+                            const size_t wi = wrow[i] + (f0 + f) * fst + l;
                             u64 v = acc[f] + shoup_lazy(xv[i], w[wi], ws[wi], q);
                             acc[f] = v >= q2 ? v - q2 : v;
                         }
@@ -490,7 +500,7 @@ u32 pow2ceil(u32 x)
 // Device-resident constants of one conv layer call: weights [RHA(K q_l)]_{q_i}
 // with Shoup companions (one row per (c', c, u, v)), the AddConst value per
 // output and limb, and the term list (input index, weight row of filter 0)
-// per output column.  Input (u, c, j) has index u * C_in * w + c * w + j.
+// per output column.  Input (u, c, j) is u << 24 | (c * w + j).
 struct ConvPlan {
     BufPtr buf;
     const Term* terms = nullptr;
@@ -504,6 +514,8 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
 {
     const u32 wo = (w + 2 * pad - k) / stride + 1, nl = level + 1;
     const size_t nw = (size_t)C_out * C_in * k * k;
+    if ((size_t)C_in * w >= (1u << kTermColBits) || k >= 256 || nw * nl >= (1ull << 32))
+        throw Error(VR_EINVAL, "conv layer too large: C_in * w must stay below 2^24, k below 256");
     std::string key = "conv:";
     u32 shape[7] = {C_in, w, pad, C_out, k, stride, level};
     key.append((const char*)shape, sizeof shape);
@@ -539,8 +551,8 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
                 int jj = (int)(stride * jo + v) - (int)pad;
                 if (jj < 0 || jj >= (int)w) continue;
                 for (u32 u = 0; u < k; u++)
-                    terms.push_back({(u32)(((size_t)u * C_in + c) * w + jj),
-                                     (u32)(((size_t)c * k + u) * k + v)});
+                    terms.push_back({(u32)(((size_t)u << kTermColBits) | ((size_t)c * w + jj)),
+                                     (u32)((((size_t)c * k + u) * k + v) * nl)});
             }
         off.push_back((u32)terms.size());
     }
