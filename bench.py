@@ -234,8 +234,8 @@ def uneven_bench(vr, n_req, level, reps, seed=4):
         if kind == "matmul":
             m, n, p = shape
             A, B = SI.matmul_operands(rs, m, n, p)
-            items.append(("matmul", ctx.encrypt_matrix_columns(keys, A, 0, m, p, level, 1004, 1000 * i),
-                          ctx.encrypt_matrix_columns(keys, B, 1, m, p, level, 1004, 1000 * i + 500),
+            items.append(("matmul", ctx.encrypt_matrix_columns(keys, A, 0, m, p, level, 1004, (2 * i) << 20),
+                          ctx.encrypt_matrix_columns(keys, B, 1, m, p, level, 1004, (2 * i + 1) << 20),
                           (m, n, p), (A, B)))
         else:
             side = shape
@@ -245,7 +245,7 @@ def uneven_bench(vr, n_req, level, reps, seed=4):
             hp = 1 << (side + 1).bit_length()
             B = ctx.slots // hp
             X = SI.images(rs, B, 1, side, side)
-            items.append(("conv", ctx.encrypt_columns(keys, X, 1, level, 1004, 1000 * i), side, B))
+            items.append(("conv", ctx.encrypt_columns(keys, X, 1, level, 1004, (2 * i) << 20), side, B))
             images += B
 
     def per_request():
@@ -329,8 +329,8 @@ def uneven_full_bench(vr, n_req, level, reps, seed=4):
         if kind == "matmul":
             m, n, p = shape
             A, B = SI.matmul_operands(rs, m, n, p)
-            items.append(("matmul", ctx.encrypt_matrix_columns(keys, A, 2, m, p, level, 1004, 100000 * i),
-                          ctx.encrypt_matrix_columns(keys, B, 3, m, p, level, 1004, 100000 * i + 90000),
+            items.append(("matmul", ctx.encrypt_matrix_columns(keys, A, 2, m, p, level, 1004, (2 * i) << 20),
+                          ctx.encrypt_matrix_columns(keys, B, 3, m, p, level, 1004, (2 * i + 1) << 20),
                           (m, n, p), (A, B)))
             lo, hi = min(m, p), max(m, p)
             rot_split += n * ((1 << (lo - 1).bit_length()) - 1)
@@ -343,7 +343,7 @@ def uneven_full_bench(vr, n_req, level, reps, seed=4):
             hp = 1 << (side + 1).bit_length()
             B = ctx.slots // hp
             X = SI.images(rs, B, 1, side, side)
-            items.append(("conv", ctx.encrypt_columns(keys, X, 1, level, 1004, 100000 * i), side, B))
+            items.append(("conv", ctx.encrypt_columns(keys, X, 1, level, 1004, (2 * i) << 20), side, B))
             images += B
     sync()
     setup_s = time.perf_counter() - t0

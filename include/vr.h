@@ -131,34 +131,46 @@ const char *vr_last_error(void);
 
 /* ------------------------------------------------------------ client side */
 
+/* Randomness.  Every `seed` below is a 256-bit ChaCha20 key given as four
+ * host words (seed[0] holds key bytes 0..7, little-endian; seed[3] bytes
+ * 24..31); a NULL seed is VR_EINVAL.  The security level the context reports
+ * holds only for a seed drawn uniformly at random and kept secret: a seed
+ * with a small range (for instance a 64-bit value in seed[0] and zeros
+ * elsewhere, as the tests use) lets anyone holding the public key search the
+ * range and recover the secret key.  Encryption randomness is a function of
+ * (seed, ct_id) only: under one public key a (seed, ct_id) pair must never be
+ * used twice, since two encryptions with the same pair share their mask and
+ * their difference reveals the difference of the messages. */
+
 /* Secret key s (ternary), public key, relinearisation key and one rotation
  * key per distinct Galois element 5^(step mod S) in rot_steps (hybrid key
  * switching, dnum digits, special primes P).  All randomness is the ChaCha20
  * stream keyed by `seed` (purpose/object nonce per key part), so the keys are
  * a deterministic function of (params, seed, steps). */
-vr_status vr_keygen(vr_context *ctx, uint64_t seed, const int32_t *rot_steps, size_t n_steps,
+vr_status vr_keygen(vr_context *ctx, const uint64_t seed[4], const int32_t *rot_steps, size_t n_steps,
                     vr_secret_key **sk, vr_eval_keys **ek);
 /* Adds rotation keys (same seed as the original keygen keeps them canonical). */
 vr_status vr_keys_add_rotations(vr_context *ctx, const vr_secret_key *sk, vr_eval_keys *ek,
-                                uint64_t seed, const int32_t *rot_steps, size_t n_steps);
+                                const uint64_t seed[4], const int32_t *rot_steps, size_t n_steps);
 /* Canonical embedding: slot j of x (j < n <= S, rest zero) is the value at
  * the root psi^(5^j); coefficients m_t = round-half-away((2 scale / N) Re
  * sum_j x_j exp(-i pi 5^j t / N)), |m_t| < 2^62, reduced into q_0..q_level. */
 vr_status vr_encode(vr_context *ctx, const double *x, size_t n, uint32_t level, double scale,
                     vr_plaintext **out);
 /* Public-key encryption (v b + e0 + m, v a + e1) with v, e0, e1 drawn from
- * the stream of (seed, ct_id). */
+ * the stream of (seed, ct_id); the pair must be unique under one public key. */
 vr_status vr_encrypt(vr_context *ctx, const vr_eval_keys *ek, const vr_plaintext *pt,
-                     uint64_t seed, uint64_t ct_id, vr_ciphertext **out);
+                     const uint64_t seed[4], uint64_t ct_id, vr_ciphertext **out);
 /* Column-wise image encoding (abstract and contributions: an h x w image is
  * w ciphertexts of h slots).  x is [B][C][h][w] row-major FP64.  Block height
  * H' = pow2(h + 2 pad); image b occupies slots b H' .. b H' + H' - 1 of every
  * column ciphertext (virtual ciphertexts), row i at b H' + pad + i.  Requires
  * B H' <= S.  cols receives C*w handles, column (c, j) at index c*w + j,
- * encrypted with ct_id = first_ct_id + c*w + j. */
+ * encrypted with ct_id = first_ct_id + c*w + j (the caller keeps the ranges
+ * of different calls under one seed and public key disjoint). */
 vr_status vr_encrypt_columns(vr_context *ctx, const vr_eval_keys *ek, const double *x,
                              uint32_t B, uint32_t C, uint32_t h, uint32_t w, uint32_t pad,
-                             uint32_t level, uint64_t seed, uint64_t first_ct_id,
+                             uint32_t level, const uint64_t seed[4], uint64_t first_ct_id,
                              vr_ciphertext **cols);
 /* Matrix operand as n column ciphertexts (abstract: A (m x n) and B (n x p)
  * as n ciphertexts each).  role 0: M is A (rows x cols = m x n), ciphertext k
@@ -170,10 +182,11 @@ vr_status vr_encrypt_columns(vr_context *ctx, const vr_eval_keys *ek, const doub
  * A'_{t,k} at index t n + k (T = ceil(m / R), R = S / P'), slot r P' + j ->
  * A[t R + r][k] for j < p and t R + r < m; role 3: M is B (n x p), n
  * ciphertexts B'_k, slot r P' + j -> B[k][j] for j < p and every r < R.
- * Ciphertext i is encrypted with ct_id = first_ct_id + i. */
+ * Ciphertext i is encrypted with ct_id = first_ct_id + i (ranges of
+ * different calls under one seed and public key must not overlap). */
 vr_status vr_encrypt_matrix_columns(vr_context *ctx, const vr_eval_keys *ek, const double *M,
                                     uint32_t rows, uint32_t cols, uint32_t role, uint32_t m,
-                                    uint32_t p, uint32_t level, uint64_t seed,
+                                    uint32_t p, uint32_t level, const uint64_t seed[4],
                                     uint64_t first_ct_id, vr_ciphertext **out);
 /* m' = c0 + c1 s (+ c2 s^2): plaintext at the ciphertext's level and scale. */
 vr_status vr_decrypt(vr_context *ctx, const vr_secret_key *sk, const vr_ciphertext *ct,

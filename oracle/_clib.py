@@ -44,10 +44,10 @@ def _load():
         "orc_rescale_limb": (None, [P, P, P, sz, u64, u64]),
         "orc_chacha_quarter": (None, [P]),
         "orc_chacha20_block": (None, [P, u32, P, P]),
-        "orc_stream_words": (None, [u64, u32, u64, u64, sz, P]),
-        "orc_sample_ternary": (None, [u64, u32, u64, sz, P]),
-        "orc_sample_gauss": (None, [u64, u32, u64, sz, P, P]),
-        "orc_sample_uniform": (None, [u64, u32, u64, u32, u32, u64, P]),
+        "orc_stream_words": (None, [P, u32, u64, u64, sz, P]),
+        "orc_sample_ternary": (None, [P, u32, u64, sz, P]),
+        "orc_sample_gauss": (None, [P, u32, u64, sz, P, P]),
+        "orc_sample_uniform": (None, [P, u32, u64, u32, u32, u64, P]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)

@@ -13,8 +13,9 @@ reach the same limbs:
   roots       psi = g^((q-1)/2N) for the smallest g >= 2 with psi^N = -1
   security    sum of prime bit lengths <= 218 / 438 / 881 / 1740 for
               N = 2^13 / 2^14 / 2^15 / 2^16 (HE standard, ternary secret)
-  randomness  ChaCha20 stream per (seed, purpose, object); fixed word
-              positions per coefficient (no rejection), see ckks_oracle.c
+  randomness  ChaCha20 stream per (seed, purpose, object), the 256-bit seed
+              being the key; fixed word positions per coefficient (no
+              rejection), see ckks_oracle.c
   keys        hybrid key switching with dnum digits (Han & Ki, CT-RSA 2020),
               CRT-idempotent key form: b_j = -a_j s + e_j + [P]_{q_i} s' on the
               limbs of digit j
@@ -315,24 +316,33 @@ class Context:
         return pow(5, step % self.slots, 2 * self.n)
 
     # ------------------------------------------------------------- sampling
+    @staticmethod
+    def seed_words(seed):
+        """The 256-bit ChaCha20 key as four little-endian 64-bit words
+        (a seed below 2^64 leaves the upper words zero)."""
+        seed = int(seed)
+        if not 0 <= seed < 1 << 256:
+            raise ValueError("seed must be a 256-bit non-negative integer")
+        return np.array([(seed >> (64 * i)) & 0xFFFFFFFFFFFFFFFF for i in range(4)], dtype=np.uint64)
+
     def stream_words(self, seed, purpose, obj, first, count):
-        out = np.empty(count, dtype=np.uint64)
-        lib.orc_stream_words(seed, purpose, obj, first, count, ptr(out))
+        out, key = np.empty(count, dtype=np.uint64), self.seed_words(seed)
+        lib.orc_stream_words(ptr(key), purpose, obj, first, count, ptr(out))
         return out
 
     def sample_ternary(self, seed, purpose, obj):
-        out = np.empty(self.n, dtype=np.int64)
-        lib.orc_sample_ternary(seed, purpose, obj, self.n, ptr(out))
+        out, key = np.empty(self.n, dtype=np.int64), self.seed_words(seed)
+        lib.orc_sample_ternary(ptr(key), purpose, obj, self.n, ptr(out))
         return out
 
     def sample_gauss(self, seed, purpose, obj):
-        out = np.empty(self.n, dtype=np.int64)
-        lib.orc_sample_gauss(seed, purpose, obj, self.n, ptr(self.cdt), ptr(out))
+        out, key = np.empty(self.n, dtype=np.int64), self.seed_words(seed)
+        lib.orc_sample_gauss(ptr(key), purpose, obj, self.n, ptr(self.cdt), ptr(out))
         return out
 
     def sample_uniform(self, seed, purpose, obj, limb, q):
-        out = np.empty(self.n, dtype=np.uint64)
-        lib.orc_sample_uniform(seed, purpose, obj, limb, self.log_n, q, ptr(out))
+        out, key = np.empty(self.n, dtype=np.uint64), self.seed_words(seed)
+        lib.orc_sample_uniform(ptr(key), purpose, obj, limb, self.log_n, q, ptr(out))
         return out
 
     # --------------------------------------------------------------- keygen

@@ -299,12 +299,17 @@ void orc_chacha20_block(const u32 *key8, u32 counter, const u32 *nonce3, u32 *ou
     for (int i = 0; i < 16; i++) out16[i] = s[i] + init[i];
 }
 
-/* Keystream words for (seed, purpose, object): key = seed as 8 little-endian
- * bytes then 24 zero bytes; nonce = purpose (u32 LE) || object (u64 LE); block
- * counter from 0; 64-bit word w is bytes 8w..8w+7 of the stream, little-endian. */
-void orc_stream_words(u64 seed, u32 purpose, u64 obj, u64 first, size_t count, u64 *out)
+/* Keystream words for (seed, purpose, object): the ChaCha20 key is the 256-bit
+ * seed as 32 little-endian bytes (seed4[0] holds bits 0..63); nonce = purpose
+ * (u32 LE) || object (u64 LE); block counter from 0; 64-bit word w is bytes
+ * 8w..8w+7 of the stream, little-endian. */
+void orc_stream_words(const u64 *seed4, u32 purpose, u64 obj, u64 first, size_t count, u64 *out)
 {
-    u32 key[8] = {(u32)seed, (u32)(seed >> 32), 0, 0, 0, 0, 0, 0};
+    u32 key[8];
+    for (int i = 0; i < 4; i++) {
+        key[2 * i] = (u32)seed4[i];
+        key[2 * i + 1] = (u32)(seed4[i] >> 32);
+    }
     u32 nonce[3] = {purpose, (u32)obj, (u32)(obj >> 32)};
     u32 blk[16];
     u64 cur = ~0ull;
@@ -322,7 +327,7 @@ void orc_stream_words(u64 seed, u32 purpose, u64 obj, u64 first, size_t count, u
 
 /* Ternary sample from one stream word: floor(3w / 2^64) - 1 in {-1, 0, 1};
  * coefficient t uses word t. */
-void orc_sample_ternary(u64 seed, u32 purpose, u64 obj, size_t n, i64 *out)
+void orc_sample_ternary(const u64 *seed, u32 purpose, u64 obj, size_t n, i64 *out)
 {
     u64 *w = (u64 *)malloc(n * sizeof(u64));
     orc_stream_words(seed, purpose, obj, 0, n, w);
@@ -333,7 +338,7 @@ void orc_sample_ternary(u64 seed, u32 purpose, u64 obj, size_t n, i64 *out)
 /* Discrete Gaussian by cumulative table: coefficient t uses word t; bit 63 is
  * the sign, the low 63 bits r give |x| = min{k : r < T[k]} (T has 20 entries,
  * T[19] = 2^63); a zero magnitude ignores the sign. */
-void orc_sample_gauss(u64 seed, u32 purpose, u64 obj, size_t n, const u64 *cdt, i64 *out)
+void orc_sample_gauss(const u64 *seed, u32 purpose, u64 obj, size_t n, const u64 *cdt, i64 *out)
 {
     u64 *w = (u64 *)malloc(n * sizeof(u64));
     orc_stream_words(seed, purpose, obj, 0, n, w);
@@ -349,7 +354,7 @@ void orc_sample_gauss(u64 seed, u32 purpose, u64 obj, size_t n, const u64 *cdt, 
 /* Uniform sample mod q for limb `limb`: coefficient t takes stream words
  * 2(limb*N + t) (low half) and 2(limb*N + t) + 1 (high half) of a 128-bit W,
  * and the value is floor(W * q / 2^128), computed as a 192-bit product. */
-void orc_sample_uniform(u64 seed, u32 purpose, u64 obj, u32 limb, u32 logn, u64 q, u64 *out)
+void orc_sample_uniform(const u64 *seed, u32 purpose, u64 obj, u32 limb, u32 logn, u64 q, u64 *out)
 {
     u64 n = 1ull << logn;
     u64 *w = (u64 *)malloc(2 * n * sizeof(u64));

@@ -303,10 +303,15 @@ def fc_plaintexts(ctx: Context, W, C, ho, wo, stride, Hp, level):
 
 
 def fc(ctx: Context, keys: Keys, Y, pts, bias, Hp):
+    """Z_o = RotSum_Hp(Rescale(sum_i Y_i * pt_{o,i})) + bias_o.  Weights encoded
+    below the inputs' level: the inputs are first dropped to it (a level drop
+    keeps the message), so the layer runs at the weights' level."""
     out = []
     for o, row in enumerate(pts):
         acc = None
         for y, pt in zip(Y, row):
+            if pt.level < y.level:
+                y = ctx.mod_drop(y, pt.level)
             t = ctx.mul_plain(y, pt)
             acc = t if acc is None else ctx.add(acc, t)
         z = ctx.rescale(acc)

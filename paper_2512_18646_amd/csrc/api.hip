@@ -42,7 +42,7 @@ using namespace vr;
 
 namespace vr {
 
-void gen_switch_key(vr_context* ctx, u64 seed, const u64* s_all, const u64* sp_all, u32 g,
+void gen_switch_key(vr_context* ctx, const Seed256& seed, const u64* s_all, const u64* sp_all, u32 g,
                     vr_switch_key& key, hipStream_t st)
 {
     const u32 nmod = ctx->nmod();
@@ -72,7 +72,7 @@ void gen_switch_key(vr_context* ctx, u64 seed, const u64* s_all, const u64* sp_a
     }
 }
 
-void add_rotation_keys(vr_context* ctx, const vr_secret_key* sk, vr_eval_keys* ek, u64 seed,
+void add_rotation_keys(vr_context* ctx, const vr_secret_key* sk, vr_eval_keys* ek, const Seed256& seed,
                        const int32_t* steps, size_t n_steps, hipStream_t st)
 {
     const u32 nmod = ctx->nmod();
@@ -227,13 +227,14 @@ vr_status vr_context_trim(vr_context* ctx)
 
 // ------------------------------------------------------------------ client
 
-vr_status vr_keygen(vr_context* ctx, uint64_t seed, const int32_t* rot_steps, size_t n_steps,
+vr_status vr_keygen(vr_context* ctx, const uint64_t* seed_words, const int32_t* rot_steps, size_t n_steps,
                     vr_secret_key** sk_out, vr_eval_keys** ek_out)
 {
     if (sk_out) *sk_out = nullptr;
     if (ek_out) *ek_out = nullptr;
     API_BEGIN
-    REQUIRE(ctx && sk_out && ek_out, "null argument");
+    REQUIRE(ctx && sk_out && ek_out && seed_words, "null argument");
+    const Seed256 seed = seed_of(seed_words);
     REQUIRE(n_steps == 0 || rot_steps, "null rotation steps");
     hipStream_t st = ctx->stream;
     const u32 nmod = ctx->nmod(), nq = ctx->L + 1;
@@ -274,12 +275,12 @@ vr_status vr_keygen(vr_context* ctx, uint64_t seed, const int32_t* rot_steps, si
 }
 
 vr_status vr_keys_add_rotations(vr_context* ctx, const vr_secret_key* sk, vr_eval_keys* ek,
-                                uint64_t seed, const int32_t* rot_steps, size_t n_steps)
+                                const uint64_t* seed, const int32_t* rot_steps, size_t n_steps)
 {
     API_BEGIN
-    REQUIRE(ctx && sk && ek, "null argument");
+    REQUIRE(ctx && sk && ek && seed, "null argument");
     REQUIRE(n_steps == 0 || rot_steps, "null rotation steps");
-    add_rotation_keys(ctx, sk, ek, seed, rot_steps, n_steps, ctx->stream);
+    add_rotation_keys(ctx, sk, ek, seed_of(seed), rot_steps, n_steps, ctx->stream);
     VR_HIP(hipStreamSynchronize(ctx->stream));
     API_END
 }
@@ -296,12 +297,12 @@ vr_status vr_encode(vr_context* ctx, const double* x, size_t n, uint32_t level, 
 }
 
 vr_status vr_encrypt(vr_context* ctx, const vr_eval_keys* ek, const vr_plaintext* pt,
-                     uint64_t seed, uint64_t ct_id, vr_ciphertext** out)
+                     const uint64_t* seed, uint64_t ct_id, vr_ciphertext** out)
 {
     if (out) *out = nullptr;
     API_BEGIN
-    REQUIRE(ctx && ek && pt && out, "null argument");
-    *out = ev_encrypt(ctx, ek, pt, seed, ct_id, ctx->stream);
+    REQUIRE(ctx && ek && pt && out && seed, "null argument");
+    *out = ev_encrypt(ctx, ek, pt, seed_of(seed), ct_id, ctx->stream);
     API_END
 }
 

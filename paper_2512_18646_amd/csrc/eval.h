@@ -44,7 +44,7 @@ void ev_rotate_many(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext
 vr_plaintext* ev_encode(vr_context* ctx, const double* x_host, size_t n, u32 level, double scale,
                         hipStream_t s);
 vr_ciphertext* ev_encrypt(vr_context* ctx, const vr_eval_keys* ek, const vr_plaintext* pt,
-                          u64 seed, u64 ct_id, hipStream_t s);
+                          const Seed256& seed, u64 ct_id, hipStream_t s);
 
 // rescale of n_ct ciphertexts laid out densely (stride = ncomp*(level+1)*N) into out
 void rescale_dense(vr_context* ctx, const u64* in, u64* out, u32 n_polys, u32 level, hipStream_t s);

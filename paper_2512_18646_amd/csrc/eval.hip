@@ -374,7 +374,7 @@ vr_plaintext* ev_encode(vr_context* ctx, const double* x_host, size_t n, u32 lev
 }
 
 vr_ciphertext* ev_encrypt(vr_context* ctx, const vr_eval_keys* ek, const vr_plaintext* pt,
-                          u64 seed, u64 ct_id, hipStream_t s)
+                          const Seed256& seed, u64 ct_id, hipStream_t s)
 {
     const u32 level = pt->level, nl = level + 1;
     const size_t n = ctx->n;

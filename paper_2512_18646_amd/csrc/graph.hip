@@ -30,7 +30,7 @@ CnnDesc make_desc(vr_context* ctx, const vr_cnn_desc* d, u32 level_in, hipStream
         const size_t count = (size_t)d->fc_out * c.C_out * c.w_out();
         const u32 nl = level_in - c.square;     // limbs of the FC input (level_in - 1 - square + 1)
         BufPtr hold;
-        c.fc_P = fc_weights(ctx, d->fc_w, count, nl, &c.fc_stride, &c.fc_scale, hold, s);
+        c.fc_P = fc_weights(ctx, d->fc_w, count, nl, &c.fc_stride, &c.fc_scale, &c.fc_level, hold, s);
         if (hold) c.fc_hold.push_back(hold);
         for (size_t i = 0; i < count; i++) c.fc_hold.push_back(d->fc_w[i]->buf);
         c.fc_bias.assign(d->fc_bias, d->fc_bias + d->fc_out);
@@ -51,14 +51,14 @@ Slab run_cnn(vr_context* ctx, const vr_eval_keys* ek, const CnnDesc& d, const Sl
     if (!d.fc_out) return y;
     const u32 per = d.C_out * d.w_out();
     if (n_sets == 1)
-        return fc_slab(ctx, ek, y, d.fc_P, d.fc_stride, d.fc_scale, d.fc_out, d.fc_bias.data(),
+        return fc_slab(ctx, ek, y, d.fc_P, d.fc_stride, d.fc_scale, d.fc_level, d.fc_out, d.fc_bias.data(),
                        d.fc_block, s);
-    Slab z = new_slab(ctx, n_sets * d.fc_out, 2, y.level - 1, 1.0, s);
+    Slab z = new_slab(ctx, n_sets * d.fc_out, 2, std::min(y.level, d.fc_level) - 1, 1.0, s);
     for (u32 st = 0; st < n_sets; st++) {
         Slab ys = y;
         ys.n = per;
         ys.base = y.ct(st * per);
-        Slab zs = fc_slab(ctx, ek, ys, d.fc_P, d.fc_stride, d.fc_scale, d.fc_out, d.fc_bias.data(),
+        Slab zs = fc_slab(ctx, ek, ys, d.fc_P, d.fc_stride, d.fc_scale, d.fc_level, d.fc_out, d.fc_bias.data(),
                           d.fc_block, s);
         z.scale = zs.scale;
         VR_HIP(hipMemcpyAsync(z.ct(st * d.fc_out), zs.base, (size_t)d.fc_out * zs.stride * sizeof(u64),

@@ -56,6 +56,7 @@ struct ConvArgs {
     u32 log_n;
     const ModQ* mq;
 };
+VR_KERNEL_ARG(ConvArgs);
 
 constexpr int kMaxOut = 48;
 
@@ -133,6 +134,7 @@ struct ConvFp {
     const double* w;   // [n_out][kMaxIn][2]: balanced [Qhat_i]_t, [2^30 Qhat_i]_t
     const double* t;   // [n_out][2]: t, 1 / t
 };
+VR_KERNEL_ARG(ConvFp);
 
 constexpr double kTwo51 = 2251799813685248.0;
 
@@ -325,6 +327,7 @@ constexpr int kMaxRuns = 4;
 struct LimbRuns {
     u32 b[kMaxRuns], len[kMaxRuns];
 };
+VR_KERNEL_ARG(LimbRuns);
 
 template <int MAXB, bool FP>
 __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_stride, const u64* D,

@@ -53,6 +53,7 @@ constexpr u32 kGatherMax = 64;
 struct GatherTable {
     const u64* src[kGatherMax];
 };
+VR_KERNEL_ARG(GatherTable);
 
 // dst + i * stride <- src[i], i < gridDim.y, as 16-byte pairs
 __global__ __launch_bounds__(kThreads) void k_gather_cts(u64* dst, u64 stride, GatherTable t, u32 pairs)
@@ -276,7 +277,7 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
 // T = sum_k A_k (x) R_k: 3-component tensor accumulate over n_terms pairs
 __global__ __launch_bounds__(kThreads) void k_tensor_acc(u64* T, const u64* A, u64 a_stride,
                                                          const u64* R, u64 r_stride, u32 n_terms,
-                                                         u32 nl, u32 log_n, const ModQ* mq)
+                                                         u32 nl, u32 log_n, const ModQ* mq, u32 accumulate)
 {
     const u32 n = 1u << log_n;
     const u32 t = blockIdx.x * kThreads + threadIdx.x;
@@ -285,6 +286,7 @@ __global__ __launch_bounds__(kThreads) void k_tensor_acc(u64* T, const u64* A, u
     const ModQ m = mq[l];
     const size_t poly = (size_t)nl * n, off = (size_t)l * n + t;
     u64 d0 = 0, d1 = 0, d2 = 0;
+    if (accumulate) d0 = T[off], d1 = T[poly + off], d2 = T[2 * poly + off];
     for (u32 k = 0; k < n_terms; k++) {
         const u64* a = A + (size_t)k * a_stride + off;
         const u64* r = R + (size_t)k * r_stride + off;
@@ -326,9 +328,9 @@ __global__ __launch_bounds__(kThreads) void k_tensor_batch(u64* out, const u64* 
 constexpr int kFcGroup = 8;
 
 __global__ __launch_bounds__(kThreads) void k_mulplain_acc(u64* out, u64 out_stride,
-                                                           const u64* Y, u64 y_stride, u32 n_in,
-                                                           const u64* P, u64 p_stride, u32 n_out,
-                                                           u32 nl, u32 log_n, const ModQ* mq)
+                                                           const u64* Y, u64 y_stride, u64 y_comp,
+                                                           u32 n_in, const u64* P, u64 p_stride,
+                                                           u32 n_out, u32 nl, u32 log_n, const ModQ* mq)
 {
     const u32 n = 1u << log_n;
     const u32 t = blockIdx.x * kThreads + threadIdx.x;
@@ -340,10 +342,12 @@ __global__ __launch_bounds__(kThreads) void k_mulplain_acc(u64* out, u64 out_str
     u64 h0[kFcGroup], l0[kFcGroup], h1[kFcGroup], l1[kFcGroup];
 #pragma unroll
     for (int g = 0; g < kFcGroup; g++) h0[g] = l0[g] = h1[g] = l1[g] = 0;
-    const size_t off0 = (size_t)l * n + t, off1 = (size_t)(nl + l) * n + t;
+    // output limbs [2][nl][N]; input component 1 at y_comp (the inputs may
+    // hold more limbs than the nl read here)
+    const size_t off0 = (size_t)l * n + t, off1 = (size_t)(nl + l) * n + t, yoff1 = y_comp + off0;
     for (u32 i = 0; i < n_in; i++) {
         const u64 y0 = Y[(size_t)i * y_stride + off0];
-        const u64 y1 = Y[(size_t)i * y_stride + off1];
+        const u64 y1 = Y[(size_t)i * y_stride + yoff1];
 #pragma unroll
         for (int g = 0; g < kFcGroup; g++) {
             if (g < (int)cnt) {
@@ -590,15 +594,20 @@ Slab layer_square(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipSt
 }
 
 Slab fc_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& y, const u64* P, u64 p_stride,
-             double p_scale, u32 n_out, const double* bias, u32 block, hipStream_t s)
+             double p_scale, u32 p_level, u32 n_out, const double* bias, u32 block, hipStream_t s)
 {
     if (y.ncomp != 2) throw Error(VR_EINVAL, "FC inputs must be 2-component");
-    if (y.level < 1) throw Error(VR_ELEVEL, "FC needs a level to rescale");
-    const u32 nl = y.level + 1;
-    Slab acc = new_slab(ctx, n_out, 2, y.level, y.scale * p_scale, s);
+    // weights encoded below the inputs' level: the inputs are read on limbs
+    // 0..p_level only (a level drop keeps the message), so the products, the
+    // rescale and the rotate-and-sum all run at the weights' level
+    const u32 level = std::min(y.level, p_level);
+    if (level < 1) throw Error(VR_ELEVEL, "FC needs a level to rescale");
+    const u32 nl = level + 1;
+    Slab acc = new_slab(ctx, n_out, 2, level, y.scale * p_scale, s);
     dim3 grid((ctx->n + kThreads - 1) / kThreads, nl, (n_out + kFcGroup - 1) / kFcGroup);
     hipLaunchKernelGGL(k_mulplain_acc, grid, dim3(kThreads), 0, s, acc.base, acc.stride, y.base,
-                       y.stride, y.n, P, p_stride, n_out, nl, ctx->log_n, ctx->d_modq);
+                       y.stride, (u64)(y.level + 1) * ctx->n, y.n, P, p_stride, n_out, nl, ctx->log_n,
+                       ctx->d_modq);
     VR_CHECK_LAUNCH();
     Slab z = rescale_slab(ctx, acc, s);
     // rotate-and-sum inside each block: z += Rot(z, 2^t)
@@ -619,7 +628,7 @@ Slab fc_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& y, const u64* 
 // Weight plaintexts as one [n_out * n_in][>= nl][N] array: in place when the
 // handles already form one (as vr_encode_fc_weights returns them), else a copy.
 const u64* fc_weights(vr_context* ctx, const vr_plaintext* const* W_pt, size_t count, u32 nl,
-                      u64* p_stride, double* p_scale, BufPtr& holder, hipStream_t s)
+                      u64* p_stride, double* p_scale, u32* p_level, BufPtr& holder, hipStream_t s)
 {
     const vr_plaintext* p0 = W_pt[0];
     if (!p0) throw Error(VR_EINVAL, "null plaintext");
@@ -627,11 +636,14 @@ const u64* fc_weights(vr_context* ctx, const vr_plaintext* const* W_pt, size_t c
     bool contiguous = true;
     for (size_t i = 0; i < count; i++) {
         if (!W_pt[i]) throw Error(VR_EINVAL, "null plaintext");
-        if (W_pt[i]->level + 1 < nl) throw Error(VR_ELEVEL, "weight plaintext below the input level");
+        if (W_pt[i]->level != p0->level) throw Error(VR_ELEVEL, "weight plaintexts at different levels");
         if (W_pt[i]->scale != p0->scale) throw Error(VR_ESCALE, "weight plaintexts at different scales");
-        contiguous = contiguous && W_pt[i]->level == p0->level && W_pt[i]->data == p0->data + i * stride;
+        contiguous = contiguous && W_pt[i]->data == p0->data + i * stride;
     }
     *p_scale = p0->scale;
+    // the layer runs at min(input level, weight level): nl limbs are read
+    nl = std::min(nl, p0->level + 1);
+    *p_level = nl - 1;
     if (contiguous) {
         *p_stride = stride;
         return p0->data;
@@ -649,7 +661,7 @@ const u64* fc_weights(vr_context* ctx, const vr_plaintext* const* W_pt, size_t c
 
 vr_ciphertext** encrypt_slots_batch(vr_context* ctx, const vr_eval_keys* ek,
                                     const std::vector<double>& slots, u32 n_ct, u32 level,
-                                    u64 seed, u64 first_id, vr_ciphertext** out, hipStream_t s)
+                                    const Seed256& seed, u64 first_id, vr_ciphertext** out, hipStream_t s)
 {
     // encode every vector in one batched FFT, then encrypt each into one slab
     const size_t n = ctx->n, S = ctx->slots;
@@ -758,35 +770,49 @@ std::vector<Slab> matmul_multi(vr_context* ctx, const vr_eval_keys* ek, const st
     for (u32 r = 0; r < nr; r++) {   // idx = 0: no rotation
         hipLaunchKernelGGL(k_tensor_acc, grid, dim3(kThreads), 0, s, T.ct(t_off[r]), reqs[r].A.base,
                            reqs[r].A.stride, SB.ct(b_off[r]), SB.stride, reqs[r].n, nl, ctx->log_n,
-                           ctx->d_modq);
+                           ctx->d_modq, 0u);
         VR_CHECK_LAUNCH();
     }
     const u32 max_p = Pp[order[0]];
     if (max_p > 1) {
+        // Bbar columns in chunks whose key-switch scratch stays bounded: one
+        // hoisted ModUp per chunk, then every rotation step its columns need;
+        // a request's tensor sum over k is accumulated chunk by chunk (the
+        // chunk holding its first column starts it).
         KsShape k = ks_shape(ctx, level);
         const u64 xs = (u64)k.beta * k.next * N, us = (u64)2 * k.next * N;
-        BufPtr xbuf = dev_alloc(ctx, ((size_t)n_tot * xs + (size_t)n_tot * k.nq * N) * sizeof(u64), s);
+        const u32 cs = switch_chunk(ctx, level, n_tot);
+        BufPtr xbuf = dev_alloc(ctx, ((size_t)cs * xs + (size_t)cs * k.nq * N) * sizeof(u64), s);
         u64* X = as_u64(xbuf);
-        keyswitch_modup_batch(ctx, SB.base + (size_t)k.nq * N, SB.stride, n_tot, level, X,
-                              X + (size_t)n_tot * xs, s);
-        BufPtr ubuf = dev_alloc(ctx, ((size_t)n_tot * us + keyswitch_moddown_scratch(ctx, level, n_tot)) * sizeof(u64), s);
+        BufPtr ubuf = dev_alloc(ctx, ((size_t)cs * us + keyswitch_moddown_scratch(ctx, level, cs)) * sizeof(u64), s);
         u64* U = as_u64(ubuf);
-        Slab R = new_slab(ctx, n_tot, 2, level, SB.scale, s);
-        for (u32 idx = 1; idx < max_p; idx++) {
-            u32 n_act = 0;   // prefix of columns whose request still needs step idx
-            for (u32 r : order)
-                if (Pp[r] > idx) n_act = b_off[r] + reqs[r].n;
-            const u32 g = galois_element(ctx, (int32_t)idx);
-            keyswitch_inner_batch(ctx, X, xs, SB.base + (size_t)k.nq * N, SB.stride, n_act,
-                                  rot_key(ek, g).data, level, g, U, us, s);
-            keyswitch_moddown_batch(ctx, U, us, n_act, level, R.base, R.base + (size_t)k.nq * N, R.stride,
-                                    SB.base, g, nullptr, SB.stride, U + (size_t)n_act * us, s);
-            for (u32 r : order) {
-                if (Pp[r] <= idx) continue;
-                hipLaunchKernelGGL(k_tensor_acc, grid, dim3(kThreads), 0, s, T.ct(t_off[r] + idx),
-                                   reqs[r].A.base, reqs[r].A.stride, R.ct(b_off[r]), R.stride, reqs[r].n,
-                                   nl, ctx->log_n, ctx->d_modq);
-                VR_CHECK_LAUNCH();
+        Slab R = new_slab(ctx, cs, 2, level, SB.scale, s);
+        for (u32 c0 = 0; c0 < n_tot; c0 += cs) {
+            const u32 nc = std::min(cs, n_tot - c0);
+            keyswitch_modup_batch(ctx, SB.ct(c0) + (size_t)k.nq * N, SB.stride, nc, level, X,
+                                  X + (size_t)cs * xs, s);
+            for (u32 idx = 1; idx < max_p; idx++) {
+                u32 n_act = 0;   // prefix of columns whose request still needs step idx
+                for (u32 r : order)
+                    if (Pp[r] > idx) n_act = b_off[r] + reqs[r].n;
+                if (n_act <= c0) break;   // the prefix only shrinks as idx grows
+                const u32 na = std::min(nc, n_act - c0);
+                const u32 g = galois_element(ctx, (int32_t)idx);
+                keyswitch_inner_batch(ctx, X, xs, SB.ct(c0) + (size_t)k.nq * N, SB.stride, na,
+                                      rot_key(ek, g).data, level, g, U, us, s);
+                keyswitch_moddown_batch(ctx, U, us, na, level, R.base, R.base + (size_t)k.nq * N, R.stride,
+                                        SB.ct(c0), g, nullptr, SB.stride, U + (size_t)na * us, s);
+                for (u32 r : order) {
+                    if (Pp[r] <= idx) continue;
+                    // columns [k0, k1) of request r inside this chunk
+                    const u32 lo = std::max(b_off[r], c0), hi = std::min(b_off[r] + reqs[r].n, c0 + na);
+                    if (lo >= hi) continue;
+                    const u32 k0 = lo - b_off[r];
+                    hipLaunchKernelGGL(k_tensor_acc, grid, dim3(kThreads), 0, s, T.ct(t_off[r] + idx),
+                                       reqs[r].A.ct(k0), reqs[r].A.stride, R.ct(lo - c0), R.stride, hi - lo,
+                                       nl, ctx->log_n, ctx->d_modq, k0 > 0 ? 1u : 0u);
+                    VR_CHECK_LAUNCH();
+                }
             }
         }
     }
@@ -831,7 +857,7 @@ std::vector<Slab> matmul_outer_multi(vr_context* ctx, const vr_eval_keys* ek, co
         for (u32 t = 0; t < T[r]; t++) {
             hipLaunchKernelGGL(k_tensor_acc, grid, dim3(kThreads), 0, s, acc.ct(off[r] + t), reqs[r].A.ct(t * reqs[r].n),
                                reqs[r].A.stride, reqs[r].B.base, reqs[r].B.stride, reqs[r].n, nl, ctx->log_n,
-                               ctx->d_modq);
+                               ctx->d_modq, 0u);
             VR_CHECK_LAUNCH();
         }
     Slab out = rescale_slab(ctx, relin_slab(ctx, ek, acc, s), s);
@@ -885,12 +911,12 @@ extern "C" {
 
 vr_status vr_encrypt_columns(vr_context* ctx, const vr_eval_keys* ek, const double* x, uint32_t B,
                              uint32_t C, uint32_t h, uint32_t w, uint32_t pad, uint32_t level,
-                             uint64_t seed, uint64_t first_ct_id, vr_ciphertext** cols)
+                             const uint64_t* seed, uint64_t first_ct_id, vr_ciphertext** cols)
 {
     if (cols)
         for (size_t i = 0; i < (size_t)C * w; i++) cols[i] = nullptr;
     API_BEGIN
-    REQUIRE(ctx && ek && x && cols, "null argument");
+    REQUIRE(ctx && ek && x && cols && seed, "null argument");
     REQUIRE(B >= 1 && C >= 1 && h >= 1 && w >= 1, "empty image batch");
     REQUIRE(level <= ctx->L, "level above the modulus chain");
     const u32 Hp = pow2ceil(h + 2 * pad);
@@ -904,14 +930,14 @@ vr_status vr_encrypt_columns(vr_context* ctx, const vr_eval_keys* ek, const doub
                 for (u32 i = 0; i < h; i++)
                     z[(size_t)b * Hp + pad + i] = x[(((size_t)b * C + c) * h + i) * w + j];
         }
-    encrypt_slots_batch(ctx, ek, slots, C * w, level, seed, first_ct_id, cols, ctx->stream);
+    encrypt_slots_batch(ctx, ek, slots, C * w, level, seed_of(seed), first_ct_id, cols, ctx->stream);
     VR_HIP(hipStreamSynchronize(ctx->stream));
     API_END
 }
 
 vr_status vr_encrypt_matrix_columns(vr_context* ctx, const vr_eval_keys* ek, const double* M,
                                     uint32_t rows, uint32_t cols, uint32_t role, uint32_t m,
-                                    uint32_t p, uint32_t level, uint64_t seed,
+                                    uint32_t p, uint32_t level, const uint64_t* seed,
                                     uint64_t first_ct_id, vr_ciphertext** out)
 {
     // outputs: role 0 cols, role 1 rows, role 2 T cols, role 3 rows
@@ -923,7 +949,7 @@ vr_status vr_encrypt_matrix_columns(vr_context* ctx, const vr_eval_keys* ek, con
     if (out)
         for (u32 i = 0; i < n_ct; i++) out[i] = nullptr;
     API_BEGIN
-    REQUIRE(ctx && ek && M && out, "null argument");
+    REQUIRE(ctx && ek && M && out && seed, "null argument");
     REQUIRE(role <= 3, "role must be 0 (A columns), 1 (Bbar columns), 2 (A outer) or 3 (B outer)");
     REQUIRE(rows >= 1 && cols >= 1 && m >= 1 && p >= 1, "empty matrix");
     REQUIRE(role == 0 || role == 2 ? rows == m : cols == p, "matrix shape does not match m / p");
@@ -959,7 +985,7 @@ vr_status vr_encrypt_matrix_columns(vr_context* ctx, const vr_eval_keys* ek, con
             }
         }
     }
-    encrypt_slots_batch(ctx, ek, slots, n_ct, level, seed, first_ct_id, out, ctx->stream);
+    encrypt_slots_batch(ctx, ek, slots, n_ct, level, seed_of(seed), first_ct_id, out, ctx->stream);
     VR_HIP(hipStreamSynchronize(ctx->stream));
     API_END
 }
@@ -1135,8 +1161,10 @@ vr_status vr_fc(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* co
     BufPtr hold;
     u64 p_stride = 0;
     double p_scale = 0;
-    const u64* P = fc_weights(ctx, W_pt, (size_t)n_out * n_in, y.level + 1, &p_stride, &p_scale, hold, s);
-    Slab z = fc_slab(ctx, ek, y, P, p_stride, p_scale, n_out, bias, block, s);
+    u32 p_level = 0;
+    const u64* P = fc_weights(ctx, W_pt, (size_t)n_out * n_in, y.level + 1, &p_stride, &p_scale, &p_level,
+                              hold, s);
+    Slab z = fc_slab(ctx, ek, y, P, p_stride, p_scale, p_level, n_out, bias, block, s);
     to_handles(ctx, z, out);
     API_END
 }

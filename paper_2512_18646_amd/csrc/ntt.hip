@@ -50,6 +50,7 @@ struct NttPass {
     u32 first, last;
     u32 max_r;          // stages per round (4, or 5 with 32 elements per thread)
 };
+VR_KERNEL_ARG(NttPass);
 
 __device__ __forceinline__ void limb_addr(const LimbSet& ls, u32 r, u32 n, u32 L,
                                           const u64** in, u64** out, u32* mod)

@@ -1,7 +1,7 @@
 // Randomness and the key-generation / encryption / decryption combiners.
 //
-// Stream: ChaCha20 (RFC 8439) keyed by the 64-bit seed (8 little-endian bytes,
-// then 24 zero bytes), nonce = purpose (u32) || object id (u64), block counter
+// Stream: ChaCha20 (RFC 8439) keyed by the 256-bit seed (32 little-endian
+// bytes), nonce = purpose (u32) || object id (u64), block counter
 // from 0; 64-bit word w is bytes 8w..8w+7 of the keystream.  Every sample sits
 // at a fixed word position, so one GPU thread computes one 64-byte block and
 // emits the samples it holds, with no sequential dependence:
@@ -28,10 +28,11 @@ __device__ __forceinline__ u32 rotl(u32 x, int n) { return (x << n) | (x >> (32 
     c += d; b ^= c; b = rotl(b, 7);
 
 // 16 output words of block `ctr` for (seed, purpose, obj)
-__device__ void chacha_block(u64 seed, u32 purpose, u64 obj, u32 ctr, u32 out[16])
+__device__ void chacha_block(const Seed256& seed, u32 purpose, u64 obj, u32 ctr, u32 out[16])
 {
     u32 x[16] = {0x61707865u, 0x3320646eu, 0x79622d32u, 0x6b206574u,
-                 (u32)seed, (u32)(seed >> 32), 0, 0, 0, 0, 0, 0,
+                 (u32)seed.w[0], (u32)(seed.w[0] >> 32), (u32)seed.w[1], (u32)(seed.w[1] >> 32),
+                 (u32)seed.w[2], (u32)(seed.w[2] >> 32), (u32)seed.w[3], (u32)(seed.w[3] >> 32),
                  ctr, purpose, (u32)obj, (u32)(obj >> 32)};
     u32 s[16];
 #pragma unroll
@@ -51,7 +52,7 @@ __device__ void chacha_block(u64 seed, u32 purpose, u64 obj, u32 ctr, u32 out[16
     for (int i = 0; i < 16; i++) out[i] = s[i] + x[i];
 }
 
-__global__ void k_sample_small(i64* out, u64 seed, u32 purpose, u64 obj, u32 n, int gauss)
+__global__ void k_sample_small(i64* out, Seed256 seed, u32 purpose, u64 obj, u32 n, int gauss)
 {
     u32 b = blockIdx.x * kThreads + threadIdx.x;
     if (8 * b >= n) return;
@@ -75,11 +76,13 @@ __global__ void k_sample_small(i64* out, u64 seed, u32 purpose, u64 obj, u32 n, 
 }
 
 struct UniArgs {
-    u64 seed, obj;
+    Seed256 seed;
+    u64 obj;
     u32 purpose, log_n, n_limbs;
     u32 limb_index[kMaxMod];
     u32 mods[kMaxMod];
 };
+VR_KERNEL_ARG(UniArgs);
 
 __global__ void k_sample_uniform(u64* out, UniArgs a, const ModQ* mq)
 {
@@ -168,7 +171,7 @@ void upload_cdt(hipStream_t s)
     g_cdt_loaded = true;
 }
 
-void launch_sample_ternary(vr_context* ctx, i64* out, u64 seed, u32 purpose, u64 obj, hipStream_t s)
+void launch_sample_ternary(vr_context* ctx, i64* out, const Seed256& seed, u32 purpose, u64 obj, hipStream_t s)
 {
     u32 blocks = (ctx->n / 8 + kThreads - 1) / kThreads;
     hipLaunchKernelGGL(k_sample_small, dim3(blocks), dim3(kThreads), 0, s, out, seed, purpose, obj,
@@ -176,7 +179,7 @@ void launch_sample_ternary(vr_context* ctx, i64* out, u64 seed, u32 purpose, u64
     VR_CHECK_LAUNCH();
 }
 
-void launch_sample_gauss(vr_context* ctx, i64* out, u64 seed, u32 purpose, u64 obj, hipStream_t s)
+void launch_sample_gauss(vr_context* ctx, i64* out, const Seed256& seed, u32 purpose, u64 obj, hipStream_t s)
 {
     upload_cdt(s);
     u32 blocks = (ctx->n / 8 + kThreads - 1) / kThreads;
@@ -185,7 +188,7 @@ void launch_sample_gauss(vr_context* ctx, i64* out, u64 seed, u32 purpose, u64 o
     VR_CHECK_LAUNCH();
 }
 
-void launch_sample_uniform(vr_context* ctx, u64* out, u64 seed, u32 purpose, u64 obj,
+void launch_sample_uniform(vr_context* ctx, u64* out, const Seed256& seed, u32 purpose, u64 obj,
                            const u32* limb_index_host, const u32* mods_host, u32 n, hipStream_t s)
 {
     UniArgs a;

@@ -34,9 +34,18 @@ typedef uint32_t u32;
 typedef unsigned __int128 u128;
 
 // Moduli per context (Q chain + special primes).  Per-limb constant tables
-// passed by value to kernels are sized by it; keep them well under the
-// kernel-argument budget (2 x 40 x 8 = 640 bytes).
+// passed by value to kernels are sized by it (2 x 40 x 8 = 640 bytes).
 constexpr int kMaxMod = 40;
+
+// Budget for a struct passed by value to a kernel.  Keys generated with two
+// 1 KiB tables among the arguments (2 KiB in all) came out wrong on limbs past
+// the first; the cause was not found, so every by-value argument struct is
+// held to this size (static_assert beside each), leaving room under 1 KiB for
+// the kernel's pointers and scalars, and larger per-limb tables live in
+// device memory.
+constexpr unsigned kMaxArgStruct = 896;
+#define VR_KERNEL_ARG(T) \
+    static_assert(sizeof(T) <= kMaxArgStruct, #T " is passed by value to kernels: keep it under the budget")
 
 // --------------------------------------------------------------- errors
 

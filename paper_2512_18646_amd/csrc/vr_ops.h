@@ -14,6 +14,7 @@ struct LimbConsts {
     u64 c[kMaxMod];
     u64 cs[kMaxMod];
 };
+VR_KERNEL_ARG(LimbConsts);
 
 // out = a (+|-) b over n_polys x nl limbs (dense [n_polys][nl][N]).
 void launch_addsub(vr_context* ctx, u64* out, const u64* a, const u64* b, u32 n_polys, u32 nl,
@@ -86,15 +87,28 @@ size_t keyswitch_moddown_scratch(vr_context* ctx, u32 level, u32 n_ct);
 
 // ---------------------------------------------------------- sampling
 
+// The 256-bit ChaCha20 key of every sample: w[0] holds key bytes 0..7
+// (little-endian), w[3] bytes 24..31.
+struct Seed256 {
+    u64 w[4];
+};
+VR_KERNEL_ARG(Seed256);
+inline Seed256 seed_of(const uint64_t* w)
+{
+    Seed256 s;
+    for (int i = 0; i < 4; i++) s.w[i] = w[i];
+    return s;
+}
+
 enum Purpose : u32 {
     kPurSk = 1, kPurPkA = 2, kPurPkE = 3, kPurSwkA = 4, kPurSwkE = 5,
     kPurEncV = 6, kPurEncE0 = 7, kPurEncE1 = 8
 };
-void launch_sample_ternary(vr_context* ctx, i64* out, u64 seed, u32 purpose, u64 obj, hipStream_t s);
-void launch_sample_gauss(vr_context* ctx, i64* out, u64 seed, u32 purpose, u64 obj, hipStream_t s);
+void launch_sample_ternary(vr_context* ctx, i64* out, const Seed256& seed, u32 purpose, u64 obj, hipStream_t s);
+void launch_sample_gauss(vr_context* ctx, i64* out, const Seed256& seed, u32 purpose, u64 obj, hipStream_t s);
 // limbs [n][N] (coefficient domain): limb i uses stream limb index limb_index[i]
 // and modulus index mods[i]
-void launch_sample_uniform(vr_context* ctx, u64* out, u64 seed, u32 purpose, u64 obj,
+void launch_sample_uniform(vr_context* ctx, u64* out, const Seed256& seed, u32 purpose, u64 obj,
                            const u32* limb_index_host, const u32* mods_host, u32 n, hipStream_t s);
 
 // keygen / encryption combiners (evaluation domain)

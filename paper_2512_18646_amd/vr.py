@@ -65,12 +65,12 @@ _SIGS = {
     "vr_context_trim": [P],
     "vr_context_set_tuning": [P, ctypes.c_char_p, ctypes.c_char_p],
     "vr_context_tuning_report": [P, ctypes.c_char_p, SZ],
-    "vr_keygen": [P, U64, P, SZ, PP, PP],
-    "vr_keys_add_rotations": [P, P, P, U64, P, SZ],
+    "vr_keygen": [P, P, P, SZ, PP, PP],
+    "vr_keys_add_rotations": [P, P, P, P, P, SZ],
     "vr_encode": [P, P, SZ, U32, DBL, PP],
-    "vr_encrypt": [P, P, P, U64, U64, PP],
-    "vr_encrypt_columns": [P, P, P, U32, U32, U32, U32, U32, U32, U64, U64, PP],
-    "vr_encrypt_matrix_columns": [P, P, P, U32, U32, U32, U32, U32, U32, U64, U64, PP],
+    "vr_encrypt": [P, P, P, P, U64, PP],
+    "vr_encrypt_columns": [P, P, P, U32, U32, U32, U32, U32, U32, P, U64, PP],
+    "vr_encrypt_matrix_columns": [P, P, P, U32, U32, U32, U32, U32, U32, P, U64, PP],
     "vr_decrypt": [P, P, P, PP],
     "vr_decode": [P, P, P, SZ],
     "vr_add": [P, P, P, PP, P],
@@ -157,6 +157,15 @@ lib = _load()
 
 def exported_symbols():
     return sorted(_SIGS)
+
+
+def _seed(seed):
+    """A seed as the four host words of its 256-bit ChaCha20 key (an integer
+    below 2^256; seed[0] holds bits 0..63)."""
+    seed = int(seed)
+    if not 0 <= seed < 1 << 256:
+        raise ValueError("seed must be a 256-bit non-negative integer")
+    return (ctypes.c_uint64 * 4)(*[(seed >> (64 * i)) & 0xFFFFFFFFFFFFFFFF for i in range(4)])
 
 
 def _check(rc):
@@ -258,7 +267,7 @@ class Keys:
 
     def add_rotations(self, seed, steps):
         st = np.ascontiguousarray(np.asarray(steps, dtype=np.int32))
-        _check(lib.vr_keys_add_rotations(self.ctx.h, self.sk, self.ek, seed, st.ctypes.data, st.size))
+        _check(lib.vr_keys_add_rotations(self.ctx.h, self.sk, self.ek, _seed(seed), st.ctypes.data, st.size))
 
 
 class Context:
@@ -331,7 +340,7 @@ class Context:
     def keygen(self, seed, rot_steps=()):
         st = np.ascontiguousarray(np.asarray(list(rot_steps), dtype=np.int32))
         sk, ek = ctypes.c_void_p(), ctypes.c_void_p()
-        _check(lib.vr_keygen(self.h, seed, st.ctypes.data if st.size else None, st.size,
+        _check(lib.vr_keygen(self.h, _seed(seed), st.ctypes.data if st.size else None, st.size,
                              ctypes.byref(sk), ctypes.byref(ek)))
         return Keys(sk.value, ek.value, self)
 
@@ -344,14 +353,14 @@ class Context:
 
     def encrypt(self, keys, pt, seed, ct_id):
         h = ctypes.c_void_p()
-        _check(lib.vr_encrypt(self.h, keys.ek, pt.h, seed, ct_id, ctypes.byref(h)))
+        _check(lib.vr_encrypt(self.h, keys.ek, pt.h, _seed(seed), ct_id, ctypes.byref(h)))
         return Ciphertext(h.value, self)
 
     def encrypt_columns(self, keys, X, pad, level, seed, first_ct_id):
         X = _f64(X)
         B, C, h, w = X.shape
         arr = (ctypes.c_void_p * (C * w))()
-        _check(lib.vr_encrypt_columns(self.h, keys.ek, X.ctypes.data, B, C, h, w, pad, level, seed,
+        _check(lib.vr_encrypt_columns(self.h, keys.ek, X.ctypes.data, B, C, h, w, pad, level, _seed(seed),
                                       first_ct_id, arr))
         return [Ciphertext(arr[i], self) for i in range(C * w)]
 
@@ -363,7 +372,7 @@ class Context:
             n = self.outer_tiles(m, p)[2] * cols
         arr = (ctypes.c_void_p * n)()
         _check(lib.vr_encrypt_matrix_columns(self.h, keys.ek, M.ctypes.data, rows, cols, role, m, p,
-                                             level, seed, first_ct_id, arr))
+                                             level, _seed(seed), first_ct_id, arr))
         return [Ciphertext(arr[i], self) for i in range(n)]
 
     def decrypt(self, keys, ct):

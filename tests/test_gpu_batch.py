@@ -122,3 +122,41 @@ def test_uneven_batch_outer_products(ctx):
             same(b.outputs(i), r, "replay %d request %d" % (rep, i))
         net.forward(g, gk, cols)[0].export()     # eager work between replays
     b.close()
+
+
+@pytest.mark.parametrize("chunk", [1, 3, 7])
+def test_products_with_chunked_key_switching(ctx, chunk):
+    """Column-split products whose Bbar columns are key-switched in chunks
+    of `chunk` ciphertexts (chunk boundaries inside requests and between
+    requests of different P'): every request's limbs identical to the
+    unchunked call, the first one against the oracle."""
+    from paper_2512_18646_amd import vr
+    o, ok, g, gk = ctx
+    rng = np.random.default_rng(73)
+    shapes = [(16, 5, 16), (8, 6, 8), (16, 3, 4), (8, 4, 3)]
+    mm = []
+    for i, (m, n, p) in enumerate(shapes):
+        A, B = rng.uniform(-1, 1, (m, n)), rng.uniform(-1, 1, (n, p))
+        Ac = [to_gpu(g, c) for c in Ly.encrypt_matrix_columns(o, ok, A, 0, m, p, 3, 110 + i, 0)]
+        Bc = [to_gpu(g, c) for c in Ly.encrypt_matrix_columns(o, ok, B, 1, m, p, 3, 110 + i, 100)]
+        mm.append((A, B, Ac, Bc, m, n, p))
+    g.set_tuning("switch_chunk", "0")
+    refs = [g.matmul(gk, Ac, Bc, m, n, p) for A, B, Ac, Bc, m, n, p in mm]
+    try:
+        g.set_tuning("switch_chunk", str(chunk))
+        b = vr.Batch(g, gk)
+        ids = [b.add_matmul(Ac, Bc, m, n, p) for A, B, Ac, Bc, m, n, p in mm]
+        b.run()
+        for i, r in zip(ids, refs):
+            same(b.outputs(i), r, "chunk %d request %d" % (chunk, i))
+        A, B, Ac, Bc, m, n, p = mm[0]
+        alone = g.matmul(gk, Ac, Bc, m, n, p)
+        same(alone, refs[0], "chunk %d single product" % chunk)
+        b.close()
+    finally:
+        g.set_tuning("switch_chunk", "0")
+    A, B, _, _, m, n, p = mm[0]
+    D = Ly.matmul(o, ok, Ly.encrypt_matrix_columns(o, ok, A, 0, m, p, 3, 110, 0),
+                  Ly.encrypt_matrix_columns(o, ok, B, 1, m, p, 3, 110, 100), m, n, p)
+    for j, (x, y) in enumerate(zip(refs[0], D)):
+        assert_same(x, y, "product %d" % j)

@@ -194,6 +194,14 @@ def test_conv_square_fc_bit_exact_small(small_cnn):
     gZ = g.fc(gk, gY2, Co, wo, gpts, fb, Hp)
     for i, (x, y) in enumerate(zip(gZ, Z)):
         assert_same(x, y, "fc %d" % i)
+    # weights one level below the inputs (conv outputs at level 2, weights at
+    # level 1): the FC reads the inputs' first two limbs only
+    pts1 = Ly.fc_plaintexts(o, W, Co, ho, wo, s, Hp, 1)
+    Z1 = Ly.fc(o, ok, Y, pts1, fb, Hp)
+    gZ1 = g.fc(gk, gY, Co, wo, [g.pt_import(pt.m, pt.level, pt.scale) for row in pts1 for pt in row], fb, Hp)
+    assert gZ1[0].level == 0
+    for i, (x, y) in enumerate(zip(gZ1, Z1)):
+        assert_same(x, y, "fc below the input level %d" % i)
     # GPU-encoded weights: decoded logits still within the bar
     gpts2 = g.encode_fc_weights(W, s, Hp, Y2[0].level)
     gZ2 = g.fc(gk, gY2, Co, wo, gpts2, fb, Hp)
@@ -272,17 +280,20 @@ def test_cnn128_trimmed_sampled():
     gcols = g.encrypt_columns(gk, X, W.pad, 3, 3003, 0)
     ocols = [None] * (W.channels * W.w)
     for c in range(W.channels):
-        for j in (0, 1):
+        for j in (0, 1, 2, 3):
             slots = Ly.image_column_slots(o, X, c, j, W.pad)
             ocols[c * W.w + j] = o.encrypt(ok, o.encode(slots, 3, o.scale), 3003, c * W.w + j)
             gcols[c * W.w + j] = to_gpu(g, ocols[c * W.w + j])
     gY = g.conv2d(gk, gcols, W.channels, W.h, W.w, W.pad, K, bias, W.stride)
     wo = Ly.conv_out_size(W.w, W.pad, W.k, W.stride)
     assert len(gY) == W.c_out * wo == 512
+    # output column 0 (its left neighbour is padding) and the interior column
+    # 1 (input columns 1, 2, 3 at offsets 0, 1, 2)
     Y = Ly.conv2d(o, ok, ocols, W.channels, W.h, W.w, W.pad, K, bias, W.c_out, W.k, W.stride,
-                  only_cols={0})
+                  only_cols={0, 1})
     for co in range(W.c_out):
-        assert_same(gY[co * wo], Y[co * wo], "cnn128 conv out (%d, 0)" % co)
+        for jo in (0, 1):
+            assert_same(gY[co * wo + jo], Y[co * wo + jo], "cnn128 conv out (%d, %d)" % (co, jo))
     gY2 = g.square(gk, gY)
     assert_same(gY2[3 * wo], Ly.square(o, ok, Y[3 * wo]), "cnn128 square")
     Wfc, bfc = W.draw_fc()
@@ -295,3 +306,45 @@ def test_cnn128_trimmed_sampled():
     ref = Ly.ref_fc(Ly.ref_conv(X, K, bias, W.stride, W.pad) ** 2, Wfc, bfc)
     assert gZ[0].meta[1] == 0
     assert Ly.rel_error(logits, ref) < EPS
+
+
+@pytest.mark.timeout(400)
+def test_cnn128_full_level_chunked_key_switching():
+    """The 3x128x128 conv and x^2 entering at level 24 (the whole L = 24
+    chain, three digits of nine primes), with the layer calls' key switching
+    forced into chunks of two ciphertexts: every filter of output column 0
+    and the square of one of them, limb for limb against the oracle (inputs
+    0 and 1 of each channel encrypted by the oracle, the rest by the GPU),
+    and the squared layer decoded against FP64."""
+    W = SI.CNN_128
+    o, ok, g, gk = pair("C3", rot_steps=(1, 2))
+    X, K, bias = W.draw()
+    lv = 24
+    gcols = g.encrypt_columns(gk, X, W.pad, lv, 3004, 0)
+    ocols = [None] * (W.channels * W.w)
+    for c in range(W.channels):
+        for j in (0, 1):
+            slots = Ly.image_column_slots(o, X, c, j, W.pad)
+            ocols[c * W.w + j] = o.encrypt(ok, o.encode(slots, lv, o.scale), 3004, c * W.w + j)
+            gcols[c * W.w + j] = to_gpu(g, ocols[c * W.w + j])
+    wo = Ly.conv_out_size(W.w, W.pad, W.k, W.stride)
+    g.set_tuning("switch_chunk", "2")
+    try:
+        gY = g.conv2d(gk, gcols, W.channels, W.h, W.w, W.pad, K, bias, W.stride)
+        gY2 = g.square(gk, gY)
+    finally:
+        g.set_tuning("switch_chunk", "0")
+    assert gY[0].level == lv - 1 and gY2[0].level == lv - 2
+    Y = Ly.conv2d(o, ok, ocols, W.channels, W.h, W.w, W.pad, K, bias, W.c_out, W.k, W.stride,
+                  only_cols={0})
+    for co in range(W.c_out):
+        assert_same(gY[co * wo], Y[co * wo], "level-24 conv out (%d, 0)" % co)
+    assert_same(gY2[5 * wo], Ly.square(o, ok, Y[5 * wo]), "level-24 square")
+    ref = Ly.ref_conv(X, K, bias, W.stride, W.pad) ** 2
+    Hp = Ly.image_block(W.h, W.pad)
+    got = np.zeros((W.batch, 2, (W.h + 2 * W.pad - W.k) // W.stride + 1))
+    for i, co in enumerate((0, 7)):
+        z = g.decode(g.decrypt(gk, gY2[co * wo + 9]))
+        for b in range(W.batch):
+            got[b, i] = z[b * Hp + W.stride * np.arange(got.shape[2])]
+    assert Ly.rel_error(got, ref[:, [0, 7], :, 9]) < EPS

@@ -226,3 +226,45 @@ def test_server_full_network_model(small):
         assert len(got) == len(ref) == 4
         for j, (a, b) in enumerate(zip(got, ref)):
             same_limbs(a, b, "request %d logit %d" % (i, j))
+
+
+@pytest.mark.timeout(300)
+def test_server_n16_identical_to_alone_and_oracle():
+    """Serving at N = 2^16 (the L = 24 chain, dnum 3) at level 3: requests of
+    two sessions and two models submitted in one burst; every served output
+    has the limbs of the same request evaluated alone, and the first request
+    (the oracle's encryption) matches the oracle's conv + x^2 limb for limb."""
+    from paper_2512_18646_amd import vr
+    o, ok, g, gk = pair("C3", rot_steps=(1, 2))
+    gk2 = g.keygen(2025, rot_steps=[1, 2])
+    B, Ci, h, w, k, s, pad = 64, 1, 8, 8, 3, 2, 1
+    rng = np.random.default_rng(41)
+    K1, b1 = rng.normal(0, 0.05, (2, Ci, k, k)), rng.normal(0, 0.05, 2)
+    K2, b2 = rng.normal(0, 0.05, (3, Ci, k, k)), rng.normal(0, 0.05, 3)
+    srv = vr.Server(g, 64 << 30, max_batch=4)
+    s1, s2 = srv.register_session(gk), srv.register_session(gk2)
+    m1 = srv.register_conv_model(Ci, h, w, pad, K1, b1, s, square=True)
+    m2 = srv.register_conv_model(Ci, h, w, pad, K2, b2, s, square=False)
+    X0 = rng.uniform(0, 1, (B, Ci, h, w))
+    ocols = Ly.encrypt_image_columns(o, ok, X0, pad, 3, 4100, 0)
+    batch = [(s1, gk, m1, K1, b1, True, [to_gpu(g, c) for c in ocols])]
+    plan = [(s1, gk, m1, K1, b1, True)] * 3 + [(s2, gk2, m1, K1, b1, True)] * 2 + \
+           [(s1, gk, m2, K2, b2, False)] * 2
+    for n, (sess, keys, model, K, bias, sq) in enumerate(plan):
+        X = rng.uniform(0, 1, (B, Ci, h, w))
+        batch.append((sess, keys, model, K, bias, sq, g.encrypt_columns(keys, X, pad, 3, 4200 + n, 0)))
+    reqs = [(srv.submit(sess, model, cols, B), keys, model, K, bias, sq, cols)
+            for sess, keys, model, K, bias, sq, cols in batch]
+    outs = [srv.poll(r[0], r[2]) for r in reqs]
+    st = srv.stats()
+    srv.close()
+    assert st["completed"] == len(reqs)
+    for (t, keys, model, K, bias, sq, cols), got in zip(reqs, outs):
+        y = g.conv2d(keys, cols, Ci, h, w, pad, K, bias, s)
+        ref = g.square(keys, y) if sq else y
+        assert len(got) == len(ref)
+        for j, (a, b) in enumerate(zip(got, ref)):
+            same_limbs(a, b, "N=2^16 ticket %d out %d" % (t, j))
+    Y = Ly.conv2d(o, ok, ocols, Ci, h, w, pad, K1, b1, 2, k, s)
+    for j, y in enumerate(Y):
+        assert_same(outs[0][j], Ly.square(o, ok, y), "N=2^16 served vs oracle %d" % j)

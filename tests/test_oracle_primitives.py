@@ -315,3 +315,85 @@ def test_automorphism_is_ring_homomorphism():
     x[1] = 1
     y = ctx.automorphism(x, g, q)
     assert int(y[g]) == 1 and int(y.sum()) == 1
+
+
+# ------------------------------------------------- add, sub and level drop
+
+def _lift(ct_c, k, t, moduli):
+    return _crt([ct_c[k, i, t] for i in range(len(moduli))], moduli)
+
+
+def test_add_sub_are_big_integer_add_sub():
+    """Add and Sub act limb-wise; through the CRT they must be addition and
+    subtraction of the lifted integers modulo Q (a missing third component
+    counts as zero).  Residues include 0 and q - 1."""
+    from oracle import Ciphertext
+    ctx = Context(Params(3, [60, 50, 50, 40], [51], 4, 30.0, allow_insecure=True))
+    rng = np.random.default_rng(11)
+    lv = 3
+    qs = ctx.q[:lv + 1]
+
+    def rand_ct(ncomp):
+        c = np.stack([np.stack([rng.integers(0, q, ctx.n, dtype=np.uint64) for q in qs])
+                      for _ in range(ncomp)])
+        for k in range(ncomp):
+            for i, q in enumerate(qs):
+                c[k, i, 0], c[k, i, 1] = 0, q - 1
+        return Ciphertext(c, lv, 2.0 ** 30)
+
+    a, b3 = rand_ct(2), rand_ct(3)
+    s_ab, d_ab, d_ba = ctx.add(a, b3), ctx.sub(a, b3), ctx.sub(b3, a)
+    assert s_ab.ncomp == d_ab.ncomp == d_ba.ncomp == 3
+    for k in range(3):
+        for t in range(ctx.n):
+            X, Q = _lift(a.c, k, t, qs) if k < 2 else (0, None)
+            Y, Q = _lift(b3.c, k, t, qs)
+            assert _lift(s_ab.c, k, t, qs)[0] == (X + Y) % Q
+            assert _lift(d_ab.c, k, t, qs)[0] == (X - Y) % Q
+            assert _lift(d_ba.c, k, t, qs)[0] == (Y - X) % Q
+
+
+def test_mod_drop_keeps_the_decrypted_message():
+    """Dropping to level l' keeps the residues mod q_0..q_l': the decryption
+    at l' is the same small integer polynomial (message plus noise) as at l,
+    so its centred lift mod Q_l' equals the centred lift mod Q_l."""
+    ctx = Context(Params(5, [60, 40, 40, 40, 40], [60], 5, 30.0, allow_insecure=True))
+    keys = ctx.keygen(21)
+    z = np.random.default_rng(12).uniform(-1, 1, ctx.slots)
+    ct = ctx.encrypt(keys, ctx.encode(z, 4, ctx.scale), 21, 3)
+
+    def centred(pt, level):
+        out = []
+        for t in range(ctx.n):
+            X, Q = _crt([pt.m[i, t] for i in range(level + 1)], ctx.q[:level + 1])
+            out.append(X - Q if X > Q // 2 else X)
+        return out
+
+    full = centred(ctx.decrypt(keys, ct), 4)
+    assert max(abs(v) for v in full) > 2 ** 20          # a real message, not noise
+    for lv in (3, 1, 0):
+        d = ctx.mod_drop(ct, lv)
+        assert d.level == lv and d.scale == ct.scale and d.c.shape == (2, lv + 1, ctx.n)
+        assert centred(ctx.decrypt(keys, d), lv) == full
+    with pytest.raises(ValueError):
+        ctx.mod_drop(ctx.mod_drop(ct, 1), 2)
+
+
+def test_stream_key_is_the_256_bit_seed():
+    """All 32 key bytes come from the seed: the key words are the seed's
+    little-endian 32-bit words, so seeds that differ only above bit 64 give
+    different streams, and a seed below 2^64 keys with 24 zero bytes."""
+    ctx = Context(PRESETS["C1"])
+    pur, obj = 3, 77
+    nonce = np.array([pur, obj, 0], dtype=np.uint32)
+    for seed in (0x1122334455667788, (0xdeadbeef << 200) | (7 << 64) | 5, (1 << 256) - 1):
+        words = ctx.stream_words(seed, pur, obj, 0, 8)
+        key = np.array([(seed >> (32 * i)) & 0xffffffff for i in range(8)], dtype=np.uint32)
+        out = np.zeros(16, dtype=np.uint32)
+        lib.orc_chacha20_block(ptr(key), 0, ptr(nonce), ptr(out))
+        assert [int(w) for w in words] == [int(out[2 * j]) | (int(out[2 * j + 1]) << 32) for j in range(8)]
+    a = ctx.stream_words(5, pur, obj, 0, 8)
+    b = ctx.stream_words(5 | (1 << 192), pur, obj, 0, 8)
+    assert not np.array_equal(a, b)
+    with pytest.raises(ValueError):
+        ctx.stream_words(1 << 256, pur, obj, 0, 8)

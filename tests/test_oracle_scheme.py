@@ -355,6 +355,14 @@ def test_conv_schedule_random_square_fc(ctx10):
     Z = Ly.fc(ctx, keys, Y2, pts, fb, Hp)
     logits = Ly.fc_decode(ctx, keys, Z, B, Hp)
     assert Ly.rel_error(logits, Ly.ref_fc(ref ** 2, W, fb)) < EPS
+    # weights one level below the inputs (conv outputs at level 2, weights at
+    # level 1): the layer runs at the weights' level and still decodes to the
+    # FP64 FC of the conv outputs
+    assert Y[0].level == 2
+    pts1 = Ly.fc_plaintexts(ctx, W, Co, ho, wo, s, Hp, 1)
+    Z1 = Ly.fc(ctx, keys, Y, pts1, fb, Hp)
+    assert Z1[0].level == 0
+    assert Ly.rel_error(Ly.fc_decode(ctx, keys, Z1, B, Hp), Ly.ref_fc(ref, W, fb)) < EPS
 
 
 def test_conv_special_cases(ctx10):
