@@ -1,19 +1,22 @@
 #!/usr/bin/env python3
-"""Throughput benchmark of the encrypted column-wise conv layer on one MI355X.
+"""Throughput benchmark of column-wise encrypted CNN inference on one MI355X.
 
-Workload (one step): the 28x28 single-channel conv layer with x^2 activation
-on `--sets` full ciphertext sets of 256 images each (images in 32-slot blocks
-of the 28 column ciphertexts at N = 2^14, L = 7, 60/40-bit primes), 5 filters
-4x4 stride 2, followed by the square activation: per set 84 rotations, 1,040
-MulConst, 65 rescales, 65 tensor + relinearise + rescale.  Inputs are
-encrypted before the timed region and stay resident in HBM; the timed region
-is the server-side evaluation only.
+Workload (one step): the 3x128x128 network at N = 2^16 (L = 24 chain of
+60 + 24x50-bit primes, 9 special primes of 51 bits, dnum 3) on one set of 128
+images, each image channel held as 128 column ciphertexts (384 per set), the
+ciphertexts entering at level 24 (the full chain): conv 3x3 stride 2 pad 1
+with 8 filters (768 hoisted rotations, 13,752 MulConst), x^2 (512 tensor +
+relinearisation + rescale), FC 8*64*64 -> 10 (5,120 MulPlain at the weights'
+level 1, 80 rotations), as one whole-network call.  Inputs are encrypted
+before the timed region and stay resident in HBM; the timed region is the
+server-side evaluation only.
 
-The JSON line adds the plain per-operation path (one C-ABI call per HE
-operation), HE rotations/s at N = 2^16 (L = 24 and a 4-limb level, batched
-with a shared key versus per operation), per-step latency percentiles, the
-live roofline of the dominant kernel (HIP events around its launches inside
-the timed region) and the CPU oracle timed on a bounded sample.
+The JSON line adds the same step as one replayed HIP graph and as one C-ABI
+call per HE operation, the network entering at level 3 (trimmed), the 28x28
+conv layer at N = 2^14, the 16x16 matrix product at N = 2^13, HE rotations/s
+at N = 2^16, serving and uneven batches, the live roofline of the step's
+dominant kernel (HIP events around its launches inside the timed region) and
+the CPU oracle timed on a bounded sample on one and on all host cores.
 """
 import argparse
 import json
@@ -35,36 +38,50 @@ FP64_BFLY_OPS = 8                          # y*w, fma, *1/q, rint, fma, +e, X+T,
 NTT_PEAK_TBFLY = VALU_LANE_OPS / FP64_BFLY_OPS / 1e12
 
 
-def ntt_roofline(cls, prof_ms, launches, units, total_s, log_n=14):
-    """Roofline of the dominant kernel (the NTT): butterflies per launch over
-    the live average launch time, against the FP64-butterfly VALU ceiling;
-    HBM traffic per launch from the counter file while the kernel source is
-    unchanged since it was measured."""
-    if cls != "ntt" or prof_ms <= 0 or launches == 0:
+def ntt_roofline(prof_ms, calls, limbs, total_s, log_n, counter_name=None):
+    """Roofline of the NTT class (the dominant kernel of the step).  One call
+    transforms `limbs / calls` limbs (at N = 2^15 and 2^16 as two kernel
+    launches, pass 0 and pass 1).  Algorithmic bytes: 16N per limb (each word
+    read and written once); operations: N/2 log2 N butterflies per limb at
+    FP64_BFLY_OPS lane operations each.  Both floors are computed per call and
+    the larger one names the bound; `achieved` is against that bound's peak.
+    `traffic`: HBM bytes per call from the FETCH_SIZE / WRITE_SIZE counter
+    file in profiles/, while the kernel source is unchanged since it was
+    measured (else null)."""
+    if prof_ms <= 0 or calls == 0:
         return None
-    import hashlib
     n = 1 << log_n
-    avg_s = prof_ms / launches / 1e3
-    limbs_per_launch = units / launches
-    bfly = limbs_per_launch * (n // 2) * log_n
-    achieved = bfly / avg_s / 1e12
+    avg_s = prof_ms / calls / 1e3
+    per_call = limbs / calls
+    alg_bytes = 16 * n * per_call
+    bfly = per_call * (n // 2) * log_n
+    hbm_floor_s = alg_bytes / (HBM_PEAK_GBS * 1e9)
+    alu_floor_s = bfly * FP64_BFLY_OPS / VALU_LANE_OPS
     traffic = None
-    try:
-        with open(os.path.join(ROOT, "profiles", "ntt_hbm_counters.json")) as f:
-            cnt = json.load(f)
-        with open(os.path.join(ROOT, "paper_2512_18646_amd", "csrc", "ntt.hip"), "rb") as f:
-            same = hashlib.sha256(f.read()).hexdigest().startswith(cnt["ntt_source_sha256_prefix"])
-        if same:
-            traffic = round((cnt["read_bytes_per_limb"] + cnt["write_bytes_per_limb"]) * limbs_per_launch)
-    except (OSError, KeyError, ValueError):
-        traffic = None
-    alg_gbs = 16 * n * limbs_per_launch / avg_s / 1e9
-    return {"bound": "alu", "kernel": "ntt", "achieved": round(achieved, 3), "peak": round(NTT_PEAK_TBFLY, 3),
-            "unit": "Tbutterfly/s", "frac": round(achieved / NTT_PEAK_TBFLY, 4), "traffic": traffic,
-            "traffic_unit": "bytes/launch", "algorithmic_bytes_per_launch": round(16 * n * limbs_per_launch),
-            "hbm_algorithmic_gbs": round(alg_gbs, 1), "hbm_frac_of_8000": round(alg_gbs / HBM_PEAK_GBS, 4),
-            "avg_launch_us": round(avg_s * 1e6, 2), "launches": launches, "limbs": units,
-            "share_of_step": round(prof_ms / (total_s * 1e3), 3)}
+    cnt = counter_file(counter_name, ("ntt.hip",)) if counter_name else None
+    if cnt:
+        traffic = round((cnt["read_bytes_per_limb"] + cnt["write_bytes_per_limb"]) * per_call)
+    hbm_gbs = alg_bytes / avg_s / 1e9
+    alu_t = bfly / avg_s / 1e12
+    out = {"kernel": "ntt", "traffic": traffic, "traffic_unit": "bytes/call",
+           "algorithmic_bytes_per_call": round(alg_bytes), "butterflies_per_call": round(bfly),
+           "hbm_floor_us_per_call": round(hbm_floor_s * 1e6, 2), "alu_floor_us_per_call": round(alu_floor_s * 1e6, 2),
+           "avg_call_us": round(avg_s * 1e6, 2), "calls": calls, "kernel_launches_per_call": 2 if log_n > 14 else 1,
+           "limbs": limbs, "share_of_step": round(prof_ms / (total_s * 1e3), 3),
+           "hbm_algorithmic_gbs": round(hbm_gbs, 1), "alu_tbutterfly_per_s": round(alu_t, 3),
+           "alu_frac": round(alu_t / NTT_PEAK_TBFLY, 4)}
+    if hbm_floor_s >= alu_floor_s:
+        out.update({"bound": "hbm", "achieved": round(hbm_gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": round(hbm_gbs / HBM_PEAK_GBS, 4)})
+    else:
+        out.update({"bound": "alu", "achieved": round(alu_t, 3), "peak": round(NTT_PEAK_TBFLY, 3),
+                    "unit": "Tbutterfly/s", "frac": round(alu_t / NTT_PEAK_TBFLY, 4)})
+    if traffic:
+        out["counter_gbs"] = round(traffic / avg_s / 1e9, 1)
+        out["counter_frac"] = round(traffic / avg_s / 1e9 / HBM_PEAK_GBS, 4)
+    # the fixed key order of the contract first
+    return {k: out[k] for k in ("bound", "achieved", "peak", "unit", "frac", "traffic")} | \
+        {k: v for k, v in out.items() if k not in ("bound", "achieved", "peak", "unit", "frac", "traffic")}
 
 
 def log_free(tag):
@@ -728,6 +745,311 @@ def convert_compare(ctx, keys, cts, level, reps):
     return res
 
 
+def cnn128_setup(vr, level_in, sets, fc_level=1, ntt_plan="auto"):
+    """The 3x128x128 network at N = 2^16 (60 + 24x50, P 9x51, dnum 3): keys,
+    `sets` encrypted 128-image sets (384 column ciphertexts each) entering at
+    level_in, and the network (conv 3x3/2 pad 1 x8, x^2, FC 8*64*64 -> 10 with
+    its weights encoded at fc_level, the level the FC runs at)."""
+    import synthetic_inputs as SI
+    W = SI.CNN_128
+    ctx = vr.Context(16, [60] + [50] * 24, [51] * 9, 3, 50.0)
+    if ntt_plan != "auto":
+        ctx.set_tuning("ntt", ntt_plan)
+    Hp = 1 << (W.h + 2 * W.pad - 1).bit_length()
+    steps = sorted(set(range(1, W.k)) | {1 << t for t in range(Hp.bit_length() - 1)})
+    keys = ctx.keygen(1003, rot_steps=steps)
+    X0, K, bias = W.draw()
+    Wfc, bfc = W.draw_fc()
+    Xs = [X0] + [SI.images(W.seed + 1000 * i, W.batch, W.channels, W.h, W.w) for i in range(1, sets)]
+    cols = [ctx.encrypt_columns(keys, X, W.pad, level_in, 1003, 10000 * i) for i, X in enumerate(Xs)]
+    W_pt = ctx.encode_fc_weights(Wfc, W.stride, Hp, min(fc_level, level_in - 2))
+    net = vr.CNN(W.channels, W.h, W.w, W.pad, K, bias, W.stride, square=True, fc_w=W_pt, fc_bias=bfc,
+                 fc_block=Hp)
+    return {"W": W, "ctx": ctx, "keys": keys, "X0": X0, "K": K, "bias": bias, "Wfc": Wfc, "bfc": bfc,
+            "W_pt": W_pt, "Hp": Hp, "cols": cols, "net": net}
+
+
+def cnn128_logit_error(C, z):
+    """Decoded logits of set 0 against the FP64 plaintext network."""
+    W, ctx, keys = C["W"], C["ctx"], C["keys"]
+    logits = np.zeros((W.batch, len(z)))
+    for o, ct in enumerate(z):
+        logits[:, o] = ctx.decode(ctx.decrypt(keys, ct))[np.arange(W.batch) * C["Hp"]]
+    ref = plain_conv_sq_fc(C["X0"], C["K"], C["bias"], W.stride, W.pad, C["Wfc"], C["bfc"])
+    return float(np.max(np.abs(logits - ref)) / np.max(np.abs(ref)))
+
+
+def headline_extras(vr, perop, C, args, ref, images):
+    """The headline step as one replayed HIP graph and as one C-ABI call per
+    HE operation (first set), limbs against the whole-network call."""
+    ctx, keys, net, W = C["ctx"], C["keys"], C["net"], C["W"]
+    flat = [c for cs in C["cols"] for c in cs]
+    res = {}
+    ctx.trim()
+    gr = vr.Graph(ctx, keys, net, flat, n_sets=len(C["cols"]))
+    gr.launch()
+    sync()
+    glat = []
+    t = time.perf_counter()
+    for _ in range(max(2, args.steps // 4)):
+        t1 = time.perf_counter()
+        gr.launch()
+        sync()
+        glat.append((time.perf_counter() - t1) * 1e3)
+    g_total = time.perf_counter() - t
+    gout = gr.outputs()
+    res["graph"] = {"images_per_s": round(images * len(glat) / g_total, 2),
+                    "ms_per_step_p50": round(percentile(glat, 50), 2),
+                    "identical": bool(all(np.array_equal(gout[i].export(), ref[i]) for i in range(len(ref))))}
+    del gout
+    gr.close()
+    ctx.trim()
+    t = time.perf_counter()
+    y = perop.square(ctx, keys, perop.conv2d(ctx, keys, C["cols"][0], W.channels, W.h, W.w, W.pad, C["K"],
+                                             C["bias"], W.stride))
+    zp = perop.fc(ctx, keys, y, C["W_pt"], C["bfc"], C["Hp"])
+    sync()
+    t_op = time.perf_counter() - t
+    res["per_op"] = {"images_per_s": round(W.batch / t_op, 2),
+                     "identical": bool(all(np.array_equal(zp[i].export(), ref[i]) for i in range(len(ref))))}
+    del y, zp
+    return res
+
+
+def matmul16_bench(vr, perop, reps=20):
+    """The 16x16 by 16x16 encrypted product at N = 2^13 (49 + 3x40, P 49,
+    dnum 4): 16 + 16 column ciphertexts at level 3, one vr_matmul call per
+    product (240 rotations hoisted over 16 ModUps, 256 tensors, 16
+    relinearisations); latency p50/p99 over `reps` calls, the per-op path, and
+    the decoded error against FP64."""
+    import synthetic_inputs as SI
+    seed, m, n, p = SI.MATMUL_16
+    ctx = vr.Context(13, [49, 40, 40, 40], [49], 4, 40.0)
+    keys = ctx.keygen(1001, rot_steps=list(range(1, 16)))
+    A, B = SI.matmul_operands(seed, m, n, p)
+    Ac = ctx.encrypt_matrix_columns(keys, A, 0, m, p, 3, 1001, 0)
+    Bc = ctx.encrypt_matrix_columns(keys, B, 1, m, p, 3, 1001, 1 << 20)
+    D = ctx.matmul(keys, Ac, Bc, m, n, p)
+    sync()
+    lat = []
+    for _ in range(reps):
+        t = time.perf_counter()
+        D = ctx.matmul(keys, Ac, Bc, m, n, p)
+        sync()
+        lat.append((time.perf_counter() - t) * 1e3)
+    C = np.full((m, p), np.nan)
+    for idx, ct in enumerate(D):
+        z = ctx.decode(ctx.decrypt(keys, ct), m)
+        for i in range(m):
+            C[i, (i + idx) % 16] = z[i]
+    err = float(np.max(np.abs(C - A @ B)) / np.max(np.abs(A @ B)))
+    t = time.perf_counter()
+    Dp = perop.matmul(ctx, keys, Ac, Bc, m, n, p)
+    sync()
+    t_op = (time.perf_counter() - t) * 1e3
+    same = all(np.array_equal(x.export(), y.export()) for x, y in zip(D, Dp))
+    return {"workload": "A(16x16) B(16x16), 16 + 16 column ciphertexts, N=2^13 (49+3x40, P 49, dnum 4), level 3",
+            "latency_ms_p50": round(percentile(lat, 50), 3), "latency_ms_p99": round(percentile(lat, 99), 3),
+            "per_op_ms": round(t_op, 2), "per_op_identical": bool(same), "decoded_rel_error": err}
+
+
+def conv28_bench(vr, perop, args):
+    """The 28x28 conv + x^2 layer at N = 2^14, L = 7 on 4 sets of 256 images
+    per step (multi-set conv call + batched x^2), its graph replay, the per-op
+    path on one set, and the live roofline of its NTT class."""
+    W, ctx, keys, K, bias, cols = conv_setup(vr, 7, 4, args.ntt_plan)
+    images = W.batch * len(cols)
+    for _ in range(2):
+        step_batched(ctx, keys, W, K, bias, cols)
+    sync()
+    steps = max(5, args.steps // 2)
+    ctx.profile_start("ntt", 1 << 18)
+    sync()
+    t = time.perf_counter()
+    for _ in range(steps):
+        y = step_batched(ctx, keys, W, K, bias, cols)
+        del y
+    sync()
+    total = time.perf_counter() - t
+    ms, la, un, _ = ctx.profile_stop()
+    res = {"workload": "conv 28x28 4x4/2 x5 + x^2, 4 sets of 256 images per step, N=2^14 L=7 (60+7x40, P 60, "
+                       "dnum 8)", "images_per_s": round(images * steps / total, 2),
+           "ms_per_step": round(total / steps * 1e3, 3),
+           "roofline_ntt": ntt_roofline(ms, la, un, total, 14, "ntt_hbm_counters.json")}
+    net = vr.CNN(W.channels, W.h, W.w, W.pad, K, bias, W.stride, square=True)
+    flat = [c for cs in cols for c in cs]
+    gr = vr.Graph(ctx, keys, net, flat, n_sets=len(cols))
+    gr.launch()
+    sync()
+    t = time.perf_counter()
+    for _ in range(steps):
+        gr.launch()
+    sync()
+    g_total = time.perf_counter() - t
+    ref = step_batched(ctx, keys, W, K, bias, cols[:1])
+    gout = gr.outputs()
+    res["graph"] = {"images_per_s": round(images * steps / g_total, 2),
+                    "identical": bool(all(np.array_equal(gout[i].export(), ref[i].export()) for i in range(len(ref))))}
+    gr.close()
+    del gout
+    t = time.perf_counter()
+    ys = perop.square(ctx, keys, perop.conv2d(ctx, keys, cols[0], W.channels, W.h, W.w, W.pad, K, bias, W.stride))
+    sync()
+    t_op = time.perf_counter() - t
+    res["per_op"] = {"images_per_s": round(W.batch / t_op, 2),
+                     "identical": bool(all(np.array_equal(ys[i].export(), ref[i].export()) for i in range(len(ref))))}
+    res["batched_over_per_op"] = round(res["images_per_s"] / res["per_op"]["images_per_s"], 2)
+    return res
+
+
+# ------------------------------------------------------------ CPU oracle leg
+#
+# The oracle runs in a child process that never loads the GPU runtime, so it
+# can fork worker processes for the all-core run.
+
+def host_info():
+    try:
+        ncpu = len(os.sched_getaffinity(0))
+    except AttributeError:
+        ncpu = os.cpu_count()
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": ncpu, "cpu_count": os.cpu_count(), "model": model}
+
+
+_ORC = {}
+
+
+def _orc_c3_sample(_=None):
+    """One sample of every operation class of the C3 network step, on the
+    oracle (keys and inputs prepared before the fork): seconds per class."""
+    o, ok, cts = _ORC["o"], _ORC["ok"], _ORC["cts"]
+    t = {}
+    t0 = time.perf_counter()
+    o.rotate(cts[24], 1, ok)
+    t["rot24"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    acc = None
+    dq = float(o.q[24])
+    for r in range(6):
+        x = o.mul_const(cts[24], 0.01 * (r + 1), dq)
+        acc = x if acc is None else o.add(acc, x)
+    t["mulconst_add24"] = (time.perf_counter() - t0) / 6
+    t0 = time.perf_counter()
+    y = o.rescale(o.add_const(acc, 0.5))
+    t["addconst_rescale24"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o.rescale(o.relinearize(o.tensor(y, y), ok))
+    t["square23"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    acc = None
+    for r in range(6):
+        x = o.mul_plain(cts[1], _ORC["pt1"])
+        acc = x if acc is None else o.add(acc, x)
+    t["mulplain_add1"] = (time.perf_counter() - t0) / 6
+    t0 = time.perf_counter()
+    z = o.rescale(acc)
+    t["rescale1"] = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    o.add(z, o.rotate(z, 1, ok))
+    t["rot_add0"] = time.perf_counter() - t0
+    return t
+
+
+# operation counts of one 128-image set of the C3 network entering at level 24
+C3_OPS = {"rot24": 768, "mulconst_add24": 13752, "addconst_rescale24": 512, "square23": 512,
+          "mulplain_add1": 5120, "rescale1": 10, "rot_add0": 80}
+
+
+def cpu_oracle_child():
+    """Runs in a fresh process: the oracle's C3 network step (single core and
+    on every host core), C1 whole, the C2 sample, NTT per limb.  Prints JSON."""
+    import multiprocessing as mp
+    from oracle import Context as OC, PRESETS
+    from oracle import layers as Ly
+    import synthetic_inputs as SI
+    res = {"host": host_info()}
+    # C3 at level 24 (keys, two input ciphertexts at levels 24 and 1, one FC
+    # weight plaintext at level 1)
+    t0 = time.perf_counter()
+    o = OC(PRESETS["C3"])
+    ok = o.keygen(1003, rot_steps=[1])
+    z = np.random.default_rng(3).uniform(0, 1, o.slots)
+    _ORC.update(o=o, ok=ok, cts={24: o.encrypt(ok, o.encode(z, 24, o.scale), 1003, 0),
+                                 1: o.encrypt(ok, o.encode(z, 1, o.scale), 1003, 1)},
+                pt1=o.encode(z * 0.01, 1, float(o.q[1])))
+    setup = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    one = _orc_c3_sample()
+    t_one = time.perf_counter() - t0
+    s_set = sum(C3_OPS[k] * one[k] for k in C3_OPS)
+    cores = max(1, min(16, res["host"]["nproc"] or 1))
+    ctxmp = mp.get_context("fork")
+    t0 = time.perf_counter()
+    with ctxmp.Pool(cores) as pool:
+        samples = pool.map(_orc_c3_sample, range(cores))
+    t_all = time.perf_counter() - t0
+    # all-core throughput: cores samples in t_all seconds, each sample standing
+    # for sample_weight of a set
+    s_set_sample = sum(C3_OPS[k] * one[k] for k in C3_OPS)
+    w_sample = t_one / s_set_sample            # fraction of a set one sample represents
+    sets_per_s_all = cores * w_sample / t_all
+    res["c3_level24"] = {
+        "single_core_images_per_s": round(128 / s_set, 5),
+        "all_core_images_per_s": round(128 * sets_per_s_all, 5), "cores": cores,
+        "seconds_per_op_single_core": {k: round(v, 4) for k, v in one.items()},
+        "op_counts_per_set": C3_OPS, "extrapolated": True,
+        "sample": "one of each operation class of the 128-image C3 set at level 24 (1 rotation at level 24, 6 "
+                  "MulConst+Add, AddConst+Rescale, one x^2 at level 23, 6 MulPlain+Add at level 1, Rescale, "
+                  "rotate+add at level 0), %.1f s on one core, scaled by the set's operation counts; all-core: "
+                  "the same sample on %d processes at once (%.1f s wall)" % (t_one, cores, t_all),
+        "setup_s": round(setup, 1)}
+    del samples
+    # C1 whole: 16x16 product at N = 2^13
+    oc = OC(PRESETS["C1"])
+    okc = oc.keygen(1001, rot_steps=list(range(1, 16)))
+    seed, m, n, p = SI.MATMUL_16
+    A, B = SI.matmul_operands(seed, m, n, p)
+    Ac = Ly.encrypt_matrix_columns(oc, okc, A, 0, m, p, 3, 1001, 0)
+    Bc = Ly.encrypt_matrix_columns(oc, okc, B, 1, m, p, 3, 1001, 1 << 20)
+    t0 = time.perf_counter()
+    Ly.matmul(oc, okc, Ac, Bc, m, n, p)
+    res["c1_matmul16"] = {"seconds": round(time.perf_counter() - t0, 3), "cores": 1,
+                          "sample": "the whole product (240 rotations, 256 tensors, 16 relinearisations)"}
+    # NTT of one limb
+    ntt = {}
+    for name, pre in (("2^13", "C1"), ("2^14", "C2"), ("2^16", "C3")):
+        oo = oc if pre == "C1" else (o if pre == "C3" else OC(PRESETS[pre]))
+        q = oo.q[1]
+        a = np.random.default_rng(9).integers(0, q, oo.n, dtype=np.uint64)
+        reps = 40 if pre != "C3" else 10
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            oo.ntt(a, q)
+        ntt[name] = {"us_per_limb": round((time.perf_counter() - t0) / reps * 1e6, 1), "cores": 1}
+    res["ntt_per_limb"] = ntt
+    res["c2_conv28"] = cpu_baseline(7, out_cols=(0, 6, 12))
+    res["c2_conv28"]["value"] = round(res["c2_conv28"]["value"], 4)
+    print(json.dumps(res), flush=True)
+
+
+def cpu_oracle_leg(timeout=900):
+    """The oracle legs in a child process (see cpu_oracle_child)."""
+    import subprocess
+    r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-oracle-child"], capture_output=True,
+                       text=True, timeout=timeout, cwd=ROOT)
+    if r.returncode != 0:
+        raise RuntimeError("oracle child failed: " + r.stderr[-2000:])
+    return json.loads(r.stdout.strip().splitlines()[-1])
+
+
 def cpu_rotations_n16(counts=((24, 2), (3, 4))):
     """The oracle's one-slot rotation at N = 2^16 (60 + 24x50, P 9x51, dnum 3)
     on one host core: `count` rotations per level, timed after key
@@ -799,10 +1121,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--sets", type=int, default=4, help="256-image ciphertext sets per step")
-    ap.add_argument("--level", type=int, default=7, help="level of the fresh ciphertexts (7 = full)")
+    ap.add_argument("--sets", type=int, default=1, help="128-image ciphertext sets per step")
+    ap.add_argument("--level", type=int, default=24, help="level of the fresh ciphertexts (24 = full chain)")
     ap.add_argument("--profile-class", default="ntt")
-    ap.add_argument("--no-extra", action="store_true", help="skip per-op, rotation and CPU legs")
+    ap.add_argument("--no-extra", action="store_true", help="only the headline step")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-cnn", action="store_true")
@@ -815,16 +1137,19 @@ def main():
     ap.add_argument("--serve-load", default="0.8,2.0",
                     help="offered loads, as fractions of the one-request-at-a-time service rate")
     ap.add_argument("--ntt-plan", default="auto",
-                    help="NTT pass plan of the main workload: auto (autotuned), fixed, or cand:i "
-                         "(pins the plan, e.g. for counter runs)")
+                    help="NTT pass plan of the N=2^14 leg: auto (autotuned), fixed, or cand:i")
     ap.add_argument("--ntt-plan-n16", default="auto",
-                    help="NTT pass plan of the N=2^16 rotation legs: auto or cand:i (cand:11 = the "
-                         "compile-time two-pass kernels with 16-column tiles)")
+                    help="NTT pass plan of the N=2^16 legs: auto or cand:i (pins the plan, e.g. for counter "
+                         "runs)")
     ap.add_argument("--rotations-only", action="store_true",
                     help="only the N=2^16 rotation leg (for profiling its kernels)")
     ap.add_argument("--breakdown", action="store_true",
-                    help="one extra step per kernel class, reporting its device time per step")
+                    help="one extra headline step per kernel class, reporting its device time per step")
+    ap.add_argument("--cpu-oracle-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    if args.cpu_oracle_child:
+        cpu_oracle_child()
+        return
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X "
               "(sharding over several GPUs is not implemented)", file=sys.stderr)
@@ -845,136 +1170,136 @@ def main():
                                        "level3": rotations_bench(vr, 3, 32, args.steps, args.ntt_plan_n16)}}
         print(json.dumps(out), flush=True)
         return
-    log("setup: encrypting %d sets of 256 images at level %d" % (args.sets, args.level))
-    W, ctx, keys, K, bias, cols = conv_setup(vr, args.level, args.sets, args.ntt_plan)
-    images = W.batch * args.sets
 
+    # ------------------------------------------------ headline: C3 network
+    log("setup: keys and %d set(s) of 128 3x128x128 images at level %d, N=2^16" % (args.sets, args.level))
+    t0 = time.perf_counter()
+    C = cnn128_setup(vr, args.level, args.sets, ntt_plan=args.ntt_plan_n16)
+    ctx, keys, net, W = C["ctx"], C["keys"], C["net"], C["W"]
+    flat = [c for cs in C["cols"] for c in cs]
+    images = W.batch * args.sets
+    sync()
+    setup_s = time.perf_counter() - t0
+
+    def step():
+        return net.forward(ctx, keys, flat, n_sets=args.sets)
+
+    z = step()
+    sync()
+    err = cnn128_logit_error(C, z[:W.fc_out])
+    ref = [c.export() for c in z[:W.fc_out]]
+    del z
     for i in range(args.warmup):
-        step_batched(ctx, keys, W, K, bias, cols)
+        z = step()
         sync()
+        del z
         log("warmup %d done" % i)
     lat = []
-    ctx.profile_start(args.profile_class, 1 << 18)
+    ctx.profile_start(args.profile_class, 1 << 20)
     sync()
     t_all = time.perf_counter()
     for i in range(args.steps):
         t = time.perf_counter()
-        outs = step_batched(ctx, keys, W, K, bias, cols)
+        z = step()
         sync()
         lat.append((time.perf_counter() - t) * 1e3)
-        del outs
+        del z
     sync()
     total = time.perf_counter() - t_all
-    prof_ms, prof_launches, prof_units, dropped = ctx.profile_stop()
+    prof_ms, prof_calls, prof_units, dropped = ctx.profile_stop()
     log("timed %d steps: %.2f ms/step" % (args.steps, total / args.steps * 1e3))
     value = images * args.steps / total
-
-    roofline = ntt_roofline(args.profile_class, prof_ms, prof_launches, prof_units, total)
-    if roofline:
-        roofline["dropped"] = dropped
-
+    roofline = None
+    if args.profile_class == "ntt":
+        roofline = ntt_roofline(prof_ms, prof_calls, prof_units, total, 16, "ntt_n16_cnn128_hbm_counters.json")
+        if roofline:
+            roofline["dropped"] = dropped
     out = {"metric": METRIC, "value": round(value, 2), "unit": "images/s", "n_gpus": 1,
            "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(total / args.steps * 1e3, 3),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
            "data": "synthetic",
-           "config": {"workload": "conv 28x28 4x4/2 x5 + x^2, 256 images per set, N=2^14 L=7 (60+7x40, P 60, dnum 8)",
-                      "sets_per_step": args.sets, "images_per_step": images, "level_in": args.level,
-                      "path": "multi-set conv call + batched x^2"},
+           "config": {"workload": "3x128x128 images, conv 3x3/2 pad 1 x8 + x^2 + FC 32768->10, N=2^16 "
+                                  "(60+24x50, P 9x51, dnum 3), ciphertexts entering at level %d, %d x 128 "
+                                  "images per step" % (args.level, args.sets),
+                      "images_per_step": images, "level_in": args.level, "fc_level": 1,
+                      "path": "whole-network call (vr_cnn_forward)"},
            "latency_ms_p50": round(percentile(lat, 50), 3), "latency_ms_p99": round(percentile(lat, 99), 3),
-           "roofline": roofline}
-
+           "roofline": roofline, "decoded_rel_error": err, "setup_s": round(setup_s, 1)}
     out["autotuned"] = ctx.tuning_report().splitlines()
-
-    if not args.no_graph:
-        log("graph capture of the step")
-        net = vr.CNN(W.channels, W.h, W.w, W.pad, K, bias, W.stride, square=True)
-        flat = [c for cs in cols for c in cs]
-        gr = vr.Graph(ctx, keys, net, flat, n_sets=len(cols))
-        for _ in range(args.warmup):
-            gr.launch()
-        sync()
-        glat = []
-        t_g = time.perf_counter()
-        for i in range(args.steps):
-            t = time.perf_counter()
-            gr.launch()
-            sync()
-            glat.append((time.perf_counter() - t) * 1e3)
-        g_total = time.perf_counter() - t_g
-        ref = step_batched(ctx, keys, W, K, bias, cols[:1])
-        gout = gr.outputs()
-        out["graph"] = {"images_per_s": round(images * args.steps / g_total, 2),
-                        "ms_per_step": round(g_total / args.steps * 1e3, 3),
-                        "latency_ms_p50": round(percentile(glat, 50), 3),
-                        "latency_ms_p99": round(percentile(glat, 99), 3),
-                        "identical": bool(all(np.array_equal(gout[i].export(), ref[i].export())
-                                              for i in (0, 33, 64)))}
-        gr.close()
-        del gout, ref
 
     if args.breakdown:
         bd = {}
         for cls in ("ntt", "ks_inner", "base_convert", "lincomb", "moddown", "tensor"):
-            ctx.profile_start(cls, 1 << 16)
-            step_batched(ctx, keys, W, K, bias, cols)
+            ctx.profile_start(cls, 1 << 20)
+            z = step()
             ms, la, un, _ = ctx.profile_stop()
+            del z
             bd[cls] = {"ms": round(ms, 3), "launches": la, "units": un}
         out["breakdown_per_step"] = bd
 
+    if not args.no_extra and not args.no_graph:
+        log("headline as a graph and per-op")
+        out.update(headline_extras(vr, perop, C, args, ref, images))
+        out["batched_over_per_op"] = round(value / out["per_op"]["images_per_s"], 2)
+    reserved, _ = ctx.mem_info()
+    out["device_gib_reserved"] = round(reserved / 2 ** 30, 1)
+    del C, ctx, keys, net, flat
+    import gc
+    gc.collect()
+
+    if not args.no_extra and not args.no_cnn:
+        log("cnn128 at level 3 (trimmed)")
+        log_free("before this leg")
+        out["cnn128_trimmed_n16"] = cnn128_bench(vr, 3, args.cnn_sets, 2, graph=True)
+        gc.collect()
+
     if not args.no_extra:
-        ctx.trim()
-        log_free("after the main step")
-        log("per-op path (one set)")
-        perop.square(ctx, keys, perop.conv2d(ctx, keys, cols[0], W.channels, W.h, W.w, W.pad, K, bias, W.stride))
-        sync()
-        t = time.perf_counter()
-        ys = perop.square(ctx, keys, perop.conv2d(ctx, keys, cols[0], W.channels, W.h, W.w, W.pad, K, bias,
-                                                  W.stride))
-        sync()
-        t_per_op = time.perf_counter() - t
-        ref = step_batched(ctx, keys, W, K, bias, cols[:1])
-        out["per_op_images_per_s"] = round(W.batch / t_per_op, 2)
-        out["per_op_identical"] = bool(all(np.array_equal(ys[i].export(), ref[i].export()) for i in (0, 33, 64)))
-        out["batched_over_per_op"] = round((W.batch * args.sets / (total / args.steps)) / (W.batch / t_per_op), 2)
-        del ys, ref
+        log("28x28 conv layer at N=2^14")
+        log_free("before this leg")
+        out["conv28_n14"] = conv28_bench(vr, perop, args)
+        gc.collect()
+        log("16x16 matmul at N=2^13")
+        out["matmul16_n13"] = matmul16_bench(vr, perop)
+        gc.collect()
         log("rotations at N=2^16")
         log_free("before this leg")
         out["rotations_per_s_n16"] = {"level24": rotations_bench(vr, 24, 8, 3),
                                       "level3": rotations_bench(vr, 3, 32, 3)}
         for v in out["rotations_per_s_n16"].values():
             v["batched"], v["per_op"] = round(v["batched"], 1), round(v["per_op"], 1)
+        gc.collect()
 
     if not args.no_extra and not args.no_serve:
-        log("serving (Poisson arrivals, image-size mix)")
-        out["serving"] = [serving_bench(vr, ctx, keys, args.serve_requests, float(x), args.level)
+        log("serving (Poisson arrivals, image-size mix) at N=2^14")
+        W2, ctx2, keys2, K2, bias2, _ = conv_setup(vr, 7, 0, args.ntt_plan)
+        out["serving"] = [serving_bench(vr, ctx2, keys2, args.serve_requests, float(x), 7)
                           for x in args.serve_load.split(",")]
-        # the N=2^14 context's allocator caches what its legs held (up to the
-        # serving budget): hand it back before the N=2^16 legs allocate
-        ctx.trim()
-        log_free("N=2^14 context trimmed")
+        del ctx2, keys2
+        gc.collect()
         log("serving at N=2^16")
+        log_free("before this leg")
         out["serving_n16"] = serving_n16_bench(vr)
-        log("serving done")
-
-    if not args.no_extra and not args.no_cnn:
-        for lv, sets in ((3, args.cnn_sets), (24, 1)):
-            log("cnn128 at level %d" % lv)
-            log_free("before this leg")
-            out.setdefault("cnn128_n16", []).append(cnn128_bench(vr, lv, sets, 2, graph=(lv == 3)))
+        gc.collect()
 
     if not args.no_extra and not args.no_uneven:
         log("uneven batch at N=2^16")
         log_free("before this leg")
         out["uneven_batch_n16"] = uneven_bench(vr, 64, 3, 2)
+        gc.collect()
         log("uneven batch at full size ranges (outer-product products)")
         log_free("before this leg")
         out["uneven_full_n16"] = uneven_full_bench(vr, 64, 3, 2)
-
+        gc.collect()
 
     if not args.no_extra and not args.no_cpu_baseline:
-        log("cpu baseline (oracle sample)")
-        out["cpu_baseline"] = cpu_baseline(args.level)
-        out["cpu_baseline"]["value"] = round(out["cpu_baseline"]["value"], 4)
+        log("cpu baseline (oracle, child process)")
+        cpu = cpu_oracle_leg()
+        c3 = cpu["c3_level24"]
+        out["cpu_baseline"] = {"value": c3["all_core_images_per_s"], "unit": "images/s", "cores": c3["cores"],
+                               "kind": "oracle", "sample": c3["sample"],
+                               "single_core_value": c3["single_core_images_per_s"], "host": cpu["host"],
+                               "extrapolated": True, "c3_level24": c3, "c1_matmul16": cpu["c1_matmul16"],
+                               "ntt_per_limb": cpu["ntt_per_limb"], "c2_conv28": cpu["c2_conv28"]}
         log("cpu baseline: oracle rotations at N=2^16")
         out["cpu_baseline"]["rotations_n16"] = cpu_rotations_n16()
     print(json.dumps(out), flush=True)

@@ -65,6 +65,10 @@ def fc(ctx, keys, Y, W_pt, bias, block, stream=None):
     per = len(Y)
     if per == 0 or len(W_pt) != len(bias) * per:
         raise ValueError("fc: %d weight plaintexts for %d outputs x %d inputs" % (len(W_pt), len(bias), per))
+    # weights encoded below the inputs' level: drop the inputs to it first
+    lv = W_pt[0].level
+    if Y[0].level > lv:
+        Y = [ctx.mod_drop(y, lv, stream=stream) for y in Y]
     out = []
     for o in range(len(bias)):
         acc = None
