@@ -239,6 +239,29 @@ vr_status vr_rotate_many(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphe
 vr_status vr_rotate_batch(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *in,
                           size_t n, int32_t step, vr_ciphertext **outs, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * rotation of vr_rotate, bit-identical to it, on a ciphertext given as device
+ * limbs.  in: device pointer to [2][level+1][N] uint64, c0 then c1, each limb
+ * i in the evaluation domain modulo q_i (the form ciphertext handles hold on
+ * the device: vr_ntt forward of the coefficient limbs vr_ct_export returns);
+ * out: device pointer to caller-owned memory of the same size and form, not
+ * overlapping in; the scale is the input's.  Every
+ * key-switching intermediate lives in one fixed device array of the library,
+ * VR_NOALLOC_SCRATCH_BYTES per GPU (held from the first context on that GPU
+ * to process exit); a level whose key switch needs more returns VR_EINVAL
+ * (the limit admits every level at N <= 2^14 and, at N = 2^16 with nine
+ * special primes and dnum 3, the whole L = 24 chain).  The call allocates
+ * nothing: the NTT plans and this level's base-conversion tables must exist
+ * already (else VR_EINVAL; one vr_rotate at the level builds them), and a
+ * missing rotation key is VR_ENOKEY.  Calls on one GPU share the array: calls
+ * that overlap in time on one GPU (different streams or threads) race; calls
+ * on one stream are ordered and safe.  Enqueued on `stream` (NULL = the
+ * context's) and returns without synchronising. */
+#define VR_NOALLOC_SCRATCH_BYTES (144ull << 20)
+vr_status vr_rotate_noalloc(vr_context *ctx, const vr_eval_keys *ek, const uint64_t *in, uint32_t level,
+                            int32_t step, uint64_t *out, void *stream);
+
 /* Column-split matrix product (abstract and contributions; "Homomorphic
  * Matrix Multiplication" with RowShifter reduced to one rotation and the
  * ciphertext-pair split of "Parallelized Matrix Multiplication"): from A_k,

@@ -8,6 +8,13 @@
 namespace vr {
 
 void build_context(vr_context* ctx, const vr_params* p, int device);
+
+// The no-allocation rotation's fixed device array (per GPU): its size, the
+// words a rotation at `level` takes from it, and its registration (device
+// address taken once per device, that device current).
+constexpr size_t kNoAllocScratchBytes = size_t(144) << 20;
+size_t noalloc_rotate_words(vr_context* ctx, u32 level);
+void noalloc_register_device(int device);
 void destroy_context_tables(vr_context* ctx);
 
 inline hipStream_t pick_stream(vr_context* ctx, void* s) { return s ? (hipStream_t)s : ctx->stream; }

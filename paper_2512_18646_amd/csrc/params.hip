@@ -10,7 +10,7 @@
 #include <cmath>
 #include <cstring>
 
-#include "vr_ops.h"
+#include "eval.h"
 
 namespace vr {
 
@@ -154,6 +154,7 @@ void build_context(vr_context* ctx, const vr_params* p, int device)
         throw Error(VR_EDEVICE, "no HIP device available");
     VR_HIP(hipSetDevice(device));
     ctx->arena = std::make_shared<DeviceArena>(device);
+    noalloc_register_device(device);   // once per device, this device current
 
     const u32 n = ctx->n, nmod = ctx->nmod();
     ctx->modq.resize(nmod);

@@ -86,6 +86,7 @@ _SIGS = {
     "vr_rotate": [P, P, P, I32, PP, P],
     "vr_rotate_many": [P, P, P, P, SZ, PP, P],
     "vr_rotate_batch": [P, P, PP, SZ, I32, PP, P],
+    "vr_rotate_noalloc": [P, P, P, U32, I32, P, P],
     "vr_matmul": [P, P, PP, PP, U32, U32, U32, PP, P],
     "vr_matmul_outer": [P, P, PP, PP, U32, U32, U32, PP, P],
     "vr_conv2d": [P, P, PP, U32, U32, U32, U32, P, P, U32, U32, U32, PP, P],
@@ -437,6 +438,12 @@ class Context:
         _check(lib.vr_rotate_batch(self.h, keys.ek, _ptr_array(cts), len(cts), int(step), arr,
                                    _stream(stream)))
         return [Ciphertext(arr[i], self) for i in range(len(cts))]
+
+    def rotate_noalloc(self, keys, in_ptr, level, step, out_ptr, stream=None):
+        """vr_rotate_noalloc: device limbs [2][level+1][N] at in_ptr rotated into
+        out_ptr, with no device allocation (integer device addresses)."""
+        _check(lib.vr_rotate_noalloc(self.h, keys.ek, ctypes.c_void_p(in_ptr), int(level), int(step),
+                                     ctypes.c_void_p(out_ptr), _stream(stream)))
 
     # ------------------------------------------------------------ layers
     def matmul(self, keys, A, Bbar, m, n, p, stream=None):
