@@ -243,7 +243,7 @@ def uneven_bench(vr, n_req, level, reps, seed=4):
     import synthetic_inputs as SI
     reqs = SI.uneven_requests(seed, n_req)
     ctx = vr.Context(16, [60] + [50] * 24, [51] * 9, 3, 50.0)
-    max_p = max(1 << (r[1][2] - 1).bit_length() for r in reqs if r[0] == "matmul")
+    max_p = max(1 << (min(r[1][0], r[1][2]) - 1).bit_length() for r in reqs if r[0] == "matmul")
     keys = ctx.keygen(1004, rot_steps=list(range(1, max(max_p, 3))))
     nets, items = {}, []
     images = 0
@@ -309,10 +309,16 @@ def uneven_bench(vr, n_req, level, reps, seed=4):
     Pp = len(outs)
     C = np.full((m, p), np.nan)
     for idx, ct in enumerate(outs):
-        z = ctx.decode(ctx.decrypt(keys, ct), m)
-        for r in range(m):
-            if (r + idx) % Pp < p:
-                C[r, (r + idx) % Pp] = z[r]
+        if m >= p:    # slot r: C[r][(r + idx) mod P']
+            z = ctx.decode(ctx.decrypt(keys, ct), m)
+            for r in range(m):
+                if (r + idx) % Pp < p:
+                    C[r, (r + idx) % Pp] = z[r]
+        else:         # transposed product: slot i: C[(i + idx) mod M'][i]
+            z = ctx.decode(ctx.decrypt(keys, ct), p)
+            for i in range(p):
+                if (i + idx) % Pp < m:
+                    C[(i + idx) % Pp, i] = z[i]
     err = float(np.nanmax(np.abs(C - A @ B)) / np.max(np.abs(A @ B)))
     batch.close()
     n_mm = sum(1 for it in items if it[0] == "matmul")
@@ -336,7 +342,7 @@ def uneven_full_bench(vr, n_req, level, reps, seed=4):
     Reports the rotations the column-split form would have needed
     (n (P' - 1) per product, transposed when p > m)."""
     import synthetic_inputs as SI
-    reqs = SI.uneven_requests(seed, n_req, dim_range=(16, 512), sides=(32, 64, 128, 256), p_le_m=False)
+    reqs = SI.uneven_requests(seed, n_req, dim_range=(16, 512), sides=(32, 64, 128, 256))
     ctx = vr.Context(16, [60] + [50] * 24, [51] * 9, 3, 50.0)
     keys = ctx.keygen(1004, rot_steps=[1, 2])
     t0 = time.perf_counter()

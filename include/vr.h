@@ -267,8 +267,11 @@ vr_status vr_rotate_noalloc(vr_context *ctx, const vr_eval_keys *ek, const uint6
  * ciphertext-pair split of "Parallelized Matrix Multiplication"): from A_k,
  * Bbar_k (k < n, from vr_encrypt_matrix_columns), for idx < P',
  *   C[idx] = Rescale(Relin(sum_k A_k * Rot(Bbar_k, idx))),
- * slot i < m of C[idx] holding (A B)[i][(i + idx) mod P'].  Needs m >= p and
- * rotation keys for steps 1..P'-1.  C receives P' handles. */
+ * slot i < m of C[idx] holding (A B)[i][(i + idx) mod P'].  Rotation keys
+ * for steps 1..P'-1; C receives P' handles.  For m < p the product is the
+ * paper's transposed one, C^T = B^T A^T, on the same ciphertexts with their
+ * roles swapped: M' = pow2(m) outputs, slot i < p of C[idx] holding
+ * (A B)[(i + idx) mod M'][i], rotation keys for steps 1..M'-1. */
 vr_status vr_matmul(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *A,
                     const vr_ciphertext *const *Bbar, uint32_t m, uint32_t n, uint32_t p,
                     vr_ciphertext **C, void *stream);

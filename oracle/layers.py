@@ -179,8 +179,14 @@ def encrypt_matrix_outer(ctx: Context, keys: Keys, M, role, m, p, level, seed, f
 
 
 def matmul(ctx: Context, keys: Keys, A_cts, B_cts, m, n, p):
+    """D_idx = Rescale(Relin(sum_k A_k * Rot(Bbar_k, idx))), idx < P'.  For
+    m < p the paper multiplies the transposes, C^T = B^T A^T: the Bbar
+    ciphertexts (slot s -> B[k][s mod P']) are exactly the A-role ciphertexts
+    of B^T and the A ciphertexts (slot s -> A[s mod M'][k]) the Bbar-role
+    ciphertexts of A^T, so the roles swap and slot i < p of D_idx holds
+    C[(i + idx) mod M'][i] (M' ciphertexts)."""
     if m < p:
-        raise ValueError("matmul schedule needs m >= p (use the transpose)")
+        return matmul(ctx, keys, B_cts, A_cts, p, n, m)
     Pp = pow2ceil(p)
     T = [None] * Pp
     for k in range(n):
@@ -192,6 +198,8 @@ def matmul(ctx: Context, keys: Keys, A_cts, B_cts, m, n, p):
 
 
 def matmul_decode(ctx: Context, keys: Keys, D, m, p):
+    if m < p:
+        return matmul_decode(ctx, keys, D, p, m).T
     Pp = pow2ceil(p)
     C = np.full((m, p), np.nan)
     for idx in range(Pp):

@@ -181,7 +181,7 @@ vr_status vr_context_set_tuning(vr_context* ctx, const char* knob, const char* v
         mode = v == "auto" ? 0 : v == "fixed" ? 1 : -1;
         if (v.compare(0, 5, "cand:") == 0) mode = 2 + std::stoi(v.substr(5));
     }
-    else if (k == "switch_chunk") mode = std::stoi(v);
+    else if (k == "switch_chunk" || k == "ntt_chunk") mode = std::stoi(v);
     else throw Error(VR_EINVAL, "unknown tuning knob");
     REQUIRE(mode >= 0, "base_convert takes auto, alu, mfma or fp64; ntt takes auto, fixed or cand:k");
     std::lock_guard<std::mutex> g(ctx->mu);

@@ -379,7 +379,6 @@ vr_status vr_batch_add_matmul(vr_batch* b, const vr_ciphertext* const* A, const 
     REQUIRE(b && A && Bbar && req_id, "null argument");
     REQUIRE(!b->exec, "batch already captured");
     REQUIRE(m >= 1 && n >= 1 && p >= 1 && A[0] && Bbar[0], "empty matrix");
-    REQUIRE(m >= p, "matmul schedule needs m >= p (multiply the transposes)");
     hipStream_t s = b->ctx->stream;
     BatchReq r;
     r.cnn = false;

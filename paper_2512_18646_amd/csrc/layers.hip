@@ -736,11 +736,17 @@ Slab conv_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& x, u32 n_set
 // ciphertexts still needing it form a prefix, rotated by one shared-key
 // inner product and one ModDown; the tensor accumulations stay per request,
 // and every request's P' products are relinearised and rescaled together.
-std::vector<Slab> matmul_multi(vr_context* ctx, const vr_eval_keys* ek, const std::vector<MatReq>& reqs,
+std::vector<Slab> matmul_multi(vr_context* ctx, const vr_eval_keys* ek, const std::vector<MatReq>& reqs_in,
                                hipStream_t s)
 {
-    const u32 nr = (u32)reqs.size();
+    const u32 nr = (u32)reqs_in.size();
     if (nr == 0) return {};
+    // m < p: the transposed product C^T = B^T A^T on the same ciphertexts
+    // with their roles swapped (the Bbar columns are the A-role columns of
+    // B^T, the A columns the Bbar-role columns of A^T)
+    std::vector<MatReq> reqs = reqs_in;
+    for (MatReq& q : reqs)
+        if (q.m < q.p) std::swap(q.A, q.B), std::swap(q.m, q.p);
     const u32 level = reqs[0].A.level, nl = level + 1;
     const double scale_ab = reqs[0].A.scale * reqs[0].B.scale;
     std::vector<u32> order(nr), Pp(nr);
@@ -749,7 +755,6 @@ std::vector<Slab> matmul_multi(vr_context* ctx, const vr_eval_keys* ek, const st
         if (q.A.level != level || q.B.level != level) throw Error(VR_ELEVEL, "matmul inputs at different levels");
         if (q.A.scale * q.B.scale != scale_ab) throw Error(VR_ESCALE, "matmul inputs at different scales");
         if (q.A.ncomp != 2 || q.B.ncomp != 2) throw Error(VR_EINVAL, "matmul inputs must be 2-component");
-        if (q.m < q.p) throw Error(VR_EINVAL, "matmul schedule needs m >= p (multiply the transposes)");
         Pp[r] = pow2ceil(q.p);
         order[r] = r;
         for (u32 i = 1; i < Pp[r]; i++) (void)rot_key(ek, galois_element(ctx, (int32_t)i));
@@ -1011,13 +1016,12 @@ vr_status vr_matmul(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext
                     const vr_ciphertext* const* Bbar, uint32_t m, uint32_t n, uint32_t p,
                     vr_ciphertext** C, void* stream)
 {
-    const u32 Pp = p ? pow2ceil(p) : 0;
+    const u32 Pp = m && p ? pow2ceil(std::min(m, p)) : 0;
     if (C)
         for (u32 i = 0; i < Pp; i++) C[i] = nullptr;
     API_BEGIN
     REQUIRE(ctx && ek && A && Bbar && C, "null argument");
     REQUIRE(m >= 1 && n >= 1 && p >= 1, "empty matrix");
-    REQUIRE(m >= p, "matmul schedule needs m >= p (multiply the transposes)");
     hipStream_t s = pick_stream(ctx, stream);
     MatReq rq;
     rq.A = gather(ctx, A, n, s);

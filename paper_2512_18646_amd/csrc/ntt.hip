@@ -49,6 +49,7 @@ struct NttPass {
     u32 s0, log_g, log_c;
     u32 first, last;
     u32 max_r;          // stages per round (4, or 5 with 32 elements per thread)
+    u32 r0;             // first limb of this launch (launches over chunks of limbs)
 };
 VR_KERNEL_ARG(NttPass);
 
@@ -382,8 +383,9 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
     const u32 tile = G << p.log_c;
     const u32 lo_bits = p.log_n - p.s0 - p.log_g;
     const u32 blocks_per_limb = (n >> p.log_g) >> p.log_c;
-    const u32 r = blockIdx.x / blocks_per_limb;
-    const u32 g0 = (blockIdx.x - r * blocks_per_limb) << p.log_c;
+    const u32 rl = blockIdx.x / blocks_per_limb;
+    const u32 g0 = (blockIdx.x - rl * blocks_per_limb) << p.log_c;
+    const u32 r = p.r0 + rl;
 
     const u64* src;
     u64* dst;
@@ -1012,7 +1014,7 @@ template <int LOGN, int LOGE, bool INV>
 __global__ __launch_bounds__(1u << (LOGN - LOGE)) void k_ntt_limb(NttPass p)
 {
     extern __shared__ u64 lds[];
-    LimbK c = limb_consts<LOGN, INV>(p, blockIdx.x);
+    LimbK c = limb_consts<LOGN, INV>(p, p.r0 + blockIdx.x);
     c.tid = threadIdx.x;
     LinePrefetch<LOGN, LOGE> pf;
     limb_transform<LOGN, LOGE, INV>(lds, c, pf);
@@ -1246,7 +1248,7 @@ __global__ __launch_bounds__((SplitShape<LOGN, A, LC, PASS>::T)) void k_ntt_spli
 {
     using S = SplitShape<LOGN, A, LC, PASS>;
     extern __shared__ u64 lds[];
-    const u32 r = blockIdx.x >> S::WG_LOG, wg = blockIdx.x & ((1u << S::WG_LOG) - 1);
+    const u32 r = p.r0 + (blockIdx.x >> S::WG_LOG), wg = blockIdx.x & ((1u << S::WG_LOG) - 1);
     LimbK c = limb_consts<LOGN, INV>(p, r);
     c.tid = threadIdx.x;
     constexpr bool FIRST = INV ? PASS == 1 : PASS == 0;
@@ -1276,6 +1278,8 @@ __global__ __launch_bounds__((SplitShape<LOGN, A, LC, PASS>::T)) void k_ntt_spli
 }
 
 namespace {
+
+constexpr u32 kSplitChunkDefault = 0;
 
 struct PassCfg {
     u32 s0, log_g, log_c;
@@ -1441,6 +1445,17 @@ void launch_pass(const NttPass& p, const PassCfg& c, u32 n_limbs, hipStream_t s)
     VR_CHECK_LAUNCH();
 }
 
+// Limbs per launch pair of the compile-time two-pass kernels (0: all limbs in
+// one launch per pass).  With chunks, pass 0 and pass 1 alternate chunk by
+// chunk, so the intermediate pass 1 reads was written moments before and is
+// still in the last-level cache.
+u32 split_chunk(vr_context* ctx)
+{
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto it = ctx->tuning.find("ntt_chunk");
+    return it == ctx->tuning.end() ? kSplitChunkDefault : (u32)it->second;
+}
+
 template <bool INV>
 void run_plan(vr_context* ctx, const LimbSet& ls, const std::vector<PassCfg>& passes, hipStream_t s)
 {
@@ -1452,17 +1467,26 @@ void run_plan(vr_context* ctx, const LimbSet& ls, const std::vector<PassCfg>& pa
     p.twf = INV ? ctx->d_itwf : ctx->d_twf;
     p.log_n = ctx->log_n;
     p.L = ctx->L;
+    p.r0 = 0;
     size_t np = passes.size();
-    for (size_t i = 0; i < np; i++) {
-        // forward runs the stage groups in order, inverse in reverse
-        const PassCfg& c = INV ? passes[np - 1 - i] : passes[i];
-        p.s0 = c.s0;
-        p.log_g = c.log_g;
-        p.log_c = c.log_c;
-        p.first = (i == 0);
-        p.last = (i == np - 1);
-        p.max_r = c.max_r;
-        launch_pass<INV>(p, c, n_limbs, s);
+    // every limb's two passes touch only that limb's words (and shared
+    // tables), so the limbs may run in chunks
+    const u32 chunk = np == 2 && passes[0].direct == 3 ? split_chunk(ctx) : 0;
+    const u32 step = chunk ? chunk : n_limbs;
+    for (u32 r0 = 0; r0 < n_limbs; r0 += step) {
+        p.r0 = r0;
+        const u32 nc = std::min(step, n_limbs - r0);
+        for (size_t i = 0; i < np; i++) {
+            // forward runs the stage groups in order, inverse in reverse
+            const PassCfg& c = INV ? passes[np - 1 - i] : passes[i];
+            p.s0 = c.s0;
+            p.log_g = c.log_g;
+            p.log_c = c.log_c;
+            p.first = (i == 0);
+            p.last = (i == np - 1);
+            p.max_r = c.max_r;
+            launch_pass<INV>(p, c, nc, s);
+        }
     }
 }
 

@@ -48,6 +48,8 @@ def square(ctx, keys, cts, stream=None):
 
 
 def matmul(ctx, keys, A, Bbar, m, n, p, stream=None):
+    if m < p:   # the transposed product on the same ciphertexts, roles swapped
+        return matmul(ctx, keys, Bbar, A, p, n, m, stream=stream)
     Pp = pow2ceil(p)
     T = [None] * Pp
     for k in range(n):

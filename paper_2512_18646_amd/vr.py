@@ -447,8 +447,8 @@ class Context:
 
     # ------------------------------------------------------------ layers
     def matmul(self, keys, A, Bbar, m, n, p, stream=None):
-        Pp = 1
-        while Pp < p:
+        Pp = 1                  # P' (M' when m < p: the transposed product)
+        while Pp < min(m, p):
             Pp *= 2
         arr = (ctypes.c_void_p * Pp)()
         _check(lib.vr_matmul(self.h, keys.ek, _ptr_array(A), _ptr_array(Bbar), m, n, p, arr,
@@ -698,7 +698,7 @@ class Batch:
         rid = U32()
         _check(lib.vr_batch_add_matmul(self.h, _ptr_array(A), _ptr_array(Bbar), m, n, p, ctypes.byref(rid)))
         pp = 1
-        while pp < p:
+        while pp < min(m, p):
             pp <<= 1
         self._cap.append(pp)
         return rid.value

@@ -80,20 +80,16 @@ CNN_128 = ConvWorkload("cnn128", 128, 3, 128, 128, 8, 3, 2, 1, 0.05, 3, fc_out=1
 MATMUL_16 = (1, 16, 16, 16)   # seed, m, n, p
 
 
-def uneven_requests(seed, count, dim_range=(8, 32), sides=(32, 64), p_le_m=True):
+def uneven_requests(seed, count, dim_range=(8, 32), sides=(32, 64)):
     """A mixed batch: even indices are products with m, n, p uniform integers
-    in dim_range (with p_le_m, m and p are swapped when p > m: the
-    column-split schedule multiplies the transposes otherwise), odd indices
-    are one-channel convolutions (3x3, 8 filters, stride 2, pad 1, then x^2)
-    on images of a side drawn from `sides`, with a full ciphertext set of
-    images; weights N(0, 0.05^2)."""
+    in dim_range, odd indices are one-channel convolutions (3x3, 8 filters,
+    stride 2, pad 1, then x^2) on images of a side drawn from `sides`, with a
+    full ciphertext set of images; weights N(0, 0.05^2)."""
     g = rng(seed)
     reqs = []
     for i in range(count):
         if i % 2 == 0:
             m, n, p = (int(v) for v in g.integers(dim_range[0], dim_range[1] + 1, 3))
-            if p_le_m and p > m:
-                m, p = p, m
             reqs.append(("matmul", (m, n, p), int(g.integers(1 << 30))))
         else:
             side = int(g.choice(sides))

@@ -28,7 +28,7 @@ def test_uneven_batch_eager_and_graph(ctx):
     o, ok, g, gk = ctx
     rng = np.random.default_rng(71)
     mm = []
-    for i, (m, n, p) in enumerate([(8, 6, 8), (16, 5, 4), (8, 8, 3), (16, 3, 16)]):
+    for i, (m, n, p) in enumerate([(8, 6, 8), (16, 5, 4), (8, 8, 3), (16, 3, 16), (3, 4, 12)]):
         A, B = rng.uniform(-1, 1, (m, n)), rng.uniform(-1, 1, (n, p))
         if i == 0:   # the oracle's encryption, to anchor the batched limbs
             Ac = [to_gpu(g, c) for c in Ly.encrypt_matrix_columns(o, ok, A, 0, m, p, 3, 81, 0)]

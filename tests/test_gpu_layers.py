@@ -68,6 +68,34 @@ def test_matmul_gpu_encrypt_end_to_end(c1mm):
     assert Ly.rel_error(gpu_matmul_decode(g, gk, gD, m, p), A @ B) < EPS
 
 
+def test_matmul_m_below_p_bit_exact(c1mm):
+    """m < p: the transposed product on the same ciphertexts, roles swapped
+    (M' = 8 outputs, slot i < p of C[idx] holding (A B)[(i + idx) mod 8][i]),
+    limb for limb against the oracle, per-op identical, decoded against FP64."""
+    o, ok, g, gk = c1mm
+    m, n, p = 5, 4, 13
+    rng = np.random.default_rng(14)
+    A, B = rng.uniform(-1, 1, (m, n)), rng.uniform(-1, 1, (n, p))
+    Ac = Ly.encrypt_matrix_columns(o, ok, A, 0, m, p, 3, 8, 0)
+    Bc = Ly.encrypt_matrix_columns(o, ok, B, 1, m, p, 3, 8, 100)
+    D = Ly.matmul(o, ok, Ac, Bc, m, n, p)
+    gA, gB = [to_gpu(g, c) for c in Ac], [to_gpu(g, c) for c in Bc]
+    gD = g.matmul(gk, gA, gB, m, n, p)
+    assert len(gD) == len(D) == 8
+    for i, (x, y) in enumerate(zip(gD, D)):
+        assert_same(x, y, "C[%d]" % i)
+    from paper_2512_18646_amd import perop
+    for i, (x, y) in enumerate(zip(perop.matmul(g, gk, gA, gB, m, n, p), D)):
+        assert_same(x, y, "per-op C[%d]" % i)
+    got = np.full((m, p), np.nan)
+    for idx, ct in enumerate(gD):
+        z = g.decode(g.decrypt(gk, ct), p)
+        for i in range(p):
+            if (i + idx) % 8 < m:
+                got[(i + idx) % 8, i] = z[i]
+    assert Ly.rel_error(got, A @ B) < EPS
+
+
 def test_matmul_ragged_identity_and_per_op(c1mm):
     o, ok, g, gk = c1mm
     m, n, p = 12, 5, 5

@@ -164,6 +164,20 @@ def test_matmul_schedule_random(ctx10):
     assert Ly.rel_error(C, A @ B) < EPS
 
 
+def test_matmul_schedule_m_below_p(ctx10):
+    """m < p through the transposed schedule, decoded against FP64."""
+    ctx, keys = ctx10
+    m, n, p = 5, 4, 13
+    rng = np.random.default_rng(13)
+    A, B = rng.uniform(-1, 1, (m, n)), rng.uniform(-1, 1, (n, p))
+    D = Ly.matmul(ctx, keys, Ly.encrypt_matrix_columns(ctx, keys, A, 0, m, p, 3, 4, 0),
+                  Ly.encrypt_matrix_columns(ctx, keys, B, 1, m, p, 3, 4, 100), m, n, p)
+    assert len(D) == Ly.pow2ceil(m)
+    got = Ly.matmul_decode(ctx, keys, D, m, p)
+    assert not np.isnan(got).any()
+    assert Ly.rel_error(got, A @ B) < EPS
+
+
 def test_matmul_schedule_identity_and_ragged(ctx10):
     """B = I gives C = A; m=12 > p=5 pads to M'=16, P'=8 (ragged tail)."""
     ctx, keys = ctx10
@@ -201,6 +215,32 @@ def test_matmul_column_slot_layout_brute_force():
                 if col < p:
                     assert D[i] == C[i, col]
                     seen[i, col] += 1
+                else:
+                    assert D[i] == 0.0
+        assert (seen == 1).all()
+
+
+def test_matmul_transposed_slot_layout_brute_force():
+    """m < p: the same ciphertexts with their roles swapped (Bbar_k as the
+    A role, A_k rotated) give C^T = B^T A^T: sum_k Bbar_k * Rot(A_k, idx)
+    holds C[(i + idx) mod M'][i] in slot i < p, zero where that row is past
+    m; every entry of A B reached once (plain slot vectors, small integers)."""
+    ctx = small_ctx(log_n=6)   # 32 slots
+    rng = np.random.default_rng(12)
+    for m, n, p in ((3, 4, 4), (5, 2, 12), (1, 3, 16), (7, 3, 32)):
+        A = rng.integers(-9, 10, (m, n)).astype(float)
+        B = rng.integers(-9, 10, (n, p)).astype(float)
+        C = A @ B
+        Mp = Ly.pow2ceil(m)
+        seen = np.zeros((m, p), int)
+        for idx in range(Mp):
+            D = sum(Ly.matrix_column_slots(ctx, B, k, 1, m, p) * np.roll(Ly.matrix_column_slots(ctx, A, k, 0, m, p), -idx)
+                    for k in range(n))
+            for i in range(p):
+                row = (i + idx) % Mp
+                if row < m:
+                    assert D[i] == C[row, i]
+                    seen[row, i] += 1
                 else:
                     assert D[i] == 0.0
         assert (seen == 1).all()
