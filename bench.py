@@ -395,12 +395,8 @@ def uneven_full_bench(vr, n_req, level, reps, seed=4):
             rows = min(R, m - t * R)
             C[t * R:t * R + rows] = z[:rows * Pp].reshape(rows, Pp)[:, :p]
         err = max(err, float(np.max(np.abs(C - A @ B)) / np.max(np.abs(A @ B))))
-    # the batch holds its own copy of every input and evaluates equal
-    # networks as one multi-set call (three 256x256 sets take ~90 GiB of
-    # intermediates): the whole mix does not fit in the device's memory in
-    # that form, so the batch and graph forms take the first quarter
-    nb = n_req // 4
-    check = [0, 1, 2, 3, nb - 2, nb - 1]   # requests whose limbs the batch must reproduce
+    # requests whose limbs the batch and its graph must reproduce
+    check = [0, 1, 2, 3, n_req // 2, n_req // 2 + 1, n_req - 2, n_req - 1]
     ref = {i: [c.export() for c in outs[i][:2]] for i in check}
     del outs
     t = time.perf_counter()
@@ -410,16 +406,9 @@ def uneven_full_bench(vr, n_req, level, reps, seed=4):
     sync()
     t_run = (time.perf_counter() - t) / reps
     n_mm = sum(1 for it in items if it[0] == "matmul")
-    items = items[:nb]
-    t = time.perf_counter()
-    for _ in range(reps):
-        o = run()
-        del o
-    sync()
-    t_half = (time.perf_counter() - t) / reps
-    half_images = sum(it[3] for it in items if it[0] == "conv")
-    # the first quarter as one uneven batch (inputs copied into it, each caller's
-    # ciphertexts released once added), eager and captured as one graph
+    # every request in one uneven batch (the batch references the callers'
+    # input slabs, so the callers' handles are released once added), eager
+    # and captured as one graph
     batch = vr.Batch(ctx, keys)
     ids = []
     for i, it in enumerate(items):
@@ -455,15 +444,13 @@ def uneven_full_bench(vr, n_req, level, reps, seed=4):
     return {"workload": "%d requests: %d products (m, n, p in 16..512, outer-product form), %d 3x3/2 x8 + x^2 "
                         "convolutions on 32x32 .. 256x256 images (full sets), N=2^16 L=24 chain at level %d"
                         % (n_req, n_mm, n_req - n_mm, level),
-            "requests_per_s": round(n_req / t_run, 2), "ms_for_all": round(t_run * 1e3, 1),
-            "conv_images_per_s": round(images / t_run, 1),
-            "first_quarter": {"requests": nb,
-                           "requests_per_s": {"per_request": round(nb / t_half, 2), "batch": round(nb / t_batch, 2),
-                                              "graph": round(nb / t_graph, 2)},
-                           "conv_images_per_s": {"per_request": round(half_images / t_half, 1),
-                                                 "batch": round(half_images / t_batch, 1),
-                                                 "graph": round(half_images / t_graph, 1)},
-                           "identical_to_per_request": bool(same_eager and same_graph)},
+            "requests_per_s": {"per_request": round(n_req / t_run, 2), "batch": round(n_req / t_batch, 2),
+                               "graph": round(n_req / t_graph, 2)},
+            "ms_for_all": {"per_request": round(t_run * 1e3, 1), "batch": round(t_batch * 1e3, 1),
+                           "graph": round(t_graph * 1e3, 1)},
+            "conv_images_per_s": {"per_request": round(images / t_run, 1), "batch": round(images / t_batch, 1),
+                                  "graph": round(images / t_graph, 1)},
+            "identical_to_per_request": bool(same_eager and same_graph), "identity_checked_requests": check,
             "product_tensors": tensors, "column_split_rotations_avoided": rot_split,
             "products_max_rel_error": err, "setup_s": round(setup_s, 1),
             "device_gib_reserved": round(reserved / 2 ** 30, 1)}
@@ -1151,8 +1138,23 @@ def main():
                     help="only the N=2^16 rotation leg (for profiling its kernels)")
     ap.add_argument("--breakdown", action="store_true",
                     help="one extra headline step per kernel class, reporting its device time per step")
+    ap.add_argument("--legs", default="all",
+                    help="extra legs to run after the headline: all, or a comma list of trimmed, conv28, "
+                         "matmul16, rotations, serving, uneven, cpu")
     ap.add_argument("--cpu-oracle-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
+    legs = set(args.legs.split(",")) if args.legs != "all" else \
+        {"trimmed", "conv28", "matmul16", "rotations", "serving", "uneven", "cpu"}
+    if args.no_extra:
+        legs = set()
+    if args.no_cnn:
+        legs.discard("trimmed")
+    if args.no_serve:
+        legs.discard("serving")
+    if args.no_uneven:
+        legs.discard("uneven")
+    if args.no_cpu_baseline:
+        legs.discard("cpu")
     if args.cpu_oracle_child:
         cpu_oracle_child()
         return
@@ -1253,20 +1255,22 @@ def main():
     import gc
     gc.collect()
 
-    if not args.no_extra and not args.no_cnn:
+    if "trimmed" in legs:
         log("cnn128 at level 3 (trimmed)")
         log_free("before this leg")
         out["cnn128_trimmed_n16"] = cnn128_bench(vr, 3, args.cnn_sets, 2, graph=True)
         gc.collect()
 
-    if not args.no_extra:
+    if "conv28" in legs:
         log("28x28 conv layer at N=2^14")
         log_free("before this leg")
         out["conv28_n14"] = conv28_bench(vr, perop, args)
         gc.collect()
+    if "matmul16" in legs:
         log("16x16 matmul at N=2^13")
         out["matmul16_n13"] = matmul16_bench(vr, perop)
         gc.collect()
+    if "rotations" in legs:
         log("rotations at N=2^16")
         log_free("before this leg")
         out["rotations_per_s_n16"] = {"level24": rotations_bench(vr, 24, 8, 3),
@@ -1275,7 +1279,7 @@ def main():
             v["batched"], v["per_op"] = round(v["batched"], 1), round(v["per_op"], 1)
         gc.collect()
 
-    if not args.no_extra and not args.no_serve:
+    if "serving" in legs:
         log("serving (Poisson arrivals, image-size mix) at N=2^14")
         W2, ctx2, keys2, K2, bias2, _ = conv_setup(vr, 7, 0, args.ntt_plan)
         out["serving"] = [serving_bench(vr, ctx2, keys2, args.serve_requests, float(x), 7)
@@ -1287,7 +1291,7 @@ def main():
         out["serving_n16"] = serving_n16_bench(vr)
         gc.collect()
 
-    if not args.no_extra and not args.no_uneven:
+    if "uneven" in legs:
         log("uneven batch at N=2^16")
         log_free("before this leg")
         out["uneven_batch_n16"] = uneven_bench(vr, 64, 3, 2)
@@ -1297,7 +1301,7 @@ def main():
         out["uneven_full_n16"] = uneven_full_bench(vr, 64, 3, 2)
         gc.collect()
 
-    if not args.no_extra and not args.no_cpu_baseline:
+    if "cpu" in legs:
         log("cpu baseline (oracle, child process)")
         cpu = cpu_oracle_leg()
         c3 = cpu["c3_level24"]

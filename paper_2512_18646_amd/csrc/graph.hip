@@ -92,6 +92,10 @@ bool same_net(const CnnDesc& a, const CnnDesc& b)
            a.fc_block == b.fc_block && a.fc_bias == b.fc_bias;
 }
 
+// Networks of a batch with the same description are merged into one
+// multi-set evaluation while their inputs together stay under this size.
+constexpr size_t kBatchMergeBytes = size_t(2) << 30;
+
 // One request of a batch: a network over its own image sets, or a product
 // (column-split, or outer-product when `outer`).
 struct BatchReq {
@@ -109,6 +113,8 @@ struct BatchReq {
 // and scale as one merged schedule.
 void run_batch(vr_context* ctx, const vr_eval_keys* ek, std::vector<BatchReq>& reqs, hipStream_t s)
 {
+    // the previous run's outputs go first, so a run never holds two sets
+    for (BatchReq& r : reqs) r.out = Slab();
     std::vector<bool> done(reqs.size(), false);
     for (size_t i = 0; i < reqs.size(); i++) {
         if (done[i] || !reqs[i].cnn) continue;
@@ -117,9 +123,22 @@ void run_batch(vr_context* ctx, const vr_eval_keys* ek, std::vector<BatchReq>& r
             if (!done[j] && reqs[j].cnn && same_net(reqs[i].desc, reqs[j].desc) &&
                 reqs[j].a.level == reqs[i].a.level && reqs[j].a.scale == reqs[i].a.scale)
                 grp.push_back(j), done[j] = true;
+        const u32 per_in = reqs[i].desc.n_in(), per_out = reqs[i].desc.n_out();
+        {
+            // merge into one multi-set evaluation only while the merged input
+            // stays small (the merge copies it); larger requests run alone on
+            // their own input slab
+            size_t bytes = 0;
+            std::vector<size_t> keep;
+            for (size_t j : grp) {
+                const size_t bj = (size_t)reqs[j].a.n * reqs[j].a.stride * sizeof(u64);
+                if (keep.empty() || bytes + bj <= kBatchMergeBytes) keep.push_back(j), bytes += bj;
+                else done[j] = false;
+            }
+            grp.swap(keep);
+        }
         u32 sets = 0;
         for (size_t j : grp) sets += reqs[j].n_sets;
-        const u32 per_in = reqs[i].desc.n_in(), per_out = reqs[i].desc.n_out();
         Slab x = reqs[i].a;
         if (grp.size() > 1) {
             x = new_slab(ctx, sets * per_in, 2, reqs[i].a.level, reqs[i].a.scale, s);
@@ -221,6 +240,17 @@ void copy_inputs(vr_context* ctx, const Slab& dst, const vr_ciphertext* const* i
                               hipMemcpyDeviceToDevice, s));
     }
     (void)ctx;
+}
+
+// A batch request's inputs: the caller's ciphertexts in place when they form
+// one slab (as the encryption calls and layer outputs return them; the
+// request then shares their allocation, so the caller may release its
+// handles), else one gathered copy.  Ciphertexts are never modified.
+Slab batch_inputs(vr_context* ctx, const vr_ciphertext* const* in, u32 n, hipStream_t s)
+{
+    Slab x = gather(ctx, in, n, s);
+    if (x.ncomp != 2) throw Error(VR_EINVAL, "inputs must be 2-component");
+    return x;
 }
 
 void release_graph(vr_graph* g)
@@ -364,8 +394,7 @@ vr_status vr_batch_add_cnn(vr_batch* b, const vr_cnn_desc* desc, const vr_cipher
     r.desc = make_desc(b->ctx, desc, in[0]->level, s);
     r.n_sets = n_sets;
     const u32 n = n_sets * r.desc.n_in();
-    r.a = new_slab(b->ctx, n, 2, in[0]->level, in[0]->scale, s);
-    copy_inputs(b->ctx, r.a, in, n, s);
+    r.a = batch_inputs(b->ctx, in, n, s);
     b->reqs.push_back(std::move(r));
     *req_id = (uint32_t)b->reqs.size() - 1;
     API_END
@@ -383,10 +412,8 @@ vr_status vr_batch_add_matmul(vr_batch* b, const vr_ciphertext* const* A, const 
     BatchReq r;
     r.cnn = false;
     r.m = m, r.n = n, r.p = p;
-    r.a = new_slab(b->ctx, n, 2, A[0]->level, A[0]->scale, s);
-    copy_inputs(b->ctx, r.a, A, n, s);
-    r.b = new_slab(b->ctx, n, 2, Bbar[0]->level, Bbar[0]->scale, s);
-    copy_inputs(b->ctx, r.b, Bbar, n, s);
+    r.a = batch_inputs(b->ctx, A, n, s);
+    r.b = batch_inputs(b->ctx, Bbar, n, s);
     b->reqs.push_back(std::move(r));
     *req_id = (uint32_t)b->reqs.size() - 1;
     API_END
@@ -407,10 +434,8 @@ vr_status vr_batch_add_matmul_outer(vr_batch* b, const vr_ciphertext* const* A, 
     r.cnn = false;
     r.outer = true;
     r.m = m, r.n = n, r.p = p;
-    r.a = new_slab(b->ctx, T * n, 2, A[0]->level, A[0]->scale, s);
-    copy_inputs(b->ctx, r.a, A, (size_t)T * n, s);
-    r.b = new_slab(b->ctx, n, 2, B[0]->level, B[0]->scale, s);
-    copy_inputs(b->ctx, r.b, B, n, s);
+    r.a = batch_inputs(b->ctx, A, T * n, s);
+    r.b = batch_inputs(b->ctx, B, n, s);
     b->reqs.push_back(std::move(r));
     *req_id = (uint32_t)b->reqs.size() - 1;
     API_END

@@ -766,10 +766,13 @@ std::vector<Slab> matmul_multi(vr_context* ctx, const vr_eval_keys* ek, const st
     std::vector<u32> b_off(nr), t_off(nr);
     for (u32 r : order) b_off[r] = n_tot, n_tot += reqs[r].n;
     for (u32 r = 0; r < nr; r++) t_off[r] = p_tot, p_tot += Pp[r];
-    Slab SB = new_slab(ctx, n_tot, 2, level, reqs[0].B.scale, s);
-    for (u32 r = 0; r < nr; r++)
-        VR_HIP(hipMemcpyAsync(SB.ct(b_off[r]), reqs[r].B.base, (size_t)reqs[r].n * SB.stride * sizeof(u64),
-                              hipMemcpyDeviceToDevice, s));
+    Slab SB = reqs[0].B;   // one request: its Bbar columns in place
+    if (nr > 1) {
+        SB = new_slab(ctx, n_tot, 2, level, reqs[0].B.scale, s);
+        for (u32 r = 0; r < nr; r++)
+            VR_HIP(hipMemcpyAsync(SB.ct(b_off[r]), reqs[r].B.base, (size_t)reqs[r].n * SB.stride * sizeof(u64),
+                                  hipMemcpyDeviceToDevice, s));
+    }
     Slab T = new_slab(ctx, p_tot, 3, level, scale_ab, s);
     dim3 grid((ctx->n + kThreads - 1) / kThreads, nl);
     for (u32 r = 0; r < nr; r++) {   // idx = 0: no rotation

@@ -173,14 +173,14 @@ def test_matmul_outer_errors(c1mm):
     assert e.value.code == vr.VR_EINVAL
 
 
-def test_matmul_rejects_m_below_p(c1mm):
+def test_matmul_rejects_operands_at_different_levels(c1mm):
     from paper_2512_18646_amd import vr
     o, ok, g, gk = c1mm
     A = g.encrypt_matrix_columns(gk, np.ones((4, 3)), 0, 4, 8, 3, 1, 0)
-    B = g.encrypt_matrix_columns(gk, np.ones((3, 8)), 1, 4, 8, 3, 1, 10)
+    B = g.encrypt_matrix_columns(gk, np.ones((3, 8)), 1, 4, 8, 2, 1, 10)
     with pytest.raises(vr.VRError) as e:
         g.matmul(gk, A, B, 4, 3, 8)
-    assert e.value.code == vr.VR_EINVAL
+    assert e.value.code == vr.VR_ELEVEL
 
 
 @pytest.fixture(scope="module")
