@@ -457,7 +457,7 @@ def uneven_full_bench(vr, n_req, level, reps, seed=4):
 
 
 def serving_n16_bench(vr, level=3, n_sessions=8, n_warm=20, n_meas=100, loads=(0.25, 0.5, 0.75, 0.9),
-                      seed=5):
+                      seed=5, max_batch=4):
     """Serving at N = 2^16 (L = 24 chain, requests entering at `level`): 8
     sessions with resident keys, Poisson arrivals of 28x28 (1 channel),
     64x64 and 128x128 (3 channels) requests in a 5:3:2 mix, each carrying
@@ -474,7 +474,7 @@ def serving_n16_bench(vr, level=3, n_sessions=8, n_warm=20, n_meas=100, loads=(0
         hp = 1 << (side + 1).bit_length()
         wo = (side + 2 - 3) // 2 + 1
         Wfc, bfc = SI.fc_weights(seed + 7 * side, 10, 8, wo, wo, 0.05)
-        pts = ctx.encode_fc_weights(Wfc, 2, hp, level - 2)
+        pts = ctx.encode_fc_weights(Wfc, 2, hp, 1)      # the FC runs at level 1
         net = vr.CNN(ch, side, side, 1, K, bias, 2, square=True, fc_w=pts, fc_bias=bfc, fc_block=hp)
         bmax = ctx.slots // hp
         cols = [ctx.encrypt_columns(keys, SI.images(seed + 31 * i + side, bmax, ch, side, side), 1, level,
@@ -482,7 +482,7 @@ def serving_n16_bench(vr, level=3, n_sessions=8, n_warm=20, n_meas=100, loads=(0
         kinds.append({"side": side, "net": net, "bmax": bmax, "cols": cols, "frac": frac})
     probs = np.array([k["frac"] for k in kinds])
     free, total = __import__("torch").cuda.mem_get_info()
-    srv = vr.Server(ctx, int(total * 0.9), max_batch=4)
+    srv = vr.Server(ctx, int(total * 0.9), max_batch=max_batch)
     sids = [srv.register_session(k) for k in sessions]
     for k in kinds:
         k["mid"] = srv.register_model(k["net"])
@@ -514,10 +514,11 @@ def serving_n16_bench(vr, level=3, n_sessions=8, n_warm=20, n_meas=100, loads=(0
         srv.poll(srv.submit(sids[0], k["mid"], k["cols"][0], 1), k["mid"])
     t0 = time.perf_counter()                     # saturation: a burst
     srv.reset_stats()
-    run(48, 0)
+    n_burst = max(24, min(48, n_meas))
+    run(n_burst, 0)
     burst_s = time.perf_counter() - t0
     sat = srv.stats()
-    sat_req_s = 48 / burst_s
+    sat_req_s = n_burst / burst_s
     levels = []
     for load in loads:
         run(n_warm, load * sat_req_s)
@@ -533,7 +534,8 @@ def serving_n16_bench(vr, level=3, n_sessions=8, n_warm=20, n_meas=100, loads=(0
                         "(B' = 1024 / 256 / 128), conv 3x3/2 x8 + x^2 + FC -> 10, %d sessions, N=2^16 L=24 "
                         "chain at level %d, %d measured requests per load" % (n_sessions, level, n_meas),
             "saturation": {"req_per_s": round(sat_req_s, 2), "images_per_s": round(sat["images_per_s"], 1),
-                           "latency_ms_p50": round(sat["p50_ms"], 2), "latency_ms_p99": round(sat["p99_ms"], 2)},
+                           "latency_ms_p50": round(sat["p50_ms"], 2), "latency_ms_p99": round(sat["p99_ms"], 2),
+                           "requests_per_wave": round(sat["batched"] / max(sat["waves"], 1), 2)},
             "loads": levels}
 
 
@@ -1127,6 +1129,8 @@ def main():
                     help="run a plain 1 GiB device copy first (counter calibration)")
     ap.add_argument("--cnn-sets", type=int, default=2)
     ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--serve-n16-requests", type=int, default=100,
+                    help="measured requests per offered load in the N=2^16 serving legs")
     ap.add_argument("--serve-load", default="0.8,2.0",
                     help="offered loads, as fractions of the one-request-at-a-time service rate")
     ap.add_argument("--ntt-plan", default="auto",
@@ -1286,9 +1290,15 @@ def main():
                           for x in args.serve_load.split(",")]
         del ctx2, keys2
         gc.collect()
-        log("serving at N=2^16")
+        log("serving at N=2^16, level 3")
         log_free("before this leg")
-        out["serving_n16"] = serving_n16_bench(vr)
+        out["serving_n16"] = serving_n16_bench(vr, level=3, n_meas=args.serve_n16_requests)
+        gc.collect()
+        log("serving at N=2^16, level 24")
+        log_free("before this leg")
+        out["serving_n16_level24"] = serving_n16_bench(vr, level=24, n_sessions=4, n_warm=10,
+                                                       n_meas=max(40, args.serve_n16_requests // 2),
+                                                       loads=(0.5, 0.9))
         gc.collect()
 
     if "uneven" in legs:

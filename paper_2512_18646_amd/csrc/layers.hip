@@ -145,6 +145,7 @@ constexpr int kMaxFilters = 8;
 
 __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, const u64* x,
                                                       const u64* r, u32 n_x, u32 n_sets, u64 stride,
+                                                      u64 ustride,
                                                       const Term* terms, const u32* term_off,
                                                       const u64* w, const u64* ws, const double* wf,
                                                       u32 w_fstride,
@@ -170,7 +171,6 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
     const size_t tile = (size_t)row * n + t;
     const u64* xb = x + (size_t)set * n_x * stride;
     const u64* rb = r + (size_t)set * n_x * stride;
-    const size_t ustride = (size_t)n_x * n_sets * stride;
     const size_t fst = (size_t)w_fstride * nl;
     constexpr u32 kColMask = (1u << kTermColBits) - 1;
     if (q < (1ull << 51)) {
@@ -381,6 +381,17 @@ __global__ __launch_bounds__(kThreads) void k_mulplain_acc(u64* out, u64 out_str
 // size runs in bounded memory (at N = 2^16, l = 24 that is ~120 ciphertexts).
 constexpr size_t kSwitchBudget = size_t(16) << 30;
 
+// key ranges must tile [0, n) in order
+void check_ranges(const std::vector<KeyRange>& keys, u32 n)
+{
+    u32 at = 0;
+    for (const KeyRange& kr : keys) {
+        if (kr.begin != at || kr.end < kr.begin || !kr.ek) throw Error(VR_EINVAL, "key ranges must tile the slab");
+        at = kr.end;
+    }
+    if (at != n) throw Error(VR_EINVAL, "key ranges must tile the slab");
+}
+
 u32 switch_chunk(vr_context* ctx, u32 level, u32 n_ct)
 {
     KsShape k = ks_shape(ctx, level);
@@ -396,17 +407,21 @@ u32 switch_chunk(vr_context* ctx, u32 level, u32 n_ct)
 
 // Rotations of every ciphertext of `in` by every step; out[si] is a slab of
 // in.n rotated ciphertexts (step si).  One ModUp per input (hoisting), one
-// inner-product launch per step and chunk of inputs.
-void rotate_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in,
-                 const std::vector<int32_t>& steps, std::vector<Slab>& out, hipStream_t s)
+// inner-product launch per step, chunk of inputs and key range (ciphertexts
+// [begin, end) of `in` switch with the keys of their range's session), one
+// ModDown per step and chunk whatever the sessions.
+void rotate_slab_keyed(vr_context* ctx, const std::vector<KeyRange>& keys, const Slab& in,
+                       const std::vector<int32_t>& steps, std::vector<Slab>& out, hipStream_t s)
 {
     const u32 level = in.level, n_ct = in.n;
     const size_t n = ctx->n;
     KsShape k = ks_shape(ctx, level);
+    check_ranges(keys, n_ct);
     std::vector<u32> gs;
     for (int32_t st : steps) {
         u32 g = galois_element(ctx, st);
-        if (g != 1) (void)rot_key(ek, g);
+        if (g != 1)
+            for (const KeyRange& kr : keys) (void)rot_key(kr.ek, g);
         gs.push_back(g);
     }
     const u32 cs = switch_chunk(ctx, level, n_ct);
@@ -435,8 +450,13 @@ void rotate_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in,
             if (gs[si] == 1) {
                 VR_HIP(hipMemcpyAsync(dst, src, (size_t)nc * in.stride * sizeof(u64), hipMemcpyDeviceToDevice, s));
             } else {
-                keyswitch_inner_batch(ctx, X, xs, src + (size_t)k.nq * n, in.stride, nc,
-                                      rot_key(ek, gs[si]).data, level, gs[si], U, us, s);
+                for (const KeyRange& kr : keys) {
+                    const u32 lo = std::max(kr.begin, c0), hi = std::min(kr.end, c0 + nc);
+                    if (lo >= hi) continue;
+                    keyswitch_inner_batch(ctx, X + (size_t)(lo - c0) * xs, xs, in.ct(lo) + (size_t)k.nq * n,
+                                          in.stride, hi - lo, rot_key(kr.ek, gs[si]).data, level, gs[si],
+                                          U + (size_t)(lo - c0) * us, us, s);
+                }
                 keyswitch_moddown_batch(ctx, U, us, nc, level, dst, dst + (size_t)k.nq * n, all.stride, src,
                                         gs[si], nullptr, in.stride, md, s);
             }
@@ -444,12 +464,20 @@ void rotate_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in,
     }
 }
 
-// relinearise a slab of 3-component ciphertexts into 2-component ones
-Slab relin_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& T, hipStream_t s)
+void rotate_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in,
+                 const std::vector<int32_t>& steps, std::vector<Slab>& out, hipStream_t s)
+{
+    rotate_slab_keyed(ctx, {KeyRange{0, in.n, ek}}, in, steps, out, s);
+}
+
+// relinearise a slab of 3-component ciphertexts into 2-component ones, each
+// key range with its session's relinearisation key
+Slab relin_slab_keyed(vr_context* ctx, const std::vector<KeyRange>& keys, const Slab& T, hipStream_t s)
 {
     const u32 level = T.level, n_ct = T.n;
     const size_t n = ctx->n;
     KsShape k = ks_shape(ctx, level);
+    check_ranges(keys, n_ct);
     const u32 cs = switch_chunk(ctx, level, n_ct);
     const u64 xs = (u64)k.beta * k.next * n, us = (u64)2 * k.next * n;
     BufPtr xbuf = dev_alloc(ctx, ((size_t)cs * xs + (size_t)cs * k.nq * n) * sizeof(u64), s);
@@ -461,13 +489,22 @@ Slab relin_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& T, hipStrea
         const u32 nc = std::min(cs, n_ct - c0);
         const u64* t = T.ct(c0);
         keyswitch_modup_batch(ctx, t + (size_t)2 * k.nq * n, T.stride, nc, level, X, X + (size_t)cs * xs, s);
-        keyswitch_inner_batch(ctx, X, xs, t + (size_t)2 * k.nq * n, T.stride, nc, ek->rlk.data, level, 1,
-                              U, us, s);
+        for (const KeyRange& kr : keys) {
+            const u32 lo = std::max(kr.begin, c0), hi = std::min(kr.end, c0 + nc);
+            if (lo >= hi) continue;
+            keyswitch_inner_batch(ctx, X + (size_t)(lo - c0) * xs, xs, T.ct(lo) + (size_t)2 * k.nq * n, T.stride,
+                                  hi - lo, kr.ek->rlk.data, level, 1, U + (size_t)(lo - c0) * us, us, s);
+        }
         u64* o = out.ct(c0);
         keyswitch_moddown_batch(ctx, U, us, nc, level, o, o + (size_t)k.nq * n, out.stride, t, 1,
                                 t + (size_t)k.nq * n, T.stride, U + (size_t)cs * us, s);
     }
     return out;
+}
+
+Slab relin_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& T, hipStream_t s)
+{
+    return relin_slab_keyed(ctx, {KeyRange{0, T.n, ek}}, T, s);
 }
 
 Slab rescale_slab(vr_context* ctx, const Slab& in, hipStream_t s)
@@ -722,7 +759,7 @@ Slab conv_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& x, u32 n_set
         ProfScope prof(ctx, kProfLincomb, s, (u64)n_sets * n_out * 2 * nl);
         hipLaunchKernelGGL(k_lincomb, dim3(8 * per_xcd), dim3(kThreads), 0, s, acc.base, acc.stride,
                            x.base, rot.empty() ? x.base : rot[0].base, C_in * w, n_sets, x.stride,
-                           plan.terms, plan.off, plan.w, plan.ws, plan.wf, C_in * k * k, plan.bias, nl,
+                           (u64)C_in * w * n_sets * x.stride, plan.terms, plan.off, plan.w, plan.ws, plan.wf, C_in * k * k, plan.bias, nl,
                            ctx->log_n, ctx->d_modq, wo, C_out, total, per_xcd);
         VR_CHECK_LAUNCH();
     }
@@ -886,6 +923,128 @@ void outer_tiles(vr_context* ctx, u32 m, u32 p, u32* Pp, u32* R, u32* T)
     if (*Pp > ctx->slots) throw Error(VR_EINVAL, "p exceeds the slot count");
     *R = (u32)(ctx->slots / *Pp);
     *T = (m + *R - 1) / *R;
+}
+
+Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab& x, hipStream_t s)
+{
+    if (segs.empty()) throw Error(VR_EINVAL, "empty wave");
+    const CnnDesc& d0 = *segs[0].d;
+    u32 n_in = 0;
+    for (const NetSeg& g : segs) {
+        const CnnDesc& d = *g.d;
+        if (d.k != d0.k || d.square != d0.square || (d.fc_out != 0) != (d0.fc_out != 0) ||
+            (d.fc_out && (d.fc_level != d0.fc_level || d.fc_scale != d0.fc_scale)))
+            throw Error(VR_EINVAL, "wave segments must share kernel size, x^2, FC presence and FC level");
+        n_in += g.n_sets * d.n_in();
+    }
+    if (x.n != n_in || x.ncomp != 2) throw Error(VR_EINVAL, "wave input slab does not match its segments");
+    if (x.level < 1) throw Error(VR_ELEVEL, "conv needs a level to rescale");
+    const u32 level = x.level, nl = level + 1;
+    // conv: rotations of every input column by 1..k-1 under each session's keys
+    std::vector<KeyRange> kin;
+    u32 at = 0;
+    for (const NetSeg& g : segs) {
+        kin.push_back(KeyRange{at, at + g.n_sets * g.d->n_in(), g.ek});
+        at = kin.back().end;
+    }
+    std::vector<int32_t> steps;
+    for (u32 u = 1; u < d0.k; u++) steps.push_back((int32_t)u);
+    std::vector<Slab> rot;
+    if (!steps.empty()) rotate_slab_keyed(ctx, kin, x, steps, rot, s);
+    const double out_scale = x.scale * (double)ctx->mod[level];
+    u32 n_conv = 0;
+    for (const NetSeg& g : segs) n_conv += g.n_sets * g.d->C_out * g.d->w_out();
+    Slab acc = new_slab(ctx, n_conv, 2, level, out_scale, s);
+    // the linear combination per network, on its own inputs and rotations
+    std::vector<KeyRange> kout;
+    u32 in_at = 0, out_at = 0;
+    for (const NetSeg& g : segs) {
+        const CnnDesc& d = *g.d;
+        const u32 wo = d.w_out(), n_out = d.C_out * wo;
+        const ConvPlan& plan = conv_plan(ctx, d.C_in, d.w, d.pad, d.K.data(), d.bias.data(), d.C_out, d.k,
+                                         d.stride, level, out_scale);
+        const u32 chunks = (ctx->n + kThreads - 1) / kThreads;
+        const u32 total = chunks * 2 * nl * g.n_sets * wo;
+        const u32 per_xcd = (total + 7) / 8;
+        ProfScope prof(ctx, kProfLincomb, s, (u64)g.n_sets * n_out * 2 * nl);
+        hipLaunchKernelGGL(k_lincomb, dim3(8 * per_xcd), dim3(kThreads), 0, s, acc.ct(out_at), acc.stride,
+                           x.ct(in_at), rot.empty() ? x.ct(in_at) : rot[0].ct(in_at), d.n_in(), g.n_sets,
+                           x.stride, (u64)x.n * x.stride, plan.terms, plan.off, plan.w, plan.ws, plan.wf,
+                           d.C_in * d.k * d.k, plan.bias, nl, ctx->log_n, ctx->d_modq, wo, d.C_out, total,
+                           per_xcd);
+        VR_CHECK_LAUNCH();
+        kout.push_back(KeyRange{out_at, out_at + g.n_sets * n_out, g.ek});
+        in_at += g.n_sets * d.n_in();
+        out_at += g.n_sets * n_out;
+    }
+    rot.clear();
+    Slab y = rescale_slab(ctx, acc, s);
+    acc = Slab();
+    if (d0.square) {
+        // tensor of everything, relinearisation per session, one rescale
+        Slab T = new_slab(ctx, y.n, 3, y.level, y.scale * y.scale, s);
+        dim3 grid((ctx->n + kThreads - 1) / kThreads, y.n * (y.level + 1));
+        {
+            ProfScope prof(ctx, kProfTensor, s, (u64)y.n * 2 * (y.level + 1));
+            hipLaunchKernelGGL(k_tensor_batch, grid, dim3(kThreads), 0, s, T.base, y.base, y.base, y.stride,
+                               y.level + 1, ctx->log_n, ctx->d_modq);
+            VR_CHECK_LAUNCH();
+        }
+        y = rescale_slab(ctx, relin_slab_keyed(ctx, kout, T, s), s);
+    }
+    if (!d0.fc_out) return y;
+    // FC: weight products per network and set at the weights' level, one
+    // rescale, the rotate-and-sum over each set's block (segments in
+    // decreasing block order, so the ones still summing form a prefix)
+    const u32 fl = std::min(y.level, d0.fc_level);
+    if (fl < 1) throw Error(VR_ELEVEL, "FC needs a level to rescale");
+    u32 n_fc = 0;
+    for (size_t i = 0; i < segs.size(); i++) {
+        n_fc += segs[i].n_sets * segs[i].d->fc_out;
+        if (i && segs[i].d->fc_block > segs[i - 1].d->fc_block)
+            throw Error(VR_EINVAL, "FC segments must come in decreasing block order");
+    }
+    Slab z = new_slab(ctx, n_fc, 2, fl, y.scale * d0.fc_scale, s);
+    std::vector<KeyRange> kfc;
+    u32 y_at = 0, z_at = 0;
+    for (const NetSeg& g : segs) {
+        const CnnDesc& d = *g.d;
+        const u32 per = d.C_out * d.w_out();
+        for (u32 st = 0; st < g.n_sets; st++) {
+            dim3 grid((ctx->n + kThreads - 1) / kThreads, fl + 1, (d.fc_out + kFcGroup - 1) / kFcGroup);
+            hipLaunchKernelGGL(k_mulplain_acc, grid, dim3(kThreads), 0, s, z.ct(z_at + st * d.fc_out), z.stride,
+                               y.ct(y_at + st * per), y.stride, (u64)(y.level + 1) * ctx->n, per, d.fc_P,
+                               d.fc_stride, d.fc_out, fl + 1, ctx->log_n, ctx->d_modq);
+            VR_CHECK_LAUNCH();
+        }
+        kfc.push_back(KeyRange{z_at, z_at + g.n_sets * d.fc_out, g.ek});
+        y_at += g.n_sets * per;
+        z_at += g.n_sets * d.fc_out;
+    }
+    y = Slab();
+    z = rescale_slab(ctx, z, s);
+    for (u32 step = 1; step < segs[0].d->fc_block; step <<= 1) {
+        std::vector<KeyRange> act;
+        for (size_t i = 0; i < segs.size(); i++)
+            if (segs[i].d->fc_block > step) act.push_back(kfc[i]);
+        Slab za = z;
+        za.n = act.back().end;
+        std::vector<Slab> r;
+        rotate_slab_keyed(ctx, act, za, {(int32_t)step}, r, s);
+        launch_addsub(ctx, za.base, za.base, r[0].base, za.n * 2, za.level + 1, false, s);
+    }
+    z_at = 0;
+    for (const NetSeg& g : segs) {
+        for (u32 st = 0; st < g.n_sets; st++)
+            for (u32 o = 0; o < g.d->fc_out; o++) {
+                LimbConsts kc;
+                for (u32 l = 0; l <= z.level; l++) kc.c[l] = double_to_mod(g.d->fc_bias[o] * z.scale, ctx->mod[l]);
+                launch_add_scalar(ctx, z.ct(z_at + st * g.d->fc_out + o), z.ct(z_at + st * g.d->fc_out + o),
+                                  z.level + 1, kc, s);
+            }
+        z_at += g.n_sets * g.d->fc_out;
+    }
+    return z;
 }
 
 }  // namespace vr

@@ -2,16 +2,21 @@
 //
 // A request is one image set (the C_in*w column ciphertexts of up to B'
 // images, the paper's mini-batch of "Secure Inference") for a registered model
-// (conv layer, optionally followed by the x^2 activation) under a session
-// whose evaluation keys stay resident in HBM.  A worker thread forms "waves":
-// the oldest pending request plus every later pending request of the same
-// session, model and level, while the wave is under max_batch requests and
-// the device-memory estimate of the in-flight waves stays under the budget.
-// A wave runs as one batched multi-set evaluation (vr_conv2d_sets semantics),
-// so requests that arrived while earlier waves were on the GPU join the next
-// wave; waves alternate between two streams so consecutive waves overlap on
-// the device.  Each request's output limbs are the same alone or in a wave:
-// every ciphertext's arithmetic is independent of the batch composition.
+// (conv layer, optionally followed by the x^2 activation and an FC layer)
+// under a session whose evaluation keys stay resident in HBM.  A worker thread
+// forms "waves": the oldest pending request plus every later pending request
+// that can be evaluated stage by stage beside it (same level and scale, models
+// with the same conv kernel size, x^2 and FC level; sessions and networks may
+// differ), while the wave is under max_batch requests and the device-memory
+// estimate of the in-flight waves stays under the budget.  A wave runs as one
+// evaluation (run_cnn_multi): the stages that do not depend on the keys
+// (ModUp, ModDown, NTTs, rescale, tensor) run once over every request's
+// ciphertexts, the key-switch inner products once per session, the linear
+// combinations and weight products once per network.  Requests that arrive
+// while earlier waves are on the GPU join the next wave; waves alternate
+// between two streams so consecutive waves overlap on the device.  Each
+// request's output limbs are the same alone or in a wave: every ciphertext's
+// arithmetic is independent of the wave's composition.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -75,7 +80,7 @@ struct Wave {
     hipEvent_t done = nullptr;
     std::vector<Request*> reqs;
     Slab y;
-    u32 per_req = 0;
+    std::vector<u32> off, cnt;    // request i's outputs: y ciphertexts [off[i], off[i] + cnt[i])
 };
 
 }  // namespace
@@ -130,21 +135,65 @@ size_t request_bytes(vr_context* ctx, const Model& m, u32 level)
     return b;
 }
 
-void run_wave(vr_server* srv, Wave& wv, const Model& m, const vr_eval_keys* ek, hipStream_t s)
+// Requests that can share one wave: same level and scale, and models whose
+// evaluations line up stage by stage (conv kernel size, x^2, FC presence and
+// the level the FC runs at); sessions and networks may differ.
+bool wave_compatible(const vr_server* srv, const Request* a, const Request* b)
+{
+    if (a->level != b->level || a->scale != b->scale) return false;
+    const Model& ma = srv->models[a->model];
+    const Model& mb = srv->models[b->model];
+    auto fc_level = [&](const Model& m, u32 level) {
+        return std::min(level - (m.square ? 1u : 0u) - 1u, m.fc_w[0]->level);
+    };
+    return ma.k == mb.k && ma.square == mb.square && (ma.fc_out != 0) == (mb.fc_out != 0) &&
+           (!ma.fc_out || (fc_level(ma, a->level) == fc_level(mb, b->level) &&
+                           ma.fc_w[0]->scale == mb.fc_w[0]->scale));
+}
+
+// One wave: requests ordered by FC block (decreasing), model and session so
+// that each (model, session) pair is one segment of consecutive image sets;
+// their columns copied into one slab and evaluated by run_cnn_multi.
+void run_wave(vr_server* srv, Wave& wv, hipStream_t s)
 {
     vr_context* ctx = srv->ctx;
+    std::stable_sort(wv.reqs.begin(), wv.reqs.end(), [&](const Request* a, const Request* b) {
+        const Model& ma = srv->models[a->model];
+        const Model& mb = srv->models[b->model];
+        if (ma.fc_block != mb.fc_block) return ma.fc_block > mb.fc_block;
+        if (a->model != b->model) return a->model < b->model;
+        return a->session < b->session;
+    });
     Request* r0 = wv.reqs[0];
-    const u32 nsets = (u32)wv.reqs.size(), ncols = m.n_cols();
-    for (Request* r : wv.reqs) VR_HIP(hipStreamWaitEvent(s, r->ready, 0));
-    Slab x = new_slab(ctx, nsets * ncols, 2, r0->level, r0->scale, s);
-    for (u32 i = 0; i < nsets; i++)
-        for (u32 c = 0; c < ncols; c++)
-            VR_HIP(hipMemcpyAsync(x.ct(i * ncols + c), wv.reqs[i]->data[c], x.stride * sizeof(u64),
-                                  hipMemcpyDeviceToDevice, s));
-    const vr_cnn_desc dd = m.desc();
-    CnnDesc d = make_desc(ctx, &dd, r0->level, s);
-    wv.y = run_cnn(ctx, ek, d, x, nsets, s);
-    wv.per_req = d.n_out();
+    std::map<u32, CnnDesc> descs;
+    std::vector<NetSeg> segs;
+    u32 n_in = 0;
+    for (Request* r : wv.reqs) {
+        VR_HIP(hipStreamWaitEvent(s, r->ready, 0));
+        auto it = descs.find(r->model);
+        if (it == descs.end()) {
+            const vr_cnn_desc dd = srv->models[r->model].desc();
+            it = descs.emplace(r->model, make_desc(ctx, &dd, r0->level, s)).first;
+        }
+        const vr_eval_keys* ek = srv->sessions.at(r->session);
+        if (!segs.empty() && segs.back().d == &it->second && segs.back().ek == ek)
+            segs.back().n_sets++;
+        else
+            segs.push_back(NetSeg{&it->second, ek, 1});
+        n_in += it->second.n_in();
+    }
+    Slab x = new_slab(ctx, n_in, 2, r0->level, r0->scale, s);
+    u32 at = 0, out_at = 0;
+    for (Request* r : wv.reqs) {
+        const CnnDesc& d = descs.at(r->model);
+        for (u32 c = 0; c < d.n_in(); c++)
+            VR_HIP(hipMemcpyAsync(x.ct(at + c), r->data[c], x.stride * sizeof(u64), hipMemcpyDeviceToDevice, s));
+        at += d.n_in();
+        wv.off.push_back(out_at);
+        wv.cnt.push_back(d.n_out());
+        out_at += d.n_out();
+    }
+    wv.y = run_cnn_multi(ctx, segs, x, s);
     VR_HIP(hipEventCreateWithFlags(&wv.done, hipEventDisableTiming));
     VR_HIP(hipEventRecord(wv.done, s));
 }
@@ -164,8 +213,8 @@ void retire(vr_server* srv)
             if (q == hipSuccess) {
                 r->state = 2;
                 r->out = wv.y;
-                r->out.n = wv.per_req;
-                r->out.base = wv.y.ct((u32)i * wv.per_req);
+                r->out.n = wv.cnt[i];
+                r->out.base = wv.y.ct(wv.off[i]);
             } else {
                 r->state = 3;
                 r->err = VR_EDEVICE;
@@ -220,8 +269,7 @@ void worker_loop(vr_server* srv)
                 for (auto it = srv->pending.begin(); it != srv->pending.end();) {
                     Request* r = *it;
                     if (wv.reqs.size() >= srv->max_batch) break;
-                    if (r->session == head->session && r->model == head->model && r->level == head->level &&
-                        r->scale == head->scale && srv->used + r->bytes <= cap) {
+                    if (wave_compatible(srv, r, head) && srv->used + r->bytes <= cap) {
                         wv.reqs.push_back(r);
                         srv->used += r->bytes;
                         it = srv->pending.erase(it);
@@ -231,15 +279,13 @@ void worker_loop(vr_server* srv)
                 }
                 for (Request* r : wv.reqs) r->state = 1;
                 hipStream_t s = srv->streams[srv->waves % 2];
-                const Model& model = srv->models[head->model];
-                const vr_eval_keys* ek = srv->sessions.at(head->session);
                 srv->waves++;
                 srv->batched_requests += wv.reqs.size();
                 lk.unlock();
                 std::string err;
                 vr_status code = VR_OK;
                 try {
-                    run_wave(srv, wv, model, ek, s);
+                    run_wave(srv, wv, s);
                 } catch (const Error& e) {
                     code = e.code;
                     err = e.what();

@@ -21,6 +21,13 @@ Slab gather(vr_context* ctx, const vr_ciphertext* const* cts, u32 n, hipStream_t
 // new handles viewing the slab's ciphertexts (they share its allocation)
 void to_handles(vr_context* ctx, const Slab& sl, vr_ciphertext** out);
 
+// Ciphertexts [begin, end) of a slab key-switch with the keys of ek (one
+// session's share of a serving wave).
+struct KeyRange {
+    u32 begin, end;
+    const vr_eval_keys* ek;
+};
+
 // conv layer over n_sets image sets (set s: ciphertexts s*C_in*w ...)
 Slab conv_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& x, u32 n_sets, u32 C_in, u32 w,
                u32 pad, const double* K, const double* bias, u32 C_out, u32 k, u32 stride,
@@ -48,6 +55,21 @@ struct CnnDesc {
     u32 levels() const { return 1 + square + (fc_out ? 1 : 0); }
 };
 CnnDesc make_desc(vr_context* ctx, const vr_cnn_desc* d, u32 level_in, hipStream_t s);
+// One segment of a serving wave: n_sets image sets of network d under the
+// keys of one session.
+struct NetSeg {
+    const CnnDesc* d;
+    const vr_eval_keys* ek;
+    u32 n_sets;
+};
+// Every segment's network over the slab x, which holds the segments' input
+// columns back to back.  Networks and sessions may differ; the segments must
+// share the conv kernel size, the x^2 flag, FC presence and the FC level,
+// and FC segments come in decreasing block order.  The stages whose keys do
+// not matter (ModUp, ModDown, NTTs, rescale, tensor) run once over all
+// segments, the inner products per session, the linear combinations and
+// weight products per network.  Outputs segment after segment, set after set.
+Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab& x, hipStream_t s);
 // the network on n_sets image sets (slab x, set after set); outputs set after set
 Slab run_cnn(vr_context* ctx, const vr_eval_keys* ek, const CnnDesc& d, const Slab& x, u32 n_sets,
              hipStream_t s);
