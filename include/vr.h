@@ -313,6 +313,20 @@ vr_status vr_conv2d_sets(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphe
 /* x^2 activation on n ciphertexts: Rescale(Relin(Tensor(y, y))). */
 vr_status vr_square(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *in,
                     size_t n, vr_ciphertext **out, void *stream);
+/* Polynomial activation sum_i coeffs[i] x^i (degree >= 1; the cubic
+ * activations of the paper's CNN, "Neural Network Architecture", Table 1) on
+ * n ciphertexts of one level and scale, by Horner's rule: t =
+ * Rescale(MulConst(x, coeffs[d]) at constant scale q_l + coeffs[d-1]), then
+ * t = Rescale(Relin(Tensor(t, x dropped to t's level))) + coeffs[i] for
+ * i = d-2 .. 0.  Depth d (VR_ELEVEL below it); out receives n handles. */
+vr_status vr_poly_eval(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *in, size_t n,
+                       const double *coeffs, uint32_t degree, vr_ciphertext **out, void *stream);
+/* Dense layer on neuron ciphertexts (the last FC of the paper's CNN, Table 1:
+ * each input holds one neuron's value at the same slots):
+ *   out_o = Rescale(sum_j MulConst(in_j, W[o][j]) + AddConst(bias[o])),
+ * W row-major [n_out][n_in] FP64, constants at scale q_l.  One level. */
+vr_status vr_dense(vr_context *ctx, const vr_ciphertext *const *in, uint32_t n_in, const double *W,
+                   const double *bias, uint32_t n_out, vr_ciphertext **out, void *stream);
 /* Fully connected layer on conv outputs Y[c*w_out + j'] (C channels):
  *   Z_o = Rescale(sum_{c,j'} MulPlain(Y, W_pt[o][c*w_out + j'])), then
  *   Z_o += Rot(Z_o, 2^t) for 2^t < block, then AddConst(bias[o]).

@@ -345,3 +345,65 @@ def fc_rotation_steps(Hp):
         steps.append(s)
         s *= 2
     return steps
+
+
+# ------------------------------------------ deeper networks (Table 1 shape)
+
+# The activations of the paper's CNN ("Neural Network Architecture", Table 1):
+# coefficients of a0 + a1 x + a2 x^2 + a3 x^3.
+ACT1 = (-0.00015120704, 0.4610149, 2.0225089, -1.4511951)
+ACT2 = (-1.5650465, -0.9943767, 1.6794522, 0.5350255)
+
+
+def poly_eval(ctx: Context, keys: Keys, ct, coeffs):
+    """sum_i coeffs[i] x^i (degree d >= 1) by Horner's rule:
+    t = MulConst(x, a_d) at constant scale q_l, rescaled, plus a_{d-1}; then
+    for i = d-2 .. 0: t = Rescale(Relin(Tensor(t, x dropped to t's level)))
+    plus a_i.  Depth d; every addition is an AddConst at the running scale."""
+    d = len(coeffs) - 1
+    if d < 1:
+        raise ValueError("degree must be at least 1")
+    t = ctx.rescale(ctx.add_const(ctx.mul_const(ct, coeffs[d], float(ctx.q[ct.level])), coeffs[d - 1]))
+    for i in range(d - 2, -1, -1):
+        x = ctx.mod_drop(ct, t.level)
+        t = ctx.add_const(ctx.rescale(ctx.relinearize(ctx.tensor(t, x), keys)), coeffs[i])
+    return t
+
+
+def ref_poly(x, coeffs):
+    return sum(c * np.asarray(x, np.float64) ** i for i, c in enumerate(coeffs))
+
+
+def dense(ctx: Context, keys: Keys, Z, W, bias):
+    """out_o = Rescale(sum_j MulConst(Z_j, W[o][j]) + AddConst(bias_o)): a
+    fully connected layer on neuron ciphertexts (each holding its neuron's
+    value at the same slots), e.g. the 64 -> 10 FC-2 of Table 1."""
+    W = np.asarray(W, np.float64)
+    dq = float(ctx.q[Z[0].level])
+    out = []
+    for o in range(W.shape[0]):
+        acc = None
+        for j, z in enumerate(Z):
+            t = ctx.mul_const(z, W[o, j], dq)
+            acc = t if acc is None else ctx.add(acc, t)
+        out.append(ctx.rescale(ctx.add_const(acc, float(bias[o]))))
+    return out
+
+
+def deep_cnn(ctx: Context, keys: Keys, cts, C_in, h, w, pad, K, kb, stride, act1, fc_pts, fc_b, Hp, act2, W2, b2):
+    """CONV -> ACT-1 -> FC-1 -> ACT-2 -> FC-2 (the layer sequence of Table 1)
+    on column ciphertexts: the conv schedule, the polynomial activation on
+    every conv output, the FC schedule to neuron ciphertexts (neuron o of
+    image b at slot b Hp), the second activation on every neuron, and the
+    dense FC-2."""
+    Y = conv2d(ctx, keys, cts, C_in, h, w, pad, K, kb, K.shape[0], K.shape[2], stride)
+    Y = [poly_eval(ctx, keys, y, act1) for y in Y]
+    Z = fc(ctx, keys, Y, fc_pts, fc_b, Hp)
+    Z = [poly_eval(ctx, keys, z, act2) for z in Z]
+    return dense(ctx, keys, Z, W2, b2)
+
+
+def ref_deep_cnn(X, K, kb, stride, pad, act1, W1, b1, act2, W2, b2):
+    Y = ref_poly(ref_conv(X, K, kb, stride, pad), act1)
+    Z = ref_poly(ref_fc(Y, W1, b1), act2)
+    return Z @ np.asarray(W2, np.float64).T + np.asarray(b2, np.float64)[None, :]

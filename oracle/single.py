@@ -373,3 +373,22 @@ def rotation_steps_conv(w, k, S):
     steps = {pos % S for pos in range(1, k)} | {(pos * w) % S for pos in range(1, k)}
     steps.discard(0)
     return sorted(steps)
+
+
+# ----------------------------------------------------------------- ReForm
+
+def reform(ops, ct, h, w, k):
+    """ReForm ("Homomorphic CNN Evaluation"): after a unit-stride k x k
+    convolution the outputs occupy the top-left (h - k + 1) x (w - k + 1) of
+    the h x w row-major block; ReForm packs them row-major into the first
+    (h - k + 1)(w - k + 1) slots of the block: row r moves left by r (k - 1)
+    slots and is kept by a mask of its destination -- h' - 1 rotations, h'
+    cMult and h' - 1 Add for h' = h - k + 1 rows (the O(h) of the text)."""
+    hp, wp = h - k + 1, w - k + 1
+    acc = None
+    for r in range(hp):
+        F = np.zeros(h * w)
+        F[r * wp:(r + 1) * wp] = 1.0
+        t = ops.cmul(replicate(F, ops.S), ops.rot(ct, r * (k - 1)))
+        acc = t if acc is None else ops.add(acc, t)
+    return acc

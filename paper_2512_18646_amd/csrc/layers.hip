@@ -515,6 +515,106 @@ Slab rescale_slab(vr_context* ctx, const Slab& in, hipStream_t s)
     return out;
 }
 
+// Dense layer on neuron ciphertexts: out_o = sum_j W[o][j] Z_j (+ bias_o on
+// every slot of c0), W[o][j] as exact residues [RHA(W q_l)]_{q_i} at
+// wq + (o n_in + j) nl + l, bias residues at bq + o nl + l.
+__global__ __launch_bounds__(kThreads) void k_dense(u64* out, u64 out_stride, const u64* Z, u64 z_stride,
+                                                    u32 n_in, const u64* wq, const u64* bq, u32 nl, u32 log_n,
+                                                    const ModQ* mq)
+{
+    const u32 n = 1u << log_n;
+    const u32 t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const u32 comp = blockIdx.y / nl, l = blockIdx.y % nl, o = blockIdx.z;
+    const ModQ m = mq[l];
+    const size_t off = ((size_t)comp * nl + l) * n + t;
+    u64 acc = comp == 0 ? bq[(size_t)o * nl + l] : 0;
+    for (u32 j = 0; j < n_in; j++)
+        acc = add_mod(acc, mul_mod(wq[((size_t)o * n_in + j) * nl + l], Z[(size_t)j * z_stride + off], m), m.q);
+    out[(size_t)o * out_stride + off] = acc;
+}
+
+// the slab's ciphertexts on their first nl limbs (a level drop keeps the message)
+Slab drop_slab(vr_context* ctx, const Slab& x, u32 level, hipStream_t s)
+{
+    if (level == x.level) return x;
+    Slab y = new_slab(ctx, x.n, x.ncomp, level, x.scale, s);
+    const size_t w = (size_t)(level + 1) * ctx->n * sizeof(u64);
+    VR_HIP(hipMemcpy2DAsync(y.base, w, x.base, (size_t)(x.level + 1) * ctx->n * sizeof(u64), w,
+                            (size_t)x.n * x.ncomp, hipMemcpyDeviceToDevice, s));
+    return y;
+}
+
+// AddConst c on every ciphertext of a slab (c0 gets [RHA(c scale)]_{q_l})
+void add_const_slab(vr_context* ctx, const Slab& x, double c, hipStream_t s)
+{
+    LimbConsts k;
+    for (u32 l = 0; l <= x.level; l++) k.c[l] = double_to_mod(c * x.scale, ctx->mod[l]);
+    for (u32 i = 0; i < x.n; i++) launch_add_scalar(ctx, x.ct(i), x.ct(i), x.level + 1, k, s);
+}
+
+// sum_i coeffs[i] x^i by Horner's rule (degree d >= 1, depth d): t =
+// Rescale(MulConst(x, a_d; q_l) + a_{d-1}), then t = Rescale(Relin(Tensor(t,
+// x dropped to t's level))) + a_i for i = d-2 .. 0.
+Slab poly_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& x, const double* coeffs, u32 d,
+               hipStream_t s)
+{
+    if (x.ncomp != 2) throw Error(VR_EINVAL, "polynomial inputs must be 2-component");
+    if (d < 1) throw Error(VR_EINVAL, "degree must be at least 1");
+    if (x.level < d) throw Error(VR_ELEVEL, "not enough levels for the polynomial's depth");
+    const u32 lv = x.level;
+    const double dq = (double)ctx->mod[lv];
+    LimbConsts k;
+    for (u32 l = 0; l <= lv; l++) {
+        k.c[l] = double_to_mod(coeffs[d] * dq, ctx->mod[l]);
+        k.cs[l] = shoup_companion(k.c[l], ctx->mod[l]);
+    }
+    Slab t = new_slab(ctx, x.n, 2, lv, x.scale * dq, s);
+    launch_mul_scalar(ctx, t.base, x.base, 2 * x.n, lv + 1, k, s);
+    add_const_slab(ctx, t, coeffs[d - 1], s);
+    t = rescale_slab(ctx, t, s);
+    for (int i = (int)d - 2; i >= 0; i--) {
+        Slab xd = drop_slab(ctx, x, t.level, s);
+        Slab P = new_slab(ctx, x.n, 3, t.level, t.scale * xd.scale, s);
+        dim3 grid((ctx->n + kThreads - 1) / kThreads, x.n * (t.level + 1));
+        {
+            ProfScope prof(ctx, kProfTensor, s, (u64)x.n * 2 * (t.level + 1));
+            hipLaunchKernelGGL(k_tensor_batch, grid, dim3(kThreads), 0, s, P.base, t.base, xd.base, t.stride,
+                               t.level + 1, ctx->log_n, ctx->d_modq);
+            VR_CHECK_LAUNCH();
+        }
+        t = rescale_slab(ctx, relin_slab(ctx, ek, P, s), s);
+        add_const_slab(ctx, t, coeffs[i], s);
+    }
+    return t;
+}
+
+Slab dense_slab(vr_context* ctx, const Slab& z, const double* W, const double* bias, u32 n_out, hipStream_t s)
+{
+    if (z.ncomp != 2) throw Error(VR_EINVAL, "dense inputs must be 2-component");
+    if (z.level < 1) throw Error(VR_ELEVEL, "dense needs a level to rescale");
+    const u32 nl = z.level + 1, n_in = z.n;
+    const double dq = (double)ctx->mod[z.level];
+    Slab acc = new_slab(ctx, n_out, 2, z.level, z.scale * dq, s);
+    std::vector<u64> h((size_t)n_out * n_in * nl + (size_t)n_out * nl);
+    for (u32 o = 0; o < n_out; o++)
+        for (u32 j = 0; j < n_in; j++)
+            for (u32 l = 0; l < nl; l++)
+                h[((size_t)o * n_in + j) * nl + l] = double_to_mod(W[(size_t)o * n_in + j] * dq, ctx->mod[l]);
+    u64* hb = h.data() + (size_t)n_out * n_in * nl;
+    for (u32 o = 0; o < n_out; o++)
+        for (u32 l = 0; l < nl; l++) hb[(size_t)o * nl + l] = double_to_mod(bias[o] * acc.scale, ctx->mod[l]);
+    BufPtr tab = dev_alloc(ctx, h.size() * sizeof(u64), s);
+    VR_HIP(hipMemcpyAsync(tab->ptr, h.data(), h.size() * sizeof(u64), hipMemcpyHostToDevice, s));
+    dim3 grid((ctx->n + kThreads - 1) / kThreads, 2 * nl, n_out);
+    hipLaunchKernelGGL(k_dense, grid, dim3(kThreads), 0, s, acc.base, acc.stride, z.base, z.stride, n_in,
+                       as_u64(tab), as_u64(tab) + (size_t)n_out * n_in * nl, nl, ctx->log_n, ctx->d_modq);
+    VR_CHECK_LAUNCH();
+    // the host table must outlive the asynchronous copy
+    VR_HIP(hipStreamSynchronize(s));
+    return rescale_slab(ctx, acc, s);
+}
+
 Slab square_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipStream_t s)
 {
     if (in.ncomp != 2) throw Error(VR_EINVAL, "square needs 2-component inputs");
@@ -1307,6 +1407,35 @@ vr_status vr_encode_fc_weights(vr_context* ctx, const double* W, uint32_t n_out,
         W_pt[i] = pt;
     }
     VR_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
+vr_status vr_poly_eval(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* const* in, size_t n,
+                       const double* coeffs, uint32_t degree, vr_ciphertext** out, void* stream)
+{
+    if (out)
+        for (size_t i = 0; i < n; i++) out[i] = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && in && coeffs && out && n >= 1, "null argument");
+    REQUIRE(degree >= 1, "degree must be at least 1");
+    hipStream_t s = pick_stream(ctx, stream);
+    Slab x = gather(ctx, in, (u32)n, s);
+    Slab y = poly_slab(ctx, ek, x, coeffs, degree, s);
+    to_handles(ctx, y, out);
+    API_END
+}
+
+vr_status vr_dense(vr_context* ctx, const vr_ciphertext* const* in, uint32_t n_in, const double* W,
+                   const double* bias, uint32_t n_out, vr_ciphertext** out, void* stream)
+{
+    if (out)
+        for (u32 i = 0; i < n_out; i++) out[i] = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && in && W && bias && out && n_in >= 1 && n_out >= 1, "null argument");
+    hipStream_t s = pick_stream(ctx, stream);
+    Slab z = gather(ctx, in, n_in, s);
+    Slab y = dense_slab(ctx, z, W, bias, n_out, s);
+    to_handles(ctx, y, out);
     API_END
 }
 

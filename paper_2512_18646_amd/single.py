@@ -213,3 +213,18 @@ def vrot(ops, ct, m, n, v, r):
     wrap = np.zeros((m, n))
     wrap[:, v - r:v] = 1.0
     return ops.add(ops.cmul(tile(keep, ops.S), ops.rot(ct, r)), ops.cmul(tile(wrap, ops.S), ops.rot(ct, r - v)))
+
+
+def reform(ops, ct, h, w, k):
+    """ReForm: the (h - k + 1) x (w - k + 1) outputs of a unit-stride
+    convolution, top-left in the h x w block, packed row-major into the
+    block's first slots (row r moves left by r (k - 1) under a mask of its
+    destination)."""
+    hp, wp = h - k + 1, w - k + 1
+    acc = None
+    for r in range(hp):
+        dest = np.zeros(h * w)
+        dest[r * wp:(r + 1) * wp] = 1.0
+        t = ops.cmul(tile(dest, ops.S), ops.rot(ct, r * (k - 1)))
+        acc = t if acc is None else ops.add(acc, t)
+    return acc

@@ -87,6 +87,8 @@ _SIGS = {
     "vr_rotate_many": [P, P, P, P, SZ, PP, P],
     "vr_rotate_batch": [P, P, PP, SZ, I32, PP, P],
     "vr_rotate_noalloc": [P, P, P, U32, I32, P, P],
+    "vr_poly_eval": [P, P, PP, SZ, P, U32, PP, P],
+    "vr_dense": [P, PP, U32, P, P, U32, PP, P],
     "vr_matmul": [P, P, PP, PP, U32, U32, U32, PP, P],
     "vr_matmul_outer": [P, P, PP, PP, U32, U32, U32, PP, P],
     "vr_conv2d": [P, P, PP, U32, U32, U32, U32, P, P, U32, U32, U32, PP, P],
@@ -497,6 +499,23 @@ class Context:
         arr = (ctypes.c_void_p * len(cts))()
         _check(lib.vr_square(self.h, keys.ek, _ptr_array(cts), len(cts), arr, _stream(stream)))
         return [Ciphertext(arr[i], self) for i in range(len(cts))]
+
+    def poly_eval(self, keys, cts, coeffs, stream=None):
+        c = _f64(coeffs)
+        arr = (ctypes.c_void_p * len(cts))()
+        _check(lib.vr_poly_eval(self.h, keys.ek, _ptr_array(cts), len(cts), c.ctypes.data, c.size - 1, arr,
+                                _stream(stream)))
+        return [Ciphertext(arr[i], self) for i in range(len(cts))]
+
+    def dense(self, cts, W, bias, stream=None):
+        W, b = _f64(W), _f64(bias)
+        n_out = b.size
+        if W.size != n_out * len(cts):
+            raise ValueError("dense: W must be n_out x n_in")
+        arr = (ctypes.c_void_p * n_out)()
+        _check(lib.vr_dense(self.h, _ptr_array(cts), len(cts), W.ctypes.data, b.ctypes.data, n_out, arr,
+                            _stream(stream)))
+        return [Ciphertext(arr[i], self) for i in range(n_out)]
 
     def encode_fc_weights(self, W, stride, block, level):
         W = _f64(W)

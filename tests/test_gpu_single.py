@@ -19,7 +19,7 @@ def ctx8():
     p = Params(8, [60, 40, 40, 40, 40, 40], [60], 6, 40.0, allow_insecure=True)
     o = OracleContext(p)
     steps = sorted(set(OS.rotation_steps_matmul(8, 4, 3, o.slots)) | set(OS.rotation_steps_matmul(8, 4, 4, o.slots)) |
-                   set(OS.rotation_steps_conv(8, 3, o.slots)) | {5, 5 - 12})
+                   set(OS.rotation_steps_conv(8, 3, o.slots)) | {5, 5 - 12} | {2 * r for r in range(1, 6)})
     steps = sorted({s % o.slots for s in steps})
     ok = o.keygen(SEED, rot_steps=steps)
     g = gpu_ctx(p)
@@ -121,3 +121,19 @@ def test_single_matmul_gpu_only_end_to_end(ctx8):
     got = GS.matmul(GS.Ops(g, gk, encrypt=encrypt), ctA, ctB, m, n, p)
     C = g.decode(g.decrypt(gk, got))[:m * n].reshape(m, n)[:, :p]
     assert np.max(np.abs(C - A @ B)) / np.max(np.abs(A @ B)) < EPS
+
+
+def test_single_reform_bit_exact(ctx8):
+    from paper_2512_18646_amd import single as GS
+    o, ok, g, gk = ctx8
+    h, w, k = 8, 8, 3
+    X = np.random.default_rng(35).uniform(-1, 1, (h, w))
+    ops = OS.HeOps(o, ok, SEED, 600)
+    ct = ops.enc(OS.replicate(X.reshape(-1), o.slots), level=3)
+    ref = OS.reform(ops, ct, h, w, k)
+    enc, _ = hooks(o, ok, g, 601)
+    got = GS.reform(GS.Ops(g, gk, encode=enc), to_gpu(g, ct), h, w, k)
+    assert_same(got, ref, "ReForm")
+    z = g.decode(g.decrypt(gk, got))[:h * w]
+    hp, wp = h - k + 1, w - k + 1
+    assert np.max(np.abs(z[:hp * wp] - X[:hp, :wp].reshape(-1))) < 1e-6

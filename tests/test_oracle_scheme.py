@@ -426,3 +426,55 @@ def test_conv_special_cases(ctx10):
     Y = Ly.conv2d(ctx, keys, cts, 1, h, w, 0, K2, np.zeros(1), 1, k, s)
     got = Ly.conv_decode(ctx, keys, Y, B, 1, h, 0, k, s, w)
     assert np.max(np.abs(got - 0.6 * K2.sum())) < 1e-6
+
+
+# --------------------------------------------- deeper networks (Table 1)
+
+def test_poly_eval_horner_against_fp64_and_depth():
+    """Horner evaluation of the Table 1 activations: depth equal to the
+    degree, decoded against the FP64 polynomial; degree 1 is one MulConst."""
+    ctx = small_ctx(log_n=9, q_bits=(60, 40, 40, 40, 40), p_bits=(60,), dnum=5)
+    keys = ctx.keygen(8)
+    z = np.random.default_rng(9).uniform(-1, 1, ctx.slots)
+    ct = ctx.encrypt(keys, ctx.encode(z, 4, ctx.scale), 8, 0)
+    for coeffs in (Ly.ACT1, Ly.ACT2, (0.5, -2.0)):
+        y = Ly.poly_eval(ctx, keys, ct, coeffs)
+        assert y.level == 4 - (len(coeffs) - 1)
+        got = ctx.decode(ctx.decrypt(keys, y))
+        assert Ly.rel_error(got, Ly.ref_poly(z, coeffs)) < EPS
+
+
+def test_dense_layer_against_fp64():
+    ctx = small_ctx(log_n=9)
+    keys = ctx.keygen(10)
+    rng = np.random.default_rng(10)
+    Z = rng.uniform(-1, 1, (5, ctx.slots))
+    W, b = rng.normal(0, 0.3, (3, 5)), rng.normal(0, 0.3, 3)
+    cts = [ctx.encrypt(keys, ctx.encode(z, 3, ctx.scale), 10, j) for j, z in enumerate(Z)]
+    out = Ly.dense(ctx, keys, cts, W, b)
+    got = np.stack([ctx.decode(ctx.decrypt(keys, c)) for c in out])
+    assert Ly.rel_error(got, W @ Z + b[:, None]) < EPS
+
+
+def test_deep_cnn_table1_shape_against_fp64():
+    """CONV 3x3 (4 kernels, stride 1) -> ACT-1 -> FC -> ACT-2 -> FC-2 with the
+    paper's activations on 28 x 28 images (FC-1 narrowed to 6 neurons and
+    FC-2 to 3 outputs to keep the oracle fast), decoded logits against the
+    FP64 network."""
+    ctx = small_ctx(log_n=10, q_bits=(60,) + (40,) * 9, p_bits=(60,), dnum=10)
+    B, h, w, k, Co = 4, 28, 28, 3, 4
+    Hp = Ly.image_block(h, 0)
+    keys = ctx.keygen(11, rot_steps=[1, 2] + Ly.fc_rotation_steps(Hp))
+    rng = np.random.default_rng(11)
+    X = rng.uniform(0, 1, (B, 1, h, w))
+    K, kb = rng.normal(0, 0.1, (Co, 1, k, k)), rng.normal(0, 0.1, Co)
+    ho = wo = h - k + 1
+    W1, b1 = rng.normal(0, 0.01, (6, Co, ho, wo)), rng.normal(0, 0.05, 6)
+    W2, b2 = rng.normal(0, 0.3, (3, 6)), rng.normal(0, 0.3, 3)
+    cts = Ly.encrypt_image_columns(ctx, keys, X, 0, 9, 11, 0)
+    pts = Ly.fc_plaintexts(ctx, W1, Co, ho, wo, 1, Hp, 5)
+    out = Ly.deep_cnn(ctx, keys, cts, 1, h, w, 0, K, kb, 1, Ly.ACT1, pts, b1, Hp, Ly.ACT2, W2, b2)
+    assert out[0].level == 0
+    got = Ly.fc_decode(ctx, keys, out, B, Hp)
+    ref = Ly.ref_deep_cnn(X, K, kb, 1, 0, Ly.ACT1, W1, b1, Ly.ACT2, W2, b2)
+    assert Ly.rel_error(got, ref) < EPS

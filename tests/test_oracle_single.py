@@ -209,3 +209,21 @@ def test_conv_encrypted_weights_against_fp64(ctx8):
         for c in range(w - k + 1):
             ref[r, c] = k0 + np.sum(K * I[r:r + k, c:c + k])
     assert np.max(np.abs(got - ref)) / np.max(np.abs(ref)) < EPS
+
+
+@pytest.mark.parametrize("h,w,k", [(3, 3, 2), (8, 8, 3), (4, 8, 2), (8, 4, 3)])
+def test_reform_packs_the_valid_region(h, w, k):
+    """The printed 3 x 3 -> 2 x 2 example and larger shapes: the valid region
+    row-major in the first h' w' slots, zero after it, junk elsewhere in the
+    input ignored; h' - 1 rotations, h' cMult, h' - 1 Add."""
+    blk = h * w
+    S = 4 * blk if blk & (blk - 1) == 0 else blk    # the printed 3 x 3 fills its ciphertext
+    rng = np.random.default_rng(h + w + k)
+    J = rng.integers(1, 100, (h, w)).astype(float)     # valid region plus junk outside it
+    x = J.reshape(-1)
+    ops = Sg.PlainOps(S)
+    hp, wp = h - k + 1, w - k + 1
+    got = Sg.reform(ops, Sg.replicate(x, S), h, w, k)[:blk]
+    assert np.array_equal(got[:hp * wp], J[:hp, :wp].reshape(-1))
+    assert not got[hp * wp:].any()
+    assert ops.count["Rot"] == hp - 1 and ops.count["cMult"] == hp and ops.count["Add"] == hp - 1
