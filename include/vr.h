@@ -313,6 +313,28 @@ vr_status vr_conv2d_sets(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphe
 /* x^2 activation on n ciphertexts: Rescale(Relin(Tensor(y, y))). */
 vr_status vr_square(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *in,
                     size_t n, vr_ciphertext **out, void *stream);
+/* Encrypted-weight mode (the paper's usage model, "Homomorphic CNN
+ * Evaluation": the model provider encrypts the weights, the cloud sees none
+ * in the clear).  The conv of vr_conv2d with K_ct[((c' C_in + c) k + u) k + v]
+ * encrypting K[c'][c][u][v] in every slot at scale q_l (same level as the
+ * inputs) and bias_ct[c'] encrypting the bias in every slot one level lower
+ * at the rescaled products' scale ((input scale q_l) / q_l as a double):
+ *   Y(c', j') = Rescale(Relin(sum_{c,u,v} Tensor(Rot(col(c, s j'+v-pi), u),
+ *               K_ct[c', c, u, v]))) + bias_ct[c']
+ * (one lazy relinearisation per output).  VR_ESCALE / VR_ELEVEL when the
+ * bias ciphertexts do not match.  out receives C_out * w_out handles. */
+vr_status vr_conv2d_encw(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *in, uint32_t C_in,
+                         uint32_t h, uint32_t w, uint32_t pad, const vr_ciphertext *const *K_ct,
+                         const vr_ciphertext *const *bias_ct, uint32_t C_out, uint32_t k, uint32_t stride,
+                         vr_ciphertext **out, void *stream);
+/* The FC of vr_fc with encrypted weights: W_ct[o n_in + i] encrypts the
+ * weight pattern vr_encode_fc_weights encodes (scale q_l, the inputs'
+ * level), bias_ct[o] the bias in every slot one level lower at the rescaled
+ * scale:  Z_o = RotSum_block(Rescale(Relin(sum_i Tensor(Y_i, W_ct[o][i])))) +
+ * bias_ct[o]. */
+vr_status vr_fc_encw(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *Y, uint32_t n_in,
+                     const vr_ciphertext *const *W_ct, const vr_ciphertext *const *bias_ct, uint32_t n_out,
+                     uint32_t block, vr_ciphertext **out, void *stream);
 /* Polynomial activation sum_i coeffs[i] x^i (degree >= 1; the cubic
  * activations of the paper's CNN, "Neural Network Architecture", Table 1) on
  * n ciphertexts of one level and scale, by Horner's rule: t =

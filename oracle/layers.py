@@ -407,3 +407,97 @@ def ref_deep_cnn(X, K, kb, stride, pad, act1, W1, b1, act2, W2, b2):
     Y = ref_poly(ref_conv(X, K, kb, stride, pad), act1)
     Z = ref_poly(ref_fc(Y, W1, b1), act2)
     return Z @ np.asarray(W2, np.float64).T + np.asarray(b2, np.float64)[None, :]
+
+
+# ------------------------------------------------ encrypted-weight layers
+
+def conv2d_encw(ctx: Context, keys: Keys, cts, C_in, h, w, pad, Kct, bias_ct, C_out, k, stride):
+    """The conv schedule with encrypted weights (the paper's usage model: the
+    model provider encrypts the kernels and the cloud sees no weight in the
+    clear).  Kct[((c' C_in + c) k + u) k + v] encrypts K[c'][c][u][v] in every
+    slot at scale q_l; bias_ct[c'] encrypts the bias in every slot one level
+    lower, at the scale the rescaled sum carries.  Each output is a sum of
+    ct x ct products relinearised once (lazy relinearisation):
+        Y(c', j') = Rescale(Relin(sum_{c,u,v} Tensor(Rot(col(c, s j'+v-pi), u),
+                    Kct[c', c, u, v]))) + bias_ct[c'].  One level."""
+    wo = conv_out_size(w, pad, k, stride)
+    rot = {}
+
+    def rotated(c, j):
+        if (c, j) not in rot:
+            ct = cts[c * w + j]
+            rot[(c, j)] = [ct] + ctx.rotate_many(ct, list(range(1, k)), keys)
+        return rot[(c, j)]
+
+    out = []
+    for co in range(C_out):
+        for jo in range(wo):
+            acc = None
+            for c in range(C_in):
+                for v in range(k):
+                    jj = stride * jo + v - pad
+                    if jj < 0 or jj >= w:
+                        continue
+                    for u in range(k):
+                        t = ctx.tensor(rotated(c, jj)[u], Kct[((co * C_in + c) * k + u) * k + v])
+                        acc = t if acc is None else ctx.add(acc, t)
+            out.append(ctx.add(ctx.rescale(ctx.relinearize(acc, keys)), bias_ct[co]))
+    return out
+
+
+def encrypt_conv_weights(ctx: Context, keys: Keys, K, bias, level, x_scale, seed, first_ct_id):
+    """The model provider's ciphertexts for conv2d_encw: every weight in every
+    slot at scale q_level; every bias in every slot at level - 1 and the scale
+    a rescaled product carries, (x_scale q_level) / q_level as a double."""
+    K = np.asarray(K, np.float64)
+    dq = float(ctx.q[level])
+    kct = [ctx.encrypt(keys, ctx.encode(np.full(ctx.slots, wv), level, dq), seed, first_ct_id + i)
+           for i, wv in enumerate(K.reshape(-1))]
+    bscale = (x_scale * dq) / dq
+    bct = [ctx.encrypt(keys, ctx.encode(np.full(ctx.slots, float(b)), level - 1, bscale), seed,
+                       first_ct_id + K.size + i) for i, b in enumerate(bias)]
+    return kct, bct
+
+
+def fc_encw(ctx: Context, keys: Keys, Y, Wct, bias_ct, Hp):
+    """FC with encrypted weights: Wct[o][i] encrypts the weight pattern of
+    fc_plaintexts (scale q_l) and bias_ct[o] the bias in every slot one level
+    lower at the scale the rescaled sum carries (see encrypt_fc_weights):
+        Z_o = RotSum_Hp(Rescale(Relin(sum_i Tensor(Y_i, Wct[o][i])))) + bias_ct[o],
+    one relinearisation per output (lazy)."""
+    out = []
+    for o, row in enumerate(Wct):
+        acc = None
+        for y, wct in zip(Y, row):
+            t = ctx.tensor(y, wct)
+            acc = t if acc is None else ctx.add(acc, t)
+        z = ctx.rescale(ctx.relinearize(acc, keys))
+        step = 1
+        while step < Hp:
+            z = ctx.add(z, ctx.rotate(z, step, keys))
+            step *= 2
+        out.append(ctx.add(z, bias_ct[o]))
+    return out
+
+
+def encrypt_fc_weights(ctx: Context, keys: Keys, W, bias, C, ho, wo, stride, Hp, level, y_scale, seed,
+                       first_ct_id):
+    """The model provider's ciphertexts for fc_encw: the weight patterns of
+    fc_plaintexts encrypted at scale q_level, and each bias in every slot at
+    level - 1 and scale (y_scale q_level) / q_level."""
+    pts = fc_plaintexts(ctx, W, C, ho, wo, stride, Hp, level)
+    dq = float(ctx.q[level])
+    i = first_ct_id
+    wct = []
+    for row in pts:
+        r = []
+        for pt in row:
+            r.append(ctx.encrypt(keys, pt, seed, i))
+            i += 1
+        wct.append(r)
+    bct = []
+    for b in bias:
+        bct.append(ctx.encrypt(keys, ctx.encode(np.full(ctx.slots, float(b)), level - 1, (y_scale * dq) / dq),
+                               seed, i))
+        i += 1
+    return wct, bct

@@ -515,6 +515,42 @@ Slab rescale_slab(vr_context* ctx, const Slab& in, hipStream_t s)
     return out;
 }
 
+// Sums of ct x ct tensor products for the encrypted-weight layers: output z
+// (group g = z / n_sub, term list z mod n_sub) is
+//   sum_t Tensor(A(term_a[t]), B + g b_group + term_b[t])   (3 components),
+// A(o) = A1 + (o & ~top) when the top bit of o is set, else A0 + o (word
+// offsets); a_comp / b_comp are the operands' component strides.
+__global__ __launch_bounds__(kThreads) void k_tensor_terms(u64* out, u64 out_stride, const u64* A0, const u64* A1,
+                                                           const u64* B, u64 b_group, const u64* term_a,
+                                                           const u64* term_b, const u32* term_off, u32 n_sub,
+                                                           u32 nl, u64 a_comp, u64 b_comp, u32 log_n,
+                                                           const ModQ* mq)
+{
+    const u32 n = 1u << log_n;
+    const u32 t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const u32 l = blockIdx.y, z = blockIdx.z;
+    const u32 g = z / n_sub, sub = z - g * n_sub;
+    const ModQ m = mq[l];
+    const size_t off = (size_t)l * n + t;
+    const u64* Bg = B + (size_t)g * b_group;
+    u64 d0 = 0, d1 = 0, d2 = 0;
+    for (u32 k = term_off[sub]; k < term_off[sub + 1]; k++) {
+        const u64 ao = term_a[k];
+        const u64* a = ((ao >> 63) ? A1 + (ao & ~(1ull << 63)) : A0 + ao) + off;
+        const u64* b = Bg + term_b[k] + off;
+        const u64 a0 = a[0], a1 = a[a_comp], b0 = b[0], b1 = b[b_comp];
+        d0 = add_mod(d0, mul_mod(a0, b0, m), m.q);
+        d1 = add_mod(d1, add_mod(mul_mod(a0, b1, m), mul_mod(a1, b0, m), m.q), m.q);
+        d2 = add_mod(d2, mul_mod(a1, b1, m), m.q);
+    }
+    u64* o = out + (size_t)z * out_stride + off;
+    const size_t oc = (size_t)nl * n;
+    o[0] = d0;
+    o[oc] = d1;
+    o[2 * oc] = d2;
+}
+
 // Dense layer on neuron ciphertexts: out_o = sum_j W[o][j] Z_j (+ bias_o on
 // every slot of c0), W[o][j] as exact residues [RHA(W q_l)]_{q_i} at
 // wq + (o n_in + j) nl + l, bias residues at bq + o nl + l.
@@ -613,6 +649,101 @@ Slab dense_slab(vr_context* ctx, const Slab& z, const double* W, const double* b
     // the host table must outlive the asynchronous copy
     VR_HIP(hipStreamSynchronize(s));
     return rescale_slab(ctx, acc, s);
+}
+
+// Encrypted-weight layers: the products summed per output, one
+// relinearisation and rescale for all outputs, then the bias ciphertexts
+// (one level lower, at the rescaled scale) added.
+Slab tensor_terms_slab(vr_context* ctx, const Slab& x, const Slab* rot_all, const Slab& W, u64 w_group,
+                       const std::vector<u64>& ta, const std::vector<u64>& tb, const std::vector<u32>& toff,
+                       u32 n_sub, u32 n_out, hipStream_t s)
+{
+    if (W.level != x.level) throw Error(VR_ELEVEL, "weight ciphertexts must sit at the inputs' level");
+    const u32 nl = x.level + 1;
+    Slab T = new_slab(ctx, n_out, 3, x.level, x.scale * W.scale, s);
+    BufPtr tab = dev_alloc(ctx, (ta.size() + tb.size()) * sizeof(u64) + toff.size() * sizeof(u32), s);
+    u64* dta = as_u64(tab);
+    u64* dtb = dta + ta.size();
+    u32* doff = (u32*)(dtb + tb.size());
+    VR_HIP(hipMemcpyAsync(dta, ta.data(), ta.size() * sizeof(u64), hipMemcpyHostToDevice, s));
+    VR_HIP(hipMemcpyAsync(dtb, tb.data(), tb.size() * sizeof(u64), hipMemcpyHostToDevice, s));
+    VR_HIP(hipMemcpyAsync(doff, toff.data(), toff.size() * sizeof(u32), hipMemcpyHostToDevice, s));
+    dim3 grid((ctx->n + kThreads - 1) / kThreads, nl, n_out);
+    {
+        ProfScope prof(ctx, kProfTensor, s, (u64)n_out * 2 * nl);
+        hipLaunchKernelGGL(k_tensor_terms, grid, dim3(kThreads), 0, s, T.base, T.stride, x.base,
+                           rot_all ? rot_all->base : x.base, W.base, w_group, dta, dtb, doff, n_sub, nl,
+                           (u64)nl * ctx->n, (u64)nl * ctx->n, ctx->log_n, ctx->d_modq);
+        VR_CHECK_LAUNCH();
+    }
+    VR_HIP(hipStreamSynchronize(s));   // the host term tables must outlive their copies
+    return T;
+}
+
+void add_bias_cts(vr_context* ctx, const Slab& y, const Slab& bias, u32 per_bias, hipStream_t s)
+{
+    if (bias.level != y.level) throw Error(VR_ELEVEL, "bias ciphertexts must sit one level below the weights");
+    if (bias.scale != y.scale) throw Error(VR_ESCALE, "bias ciphertexts must carry the rescaled products' scale");
+    if (bias.ncomp != 2) throw Error(VR_EINVAL, "bias ciphertexts must be 2-component");
+    for (u32 i = 0; i < y.n; i++)
+        launch_addsub(ctx, y.ct(i), y.ct(i), bias.ct(i / per_bias), 2, y.level + 1, false, s);
+}
+
+Slab conv_encw_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& x, u32 C_in, u32 w, u32 pad,
+                    const Slab& Kw, const Slab& Bias, u32 C_out, u32 k, u32 stride, hipStream_t s)
+{
+    if (x.ncomp != 2 || Kw.ncomp != 2) throw Error(VR_EINVAL, "inputs and weights must be 2-component");
+    if (Kw.n != C_out * C_in * k * k || Bias.n != C_out) throw Error(VR_EINVAL, "weight or bias count");
+    const u32 wo = (w + 2 * pad - k) / stride + 1;
+    std::vector<int32_t> steps;
+    for (u32 u = 1; u < k; u++) steps.push_back((int32_t)u);
+    std::vector<Slab> rot;
+    if (!steps.empty()) rotate_slab(ctx, ek, x, steps, rot, s);
+    const u32 n_x = C_in * w;
+    std::vector<u64> ta, tb;
+    std::vector<u32> toff{0};
+    for (u32 jo = 0; jo < wo; jo++) {
+        for (u32 c = 0; c < C_in; c++)
+            for (u32 v = 0; v < k; v++) {
+                const int jj = (int)(stride * jo + v) - (int)pad;
+                if (jj < 0 || jj >= (int)w) continue;
+                for (u32 u = 0; u < k; u++) {
+                    const u64 col = (u64)c * w + (u32)jj;
+                    ta.push_back(u == 0 ? col * x.stride
+                                        : ((u64)1 << 63) | (((u64)(u - 1) * n_x + col) * x.stride));
+                    tb.push_back((((u64)c * k + u) * k + v) * Kw.stride);
+                }
+            }
+        toff.push_back((u32)ta.size());
+    }
+    Slab T = tensor_terms_slab(ctx, x, rot.empty() ? nullptr : &rot[0], Kw, (u64)C_in * k * k * Kw.stride, ta,
+                               tb, toff, wo, C_out * wo, s);
+    rot.clear();
+    Slab y = rescale_slab(ctx, relin_slab(ctx, ek, T, s), s);
+    add_bias_cts(ctx, y, Bias, wo, s);
+    return y;
+}
+
+Slab fc_encw_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& y, const Slab& Wc, const Slab& Bias,
+                  u32 n_out, u32 block, hipStream_t s)
+{
+    if (Wc.n != n_out * y.n || Bias.n != n_out) throw Error(VR_EINVAL, "weight or bias count");
+    std::vector<u64> ta, tb;
+    std::vector<u32> toff{0};
+    for (u32 i = 0; i < y.n; i++) {
+        ta.push_back((u64)i * y.stride);
+        tb.push_back((u64)i * Wc.stride);
+    }
+    toff.push_back((u32)ta.size());
+    Slab T = tensor_terms_slab(ctx, y, nullptr, Wc, (u64)y.n * Wc.stride, ta, tb, toff, 1, n_out, s);
+    Slab z = rescale_slab(ctx, relin_slab(ctx, ek, T, s), s);
+    for (u32 st = 1; st < block; st <<= 1) {
+        std::vector<Slab> r;
+        rotate_slab(ctx, ek, z, {(int32_t)st}, r, s);
+        launch_addsub(ctx, z.base, z.base, r[0].base, z.n * 2, z.level + 1, false, s);
+    }
+    add_bias_cts(ctx, z, Bias, 1, s);
+    return z;
 }
 
 Slab square_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipStream_t s)
@@ -1407,6 +1538,45 @@ vr_status vr_encode_fc_weights(vr_context* ctx, const double* W, uint32_t n_out,
         W_pt[i] = pt;
     }
     VR_HIP(hipStreamSynchronize(s));
+    API_END
+}
+
+vr_status vr_conv2d_encw(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* const* in, uint32_t C_in,
+                         uint32_t h, uint32_t w, uint32_t pad, const vr_ciphertext* const* K_ct,
+                         const vr_ciphertext* const* bias_ct, uint32_t C_out, uint32_t k, uint32_t stride,
+                         vr_ciphertext** out, void* stream)
+{
+    const u32 wo = (k >= 1 && stride >= 1 && w + 2 * pad >= k) ? (w + 2 * pad - k) / stride + 1 : 0;
+    if (out)
+        for (u32 i = 0; i < C_out * wo; i++) out[i] = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && in && K_ct && bias_ct && out, "null argument");
+    REQUIRE(C_in >= 1 && C_out >= 1 && k >= 1 && stride >= 1 && pad < k && wo >= 1 && h + 2 * pad >= k,
+            "bad conv shape");
+    hipStream_t s = pick_stream(ctx, stream);
+    Slab x = gather(ctx, in, C_in * w, s);
+    Slab Kw = gather(ctx, K_ct, C_out * C_in * k * k, s);
+    Slab B = gather(ctx, bias_ct, C_out, s);
+    Slab y = conv_encw_slab(ctx, ek, x, C_in, w, pad, Kw, B, C_out, k, stride, s);
+    to_handles(ctx, y, out);
+    API_END
+}
+
+vr_status vr_fc_encw(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* const* Y, uint32_t n_in,
+                     const vr_ciphertext* const* W_ct, const vr_ciphertext* const* bias_ct, uint32_t n_out,
+                     uint32_t block, vr_ciphertext** out, void* stream)
+{
+    if (out)
+        for (u32 i = 0; i < n_out; i++) out[i] = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && Y && W_ct && bias_ct && out && n_in >= 1 && n_out >= 1, "null argument");
+    REQUIRE(block >= 1 && (block & (block - 1)) == 0 && block <= ctx->slots, "block must be a power of two <= S");
+    hipStream_t s = pick_stream(ctx, stream);
+    Slab y = gather(ctx, Y, n_in, s);
+    Slab Wc = gather(ctx, W_ct, n_out * n_in, s);
+    Slab B = gather(ctx, bias_ct, n_out, s);
+    Slab z = fc_encw_slab(ctx, ek, y, Wc, B, n_out, block, s);
+    to_handles(ctx, z, out);
     API_END
 }
 

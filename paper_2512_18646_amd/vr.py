@@ -88,6 +88,8 @@ _SIGS = {
     "vr_rotate_batch": [P, P, PP, SZ, I32, PP, P],
     "vr_rotate_noalloc": [P, P, P, U32, I32, P, P],
     "vr_poly_eval": [P, P, PP, SZ, P, U32, PP, P],
+    "vr_conv2d_encw": [P, P, PP, U32, U32, U32, U32, PP, PP, U32, U32, U32, PP, P],
+    "vr_fc_encw": [P, P, PP, U32, PP, PP, U32, U32, PP, P],
     "vr_dense": [P, PP, U32, P, P, U32, PP, P],
     "vr_matmul": [P, P, PP, PP, U32, U32, U32, PP, P],
     "vr_matmul_outer": [P, P, PP, PP, U32, U32, U32, PP, P],
@@ -499,6 +501,20 @@ class Context:
         arr = (ctypes.c_void_p * len(cts))()
         _check(lib.vr_square(self.h, keys.ek, _ptr_array(cts), len(cts), arr, _stream(stream)))
         return [Ciphertext(arr[i], self) for i in range(len(cts))]
+
+    def conv2d_encw(self, keys, cols, C_in, h, w, pad, K_ct, bias_ct, C_out, k, stride, stream=None):
+        wo = (w + 2 * pad - k) // stride + 1
+        arr = (ctypes.c_void_p * (C_out * wo))()
+        _check(lib.vr_conv2d_encw(self.h, keys.ek, _ptr_array(cols), C_in, h, w, pad, _ptr_array(K_ct),
+                                  _ptr_array(bias_ct), C_out, k, stride, arr, _stream(stream)))
+        return [Ciphertext(arr[i], self) for i in range(C_out * wo)]
+
+    def fc_encw(self, keys, Y, W_ct, bias_ct, block, stream=None):
+        n_out = len(bias_ct)
+        arr = (ctypes.c_void_p * n_out)()
+        _check(lib.vr_fc_encw(self.h, keys.ek, _ptr_array(Y), len(Y), _ptr_array(W_ct), _ptr_array(bias_ct),
+                              n_out, block, arr, _stream(stream)))
+        return [Ciphertext(arr[i], self) for i in range(n_out)]
 
     def poly_eval(self, keys, cts, coeffs, stream=None):
         c = _f64(coeffs)

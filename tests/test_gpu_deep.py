@@ -68,3 +68,35 @@ def test_deep_cnn_table1_shape_bit_exact(deep):
         logits[:, oi] = g.decode(g.decrypt(gk, z))[np.arange(B) * Hp]
     expect = Ly.ref_deep_cnn(X, K, kb, 1, 0, Ly.ACT1, W1, b1, Ly.ACT2, W2, b2)
     assert Ly.rel_error(logits, expect) < EPS
+
+
+def test_encrypted_weight_conv_and_fc_bit_exact():
+    """Encrypted-weight conv and FC (ct x ct products, one lazy
+    relinearisation per output, bias ciphertexts added after the rescale):
+    limb for limb against the oracle, decoded against FP64."""
+    from tests.gpu_helpers import pair
+    o, ok, g, gk = pair("C1", rot_steps=(1, 2, 4, 8), log_n=10)
+    B, Ci, h, w, Co, k, s, pad = 8, 2, 10, 9, 3, 3, 2, 1
+    rng = np.random.default_rng(15)
+    X = rng.uniform(0, 1, (B, Ci, h, w))
+    K, bias = rng.normal(0, 0.1, (Co, Ci, k, k)), rng.normal(0, 0.1, Co)
+    cts = Ly.encrypt_image_columns(o, ok, X, pad, 3, 15, 0)
+    kct, bct = Ly.encrypt_conv_weights(o, ok, K, bias, 3, cts[0].scale, 16, 0)
+    Y = Ly.conv2d_encw(o, ok, cts, Ci, h, w, pad, kct, bct, Co, k, s)
+    gY = g.conv2d_encw(gk, [to_gpu(g, c) for c in cts], Ci, h, w, pad, [to_gpu(g, c) for c in kct],
+                       [to_gpu(g, c) for c in bct], Co, k, s)
+    for i, (x, y) in enumerate(zip(gY, Y)):
+        assert_same(x, y, "encrypted-weight conv %d" % i)
+    Hp = Ly.image_block(h, pad)
+    ref = Ly.ref_conv(X, K, bias, s, pad)
+    ho, wo = ref.shape[2], ref.shape[3]
+    W, fb = rng.normal(0, 0.05, (4, Co, ho, wo)), rng.normal(0, 0.05, 4)
+    wct, fbct = Ly.encrypt_fc_weights(o, ok, W, fb, Co, ho, wo, s, Hp, 2, Y[0].scale, 17, 0)
+    Z = Ly.fc_encw(o, ok, Y, wct, fbct, Hp)
+    gZ = g.fc_encw(gk, gY, [to_gpu(g, c) for row in wct for c in row], [to_gpu(g, c) for c in fbct], Hp)
+    for i, (x, y) in enumerate(zip(gZ, Z)):
+        assert_same(x, y, "encrypted-weight fc %d" % i)
+    logits = np.zeros((B, 4))
+    for oi, z in enumerate(gZ):
+        logits[:, oi] = g.decode(g.decrypt(gk, z))[np.arange(B) * Hp]
+    assert Ly.rel_error(logits, Ly.ref_fc(ref, W, fb)) < EPS

@@ -478,3 +478,30 @@ def test_deep_cnn_table1_shape_against_fp64():
     got = Ly.fc_decode(ctx, keys, out, B, Hp)
     ref = Ly.ref_deep_cnn(X, K, kb, 1, 0, Ly.ACT1, W1, b1, Ly.ACT2, W2, b2)
     assert Ly.rel_error(got, ref) < EPS
+
+
+# ------------------------------------------------ encrypted-weight mode
+
+def test_encrypted_weight_conv_and_fc_against_fp64(ctx10):
+    """Conv and FC with encrypted weights (ct x ct products, one lazy
+    relinearisation per output) decode to the FP64 layers; with the same
+    weights the conv output decodes like the plaintext-weight schedule."""
+    ctx, keys = ctx10
+    B, Ci, h, w, Co, k, s, pad = 8, 2, 10, 9, 3, 3, 2, 1
+    rng = np.random.default_rng(15)
+    X = rng.uniform(0, 1, (B, Ci, h, w))
+    K, bias = rng.normal(0, 0.1, (Co, Ci, k, k)), rng.normal(0, 0.1, Co)
+    cts = Ly.encrypt_image_columns(ctx, keys, X, pad, 3, 15, 0)
+    kct, bct = Ly.encrypt_conv_weights(ctx, keys, K, bias, 3, cts[0].scale, 16, 0)
+    Y = Ly.conv2d_encw(ctx, keys, cts, Ci, h, w, pad, kct, bct, Co, k, s)
+    assert Y[0].level == 2 and Y[0].ncomp == 2
+    ref = Ly.ref_conv(X, K, bias, s, pad)
+    got = Ly.conv_decode(ctx, keys, Y, B, Co, h, pad, k, s, w)
+    assert Ly.rel_error(got, ref) < EPS
+    Hp = Ly.image_block(h, pad)
+    ho, wo = ref.shape[2], ref.shape[3]
+    W, fb = rng.normal(0, 0.05, (4, Co, ho, wo)), rng.normal(0, 0.05, 4)
+    wct, fbct = Ly.encrypt_fc_weights(ctx, keys, W, fb, Co, ho, wo, s, Hp, 2, Y[0].scale, 17, 0)
+    Z = Ly.fc_encw(ctx, keys, Y, wct, fbct, Hp)
+    logits = Ly.fc_decode(ctx, keys, Z, B, Hp)
+    assert Ly.rel_error(logits, Ly.ref_fc(ref, W, fb)) < EPS
