@@ -182,6 +182,12 @@ vr_status vr_encrypt_columns(vr_context *ctx, const vr_eval_keys *ek, const doub
  * A'_{t,k} at index t n + k (T = ceil(m / R), R = S / P'), slot r P' + j ->
  * A[t R + r][k] for j < p and t R + r < m; role 3: M is B (n x p), n
  * ciphertexts B'_k, slot r P' + j -> B[k][j] for j < p and every r < R.
+ * Column-block operands (vr_matmul_block; blocks of Mb = P' ceil((m + P' -
+ * 1) / P') slots, c columns per ciphertext, nb = ceil(n / c) ciphertexts,
+ * see vr_matmul_plan): role 4: M is A (m x n), block j of ciphertext K holds
+ * column K c + j of A in its first m slots; role 5: M is B (n x p), block j
+ * holds row K c + j of B, entry r mod P' in slot r of the block (r mod P' <
+ * p).  out receives nb handles for roles 4 and 5.
  * Ciphertext i is encrypted with ct_id = first_ct_id + i (ranges of
  * different calls under one seed and public key must not overlap). */
 vr_status vr_encrypt_matrix_columns(vr_context *ctx, const vr_eval_keys *ek, const double *M,
@@ -290,6 +296,38 @@ vr_status vr_matmul(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext
 vr_status vr_matmul_outer(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *A,
                           const vr_ciphertext *const *B, uint32_t m, uint32_t n, uint32_t p,
                           vr_ciphertext **C, void *stream);
+
+/* Column-block form of the column-split product: c columns per ciphertext
+ * (roles 4 / 5 of vr_encrypt_matrix_columns), each in a block padded by P' -
+ * 1 slots past m so that every rotated read of Bbar stays in its own block
+ * wherever A is non-zero (no RowShifter fix-up):
+ *   D[idx] = Rescale(Relin(sum_K A_K * Rot(Bbar_K, idx))), idx < P',
+ * then the c blocks folded into block 0, D += Rot(D, Mb 2^t) for t <
+ * log2 c.  Slot i < m of C[idx] holds (A B)[i][(i + idx) mod P'].  Needs
+ * m >= p; rotation keys for steps 1..P'-1 and Mb 2^t.  nb (P' - 1) + P'
+ * log2 c rotations against n (P' - 1) for the column-split form.  C
+ * receives P' handles. */
+vr_status vr_matmul_block(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *A,
+                          const vr_ciphertext *const *Bbar, uint32_t m, uint32_t n, uint32_t p,
+                          vr_ciphertext **C, void *stream);
+
+/* Cost-model planner for one product A (m x n) B (n x p) at `level`: fills
+ * costs[form] for the column-split (vr_matmul), column-block
+ * (vr_matmul_block) and outer-product (vr_matmul_outer) forms -- the client's
+ * ciphertext count (its upload), key switches (rotations and
+ * relinearisations), tensors, and an estimated device time from the limb
+ * passes each form streams (at 5 TB/s effective) -- and picks the cheapest
+ * feasible form whose client ciphertexts fit max_client_cts (0: no limit).
+ * For m < p the column forms multiply the transposes (transposed = 1: the
+ * client encodes B^T as A and A^T as B).  VR_EINVAL when no form fits. */
+enum { VR_MATMUL_COLUMN_SPLIT = 0, VR_MATMUL_COLUMN_BLOCK = 1, VR_MATMUL_OUTER = 2, VR_MATMUL_NONE = 0xffffffffu };
+typedef struct {
+    uint32_t feasible, transposed;
+    uint64_t client_cts, key_switches, tensors;
+    double est_us;
+} vr_matmul_cost;
+vr_status vr_matmul_plan(vr_context *ctx, uint32_t m, uint32_t n, uint32_t p, uint32_t level,
+                         uint64_t max_client_cts, vr_matmul_cost costs[3], uint32_t *chosen);
 /* Column convolution (conv layer of "Convolutional Neural Networks", with
  * per-channel accumulation of "Parallelized Convolution Operation"): inputs
  * in[c*w + j] from vr_encrypt_columns; K is [C_out][C_in][k][k], bias

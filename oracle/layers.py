@@ -501,3 +501,81 @@ def encrypt_fc_weights(ctx: Context, keys: Keys, W, bias, C, ho, wo, stride, Hp,
                                seed, i))
         i += 1
     return wct, bct
+
+
+# ------------------------------------- column-block packing of the product
+
+def block_shape(ctx: Context, m, n, p):
+    """(P', Mb, c, nb) of the column-block form: blocks of Mb = P' ceil((m +
+    P' - 1) / P') slots (a multiple of P', at least m + P' - 1), c = the
+    largest power of two with c Mb <= S and c <= pow2(n) columns per
+    ciphertext, nb = ceil(n / c) ciphertexts per operand."""
+    Pp = pow2ceil(p)
+    Mb = Pp * -(-(m + Pp - 1) // Pp)
+    if Mb > ctx.slots:
+        raise ValueError("m + P' - 1 exceeds the slot count")
+    c = 1
+    while 2 * c * Mb <= ctx.slots and c < pow2ceil(n):
+        c *= 2
+    return Pp, Mb, c, -(-n // c)
+
+
+def matrix_block_slots(ctx: Context, M, K, role, m, n, p):
+    """Ciphertext K of the column-block form (NEXT to the column-split form:
+    c columns per ciphertext instead of one).  role 4 (A): block j holds
+    column K c + j of A in its first m slots; role 5 (Bbar): block j holds row
+    K c + j of B, entry j' in every slot r with r mod P' = j' < p.  Zero past
+    the n columns, past m rows / p columns and past the c blocks."""
+    M = np.asarray(M, np.float64)
+    Pp, Mb, c, nb = block_shape(ctx, m, n, p)
+    z = np.zeros(ctx.slots)
+    for j in range(c):
+        col = K * c + j
+        if col >= n:
+            break
+        base = j * Mb
+        if role == 4:
+            z[base:base + m] = M[:, col]
+        else:
+            r = np.arange(Mb)
+            z[base:base + Mb] = np.where(r % Pp < p, M[col, np.minimum(r % Pp, p - 1)], 0.0)
+    return z
+
+
+def encrypt_matrix_blocks(ctx: Context, keys: Keys, M, role, m, n, p, level, seed, first_ct_id):
+    nb = block_shape(ctx, m, n, p)[3]
+    return [ctx.encrypt(keys, ctx.encode(matrix_block_slots(ctx, M, K, role, m, n, p), level, ctx.scale),
+                        seed, first_ct_id + K) for K in range(nb)]
+
+
+def matmul_block(ctx: Context, keys: Keys, A_cts, B_cts, m, n, p):
+    """The column-split revolver on column blocks: D_idx =
+    Rescale(Relin(sum_K A_K * Rot(Bbar_K, idx))) for idx < P' (the blocks'
+    padding of P' - 1 slots past m keeps every rotated read inside its own
+    block wherever A is non-zero, so no RowShifter fix-up is needed), then
+    the c blocks are folded into block 0 by D += Rot(D, Mb 2^t), t < log2 c.
+    Slot i < m of D_idx holds C[i][(i + idx) mod P'].  Needs m >= p."""
+    if m < p:
+        raise ValueError("the column-block form needs m >= p (multiply the transposes)")
+    Pp, Mb, c, nb = block_shape(ctx, m, n, p)
+    if len(A_cts) != nb or len(B_cts) != nb:
+        raise ValueError("column-block operands need %d ciphertexts each" % nb)
+    D = matmul(ctx, keys, A_cts, B_cts, m, nb, p)
+    out = []
+    for d in D:
+        t = 1
+        while t < c:
+            d = ctx.add(d, ctx.rotate(d, Mb * t, keys))
+            t *= 2
+        out.append(d)
+    return out
+
+
+def block_rotation_steps(ctx: Context, m, n, p):
+    Pp, Mb, c, nb = block_shape(ctx, m, n, p)
+    steps = list(range(1, Pp))
+    t = 1
+    while t < c:
+        steps.append(Mb * t)
+        t *= 2
+    return steps

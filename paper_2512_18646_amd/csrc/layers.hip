@@ -1146,6 +1146,21 @@ std::vector<Slab> matmul_outer_multi(vr_context* ctx, const vr_eval_keys* ek, co
     return res;
 }
 
+// (P', Mb, c, nb) of the column-block form: blocks of Mb = P' ceil((m + P' -
+// 1) / P') slots, c (a power of two, c Mb <= S, c <= pow2(n)) columns per
+// ciphertext, nb = ceil(n / c) ciphertexts per operand
+void block_shape(vr_context* ctx, u32 m, u32 n, u32 p, u32* Pp, u32* Mb, u32* c, u32* nb)
+{
+    *Pp = pow2ceil(p);
+    const u64 mb = (u64)*Pp * (((u64)m + *Pp - 1 + *Pp - 1) / *Pp);
+    if (mb > ctx->slots) throw Error(VR_EINVAL, "m + P' - 1 exceeds the slot count");
+    *Mb = (u32)mb;
+    u32 cc = 1;
+    while ((u64)2 * cc * mb <= ctx->slots && cc < pow2ceil(n)) cc *= 2;
+    *c = cc;
+    *nb = (n + cc - 1) / cc;
+}
+
 // (P', R, T) of the outer-product form: column padding, rows per ciphertext,
 // row tiles
 void outer_tiles(vr_context* ctx, u32 m, u32 p, u32* Pp, u32* R, u32* T)
@@ -1338,19 +1353,30 @@ vr_status vr_encrypt_matrix_columns(vr_context* ctx, const vr_eval_keys* ek, con
                                     uint32_t p, uint32_t level, const uint64_t* seed,
                                     uint64_t first_ct_id, vr_ciphertext** out)
 {
-    // outputs: role 0 cols, role 1 rows, role 2 T cols, role 3 rows
+    // outputs: role 0 cols, role 1 rows, role 2 T cols, role 3 rows, roles 4 / 5 nb
     u32 n_ct = role == 0 || role == 2 ? cols : rows;
     if (role == 2 && ctx && p >= 1 && p <= ctx->slots && m >= 1) {
         const u32 R = (u32)(ctx->slots / pow2ceil(p));
         n_ct = ((m + R - 1) / R) * cols;
     }
+    u32 bPp = 0, bMb = 0, bc = 0, bnb = 0;
+    if ((role == 4 || role == 5) && ctx && m >= 1 && p >= 1 && rows >= 1 && cols >= 1) {
+        try {
+            block_shape(ctx, m, role == 4 ? cols : rows, p, &bPp, &bMb, &bc, &bnb);
+        } catch (const Error&) {
+            bnb = 0;
+        }
+        n_ct = bnb;
+    }
     if (out)
         for (u32 i = 0; i < n_ct; i++) out[i] = nullptr;
     API_BEGIN
     REQUIRE(ctx && ek && M && out && seed, "null argument");
-    REQUIRE(role <= 3, "role must be 0 (A columns), 1 (Bbar columns), 2 (A outer) or 3 (B outer)");
+    REQUIRE(role <= 5, "role must be 0 (A columns), 1 (Bbar columns), 2 (A outer), 3 (B outer), "
+                       "4 (A column blocks) or 5 (Bbar column blocks)");
     REQUIRE(rows >= 1 && cols >= 1 && m >= 1 && p >= 1, "empty matrix");
-    REQUIRE(role == 0 || role == 2 ? rows == m : cols == p, "matrix shape does not match m / p");
+    REQUIRE(role == 0 || role == 2 || role == 4 ? rows == m : cols == p, "matrix shape does not match m / p");
+    if (role >= 4) REQUIRE(bnb >= 1, "m + P' - 1 exceeds the slot count");
     REQUIRE(level <= ctx->L, "level above the modulus chain");
     const u32 Mp = pow2ceil(m), Pp = pow2ceil(p);
     REQUIRE(Pp <= ctx->slots && (role >= 2 || Mp <= ctx->slots), "matrix dimension exceeds the slot count");
@@ -1370,6 +1396,21 @@ vr_status vr_encrypt_matrix_columns(vr_context* ctx, const vr_eval_keys* ek, con
             // B'_k: slot r P' + j -> B[k][j], j < p, every row r
             for (u32 r = 0; r < R; r++)
                 for (u32 j = 0; j < p; j++) z[(size_t)r * Pp + j] = M[(size_t)c * cols + j];
+            continue;
+        }
+        if (role >= 4) {
+            // column blocks: block j of ciphertext c holds column c bc + j of A
+            // (role 4, first m slots) or row c bc + j of B (role 5, entry
+            // r mod P' in slot r of the block)
+            const u32 nn = role == 4 ? cols : rows;
+            for (u32 j = 0; j < bc && (size_t)c * bc + j < nn; j++) {
+                const u32 col = c * bc + j;
+                double* blk = z + (size_t)j * bMb;
+                if (role == 4)
+                    for (u32 i = 0; i < m; i++) blk[i] = M[(size_t)i * cols + col];
+                else
+                    for (u32 r = 0; r < bMb; r++) blk[r] = r % bPp < p ? M[(size_t)col * cols + r % bPp] : 0.0;
+            }
             continue;
         }
         const u32 k = c;
@@ -1422,6 +1463,100 @@ vr_status vr_matmul(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext
     rq.m = m, rq.n = n, rq.p = p;
     std::vector<Slab> out = matmul_multi(ctx, ek, {rq}, s);
     to_handles(ctx, out[0], C);
+    API_END
+}
+
+vr_status vr_matmul_block(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* const* A,
+                          const vr_ciphertext* const* Bbar, uint32_t m, uint32_t n, uint32_t p,
+                          vr_ciphertext** C, void* stream)
+{
+    const u32 Pp = p ? pow2ceil(p) : 0;
+    if (C)
+        for (u32 i = 0; i < Pp; i++) C[i] = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && A && Bbar && C, "null argument");
+    REQUIRE(m >= 1 && n >= 1 && p >= 1, "empty matrix");
+    REQUIRE(m >= p, "the column-block form needs m >= p (multiply the transposes)");
+    u32 bPp, Mb, c, nb;
+    block_shape(ctx, m, n, p, &bPp, &Mb, &c, &nb);
+    hipStream_t s = pick_stream(ctx, stream);
+    MatReq rq;
+    rq.A = gather(ctx, A, nb, s);
+    rq.B = gather(ctx, Bbar, nb, s);
+    rq.m = m, rq.n = nb, rq.p = p;
+    Slab D = matmul_multi(ctx, ek, {rq}, s)[0];
+    // fold the c blocks into block 0
+    for (u32 t = 1; t < c; t <<= 1) {
+        std::vector<Slab> r;
+        rotate_slab(ctx, ek, D, {(int32_t)(Mb * t)}, r, s);
+        launch_addsub(ctx, D.base, D.base, r[0].base, D.n * 2, D.level + 1, false, s);
+    }
+    to_handles(ctx, D, C);
+    API_END
+}
+
+vr_status vr_matmul_plan(vr_context* ctx, uint32_t m, uint32_t n, uint32_t p, uint32_t level,
+                         uint64_t max_client_cts, vr_matmul_cost* costs, uint32_t* chosen)
+{
+    if (chosen) *chosen = VR_MATMUL_NONE;
+    API_BEGIN
+    REQUIRE(ctx && costs && chosen, "null argument");
+    REQUIRE(m >= 1 && n >= 1 && p >= 1, "empty matrix");
+    REQUIRE(level >= 1 && level <= ctx->L, "level must leave one level for the rescale");
+    // the column-split and column-block forms multiply the transposes when m < p
+    const bool tr = m < p;
+    const u32 mm = tr ? p : m, pp = tr ? m : p;
+    KsShape k = ks_shape(ctx, level);
+    const double nl = level + 1, ext = k.next;
+    // device work in limb passes (one pass reads or writes N words): a
+    // tensor reads four limbs and writes three per level; a key switch
+    // transforms about 2 nl + beta (ext - alpha) + 2 (K + nl) limbs (two
+    // passes each at the larger sizes), converts beta digits and the P part,
+    // and reads beta digits plus the key for two outputs per extended limb
+    const double tensor_pass = 7.0 * nl;
+    const double ks_pass = 2.0 * (nl + k.beta * (ext - ctx->alpha) + 2.0 * (ctx->K + nl)) +
+                           (k.beta * (ctx->alpha + ext) + 2.0 * (ctx->K + nl)) + (k.beta + 2.0) * ext +
+                           2.0 * k.beta * ext;
+    const double us_per_pass = (double)ctx->n * 8.0 / 5.0e12 * 1e6;   // 8N bytes at 5 TB/s effective
+    for (int f = 0; f < 3; f++) costs[f] = vr_matmul_cost{};
+    auto fill = [&](int f, double cts, double ks, double tens, int feasible) {
+        costs[f].feasible = feasible;
+        costs[f].transposed = f == VR_MATMUL_OUTER ? 0 : (tr ? 1 : 0);
+        costs[f].client_cts = (uint64_t)cts;
+        costs[f].key_switches = (uint64_t)ks;
+        costs[f].tensors = (uint64_t)tens;
+        costs[f].est_us = (ks * ks_pass + tens * tensor_pass) * us_per_pass;
+    };
+    {
+        const double P1 = pow2ceil(pp);
+        const bool ok = pow2ceil(mm) <= ctx->slots;
+        fill(VR_MATMUL_COLUMN_SPLIT, 2.0 * n, n * (P1 - 1) + P1, n * P1, ok ? 1 : 0);
+    }
+    {
+        u32 bP, Mb, c, nb;
+        bool ok = true;
+        try {
+            block_shape(ctx, mm, n, pp, &bP, &Mb, &c, &nb);
+        } catch (const Error&) {
+            ok = false, bP = 1, Mb = 1, c = 1, nb = n;
+        }
+        double lc = 0;
+        for (u32 t = 1; t < c; t <<= 1) lc += 1;
+        fill(VR_MATMUL_COLUMN_BLOCK, 2.0 * nb, nb * (bP - 1.0) + bP * lc + bP, (double)nb * bP, ok ? 1 : 0);
+    }
+    {
+        const u32 P1 = pow2ceil(p);
+        const bool ok = P1 <= ctx->slots;
+        const double R = ok ? (double)(ctx->slots / P1) : 1.0, T = std::ceil(m / R);
+        fill(VR_MATMUL_OUTER, T * n + n, T, T * n, ok ? 1 : 0);
+    }
+    int best = -1;
+    for (int f = 0; f < 3; f++) {
+        if (!costs[f].feasible || (max_client_cts && costs[f].client_cts > max_client_cts)) continue;
+        if (best < 0 || costs[f].est_us < costs[best].est_us) best = f;
+    }
+    REQUIRE(best >= 0, "no form fits the client ciphertext limit");
+    *chosen = (uint32_t)best;
     API_END
 }
 

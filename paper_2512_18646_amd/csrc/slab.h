@@ -90,6 +90,9 @@ std::vector<Slab> matmul_outer_multi(vr_context* ctx, const vr_eval_keys* ek, co
                                      hipStream_t s);
 // (P', R, T) of the outer-product form: column padding, rows per ciphertext, tiles
 void outer_tiles(vr_context* ctx, u32 m, u32 p, u32* Pp, u32* R, u32* T);
+// (P', Mb, c, nb) of the column-block form: block size, columns per
+// ciphertext, ciphertexts per operand
+void block_shape(vr_context* ctx, u32 m, u32 n, u32 p, u32* Pp, u32* Mb, u32* c, u32* nb);
 // Weight plaintexts as one array of count plaintexts; *p_level = the level
 // the layer runs at, min(nl - 1, the plaintexts' level).
 const u64* fc_weights(vr_context* ctx, const vr_plaintext* const* W_pt, size_t count, u32 nl,

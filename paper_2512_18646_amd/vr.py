@@ -43,6 +43,14 @@ class vr_cnn_desc(ctypes.Structure):
                 ("fc_out", ctypes.c_uint32), ("fc_block", ctypes.c_uint32)]
 
 
+class vr_matmul_cost(ctypes.Structure):
+    _fields_ = [("feasible", ctypes.c_uint32), ("transposed", ctypes.c_uint32), ("client_cts", ctypes.c_uint64),
+                ("key_switches", ctypes.c_uint64), ("tensors", ctypes.c_uint64), ("est_us", ctypes.c_double)]
+
+
+MATMUL_FORMS = ("column_split", "column_block", "outer")
+
+
 class vr_params(ctypes.Structure):
     _fields_ = [("log_n", ctypes.c_uint32), ("n_q", ctypes.c_uint32), ("n_p", ctypes.c_uint32),
                 ("dnum", ctypes.c_uint32), ("q_bits", ctypes.POINTER(ctypes.c_uint32)),
@@ -89,6 +97,8 @@ _SIGS = {
     "vr_rotate_noalloc": [P, P, P, U32, I32, P, P],
     "vr_poly_eval": [P, P, PP, SZ, P, U32, PP, P],
     "vr_conv2d_encw": [P, P, PP, U32, U32, U32, U32, PP, PP, U32, U32, U32, PP, P],
+    "vr_matmul_block": [P, P, PP, PP, U32, U32, U32, PP, P],
+    "vr_matmul_plan": [P, U32, U32, U32, U32, U64, P, ctypes.POINTER(U32)],
     "vr_fc_encw": [P, P, PP, U32, PP, PP, U32, U32, PP, P],
     "vr_dense": [P, PP, U32, P, P, U32, PP, P],
     "vr_matmul": [P, P, PP, PP, U32, U32, U32, PP, P],
@@ -372,9 +382,11 @@ class Context:
     def encrypt_matrix_columns(self, keys, M, role, m, p, level, seed, first_ct_id):
         M = _f64(M)
         rows, cols = M.shape
-        n = cols if role == 0 else rows
+        n = cols if role in (0, 2, 4) else rows
         if role == 2:
             n = self.outer_tiles(m, p)[2] * cols
+        elif role in (4, 5):
+            n = self.block_shape(m, n, p)[3]
         arr = (ctypes.c_void_p * n)()
         _check(lib.vr_encrypt_matrix_columns(self.h, keys.ek, M.ctypes.data, rows, cols, role, m, p,
                                              level, _seed(seed), first_ct_id, arr))
@@ -458,6 +470,41 @@ class Context:
         _check(lib.vr_matmul(self.h, keys.ek, _ptr_array(A), _ptr_array(Bbar), m, n, p, arr,
                              _stream(stream)))
         return [Ciphertext(arr[i], self) for i in range(Pp)]
+
+    def block_shape(self, m, n, p):
+        """(P', Mb, c, nb) of the column-block form (the sizes vr_matmul_block
+        and roles 4 / 5 use: block size, columns per ciphertext, ciphertexts
+        per operand), for sizing the handle arrays."""
+        Pp = 1
+        while Pp < p:
+            Pp *= 2
+        Mb = Pp * -(-(m + Pp - 1) // Pp)
+        n2 = 1
+        while n2 < n:
+            n2 *= 2
+        c = 1
+        while 2 * c * Mb <= self.slots and c < n2:
+            c *= 2
+        return Pp, Mb, c, -(-n // c)
+
+    def matmul_block(self, keys, A, Bbar, m, n, p, stream=None):
+        Pp = 1
+        while Pp < p:
+            Pp *= 2
+        arr = (ctypes.c_void_p * Pp)()
+        _check(lib.vr_matmul_block(self.h, keys.ek, _ptr_array(A), _ptr_array(Bbar), m, n, p, arr,
+                                   _stream(stream)))
+        return [Ciphertext(arr[i], self) for i in range(Pp)]
+
+    def matmul_plan(self, m, n, p, level, max_client_cts=0):
+        """(chosen form name, {form: cost dict}) of the cost-model planner."""
+        costs = (vr_matmul_cost * 3)()
+        chosen = U32()
+        _check(lib.vr_matmul_plan(self.h, m, n, p, level, max_client_cts, costs, ctypes.byref(chosen)))
+        out = {}
+        for f, c in zip(MATMUL_FORMS, costs):
+            out[f] = {k: getattr(c, k) for k, _ in vr_matmul_cost._fields_}
+        return MATMUL_FORMS[chosen.value], out
 
     def outer_tiles(self, m, p):
         """(P', R, T) of the outer-product product: column padding, rows per

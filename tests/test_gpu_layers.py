@@ -376,3 +376,44 @@ def test_cnn128_full_level_chunked_key_switching():
         for b in range(W.batch):
             got[b, i] = z[b * Hp + W.stride * np.arange(got.shape[2])]
     assert Ly.rel_error(got, ref[:, [0, 7]][:, :, :, 9]) < EPS
+
+
+def test_matmul_block_bit_exact_and_planner(c1mm):
+    """Column-block form at N = 2^13 (S = 4096): m = 12, n = 40, p = 5 gives
+    blocks of 24 slots, 64 columns per ciphertext, one ciphertext per
+    operand; limb for limb against the oracle (operands encrypted by the
+    oracle), GPU-encrypted end to end against FP64; the planner's choices."""
+    o, ok, g, gk = c1mm
+    m, n, p = 12, 40, 5
+    Pp, Mb, c, nb = Ly.block_shape(o, m, n, p)
+    assert g.block_shape(m, n, p) == (Pp, Mb, c, nb) == (8, 24, 64, 1)
+    steps = Ly.block_rotation_steps(o, m, n, p)
+    ok2 = o.keygen(1001, rot_steps=steps)
+    gk2 = g.keygen(1001, rot_steps=steps)
+    rng = np.random.default_rng(19)
+    A, B = rng.uniform(-1, 1, (m, n)), rng.uniform(-1, 1, (n, p))
+    Ac = Ly.encrypt_matrix_blocks(o, ok2, A, 4, m, n, p, 3, 9, 0)
+    Bc = Ly.encrypt_matrix_blocks(o, ok2, B, 5, m, n, p, 3, 9, 100)
+    D = Ly.matmul_block(o, ok2, Ac, Bc, m, n, p)
+    gD = g.matmul_block(gk2, [to_gpu(g, x) for x in Ac], [to_gpu(g, x) for x in Bc], m, n, p)
+    for i, (x, y) in enumerate(zip(gD, D)):
+        assert_same(x, y, "block C[%d]" % i)
+    gA = g.encrypt_matrix_columns(gk2, A, 4, m, p, 3, 9, 1000)
+    gB = g.encrypt_matrix_columns(gk2, B, 5, m, p, 3, 9, 2000)
+    assert len(gA) == len(gB) == nb
+    assert Ly.rel_error(gpu_matmul_decode(g, gk2, g.matmul_block(gk2, gA, gB, m, n, p), m, p), A @ B) < EPS
+    # planner: the outer form wins on device work (one tile, one key switch
+    # for 16 x 16 x 16); a client limit below its upload (32 ciphertexts)
+    # leaves the block form, which needs fewer key switches than the
+    # column-split one; the transposed flag for m < p
+    form, cost = g.matmul_plan(16, 16, 16, 3)
+    assert form == "outer" and cost["outer"]["client_cts"] == 32 and cost["outer"]["key_switches"] == 1
+    assert cost["column_block"]["key_switches"] < cost["column_split"]["key_switches"]
+    form, cost = g.matmul_plan(16, 16, 16, 3, max_client_cts=4)
+    assert form == "column_block" and cost["column_block"]["client_cts"] == 2
+    form, cost = g.matmul_plan(512, 512, 512, 3)
+    assert form == "outer"
+    form2, _ = g.matmul_plan(512, 512, 512, 3, max_client_cts=cost["column_block"]["client_cts"])
+    assert form2 in ("column_block", "column_split")
+    _, cost = g.matmul_plan(5, 8, 13, 3)
+    assert cost["column_split"]["transposed"] == 1 and cost["outer"]["transposed"] == 0

@@ -505,3 +505,50 @@ def test_encrypted_weight_conv_and_fc_against_fp64(ctx10):
     Z = Ly.fc_encw(ctx, keys, Y, wct, fbct, Hp)
     logits = Ly.fc_decode(ctx, keys, Z, B, Hp)
     assert Ly.rel_error(logits, Ly.ref_fc(ref, W, fb)) < EPS
+
+
+# --------------------------------------------------- column-block form
+
+def test_matmul_block_slot_layout_brute_force():
+    """Column blocks on plain slot vectors: sum_K A_K * Rot(Bbar_K, idx), then
+    the fold over the c blocks, holds C[i][(i + idx) mod P'] in slot i < m
+    (zero where that column is past p), exact on small integers, every entry
+    reached once; ragged shapes with several ciphertexts per operand."""
+    ctx = small_ctx(log_n=7)   # 64 slots
+    rng = np.random.default_rng(17)
+    for m, n, p in ((4, 3, 3), (5, 9, 4), (8, 20, 2), (12, 5, 5), (3, 17, 1)):
+        A = rng.integers(-9, 10, (m, n)).astype(float)
+        B = rng.integers(-9, 10, (n, p)).astype(float)
+        C = A @ B
+        Pp, Mb, c, nb = Ly.block_shape(ctx, m, n, p)
+        assert Mb >= m + Pp - 1 and Mb % Pp == 0 and c * Mb <= ctx.slots and nb * c >= n
+        seen = np.zeros((m, p), int)
+        for idx in range(Pp):
+            D = sum(Ly.matrix_block_slots(ctx, A, K, 4, m, n, p) *
+                    np.roll(Ly.matrix_block_slots(ctx, B, K, 5, m, n, p), -idx) for K in range(nb))
+            t = 1
+            while t < c:
+                D = D + np.roll(D, -Mb * t)
+                t *= 2
+            for i in range(m):
+                col = (i + idx) % Pp
+                if col < p:
+                    assert D[i] == C[i, col]
+                    seen[i, col] += 1
+                else:
+                    assert D[i] == 0.0
+        assert (seen == 1).all()
+
+
+def test_matmul_block_schedule_against_fp64(ctx10):
+    ctx, keys = ctx10
+    m, n, p = 12, 20, 5
+    rng = np.random.default_rng(18)
+    A, B = rng.uniform(-1, 1, (m, n)), rng.uniform(-1, 1, (n, p))
+    Pp, Mb, c, nb = Ly.block_shape(ctx, m, n, p)
+    k2 = ctx.keygen(1001, rot_steps=Ly.block_rotation_steps(ctx, m, n, p))
+    D = Ly.matmul_block(ctx, k2, Ly.encrypt_matrix_blocks(ctx, k2, A, 4, m, n, p, 3, 5, 0),
+                        Ly.encrypt_matrix_blocks(ctx, k2, B, 5, m, n, p, 3, 5, 100), m, n, p)
+    assert len(D) == Pp and nb == 2 and c == 16   # two ciphertexts per operand, the second ragged
+    got = Ly.matmul_decode(ctx, k2, D, m, p)
+    assert Ly.rel_error(got, A @ B) < EPS
