@@ -941,7 +941,7 @@ def _orc_c3_sample(_=None):
     y = o.rescale(o.add_const(acc, 0.5))
     t["addconst_rescale24"] = time.perf_counter() - t0
     t0 = time.perf_counter()
-    o.rescale(o.relinearize(o.tensor(y, y), ok))
+    o.relin_rescale(o.tensor(y, y), ok)
     t["square23"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     acc = None

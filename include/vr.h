@@ -229,6 +229,23 @@ vr_status vr_mul(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *a
                  const vr_ciphertext *b, vr_ciphertext **out, void *stream);
 /* Divide by q_level with a centred last limb; level - 1; scale /= q_level. */
 vr_status vr_rescale(vr_context *ctx, const vr_ciphertext *a, vr_ciphertext **out, void *stream);
+/* Relinearisation and the rescale that follows it (every ciphertext product of
+ * "Homomorphic Matrix Multiplication" and of the layers in "Secure Inference"
+ * is a Mul followed by a Rescale) as one ModDown by P q_level: with
+ * (u0, u1) the key-switch sums of the s^2 component over q_0..q_level and the
+ * special primes, out_j = round((u_j + P c_j) / (P q_level)) on q_0..q_{level-1}
+ * (the centred fast conversion of ModDown, now from {q_level, p_0..p_{K-1}}).
+ * `a` must have 3 components and level >= 1 (VR_ELEVEL otherwise); output at
+ * level - 1 with scale / q_level.  Equal to vr_rescale(vr_relinearize(a)) up
+ * to one rounding (a few units in the last place of the coefficients), not
+ * word for word.  *out is a new ciphertext owned by the caller.  The layer
+ * calls below write this operation RelinRescale(.) and use it for every
+ * product they relinearise. */
+vr_status vr_relin_rescale(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *a,
+                           vr_ciphertext **out, void *stream);
+/* vr_tensor then vr_relin_rescale. */
+vr_status vr_mul_rescale(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *a,
+                         const vr_ciphertext *b, vr_ciphertext **out, void *stream);
 /* Drop limbs above `level` (scale unchanged). */
 vr_status vr_mod_drop(vr_context *ctx, const vr_ciphertext *a, uint32_t level,
                       vr_ciphertext **out, void *stream);
@@ -272,7 +289,7 @@ vr_status vr_rotate_noalloc(vr_context *ctx, const vr_eval_keys *ek, const uint6
  * Matrix Multiplication" with RowShifter reduced to one rotation and the
  * ciphertext-pair split of "Parallelized Matrix Multiplication"): from A_k,
  * Bbar_k (k < n, from vr_encrypt_matrix_columns), for idx < P',
- *   C[idx] = Rescale(Relin(sum_k A_k * Rot(Bbar_k, idx))),
+ *   C[idx] = RelinRescale(sum_k A_k * Rot(Bbar_k, idx)),
  * slot i < m of C[idx] holding (A B)[i][(i + idx) mod P'].  Rotation keys
  * for steps 1..P'-1; C receives P' handles.  For m < p the product is the
  * paper's transposed one, C^T = B^T A^T, on the same ciphertexts with their
@@ -288,7 +305,7 @@ vr_status vr_matmul(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext
  * S slots), T = ceil(m / R) tiles.  A holds T n ciphertexts A'_{t,k} (index
  * t n + k; vr_encrypt_matrix_columns role 2): slot r P' + j = A[t R + r][k]
  * for j < p; B holds n ciphertexts B'_k (role 3): slot r P' + j = B[k][j].
- *   C[t] = Rescale(Relin(sum_k A'_{t,k} * B'_k)),
+ *   C[t] = RelinRescale(sum_k A'_{t,k} * B'_k),
  * slot r P' + j of C[t] holding (A B)[t R + r][j].  No rotation and no
  * rotation key; any m, n and p with P' <= S.  C receives T handles.
  * VR_EINVAL for empty shapes or p above S; VR_ELEVEL / VR_ESCALE when the
@@ -301,7 +318,7 @@ vr_status vr_matmul_outer(vr_context *ctx, const vr_eval_keys *ek, const vr_ciph
  * (roles 4 / 5 of vr_encrypt_matrix_columns), each in a block padded by P' -
  * 1 slots past m so that every rotated read of Bbar stays in its own block
  * wherever A is non-zero (no RowShifter fix-up):
- *   D[idx] = Rescale(Relin(sum_K A_K * Rot(Bbar_K, idx))), idx < P',
+ *   D[idx] = RelinRescale(sum_K A_K * Rot(Bbar_K, idx)), idx < P',
  * then the c blocks folded into block 0, D += Rot(D, Mb 2^t) for t <
  * log2 c.  Slot i < m of C[idx] holds (A B)[i][(i + idx) mod P'].  Needs
  * m >= p; rotation keys for steps 1..P'-1 and Mb 2^t.  nb (P' - 1) + P'
@@ -348,7 +365,7 @@ vr_status vr_conv2d_sets(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphe
                          uint32_t n_sets, uint32_t C_in, uint32_t h, uint32_t w, uint32_t pad,
                          const double *K, const double *bias, uint32_t C_out, uint32_t k,
                          uint32_t stride, vr_ciphertext **out, void *stream);
-/* x^2 activation on n ciphertexts: Rescale(Relin(Tensor(y, y))). */
+/* x^2 activation on n ciphertexts: RelinRescale(Tensor(y, y)). */
 vr_status vr_square(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *in,
                     size_t n, vr_ciphertext **out, void *stream);
 /* Encrypted-weight mode (the paper's usage model, "Homomorphic CNN
@@ -357,8 +374,8 @@ vr_status vr_square(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext
  * encrypting K[c'][c][u][v] in every slot at scale q_l (same level as the
  * inputs) and bias_ct[c'] encrypting the bias in every slot one level lower
  * at the rescaled products' scale ((input scale q_l) / q_l as a double):
- *   Y(c', j') = Rescale(Relin(sum_{c,u,v} Tensor(Rot(col(c, s j'+v-pi), u),
- *               K_ct[c', c, u, v]))) + bias_ct[c']
+ *   Y(c', j') = RelinRescale(sum_{c,u,v} Tensor(Rot(col(c, s j'+v-pi), u),
+ *               K_ct[c', c, u, v])) + bias_ct[c']
  * (one lazy relinearisation per output).  VR_ESCALE / VR_ELEVEL when the
  * bias ciphertexts do not match.  out receives C_out * w_out handles. */
 vr_status vr_conv2d_encw(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *in, uint32_t C_in,
@@ -368,7 +385,7 @@ vr_status vr_conv2d_encw(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphe
 /* The FC of vr_fc with encrypted weights: W_ct[o n_in + i] encrypts the
  * weight pattern vr_encode_fc_weights encodes (scale q_l, the inputs'
  * level), bias_ct[o] the bias in every slot one level lower at the rescaled
- * scale:  Z_o = RotSum_block(Rescale(Relin(sum_i Tensor(Y_i, W_ct[o][i])))) +
+ * scale:  Z_o = RotSum_block(RelinRescale(sum_i Tensor(Y_i, W_ct[o][i]))) +
  * bias_ct[o]. */
 vr_status vr_fc_encw(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *Y, uint32_t n_in,
                      const vr_ciphertext *const *W_ct, const vr_ciphertext *const *bias_ct, uint32_t n_out,
@@ -377,7 +394,7 @@ vr_status vr_fc_encw(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertex
  * activations of the paper's CNN, "Neural Network Architecture", Table 1) on
  * n ciphertexts of one level and scale, by Horner's rule: t =
  * Rescale(MulConst(x, coeffs[d]) at constant scale q_l + coeffs[d-1]), then
- * t = Rescale(Relin(Tensor(t, x dropped to t's level))) + coeffs[i] for
+ * t = RelinRescale(Tensor(t, x dropped to t's level)) + coeffs[i] for
  * i = d-2 .. 0.  Depth d (VR_ELEVEL below it); out receives n handles. */
 vr_status vr_poly_eval(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *in, size_t n,
                        const double *coeffs, uint32_t degree, vr_ciphertext **out, void *stream);

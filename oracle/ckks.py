@@ -616,6 +616,41 @@ class Context:
     def mul(self, a, b, keys):
         return self.relinearize(self.tensor(a, b), keys)
 
+    def relin_rescale(self, a: Ciphertext, keys: Keys):
+        """Relinearisation and rescale as one ModDown by P q_l: with (u0, u1)
+        the key-switch sums of c2 over q_0..q_l, p_0..p_{K-1}, each component
+        v = u + P c (P c vanishes on the special primes) is divided by P q_l
+        with the same centred fast conversion ModDown uses, now from the drop
+        set {q_l, p_0..p_{K-1}} to q_0..q_{l-1}:
+            out_i = (v_i - conv(v_D)_i) (P q_l)^-1 mod q_i,   i < l.
+        Level l - 1, scale / q_l as for rescale.  It equals rescale(relinearize(a))
+        up to a rounding difference of the division (not limb for limb)."""
+        assert a.ncomp == 3
+        lv = a.level
+        if lv == 0:
+            raise ValueError("no limb left to rescale by")
+        d = a.c[2]
+        xs = [self.mod_up(d, lv, j) for j in range(self.n_digits(lv))]
+        u = self.inner_product(xs, keys.rlk, lv)
+        nq = lv + 1
+        Pm = 1
+        for pk in self.p:
+            Pm *= pk
+        drop = [self.q[lv]] + list(self.p)
+        c = np.empty((2, lv, self.n), dtype=np.uint64)
+        for comp in range(2):
+            v = u[comp].copy()
+            for i in range(nq):
+                q = self.q[i]
+                v[i] = self.vadd(u[comp][i], self.vscale(a.c[comp, i], Pm % q, q), q)
+            vD = np.stack([v[lv]] + [v[nq + k] for k in range(self.K)])
+            y = self.base_convert(vD, drop, self.q[:lv])
+            for i in range(lv):
+                q = self.q[i]
+                inv = pow(Pm * self.q[lv] % q, q - 2, q)
+                c[comp, i] = self.vscale(self.vsub(v[i], y[i], q), inv, q)
+        return Ciphertext(c, lv - 1, a.scale / float(self.q[lv]))
+
     def rotate(self, a: Ciphertext, step, keys: Keys):
         """Left rotation of the slots by `step`."""
         assert a.ncomp == 2

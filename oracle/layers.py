@@ -16,7 +16,7 @@ from its single-ciphertext algorithms:
           revolver shift (RowShifter, which is one rotation when m mod p = 0,
           per "Homomorphic Matrix Multiplication") becomes Rot(Bbar_k, idx), and
           SumColVec becomes the sum over k:
-              D_idx = Rescale(Relin(sum_k A_k * Rot(Bbar_k, idx))),
+              D_idx = RelinRescale(sum_k A_k * Rot(Bbar_k, idx)),
           slot i < m of D_idx holds C[i][(i + idx) mod P'].
   conv    the CNN convolution of "Convolutional Neural Networks" with stride s
           and zero padding pi; images are packed in blocks of H' = pow2(h+2pi)
@@ -32,12 +32,18 @@ from its single-ciphertext algorithms:
           every slot r P' + j with j < p (column k of A replicated across the
           row), and B'_k holds B[k][j] in slot r P' + j for every r (row k of
           B tiled down the rows).  Then
-              C_t = Rescale(Relin(sum_k A'_{t,k} * B'_k)),
+              C_t = RelinRescale(sum_k A'_{t,k} * B'_k),
           slot r P' + j of C_t holds C[t R + r][j]: n tensors and one
           relinearisation per tile, no rotation.
-  square  Rescale(Relin(Tensor(Y, Y))).
+  square  RelinRescale(Tensor(Y, Y)).
   fc      Rescale(sum_{c',j'} MulPlain(Y(c',j'), pt_{o,c',j'})), then the
           SumColVec-style Z += Rot(Z, 2^t) over the H' block, then the bias.
+
+RelinRescale(.) is the relinearisation and the rescale that follow every
+ciphertext product, computed as one ModDown by P q_l (Context.relin_rescale):
+one rounding instead of two, so its words differ from Rescale(Relin(.)) by a
+few units of the coefficients while the decrypted values agree to within that
+rounding.
 
 Parity status: "parity unpinned by the paper" -- the paper gives no worked
 example, figure or number for the split schedules; they are pinned only by the
@@ -179,7 +185,7 @@ def encrypt_matrix_outer(ctx: Context, keys: Keys, M, role, m, p, level, seed, f
 
 
 def matmul(ctx: Context, keys: Keys, A_cts, B_cts, m, n, p):
-    """D_idx = Rescale(Relin(sum_k A_k * Rot(Bbar_k, idx))), idx < P'.  For
+    """D_idx = RelinRescale(sum_k A_k * Rot(Bbar_k, idx)), idx < P'.  For
     m < p the paper multiplies the transposes, C^T = B^T A^T: the Bbar
     ciphertexts (slot s -> B[k][s mod P']) are exactly the A-role ciphertexts
     of B^T and the A ciphertexts (slot s -> A[s mod M'][k]) the Bbar-role
@@ -194,7 +200,7 @@ def matmul(ctx: Context, keys: Keys, A_cts, B_cts, m, n, p):
         for idx in range(Pp):
             t = ctx.tensor(A_cts[k], rots[idx])
             T[idx] = t if T[idx] is None else ctx.add(T[idx], t)
-    return [ctx.rescale(ctx.relinearize(T[idx], keys)) for idx in range(Pp)]
+    return [ctx.relin_rescale(T[idx], keys) for idx in range(Pp)]
 
 
 def matmul_decode(ctx: Context, keys: Keys, D, m, p):
@@ -212,7 +218,7 @@ def matmul_decode(ctx: Context, keys: Keys, D, m, p):
 
 
 def matmul_outer(ctx: Context, keys: Keys, A_cts, B_cts, m, n, p):
-    """C_t = Rescale(Relin(sum_k Tensor(A'_{t,k}, B'_k))) for every row tile t."""
+    """C_t = RelinRescale(sum_k Tensor(A'_{t,k}, B'_k)) for every row tile t."""
     _, _, T = outer_tiles(ctx, m, p)
     out = []
     for t in range(T):
@@ -220,7 +226,7 @@ def matmul_outer(ctx: Context, keys: Keys, A_cts, B_cts, m, n, p):
         for k in range(n):
             x = ctx.tensor(A_cts[t * n + k], B_cts[k])
             acc = x if acc is None else ctx.add(acc, x)
-        out.append(ctx.rescale(ctx.relinearize(acc, keys)))
+        out.append(ctx.relin_rescale(acc, keys))
     return out
 
 
@@ -289,7 +295,7 @@ def conv_decode(ctx: Context, keys: Keys, Y, B, C_out, h, pad, k, stride, w):
 
 
 def square(ctx: Context, keys: Keys, ct):
-    return ctx.rescale(ctx.relinearize(ctx.tensor(ct, ct), keys))
+    return ctx.relin_rescale(ctx.tensor(ct, ct), keys)
 
 
 def fc_plaintexts(ctx: Context, W, C, ho, wo, stride, Hp, level):
@@ -358,7 +364,7 @@ ACT2 = (-1.5650465, -0.9943767, 1.6794522, 0.5350255)
 def poly_eval(ctx: Context, keys: Keys, ct, coeffs):
     """sum_i coeffs[i] x^i (degree d >= 1) by Horner's rule:
     t = MulConst(x, a_d) at constant scale q_l, rescaled, plus a_{d-1}; then
-    for i = d-2 .. 0: t = Rescale(Relin(Tensor(t, x dropped to t's level)))
+    for i = d-2 .. 0: t = RelinRescale(Tensor(t, x dropped to t's level))
     plus a_i.  Depth d; every addition is an AddConst at the running scale."""
     d = len(coeffs) - 1
     if d < 1:
@@ -366,7 +372,7 @@ def poly_eval(ctx: Context, keys: Keys, ct, coeffs):
     t = ctx.rescale(ctx.add_const(ctx.mul_const(ct, coeffs[d], float(ctx.q[ct.level])), coeffs[d - 1]))
     for i in range(d - 2, -1, -1):
         x = ctx.mod_drop(ct, t.level)
-        t = ctx.add_const(ctx.rescale(ctx.relinearize(ctx.tensor(t, x), keys)), coeffs[i])
+        t = ctx.add_const(ctx.relin_rescale(ctx.tensor(t, x), keys), coeffs[i])
     return t
 
 
@@ -418,8 +424,8 @@ def conv2d_encw(ctx: Context, keys: Keys, cts, C_in, h, w, pad, Kct, bias_ct, C_
     slot at scale q_l; bias_ct[c'] encrypts the bias in every slot one level
     lower, at the scale the rescaled sum carries.  Each output is a sum of
     ct x ct products relinearised once (lazy relinearisation):
-        Y(c', j') = Rescale(Relin(sum_{c,u,v} Tensor(Rot(col(c, s j'+v-pi), u),
-                    Kct[c', c, u, v]))) + bias_ct[c'].  One level."""
+        Y(c', j') = RelinRescale(sum_{c,u,v} Tensor(Rot(col(c, s j'+v-pi), u),
+                    Kct[c', c, u, v])) + bias_ct[c'].  One level."""
     wo = conv_out_size(w, pad, k, stride)
     rot = {}
 
@@ -441,7 +447,7 @@ def conv2d_encw(ctx: Context, keys: Keys, cts, C_in, h, w, pad, Kct, bias_ct, C_
                     for u in range(k):
                         t = ctx.tensor(rotated(c, jj)[u], Kct[((co * C_in + c) * k + u) * k + v])
                         acc = t if acc is None else ctx.add(acc, t)
-            out.append(ctx.add(ctx.rescale(ctx.relinearize(acc, keys)), bias_ct[co]))
+            out.append(ctx.add(ctx.relin_rescale(acc, keys), bias_ct[co]))
     return out
 
 
@@ -463,7 +469,7 @@ def fc_encw(ctx: Context, keys: Keys, Y, Wct, bias_ct, Hp):
     """FC with encrypted weights: Wct[o][i] encrypts the weight pattern of
     fc_plaintexts (scale q_l) and bias_ct[o] the bias in every slot one level
     lower at the scale the rescaled sum carries (see encrypt_fc_weights):
-        Z_o = RotSum_Hp(Rescale(Relin(sum_i Tensor(Y_i, Wct[o][i])))) + bias_ct[o],
+        Z_o = RotSum_Hp(RelinRescale(sum_i Tensor(Y_i, Wct[o][i]))) + bias_ct[o],
     one relinearisation per output (lazy)."""
     out = []
     for o, row in enumerate(Wct):
@@ -471,7 +477,7 @@ def fc_encw(ctx: Context, keys: Keys, Y, Wct, bias_ct, Hp):
         for y, wct in zip(Y, row):
             t = ctx.tensor(y, wct)
             acc = t if acc is None else ctx.add(acc, t)
-        z = ctx.rescale(ctx.relinearize(acc, keys))
+        z = ctx.relin_rescale(acc, keys)
         step = 1
         while step < Hp:
             z = ctx.add(z, ctx.rotate(z, step, keys))
@@ -550,7 +556,7 @@ def encrypt_matrix_blocks(ctx: Context, keys: Keys, M, role, m, n, p, level, see
 
 def matmul_block(ctx: Context, keys: Keys, A_cts, B_cts, m, n, p):
     """The column-split revolver on column blocks: D_idx =
-    Rescale(Relin(sum_K A_K * Rot(Bbar_K, idx))) for idx < P' (the blocks'
+    RelinRescale(sum_K A_K * Rot(Bbar_K, idx)) for idx < P' (the blocks'
     padding of P' - 1 slots past m keeps every rotated read inside its own
     block wherever A is non-zero, so no RowShifter fix-up is needed), then
     the c blocks are folded into block 0 by D += Rot(D, Mb 2^t), t < log2 c.

@@ -138,8 +138,9 @@ class PlainOps:
 
 class HeOps:
     """The algorithms on oracle ciphertexts.  cMult encodes its mask at scale
-    q_l of the ciphertext's level and rescales; Mult is tensor,
-    relinearisation and rescale; Add drops the higher operand to the lower
+    q_l of the ciphertext's level and rescales; Mult is the tensor product
+    followed by the fused relinearisation and rescale; Add drops the higher
+    operand to the lower
     level (a level drop keeps the message); Enc encrypts a vector at a given
     ciphertext's level and scale (the third party's or client's encryption)."""
 
@@ -180,7 +181,7 @@ class HeOps:
     def mul(self, a, b):
         self.count["Mult"] += 1
         a, b = self._align(a, b)
-        return self.ctx.rescale(self.ctx.mul(a, b, self.keys))
+        return self.ctx.relin_rescale(self.ctx.tensor(a, b), self.keys)
 
     def enc(self, vec, like=None, level=None):
         lv = like.level if like is not None else level

@@ -204,6 +204,10 @@ vr_status vr_context_tuning_report(vr_context* ctx, char* buf, size_t cap)
         r += "moddown l" + std::to_string(kv.first) + " " + std::to_string(kv.second.n_in) + "->" +
              std::to_string(kv.second.n_out) + ": " +
              name(kv.second.choice ? kv.second.choice->load() : -1) + "\n";
+    for (auto& kv : ctx->moddown_rs_tables)
+        r += "moddown-rescale l" + std::to_string(kv.first) + " " + std::to_string(kv.second.n_in) + "->" +
+             std::to_string(kv.second.n_out) + ": " +
+             name(kv.second.choice ? kv.second.choice->load() : -1) + "\n";
     for (int d = 0; d < 2; d++) {
         if (ctx->ntt_plan[d].empty()) continue;
         r += std::string("ntt N=2^") + std::to_string(ctx->log_n) + (d ? " inverse:" : " forward:");
@@ -419,6 +423,28 @@ vr_status vr_mul(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* a
     hipStream_t s = pick_stream(ctx, stream);
     std::unique_ptr<vr_ciphertext> t(ev_tensor(ctx, a, b, s));
     *out = ev_relin(ctx, ek, t.get(), s);
+    API_END
+}
+
+vr_status vr_relin_rescale(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* a,
+                           vr_ciphertext** out, void* stream)
+{
+    if (out) *out = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && a && out, "null argument");
+    *out = ev_relin_rescale(ctx, ek, a, pick_stream(ctx, stream));
+    API_END
+}
+
+vr_status vr_mul_rescale(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* a,
+                         const vr_ciphertext* b, vr_ciphertext** out, void* stream)
+{
+    if (out) *out = nullptr;
+    API_BEGIN
+    REQUIRE(ctx && ek && a && b && out, "null argument");
+    hipStream_t s = pick_stream(ctx, stream);
+    std::unique_ptr<vr_ciphertext> t(ev_tensor(ctx, a, b, s));
+    *out = ev_relin_rescale(ctx, ek, t.get(), s);
     API_END
 }
 

@@ -41,6 +41,9 @@ vr_ciphertext* ev_mul_plain(vr_context* ctx, const vr_ciphertext* a, const vr_pl
                             hipStream_t s);
 vr_ciphertext* ev_tensor(vr_context* ctx, const vr_ciphertext* a, const vr_ciphertext* b,
                          hipStream_t s);
+// Relinearisation and rescale in one ModDown by P q_l (level l - 1).
+vr_ciphertext* ev_relin_rescale(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* a,
+                                hipStream_t s);
 vr_ciphertext* ev_relin(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* a,
                         hipStream_t s);
 vr_ciphertext* ev_rescale(vr_context* ctx, const vr_ciphertext* a, hipStream_t s);

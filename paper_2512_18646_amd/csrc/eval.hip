@@ -275,6 +275,30 @@ vr_ciphertext* ev_relin(vr_context* ctx, const vr_eval_keys* ek, const vr_cipher
     return out.release();
 }
 
+vr_ciphertext* ev_relin_rescale(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* a,
+                                hipStream_t s)
+{
+    if (a->ncomp != 3) throw Error(VR_EINVAL, "relinearisation needs 3 components");
+    if (a->level == 0) throw Error(VR_ELEVEL, "no limb left to rescale by");
+    const u32 level = a->level;
+    KsShape k = ks_shape(ctx, level);
+    const size_t n = ctx->n, poly = (size_t)(level + 1) * n;
+    auto out = hold(new_ct(ctx, 2, level - 1, a->scale / (double)ctx->mod[level], s));
+    size_t words = keyswitch_modup_scratch(ctx, level) + (size_t)2 * k.next * n +
+                   keyswitch_moddown_scratch(ctx, level, 1);
+    BufPtr scratch = dev_alloc(ctx, words * sizeof(u64), s);
+    u64* X = as_u64(scratch);
+    u64* coef = X + (size_t)k.beta * k.next * n;
+    u64* U = coef + (size_t)k.nq * n;
+    u64* md = U + (size_t)2 * k.next * n;
+    const u64* d = a->data + 2 * poly;
+    keyswitch_modup(ctx, d, level, X, coef, s);
+    keyswitch_inner(ctx, X, d, ek->rlk.data, level, 1, U, s);
+    keyswitch_moddown_rescale_batch(ctx, U, (u64)2 * k.next * n, 1, level, out->data,
+                                    out->data + (size_t)level * n, 0, a->data, a->data + poly, 0, md, s);
+    return out.release();
+}
+
 void rescale_dense(vr_context* ctx, const u64* in, u64* out, u32 n_polys, u32 level, hipStream_t s)
 {
     const size_t n = ctx->n;

@@ -418,29 +418,50 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
     }
 }
 
-// out_k = (U_k - Y_k) * P^-1 (+ add_k), k = 0, 1; limb i < nq
+// out_k = (U_k - Y_k) e_i (+ add_k b_i, or + add_k when bm is null), k = 0,
+// 1; limb i < nq, (e_i, b_i) = (cm[i], bm[i]) with Shoup companions
 __global__ __launch_bounds__(kThreads) void k_moddown_finish(
     const u64* U, u64 u_stride, const u64* Y, u32 nq, u32 next, u32 log_n, u64* out0, u64* out1,
-    u64 out_stride, const u64* add0, u32 add0_g, const u64* add1, u64 add_stride, const ModQ* mq)
+    u64 out_stride, const u64* add0, u32 add0_g, const u64* add1, u64 add_stride, const ModQ* mq,
+    const ulonglong2* cm, const ulonglong2* bm)
 {
     const u32 n = 1u << log_n;
     const u32 t = blockIdx.x * kThreads + threadIdx.x;
     if (t >= n) return;
     const u32 i = blockIdx.y % nq;
     const u32 c = blockIdx.y / nq;
-    const ModQ m = mq[i];
-    const u64 q = m.q;
+    const u64 q = mq[i].q;
+    const ulonglong2 e = cm[i];
     const u64* u = U + (size_t)c * u_stride + (size_t)i * n + t;
     const u64* y = Y + ((size_t)c * 2 * nq + i) * n + t;
-    u64 r0 = shoup(u[0] + q - y[0], m.pinv, m.pinv_s, q);
-    u64 r1 = shoup(u[(size_t)next * n] + q - y[(size_t)nq * n], m.pinv, m.pinv_s, q);
+    u64 r0 = shoup(u[0] + q - y[0], e.x, e.y, q);
+    u64 r1 = shoup(u[(size_t)next * n] + q - y[(size_t)nq * n], e.x, e.y, q);
     if (add0) {
         u32 src = add0_g == 1 ? t : galois_src(t, add0_g, log_n);
-        r0 = add_mod(r0, add0[(size_t)c * add_stride + (size_t)i * n + src], q);
+        u64 b = add0[(size_t)c * add_stride + (size_t)i * n + src];
+        r0 = add_mod(r0, bm ? shoup(b, bm[i].x, bm[i].y, q) : b, q);
     }
-    if (add1) r1 = add_mod(r1, add1[(size_t)c * add_stride + (size_t)i * n + t], q);
+    if (add1) {
+        u64 b = add1[(size_t)c * add_stride + (size_t)i * n + t];
+        r1 = add_mod(r1, bm ? shoup(b, bm[i].x, bm[i].y, q) : b, q);
+    }
     out0[(size_t)c * out_stride + (size_t)i * n + t] = r0;
     out1[(size_t)c * out_stride + (size_t)i * n + t] = r1;
+}
+
+// Fold of P c into the q_l limb before a ModDown by P q_l: u += [P]_{q_l} c
+// on limb q_l of both components of every ciphertext (u, c0, c1 point at
+// that limb).
+__global__ __launch_bounds__(kThreads) void k_fold_pc(u64* U, u64 u_stride, u64 u_comp, const u64* c0,
+                                                      const u64* c1, u64 c_stride, u64 pm, u64 pm_s, u64 q,
+                                                      u32 n)
+{
+    const u32 t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const u32 ct = blockIdx.y >> 1, j = blockIdx.y & 1;
+    u64* u = U + (size_t)ct * u_stride + (size_t)j * u_comp + t;
+    const u64 c = (j ? c1 : c0)[(size_t)ct * c_stride + t];
+    *u = add_mod(*u, shoup(c, pm, pm_s, q), q);
 }
 
 u64 powmod_h(u64 b, u64 e, u64 q)
@@ -572,6 +593,19 @@ const ConvTable& moddown_table(vr_context* ctx, u32 level)
     for (u32 k = 0; k < ctx->K; k++) in.push_back(ctx->L + 1 + k);
     for (u32 i = 0; i <= level; i++) out.push_back(i);
     return ctx->moddown_tables[(int)level] = build_table(ctx, in, out);
+}
+
+// {q_l, p_0, ..., p_{K-1}} -> q_0..q_{l-1}: the conversion of a ModDown that
+// also drops q_l (relinearisation fused with the rescale)
+const ConvTable& moddown_rs_table(vr_context* ctx, u32 level)
+{
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto it = ctx->moddown_rs_tables.find((int)level);
+    if (it != ctx->moddown_rs_tables.end()) return it->second;
+    std::vector<u32> in{level}, out;
+    for (u32 k = 0; k < ctx->K; k++) in.push_back(ctx->L + 1 + k);
+    for (u32 i = 0; i < level; i++) out.push_back(i);
+    return ctx->moddown_rs_tables[(int)level] = build_table(ctx, in, out);
 }
 
 void launch_alu(vr_context* ctx, const ConvArgs& a, u32 n_polys, hipStream_t s)
@@ -904,7 +938,75 @@ void keyswitch_moddown_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u3
     ProfScope prof(ctx, kProfModDown, s, (u64)n_ct * 2 * k.nq);
     hipLaunchKernelGGL(k_moddown_finish, grid, dim3(kThreads), 0, s, U, u_stride, Y, k.nq, k.next,
                        ctx->log_n, out0, out1, out_stride, add0, add0_g, add1, add_stride,
-                       ctx->d_modq);
+                       ctx->d_modq, ctx->d_pinv_tab, (const ulonglong2*)nullptr);
+    VR_CHECK_LAUNCH();
+}
+
+// Relinearisation and rescale as one ModDown by P q_l (l = level): v_j = U_j
+// + P c_j on the Q limbs (U_j on the special ones, where P c_j vanishes), and
+//   out_j,i = (v_j,i - conv(v_j over {q_l, P})_i) (P q_l)^-1
+//           = (U_j,i - y_j,i) (P q_l)^-1 + c_j,i q_l^-1,   i < l,
+// so only the q_l limb takes the fold of P c_j before the conversion.
+void keyswitch_moddown_rescale_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u32 level,
+                                     u64* out0, u64* out1, u64 out_stride, const u64* c0,
+                                     const u64* c1, u64 c_stride, u64* scratch, hipStream_t s)
+{
+    if (level == 0) throw Error(VR_ELEVEL, "no limb left to rescale by");
+    KsShape k = ks_shape(ctx, level);
+    const u32 n = ctx->n, K = ctx->K, nd = K + 1, no = level;
+    if (u_stride != (u64)2 * k.next * n) throw Error(VR_EINVAL, "moddown: U blocks must be dense");
+    if (!c0 || !c1) throw Error(VR_EINVAL, "moddown-rescale: needs the ciphertext's c0 and c1");
+    u64* dcoef = scratch;                                   // [n_ct*2][K+1][N]
+    u64* Y = scratch + (size_t)n_ct * 2 * nd * n;           // [n_ct*2][level][N]
+    {
+        const u64 ql = ctx->mod[level];
+        u64 pm = 1 % ql;
+        for (u32 j = 0; j < K; j++) pm = (u64)((u128)pm * (ctx->mod[ctx->L + 1 + j] % ql) % ql);
+        dim3 grid((n + kThreads - 1) / kThreads, n_ct * 2);
+        hipLaunchKernelGGL(k_fold_pc, grid, dim3(kThreads), 0, s, U + (size_t)level * n, u_stride,
+                           (u64)k.next * n, c0 + (size_t)level * n, c1 + (size_t)level * n, c_stride, pm,
+                           shoup_companion(pm, ql), ql, n);
+        VR_CHECK_LAUNCH();
+    }
+    // q_l and the special limbs (consecutive in U) to the coefficient domain
+    LimbSet ls = poly_limbs(U, dcoef, n_ct * 2, nd, (u64)k.next * n, (int)level);
+    ls.slot0 = level;
+    ls.out_dense = 1;
+    ntt_inverse(ctx, ls, s);
+    const ConvTable& tb = moddown_rs_table(ctx, level);
+    ConvArgs a;
+    a.in = dcoef;
+    a.in_stride = (u64)nd * n;
+    a.out = Y;
+    a.out_stride = (u64)no * n;
+    a.skip_at = 0xffffffffu;
+    a.skip_len = 0;
+    a.tab = tb.dev;
+    a.n_in = tb.n_in;
+    a.n_out = tb.n_out;
+    a.log_n = ctx->log_n;
+    a.mq = ctx->d_modq;
+    launch_convert(ctx, a, tb, n_ct * 2, s);
+    LimbSet ly = poly_limbs(Y, Y, n_ct * 2, no, (u64)no * n, (int)level);
+    NttEpilogue& ep = ly.epi;
+    ep.a = U;
+    ep.a_ct = u_stride;
+    ep.a_comp = (u64)k.next * n;
+    ep.out0 = out0;
+    ep.out1 = out1;
+    ep.out_ct = out_stride;
+    ep.add0 = c0;
+    ep.add1 = c1;
+    ep.add_ct = c_stride;
+    ep.cmul = ctx->d_prinv_tab + (size_t)level * ctx->nmod();
+    ep.bmul = ctx->d_rinv_tab + (size_t)level * ctx->nmod();
+    if (ntt_forward(ctx, ly, s)) return;
+    dim3 grid((n + kThreads - 1) / kThreads, n_ct * no);
+    ProfScope prof(ctx, kProfModDown, s, (u64)n_ct * 2 * no);
+    hipLaunchKernelGGL(k_moddown_finish, grid, dim3(kThreads), 0, s, U, u_stride, Y, no, k.next,
+                       ctx->log_n, out0, out1, out_stride, c0, 1u, c1, c_stride, ctx->d_modq,
+                       ctx->d_prinv_tab + (size_t)level * ctx->nmod(),
+                       ctx->d_rinv_tab + (size_t)level * ctx->nmod());
     VR_CHECK_LAUNCH();
 }
 

@@ -471,10 +471,13 @@ void rotate_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in,
 }
 
 // relinearise a slab of 3-component ciphertexts into 2-component ones, each
-// key range with its session's relinearisation key
-Slab relin_slab_keyed(vr_context* ctx, const std::vector<KeyRange>& keys, const Slab& T, hipStream_t s)
+// key range with its session's relinearisation key; with `rescale` the
+// ModDown also divides by q_l (one rounding, level l - 1, scale / q_l)
+Slab relin_slab_keyed(vr_context* ctx, const std::vector<KeyRange>& keys, const Slab& T, hipStream_t s,
+                      bool rescale)
 {
     const u32 level = T.level, n_ct = T.n;
+    if (rescale && level == 0) throw Error(VR_ELEVEL, "no limb left to rescale by");
     const size_t n = ctx->n;
     KsShape k = ks_shape(ctx, level);
     check_ranges(keys, n_ct);
@@ -484,7 +487,9 @@ Slab relin_slab_keyed(vr_context* ctx, const std::vector<KeyRange>& keys, const 
     u64* X = as_u64(xbuf);
     BufPtr ubuf = dev_alloc(ctx, ((size_t)cs * us + keyswitch_moddown_scratch(ctx, level, cs)) * sizeof(u64), s);
     u64* U = as_u64(ubuf);
-    Slab out = new_slab(ctx, n_ct, 2, level, T.scale, s);
+    Slab out = rescale ? new_slab(ctx, n_ct, 2, level - 1, T.scale / (double)ctx->mod[level], s)
+                       : new_slab(ctx, n_ct, 2, level, T.scale, s);
+    const size_t out_comp = (size_t)(rescale ? level : level + 1) * n;
     for (u32 c0 = 0; c0 < n_ct; c0 += cs) {
         const u32 nc = std::min(cs, n_ct - c0);
         const u64* t = T.ct(c0);
@@ -496,15 +501,24 @@ Slab relin_slab_keyed(vr_context* ctx, const std::vector<KeyRange>& keys, const 
                                   hi - lo, kr.ek->rlk.data, level, 1, U + (size_t)(lo - c0) * us, us, s);
         }
         u64* o = out.ct(c0);
-        keyswitch_moddown_batch(ctx, U, us, nc, level, o, o + (size_t)k.nq * n, out.stride, t, 1,
-                                t + (size_t)k.nq * n, T.stride, U + (size_t)cs * us, s);
+        if (rescale)
+            keyswitch_moddown_rescale_batch(ctx, U, us, nc, level, o, o + out_comp, out.stride, t,
+                                            t + (size_t)k.nq * n, T.stride, U + (size_t)cs * us, s);
+        else
+            keyswitch_moddown_batch(ctx, U, us, nc, level, o, o + out_comp, out.stride, t, 1,
+                                    t + (size_t)k.nq * n, T.stride, U + (size_t)cs * us, s);
     }
     return out;
 }
 
 Slab relin_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& T, hipStream_t s)
 {
-    return relin_slab_keyed(ctx, {KeyRange{0, T.n, ek}}, T, s);
+    return relin_slab_keyed(ctx, {KeyRange{0, T.n, ek}}, T, s, false);
+}
+
+Slab relin_rescale_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& T, hipStream_t s)
+{
+    return relin_slab_keyed(ctx, {KeyRange{0, T.n, ek}}, T, s, true);
 }
 
 Slab rescale_slab(vr_context* ctx, const Slab& in, hipStream_t s)
@@ -619,7 +633,7 @@ Slab poly_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& x, const dou
                                t.level + 1, ctx->log_n, ctx->d_modq);
             VR_CHECK_LAUNCH();
         }
-        t = rescale_slab(ctx, relin_slab(ctx, ek, P, s), s);
+        t = relin_rescale_slab(ctx, ek, P, s);
         add_const_slab(ctx, t, coeffs[i], s);
     }
     return t;
@@ -719,7 +733,7 @@ Slab conv_encw_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& x, u32 
     Slab T = tensor_terms_slab(ctx, x, rot.empty() ? nullptr : &rot[0], Kw, (u64)C_in * k * k * Kw.stride, ta,
                                tb, toff, wo, C_out * wo, s);
     rot.clear();
-    Slab y = rescale_slab(ctx, relin_slab(ctx, ek, T, s), s);
+    Slab y = relin_rescale_slab(ctx, ek, T, s);
     add_bias_cts(ctx, y, Bias, wo, s);
     return y;
 }
@@ -736,7 +750,7 @@ Slab fc_encw_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& y, const 
     }
     toff.push_back((u32)ta.size());
     Slab T = tensor_terms_slab(ctx, y, nullptr, Wc, (u64)y.n * Wc.stride, ta, tb, toff, 1, n_out, s);
-    Slab z = rescale_slab(ctx, relin_slab(ctx, ek, T, s), s);
+    Slab z = relin_rescale_slab(ctx, ek, T, s);
     for (u32 st = 1; st < block; st <<= 1) {
         std::vector<Slab> r;
         rotate_slab(ctx, ek, z, {(int32_t)st}, r, s);
@@ -758,8 +772,7 @@ Slab square_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipStr
                            in.stride, nl, ctx->log_n, ctx->d_modq);
         VR_CHECK_LAUNCH();
     }
-    Slab R = relin_slab(ctx, ek, T, s);
-    return rescale_slab(ctx, R, s);
+    return relin_rescale_slab(ctx, ek, T, s);
 }
 
 u32 pow2ceil(u32 x)
@@ -1092,7 +1105,7 @@ std::vector<Slab> matmul_multi(vr_context* ctx, const vr_eval_keys* ek, const st
             }
         }
     }
-    Slab out = rescale_slab(ctx, relin_slab(ctx, ek, T, s), s);
+    Slab out = relin_rescale_slab(ctx, ek, T, s);
     std::vector<Slab> res(nr);
     for (u32 r = 0; r < nr; r++) {
         res[r] = out;
@@ -1136,7 +1149,7 @@ std::vector<Slab> matmul_outer_multi(vr_context* ctx, const vr_eval_keys* ek, co
                                ctx->d_modq, 0u);
             VR_CHECK_LAUNCH();
         }
-    Slab out = rescale_slab(ctx, relin_slab(ctx, ek, acc, s), s);
+    Slab out = relin_rescale_slab(ctx, ek, acc, s);
     std::vector<Slab> res(nr);
     for (u32 r = 0; r < nr; r++) {
         res[r] = out;
@@ -1236,7 +1249,7 @@ Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab&
                                y.level + 1, ctx->log_n, ctx->d_modq);
             VR_CHECK_LAUNCH();
         }
-        y = rescale_slab(ctx, relin_slab_keyed(ctx, kout, T, s), s);
+        y = relin_slab_keyed(ctx, kout, T, s, true);
     }
     if (!d0.fc_out) return y;
     // FC: weight products per network and set at the weights' level, one

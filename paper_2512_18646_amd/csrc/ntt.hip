@@ -707,6 +707,9 @@ struct LimbK {
     u32 eb_g;
     ulonglong2 ec;
     double ecf;
+    bool ebm;          // B is scaled by ebc before it is added
+    ulonglong2 ebc;
+    double ebcf;
 };
 
 // Where limb r's input comes from: the limb itself, or (forward, fused
@@ -757,6 +760,11 @@ __device__ __forceinline__ LimbK limb_consts(const NttPass& p, u32 r)
         c.eb_g = j ? 1 : ep.add0_g;
         c.ec = ep.cmul[mod];
         c.ecf = to_bal(c.ec.x, c.q, c.qd);
+        c.ebm = ep.bmul != nullptr;
+        if (c.ebm) {
+            c.ebc = ep.bmul[mod];
+            c.ebcf = to_bal(c.ebc.x, c.q, c.qd);
+        }
     }
     return c;
 }
@@ -771,14 +779,18 @@ __device__ __forceinline__ void wave_lds_sync()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// The finish of a forward transform on one word: (A - y) c (+ B) with B read
-// through the Galois map, FP64 path (|A - y| < 27 q, the product within 1.5 q,
-// 3 q when q >= 2^50, reduced before B is added) or integer path (y lazy in
-// [0, 4q)).
+// The finish of a forward transform on one word: (A - y) c (+ B, or + B c_b)
+// with B read through the Galois map, FP64 path (|A - y| < 27 q, the product
+// within 1.5 q, 3 q when q >= 2^50, reduced before B is added) or integer path
+// (y lazy in [0, 4q)).
 __device__ __forceinline__ u64 finish_fp(const LimbK& c, u64 a, u64 b, double y)
 {
     double v = fbal(fmulmod(to_bal(a, c.q, c.qd) - y, c.ecf, c.qd, c.qinv), c.qd, c.qinv);
-    if (c.eb) v += to_bal(b, c.q, c.qd);
+    if (c.eb) {
+        double bb = to_bal(b, c.q, c.qd);
+        if (c.ebm) bb = fbal(fmulmod(bb, c.ebcf, c.qd, c.qinv), c.qd, c.qinv);
+        v += bb;
+    }
     return to_canon(v, c.qd, c.qinv);
 }
 
@@ -788,7 +800,7 @@ __device__ __forceinline__ u64 finish_int(const LimbK& c, u64 a, u64 b, u64 y)
     y = y >= q2 ? y - q2 : y;
     y = y >= q ? y - q : y;
     u64 v = shoup(a + q - y, c.ec.x, c.ec.y, q);
-    if (c.eb) v = add_mod(v, b, q);
+    if (c.eb) v = add_mod(v, c.ebm ? shoup(b, c.ebc.x, c.ebc.y, q) : b, q);
     return v;
 }
 

@@ -205,15 +205,21 @@ void build_context(vr_context* ctx, const vr_params* p, int device)
     }
     ctx->d_modq = upload(ctx->modq);
     {
-        std::vector<ulonglong2> pinv(nmod), rinv((size_t)(ctx->L + 1) * nmod);
+        std::vector<ulonglong2> pinv(nmod), rinv((size_t)(ctx->L + 1) * nmod),
+            prinv((size_t)(ctx->L + 1) * nmod);
         for (u32 m = 0; m < nmod; m++) pinv[m] = make_ulonglong2(ctx->modq[m].pinv, ctx->modq[m].pinv_s);
         for (u32 l = 0; l <= ctx->L; l++)
             for (u32 i = 0; i < l; i++) {
                 const u64 q = ctx->mod[i], c = powmod_p(ctx->mod[l] % q, q - 2, q);
                 rinv[(size_t)l * nmod + i] = make_ulonglong2(c, shoup_companion(c, q));
+                u64 pq = ctx->mod[l] % q;
+                for (u32 k = 0; k < ctx->K; k++) pq = (u64)((u128)pq * (ctx->mod[ctx->L + 1 + k] % q) % q);
+                const u64 e = powmod_p(pq, q - 2, q);
+                prinv[(size_t)l * nmod + i] = make_ulonglong2(e, shoup_companion(e, q));
             }
         ctx->d_pinv_tab = upload(pinv);
         ctx->d_rinv_tab = upload(rinv);
+        ctx->d_prinv_tab = upload(prinv);
     }
     ctx->d_tw = upload(tw);
     ctx->d_itw = upload(itw);
@@ -247,11 +253,14 @@ void destroy_context_tables(vr_context* ctx)
     (void)hipFree(ctx->d_itwf);
     (void)hipFree(ctx->d_fft_tw);
     (void)hipFree(ctx->d_pinv_tab);
+    (void)hipFree(ctx->d_prinv_tab);
     (void)hipFree(ctx->d_rinv_tab);
     (void)hipFree(ctx->d_gexp);
     for (auto& kv : ctx->modup_tables)
         (void)hipFree(kv.second.dev), (void)hipFree(kv.second.wt), (void)hipFree(kv.second.wf);
     for (auto& kv : ctx->moddown_tables)
+        (void)hipFree(kv.second.dev), (void)hipFree(kv.second.wt), (void)hipFree(kv.second.wf);
+    for (auto& kv : ctx->moddown_rs_tables)
         (void)hipFree(kv.second.dev), (void)hipFree(kv.second.wt), (void)hipFree(kv.second.wf);
 }
 

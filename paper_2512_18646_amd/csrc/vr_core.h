@@ -318,11 +318,13 @@ struct vr_context {
     // (c, Shoup companion) per modulus: P^-1 mod q_i (Q chain), and for each
     // level l, q_l^-1 mod q_i at [l][i] (i < l): the ModDown and rescale scalings
     ulonglong2* d_pinv_tab = nullptr;  // [nmod]
-    ulonglong2* d_rinv_tab = nullptr;  // [L + 1][nmod]
+    ulonglong2* d_rinv_tab = nullptr;  // [L + 1][nmod]: q_l^-1 mod q_i, i < l
+    ulonglong2* d_prinv_tab = nullptr; // [L + 1][nmod]: (P q_l)^-1 mod q_i, i < l
     int* d_gexp = nullptr;            // [S] 5^j mod 2N
     vr::u64 cdt[20];
     std::map<std::pair<int, int>, vr::ConvTable> modup_tables;   // (level, digit)
     std::map<int, vr::ConvTable> moddown_tables;                 // level
+    std::map<int, vr::ConvTable> moddown_rs_tables;              // level: {q_l, P} -> q_<l
     // device-resident constants of layer calls (weights, term lists), keyed by
     // the call's shape and weight bytes, so repeated calls upload nothing
     std::map<std::string, std::shared_ptr<void>> plans;
@@ -430,7 +432,8 @@ struct ProfScope {
 // (A - y) c (+ B) mod q, with A(p, i) = a + k a_ct + j a_comp + i N,
 // out(p, i) = out_j + k out_ct + i N, B(p, i) = add_j + k add_ct + i N
 // (component 0 read through sigma_g when add0_g != 1, a null add_j adds
-// nothing) and (c, floor(c 2^64 / q)) = cmul[modulus of the limb].  The
+// nothing; B is first multiplied by bmul[modulus of the limb] when bmul is
+// set) and (c, floor(c 2^64 / q)) = cmul[modulus of the limb].  The
 // limbs of each poly are its first per_poly ones (no skip).  Applied only by
 // the whole-limb transform; ntt_forward reports whether it was.
 struct NttEpilogue {
@@ -444,6 +447,7 @@ struct NttEpilogue {
     u64 add_ct = 0;
     u32 add0_g = 1;
     const ulonglong2* cmul = nullptr;
+    const ulonglong2* bmul = nullptr;
 };
 
 struct LimbSet {

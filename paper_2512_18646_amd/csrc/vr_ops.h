@@ -81,6 +81,13 @@ void keyswitch_moddown(vr_context* ctx, u64* U, u32 level, u64* out0, u64* out1,
 void keyswitch_moddown_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u32 level,
                              u64* out0, u64* out1, u64 out_stride, const u64* add0, u32 add0_g,
                              const u64* add1, u64 add_stride, u64* scratch, hipStream_t s);
+// Relinearisation fused with the rescale: ModDown of U by P q_l (l = level)
+// with c0/c1 (the ciphertext's first two components, level l, c_stride apart
+// per ciphertext) folded in; out0/out1 get l limbs (level l - 1).  Scratch as
+// keyswitch_moddown_scratch(level, n_ct).
+void keyswitch_moddown_rescale_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u32 level,
+                                     u64* out0, u64* out1, u64 out_stride, const u64* c0,
+                                     const u64* c1, u64 c_stride, u64* scratch, hipStream_t s);
 // scratch sizes in u64 words
 size_t keyswitch_modup_scratch(vr_context* ctx, u32 level);     // X + coef
 size_t keyswitch_moddown_scratch(vr_context* ctx, u32 level, u32 n_ct);

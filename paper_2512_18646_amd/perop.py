@@ -3,7 +3,8 @@
 This is the plain per-operation path the batched layer calls (vr_conv2d,
 vr_square, vr_fc, vr_matmul) are measured against; it issues exactly the
 operations of the schedules (rotations hoisted per input column, MulConst,
-MulPlain, Add, AddConst, Rescale, Tensor, Relinearise, Rotate) and therefore
+MulPlain, Add, AddConst, Rescale, Tensor, the fused Relinearise-Rescale,
+Rotate) and therefore
 reaches the same limbs.  Every arithmetic step runs in libvr.so.
 """
 
@@ -43,8 +44,7 @@ def conv2d(ctx, keys, cols, C_in, h, w, pad, K, bias, stride, stream=None):
 
 
 def square(ctx, keys, cts, stream=None):
-    return [ctx.rescale(ctx.relinearize(keys, ctx.tensor(y, y, stream=stream), stream=stream), stream=stream)
-            for y in cts]
+    return [ctx.relin_rescale(keys, ctx.tensor(y, y, stream=stream), stream=stream) for y in cts]
 
 
 def matmul(ctx, keys, A, Bbar, m, n, p, stream=None):
@@ -57,7 +57,7 @@ def matmul(ctx, keys, A, Bbar, m, n, p, stream=None):
         for idx in range(Pp):
             t = ctx.tensor(A[k], rots[idx], stream=stream)
             T[idx] = t if T[idx] is None else ctx.add(T[idx], t, stream=stream)
-    return [ctx.rescale(ctx.relinearize(keys, T[idx], stream=stream), stream=stream) for idx in range(Pp)]
+    return [ctx.relin_rescale(keys, T[idx], stream=stream) for idx in range(Pp)]
 
 
 def fc(ctx, keys, Y, W_pt, bias, block, stream=None):

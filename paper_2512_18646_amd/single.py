@@ -5,8 +5,9 @@ homomorphic convolution (Algorithm 4), and the virtual rotation vRot
 (Algorithm 5).  This is the prior method the column-wise encodings replace
 when an image or matrix fits one ciphertext.
 
-Every arithmetic step is one C-ABI call (vr_rotate, vr_mul_plain, vr_mul,
-vr_rescale, vr_add, vr_mod_drop); this module only builds the 0/1 masks and
+Every arithmetic step is one C-ABI call (vr_rotate, vr_mul_plain,
+vr_mul_rescale, vr_rescale, vr_add, vr_mod_drop); this module only builds the
+0/1 masks and
 chooses the calls.  Layout: an r x c matrix is packed row-major into r c
 slots and that block is repeated over the S slots (r c a power of two), so a
 rotation of the ciphertext acts cyclically on every copy.  Masks are encoded
@@ -94,8 +95,8 @@ class Ops:
 
     def mul(self, a, b):
         a, b = self._level(a, b)
-        self.calls += 2
-        return self.ctx.rescale(self.ctx.mul(self.keys, a, b, stream=self.stream), stream=self.stream)
+        self.calls += 1
+        return self.ctx.mul_rescale(self.keys, a, b, stream=self.stream)
 
     def enc(self, vec, like):
         if self._encrypt is None:

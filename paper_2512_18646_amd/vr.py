@@ -90,6 +90,8 @@ _SIGS = {
     "vr_relinearize": [P, P, P, PP, P],
     "vr_mul": [P, P, P, P, PP, P],
     "vr_rescale": [P, P, PP, P],
+    "vr_relin_rescale": [P, P, P, PP, P],
+    "vr_mul_rescale": [P, P, P, P, PP, P],
     "vr_mod_drop": [P, P, U32, PP, P],
     "vr_rotate": [P, P, P, I32, PP, P],
     "vr_rotate_many": [P, P, P, P, SZ, PP, P],
@@ -436,6 +438,13 @@ class Context:
 
     def rescale(self, a, stream=None):
         return self._unary(lib.vr_rescale, a.h, stream=stream)
+
+    def relin_rescale(self, keys, a, stream=None):
+        """Relinearisation and rescale as one ModDown by P q_l (level - 1)."""
+        return self._unary(lib.vr_relin_rescale, keys.ek, a.h, stream=stream)
+
+    def mul_rescale(self, keys, a, b, stream=None):
+        return self._unary(lib.vr_mul_rescale, keys.ek, a.h, b.h, stream=stream)
 
     def mod_drop(self, a, level, stream=None):
         return self._unary(lib.vr_mod_drop, a.h, level, stream=stream)

@@ -272,6 +272,8 @@ def test_keyswitch_match_other_chains(name, level, mode):
         assert_same(many[0], o.rotate(a, 3, ok), "%s hoisted 3 %s" % (name, mode))
         t = o.tensor(a, a)
         assert_same(g.relinearize(gk, to_gpu(g, t)), o.relinearize(t, ok), "%s relin %s" % (name, mode))
+        assert_same(g.relin_rescale(gk, to_gpu(g, t)), o.relin_rescale(t, ok),
+                    "%s relin-rescale l=%d %s" % (name, level, mode))
         if mode == "auto" and name == "C3":   # one-limb digits (C2) convert inside the NTT
             rep = g.tuning_report()
             assert "modup l%d d0" % level in rep and "untimed" not in rep.split("modup l%d d0" % level)[1].split("\n")[0]
@@ -298,6 +300,7 @@ def test_finish_in_transform_and_separate_match(name, level, plan):
         assert_same(many[0], o.rotate(a, 3, ok), "%s hoisted 3 %s" % (name, plan))
         t = o.tensor(a, a)
         assert_same(g.relinearize(gk, to_gpu(g, t)), o.relinearize(t, ok), "%s relin %s" % (name, plan))
+        assert_same(g.relin_rescale(gk, to_gpu(g, t)), o.relin_rescale(t, ok), "%s relin-rescale %s" % (name, plan))
         assert_same(g.rescale(ga), o.rescale(a), "%s rescale %s" % (name, plan))
         assert_same(g.rescale(to_gpu(g, t)), o.rescale(t), "%s rescale 3 comps %s" % (name, plan))
     finally:
@@ -315,7 +318,8 @@ def test_finish_every_plan_n16():
     z = np.random.default_rng(44).uniform(-1, 1, o.slots)
     a = o.encrypt(ok, o.encode(z, 3, o.scale), 12, 3)
     t = o.tensor(a, a)
-    want = [o.rotate(a, 1, ok), o.rotate(a, 3, ok), o.relinearize(t, ok), o.rescale(a), o.rescale(t)]
+    want = [o.rotate(a, 1, ok), o.rotate(a, 3, ok), o.relinearize(t, ok), o.rescale(a), o.rescale(t),
+            o.relin_rescale(t, ok)]
     ga, gt = to_gpu(g, a), to_gpu(g, t)
     tried = 0
     try:
@@ -331,10 +335,33 @@ def test_finish_every_plan_n16():
             assert_same(g.relinearize(gk, gt), want[2], "relin cand:%d" % tried)
             assert_same(g.rescale(ga), want[3], "rescale cand:%d" % tried)
             assert_same(g.rescale(gt), want[4], "rescale 3 comps cand:%d" % tried)
+            assert_same(g.relin_rescale(gk, gt), want[5], "relin-rescale cand:%d" % tried)
             tried += 1
     finally:
         g.set_tuning("ntt", "auto")
     assert tried >= 4
+
+
+def test_relin_rescale_product_and_errors(c1):
+    """vr_mul_rescale is the tensor then the fused ModDown by P q_l (against the
+    oracle word for word, and decoded against FP64); a level-0 or 2-component
+    input is refused."""
+    from paper_2512_18646_amd import vr
+    o, ok, g, gk = c1
+    rng = np.random.default_rng(46)
+    x, y = rng.uniform(-1, 1, o.slots), rng.uniform(-1, 1, o.slots)
+    a = o.encrypt(ok, o.encode(x, o.L, o.scale), 13, 0)
+    b = o.encrypt(ok, o.encode(y, o.L, o.scale), 13, 1)
+    got = g.mul_rescale(gk, to_gpu(g, a), to_gpu(g, b))
+    assert_same(got, o.relin_rescale(o.tensor(a, b), ok), "mul-rescale")
+    assert np.max(np.abs(g.decode(g.decrypt(gk, got)) - x * y)) < 2.0 ** -20
+    with pytest.raises(vr.VRError) as e:
+        g.relin_rescale(gk, to_gpu(g, a))
+    assert e.value.code == vr.VR_EINVAL
+    t0 = o.tensor(o.mod_drop(a, 0), o.mod_drop(b, 0))
+    with pytest.raises(vr.VRError) as e:
+        g.relin_rescale(gk, to_gpu(g, t0))
+    assert e.value.code == vr.VR_ELEVEL
 
 
 def test_error_paths(c1):

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 import sympy
 
-from oracle import Context, Params, PRESETS, gen_primes, find_psi, cdt_table, security_bound
+from oracle import Context, Params, PRESETS, Ciphertext, gen_primes, find_psi, cdt_table, security_bound
 from oracle._clib import lib, ptr
 from oracle.ckks import rha, rha_array
 
@@ -295,6 +295,39 @@ def test_mod_down_is_division_by_p():
         if diff > Qm // 2:
             diff -= Qm
         assert abs(diff) <= ctx.K / 2 + 1
+
+
+@pytest.mark.parametrize("p_bits,dnum", [((51, 51, 51), 1), ((51,), 3)])
+def test_relin_rescale_is_one_rounded_division(p_bits, dnum):
+    """Relinearisation and rescale as one ModDown by P q_l agree, coefficient
+    by coefficient over q_0..q_{l-1}, with Rescale(Relin(.)) to within the two
+    roundings (|diff| <= K/2 + 2): a dropped P c term or a division by the
+    wrong prime moves the result by about q_l or P."""
+    ctx = Context(Params(3, [60, 50, 50, 50], list(p_bits), dnum, 30.0, allow_insecure=True))
+    keys = ctx.keygen(12)
+    rng = np.random.default_rng(9)
+    lv = 3
+    c = np.stack([np.stack([rng.integers(0, q, ctx.n, dtype=np.uint64) for q in ctx.moduli(lv)])
+                  for _ in range(3)])
+    a = Ciphertext(c, lv, 2.0 ** 60)
+    fused = ctx.relin_rescale(a, keys)
+    ref = ctx.rescale(ctx.relinearize(a, keys))
+    assert fused.level == ref.level == lv - 1 and fused.scale == ref.scale
+    Qm = 1
+    for q in ctx.q[:lv]:
+        Qm *= q
+    for comp in range(2):
+        for t in range(ctx.n):
+            X, _ = _crt([fused.c[comp, i, t] for i in range(lv)], ctx.q[:lv])
+            Y, _ = _crt([ref.c[comp, i, t] for i in range(lv)], ctx.q[:lv])
+            diff = (X - Y) % Qm
+            if diff > Qm // 2:
+                diff -= Qm
+            assert abs(diff) <= ctx.K / 2 + 2
+    # the fused form is not the unfused one limb for limb on random words
+    assert not np.array_equal(fused.c, ref.c)
+    with pytest.raises(ValueError):
+        ctx.relin_rescale(Ciphertext(c[:, :1], 0, 1.0), keys)
 
 
 # -------------------------------------------------------------- automorphism

@@ -100,6 +100,25 @@ def test_key_switch_noise_bound():
         assert np.abs(e).max() < 2.0 ** 16
 
 
+def test_relin_rescale_decrypts_the_product():
+    """x y through the fused relinearise-and-rescale decodes to the FP64
+    product at the scale of a rescale, with no more error than the two-step
+    form."""
+    ctx = Context(PRESETS["C1"])
+    keys = ctx.keygen(21)
+    rng = np.random.default_rng(22)
+    x, y = rng.uniform(-1, 1, ctx.slots), rng.uniform(-1, 1, ctx.slots)
+    cx = ctx.encrypt(keys, ctx.encode(x, ctx.L, ctx.scale), 3, 0)
+    cy = ctx.encrypt(keys, ctx.encode(y, ctx.L, ctx.scale), 3, 1)
+    T = ctx.tensor(cx, cy)
+    f = ctx.relin_rescale(T, keys)
+    r = ctx.rescale(ctx.relinearize(T, keys))
+    assert f.level == ctx.L - 1 and f.scale == r.scale
+    ef = np.max(np.abs(ctx.decode(ctx.decrypt(keys, f)) - x * y))
+    er = np.max(np.abs(ctx.decode(ctx.decrypt(keys, r)) - x * y))
+    assert ef < EPS and ef < 2 * er + 1e-12
+
+
 # ----------------------------------------------------------------- rotations
 
 def test_rotation_invariants():
