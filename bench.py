@@ -113,6 +113,19 @@ def conv_setup(vr, level, sets, ntt_plan="auto"):
     return W, ctx, keys, K, bias, cols
 
 
+def decoded_gap(ctx, keys, got, ref):
+    """max |decode(got) - decode(ref)| / max |decode(ref)| over paired
+    ciphertexts: the per-operation path runs the plain conv (a ModDown per
+    rotation) where the layer calls round once per output, so the two agree
+    in their messages, not their limbs."""
+    num = den = 0.0
+    for a, b in zip(got, ref):
+        da, db = ctx.decode(ctx.decrypt(keys, a)), ctx.decode(ctx.decrypt(keys, b))
+        num = max(num, float(np.max(np.abs(da - db))))
+        den = max(den, float(np.max(np.abs(db))))
+    return num / den if den else num
+
+
 def step_batched(ctx, keys, W, K, bias, cols):
     """All sets in one multi-set conv call, then x^2 over every output."""
     flat = [c for cs in cols for c in cs]
@@ -227,8 +240,8 @@ def cnn128_bench(vr, level_in, sets, reps, graph=False):
         zp = perop.fc(ctx, keys, y, W_pt, bfc, Hp)
         sync()
         t_op = time.perf_counter() - t
-        same = all(np.array_equal(zp[i].export(), ref[i].export()) for i in range(len(ref)))
-        res["per_op"] = {"images_per_s": round(W.batch / t_op, 2), "identical": bool(same)}
+        res["per_op"] = {"images_per_s": round(W.batch / t_op, 2),
+                         "message_rel_diff": decoded_gap(ctx, keys, zp, ref)}
         del gout, ref, y, zp
     reserved, _ = ctx.mem_info()
     res["device_gib_reserved"] = round(reserved / 2 ** 30, 1)
@@ -775,8 +788,9 @@ def cnn128_logit_error(C, z):
 
 
 def headline_extras(vr, perop, C, args, ref, images):
-    """The headline step as one replayed HIP graph and as one C-ABI call per
-    HE operation (first set), limbs against the whole-network call."""
+    """The headline step as one replayed HIP graph (limbs against the
+    whole-network call) and as one C-ABI call per HE operation on the first
+    set (the plain conv schedule: its decoded logits against FP64)."""
     ctx, keys, net, W = C["ctx"], C["keys"], C["net"], C["W"]
     flat = [c for cs in C["cols"] for c in cs]
     res = {}
@@ -806,7 +820,7 @@ def headline_extras(vr, perop, C, args, ref, images):
     sync()
     t_op = time.perf_counter() - t
     res["per_op"] = {"images_per_s": round(W.batch / t_op, 2),
-                     "identical": bool(all(np.array_equal(zp[i].export(), ref[i]) for i in range(len(ref))))}
+                     "decoded_rel_error": cnn128_logit_error(C, zp)}
     del y, zp
     return res
 
@@ -892,7 +906,7 @@ def conv28_bench(vr, perop, args):
     sync()
     t_op = time.perf_counter() - t
     res["per_op"] = {"images_per_s": round(W.batch / t_op, 2),
-                     "identical": bool(all(np.array_equal(ys[i].export(), ref[i].export()) for i in range(len(ref))))}
+                     "message_rel_diff": decoded_gap(ctx, keys, ys, ref)}
     res["batched_over_per_op"] = round(res["images_per_s"] / res["per_op"]["images_per_s"], 2)
     return res
 
@@ -928,17 +942,17 @@ def _orc_c3_sample(_=None):
     o, ok, cts = _ORC["o"], _ORC["ok"], _ORC["cts"]
     t = {}
     t0 = time.perf_counter()
-    o.rotate(cts[24], 1, ok)
+    r1 = o.rotate_ext(cts[24], 1, ok)
     t["rot24"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     acc = None
     dq = float(o.q[24])
     for r in range(6):
-        x = o.mul_const(cts[24], 0.01 * (r + 1), dq)
-        acc = x if acc is None else o.add(acc, x)
+        x = o.mul_const_ext(r1, 0.01 * (r + 1), dq)
+        acc = x if acc is None else o.add_ext(acc, x)
     t["mulconst_add24"] = (time.perf_counter() - t0) / 6
     t0 = time.perf_counter()
-    y = o.rescale(o.add_const(acc, 0.5))
+    y = o.mod_down_rescale(o.add_const_ext(acc, 0.5))
     t["addconst_rescale24"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     o.relin_rescale(o.tensor(y, y), ok)
@@ -1001,8 +1015,9 @@ def cpu_oracle_child():
         "all_core_images_per_s": round(128 * sets_per_s_all, 5), "cores": cores,
         "seconds_per_op_single_core": {k: round(v, 4) for k, v in one.items()},
         "op_counts_per_set": C3_OPS, "extrapolated": True,
-        "sample": "one of each operation class of the 128-image C3 set at level 24 (1 rotation at level 24, 6 "
-                  "MulConst+Add, AddConst+Rescale, one x^2 at level 23, 6 MulPlain+Add at level 1, Rescale, "
+        "sample": "one of each operation class of the 128-image C3 set at level 24 (1 rotation kept in the "
+                  "extended basis at level 24, 6 MulConst+Add there, AddConst + ModDown by P q_l, one x^2 "
+                  "(tensor + fused relinearise-rescale) at level 23, 6 MulPlain+Add at level 1, Rescale, "
                   "rotate+add at level 0), %.1f s on one core, scaled by the set's operation counts; all-core: "
                   "the same sample on %d processes at once (%.1f s wall)" % (t_one, cores, t_all),
         "setup_s": round(setup, 1)}

@@ -16,5 +16,5 @@ Layout:
 
 Parity status per function is listed in the header of each module.
 """
-from .ckks import (Params, Context, Ciphertext, Plaintext, Keys, SwitchingKey,  # noqa: F401
+from .ckks import (Params, Context, Ciphertext, ExtCiphertext, Plaintext, Keys, SwitchingKey,  # noqa: F401
                    gen_primes, find_psi, cdt_table, security_bound, PRESETS)

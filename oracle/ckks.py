@@ -24,6 +24,11 @@ reach the same limbs:
   rotation    ModUp(c1), automorphism of every extended digit, inner product
               with the key of sigma_g(s), ModDown, plus sigma_g(c0)
   rescale     centred last limb, (c_i - [r]_{q_i}) * q_l^-1
+  lazy ModDown  a product's relinearisation and its rescale, or a sum of
+              scaled rotations and its rescale, end in one ModDown by P q_l:
+              the operands stay P times a ciphertext over q_0..q_l, P
+              (ExtCiphertext) and the centred conversion of their
+              {q_l, p_0..p_{K-1}} limbs is divided out once
   encode      m_t = RHA((2*scale/N) Re sum_j z_j exp(-i pi g_j t / N)),
               g_j = 5^j mod 2N, via a 2N-point FFT; decode reads limb q_0
   constants   MulConst: RHA(c * dc) exactly as an integer; AddConst adds
@@ -168,6 +173,17 @@ class Ciphertext:
     @property
     def ncomp(self):
         return self.c.shape[0]
+
+
+@dataclass
+class ExtCiphertext:
+    """P times a 2-component ciphertext, over q_0..q_level, p_0..p_{K-1}
+    (coefficient domain): a key switch before its ModDown, on which linear
+    operations continue until one ModDown by P q_level.  `scale` is the scale
+    of the ciphertext it stands for (P is implicit)."""
+    c: np.ndarray          # [2, level+1+K, N] uint64
+    level: int
+    scale: float
 
 
 @dataclass
@@ -616,40 +632,114 @@ class Context:
     def mul(self, a, b, keys):
         return self.relinearize(self.tensor(a, b), keys)
 
-    def relin_rescale(self, a: Ciphertext, keys: Keys):
-        """Relinearisation and rescale as one ModDown by P q_l: with (u0, u1)
-        the key-switch sums of c2 over q_0..q_l, p_0..p_{K-1}, each component
-        v = u + P c (P c vanishes on the special primes) is divided by P q_l
-        with the same centred fast conversion ModDown uses, now from the drop
-        set {q_l, p_0..p_{K-1}} to q_0..q_{l-1}:
-            out_i = (v_i - conv(v_D)_i) (P q_l)^-1 mod q_i,   i < l.
-        Level l - 1, scale / q_l as for rescale.  It equals rescale(relinearize(a))
-        up to a rounding difference of the division (not limb for limb)."""
-        assert a.ncomp == 3
+    # ------------------------------------------------ lazy ModDown (P basis)
+    def p_mod(self, q):
+        P = 1
+        for pk in self.p:
+            P = P * pk % q
+        return P
+
+    def lift(self, a: Ciphertext):
+        """P a over q_0..q_l, P: P c_i on the Q limbs, zero on the special
+        limbs (P vanishes there)."""
+        assert a.ncomp == 2
         lv = a.level
+        c = np.zeros((2, lv + 1 + self.K, self.n), dtype=np.uint64)
+        for k in range(2):
+            for i, q in enumerate(self.moduli(lv)):
+                c[k, i] = self.vscale(a.c[k, i], self.p_mod(q), q)
+        return ExtCiphertext(c, lv, a.scale)
+
+    def rotate_ext(self, a: Ciphertext, step, keys: Keys):
+        """Rotation without its ModDown: (u0 + P sigma_g(c0), u1) with (u0, u1)
+        the key-switch sums of sigma_g(ModUp(c1)) -- mod_down_rescale of it is
+        the rescaled rotation up to one rounding."""
+        assert a.ncomp == 2
+        g = self.galois_element(step)
+        if g == 1:
+            return self.lift(a)
+        if g not in keys.rot:
+            raise KeyError("no rotation key for step %d" % step)
+        lv = a.level
+        ext = self.ext_moduli(lv)
+        xs = [self.mod_up(a.c[1], lv, j) for j in range(self.n_digits(lv))]
+        xs = [np.stack([self.automorphism(x[e], g, q) for e, q in enumerate(ext)]) for x in xs]
+        u = self.inner_product(xs, keys.rot[g], lv)
+        for i, q in enumerate(self.moduli(lv)):
+            u[0, i] = self.vadd(u[0, i], self.vscale(self.automorphism(a.c[0, i], g, q), self.p_mod(q), q), q)
+        return ExtCiphertext(u, lv, a.scale)
+
+    def rotate_many_ext(self, a, steps, keys):
+        return [self.rotate_ext(a, r, keys) for r in steps]
+
+    def mul_const_ext(self, e: ExtCiphertext, value, const_scale):
+        """MulConst on every limb of the extended basis: C = RHA(value
+        const_scale) reduced modulo each q_i and p_k."""
+        C = rha(float(value) * float(const_scale))
+        c = np.empty_like(e.c)
+        for k in range(2):
+            for i, q in enumerate(self.ext_moduli(e.level)):
+                c[k, i] = self.vscale(e.c[k, i], C % q, q)
+        return ExtCiphertext(c, e.level, e.scale * float(const_scale))
+
+    def add_ext(self, a: ExtCiphertext, b: ExtCiphertext):
+        if a.level != b.level:
+            raise ValueError("level mismatch")
+        if abs(a.scale - b.scale) > 1e-9 * a.scale:
+            raise ValueError("scale mismatch")
+        c = np.empty_like(a.c)
+        for k in range(2):
+            for i, q in enumerate(self.ext_moduli(a.level)):
+                c[k, i] = self.vadd(a.c[k, i], b.c[k, i], q)
+        return ExtCiphertext(c, a.level, a.scale)
+
+    def add_const_ext(self, e: ExtCiphertext, value):
+        """AddConst of P times the ciphertext: P [RHA(value scale)]_q added to
+        coefficient 0 of c0 on the Q limbs."""
+        C = rha(float(value) * e.scale)
+        c = e.c.copy()
+        for i, q in enumerate(self.moduli(e.level)):
+            c[0, i, 0] = (int(c[0, i, 0]) + (C % q) * self.p_mod(q)) % q
+        return ExtCiphertext(c, e.level, e.scale)
+
+    def mod_down_rescale(self, e: ExtCiphertext):
+        """ModDown by P q_l: each component v is divided by P q_l with the
+        centred fast conversion ModDown uses, from the drop set {q_l, p_0..
+        p_{K-1}} to q_0..q_{l-1}:
+            out_i = (v_i - conv(v_D)_i) (P q_l)^-1 mod q_i,   i < l.
+        Level l - 1, scale / q_l as for rescale.  Of a lifted ciphertext it is
+        exactly the rescale."""
+        lv = e.level
         if lv == 0:
             raise ValueError("no limb left to rescale by")
-        d = a.c[2]
-        xs = [self.mod_up(d, lv, j) for j in range(self.n_digits(lv))]
-        u = self.inner_product(xs, keys.rlk, lv)
         nq = lv + 1
-        Pm = 1
-        for pk in self.p:
-            Pm *= pk
         drop = [self.q[lv]] + list(self.p)
         c = np.empty((2, lv, self.n), dtype=np.uint64)
         for comp in range(2):
-            v = u[comp].copy()
-            for i in range(nq):
-                q = self.q[i]
-                v[i] = self.vadd(u[comp][i], self.vscale(a.c[comp, i], Pm % q, q), q)
+            v = e.c[comp]
             vD = np.stack([v[lv]] + [v[nq + k] for k in range(self.K)])
             y = self.base_convert(vD, drop, self.q[:lv])
             for i in range(lv):
                 q = self.q[i]
-                inv = pow(Pm * self.q[lv] % q, q - 2, q)
+                inv = pow(self.p_mod(q) * self.q[lv] % q, q - 2, q)
                 c[comp, i] = self.vscale(self.vsub(v[i], y[i], q), inv, q)
-        return Ciphertext(c, lv - 1, a.scale / float(self.q[lv]))
+        return Ciphertext(c, lv - 1, e.scale / float(self.q[lv]))
+
+    def relin_rescale(self, a: Ciphertext, keys: Keys):
+        """Relinearisation and rescale as one ModDown by P q_l: with (u0, u1)
+        the key-switch sums of c2 over q_0..q_l, p_0..p_{K-1}, the extended
+        ciphertext u + P (c0, c1) goes through mod_down_rescale.  It equals
+        rescale(relinearize(a)) up to a rounding difference of the division
+        (not limb for limb)."""
+        assert a.ncomp == 3
+        lv = a.level
+        if lv == 0:
+            raise ValueError("no limb left to rescale by")
+        xs = [self.mod_up(a.c[2], lv, j) for j in range(self.n_digits(lv))]
+        u = self.inner_product(xs, keys.rlk, lv)
+        lifted = self.lift(Ciphertext(a.c[:2], lv, a.scale))
+        v = self.add_ext(ExtCiphertext(u, lv, a.scale), lifted)
+        return self.mod_down_rescale(v)
 
     def rotate(self, a: Ciphertext, step, keys: Keys):
         """Left rotation of the slots by `step`."""

@@ -23,7 +23,8 @@ from its single-ciphertext algorithms:
           slots (virtual ciphertexts, B' = S/H' images per ciphertext); output
           column j' sums MulConst(Rot(col(c, s j'+v-pi), u), K[c'][c][u][v]) over
           c, u, v, adds the bias and rescales; slot b H' + s i' holds output
-          row i' of image b.
+          row i' of image b.  The rotations' ModDown is deferred into the
+          rescale (one ModDown by P q_l per output, see conv2d).
   matmul (outer-product form; the rotation-free alternative to the
           revolver above, built from the paper's observation that split
           operands are multiplied pair-wise and summed by linearity): C is
@@ -247,19 +248,37 @@ def conv_out_size(h, pad, k, stride):
 
 
 def conv2d(ctx: Context, keys: Keys, cts, C_in, h, w, pad, K, bias, C_out, k, stride,
-           only_cols=None):
+           only_cols=None, lazy=None):
     """All C_out * w_out outputs (index c' * w_out + j'), or, with only_cols,
-    just the outputs of those output columns j' (same order, others None)."""
+    just the outputs of those output columns j' (same order, others None).
+
+    lazy: the rotations stay P times a ciphertext over q_0..q_l, P
+    (rotate_ext, the unrotated columns lifted), MulConst, Add and AddConst act
+    there, and one ModDown by P q_l per output finishes every key switch of
+    its sum and rescales it (mod_down_rescale).  lazy=False is the plain
+    sequence Rot, MulConst, Add, AddConst, Rescale: the same message, rounded
+    once per rotation instead of once per output.  Default: lazy when the
+    kernel rotates (k > 1) and K <= level + 1 (the extended basis at most
+    doubles the limbs), the rule the library applies."""
     K = np.asarray(K, np.float64)
     wo = conv_out_size(w, pad, k, stride)
     level = cts[0].level
     dc = float(ctx.q[level])
+    if lazy is None:
+        lazy = k > 1 and ctx.K <= level + 1
+    mul_const = ctx.mul_const_ext if lazy else ctx.mul_const
+    add = ctx.add_ext if lazy else ctx.add
+    add_const = ctx.add_const_ext if lazy else ctx.add_const
+    finish = ctx.mod_down_rescale if lazy else ctx.rescale
     rot = [[None] * w for _ in range(C_in)]
 
     def rotated(c, j):
         if rot[c][j] is None:
             ct = cts[c * w + j]
-            rot[c][j] = [ct] + ctx.rotate_many(ct, list(range(1, k)), keys)
+            if lazy:
+                rot[c][j] = [ctx.lift(ct)] + ctx.rotate_many_ext(ct, list(range(1, k)), keys)
+            else:
+                rot[c][j] = [ct] + ctx.rotate_many(ct, list(range(1, k)), keys)
         return rot[c][j]
 
     out = []
@@ -275,10 +294,10 @@ def conv2d(ctx: Context, keys: Keys, cts, C_in, h, w, pad, K, bias, C_out, k, st
                     if jj < 0 or jj >= w:
                         continue
                     for u in range(k):
-                        t = ctx.mul_const(rotated(c, jj)[u], K[co, c, u, v], dc)
-                        acc = t if acc is None else ctx.add(acc, t)
-            acc = ctx.add_const(acc, float(bias[co]))
-            out.append(ctx.rescale(acc))
+                        t = mul_const(rotated(c, jj)[u], K[co, c, u, v], dc)
+                        acc = t if acc is None else add(acc, t)
+            acc = add_const(acc, float(bias[co]))
+            out.append(finish(acc))
     return out
 
 

@@ -334,7 +334,8 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
                                                       u64 d_stride, u32 n_ct, const u64* key, u32 nmod,
                                                       u32 level, u32 next, u32 beta, u32 alpha, u32 L,
                                                       u32 log_n, u32 g_inv, u64* U, u64 u_stride,
-                                                      const ModQ* mq, LimbRuns runs)
+                                                      const ModQ* mq, LimbRuns runs, const u64* F,
+                                                      u64 f_stride, const ulonglong2* pmod)
 {
     const u32 n = 1u << log_n;
     const u32 s = blockIdx.x * kThreads + threadIdx.x;
@@ -360,6 +361,7 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
     };
     if constexpr (FP) {
         const double qd = (double)m.q, qinv = 1.0 / qd;
+        const double pf = F && e <= level ? to_bal(pmod[mod].x, m.q, qd) : 0.0;
         double fb[MAXB], fa[MAXB];
 #pragma unroll
         for (int j = 0; j < MAXB; j++) {
@@ -385,6 +387,8 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
                     }
                 }
             }
+            if (F && e <= level)   // + P sigma_g(c0): c0 read where X is, stored where U is
+                s0 += fmulmod(to_bal(F[(size_t)c * f_stride + (size_t)e * n + s], m.q, qd), pf, qd, qinv);
             u64* u = U + (size_t)c * u_stride + (size_t)e * n + t;
             u[0] = to_canon(s0, qd, qinv);
             u[(size_t)next * n] = to_canon(s1, qd, qinv);
@@ -411,6 +415,7 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
                     mac128(h1, l1, xv[j], ka[j]);
                 }
             }
+            if (F && e <= level) mac128(h0, l0, F[(size_t)c * f_stride + (size_t)e * n + s], pmod[mod].x);
             u64* u = U + (size_t)c * u_stride + (size_t)e * n + t;
             u[0] = reduce128(h0, l0, m);
             u[(size_t)next * n] = reduce128(h1, l1, m);
@@ -645,6 +650,8 @@ void launch_fp_w(const ConvArgs& a, const ConvFp& f, dim3 grid, hipStream_t s)
         hipLaunchKernelGGL((k_base_convert_fp<8, W0>), grid, dim3(kThreads), 0, s, a, f);
     else if (a.n_in == 9)   // digits of nine primes
         hipLaunchKernelGGL((k_base_convert_fp<9, W0>), grid, dim3(kThreads), 0, s, a, f);
+    else if (a.n_in == 10)  // nine special primes and q_l (ModDown with the rescale)
+        hipLaunchKernelGGL((k_base_convert_fp<10, W0>), grid, dim3(kThreads), 0, s, a, f);
     else if (a.n_in <= 12)
         hipLaunchKernelGGL((k_base_convert_fp<12, W0>), grid, dim3(kThreads), 0, s, a, f);
     else
@@ -803,7 +810,7 @@ void keyswitch_modup(vr_context* ctx, const u64* d, u32 level, u64* X, u64* coef
 
 void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u64* d, u64 d_stride,
                            u32 n_ct, const u64* key, u32 level, u32 g, u64* U, u64 u_stride,
-                           hipStream_t s)
+                           hipStream_t s, const u64* fold_c0, u64 fold_stride)
 {
     KsShape k = ks_shape(ctx, level);
     // at least ~4096 blocks: split the ciphertexts (each group re-reads the key)
@@ -849,7 +856,7 @@ void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u6
 #define VR_KS_INNER(B, F)                                                                             \
     hipLaunchKernelGGL((k_ks_inner<B, F>), g2, dim3(kThreads), 0, s, X, x_stride, d, d_stride, n_ct, key, \
                        ctx->nmod(), level, k.next, k.beta, ctx->alpha, ctx->L, ctx->log_n, g_inv, U,   \
-                       u_stride, ctx->d_modq, lr)
+                       u_stride, ctx->d_modq, lr, fold_c0, fold_stride, ctx->d_pmod_tab)
             if (k.beta <= 4) {
                 if (fp)
                     VR_KS_INNER(4, true);
@@ -946,7 +953,8 @@ void keyswitch_moddown_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u3
 // + P c_j on the Q limbs (U_j on the special ones, where P c_j vanishes), and
 //   out_j,i = (v_j,i - conv(v_j over {q_l, P})_i) (P q_l)^-1
 //           = (U_j,i - y_j,i) (P q_l)^-1 + c_j,i q_l^-1,   i < l,
-// so only the q_l limb takes the fold of P c_j before the conversion.
+// so only the q_l limb takes the fold of P c_j before the conversion.  With
+// c0 = c1 = null, U is already the whole extended ciphertext v.
 void keyswitch_moddown_rescale_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u32 level,
                                      u64* out0, u64* out1, u64 out_stride, const u64* c0,
                                      const u64* c1, u64 c_stride, u64* scratch, hipStream_t s)
@@ -955,10 +963,10 @@ void keyswitch_moddown_rescale_batch(vr_context* ctx, u64* U, u64 u_stride, u32 
     KsShape k = ks_shape(ctx, level);
     const u32 n = ctx->n, K = ctx->K, nd = K + 1, no = level;
     if (u_stride != (u64)2 * k.next * n) throw Error(VR_EINVAL, "moddown: U blocks must be dense");
-    if (!c0 || !c1) throw Error(VR_EINVAL, "moddown-rescale: needs the ciphertext's c0 and c1");
+    if (!c0 != !c1) throw Error(VR_EINVAL, "moddown-rescale: c0 and c1 come together");
     u64* dcoef = scratch;                                   // [n_ct*2][K+1][N]
     u64* Y = scratch + (size_t)n_ct * 2 * nd * n;           // [n_ct*2][level][N]
-    {
+    if (c0) {
         const u64 ql = ctx->mod[level];
         u64 pm = 1 % ql;
         for (u32 j = 0; j < K; j++) pm = (u64)((u128)pm * (ctx->mod[ctx->L + 1 + j] % ql) % ql);
@@ -999,7 +1007,7 @@ void keyswitch_moddown_rescale_batch(vr_context* ctx, u64* U, u64 u_stride, u32 
     ep.add1 = c1;
     ep.add_ct = c_stride;
     ep.cmul = ctx->d_prinv_tab + (size_t)level * ctx->nmod();
-    ep.bmul = ctx->d_rinv_tab + (size_t)level * ctx->nmod();
+    ep.bmul = c0 ? ctx->d_rinv_tab + (size_t)level * ctx->nmod() : nullptr;
     if (ntt_forward(ctx, ly, s)) return;
     dim3 grid((n + kThreads - 1) / kThreads, n_ct * no);
     ProfScope prof(ctx, kProfModDown, s, (u64)n_ct * 2 * no);

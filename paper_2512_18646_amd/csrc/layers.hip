@@ -49,6 +49,20 @@ Slab new_slab(vr_context* ctx, u32 n, u32 ncomp, u32 level, double scale, hipStr
     return sl;
 }
 
+Slab new_ext_slab(vr_context* ctx, u32 n, u32 level, double scale, hipStream_t s)
+{
+    Slab sl;
+    sl.n = n;
+    sl.ncomp = 2;
+    sl.level = level;
+    sl.ext = 1;
+    sl.scale = scale;
+    sl.stride = (u64)2 * (level + 1 + ctx->K) * ctx->n;
+    sl.buf = dev_alloc(ctx, std::max<size_t>(1, (size_t)n * sl.stride) * sizeof(u64), s);
+    sl.base = as_u64(sl.buf);
+    return sl;
+}
+
 constexpr u32 kGatherMax = 64;
 struct GatherTable {
     const u64* src[kGatherMax];
@@ -129,11 +143,14 @@ constexpr u32 kTermColBits = 24;
 
 // For each of n_sets independent image sets s and each output column j':
 // out[s][f][j'] = sum_{terms of j'} w_f * in (+ bias on component 0) for every
-// filter f, 2 components.  The filters of one column read the same inputs, so
-// a block keeps all filters' sums in registers and reads each input word
-// once.  Term input (u, j): for u = 0 ciphertext s * n_x + j of slab x, for
-// u >= 1 ciphertext (u - 1) * n_x * n_sets + s * n_x + j of slab r (the
-// rotations by u of every column of every set), all with stride `stride`.
+// filter f, 2 components of nl limbs.  The filters of one column read the
+// same inputs, so a block keeps all filters' sums in registers and reads each
+// input word once.  Term input (u, j): for u = 0 ciphertext s * n_x + j of
+// slab x (stride `stride`, nqx limbs per component: limbs l >= nqx of the
+// output take nothing from it), for u >= 1 ciphertext (u - 1) * ustride / rstride
+// + s * n_x + j of slab r (the rotations by u of every column of every set,
+// stride `rstride`, nl limbs per component).  Limb l has modulus l below nqx
+// and l + modoff from there (the special primes of an extended basis).
 // Term weight offset for filter f and limb l: w_idx + f * w_fstride * nl + l.
 //
 // Launch order: the logical block id runs over output columns fastest, then
@@ -145,12 +162,12 @@ constexpr int kMaxFilters = 8;
 
 __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, const u64* x,
                                                       const u64* r, u32 n_x, u32 n_sets, u64 stride,
-                                                      u64 ustride,
+                                                      u64 rstride, u64 ustride,
                                                       const Term* terms, const u32* term_off,
                                                       const u64* w, const u64* ws, const double* wf,
                                                       u32 w_fstride,
-                                                      const u64* bias, u32 nl, u32 log_n,
-                                                      const ModQ* mq, u32 wo, u32 n_filters,
+                                                      const u64* bias, u32 nl, u32 nqx, u32 modoff,
+                                                      u32 log_n, const ModQ* mq, u32 wo, u32 n_filters,
                                                       u32 total, u32 per_xcd)
 {
     const u32 logical = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
@@ -165,12 +182,14 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
     const u32 t = chunk * kThreads + threadIdx.x;
     if (t >= n) return;
     const u32 l = row % nl;
-    const u64 q = mq[l].q, q2 = 2 * q;
+    const u64 q = mq[l < nqx ? l : l + modoff].q, q2 = 2 * q;
     const u32 a = term_off[jo], b = term_off[jo + 1];
     const u32 n_out = n_filters * wo;
     const size_t tile = (size_t)row * n + t;
+    const bool x_has = l < nqx;
+    const size_t xtile = ((size_t)(row / nl) * nqx + (x_has ? l : 0)) * n + t;
     const u64* xb = x + (size_t)set * n_x * stride;
-    const u64* rb = r + (size_t)set * n_x * stride;
+    const u64* rb = r + (size_t)set * n_x * rstride;
     const size_t fst = (size_t)w_fstride * nl;
     constexpr u32 kColMask = (1u << kTermColBits) - 1;
     if (q < (1ull << 51)) {
@@ -191,8 +210,10 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
                     if (k0 + i < b) {
                         const Term tm = terms[k0 + i];
                         const u32 u = tm.in_idx >> kTermColBits, j = tm.in_idx & kColMask;
-                        const u64* src = u == 0 ? xb : rb + (u - 1) * ustride;
-                        xv[i] = src[(size_t)j * stride + tile];
+                        if (u == 0)
+                            xv[i] = x_has ? xb[(size_t)j * stride + xtile] : 0;
+                        else
+                            xv[i] = rb[(u - 1) * ustride + (size_t)j * rstride + tile];
                         wrow[i] = tm.w_idx;
                     }
                 }
@@ -241,8 +262,10 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
                 if (k0 + i < b) {
                     const Term tm = terms[k0 + i];
                     const u32 u = tm.in_idx >> kTermColBits, j = tm.in_idx & kColMask;
-                    const u64* src = u == 0 ? xb : rb + (u - 1) * ustride;
-                    xv[i] = src[(size_t)j * stride + tile];
+                    if (u == 0)
+                        xv[i] = x_has ? xb[(size_t)j * stride + xtile] : 0;
+                    else
+                        xv[i] = rb[(u - 1) * ustride + (size_t)j * rstride + tile];
                     wrow[i] = tm.w_idx;
                 }
             }
@@ -468,6 +491,73 @@ void rotate_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in,
                  const std::vector<int32_t>& steps, std::vector<Slab>& out, hipStream_t s)
 {
     rotate_slab_keyed(ctx, {KeyRange{0, in.n, ek}}, in, steps, out, s);
+}
+
+// The rotations of rotate_slab_keyed without their ModDown: out[si] is an
+// extended slab holding, per ciphertext, P times its rotation by steps[si]
+// (the key-switch sums of sigma_g(ModUp(c1)) with P sigma_g(c0) folded into
+// component 0's Q limbs by the inner-product kernel).  Steps must not be 0
+// mod the slot count.
+void rotate_slab_ext(vr_context* ctx, const std::vector<KeyRange>& keys, const Slab& in,
+                     const std::vector<int32_t>& steps, std::vector<Slab>& out, hipStream_t s)
+{
+    const u32 level = in.level, n_ct = in.n;
+    const size_t n = ctx->n;
+    if (in.ext || in.ncomp != 2) throw Error(VR_EINVAL, "rotation needs 2-component ciphertexts");
+    KsShape k = ks_shape(ctx, level);
+    check_ranges(keys, n_ct);
+    std::vector<u32> gs;
+    for (int32_t st : steps) {
+        u32 g = galois_element(ctx, st);
+        if (g == 1) throw Error(VR_EINVAL, "extended rotation by 0");
+        for (const KeyRange& kr : keys) (void)rot_key(kr.ek, g);
+        gs.push_back(g);
+    }
+    const u32 cs = switch_chunk(ctx, level, n_ct);
+    const u64 xs = (u64)k.beta * k.next * n;
+    BufPtr xbuf = dev_alloc(ctx, ((size_t)cs * xs + (size_t)cs * k.nq * n) * sizeof(u64), s);
+    u64* X = as_u64(xbuf);
+    u64* coef = X + (size_t)cs * xs;
+    out.clear();
+    Slab all = new_ext_slab(ctx, n_ct * (u32)steps.size(), level, in.scale, s);
+    for (size_t si = 0; si < steps.size(); si++) {
+        Slab r = all;
+        r.n = n_ct;
+        r.base = all.base + si * n_ct * all.stride;
+        out.push_back(r);
+    }
+    for (u32 c0 = 0; c0 < n_ct; c0 += cs) {
+        const u32 nc = std::min(cs, n_ct - c0);
+        keyswitch_modup_batch(ctx, in.ct(c0) + (size_t)k.nq * n, in.stride, nc, level, X, coef, s);
+        for (size_t si = 0; si < steps.size(); si++)
+            for (const KeyRange& kr : keys) {
+                const u32 lo = std::max(kr.begin, c0), hi = std::min(kr.end, c0 + nc);
+                if (lo >= hi) continue;
+                keyswitch_inner_batch(ctx, X + (size_t)(lo - c0) * xs, xs, in.ct(lo) + (size_t)k.nq * n, in.stride,
+                                      hi - lo, rot_key(kr.ek, gs[si]).data, level, gs[si], out[si].ct(lo),
+                                      all.stride, s, in.ct(lo), in.stride);
+            }
+    }
+}
+
+// ModDown by P q_l of every ciphertext of an extended slab: level l - 1,
+// scale / q_l (chunked so the conversion scratch stays bounded)
+Slab mod_down_rescale_slab(vr_context* ctx, const Slab& in, hipStream_t s)
+{
+    if (!in.ext) throw Error(VR_EINVAL, "ModDown by P q_l needs an extended slab");
+    const u32 level = in.level;
+    if (level == 0) throw Error(VR_ELEVEL, "no limb left to rescale by");
+    const size_t n = ctx->n;
+    Slab out = new_slab(ctx, in.n, 2, level - 1, in.scale / (double)ctx->mod[level], s);
+    const u32 cs = switch_chunk(ctx, level, in.n);
+    BufPtr md = dev_alloc(ctx, keyswitch_moddown_scratch(ctx, level, cs) * sizeof(u64), s);
+    for (u32 c0 = 0; c0 < in.n; c0 += cs) {
+        const u32 nc = std::min(cs, in.n - c0);
+        u64* o = out.ct(c0);
+        keyswitch_moddown_rescale_batch(ctx, in.ct(c0), in.stride, nc, level, o, o + (size_t)level * n, out.stride,
+                                        nullptr, nullptr, 0, as_u64(md), s);
+    }
+    return out;
 }
 
 // relinearise a slab of 3-component ciphertexts into 2-component ones, each
@@ -794,14 +884,28 @@ struct ConvPlan {
     const double* wf = nullptr;   // the weights as balanced doubles (moduli below 2^51)
 };
 
-const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const double* K,
-                          const double* bias, u32 C_out, u32 k, u32 stride, u32 level, double out_scale)
+// P mod q (host)
+u64 p_mod_h(vr_context* ctx, u64 q)
 {
-    const u32 wo = (w + 2 * pad - k) / stride + 1, nl = level + 1;
+    u64 v = 1 % q;
+    for (u32 k = 0; k < ctx->K; k++) v = (u64)((u128)v * (ctx->mod[ctx->L + 1 + k] % q) % q);
+    return v;
+}
+
+// The conv's weight and bias tables over nl limbs: q_0..q_level, and with
+// `ext` also p_0..p_{K-1} for the lazy-ModDown form, where the unrotated
+// terms (u = 0) and the bias act on P times the input (P w on the Q limbs,
+// nothing on the special ones) and the rotated terms on the rotations'
+// key-switch sums (w on every limb).
+const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const double* K,
+                          const double* bias, u32 C_out, u32 k, u32 stride, u32 level, double out_scale,
+                          bool ext)
+{
+    const u32 wo = (w + 2 * pad - k) / stride + 1, nq = level + 1, nl = ext ? nq + ctx->K : nq;
     const size_t nw = (size_t)C_out * C_in * k * k;
     if ((size_t)C_in * w >= (1u << kTermColBits) || k >= 256 || nw * nl >= (1ull << 32))
         throw Error(VR_EINVAL, "conv layer too large: C_in * w must stay below 2^24, k below 256");
-    std::string key = "conv:";
+    std::string key = ext ? "convx:" : "conv:";
     u32 shape[7] = {C_in, w, pad, C_out, k, stride, level};
     key.append((const char*)shape, sizeof shape);
     key.append((const char*)&out_scale, sizeof out_scale);
@@ -814,16 +918,22 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
     const double dq = (double)ctx->mod[level];
     std::vector<u64> wv(nw * nl), wsv(nw * nl), bv((size_t)C_out * wo * nl);
     std::vector<double> wfv(nw * nl);
+    auto mod_of = [&](u32 l) { return l < nq ? l : ctx->L + 1 + (l - nq); };
     for (size_t r = 0; r < nw; r++)
         for (u32 l = 0; l < nl; l++) {
-            const u64 q = ctx->mod[l], v = double_to_mod(K[r] * dq, q);
+            const u64 q = ctx->mod[mod_of(l)];
+            u64 v = double_to_mod(K[r] * dq, q);
+            if (ext && (r / k) % k == 0)   // unrotated term: P w on Q limbs, none on P limbs
+                v = l < nq ? (u64)((u128)v * p_mod_h(ctx, q) % q) : 0;
             wv[r * nl + l] = v;
             wsv[r * nl + l] = shoup_companion(v, q);
             wfv[r * nl + l] = v > q / 2 ? -(double)(q - v) : (double)v;
         }
     for (u32 co = 0; co < C_out; co++)
         for (u32 l = 0; l < nl; l++) {
-            u64 b = double_to_mod(bias[co] * out_scale, ctx->mod[l]);
+            const u64 q = ctx->mod[mod_of(l)];
+            u64 b = l < nq ? double_to_mod(bias[co] * out_scale, q) : 0;
+            if (ext && l < nq) b = (u64)((u128)b * p_mod_h(ctx, q) % q);
             for (u32 jo = 0; jo < wo; jo++) bv[((size_t)co * wo + jo) * nl + l] = b;
         }
     // one term list per output column, weight rows of filter 0 (filter c'
@@ -974,40 +1084,80 @@ vr_ciphertext** encrypt_slots_batch(vr_context* ctx, const vr_eval_keys* ek,
     return out;
 }
 
+// The conv's rotations and linear combination over `keys` (ciphertexts of x
+// in the ranges of each session), one network per call of conv_lincomb_into.
+// Lazy form when the kernel rotates (k > 1) and the special primes are no
+// more than the Q limbs (K <= level + 1, so the extended basis at most doubles
+// the limbs): the rotations by 1..k-1 of every column stay in the extended
+// basis (no ModDown), the sums are taken there, and one ModDown by P q_l per
+// output both finishes the key switches and rescales.  Otherwise the plain
+// form: rotations with their ModDown, sums in Q, a rescale.
+struct ConvRot {
+    std::vector<Slab> rot;
+    bool ext = false;
+};
+
+bool conv_lazy(vr_context* ctx, u32 k, u32 level) { return k > 1 && ctx->K <= level + 1; }
+
+ConvRot conv_rotations(vr_context* ctx, const std::vector<KeyRange>& keys, const Slab& x, u32 k, hipStream_t s)
+{
+    ConvRot cr;
+    std::vector<int32_t> steps;
+    for (u32 u = 1; u < k; u++) steps.push_back((int32_t)u);
+    if (steps.empty()) return cr;
+    cr.ext = conv_lazy(ctx, k, x.level);
+    if (cr.ext)
+        rotate_slab_ext(ctx, keys, x, steps, cr.rot, s);
+    else
+        rotate_slab_keyed(ctx, keys, x, steps, cr.rot, s);
+    return cr;
+}
+
+// out (n_sets * C_out * w_out ciphertexts, extended when cr.ext) = the
+// linear combination of the inputs x_in (n_sets sets of C_in * w columns)
+// and their rotations cr.rot[u - 1] starting at ciphertext r_at
+void conv_lincomb_into(vr_context* ctx, const Slab& out, u32 out_at, const Slab& x, u32 x_at, const ConvRot& cr,
+                       u32 r_at, u32 n_sets, u32 C_in, u32 w, u32 pad, const double* K, const double* bias,
+                       u32 C_out, u32 k, u32 stride, hipStream_t s)
+{
+    const u32 level = x.level, nq = level + 1;
+    const u32 wo = (w + 2 * pad - k) / stride + 1, n_out = C_out * wo;
+    const double out_scale = x.scale * (double)ctx->mod[level];
+    const ConvPlan& plan = conv_plan(ctx, C_in, w, pad, K, bias, C_out, k, stride, level, out_scale, cr.ext);
+    const u32 nl = cr.ext ? nq + ctx->K : nq;
+    const Slab& r = cr.rot.empty() ? x : cr.rot[0];
+    const u32 chunks = (ctx->n + kThreads - 1) / kThreads;
+    const u32 total = chunks * 2 * nl * n_sets * wo;
+    const u32 per_xcd = (total + 7) / 8;
+    ProfScope prof(ctx, kProfLincomb, s, (u64)n_sets * n_out * 2 * nl);
+    hipLaunchKernelGGL(k_lincomb, dim3(8 * per_xcd), dim3(kThreads), 0, s, out.ct(out_at), out.stride, x.ct(x_at),
+                       cr.rot.empty() ? x.ct(x_at) : r.ct(r_at), C_in * w, n_sets, x.stride, r.stride,
+                       (u64)r.n * r.stride, plan.terms, plan.off, plan.w, plan.ws, plan.wf, C_in * k * k,
+                       plan.bias, nl, nq, ctx->L + 1 - nq, ctx->log_n, ctx->d_modq, wo, C_out, total, per_xcd);
+    VR_CHECK_LAUNCH();
+}
+
 // Conv layer over n_sets image sets laid out in one slab (set s occupies
 // ciphertexts s * C_in * w .. (s + 1) * C_in * w - 1): one hoisted ModUp per
 // column, one shared-key inner-product launch per rotation step for every
-// column of every set, one fused MulConst/AddConst launch, one rescale.
+// column of every set (rotations kept in the extended basis), one fused
+// MulConst/AddConst launch, one ModDown by P q_l per output.
 Slab conv_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& x, u32 n_sets, u32 C_in, u32 w,
                u32 pad, const double* K, const double* bias, u32 C_out, u32 k, u32 stride,
                hipStream_t s)
 {
-    if (x.ncomp != 2) throw Error(VR_EINVAL, "conv inputs must be 2-component");
+    if (x.ncomp != 2 || x.ext) throw Error(VR_EINVAL, "conv inputs must be 2-component");
     if (x.level < 1) throw Error(VR_ELEVEL, "conv needs a level to rescale");
     const u32 wo = (w + 2 * pad - k) / stride + 1;
-    const u32 level = x.level, nl = level + 1;
-    // rotations by 1..k-1 of every column (step 0 is the input itself)
-    std::vector<int32_t> steps;
-    for (u32 u = 1; u < k; u++) steps.push_back((int32_t)u);
-    std::vector<Slab> rot;
-    if (!steps.empty()) rotate_slab(ctx, ek, x, steps, rot, s);
-    const double dq = (double)ctx->mod[level];
-    const double out_scale = x.scale * dq;
-    const ConvPlan& plan = conv_plan(ctx, C_in, w, pad, K, bias, C_out, k, stride, level, out_scale);
+    const u32 level = x.level;
+    ConvRot cr = conv_rotations(ctx, {KeyRange{0, x.n, ek}}, x, k, s);
+    const double out_scale = x.scale * (double)ctx->mod[level];
     const u32 n_out = C_out * wo;
-    Slab acc = new_slab(ctx, n_sets * n_out, 2, level, out_scale, s);
-    {
-        const u32 chunks = (ctx->n + kThreads - 1) / kThreads;
-        const u32 total = chunks * 2 * nl * n_sets * wo;
-        const u32 per_xcd = (total + 7) / 8;
-        ProfScope prof(ctx, kProfLincomb, s, (u64)n_sets * n_out * 2 * nl);
-        hipLaunchKernelGGL(k_lincomb, dim3(8 * per_xcd), dim3(kThreads), 0, s, acc.base, acc.stride,
-                           x.base, rot.empty() ? x.base : rot[0].base, C_in * w, n_sets, x.stride,
-                           (u64)C_in * w * n_sets * x.stride, plan.terms, plan.off, plan.w, plan.ws, plan.wf, C_in * k * k, plan.bias, nl,
-                           ctx->log_n, ctx->d_modq, wo, C_out, total, per_xcd);
-        VR_CHECK_LAUNCH();
-    }
-    return rescale_slab(ctx, acc, s);
+    Slab acc = cr.ext ? new_ext_slab(ctx, n_sets * n_out, level, out_scale, s)
+                      : new_slab(ctx, n_sets * n_out, 2, level, out_scale, s);
+    conv_lincomb_into(ctx, acc, 0, x, 0, cr, 0, n_sets, C_in, w, pad, K, bias, C_out, k, stride, s);
+    cr.rot.clear();
+    return cr.ext ? mod_down_rescale_slab(ctx, acc, s) : rescale_slab(ctx, acc, s);
 }
 
 // Several column-split products at one level and scale in one schedule
@@ -1206,38 +1356,25 @@ Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab&
         kin.push_back(KeyRange{at, at + g.n_sets * g.d->n_in(), g.ek});
         at = kin.back().end;
     }
-    std::vector<int32_t> steps;
-    for (u32 u = 1; u < d0.k; u++) steps.push_back((int32_t)u);
-    std::vector<Slab> rot;
-    if (!steps.empty()) rotate_slab_keyed(ctx, kin, x, steps, rot, s);
+    ConvRot cr = conv_rotations(ctx, kin, x, d0.k, s);
     const double out_scale = x.scale * (double)ctx->mod[level];
     u32 n_conv = 0;
     for (const NetSeg& g : segs) n_conv += g.n_sets * g.d->C_out * g.d->w_out();
-    Slab acc = new_slab(ctx, n_conv, 2, level, out_scale, s);
+    Slab acc = cr.ext ? new_ext_slab(ctx, n_conv, level, out_scale, s) : new_slab(ctx, n_conv, 2, level, out_scale, s);
     // the linear combination per network, on its own inputs and rotations
     std::vector<KeyRange> kout;
     u32 in_at = 0, out_at = 0;
     for (const NetSeg& g : segs) {
         const CnnDesc& d = *g.d;
-        const u32 wo = d.w_out(), n_out = d.C_out * wo;
-        const ConvPlan& plan = conv_plan(ctx, d.C_in, d.w, d.pad, d.K.data(), d.bias.data(), d.C_out, d.k,
-                                         d.stride, level, out_scale);
-        const u32 chunks = (ctx->n + kThreads - 1) / kThreads;
-        const u32 total = chunks * 2 * nl * g.n_sets * wo;
-        const u32 per_xcd = (total + 7) / 8;
-        ProfScope prof(ctx, kProfLincomb, s, (u64)g.n_sets * n_out * 2 * nl);
-        hipLaunchKernelGGL(k_lincomb, dim3(8 * per_xcd), dim3(kThreads), 0, s, acc.ct(out_at), acc.stride,
-                           x.ct(in_at), rot.empty() ? x.ct(in_at) : rot[0].ct(in_at), d.n_in(), g.n_sets,
-                           x.stride, (u64)x.n * x.stride, plan.terms, plan.off, plan.w, plan.ws, plan.wf,
-                           d.C_in * d.k * d.k, plan.bias, nl, ctx->log_n, ctx->d_modq, wo, d.C_out, total,
-                           per_xcd);
-        VR_CHECK_LAUNCH();
+        const u32 n_out = d.C_out * d.w_out();
+        conv_lincomb_into(ctx, acc, out_at, x, in_at, cr, in_at, g.n_sets, d.C_in, d.w, d.pad, d.K.data(),
+                          d.bias.data(), d.C_out, d.k, d.stride, s);
         kout.push_back(KeyRange{out_at, out_at + g.n_sets * n_out, g.ek});
         in_at += g.n_sets * d.n_in();
         out_at += g.n_sets * n_out;
     }
-    rot.clear();
-    Slab y = rescale_slab(ctx, acc, s);
+    cr.rot.clear();
+    Slab y = cr.ext ? mod_down_rescale_slab(ctx, acc, s) : rescale_slab(ctx, acc, s);
     acc = Slab();
     if (d0.square) {
         // tensor of everything, relinearisation per session, one rescale

@@ -206,7 +206,13 @@ void build_context(vr_context* ctx, const vr_params* p, int device)
     ctx->d_modq = upload(ctx->modq);
     {
         std::vector<ulonglong2> pinv(nmod), rinv((size_t)(ctx->L + 1) * nmod),
-            prinv((size_t)(ctx->L + 1) * nmod);
+            prinv((size_t)(ctx->L + 1) * nmod), pmod(nmod);
+        for (u32 m = 0; m < nmod; m++) {
+            const u64 q = ctx->mod[m];
+            u64 v = 1 % q;
+            for (u32 k = 0; k < ctx->K; k++) v = (u64)((u128)v * (ctx->mod[ctx->L + 1 + k] % q) % q);
+            pmod[m] = make_ulonglong2(v, shoup_companion(v, q));
+        }
         for (u32 m = 0; m < nmod; m++) pinv[m] = make_ulonglong2(ctx->modq[m].pinv, ctx->modq[m].pinv_s);
         for (u32 l = 0; l <= ctx->L; l++)
             for (u32 i = 0; i < l; i++) {
@@ -220,6 +226,7 @@ void build_context(vr_context* ctx, const vr_params* p, int device)
         ctx->d_pinv_tab = upload(pinv);
         ctx->d_rinv_tab = upload(rinv);
         ctx->d_prinv_tab = upload(prinv);
+        ctx->d_pmod_tab = upload(pmod);
     }
     ctx->d_tw = upload(tw);
     ctx->d_itw = upload(itw);
@@ -254,6 +261,7 @@ void destroy_context_tables(vr_context* ctx)
     (void)hipFree(ctx->d_fft_tw);
     (void)hipFree(ctx->d_pinv_tab);
     (void)hipFree(ctx->d_prinv_tab);
+    (void)hipFree(ctx->d_pmod_tab);
     (void)hipFree(ctx->d_rinv_tab);
     (void)hipFree(ctx->d_gexp);
     for (auto& kv : ctx->modup_tables)

@@ -320,6 +320,7 @@ struct vr_context {
     ulonglong2* d_pinv_tab = nullptr;  // [nmod]
     ulonglong2* d_rinv_tab = nullptr;  // [L + 1][nmod]: q_l^-1 mod q_i, i < l
     ulonglong2* d_prinv_tab = nullptr; // [L + 1][nmod]: (P q_l)^-1 mod q_i, i < l
+    ulonglong2* d_pmod_tab = nullptr;  // [nmod]: P mod q_m (zero on the special primes)
     int* d_gexp = nullptr;            // [S] 5^j mod 2N
     vr::u64 cdt[20];
     std::map<std::pair<int, int>, vr::ConvTable> modup_tables;   // (level, digit)

@@ -68,10 +68,12 @@ void keyswitch_modup_batch(vr_context* ctx, const u64* d, u64 d_stride, u32 n_ct
 void keyswitch_inner(vr_context* ctx, const u64* X, const u64* d, const u64* key, u32 level, u32 g,
                      u64* U, hipStream_t s);
 // Batched inner product: n_ct digit sets X + c*x_stride (ModUp inputs
-// d + c*d_stride) share one key read.
+// d + c*d_stride) share one key read.  With fold_c0 (ciphertext c's c0 at
+// fold_c0 + c*fold_stride, level limbs) the Q limbs of U_0 also take
+// P sigma_g(c0): U is then P times the rotation before its ModDown.
 void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u64* d, u64 d_stride,
                            u32 n_ct, const u64* key, u32 level, u32 g, u64* U, u64 u_stride,
-                           hipStream_t s);
+                           hipStream_t s, const u64* fold_c0 = nullptr, u64 fold_stride = 0);
 // ModDown of U ([2][next][N]) to out0/out1 (nq limbs each, may be strided),
 // adding add0 (optionally through sigma_g) and add1 when non-null.
 void keyswitch_moddown(vr_context* ctx, u64* U, u32 level, u64* out0, u64* out1, const u64* add0,
@@ -83,8 +85,8 @@ void keyswitch_moddown_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u3
                              const u64* add1, u64 add_stride, u64* scratch, hipStream_t s);
 // Relinearisation fused with the rescale: ModDown of U by P q_l (l = level)
 // with c0/c1 (the ciphertext's first two components, level l, c_stride apart
-// per ciphertext) folded in; out0/out1 get l limbs (level l - 1).  Scratch as
-// keyswitch_moddown_scratch(level, n_ct).
+// per ciphertext) folded in (both null: U is taken as it is); out0/out1 get
+// l limbs (level l - 1).  Scratch as keyswitch_moddown_scratch(level, n_ct).
 void keyswitch_moddown_rescale_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u32 level,
                                      u64* out0, u64* out1, u64 out_stride, const u64* c0,
                                      const u64* c1, u64 c_stride, u64* scratch, hipStream_t s);

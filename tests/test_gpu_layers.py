@@ -202,8 +202,10 @@ def test_conv_square_fc_bit_exact_small(small_cnn):
     gY = g.conv2d(gk, gcts, Ci, h, w, pad, K, bias, s)
     for i, (x, y) in enumerate(zip(gY, Y)):
         assert_same(x, y, "conv %d" % i)
+    # the per-operation path issues the plain sequence (a ModDown per rotation)
     from paper_2512_18646_amd import perop
-    for i, (x, y) in enumerate(zip(perop.conv2d(g, gk, gcts, Ci, h, w, pad, K, bias, s), Y)):
+    Yp = Ly.conv2d(o, ok, cts, Ci, h, w, pad, K, bias, Co, k, s, lazy=False)
+    for i, (x, y) in enumerate(zip(perop.conv2d(g, gk, gcts, Ci, h, w, pad, K, bias, s), Yp)):
         assert_same(x, y, "per-op conv %d" % i)
     Y2 = [Ly.square(o, ok, y) for y in Y]
     gY2 = g.square(gk, gY)

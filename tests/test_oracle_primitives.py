@@ -330,6 +330,75 @@ def test_relin_rescale_is_one_rounded_division(p_bits, dnum):
         ctx.relin_rescale(Ciphertext(c[:, :1], 0, 1.0), keys)
 
 
+def _crt_diff(x, y, moduli):
+    M = 1
+    for q in moduli:
+        M *= q
+    X, _ = _crt(x, moduli)
+    Y, _ = _crt(y, moduli)
+    d = (X - Y) % M
+    return d - M if d > M // 2 else d
+
+
+def test_lazy_moddown_of_lifted_ops_is_the_plain_rescale():
+    """On P times a ciphertext (lift), MulConst, Add and AddConst in the
+    extended basis followed by the ModDown by P q_l give exactly the rescale
+    of the same operations on the ciphertext: the conversion of
+    (P c_l, 0, ..., 0) is P [c_l] with no overflow term."""
+    ctx = Context(Params(4, [60, 50, 50, 50], [51, 51, 51], 1, 30.0, allow_insecure=True))
+    keys = ctx.keygen(14)
+    rng = np.random.default_rng(15)
+    lv = 3
+    mk = lambda: Ciphertext(np.stack([np.stack([rng.integers(0, q, ctx.n, dtype=np.uint64)
+                                                for q in ctx.moduli(lv)]) for _ in range(2)]), lv, 2.0 ** 30)
+    a, b = mk(), mk()
+    dq = float(ctx.q[lv])
+    plain = ctx.add_const(ctx.add(ctx.mul_const(a, 0.37, dq), ctx.mul_const(b, -1.25, dq)), 0.5)
+    ext = ctx.add_const_ext(ctx.add_ext(ctx.mul_const_ext(ctx.lift(a), 0.37, dq),
+                                        ctx.mul_const_ext(ctx.lift(b), -1.25, dq)), 0.5)
+    got, want = ctx.mod_down_rescale(ext), ctx.rescale(plain)
+    assert got.level == want.level and got.scale == want.scale
+    assert np.array_equal(got.c, want.c)
+    # the special limbs of a lift are zero, its Q limbs P c
+    la = ctx.lift(a)
+    assert not la.c[:, lv + 1:].any()
+    q = ctx.q[1]
+    assert int(la.c[0, 1, 3]) == int(a.c[0, 1, 3]) * ctx.p[0] * ctx.p[1] * ctx.p[2] % q
+
+
+def test_lazy_rotation_sum_within_the_roundings():
+    """sum_t w_t Rot(a, r_t) rescaled once through the extended basis stays
+    within the roundings of the plain form: each plain rotation's ModDown
+    error (<= K/2 + 1) is scaled by |C_t| / q_l, the lazy form rounds once."""
+    ctx = Context(Params(4, [60, 50, 50, 50], [51, 51, 51], 1, 30.0, allow_insecure=True))
+    steps = [1, 3]
+    keys = ctx.keygen(16, rot_steps=steps)
+    rng = np.random.default_rng(17)
+    lv = 3
+    a = Ciphertext(np.stack([np.stack([rng.integers(0, q, ctx.n, dtype=np.uint64) for q in ctx.moduli(lv)])
+                             for _ in range(2)]), lv, 2.0 ** 30)
+    dq = float(ctx.q[lv])
+    ws = [0.75, -0.5, 0.25]
+    plain = ctx.mul_const(a, ws[0], dq)
+    ext = ctx.mul_const_ext(ctx.lift(a), ws[0], dq)
+    for w, r in zip(ws[1:], steps):
+        plain = ctx.add(plain, ctx.mul_const(ctx.rotate(a, r, keys), w, dq))
+        ext = ctx.add_ext(ext, ctx.mul_const_ext(ctx.rotate_ext(a, r, keys), w, dq))
+    got, want = ctx.mod_down_rescale(ext), ctx.rescale(plain)
+    bound = sum(abs(w) for w in ws[1:]) * (ctx.K / 2 + 1) + ctx.K / 2 + 2
+    for comp in range(2):
+        for t in range(ctx.n):
+            d = _crt_diff(got.c[comp, :, t], want.c[comp, :, t], ctx.q[:lv])
+            assert abs(d) <= bound
+    # one rotation alone: ModDown by P q_l of (u0 + P sigma(c0), u1)
+    one = ctx.mod_down_rescale(ctx.rotate_ext(a, 3, keys))
+    ref = ctx.rescale(ctx.rotate(a, 3, keys))
+    for t in range(ctx.n):
+        assert abs(_crt_diff(one.c[0, :, t], ref.c[0, :, t], ctx.q[:lv])) <= ctx.K / 2 + 2
+    # step 0 is the lift
+    assert np.array_equal(ctx.rotate_ext(a, 0, keys).c, ctx.lift(a).c)
+
+
 # -------------------------------------------------------------- automorphism
 
 def test_automorphism_is_ring_homomorphism():

@@ -119,6 +119,20 @@ def test_relin_rescale_decrypts_the_product():
     assert ef < EPS and ef < 2 * er + 1e-12
 
 
+def test_lazy_rotation_decrypts():
+    """A rotation kept in the extended basis and rescaled by the ModDown by
+    P q_l decrypts to the rotated message at the rescaled scale."""
+    ctx = small_ctx(log_n=8)
+    keys = ctx.keygen(23, rot_steps=[5])
+    z = np.random.default_rng(24).uniform(-1, 1, ctx.slots)
+    ct = ctx.encrypt(keys, ctx.encode(z, 3, ctx.scale), 1, 0)
+    dq = float(ctx.q[3])
+    e = ctx.add_const_ext(ctx.mul_const_ext(ctx.rotate_ext(ct, 5, keys), 0.5, dq), 0.25)
+    y = ctx.mod_down_rescale(e)
+    assert y.level == 2 and y.scale == ctx.scale
+    assert np.max(np.abs(ctx.decode(ctx.decrypt(keys, y)) - (0.5 * np.roll(z, -5) + 0.25))) < 1e-7
+
+
 # ----------------------------------------------------------------- rotations
 
 def test_rotation_invariants():
