@@ -753,11 +753,13 @@ def convert_compare(ctx, keys, cts, level, reps):
     return res
 
 
-def cnn128_setup(vr, level_in, sets, fc_level=1, ntt_plan="auto"):
+def cnn128_setup(vr, level_in, sets, fc_level=3, ntt_plan="auto"):
     """The 3x128x128 network at N = 2^16 (60 + 24x50, P 9x51, dnum 3): keys,
     `sets` encrypted 128-image sets (384 column ciphertexts each) entering at
     level_in, and the network (conv 3x3/2 pad 1 x8, x^2, FC 8*64*64 -> 10 with
-    its weights encoded at fc_level, the level the FC runs at)."""
+    its weights encoded at fc_level, the level the FC runs at: at 3 the
+    network call takes the x^2 tensors into the FC unrelinearised and
+    relinearises the ten sums)."""
     import synthetic_inputs as SI
     W = SI.CNN_128
     ctx = vr.Context(16, [60] + [50] * 24, [51] * 9, 3, 50.0)
@@ -770,11 +772,12 @@ def cnn128_setup(vr, level_in, sets, fc_level=1, ntt_plan="auto"):
     Wfc, bfc = W.draw_fc()
     Xs = [X0] + [SI.images(W.seed + 1000 * i, W.batch, W.channels, W.h, W.w) for i in range(1, sets)]
     cols = [ctx.encrypt_columns(keys, X, W.pad, level_in, 1003, 10000 * i) for i, X in enumerate(Xs)]
-    W_pt = ctx.encode_fc_weights(Wfc, W.stride, Hp, min(fc_level, level_in - 2))
+    fc_level = min(fc_level, level_in - 1)
+    W_pt = ctx.encode_fc_weights(Wfc, W.stride, Hp, fc_level)
     net = vr.CNN(W.channels, W.h, W.w, W.pad, K, bias, W.stride, square=True, fc_w=W_pt, fc_bias=bfc,
                  fc_block=Hp)
     return {"W": W, "ctx": ctx, "keys": keys, "X0": X0, "K": K, "bias": bias, "Wfc": Wfc, "bfc": bfc,
-            "W_pt": W_pt, "Hp": Hp, "cols": cols, "net": net}
+            "W_pt": W_pt, "Hp": Hp, "cols": cols, "net": net, "fc_level": fc_level}
 
 
 def cnn128_logit_error(C, z):
@@ -1248,8 +1251,9 @@ def main():
            "config": {"workload": "3x128x128 images, conv 3x3/2 pad 1 x8 + x^2 + FC 32768->10, N=2^16 "
                                   "(60+24x50, P 9x51, dnum 3), ciphertexts entering at level %d, %d x 128 "
                                   "images per step" % (args.level, args.sets),
-                      "images_per_step": images, "level_in": args.level, "fc_level": 1,
-                      "path": "whole-network call (vr_cnn_forward)"},
+                      "images_per_step": images, "level_in": args.level, "fc_level": C["fc_level"],
+                      "path": "whole-network call (vr_cnn_forward); x^2 relinearised once per FC output "
+                              "when the FC level has room (fc_level >= 3 here)"},
            "latency_ms_p50": round(percentile(lat, 50), 3), "latency_ms_p99": round(percentile(lat, 99), 3),
            "roofline": roofline, "decoded_rel_error": err, "setup_s": round(setup_s, 1)}
     out["autotuned"] = ctx.tuning_report().splitlines()

@@ -51,6 +51,8 @@ example, figure or number for the split schedules; they are pinned only by the
 FP64 plaintext layers below (and special cases: identity matrix, delta kernel,
 constant image) to within 2^-20 normwise relative error.
 """
+import math
+
 import numpy as np
 
 from .ckks import Context, Keys, pow2ceil, Plaintext
@@ -348,6 +350,51 @@ def fc(ctx: Context, keys: Keys, Y, pts, bias, Hp):
             t = ctx.mul_plain(y, pt)
             acc = t if acc is None else ctx.add(acc, t)
         z = ctx.rescale(acc)
+        step = 1
+        while step < Hp:
+            z = ctx.add(z, ctx.rotate(z, step, keys))
+            step *= 2
+        out.append(ctx.add_const(z, float(bias[o])))
+    return out
+
+
+def square_fc_lazy(ctx: Context, y_scale, p_scale, level):
+    """Whether x^2 and the FC run with one relinearisation per FC output: the
+    FC level l >= 2 and 2^10 times the tensors' weight-product scale
+    y_scale^2 p_scale stays below Q_l / 2, checked in integers: with e the
+    binary exponent of that scale (it is below 2^e) and b the total bit length
+    of q_0..q_l (Q_l >= 2^(b - l - 1)), e + l + 12 <= b."""
+    if level < 2:
+        return False
+    e = math.frexp(y_scale * y_scale * p_scale)[1]
+    b = sum(int(q).bit_length() for q in ctx.q[:level + 1])
+    return e + level + 12 <= b
+
+
+def square_fc(ctx: Context, keys: Keys, Y, pts, bias, Hp):
+    """x^2 then fc with lazy relinearisation (the paper's Mul of the
+    activation, its relinearisation moved past the FC's linear sums): each
+    input's tensor Tensor(Y_i, Y_i), taken on the FC level's limbs, is
+    multiplied by the weight plaintexts and summed, and only the sums are
+    relinearised:
+        Z_o = RotSum_Hp(Rescale(RelinRescale(sum_i Tensor(Y_i, Y_i) pt_{o,i}))) + bias_o.
+    One key switch per output instead of one per input; the decrypted
+    result is that of fc(square(Y)) up to rounding.  Needs
+    square_fc_lazy(Y scale, pt scale, level)."""
+    level = min(Y[0].level, pts[0][0].level)
+    if not square_fc_lazy(ctx, Y[0].scale, pts[0][0].scale, level):
+        raise ValueError("no room for the unrelinearised FC products at this level")
+    T = []
+    for y in Y:
+        yd = ctx.mod_drop(y, level) if y.level > level else y
+        T.append(ctx.tensor(yd, yd))
+    out = []
+    for o, row in enumerate(pts):
+        acc = None
+        for t, pt in zip(T, row):
+            p = ctx.mul_plain(t, pt)
+            acc = p if acc is None else ctx.add(acc, p)
+        z = ctx.rescale(ctx.relin_rescale(acc, keys))
         step = 1
         while step < Hp:
             z = ctx.add(z, ctx.rotate(z, step, keys))

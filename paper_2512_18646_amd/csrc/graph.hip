@@ -41,30 +41,11 @@ CnnDesc make_desc(vr_context* ctx, const vr_cnn_desc* d, u32 level_in, hipStream
 }
 
 // the network on the slab x of n_sets * C_in * w ciphertexts; outputs set
-// after set (n_out() each)
+// after set (n_out() each): the one-session case of run_cnn_multi
 Slab run_cnn(vr_context* ctx, const vr_eval_keys* ek, const CnnDesc& d, const Slab& x, u32 n_sets,
              hipStream_t s)
 {
-    Slab y = conv_slab(ctx, ek, x, n_sets, d.C_in, d.w, d.pad, d.K.data(), d.bias.data(), d.C_out,
-                       d.k, d.stride, s);
-    if (d.square) y = layer_square(ctx, ek, y, s);
-    if (!d.fc_out) return y;
-    const u32 per = d.C_out * d.w_out();
-    if (n_sets == 1)
-        return fc_slab(ctx, ek, y, d.fc_P, d.fc_stride, d.fc_scale, d.fc_level, d.fc_out, d.fc_bias.data(),
-                       d.fc_block, s);
-    Slab z = new_slab(ctx, n_sets * d.fc_out, 2, std::min(y.level, d.fc_level) - 1, 1.0, s);
-    for (u32 st = 0; st < n_sets; st++) {
-        Slab ys = y;
-        ys.n = per;
-        ys.base = y.ct(st * per);
-        Slab zs = fc_slab(ctx, ek, ys, d.fc_P, d.fc_stride, d.fc_scale, d.fc_level, d.fc_out, d.fc_bias.data(),
-                          d.fc_block, s);
-        z.scale = zs.scale;
-        VR_HIP(hipMemcpyAsync(z.ct(st * d.fc_out), zs.base, (size_t)d.fc_out * zs.stride * sizeof(u64),
-                              hipMemcpyDeviceToDevice, s));
-    }
-    return z;
+    return run_cnn_multi(ctx, {NetSeg{&d, ek, n_sets}}, x, s);
 }
 
 // Sets the thread's capture pool for the guard's lifetime.  The context's
@@ -259,12 +240,17 @@ void release_graph(vr_graph* g)
     (void)hipDeviceSynchronize();
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
-    // later frees of the input slab follow the context's stream; the graph's
-    // own blocks return when the last handle into them is gone
+    // later frees of the input slab and of the description's gathered FC
+    // weights (both made on the capture stream) follow the context's stream,
+    // and happen before that stream goes; the graph's own blocks return when
+    // the last handle into them is gone
     if (g->in.buf) g->in.buf->stream = g->ctx->stream;
+    for (BufPtr& b : g->desc.fc_hold)
+        if (b && b->stream == g->cap) b->stream = g->ctx->stream;
     g->keep.reset();
     g->out = Slab();
     g->in = Slab();
+    g->desc = CnnDesc();
     if (g->cap) (void)hipStreamDestroy(g->cap);
     delete g;
 }

@@ -350,6 +350,60 @@ __global__ __launch_bounds__(kThreads) void k_tensor_batch(u64* out, const u64* 
 // P + (o * n_in + i) * p_stride, limbs [N] each.
 constexpr int kFcGroup = 8;
 
+// FC weight products of the x^2 tensors (lazy relinearisation): for outputs
+// o0 .. o0 + kFcGroup - 1 and limb l,
+//   out_o = sum_i (y_i0^2, 2 y_i0 y_i1, y_i1^2) P[o][i]     (3 components),
+// the tensor of each input formed once per limb and weight group.
+__global__ __launch_bounds__(kThreads) void k_sqfc_acc(u64* out, u64 out_stride, const u64* Y, u64 y_stride,
+                                                       u64 y_comp, u32 n_in, const u64* P, u64 p_stride,
+                                                       u32 n_out, u32 nl, u32 log_n, const ModQ* mq)
+{
+    const u32 n = 1u << log_n;
+    const u32 t = blockIdx.x * kThreads + threadIdx.x;
+    if (t >= n) return;
+    const u32 l = blockIdx.y;
+    const u32 o0 = blockIdx.z * kFcGroup;
+    const u32 cnt = min((u32)kFcGroup, n_out - o0);
+    const ModQ m = mq[l];
+    u64 h[3][kFcGroup], lo[3][kFcGroup];
+#pragma unroll
+    for (int c = 0; c < 3; c++)
+#pragma unroll
+        for (int g = 0; g < kFcGroup; g++) h[c][g] = lo[c][g] = 0;
+    const size_t off0 = (size_t)l * n + t, yoff1 = y_comp + off0;
+    for (u32 i = 0; i < n_in; i++) {
+        const u64 y0 = Y[(size_t)i * y_stride + off0];
+        const u64 y1 = Y[(size_t)i * y_stride + yoff1];
+        const u64 x01 = mul_mod(y0, y1, m);
+        const u64 d[3] = {mul_mod(y0, y0, m), add_mod(x01, x01, m.q), mul_mod(y1, y1, m)};
+#pragma unroll
+        for (int g = 0; g < kFcGroup; g++) {
+            if (g < (int)cnt) {
+                const u64 p = P[((size_t)(o0 + g) * n_in + i) * p_stride + off0];
+#pragma unroll
+                for (int c = 0; c < 3; c++) mac128(h[c][g], lo[c][g], d[c], p);
+            }
+        }
+        if ((i & 31) == 31) {   // keep every 128-bit sum below 2^127
+#pragma unroll
+            for (int c = 0; c < 3; c++)
+#pragma unroll
+                for (int g = 0; g < kFcGroup; g++) {
+                    lo[c][g] = reduce128(h[c][g], lo[c][g], m);
+                    h[c][g] = 0;
+                }
+        }
+    }
+#pragma unroll
+    for (int g = 0; g < kFcGroup; g++) {
+        if (g < (int)cnt) {
+            u64* o = out + (size_t)(o0 + g) * out_stride + off0;
+#pragma unroll
+            for (int c = 0; c < 3; c++) o[(size_t)c * nl * n] = reduce128(h[c][g], lo[c][g], m);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kThreads) void k_mulplain_acc(u64* out, u64 out_stride,
                                                            const u64* Y, u64 y_stride, u64 y_comp,
                                                            u32 n_in, const u64* P, u64 p_stride,
@@ -1334,6 +1388,21 @@ void outer_tiles(vr_context* ctx, u32 m, u32 p, u32* Pp, u32* R, u32* T)
     *T = (m + *R - 1) / *R;
 }
 
+// x^2 followed by the FC with one relinearisation per FC output (lazy
+// relinearisation) when the FC level l >= 2 leaves room for the tensors'
+// weight products: with e the binary exponent of y_scale^2 p_scale (the
+// product scale is below 2^e) and b the total bit length of q_0..q_l,
+// e + l + 12 <= b keeps 2^10 times the scale below Q_l / 2.
+bool square_fc_lazy(vr_context* ctx, double y_scale, double p_scale, u32 fl)
+{
+    if (fl < 2) return false;
+    int e = 0;
+    (void)std::frexp(y_scale * y_scale * p_scale, &e);
+    int bits = 0;
+    for (u32 i = 0; i <= fl; i++) bits += 64 - __builtin_clzll(ctx->mod[i]);
+    return e + (int)fl + 12 <= bits;
+}
+
 Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab& x, hipStream_t s)
 {
     if (segs.empty()) throw Error(VR_EINVAL, "empty wave");
@@ -1376,7 +1445,10 @@ Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab&
     cr.rot.clear();
     Slab y = cr.ext ? mod_down_rescale_slab(ctx, acc, s) : rescale_slab(ctx, acc, s);
     acc = Slab();
-    if (d0.square) {
+    // x^2 and FC fused: the squares' tensors meet the FC weights unrelinearised
+    const bool lazy_fc = d0.square && d0.fc_out &&
+                         square_fc_lazy(ctx, y.scale, d0.fc_scale, std::min(y.level, d0.fc_level));
+    if (d0.square && !lazy_fc) {
         // tensor of everything, relinearisation per session, one rescale
         Slab T = new_slab(ctx, y.n, 3, y.level, y.scale * y.scale, s);
         dim3 grid((ctx->n + kThreads - 1) / kThreads, y.n * (y.level + 1));
@@ -1390,7 +1462,8 @@ Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab&
     }
     if (!d0.fc_out) return y;
     // FC: weight products per network and set at the weights' level, one
-    // rescale, the rotate-and-sum over each set's block (segments in
+    // rescale (lazy: the relinearisation fused with a rescale, then a second
+    // rescale), the rotate-and-sum over each set's block (segments in
     // decreasing block order, so the ones still summing form a prefix)
     const u32 fl = std::min(y.level, d0.fc_level);
     if (fl < 1) throw Error(VR_ELEVEL, "FC needs a level to rescale");
@@ -1400,7 +1473,8 @@ Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab&
         if (i && segs[i].d->fc_block > segs[i - 1].d->fc_block)
             throw Error(VR_EINVAL, "FC segments must come in decreasing block order");
     }
-    Slab z = new_slab(ctx, n_fc, 2, fl, y.scale * d0.fc_scale, s);
+    Slab z = lazy_fc ? new_slab(ctx, n_fc, 3, fl, y.scale * y.scale * d0.fc_scale, s)
+                     : new_slab(ctx, n_fc, 2, fl, y.scale * d0.fc_scale, s);
     std::vector<KeyRange> kfc;
     u32 y_at = 0, z_at = 0;
     for (const NetSeg& g : segs) {
@@ -1408,9 +1482,15 @@ Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab&
         const u32 per = d.C_out * d.w_out();
         for (u32 st = 0; st < g.n_sets; st++) {
             dim3 grid((ctx->n + kThreads - 1) / kThreads, fl + 1, (d.fc_out + kFcGroup - 1) / kFcGroup);
-            hipLaunchKernelGGL(k_mulplain_acc, grid, dim3(kThreads), 0, s, z.ct(z_at + st * d.fc_out), z.stride,
-                               y.ct(y_at + st * per), y.stride, (u64)(y.level + 1) * ctx->n, per, d.fc_P,
-                               d.fc_stride, d.fc_out, fl + 1, ctx->log_n, ctx->d_modq);
+            ProfScope prof(ctx, kProfTensor, s, (u64)d.fc_out * (lazy_fc ? 3 : 2) * (fl + 1));
+            if (lazy_fc)
+                hipLaunchKernelGGL(k_sqfc_acc, grid, dim3(kThreads), 0, s, z.ct(z_at + st * d.fc_out), z.stride,
+                                   y.ct(y_at + st * per), y.stride, (u64)(y.level + 1) * ctx->n, per, d.fc_P,
+                                   d.fc_stride, d.fc_out, fl + 1, ctx->log_n, ctx->d_modq);
+            else
+                hipLaunchKernelGGL(k_mulplain_acc, grid, dim3(kThreads), 0, s, z.ct(z_at + st * d.fc_out), z.stride,
+                                   y.ct(y_at + st * per), y.stride, (u64)(y.level + 1) * ctx->n, per, d.fc_P,
+                                   d.fc_stride, d.fc_out, fl + 1, ctx->log_n, ctx->d_modq);
             VR_CHECK_LAUNCH();
         }
         kfc.push_back(KeyRange{z_at, z_at + g.n_sets * d.fc_out, g.ek});
@@ -1418,6 +1498,7 @@ Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab&
         z_at += g.n_sets * d.fc_out;
     }
     y = Slab();
+    if (lazy_fc) z = relin_slab_keyed(ctx, kfc, z, s, true);
     z = rescale_slab(ctx, z, s);
     for (u32 step = 1; step < segs[0].d->fc_block; step <<= 1) {
         std::vector<KeyRange> act;

@@ -88,6 +88,53 @@ def test_graph_replays_match_eager(net):
     g2.close()
 
 
+@pytest.mark.parametrize("fc_level", [3, 1])
+def test_network_square_fc_lazy_relinearisation(fc_level):
+    """FC weights at a level with room for the unrelinearised products (3):
+    the network call fuses x^2 into the FC, one relinearisation per output,
+    limb for limb the oracle's square_fc after its (lazy) conv, also as a
+    replayed graph; at level 1 it keeps the per-layer form.  Both decode to
+    the FP64 network."""
+    from paper_2512_18646_amd import vr
+    from tests.gpu_helpers import to_gpu, assert_same
+    o, ok, g, gk = pair("C2", rot_steps=(1, 2, 4, 8), log_n=10)
+    B, Ci, h, w, Co, k, s, pad, lv = 4, 2, 10, 9, 3, 3, 2, 1, 5
+    rng = np.random.default_rng(52)
+    X = rng.uniform(0, 1, (B, Ci, h, w))
+    K = rng.normal(0, 0.1, (Co, Ci, k, k))
+    bias = rng.normal(0, 0.1, Co)
+    Hp = Ly.image_block(h, pad)
+    ref = Ly.ref_conv(X, K, bias, s, pad)
+    ho, wo = ref.shape[2], ref.shape[3]
+    W = rng.normal(0, 0.05, (4, Co, ho, wo))
+    fb = rng.normal(0, 0.05, 4)
+    cts = Ly.encrypt_image_columns(o, ok, X, pad, lv, 3, 0)
+    Y = Ly.conv2d(o, ok, cts, Ci, h, w, pad, K, bias, Co, k, s)
+    pts = Ly.fc_plaintexts(o, W, Co, ho, wo, s, Hp, fc_level)
+    lazy = Ly.square_fc_lazy(o, Y[0].scale, pts[0][0].scale, min(Y[0].level, fc_level))
+    assert lazy == (fc_level == 3)
+    if lazy:
+        Z = Ly.square_fc(o, ok, Y, pts, fb, Hp)
+    else:
+        Z = Ly.fc(o, ok, [Ly.square(o, ok, y) for y in Y], pts, fb, Hp)
+    gpts = [g.pt_import(pt.m, pt.level, pt.scale) for row in pts for pt in row]
+    net = vr.CNN(Ci, h, w, pad, K, bias, s, square=True, fc_w=gpts, fc_bias=fb, fc_block=Hp)
+    gcts = [to_gpu(g, c) for c in cts]
+    out = net.forward(g, gk, gcts, n_sets=1)
+    for i, (a, b) in enumerate(zip(out, Z)):
+        assert_same(a, b, "network output %d (fc level %d)" % (i, fc_level))
+    gr = vr.Graph(g, gk, net, gcts, n_sets=1)
+    for rep in range(2):
+        gr.launch()
+        for i, (a, b) in enumerate(zip(gr.outputs(), Z)):
+            assert_same(a, b, "graph replay %d output %d" % (rep, i))
+    gr.close()
+    logits = np.zeros((B, 4))
+    for oi, z in enumerate(out):
+        logits[:, oi] = g.decode(g.decrypt(gk, z))[np.arange(B) * Hp]
+    assert Ly.rel_error(logits, Ly.ref_fc(ref ** 2, W, fb)) < 2.0 ** -20
+
+
 def test_per_op_network_matches_layer_calls(net):
     """The network as one C-ABI call per HE operation (conv: hoisted
     rotations, MulConst, Add, AddConst, Rescale; x^2: Tensor, the fused

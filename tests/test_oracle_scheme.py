@@ -438,6 +438,40 @@ def test_conv_schedule_random_square_fc(ctx10):
     assert Ly.rel_error(Ly.fc_decode(ctx, keys, Z1, B, Hp), Ly.ref_fc(ref, W, fb)) < EPS
 
 
+def test_square_fc_lazy_relinearisation_against_fp64():
+    """x^2 and FC with one relinearisation per FC output decode to the FP64
+    FC of the squared conv outputs, as the per-layer form does; the rule
+    refuses levels without room for the unrelinearised products."""
+    ctx = small_ctx(log_n=10, q_bits=(49, 40, 40, 40, 40, 40), p_bits=(49,), dnum=6)
+    keys = ctx.keygen(1002, rot_steps=list(range(1, 3)) + [2 ** i for i in range(2, 8)])
+    B, Ci, h, w, Co, k, s, pad = 4, 2, 10, 9, 3, 3, 2, 1
+    rng = np.random.default_rng(30)
+    X = rng.uniform(0, 1, (B, Ci, h, w))
+    K = rng.normal(0, 0.1, (Co, Ci, k, k))
+    bias = rng.normal(0, 0.1, Co)
+    cts = Ly.encrypt_image_columns(ctx, keys, X, pad, 5, 3, 0)
+    Y = Ly.conv2d(ctx, keys, cts, Ci, h, w, pad, K, bias, Co, k, s)
+    assert Y[0].level == 4
+    ref = Ly.ref_conv(X, K, bias, s, pad)
+    Hp = Ly.image_block(h, pad)
+    ho, wo = ref.shape[2], ref.shape[3]
+    W = rng.normal(0, 0.05, (4, Co, ho, wo))
+    fb = rng.normal(0, 0.05, 4)
+    pts = Ly.fc_plaintexts(ctx, W, Co, ho, wo, s, Hp, 3)
+    assert Ly.square_fc_lazy(ctx, Y[0].scale, pts[0][0].scale, 3)
+    assert not Ly.square_fc_lazy(ctx, Y[0].scale, pts[0][0].scale, 2)
+    assert not Ly.square_fc_lazy(ctx, Y[0].scale, pts[0][0].scale, 1)
+    Z = Ly.square_fc(ctx, keys, Y, pts, fb, Hp)
+    assert Z[0].level == 1
+    want = Ly.ref_fc(ref ** 2, W, fb)
+    lazy = Ly.fc_decode(ctx, keys, Z, B, Hp)
+    assert Ly.rel_error(lazy, want) < EPS
+    plain = Ly.fc_decode(ctx, keys, Ly.fc(ctx, keys, [Ly.square(ctx, keys, y) for y in Y], pts, fb, Hp), B, Hp)
+    assert Ly.rel_error(plain, want) < EPS
+    with pytest.raises(ValueError):
+        Ly.square_fc(ctx, keys, Y, Ly.fc_plaintexts(ctx, W, Co, ho, wo, s, Hp, 2), fb, Hp)
+
+
 def test_conv_special_cases(ctx10):
     """A delta kernel returns the strided, shifted image; a constant image
     returns the constant times the kernel sum (interior outputs)."""
