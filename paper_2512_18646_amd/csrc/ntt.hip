@@ -72,6 +72,18 @@ __device__ __forceinline__ void limb_addr(const LimbSet& ls, u32 r, u32 n, u32 L
     *out = ls.out_dense ? ls.out + (size_t)r * n : ls.out + off;
 }
 
+// Dispatch order of a set's limbs: slot l of every poly before slot l + 1,
+// so limbs that share a modulus, and so its twiddle tables, run close
+// together and the tables are read from each XCD's L2 rather than from HBM
+// once per limb.  rr (dispatch index) -> r = poly * per_poly + l.
+__device__ __forceinline__ u32 limb_order(const LimbSet& ls, u32 rr)
+{
+    const u32 np = ls.n_polys;
+    if (np <= 1) return rr;
+    const u32 l = rr / np;
+    return (rr - l * np) * ls.per_poly + l;
+}
+
 __device__ __forceinline__ u32 pad(u32 i) { return i + (i >> 4); }
 
 // words per thread moved between global memory and LDS with their loads all
@@ -385,7 +397,7 @@ __global__ __launch_bounds__(THREADS) void k_ntt_pass(NttPass p)
     const u32 blocks_per_limb = (n >> p.log_g) >> p.log_c;
     const u32 rl = blockIdx.x / blocks_per_limb;
     const u32 g0 = (blockIdx.x - rl * blocks_per_limb) << p.log_c;
-    const u32 r = p.r0 + rl;
+    const u32 r = limb_order(p.ls, p.r0 + rl);
 
     const u64* src;
     u64* dst;
@@ -1026,7 +1038,7 @@ template <int LOGN, int LOGE, bool INV>
 __global__ __launch_bounds__(1u << (LOGN - LOGE)) void k_ntt_limb(NttPass p)
 {
     extern __shared__ u64 lds[];
-    LimbK c = limb_consts<LOGN, INV>(p, p.r0 + blockIdx.x);
+    LimbK c = limb_consts<LOGN, INV>(p, limb_order(p.ls, p.r0 + blockIdx.x));
     c.tid = threadIdx.x;
     LinePrefetch<LOGN, LOGE> pf;
     limb_transform<LOGN, LOGE, INV>(lds, c, pf);
@@ -1260,7 +1272,7 @@ __global__ __launch_bounds__((SplitShape<LOGN, A, LC, PASS>::T)) void k_ntt_spli
 {
     using S = SplitShape<LOGN, A, LC, PASS>;
     extern __shared__ u64 lds[];
-    const u32 r = p.r0 + (blockIdx.x >> S::WG_LOG), wg = blockIdx.x & ((1u << S::WG_LOG) - 1);
+    const u32 r = limb_order(p.ls, p.r0 + (blockIdx.x >> S::WG_LOG)), wg = blockIdx.x & ((1u << S::WG_LOG) - 1);
     LimbK c = limb_consts<LOGN, INV>(p, r);
     c.tid = threadIdx.x;
     constexpr bool FIRST = INV ? PASS == 1 : PASS == 0;
