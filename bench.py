@@ -957,27 +957,31 @@ def _orc_c3_sample(_=None):
     t0 = time.perf_counter()
     y = o.mod_down_rescale(o.add_const_ext(acc, 0.5))
     t["addconst_rescale24"] = time.perf_counter() - t0
+    # x^2 into the FC at level 3 (square_fc): tensor on the FC's limbs, the
+    # weight products on 3 components, one relinearisation per output
     t0 = time.perf_counter()
-    o.relin_rescale(o.tensor(y, y), ok)
-    t["square23"] = time.perf_counter() - t0
+    y3 = o.mod_drop(y, 3)
+    T = o.tensor(y3, y3)
+    t["tensor3"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     acc = None
     for r in range(6):
-        x = o.mul_plain(cts[1], _ORC["pt1"])
+        x = o.mul_plain(T, _ORC["pt3"])
         acc = x if acc is None else o.add(acc, x)
-    t["mulplain_add1"] = (time.perf_counter() - t0) / 6
+    t["mulplain_add3"] = (time.perf_counter() - t0) / 6
     t0 = time.perf_counter()
-    z = o.rescale(acc)
-    t["rescale1"] = time.perf_counter() - t0
+    z = o.rescale(o.relin_rescale(acc, ok))
+    t["relin_rescale3"] = time.perf_counter() - t0
     t0 = time.perf_counter()
     o.add(z, o.rotate(z, 1, ok))
-    t["rot_add0"] = time.perf_counter() - t0
+    t["rot_add1"] = time.perf_counter() - t0
     return t
 
 
 # operation counts of one 128-image set of the C3 network entering at level 24
-C3_OPS = {"rot24": 768, "mulconst_add24": 13752, "addconst_rescale24": 512, "square23": 512,
-          "mulplain_add1": 5120, "rescale1": 10, "rot_add0": 80}
+# (FC weights at level 3: x^2 relinearised once per FC output)
+C3_OPS = {"rot24": 768, "mulconst_add24": 13752, "addconst_rescale24": 512, "tensor3": 512,
+          "mulplain_add3": 5120, "relin_rescale3": 10, "rot_add1": 80}
 
 
 def cpu_oracle_child():
@@ -988,15 +992,14 @@ def cpu_oracle_child():
     from oracle import layers as Ly
     import synthetic_inputs as SI
     res = {"host": host_info()}
-    # C3 at level 24 (keys, two input ciphertexts at levels 24 and 1, one FC
-    # weight plaintext at level 1)
+    # C3 at level 24 (keys, one input ciphertext at level 24, one FC weight
+    # plaintext at level 3)
     t0 = time.perf_counter()
     o = OC(PRESETS["C3"])
     ok = o.keygen(1003, rot_steps=[1])
     z = np.random.default_rng(3).uniform(0, 1, o.slots)
-    _ORC.update(o=o, ok=ok, cts={24: o.encrypt(ok, o.encode(z, 24, o.scale), 1003, 0),
-                                 1: o.encrypt(ok, o.encode(z, 1, o.scale), 1003, 1)},
-                pt1=o.encode(z * 0.01, 1, float(o.q[1])))
+    _ORC.update(o=o, ok=ok, cts={24: o.encrypt(ok, o.encode(z, 24, o.scale), 1003, 0)},
+                pt3=o.encode(z * 0.01, 3, float(o.q[3])))
     setup = time.perf_counter() - t0
     t0 = time.perf_counter()
     one = _orc_c3_sample()
@@ -1020,8 +1023,9 @@ def cpu_oracle_child():
         "op_counts_per_set": C3_OPS, "extrapolated": True,
         "sample": "one of each operation class of the 128-image C3 set at level 24 (1 rotation kept in the "
                   "extended basis at level 24, 6 MulConst+Add there, AddConst + ModDown by P q_l, one x^2 "
-                  "(tensor + fused relinearise-rescale) at level 23, 6 MulPlain+Add at level 1, Rescale, "
-                  "rotate+add at level 0), %.1f s on one core, scaled by the set's operation counts; all-core: "
+                  "tensor on the FC's level-3 limbs, 6 MulPlain+Add of 3-component tensors at level 3, one "
+                  "relinearise-rescale + rescale, "
+                  "rotate+add at level 1), %.1f s on one core, scaled by the set's operation counts; all-core: "
                   "the same sample on %d processes at once (%.1f s wall)" % (t_one, cores, t_all),
         "setup_s": round(setup, 1)}
     del samples

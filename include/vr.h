@@ -352,7 +352,12 @@ vr_status vr_matmul_plan(vr_context *ctx, uint32_t m, uint32_t n, uint32_t p, ui
  *   Rescale(sum_{c,u,v} MulConst(Rot(in[c][s j'+v-pad], u), K[c'][c][u][v],
  *           q_level) + AddConst(bias[c'])),
  * slot b H' + s i' holding output row i' of image b.  Needs rotation keys for
- * steps 1..k-1. */
+ * steps 1..k-1.  When k > 1 and the special primes number at most level + 1,
+ * the rotations keep their key-switch sums in the extended basis (P times the
+ * rotated ciphertext over q_0..q_level and the special primes), the sum is
+ * taken there and one ModDown by P q_level per output both finishes the key
+ * switches and rescales (one rounding per output instead of one per
+ * rotation; the same message). */
 vr_status vr_conv2d(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *const *in,
                     uint32_t C_in, uint32_t h, uint32_t w, uint32_t pad, const double *K,
                     const double *bias, uint32_t C_out, uint32_t k, uint32_t stride,
@@ -467,7 +472,15 @@ vr_status vr_profile_stop(vr_context *ctx, double *total_ms, uint64_t *launches,
  * The encrypted CNN of "Convolutional Neural Networks" with the column-wise
  * layout: conv (as vr_conv2d), then x^2 when square != 0, then the FC layer
  * (as vr_fc) when fc_w != NULL.  fc_w holds fc_out * C_out * w_out weight
- * plaintexts in vr_fc's order, at a level >= the FC input level. */
+ * plaintexts in vr_fc's order; the FC runs at min(its input's level, the
+ * plaintexts' level).  x^2 followed by the FC is evaluated with lazy
+ * relinearisation when the FC level l >= 2 has room for the unrelinearised
+ * products (with e the binary exponent of y_scale^2 * pt_scale and b the
+ * total bit length of q_0..q_l: e + l + 12 <= b): each input's tensor,
+ * formed on the FC level's limbs, is multiplied by the weights and summed,
+ * and each FC output is relinearised once (RelinRescale, then Rescale): two
+ * levels from the conv output.  Otherwise x^2 and the FC run as the layer
+ * calls do. */
 typedef struct {
     uint32_t C_in, h, w, pad, C_out, k, stride;
     const double *K;                  /* [C_out][C_in][k][k] */
@@ -481,7 +494,8 @@ typedef struct vr_graph vr_graph;
 
 /* The network on n_sets image sets (in[s*C_in*w + c*w + j]) in one call:
  * out receives n_sets * (fc_w ? fc_out : C_out*w_out) handles, set after
- * set.  Identical limbs to the per-layer calls. */
+ * set.  Identical limbs to the per-layer calls, except that with lazy
+ * relinearisation (above) x^2 and the FC form one fused stage. */
 vr_status vr_cnn_forward(vr_context *ctx, const vr_eval_keys *ek, const vr_cnn_desc *desc,
                          const vr_ciphertext *const *in, uint32_t n_sets, vr_ciphertext **out,
                          void *stream);
@@ -508,9 +522,11 @@ void vr_graph_destroy(vr_graph *g);
  * as vr_matmul).  Networks with the same description, input level and scale
  * run as one multi-set evaluation; products at one level and scale share one
  * hoisted ModUp and, per rotation step, one shared-key inner product and one
- * ModDown for every request still needing that step.  Inputs are copied into
- * the batch when added.  Every request's output limbs are identical to its
- * own vr_cnn_forward / vr_matmul call. */
+ * ModDown for every request still needing that step.  A request's inputs are
+ * referenced in place (the batch shares their allocation) when they are one
+ * contiguous run of ciphertexts of one allocation, else gathered into the
+ * batch when added.  Every request's output limbs are identical to its own
+ * vr_cnn_forward / vr_matmul call. */
 typedef struct vr_batch vr_batch;
 vr_status vr_batch_create(vr_context *ctx, const vr_eval_keys *ek, vr_batch **out);
 /* *req_id indexes the request for vr_batch_outputs. */

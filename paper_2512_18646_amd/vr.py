@@ -326,6 +326,31 @@ class Context:
     def set_stream(self, stream):
         _check(lib.vr_context_set_stream(self.h, _stream(stream)))
 
+    def use_torch_allocator(self):
+        """Device memory from PyTorch's caching allocator (vr_context_set_allocator
+        with torch.cuda.caching_allocator_alloc / _delete on the stream the
+        library uses the memory on), so the library and the framework share
+        one pool.  Graph capture needs the built-in allocator."""
+        import torch
+        alloc_t = ctypes.CFUNCTYPE(ctypes.c_void_p, SZ, ctypes.c_void_p, ctypes.c_void_p)
+        free_t = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p)
+        dev = torch.cuda.current_device()
+
+        def alloc(nbytes, stream, user):
+            try:
+                return torch.cuda.caching_allocator_alloc(int(nbytes), dev, int(stream or 0))
+            except RuntimeError:
+                return None
+
+        def free(ptr, stream, user):
+            torch.cuda.caching_allocator_delete(ptr)
+        self._alloc_cbs = (alloc_t(alloc), free_t(free))   # kept alive with the context
+        _check(lib.vr_context_set_allocator(self.h, ctypes.cast(self._alloc_cbs[0], ctypes.c_void_p),
+                                            ctypes.cast(self._alloc_cbs[1], ctypes.c_void_p), None))
+
+    def use_builtin_allocator(self):
+        _check(lib.vr_context_set_allocator(self.h, None, None, None))
+
     def mem_info(self):
         """(reserved, in_use) bytes of the built-in caching allocator."""
         r, u = SZ(), SZ()
