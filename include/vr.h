@@ -120,7 +120,12 @@ vr_status vr_context_trim(vr_context *ctx);
  * fastest), "fixed" (the built-in plan) or "cand:<i>" (candidate i,
  * for tests; VR_EINVAL at the next transform if there is none).  Knob
  * "switch_chunk": "<k>" key-switches at most k ciphertexts per launch in the
- * layer calls ("0": as many as 16 GiB of scratch allows, the default).
+ * layer calls ("0": as many as 16 GiB of scratch allows, the default).  Knob
+ * "conv_prune": "on" (default) or "off": in the network call, when the FC
+ * reads the conv's output only on limbs q_0..q_f (the unrelinearised x^2
+ * into an FC at level f), the conv's rotations, sums and ModDown by P q_l
+ * produce only those limbs; "off" computes every limb and drops them after
+ * (identical words).
  * Tuning synchronises
  * once; the transform is the same exact map under every plan. */
 vr_status vr_context_set_tuning(vr_context *ctx, const char *knob, const char *value);

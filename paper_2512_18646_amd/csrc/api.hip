@@ -182,8 +182,10 @@ vr_status vr_context_set_tuning(vr_context* ctx, const char* knob, const char* v
         if (v.compare(0, 5, "cand:") == 0) mode = 2 + std::stoi(v.substr(5));
     }
     else if (k == "switch_chunk" || k == "ntt_chunk") mode = std::stoi(v);
+    else if (k == "conv_prune") mode = v == "on" ? 0 : v == "off" ? 1 : -1;
     else throw Error(VR_EINVAL, "unknown tuning knob");
-    REQUIRE(mode >= 0, "base_convert takes auto, alu, mfma or fp64; ntt takes auto, fixed or cand:k");
+    REQUIRE(mode >= 0, "base_convert takes auto, alu, mfma or fp64; ntt takes auto, fixed or cand:k; "
+                       "conv_prune takes on or off");
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->tuning[k] = mode;
     API_END
@@ -205,7 +207,7 @@ vr_status vr_context_tuning_report(vr_context* ctx, char* buf, size_t cap)
              std::to_string(kv.second.n_out) + ": " +
              name(kv.second.choice ? kv.second.choice->load() : -1) + "\n";
     for (auto& kv : ctx->moddown_rs_tables)
-        r += "moddown-rescale l" + std::to_string(kv.first) + " " + std::to_string(kv.second.n_in) + "->" +
+        r += "moddown-rescale l" + std::to_string(kv.first / 1024) + " " + std::to_string(kv.second.n_in) + "->" +
              std::to_string(kv.second.n_out) + ": " +
              name(kv.second.choice ? kv.second.choice->load() : -1) + "\n";
     for (int d = 0; d < 2; d++) {

@@ -326,6 +326,7 @@ __global__ __launch_bounds__(256) void k_base_convert_mfma(ConvArgs a, const u64
 constexpr int kMaxRuns = 4;
 struct LimbRuns {
     u32 b[kMaxRuns], len[kMaxRuns];
+    u32 o[kMaxRuns];   // output position (limb of U) of each run's first limb
 };
 VR_KERNEL_ARG(LimbRuns);
 
@@ -335,13 +336,14 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
                                                       u32 level, u32 next, u32 beta, u32 alpha, u32 L,
                                                       u32 log_n, u32 g_inv, u64* U, u64 u_stride,
                                                       const ModQ* mq, LimbRuns runs, const u64* F,
-                                                      u64 f_stride, const ulonglong2* pmod)
+                                                      u64 f_stride, const ulonglong2* pmod, u32 u_limbs)
 {
     const u32 n = 1u << log_n;
     const u32 s = blockIdx.x * kThreads + threadIdx.x;
     if (s >= n) return;
     u32 e = blockIdx.y, r = 0;
     while (r + 1 < kMaxRuns && e >= runs.len[r]) e -= runs.len[r++];
+    const u32 pos = runs.o[r] + e;   // limb of U this block writes
     e += runs.b[r];
     const u32 mod = e <= level ? e : L + 1 + (e - level - 1);
     const ModQ m = mq[mod];
@@ -389,9 +391,9 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
             }
             if (F && e <= level)   // + P sigma_g(c0): c0 read where X is, stored where U is
                 s0 += fmulmod(to_bal(F[(size_t)c * f_stride + (size_t)e * n + s], m.q, qd), pf, qd, qinv);
-            u64* u = U + (size_t)c * u_stride + (size_t)e * n + t;
+            u64* u = U + (size_t)c * u_stride + (size_t)pos * n + t;
             u[0] = to_canon(s0, qd, qinv);
-            u[(size_t)next * n] = to_canon(s1, qd, qinv);
+            u[(size_t)u_limbs * n] = to_canon(s1, qd, qinv);
 #pragma unroll
             for (int j = 0; j < MAXB; j++) xv[j] = xn[j];
         }
@@ -416,9 +418,9 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
                 }
             }
             if (F && e <= level) mac128(h0, l0, F[(size_t)c * f_stride + (size_t)e * n + s], pmod[mod].x);
-            u64* u = U + (size_t)c * u_stride + (size_t)e * n + t;
+            u64* u = U + (size_t)c * u_stride + (size_t)pos * n + t;
             u[0] = reduce128(h0, l0, m);
-            u[(size_t)next * n] = reduce128(h1, l1, m);
+            u[(size_t)u_limbs * n] = reduce128(h1, l1, m);
         }
     }
 }
@@ -600,17 +602,19 @@ const ConvTable& moddown_table(vr_context* ctx, u32 level)
     return ctx->moddown_tables[(int)level] = build_table(ctx, in, out);
 }
 
-// {q_l, p_0, ..., p_{K-1}} -> q_0..q_{l-1}: the conversion of a ModDown that
-// also drops q_l (relinearisation fused with the rescale)
-const ConvTable& moddown_rs_table(vr_context* ctx, u32 level)
+// {q_l, p_0, ..., p_{K-1}} -> q_0..q_{nk-1} (nk <= l): the conversion of a
+// ModDown that also drops q_l (relinearisation fused with the rescale), to
+// the nk limbs the consumer reads
+const ConvTable& moddown_rs_table(vr_context* ctx, u32 level, u32 nk)
 {
     std::lock_guard<std::mutex> g(ctx->mu);
-    auto it = ctx->moddown_rs_tables.find((int)level);
+    const int key = (int)(level * 1024 + nk);
+    auto it = ctx->moddown_rs_tables.find(key);
     if (it != ctx->moddown_rs_tables.end()) return it->second;
     std::vector<u32> in{level}, out;
     for (u32 k = 0; k < ctx->K; k++) in.push_back(ctx->L + 1 + k);
-    for (u32 i = 0; i < level; i++) out.push_back(i);
-    return ctx->moddown_rs_tables[(int)level] = build_table(ctx, in, out);
+    for (u32 i = 0; i < nk; i++) out.push_back(i);
+    return ctx->moddown_rs_tables[key] = build_table(ctx, in, out);
 }
 
 void launch_alu(vr_context* ctx, const ConvArgs& a, u32 n_polys, hipStream_t s)
@@ -810,7 +814,7 @@ void keyswitch_modup(vr_context* ctx, const u64* d, u32 level, u64* X, u64* coef
 
 void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u64* d, u64 d_stride,
                            u32 n_ct, const u64* key, u32 level, u32 g, u64* U, u64 u_stride,
-                           hipStream_t s, const u64* fold_c0, u64 fold_stride)
+                           hipStream_t s, const u64* fold_c0, u64 fold_stride, u32 keep_q)
 {
     KsShape k = ks_shape(ctx, level);
     // at least ~4096 blocks: split the ciphertexts (each group re-reads the key)
@@ -830,7 +834,9 @@ void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u6
         if (r * g % two_n != 1) throw Error(VR_EINVAL, "key switching: no inverse Galois element");
         g_inv = (u32)r;
     }
-    ProfScope prof(ctx, kProfKsInner, s, (u64)n_ct * k.next);
+    const u32 u_limbs = keep_q ? keep_q + 1 + ctx->K : k.next;
+    if (keep_q > level) throw Error(VR_EINVAL, "key switching: kept limbs above the level");
+    ProfScope prof(ctx, kProfKsInner, s, (u64)n_ct * u_limbs);
     if (k.beta > 16) throw Error(VR_EINVAL, "key switching: more than 16 digits");
     // one launch per path (FP64 below 2^51, else integer) over its runs of
     // consecutive extended limbs, so each kernel gets its own registers
@@ -839,6 +845,7 @@ void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u6
         std::vector<std::pair<u32, u32>> runs;   // (begin, length)
         for (u32 e = 0; e < k.next; e++) {
             if ((ctx->modq[ctx->ext_mod(e, level)].q < (1ull << 51)) != fp) continue;
+            if (keep_q && e >= keep_q && e < level) continue;   // Q limbs nobody reads
             if (!runs.empty() && runs.back().first + runs.back().second == e)
                 runs.back().second++;
             else
@@ -848,15 +855,17 @@ void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u6
             LimbRuns lr = {};
             u32 rows = 0;
             for (size_t r = r0; r < std::min(runs.size(), r0 + kMaxRuns); r++) {
-                lr.b[r - r0] = runs[r].first;
+                const u32 b = runs[r].first;
+                lr.b[r - r0] = b;
                 lr.len[r - r0] = runs[r].second;
+                lr.o[r - r0] = keep_q && b >= level ? b - level + keep_q : b;
                 rows += runs[r].second;
             }
             dim3 g2(grid.x, rows, grid.z);
 #define VR_KS_INNER(B, F)                                                                             \
     hipLaunchKernelGGL((k_ks_inner<B, F>), g2, dim3(kThreads), 0, s, X, x_stride, d, d_stride, n_ct, key, \
                        ctx->nmod(), level, k.next, k.beta, ctx->alpha, ctx->L, ctx->log_n, g_inv, U,   \
-                       u_stride, ctx->d_modq, lr, fold_c0, fold_stride, ctx->d_pmod_tab)
+                       u_stride, ctx->d_modq, lr, fold_c0, fold_stride, ctx->d_pmod_tab, u_limbs)
             if (k.beta <= 4) {
                 if (fp)
                     VR_KS_INNER(4, true);
@@ -954,34 +963,39 @@ void keyswitch_moddown_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u3
 //   out_j,i = (v_j,i - conv(v_j over {q_l, P})_i) (P q_l)^-1
 //           = (U_j,i - y_j,i) (P q_l)^-1 + c_j,i q_l^-1,   i < l,
 // so only the q_l limb takes the fold of P c_j before the conversion.  With
-// c0 = c1 = null, U is already the whole extended ciphertext v.
+// c0 = c1 = null, U is already the whole extended ciphertext v.  keep_q = nk
+// > 0: U is compact ([2][nk + 1 + K][N]: q_0..q_{nk-1}, q_l, the special
+// primes) and only output limbs 0..nk-1 are made (level nk - 1).
 void keyswitch_moddown_rescale_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u32 level,
                                      u64* out0, u64* out1, u64 out_stride, const u64* c0,
-                                     const u64* c1, u64 c_stride, u64* scratch, hipStream_t s)
+                                     const u64* c1, u64 c_stride, u64* scratch, hipStream_t s, u32 keep_q)
 {
     if (level == 0) throw Error(VR_ELEVEL, "no limb left to rescale by");
-    KsShape k = ks_shape(ctx, level);
-    const u32 n = ctx->n, K = ctx->K, nd = K + 1, no = level;
-    if (u_stride != (u64)2 * k.next * n) throw Error(VR_EINVAL, "moddown: U blocks must be dense");
+    if (keep_q > level) throw Error(VR_EINVAL, "moddown-rescale: kept limbs above the level");
+    const u32 n = ctx->n, K = ctx->K, nd = K + 1, no = keep_q ? keep_q : level;
+    const u32 ul = no + 1 + K;   // limbs of U per component; q_l at limb no
+    if (u_stride != (u64)2 * ul * n) throw Error(VR_EINVAL, "moddown: U blocks must be dense");
     if (!c0 != !c1) throw Error(VR_EINVAL, "moddown-rescale: c0 and c1 come together");
     u64* dcoef = scratch;                                   // [n_ct*2][K+1][N]
-    u64* Y = scratch + (size_t)n_ct * 2 * nd * n;           // [n_ct*2][level][N]
+    u64* Y = scratch + (size_t)n_ct * 2 * nd * n;           // [n_ct*2][no][N]
     if (c0) {
         const u64 ql = ctx->mod[level];
         u64 pm = 1 % ql;
         for (u32 j = 0; j < K; j++) pm = (u64)((u128)pm * (ctx->mod[ctx->L + 1 + j] % ql) % ql);
         dim3 grid((n + kThreads - 1) / kThreads, n_ct * 2);
-        hipLaunchKernelGGL(k_fold_pc, grid, dim3(kThreads), 0, s, U + (size_t)level * n, u_stride,
-                           (u64)k.next * n, c0 + (size_t)level * n, c1 + (size_t)level * n, c_stride, pm,
+        hipLaunchKernelGGL(k_fold_pc, grid, dim3(kThreads), 0, s, U + (size_t)no * n, u_stride,
+                           (u64)ul * n, c0 + (size_t)level * n, c1 + (size_t)level * n, c_stride, pm,
                            shoup_companion(pm, ql), ql, n);
         VR_CHECK_LAUNCH();
     }
     // q_l and the special limbs (consecutive in U) to the coefficient domain
-    LimbSet ls = poly_limbs(U, dcoef, n_ct * 2, nd, (u64)k.next * n, (int)level);
-    ls.slot0 = level;
+    LimbSet ls = poly_limbs(U, dcoef, n_ct * 2, nd, (u64)ul * n, (int)no);
+    ls.slot0 = no;
     ls.out_dense = 1;
+    ls.remap_slot = no;
+    ls.remap_mod = level;
     ntt_inverse(ctx, ls, s);
-    const ConvTable& tb = moddown_rs_table(ctx, level);
+    const ConvTable& tb = moddown_rs_table(ctx, level, no);
     ConvArgs a;
     a.in = dcoef;
     a.in_stride = (u64)nd * n;
@@ -999,7 +1013,7 @@ void keyswitch_moddown_rescale_batch(vr_context* ctx, u64* U, u64 u_stride, u32 
     NttEpilogue& ep = ly.epi;
     ep.a = U;
     ep.a_ct = u_stride;
-    ep.a_comp = (u64)k.next * n;
+    ep.a_comp = (u64)ul * n;
     ep.out0 = out0;
     ep.out1 = out1;
     ep.out_ct = out_stride;
@@ -1011,7 +1025,7 @@ void keyswitch_moddown_rescale_batch(vr_context* ctx, u64* U, u64 u_stride, u32 
     if (ntt_forward(ctx, ly, s)) return;
     dim3 grid((n + kThreads - 1) / kThreads, n_ct * no);
     ProfScope prof(ctx, kProfModDown, s, (u64)n_ct * 2 * no);
-    hipLaunchKernelGGL(k_moddown_finish, grid, dim3(kThreads), 0, s, U, u_stride, Y, no, k.next,
+    hipLaunchKernelGGL(k_moddown_finish, grid, dim3(kThreads), 0, s, U, u_stride, Y, no, ul,
                        ctx->log_n, out0, out1, out_stride, c0, 1u, c1, c_stride, ctx->d_modq,
                        ctx->d_prinv_tab + (size_t)level * ctx->nmod(),
                        ctx->d_rinv_tab + (size_t)level * ctx->nmod());

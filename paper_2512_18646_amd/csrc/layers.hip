@@ -49,15 +49,17 @@ Slab new_slab(vr_context* ctx, u32 n, u32 ncomp, u32 level, double scale, hipStr
     return sl;
 }
 
-Slab new_ext_slab(vr_context* ctx, u32 n, u32 level, double scale, hipStream_t s)
+Slab new_ext_slab(vr_context* ctx, u32 n, u32 level, double scale, hipStream_t s, u32 keep)
 {
+    if (keep > level) throw Error(VR_EINVAL, "kept limbs above the level");
     Slab sl;
     sl.n = n;
     sl.ncomp = 2;
     sl.level = level;
     sl.ext = 1;
+    sl.keep = keep;
     sl.scale = scale;
-    sl.stride = (u64)2 * (level + 1 + ctx->K) * ctx->n;
+    sl.stride = (u64)2 * ((keep ? keep : level) + 1 + ctx->K) * ctx->n;
     sl.buf = dev_alloc(ctx, std::max<size_t>(1, (size_t)n * sl.stride) * sizeof(u64), s);
     sl.base = as_u64(sl.buf);
     return sl;
@@ -146,11 +148,13 @@ constexpr u32 kTermColBits = 24;
 // filter f, 2 components of nl limbs.  The filters of one column read the
 // same inputs, so a block keeps all filters' sums in registers and reads each
 // input word once.  Term input (u, j): for u = 0 ciphertext s * n_x + j of
-// slab x (stride `stride`, nqx limbs per component: limbs l >= nqx of the
-// output take nothing from it), for u >= 1 ciphertext (u - 1) * ustride / rstride
-// + s * n_x + j of slab r (the rotations by u of every column of every set,
-// stride `rstride`, nl limbs per component).  Limb l has modulus l below nqx
-// and l + modoff from there (the special primes of an extended basis).
+// slab x (stride `stride`, x_limbs limbs per component), for u >= 1
+// ciphertext (u - 1) * ustride / rstride + s * n_x + j of slab r (the
+// rotations by u of every column of every set, stride `rstride`, nl limbs
+// per component).  Output limb l < nk is q_l, limb nk is q_lvl (both read
+// from that limb of x), limbs past nk are special primes (modulus l + modoff;
+// x contributes nothing): the Q basis is nk = lvl = nl - 1, the extended one
+// nk = lvl, and a compact extended one keeps nk < lvl low limbs.
 // Term weight offset for filter f and limb l: w_idx + f * w_fstride * nl + l.
 //
 // Launch order: the logical block id runs over output columns fastest, then
@@ -158,36 +162,45 @@ constexpr u32 kTermColBits = 24;
 // same input chunk run back to back; the logical ids are dealt to the 8 XCDs
 // in contiguous ranges (hardware hands block b to XCD b mod 8), so those
 // blocks share one L2.
+//
+// Each column's terms come with its rotated terms (u >= 1) first, the
+// unrotated ones from rot_end[jo]: the extended basis' special limbs take
+// only the rotated terms.  The FP64 path copies its weights (one contiguous
+// [term][filter] run per limb and filter group, up to kTermChunk terms at a
+// time) into LDS once per block, and each block covers cpb consecutive
+// 256-coefficient chunks with them; the products read the weights with
+// broadcast LDS loads instead of one scalar load each.
 constexpr int kMaxFilters = 8;
+constexpr u32 kTermChunk = 256;
 
 __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, const u64* x,
                                                       const u64* r, u32 n_x, u32 n_sets, u64 stride,
                                                       u64 rstride, u64 ustride,
                                                       const Term* terms, const u32* term_off,
-                                                      const u64* w, const u64* ws, const double* wf,
-                                                      u32 w_fstride,
-                                                      const u64* bias, u32 nl, u32 nqx, u32 modoff,
-                                                      u32 log_n, const ModQ* mq, u32 wo, u32 n_filters,
-                                                      u32 total, u32 per_xcd)
+                                                      const u32* rot_end,
+                                                      const u64* w, const u64* ws, const double* wt,
+                                                      u32 t_total, u32 w_fstride,
+                                                      const u64* bias, u32 nl, u32 nk, u32 lvl, u32 modoff,
+                                                      u32 x_limbs, u32 log_n, const ModQ* mq, u32 wo,
+                                                      u32 n_filters, u32 total, u32 per_xcd, u32 cpb)
 {
+    extern __shared__ double wl[];   // [term of the chunk][filter]
     const u32 logical = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
-    if (logical >= total) return;
+    if (logical >= total) return;   // whole blocks only: no barrier is skipped
     const u32 n = 1u << log_n;
+    const u32 chunks = (n + kThreads - 1) / kThreads;
     const u32 jo = logical % wo;
     u32 rest = logical / wo;
     const u32 set = rest % n_sets;
     rest /= n_sets;
     const u32 row = rest % (2 * nl);   // component * nl + limb
-    const u32 chunk = rest / (2 * nl);
-    const u32 t = chunk * kThreads + threadIdx.x;
-    if (t >= n) return;
+    const u32 chunk0 = (rest / (2 * nl)) * cpb;
     const u32 l = row % nl;
-    const u64 q = mq[l < nqx ? l : l + modoff].q, q2 = 2 * q;
-    const u32 a = term_off[jo], b = term_off[jo + 1];
+    const u64 q = mq[l < nk ? l : l == nk ? lvl : l + modoff].q, q2 = 2 * q;
+    const bool x_has = l <= nk;
+    const u32 xl = l < nk ? l : lvl;
+    const u32 a = term_off[jo], b = x_has ? term_off[jo + 1] : rot_end[jo];
     const u32 n_out = n_filters * wo;
-    const size_t tile = (size_t)row * n + t;
-    const bool x_has = l < nqx;
-    const size_t xtile = ((size_t)(row / nl) * nqx + (x_has ? l : 0)) * n + t;
     const u64* xb = x + (size_t)set * n_x * stride;
     const u64* rb = r + (size_t)set * n_x * rstride;
     const size_t fst = (size_t)w_fstride * nl;
@@ -197,11 +210,82 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
         // weights balanced, each product within 0.75 q, the sums reduced
         // every four terms (below 3.5 q < 2^53)
         const double qd = (double)q, qinv = 1.0 / qd;
+        for (u32 f0 = 0, g = 0; f0 < n_filters; f0 += kMaxFilters, g++) {
+            const u32 nf = min((u32)kMaxFilters, n_filters - f0);
+            const double* wg = wt + (size_t)(g * nl + l) * t_total * kMaxFilters;
+            u32 loaded = 0xffffffffu;   // first term of the chunk held in LDS
+            for (u32 cc = 0; cc < cpb && chunk0 + cc < chunks; cc++) {
+                const u32 t = (chunk0 + cc) * kThreads + threadIdx.x;
+                const bool active = t < n;
+                const size_t tile = (size_t)row * n + t;
+                const size_t xtile = ((size_t)(row / nl) * x_limbs + (x_has ? xl : 0)) * n + t;
+                double acc[kMaxFilters];
+#pragma unroll
+                for (int f = 0; f < kMaxFilters; f++) acc[f] = 0;
+                for (u32 c0 = a; c0 < b; c0 += kTermChunk) {
+                    const u32 ce = min(b, c0 + kTermChunk);
+                    if (c0 != loaded) {
+                        __syncthreads();   // readers of the previous chunk are done
+                        for (u32 i = threadIdx.x; i < (ce - c0) * kMaxFilters; i += kThreads)
+                            wl[i] = wg[(size_t)c0 * kMaxFilters + i];
+                        __syncthreads();
+                        loaded = c0;
+                    }
+                    for (u32 k0 = c0; k0 < ce; k0 += 8) {
+                        u64 xv[8];
+#pragma unroll
+                        for (int i = 0; i < 8; i++) {
+                            if (k0 + i < ce) {
+                                const Term tm = terms[k0 + i];
+                                const u32 u = tm.in_idx >> kTermColBits, j = tm.in_idx & kColMask;
+                                xv[i] = !active ? 0
+                                        : u == 0 ? xb[(size_t)j * stride + xtile]
+                                                 : rb[(u - 1) * ustride + (size_t)j * rstride + tile];
+                            }
+                        }
+#pragma unroll
+                        for (int i = 0; i < 8; i++) {
+                            if (k0 + i < ce) {
+                                const double xf = to_bal(xv[i], q, qd);
+                                const double* wk = wl + (k0 + i - c0) * kMaxFilters;
+#pragma unroll
+                                for (int f = 0; f < kMaxFilters; f++)
+                                    if (f < (int)nf) acc[f] += fmulmod(xf, wk[f], qd, qinv);
+                            }
+                            if ((i & 3) == 3) {
+#pragma unroll
+                                for (int f = 0; f < kMaxFilters; f++) acc[f] = fbal(acc[f], qd, qinv);
+                            }
+                        }
+                    }
+                }
+                if (!active) continue;
+#pragma unroll
+                for (int f = 0; f < kMaxFilters; f++) {
+                    if (f < (int)nf) {
+                        const u32 o = (f0 + f) * wo + jo;
+                        double v = acc[f];
+                        if (bias && row < nl) v += to_bal(bias[(size_t)o * nl + l], q, qd);
+                        out[(size_t)(set * n_out + o) * out_stride + tile] = to_canon(v, qd, qinv);
+                    }
+                }
+            }
+        }
+        return;
+    }
+    // integer path (limbs of 2^51 or more): no barrier, scalar weight loads
+    for (u32 cc = 0; cc < cpb && chunk0 + cc < chunks; cc++) {
+        const u32 t = (chunk0 + cc) * kThreads + threadIdx.x;
+        if (t >= n) break;
+        const size_t tile = (size_t)row * n + t;
+        const size_t xtile = ((size_t)(row / nl) * x_limbs + (x_has ? xl : 0)) * n + t;
         for (u32 f0 = 0; f0 < n_filters; f0 += kMaxFilters) {
             const u32 nf = min((u32)kMaxFilters, n_filters - f0);
-            double acc[kMaxFilters];
+            u64 acc[kMaxFilters];
 #pragma unroll
             for (int f = 0; f < kMaxFilters; f++) acc[f] = 0;
+            // eight terms at a time: their input words are loaded together so the
+            // loads overlap instead of each waiting on the previous one
             for (u32 k0 = a; k0 < b; k0 += 8) {
                 u64 xv[8];
                 u32 wrow[8];
@@ -210,28 +294,21 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
                     if (k0 + i < b) {
                         const Term tm = terms[k0 + i];
                         const u32 u = tm.in_idx >> kTermColBits, j = tm.in_idx & kColMask;
-                        if (u == 0)
-                            xv[i] = x_has ? xb[(size_t)j * stride + xtile] : 0;
-                        else
-                            xv[i] = rb[(u - 1) * ustride + (size_t)j * rstride + tile];
+                        xv[i] = u == 0 ? xb[(size_t)j * stride + xtile] : rb[(u - 1) * ustride + (size_t)j * rstride + tile];
                         wrow[i] = tm.w_idx;
                     }
                 }
 #pragma unroll
                 for (int i = 0; i < 8; i++) {
                     if (k0 + i < b) {
-                        const double xf = to_bal(xv[i], q, qd);
 #pragma unroll
                         for (int f = 0; f < kMaxFilters; f++) {
                             if (f < (int)nf) {
                                 const size_t wi = wrow[i] + (f0 + f) * fst + l;
-                                acc[f] += fmulmod(xf, wf[wi], qd, qinv);
+                                u64 v = acc[f] + shoup_lazy(xv[i], w[wi], ws[wi], q);
+                                acc[f] = v >= q2 ? v - q2 : v;
                             }
                         }
-                    }
-                    if ((i & 3) == 3) {
-#pragma unroll
-                        for (int f = 0; f < kMaxFilters; f++) acc[f] = fbal(acc[f], qd, qinv);
                     }
                 }
             }
@@ -239,59 +316,12 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
             for (int f = 0; f < kMaxFilters; f++) {
                 if (f < (int)nf) {
                     const u32 o = (f0 + f) * wo + jo;
-                    double v = acc[f];
-                    if (bias && row < nl) v += to_bal(bias[(size_t)o * nl + l], q, qd);
-                    out[(size_t)(set * n_out + o) * out_stride + (size_t)row * n + t] = to_canon(v, qd, qinv);
+                    u64 v = acc[f];
+                    if (bias && row < nl) v += bias[(size_t)o * nl + l];
+                    v = v >= q2 ? v - q2 : v;
+                    v = v >= q ? v - q : v;
+                    out[(size_t)(set * n_out + o) * out_stride + tile] = v;
                 }
-            }
-        }
-        return;
-    }
-    for (u32 f0 = 0; f0 < n_filters; f0 += kMaxFilters) {
-        const u32 nf = min((u32)kMaxFilters, n_filters - f0);
-        u64 acc[kMaxFilters];
-#pragma unroll
-        for (int f = 0; f < kMaxFilters; f++) acc[f] = 0;
-        // eight terms at a time: their input words are loaded together so the
-        // loads overlap instead of each waiting on the previous one
-        for (u32 k0 = a; k0 < b; k0 += 8) {
-            u64 xv[8];
-            u32 wrow[8];
-#pragma unroll
-            for (int i = 0; i < 8; i++) {
-                if (k0 + i < b) {
-                    const Term tm = terms[k0 + i];
-                    const u32 u = tm.in_idx >> kTermColBits, j = tm.in_idx & kColMask;
-                    if (u == 0)
-                        xv[i] = x_has ? xb[(size_t)j * stride + xtile] : 0;
-                    else
-                        xv[i] = rb[(u - 1) * ustride + (size_t)j * rstride + tile];
-                    wrow[i] = tm.w_idx;
-                }
-            }
-#pragma unroll
-            for (int i = 0; i < 8; i++) {
-                if (k0 + i < b) {
-#pragma unroll
-                    for (int f = 0; f < kMaxFilters; f++) {
-                        if (f < (int)nf) {
-                            const size_t wi = wrow[i] + (f0 + f) * fst + l;
-                            u64 v = acc[f] + shoup_lazy(xv[i], w[wi], ws[wi], q);
-                            acc[f] = v >= q2 ? v - q2 : v;
-                        }
-                    }
-                }
-            }
-        }
-#pragma unroll
-        for (int f = 0; f < kMaxFilters; f++) {
-            if (f < (int)nf) {
-                const u32 o = (f0 + f) * wo + jo;
-                u64 v = acc[f];
-                if (bias && row < nl) v += bias[(size_t)o * nl + l];
-                v = v >= q2 ? v - q2 : v;
-                v = v >= q ? v - q : v;
-                out[(size_t)(set * n_out + o) * out_stride + (size_t)row * n + t] = v;
             }
         }
     }
@@ -551,9 +581,10 @@ void rotate_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& in,
 // extended slab holding, per ciphertext, P times its rotation by steps[si]
 // (the key-switch sums of sigma_g(ModUp(c1)) with P sigma_g(c0) folded into
 // component 0's Q limbs by the inner-product kernel).  Steps must not be 0
-// mod the slot count.
+// mod the slot count.  keep > 0: only the limbs of a compact extended slab
+// (q_0..q_{keep-1}, q_level, the special primes) are made.
 void rotate_slab_ext(vr_context* ctx, const std::vector<KeyRange>& keys, const Slab& in,
-                     const std::vector<int32_t>& steps, std::vector<Slab>& out, hipStream_t s)
+                     const std::vector<int32_t>& steps, std::vector<Slab>& out, hipStream_t s, u32 keep)
 {
     const u32 level = in.level, n_ct = in.n;
     const size_t n = ctx->n;
@@ -573,7 +604,7 @@ void rotate_slab_ext(vr_context* ctx, const std::vector<KeyRange>& keys, const S
     u64* X = as_u64(xbuf);
     u64* coef = X + (size_t)cs * xs;
     out.clear();
-    Slab all = new_ext_slab(ctx, n_ct * (u32)steps.size(), level, in.scale, s);
+    Slab all = new_ext_slab(ctx, n_ct * (u32)steps.size(), level, in.scale, s, keep);
     for (size_t si = 0; si < steps.size(); si++) {
         Slab r = all;
         r.n = n_ct;
@@ -589,7 +620,7 @@ void rotate_slab_ext(vr_context* ctx, const std::vector<KeyRange>& keys, const S
                 if (lo >= hi) continue;
                 keyswitch_inner_batch(ctx, X + (size_t)(lo - c0) * xs, xs, in.ct(lo) + (size_t)k.nq * n, in.stride,
                                       hi - lo, rot_key(kr.ek, gs[si]).data, level, gs[si], out[si].ct(lo),
-                                      all.stride, s, in.ct(lo), in.stride);
+                                      all.stride, s, in.ct(lo), in.stride, keep);
             }
     }
 }
@@ -602,14 +633,15 @@ Slab mod_down_rescale_slab(vr_context* ctx, const Slab& in, hipStream_t s)
     const u32 level = in.level;
     if (level == 0) throw Error(VR_ELEVEL, "no limb left to rescale by");
     const size_t n = ctx->n;
-    Slab out = new_slab(ctx, in.n, 2, level - 1, in.scale / (double)ctx->mod[level], s);
+    const u32 no = in.keep ? in.keep : level;   // output limbs
+    Slab out = new_slab(ctx, in.n, 2, no - 1, in.scale / (double)ctx->mod[level], s);
     const u32 cs = switch_chunk(ctx, level, in.n);
     BufPtr md = dev_alloc(ctx, keyswitch_moddown_scratch(ctx, level, cs) * sizeof(u64), s);
     for (u32 c0 = 0; c0 < in.n; c0 += cs) {
         const u32 nc = std::min(cs, in.n - c0);
         u64* o = out.ct(c0);
-        keyswitch_moddown_rescale_batch(ctx, in.ct(c0), in.stride, nc, level, o, o + (size_t)level * n, out.stride,
-                                        nullptr, nullptr, 0, as_u64(md), s);
+        keyswitch_moddown_rescale_batch(ctx, in.ct(c0), in.stride, nc, level, o, o + (size_t)no * n, out.stride,
+                                        nullptr, nullptr, 0, as_u64(md), s, in.keep);
     }
     return out;
 }
@@ -934,8 +966,12 @@ struct ConvPlan {
     BufPtr buf;
     const Term* terms = nullptr;
     const u32* off = nullptr;
+    const u32* rot_end = nullptr;   // per column: first unrotated term
     const u64 *w = nullptr, *ws = nullptr, *bias = nullptr;
-    const double* wf = nullptr;   // the weights as balanced doubles (moduli below 2^51)
+    // balanced FP64 weights per filter group g, limb l and term t (global
+    // index), filter f: wt[((g nl + l) t_total + t) 8 + f] (moduli below 2^51)
+    const double* wt = nullptr;
+    u32 t_total = 0, max_col = 0;   // terms in all, most terms of one column
 };
 
 // P mod q (host)
@@ -953,14 +989,17 @@ u64 p_mod_h(vr_context* ctx, u64 q)
 // key-switch sums (w on every limb).
 const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const double* K,
                           const double* bias, u32 C_out, u32 k, u32 stride, u32 level, double out_scale,
-                          bool ext)
+                          bool ext, u32 keep)
 {
-    const u32 wo = (w + 2 * pad - k) / stride + 1, nq = level + 1, nl = ext ? nq + ctx->K : nq;
+    // limbs as k_lincomb maps them: q_0..q_{nk-1}, q_level, then the special
+    // primes when ext (nk = keep for a compact extended basis, else level)
+    const u32 wo = (w + 2 * pad - k) / stride + 1, nk = ext && keep ? keep : level;
+    const u32 nl = ext ? nk + 1 + ctx->K : level + 1;
     const size_t nw = (size_t)C_out * C_in * k * k;
     if ((size_t)C_in * w >= (1u << kTermColBits) || k >= 256 || nw * nl >= (1ull << 32))
         throw Error(VR_EINVAL, "conv layer too large: C_in * w must stay below 2^24, k below 256");
     std::string key = ext ? "convx:" : "conv:";
-    u32 shape[7] = {C_in, w, pad, C_out, k, stride, level};
+    u32 shape[8] = {C_in, w, pad, C_out, k, stride, level, ext ? keep : 0u};
     key.append((const char*)shape, sizeof shape);
     key.append((const char*)&out_scale, sizeof out_scale);
     key.append((const char*)K, nw * sizeof(double));
@@ -972,13 +1011,13 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
     const double dq = (double)ctx->mod[level];
     std::vector<u64> wv(nw * nl), wsv(nw * nl), bv((size_t)C_out * wo * nl);
     std::vector<double> wfv(nw * nl);
-    auto mod_of = [&](u32 l) { return l < nq ? l : ctx->L + 1 + (l - nq); };
+    auto mod_of = [&](u32 l) { return l < nk ? l : l == nk ? level : ctx->L + 1 + (l - nk - 1); };
     for (size_t r = 0; r < nw; r++)
         for (u32 l = 0; l < nl; l++) {
             const u64 q = ctx->mod[mod_of(l)];
             u64 v = double_to_mod(K[r] * dq, q);
             if (ext && (r / k) % k == 0)   // unrotated term: P w on Q limbs, none on P limbs
-                v = l < nq ? (u64)((u128)v * p_mod_h(ctx, q) % q) : 0;
+                v = l <= nk ? (u64)((u128)v * p_mod_h(ctx, q) % q) : 0;
             wv[r * nl + l] = v;
             wsv[r * nl + l] = shoup_companion(v, q);
             wfv[r * nl + l] = v > q / 2 ? -(double)(q - v) : (double)v;
@@ -986,27 +1025,50 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
     for (u32 co = 0; co < C_out; co++)
         for (u32 l = 0; l < nl; l++) {
             const u64 q = ctx->mod[mod_of(l)];
-            u64 b = l < nq ? double_to_mod(bias[co] * out_scale, q) : 0;
-            if (ext && l < nq) b = (u64)((u128)b * p_mod_h(ctx, q) % q);
+            u64 b = l <= nk ? double_to_mod(bias[co] * out_scale, q) : 0;
+            if (ext && l <= nk) b = (u64)((u128)b * p_mod_h(ctx, q) % q);
             for (u32 jo = 0; jo < wo; jo++) bv[((size_t)co * wo + jo) * nl + l] = b;
         }
     // one term list per output column, weight rows of filter 0 (filter c'
-    // adds c' * C_in * k * k)
+    // adds c' * C_in * k * k): the rotated terms (u >= 1) first, the
+    // unrotated ones from rot_end[jo]
     std::vector<Term> terms;
-    std::vector<u32> off(1, 0);
+    std::vector<u32> off(1, 0), rot_end;
     for (u32 jo = 0; jo < wo; jo++) {
-        for (u32 c = 0; c < C_in; c++)
-            for (u32 v = 0; v < k; v++) {
-                int jj = (int)(stride * jo + v) - (int)pad;
-                if (jj < 0 || jj >= (int)w) continue;
-                for (u32 u = 0; u < k; u++)
-                    terms.push_back({(u32)(((size_t)u << kTermColBits) | ((size_t)c * w + jj)),
-                                     (u32)((((size_t)c * k + u) * k + v) * nl)});
-            }
+        for (int pass = 0; pass < 2; pass++) {
+            if (pass == 1) rot_end.push_back((u32)terms.size());
+            for (u32 c = 0; c < C_in; c++)
+                for (u32 v = 0; v < k; v++) {
+                    int jj = (int)(stride * jo + v) - (int)pad;
+                    if (jj < 0 || jj >= (int)w) continue;
+                    for (u32 u = pass ? 0 : 1; u < (pass ? 1 : k); u++)
+                        terms.push_back({(u32)(((size_t)u << kTermColBits) | ((size_t)c * w + jj)),
+                                         (u32)((((size_t)c * k + u) * k + v) * nl)});
+                }
+        }
         off.push_back((u32)terms.size());
     }
-    // one device buffer: terms | off | w | ws | bias | wf (8-byte aligned parts)
+    // the FP64 weights as contiguous [term][filter] runs per group and limb
+    const u32 groups = (C_out + kMaxFilters - 1) / kMaxFilters, t_total = (u32)terms.size();
+    const size_t fst = (size_t)C_in * k * k * nl;
+    std::vector<double> wtv((size_t)groups * nl * t_total * kMaxFilters, 0.0);
+    for (u32 g = 0; g < groups; g++)
+        for (u32 l = 0; l < nl; l++)
+            for (u32 t = 0; t < t_total; t++)
+                for (u32 f = 0; f < kMaxFilters; f++) {
+                    const u32 co = g * kMaxFilters + f;
+                    if (co < C_out)
+                        wtv[(((size_t)g * nl + l) * t_total + t) * kMaxFilters + f] =
+                            wfv[terms[t].w_idx + co * fst + l];
+                }
+    u32 max_col = 0;
+    for (u32 jo = 0; jo < wo; jo++) max_col = std::max(max_col, off[jo + 1] - off[jo]);
+    wfv.swap(wtv);
+    // one device buffer: terms | off | rot_end | w | ws | bias | wt (8-byte
+    // aligned parts)
     size_t b_terms = terms.size() * sizeof(Term), b_off = ((off.size() * 4 + 7) / 8) * 8;
+    size_t b_rot = ((rot_end.size() * 4 + 7) / 8) * 8;
+    b_off += b_rot;
     size_t total = b_terms + b_off + (wv.size() + wsv.size() + bv.size() + wfv.size()) * 8;
     auto plan = std::make_shared<ConvPlan>();
     VR_HIP(hipDeviceSynchronize());
@@ -1015,6 +1077,7 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
     std::vector<char> h(total, 0);
     memcpy(h.data(), terms.data(), b_terms);
     memcpy(h.data() + b_terms, off.data(), off.size() * 4);
+    memcpy(h.data() + b_terms + (b_off - b_rot), rot_end.data(), rot_end.size() * 4);
     size_t o = b_terms + b_off;
     memcpy(h.data() + o, wv.data(), wv.size() * 8);
     memcpy(h.data() + o + wv.size() * 8, wsv.data(), wsv.size() * 8);
@@ -1023,10 +1086,13 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
     VR_HIP(hipMemcpy(base, h.data(), total, hipMemcpyHostToDevice));
     plan->terms = (const Term*)base;
     plan->off = (const u32*)(base + b_terms);
+    plan->rot_end = (const u32*)(base + b_terms + (b_off - b_rot));
     plan->w = (const u64*)(base + o);
     plan->ws = plan->w + wv.size();
     plan->bias = plan->ws + wsv.size();
-    plan->wf = (const double*)(plan->bias + bv.size());
+    plan->wt = (const double*)(plan->bias + bv.size());
+    plan->t_total = t_total;
+    plan->max_col = max_col;
     ctx->plans[key] = plan;
     return *plan;
 }
@@ -1149,19 +1215,24 @@ vr_ciphertext** encrypt_slots_batch(vr_context* ctx, const vr_eval_keys* ek,
 struct ConvRot {
     std::vector<Slab> rot;
     bool ext = false;
+    u32 keep = 0;
 };
 
 bool conv_lazy(vr_context* ctx, u32 k, u32 level) { return k > 1 && ctx->K <= level + 1; }
 
-ConvRot conv_rotations(vr_context* ctx, const std::vector<KeyRange>& keys, const Slab& x, u32 k, hipStream_t s)
+// keep > 0 (lazy form only): the sums and the ModDown make output limbs
+// q_0..q_{keep-1} alone (a consumer that reads no others)
+ConvRot conv_rotations(vr_context* ctx, const std::vector<KeyRange>& keys, const Slab& x, u32 k, hipStream_t s,
+                       u32 keep)
 {
     ConvRot cr;
     std::vector<int32_t> steps;
     for (u32 u = 1; u < k; u++) steps.push_back((int32_t)u);
     if (steps.empty()) return cr;
     cr.ext = conv_lazy(ctx, k, x.level);
+    cr.keep = cr.ext ? keep : 0;
     if (cr.ext)
-        rotate_slab_ext(ctx, keys, x, steps, cr.rot, s);
+        rotate_slab_ext(ctx, keys, x, steps, cr.rot, s, cr.keep);
     else
         rotate_slab_keyed(ctx, keys, x, steps, cr.rot, s);
     return cr;
@@ -1177,17 +1248,23 @@ void conv_lincomb_into(vr_context* ctx, const Slab& out, u32 out_at, const Slab&
     const u32 level = x.level, nq = level + 1;
     const u32 wo = (w + 2 * pad - k) / stride + 1, n_out = C_out * wo;
     const double out_scale = x.scale * (double)ctx->mod[level];
-    const ConvPlan& plan = conv_plan(ctx, C_in, w, pad, K, bias, C_out, k, stride, level, out_scale, cr.ext);
-    const u32 nl = cr.ext ? nq + ctx->K : nq;
+    const ConvPlan& plan = conv_plan(ctx, C_in, w, pad, K, bias, C_out, k, stride, level, out_scale, cr.ext,
+                                     cr.keep);
+    const u32 nk = cr.keep ? cr.keep : level;
+    const u32 nl = cr.ext ? nk + 1 + ctx->K : nq;
     const Slab& r = cr.rot.empty() ? x : cr.rot[0];
+    // cpb 256-coefficient chunks per block share one copy of its weights
     const u32 chunks = (ctx->n + kThreads - 1) / kThreads;
-    const u32 total = chunks * 2 * nl * n_sets * wo;
+    const u32 cpb = chunks >= 16 ? 4 : 1;
+    const u32 total = ((chunks + cpb - 1) / cpb) * 2 * nl * n_sets * wo;
     const u32 per_xcd = (total + 7) / 8;
+    const size_t shmem = (size_t)std::min(plan.max_col, kTermChunk) * kMaxFilters * sizeof(double);
     ProfScope prof(ctx, kProfLincomb, s, (u64)n_sets * n_out * 2 * nl);
-    hipLaunchKernelGGL(k_lincomb, dim3(8 * per_xcd), dim3(kThreads), 0, s, out.ct(out_at), out.stride, x.ct(x_at),
+    hipLaunchKernelGGL(k_lincomb, dim3(8 * per_xcd), dim3(kThreads), shmem, s, out.ct(out_at), out.stride, x.ct(x_at),
                        cr.rot.empty() ? x.ct(x_at) : r.ct(r_at), C_in * w, n_sets, x.stride, r.stride,
-                       (u64)r.n * r.stride, plan.terms, plan.off, plan.w, plan.ws, plan.wf, C_in * k * k,
-                       plan.bias, nl, nq, ctx->L + 1 - nq, ctx->log_n, ctx->d_modq, wo, C_out, total, per_xcd);
+                       (u64)r.n * r.stride, plan.terms, plan.off, plan.rot_end, plan.w, plan.ws, plan.wt,
+                       plan.t_total, C_in * k * k, plan.bias, nl, nk, level, ctx->L - nk, nq, ctx->log_n,
+                       ctx->d_modq, wo, C_out, total, per_xcd, cpb);
     VR_CHECK_LAUNCH();
 }
 
@@ -1204,7 +1281,7 @@ Slab conv_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& x, u32 n_set
     if (x.level < 1) throw Error(VR_ELEVEL, "conv needs a level to rescale");
     const u32 wo = (w + 2 * pad - k) / stride + 1;
     const u32 level = x.level;
-    ConvRot cr = conv_rotations(ctx, {KeyRange{0, x.n, ek}}, x, k, s);
+    ConvRot cr = conv_rotations(ctx, {KeyRange{0, x.n, ek}}, x, k, s, 0);
     const double out_scale = x.scale * (double)ctx->mod[level];
     const u32 n_out = C_out * wo;
     Slab acc = cr.ext ? new_ext_slab(ctx, n_sets * n_out, level, out_scale, s)
@@ -1417,7 +1494,7 @@ Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab&
     }
     if (x.n != n_in || x.ncomp != 2) throw Error(VR_EINVAL, "wave input slab does not match its segments");
     if (x.level < 1) throw Error(VR_ELEVEL, "conv needs a level to rescale");
-    const u32 level = x.level, nl = level + 1;
+    const u32 level = x.level;
     // conv: rotations of every input column by 1..k-1 under each session's keys
     std::vector<KeyRange> kin;
     u32 at = 0;
@@ -1425,11 +1502,25 @@ Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab&
         kin.push_back(KeyRange{at, at + g.n_sets * g.d->n_in(), g.ek});
         at = kin.back().end;
     }
-    ConvRot cr = conv_rotations(ctx, kin, x, d0.k, s);
     const double out_scale = x.scale * (double)ctx->mod[level];
+    // x^2 and FC fused: the squares' tensors meet the FC weights
+    // unrelinearised, on the FC level's limbs only; the conv then makes just
+    // those limbs of its outputs (they are all the FC reads)
+    const double y_scale = out_scale / (double)ctx->mod[level];
+    const u32 fl0 = std::min(level - 1, d0.fc_level);
+    const bool lazy_fc = d0.square && d0.fc_out && square_fc_lazy(ctx, y_scale, d0.fc_scale, fl0);
+    bool prune = true;
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->tuning.find("conv_prune");
+        if (it != ctx->tuning.end()) prune = it->second == 0;
+    }
+    const u32 keep = lazy_fc && prune && fl0 + 1 < level ? fl0 + 1 : 0;
+    ConvRot cr = conv_rotations(ctx, kin, x, d0.k, s, keep);
     u32 n_conv = 0;
     for (const NetSeg& g : segs) n_conv += g.n_sets * g.d->C_out * g.d->w_out();
-    Slab acc = cr.ext ? new_ext_slab(ctx, n_conv, level, out_scale, s) : new_slab(ctx, n_conv, 2, level, out_scale, s);
+    Slab acc = cr.ext ? new_ext_slab(ctx, n_conv, level, out_scale, s, cr.keep)
+                      : new_slab(ctx, n_conv, 2, level, out_scale, s);
     // the linear combination per network, on its own inputs and rotations
     std::vector<KeyRange> kout;
     u32 in_at = 0, out_at = 0;
@@ -1445,9 +1536,8 @@ Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab&
     cr.rot.clear();
     Slab y = cr.ext ? mod_down_rescale_slab(ctx, acc, s) : rescale_slab(ctx, acc, s);
     acc = Slab();
-    // x^2 and FC fused: the squares' tensors meet the FC weights unrelinearised
-    const bool lazy_fc = d0.square && d0.fc_out &&
-                         square_fc_lazy(ctx, y.scale, d0.fc_scale, std::min(y.level, d0.fc_level));
+    if (y.scale != y_scale) throw Error(VR_EINVAL, "conv output scale differs from its prediction");
+    if (cr.keep && y.level != fl0) throw Error(VR_EINVAL, "pruned conv output at the wrong level");
     if (d0.square && !lazy_fc) {
         // tensor of everything, relinearisation per session, one rescale
         Slab T = new_slab(ctx, y.n, 3, y.level, y.scale * y.scale, s);

@@ -67,6 +67,7 @@ __device__ __forceinline__ void limb_addr(const LimbSet& ls, u32 r, u32 n, u32 L
     }
     u32 slot = ls.slot0 + (l < skip_at ? l : l + skip_len);
     *mod = ((int)slot <= ls.level) ? slot : (u32)((int)L + 1 + (int)slot - ls.level - 1);
+    if (slot == ls.remap_slot) *mod = ls.remap_mod;
     size_t off = (size_t)poly * ls.poly_stride + (size_t)slot * n;
     *in = ls.in + off;
     *out = ls.out_dense ? ls.out + (size_t)r * n : ls.out + off;

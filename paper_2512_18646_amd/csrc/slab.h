@@ -11,14 +11,16 @@ struct Slab {
     u64* base = nullptr;
     u32 n = 0, ncomp = 2, level = 0;
     u32 ext = 0;      // 1: P times 2-component ciphertexts over q_0..q_level, p_0..p_{K-1}
+    u32 keep = 0;     // ext with keep > 0: only q_0..q_{keep-1}, q_level, p_0..p_{K-1}
     u64 stride = 0;   // words between ciphertexts
     double scale = 1.0;
     u64* ct(u32 i) const { return base + (size_t)i * stride; }
 };
 
 Slab new_slab(vr_context* ctx, u32 n, u32 ncomp, u32 level, double scale, hipStream_t s);
-// n ciphertexts in the extended basis (level + 1 + K limbs per component)
-Slab new_ext_slab(vr_context* ctx, u32 n, u32 level, double scale, hipStream_t s);
+// n ciphertexts in the extended basis (level + 1 + K limbs per component, or
+// keep + 1 + K with keep > 0: q_0..q_{keep-1}, q_level, the special primes)
+Slab new_ext_slab(vr_context* ctx, u32 n, u32 level, double scale, hipStream_t s, u32 keep = 0);
 // the ciphertexts in place when they already form a slab, else a copy
 Slab gather(vr_context* ctx, const vr_ciphertext* const* cts, u32 n, hipStream_t s);
 // new handles viewing the slab's ciphertexts (they share its allocation)

@@ -325,7 +325,7 @@ struct vr_context {
     vr::u64 cdt[20];
     std::map<std::pair<int, int>, vr::ConvTable> modup_tables;   // (level, digit)
     std::map<int, vr::ConvTable> moddown_tables;                 // level
-    std::map<int, vr::ConvTable> moddown_rs_tables;              // level: {q_l, P} -> q_<l
+    std::map<int, vr::ConvTable> moddown_rs_tables;              // level * 1024 + nk: {q_l, P} -> q_<nk
     // device-resident constants of layer calls (weights, term lists), keyed by
     // the call's shape and weight bytes, so repeated calls upload nothing
     std::map<std::string, std::shared_ptr<void>> plans;
@@ -462,6 +462,9 @@ struct LimbSet {
     u32 skip_at = 0xffffffffu, skip_len = 0;
     u32 digit_skip = 0, alpha = 0, beta = 0, nq = 0;
     u32 out_dense = 0;
+    // slot remap_slot takes modulus remap_mod instead (a compact extended
+    // layout that holds q_level right after the kept low limbs)
+    u32 remap_slot = 0xffffffffu, remap_mod = 0;
     // forward only: the first pass reads, instead of each limb, the one-limb
     // source it is the fast base conversion of (digits of one modulus): poly
     // p takes limb cv_src + (p / cv_beta) * cv_ct_stride + (p % cv_beta) * N,

@@ -70,10 +70,14 @@ void keyswitch_inner(vr_context* ctx, const u64* X, const u64* d, const u64* key
 // Batched inner product: n_ct digit sets X + c*x_stride (ModUp inputs
 // d + c*d_stride) share one key read.  With fold_c0 (ciphertext c's c0 at
 // fold_c0 + c*fold_stride, level limbs) the Q limbs of U_0 also take
-// P sigma_g(c0): U is then P times the rotation before its ModDown.
+// P sigma_g(c0): U is then P times the rotation before its ModDown.  With
+// keep_q > 0 only the limbs q_0..q_{keep_q-1}, q_level and the special primes
+// are computed, and U holds them compactly in that order ([2][keep_q+1+K][N]
+// per ciphertext).
 void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u64* d, u64 d_stride,
                            u32 n_ct, const u64* key, u32 level, u32 g, u64* U, u64 u_stride,
-                           hipStream_t s, const u64* fold_c0 = nullptr, u64 fold_stride = 0);
+                           hipStream_t s, const u64* fold_c0 = nullptr, u64 fold_stride = 0,
+                           u32 keep_q = 0);
 // ModDown of U ([2][next][N]) to out0/out1 (nq limbs each, may be strided),
 // adding add0 (optionally through sigma_g) and add1 when non-null.
 void keyswitch_moddown(vr_context* ctx, u64* U, u32 level, u64* out0, u64* out1, const u64* add0,
@@ -87,9 +91,12 @@ void keyswitch_moddown_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u3
 // with c0/c1 (the ciphertext's first two components, level l, c_stride apart
 // per ciphertext) folded in (both null: U is taken as it is); out0/out1 get
 // l limbs (level l - 1).  Scratch as keyswitch_moddown_scratch(level, n_ct).
+// keep_q > 0: U is the compact layout of keyswitch_inner_batch's keep_q and
+// only output limbs 0..keep_q-1 are made (level keep_q - 1).
 void keyswitch_moddown_rescale_batch(vr_context* ctx, u64* U, u64 u_stride, u32 n_ct, u32 level,
                                      u64* out0, u64* out1, u64 out_stride, const u64* c0,
-                                     const u64* c1, u64 c_stride, u64* scratch, hipStream_t s);
+                                     const u64* c1, u64 c_stride, u64* scratch, hipStream_t s,
+                                     u32 keep_q = 0);
 // scratch sizes in u64 words
 size_t keyswitch_modup_scratch(vr_context* ctx, u32 level);     // X + coef
 size_t keyswitch_moddown_scratch(vr_context* ctx, u32 level, u32 n_ct);

@@ -88,17 +88,19 @@ def test_graph_replays_match_eager(net):
     g2.close()
 
 
-@pytest.mark.parametrize("fc_level", [3, 1])
-def test_network_square_fc_lazy_relinearisation(fc_level):
+@pytest.mark.parametrize("fc_level,lv", [(3, 5), (1, 5), (3, 7)])
+def test_network_square_fc_lazy_relinearisation(fc_level, lv):
     """FC weights at a level with room for the unrelinearised products (3):
     the network call fuses x^2 into the FC, one relinearisation per output,
     limb for limb the oracle's square_fc after its (lazy) conv, also as a
-    replayed graph; at level 1 it keeps the per-layer form.  Both decode to
-    the FP64 network."""
+    replayed graph; the conv then makes only the FC level's limbs of its
+    outputs (entering at 7, 4 of the 7 limbs), identical to making every
+    limb and dropping them after (conv_prune off); at level 1 the network
+    keeps the per-layer form.  All decode to the FP64 network."""
     from paper_2512_18646_amd import vr
     from tests.gpu_helpers import to_gpu, assert_same
     o, ok, g, gk = pair("C2", rot_steps=(1, 2, 4, 8), log_n=10)
-    B, Ci, h, w, Co, k, s, pad, lv = 4, 2, 10, 9, 3, 3, 2, 1, 5
+    B, Ci, h, w, Co, k, s, pad = 4, 2, 10, 9, 3, 3, 2, 1
     rng = np.random.default_rng(52)
     X = rng.uniform(0, 1, (B, Ci, h, w))
     K = rng.normal(0, 0.1, (Co, Ci, k, k))
@@ -122,7 +124,14 @@ def test_network_square_fc_lazy_relinearisation(fc_level):
     gcts = [to_gpu(g, c) for c in cts]
     out = net.forward(g, gk, gcts, n_sets=1)
     for i, (a, b) in enumerate(zip(out, Z)):
-        assert_same(a, b, "network output %d (fc level %d)" % (i, fc_level))
+        assert_same(a, b, "network output %d (fc level %d, entering at %d)" % (i, fc_level, lv))
+    g.set_tuning("conv_prune", "off")
+    try:
+        full = net.forward(g, gk, gcts, n_sets=1)
+    finally:
+        g.set_tuning("conv_prune", "on")
+    for i, (a, b) in enumerate(zip(full, Z)):
+        assert_same(a, b, "network output %d, every conv limb" % i)
     gr = vr.Graph(g, gk, net, gcts, n_sets=1)
     for rep in range(2):
         gr.launch()

@@ -7,7 +7,7 @@ import pytest
 
 import synthetic_inputs as SI
 from oracle import layers as Ly
-from oracle import Params, Context as OracleContext
+from oracle import Params, PRESETS, Context as OracleContext
 from tests.gpu_helpers import pair, to_gpu, assert_same, gpu_ctx, SEED_KEYS
 
 pytestmark = pytest.mark.gpu
@@ -378,6 +378,41 @@ def test_cnn128_full_level_chunked_key_switching():
         for b in range(W.batch):
             got[b, i] = z[b * Hp + W.stride * np.arange(got.shape[2])]
     assert Ly.rel_error(got, ref[:, [0, 7]][:, :, :, 9]) < EPS
+
+
+def test_cnn128_network_level24_pruned_equals_full():
+    """The headline network (3x128x128, conv 3x3/2 pad 1 x8, x^2, FC 32768 ->
+    10 with its weights at level 3) entering at level 24: the network call,
+    whose conv makes only the 4 limbs the FC reads, gives the same words as
+    with every conv limb made and dropped after (conv_prune off), and its
+    logits decode to the FP64 network."""
+    from paper_2512_18646_amd import vr
+    W = SI.CNN_128
+    Hp = Ly.image_block(W.h, W.pad)
+    steps = sorted(set(range(1, W.k)) | {1 << t for t in range(Hp.bit_length() - 1)})
+    g = gpu_ctx(PRESETS["C3"])
+    gk = g.keygen(1003, rot_steps=steps)
+    X, K, bias = W.draw()
+    Wfc, bfc = W.draw_fc()
+    cols = g.encrypt_columns(gk, X, W.pad, 24, 3005, 0)
+    pts = g.encode_fc_weights(Wfc, W.stride, Hp, 3)
+    net = vr.CNN(W.channels, W.h, W.w, W.pad, K, bias, W.stride, square=True, fc_w=pts, fc_bias=bfc,
+                 fc_block=Hp)
+    out = net.forward(g, gk, cols)
+    g.set_tuning("conv_prune", "off")
+    try:
+        full = net.forward(g, gk, cols)
+    finally:
+        g.set_tuning("conv_prune", "on")
+    assert len(out) == len(full) == W.fc_out
+    for i, (a, b) in enumerate(zip(out, full)):
+        assert a.meta == b.meta and a.meta[1] == 1, i
+        assert np.array_equal(a.export(), b.export()), "logit ciphertext %d" % i
+    logits = np.zeros((W.batch, W.fc_out))
+    for oi, z in enumerate(out):
+        logits[:, oi] = g.decode(g.decrypt(gk, z))[np.arange(W.batch) * Hp]
+    ref = Ly.ref_fc(Ly.ref_conv(X, K, bias, W.stride, W.pad) ** 2, Wfc, bfc)
+    assert Ly.rel_error(logits, ref) < EPS
 
 
 def test_matmul_block_bit_exact_and_planner(c1mm):
