@@ -202,6 +202,11 @@ vr_status vr_context_tuning_report(vr_context* ctx, char* buf, size_t cap)
         r += "modup l" + std::to_string(kv.first.first) + " d" + std::to_string(kv.first.second) + " " +
              std::to_string(kv.second.n_in) + "->" + std::to_string(kv.second.n_out) + ": " +
              name(kv.second.choice ? kv.second.choice->load() : -1) + "\n";
+    for (auto& kv : ctx->modup_range_tables)
+        r += "modup l" + std::to_string(kv.first[0]) + " d" + std::to_string(kv.first[1]) + " [" +
+             std::to_string(kv.first[2]) + "," + std::to_string(kv.first[3]) + ") " +
+             std::to_string(kv.second.n_in) + "->" + std::to_string(kv.second.n_out) + ": " +
+             name(kv.second.choice ? kv.second.choice->load() : -1) + "\n";
     for (auto& kv : ctx->moddown_tables)
         r += "moddown l" + std::to_string(kv.first) + " " + std::to_string(kv.second.n_in) + "->" +
              std::to_string(kv.second.n_out) + ": " +

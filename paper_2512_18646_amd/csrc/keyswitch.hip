@@ -591,6 +591,20 @@ const ConvTable& modup_table(vr_context* ctx, u32 level, u32 j)
     return ctx->modup_tables[key] = build_table(ctx, in, out);
 }
 
+// digit j of `level` to the extended limbs [e0, e1) (none of them its own)
+const ConvTable& modup_range_table(vr_context* ctx, u32 level, u32 j, u32 e0, u32 e1)
+{
+    std::lock_guard<std::mutex> g(ctx->mu);
+    const std::array<int, 4> key{(int)level, (int)j, (int)e0, (int)e1};
+    auto it = ctx->modup_range_tables.find(key);
+    if (it != ctx->modup_range_tables.end()) return it->second;
+    u32 lo = j * ctx->alpha, hi = std::min((j + 1) * ctx->alpha, level + 1);
+    std::vector<u32> in, out;
+    for (u32 i = lo; i < hi; i++) in.push_back(i);
+    for (u32 e = e0; e < e1; e++) out.push_back(ctx->ext_mod(e, level));
+    return ctx->modup_range_tables[key] = build_table(ctx, in, out);
+}
+
 const ConvTable& moddown_table(vr_context* ctx, u32 level)
 {
     std::lock_guard<std::mutex> g(ctx->mu);
@@ -749,7 +763,7 @@ size_t keyswitch_moddown_scratch(vr_context* ctx, u32 level, u32 n_ct)
 // d_c = d + c * d_stride: [nq][N] evaluation domain, c < n_ct.
 // X_c = X + c * beta * next * N: [beta][next][N].  coef: [n_ct][nq][N] scratch.
 void keyswitch_modup_batch(vr_context* ctx, const u64* d, u64 d_stride, u32 n_ct, u32 level,
-                           u64* X, u64* coef, hipStream_t s)
+                           u64* X, u64* coef, hipStream_t s, u32 keep_q)
 {
     KsShape k = ks_shape(ctx, level);
     const u32 n = ctx->n;
@@ -758,6 +772,40 @@ void keyswitch_modup_batch(vr_context* ctx, const u64* d, u64 d_stride, u32 n_ct
     LimbSet ls = poly_limbs(const_cast<u64*>(d), coef, n_ct, k.nq, d_stride, (int)level);
     ls.out_dense = 1;
     ntt_inverse(ctx, ls, s);
+    if (keep_q && ctx->alpha > 1) {
+        // only the extended limbs the inner product will read, q_0..q_{keep-1},
+        // q_level and the special primes, outside each digit's own limbs: per
+        // digit at most three runs, each converted and transformed on its own
+        if (keep_q > level) throw Error(VR_EINVAL, "ModUp: kept limbs above the level");
+        for (u32 j = 0; j < k.beta; j++) {
+            const u32 lo = j * ctx->alpha, hi = std::min((j + 1) * ctx->alpha, k.nq);
+            std::vector<std::pair<u32, u32>> runs;
+            if (std::min(keep_q, lo) > 0) runs.push_back({0, std::min(keep_q, lo)});
+            if (hi < keep_q) runs.push_back({hi, keep_q});
+            runs.push_back({std::max(level, hi), k.next});
+            for (const auto& r : runs) {
+                const ConvTable& tb = modup_range_table(ctx, level, j, r.first, r.second);
+                ConvArgs a;
+                a.in = coef + (size_t)lo * n;
+                a.in_stride = (u64)k.nq * n;
+                a.out = X + ((size_t)j * k.next + r.first) * n;
+                a.out_stride = xs;
+                a.skip_at = 0xffffffffu;
+                a.skip_len = 0;
+                a.tab = tb.dev;
+                a.n_in = tb.n_in;
+                a.n_out = tb.n_out;
+                a.log_n = ctx->log_n;
+                a.mq = ctx->d_modq;
+                launch_convert(ctx, a, tb, n_ct, s);
+                LimbSet t = poly_limbs(X + (size_t)j * k.next * n, X + (size_t)j * k.next * n, n_ct,
+                                       r.second - r.first, xs, (int)level);
+                t.slot0 = r.first;
+                ntt_forward(ctx, t, s);
+            }
+        }
+        return;
+    }
     // one-limb digits: the conversion is a centred reduction, done by the
     // NTT as it loads each limb (below); wider digits convert first
     const bool fused = ctx->alpha == 1;

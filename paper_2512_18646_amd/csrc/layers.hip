@@ -613,7 +613,7 @@ void rotate_slab_ext(vr_context* ctx, const std::vector<KeyRange>& keys, const S
     }
     for (u32 c0 = 0; c0 < n_ct; c0 += cs) {
         const u32 nc = std::min(cs, n_ct - c0);
-        keyswitch_modup_batch(ctx, in.ct(c0) + (size_t)k.nq * n, in.stride, nc, level, X, coef, s);
+        keyswitch_modup_batch(ctx, in.ct(c0) + (size_t)k.nq * n, in.stride, nc, level, X, coef, s, keep);
         for (size_t si = 0; si < steps.size(); si++)
             for (const KeyRange& kr : keys) {
                 const u32 lo = std::max(kr.begin, c0), hi = std::min(kr.end, c0 + nc);

@@ -266,6 +266,8 @@ void destroy_context_tables(vr_context* ctx)
     (void)hipFree(ctx->d_gexp);
     for (auto& kv : ctx->modup_tables)
         (void)hipFree(kv.second.dev), (void)hipFree(kv.second.wt), (void)hipFree(kv.second.wf);
+    for (auto& kv : ctx->modup_range_tables)
+        (void)hipFree(kv.second.dev), (void)hipFree(kv.second.wt), (void)hipFree(kv.second.wf);
     for (auto& kv : ctx->moddown_tables)
         (void)hipFree(kv.second.dev), (void)hipFree(kv.second.wt), (void)hipFree(kv.second.wf);
     for (auto& kv : ctx->moddown_rs_tables)

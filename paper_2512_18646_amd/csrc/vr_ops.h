@@ -61,8 +61,11 @@ KsShape ks_shape(vr_context* ctx, u32 level);
 void keyswitch_modup(vr_context* ctx, const u64* d, u32 level, u64* X, u64* coef, hipStream_t s);
 // Batched ModUp: d_c = d + c*d_stride (c < n_ct), X_c = X + c*beta*next*N,
 // coef: [n_ct][nq][N] scratch.
+// keep_q > 0 (digits of more than one limb): only the extended limbs
+// q_0..q_{keep_q-1}, q_level and the special primes of X are made (the ones a
+// keep_q inner product reads); the rest of X is left as it was.
 void keyswitch_modup_batch(vr_context* ctx, const u64* d, u64 d_stride, u32 n_ct, u32 level,
-                           u64* X, u64* coef, hipStream_t s);
+                           u64* X, u64* coef, hipStream_t s, u32 keep_q = 0);
 // U = [2][next][N]: sum_j sigma_g(X_j) * (b_j, a_j) (g = 1: no automorphism);
 // d is the ModUp input (the digits' own limbs).
 void keyswitch_inner(vr_context* ctx, const u64* X, const u64* d, const u64* key, u32 level, u32 g,
