@@ -487,7 +487,10 @@ def serving_n16_bench(vr, level=3, n_sessions=8, n_warm=20, n_meas=100, loads=(0
         hp = 1 << (side + 1).bit_length()
         wo = (side + 2 - 3) // 2 + 1
         Wfc, bfc = SI.fc_weights(seed + 7 * side, 10, 8, wo, wo, 0.05)
-        pts = ctx.encode_fc_weights(Wfc, 2, hp, 1)      # the FC runs at level 1
+        # the FC runs at level 1, or at level 3 when the requests enter high
+        # enough: x^2 then goes into it unrelinearised (one key switch per FC
+        # output) and the conv makes only the FC's limbs
+        pts = ctx.encode_fc_weights(Wfc, 2, hp, 3 if level >= 4 else 1)
         net = vr.CNN(ch, side, side, 1, K, bias, 2, square=True, fc_w=pts, fc_bias=bfc, fc_block=hp)
         bmax = ctx.slots // hp
         cols = [ctx.encrypt_columns(keys, SI.images(seed + 31 * i + side, bmax, ch, side, side), 1, level,
