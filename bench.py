@@ -19,6 +19,7 @@ dominant kernel (HIP events around its launches inside the timed region) and
 the CPU oracle timed on a bounded sample on one and on all host cores.
 """
 import argparse
+import collections
 import json
 import os
 import sys
@@ -510,11 +511,13 @@ def serving_n16_bench(vr, level=3, n_sessions=8, n_warm=20, n_meas=100, loads=(0
         k = kinds[ki]
         return ki, si, int(rng.integers(1, k["bmax"] + 1))
 
-    def run(n, rate):
-        tickets = []
+    def run(n, rate, tag=None):
+        # results are collected once 256 newer requests are in flight, so a
+        # long run holds a bounded number of outputs
+        pending = collections.deque()
         t0 = time.perf_counter()
         due = t0
-        for _ in range(n):
+        for i in range(n):
             ki, si, b = draw_request()
             if rate:
                 due += rng.exponential(1.0 / rate)
@@ -522,8 +525,14 @@ def serving_n16_bench(vr, level=3, n_sessions=8, n_warm=20, n_meas=100, loads=(0
                 if delay > 0:
                     time.sleep(delay)
             k = kinds[ki]
-            tickets.append((srv.submit(sids[si], k["mid"], k["cols"][si], b), k["mid"]))
-        for t, mid in tickets:
+            pending.append((srv.submit(sids[si], k["mid"], k["cols"][si], b), k["mid"]))
+            while len(pending) > 256:
+                t, mid = pending.popleft()
+                srv.poll(t, mid)
+            if tag and (i + 1) % 500 == 0:
+                log("%s: %d of %d requests submitted" % (tag, i + 1, n))
+        while pending:
+            t, mid = pending.popleft()
             srv.poll(t, mid)
 
     for k in kinds:                              # warm the cached constants of every network
@@ -539,7 +548,7 @@ def serving_n16_bench(vr, level=3, n_sessions=8, n_warm=20, n_meas=100, loads=(0
     for load in loads:
         run(n_warm, load * sat_req_s)
         srv.reset_stats()
-        run(n_meas, load * sat_req_s)
+        run(n_meas, load * sat_req_s, "level %d, load %.2f" % (level, load))
         st = srv.stats()
         levels.append({"offered_load": load, "offered_req_per_s": round(load * sat_req_s, 2),
                        "images_per_s": round(st["images_per_s"], 1), "latency_ms_p50": round(st["p50_ms"], 2),
@@ -1155,7 +1164,11 @@ def main():
     ap.add_argument("--cnn-sets", type=int, default=2)
     ap.add_argument("--serve-requests", type=int, default=60)
     ap.add_argument("--serve-n16-requests", type=int, default=100,
-                    help="measured requests per offered load in the N=2^16 serving legs")
+                    help="measured requests per offered load in the N=2^16 serving leg at level 3")
+    ap.add_argument("--serve-n16-requests-24", type=int, default=50,
+                    help="measured requests per offered load in the N=2^16 serving leg at level 24")
+    ap.add_argument("--serve-n16-levels", default="3,24",
+                    help="levels of the N=2^16 serving legs (comma list of 3 and 24)")
     ap.add_argument("--serve-load", default="0.8,2.0",
                     help="offered loads, as fractions of the one-request-at-a-time service rate")
     ap.add_argument("--ntt-plan", default="auto",
@@ -1169,7 +1182,7 @@ def main():
                     help="one extra headline step per kernel class, reporting its device time per step")
     ap.add_argument("--legs", default="all",
                     help="extra legs to run after the headline: all, or a comma list of trimmed, conv28, "
-                         "matmul16, rotations, serving, uneven, cpu")
+                         "matmul16, rotations, serving, serving16 (the N=2^16 serving legs only), uneven, cpu")
     ap.add_argument("--cpu-oracle-child", action="store_true", help=argparse.SUPPRESS)
     args = ap.parse_args()
     legs = set(args.legs.split(",")) if args.legs != "all" else \
@@ -1316,16 +1329,19 @@ def main():
                           for x in args.serve_load.split(",")]
         del ctx2, keys2
         gc.collect()
-        log("serving at N=2^16, level 3")
-        log_free("before this leg")
-        out["serving_n16"] = serving_n16_bench(vr, level=3, n_meas=args.serve_n16_requests)
-        gc.collect()
-        log("serving at N=2^16, level 24")
-        log_free("before this leg")
-        out["serving_n16_level24"] = serving_n16_bench(vr, level=24, n_sessions=4, n_warm=10,
-                                                       n_meas=max(40, args.serve_n16_requests // 2),
-                                                       loads=(0.5, 0.9))
-        gc.collect()
+    if "serving" in legs or "serving16" in legs:
+        s_levels = [int(x) for x in args.serve_n16_levels.split(",")]
+        if 3 in s_levels:
+            log("serving at N=2^16, level 3")
+            log_free("before this leg")
+            out["serving_n16"] = serving_n16_bench(vr, level=3, n_meas=args.serve_n16_requests)
+            gc.collect()
+        if 24 in s_levels:
+            log("serving at N=2^16, level 24")
+            log_free("before this leg")
+            out["serving_n16_level24"] = serving_n16_bench(vr, level=24, n_sessions=4, n_warm=10,
+                                                           n_meas=args.serve_n16_requests_24, loads=(0.5, 0.9))
+            gc.collect()
 
     if "uneven" in legs:
         log("uneven batch at N=2^16")
