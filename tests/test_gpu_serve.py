@@ -228,6 +228,40 @@ def test_server_full_network_model(small):
             same_limbs(a, b, "request %d logit %d" % (i, j))
 
 
+def test_server_lazy_fc_pruned_waves_identical_to_alone():
+    """Requests entering at level 7 of the C2 chain with FC weights at level 3
+    (x^2 relinearised once per FC output, the conv pruned to the FC's four
+    limbs), from two sessions with their own keys: every served result is
+    identical to the whole-network call on that request alone."""
+    from paper_2512_18646_amd import vr
+    o, ok, g, gk = pair("C2", rot_steps=(1, 2, 4, 8), log_n=10)
+    gk2 = g.keygen(77, rot_steps=[1, 2, 4, 8])
+    S = SHAPE
+    rng = np.random.default_rng(82)
+    _, K, bias = draw(rng)
+    Hp = Ly.image_block(S["h"], S["pad"])
+    wo = Ly.conv_out_size(S["w"], S["pad"], S["k"], S["s"])
+    ho = Ly.conv_out_size(S["h"], S["pad"], S["k"], S["s"])
+    pts = g.encode_fc_weights(rng.normal(0, 0.05, (4, 3, ho, wo)), S["s"], Hp, 3)
+    net = vr.CNN(S["Ci"], S["h"], S["w"], S["pad"], K, bias, S["s"], square=True, fc_w=pts,
+                 fc_bias=rng.normal(0, 0.05, 4), fc_block=Hp)
+    srv = vr.Server(g, 8 << 30, max_batch=4)
+    sids = [srv.register_session(gk), srv.register_session(gk2)]
+    mid = srv.register_model(net)
+    keys = [gk, gk2]
+    inputs = [g.encrypt_columns(keys[i % 2], rng.uniform(0, 1, (S["B"], S["Ci"], S["h"], S["w"])), S["pad"], 7,
+                                600 + i, 0) for i in range(6)]
+    tickets = [srv.submit(sids[i % 2], mid, c, S["B"]) for i, c in enumerate(inputs)]
+    outs = [srv.poll(t, mid) for t in tickets]
+    srv.close()
+    for i, (c, got) in enumerate(zip(inputs, outs)):
+        ref = net.forward(g, keys[i % 2], c)
+        assert len(got) == len(ref) == 4
+        for j, (a, b) in enumerate(zip(got, ref)):
+            assert a.meta[1] == 1, (i, j)
+            same_limbs(a, b, "request %d logit %d" % (i, j))
+
+
 @pytest.mark.timeout(300)
 def test_server_n16_identical_to_alone_and_oracle():
     """Serving at N = 2^16 (the L = 24 chain, dnum 3) at level 3: requests of
