@@ -125,7 +125,11 @@ vr_status vr_context_trim(vr_context *ctx);
  * reads the conv's output only on limbs q_0..q_f (the unrelinearised x^2
  * into an FC at level f), the conv's rotations, sums and ModDown by P q_l
  * produce only those limbs; "off" computes every limb and drops them after
- * (identical words).
+ * (identical words).  Knob "fc_compact": "on" (default) or "off": FC weights
+ * from vr_encode_fc_weights lie in the subring Z[X^r], r = N / (2 block), so
+ * each limb in the evaluation domain repeats in runs of r words; the FC reads
+ * a copy that keeps each run once (N / r words per limb) instead of the full
+ * limbs ("off"; identical words).
  * Tuning synchronises
  * once; the transform is the same exact map under every plan. */
 vr_status vr_context_set_tuning(vr_context *ctx, const char *knob, const char *value);
@@ -424,8 +428,13 @@ vr_status vr_fc(vr_context *ctx, const vr_eval_keys *ek, const vr_ciphertext *co
                 uint32_t n_out, uint32_t block, vr_ciphertext **out, void *stream);
 /* Model-provider side of the FC layer: W is [n_out][C][h_out][w_out];
  * plaintext (o, c, j') has slot b*block + stride*i' -> W[o][c][i'][j'] for
- * i' < h_out in every block b, encoded at scale (double) q_level.  W_pt
- * receives n_out*C*w_out handles, index (o*C + c)*w_out + j'. */
+ * i' < h_out in every block b, encoded at scale (double) q_level.  The slot
+ * vector repeats with period `block`, so its exact encoding lies in Z[X^r],
+ * r = N / (2 block): coefficients off that subring are set to zero rather
+ * than rounded, and each plaintext also keeps a compact evaluation-domain
+ * copy (each limb's runs of r equal words kept once) that vr_fc and the
+ * network call read.  W_pt receives n_out*C*w_out handles, index
+ * (o*C + c)*w_out + j'. */
 vr_status vr_encode_fc_weights(vr_context *ctx, const double *W, uint32_t n_out, uint32_t C,
                                uint32_t h_out, uint32_t w_out, uint32_t stride, uint32_t block,
                                uint32_t level, vr_plaintext **W_pt);

@@ -421,21 +421,27 @@ class Context:
         return Keys(s, pb, pa, rlk, rot)
 
     # -------------------------------------------------------- encode/decode
-    def encode_int(self, z, scale):
-        """Integer coefficients m_t (int64) of the slot vector z (real, length <= S)."""
+    def encode_int(self, z, scale, sub_log=0):
+        """Integer coefficients m_t (int64) of the slot vector z (real, length <= S).
+        sub_log > 0: z repeats with period S / 2^sub_log, so in exact arithmetic
+        the polynomial lies in Z[X^(2^sub_log)]; the coefficients off that
+        subring (rounding noise of the FFT) are set to zero before rounding."""
         z = np.zeros(self.slots) if z is None else np.asarray(z, dtype=np.float64)
         zz = np.zeros(self.slots)
         zz[:len(z)] = z
         w = np.zeros(2 * self.n, dtype=np.complex128)
         w[self.gexp] = zz
         f = np.fft.fft(w)[:self.n]
-        m = rha_array((2.0 * scale / self.n) * f.real)
+        re = f.real.copy()
+        if sub_log:
+            re[np.arange(self.n) % (1 << sub_log) != 0] = 0.0
+        m = rha_array((2.0 * scale / self.n) * re)
         if np.any(np.abs(m) >= 2.0 ** 62):
             raise ValueError("encoded coefficient out of range")
         return m.astype(np.int64)
 
-    def encode(self, z, level, scale):
-        m = self.encode_int(z, scale)
+    def encode(self, z, level, scale, sub_log=0):
+        m = self.encode_int(z, scale, sub_log)
         return Plaintext(self._int_poly_limbs(m, self.moduli(level)), level, float(scale))
 
     def decode(self, pt: Plaintext, n=None):

@@ -321,9 +321,11 @@ def square(ctx: Context, keys: Keys, ct):
 
 def fc_plaintexts(ctx: Context, W, C, ho, wo, stride, Hp, level):
     """pt[o][c*wo + j'] has slot b H' + s i' -> W[o][c][i'][j'] for i' < ho, every
-    block b; encoded at scale (double) q_level."""
+    block b; encoded at scale (double) q_level.  The slot vector repeats with
+    period H', so it is encoded in the subring Z[X^r], r = N / (2 H')."""
     W = np.asarray(W, np.float64).reshape(-1, C, ho, wo)
     nb = ctx.slots // Hp
+    sub_log = (ctx.n // (2 * Hp)).bit_length() - 1
     pts = []
     for o in range(W.shape[0]):
         row = []
@@ -332,7 +334,7 @@ def fc_plaintexts(ctx: Context, W, C, ho, wo, stride, Hp, level):
                 z = np.zeros(ctx.slots)
                 for b in range(nb):
                     z[b * Hp + stride * np.arange(ho)] = W[o, c, :, jo]
-                row.append(ctx.encode(z, level, float(ctx.q[level])))
+                row.append(ctx.encode(z, level, float(ctx.q[level]), sub_log))
         pts.append(row)
     return pts
 

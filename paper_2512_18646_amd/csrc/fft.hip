@@ -44,14 +44,15 @@ __global__ void k_fft_stage(const double2* in, double2* out, u32 m_points, u32 l
 }
 
 // m_t = RHA(c * Re F[t]) reduced into nl limbs
+// sub_mask != 0: coefficients t with t & sub_mask off the subring are zero
 __global__ void k_round_to_limbs(const double2* F, u32 m_points, double c, u64* limbs, u32 nl,
-                                 u64 limbs_stride, u32 log_n, const ModQ* mq, int* overflow)
+                                 u64 limbs_stride, u32 log_n, const ModQ* mq, int* overflow, u32 sub_mask)
 {
     u32 t = blockIdx.x * kThreads + threadIdx.x;
     u32 n = 1u << log_n;
     if (t >= n) return;
     u32 v = blockIdx.y;
-    double x = round(c * F[(size_t)v * m_points + t].x);
+    double x = (t & sub_mask) ? 0.0 : round(c * F[(size_t)v * m_points + t].x);
     if (!(fabs(x) < 4611686018427387904.0)) {   // 2^62
         *overflow = 1;
         x = 0.0;
@@ -102,7 +103,7 @@ double2* fft(vr_context* ctx, double2* a, double2* b, u32 n_vec, hipStream_t s)
 }  // namespace
 
 void encode_to_limbs(vr_context* ctx, const double* x_dev, u32 n, u32 n_vec, u64 vec_stride_x,
-                     double scale, u64* limbs, u32 nl, u64 limbs_stride, hipStream_t s)
+                     double scale, u64* limbs, u32 nl, u64 limbs_stride, hipStream_t s, u32 sub_log)
 {
     u32 m_points = 2 * ctx->n;
     size_t bytes = (size_t)n_vec * m_points * sizeof(double2);
@@ -120,7 +121,7 @@ void encode_to_limbs(vr_context* ctx, const double* x_dev, u32 n, u32 n_vec, u64
     dim3 g2((ctx->n + kThreads - 1) / kThreads, n_vec);
     hipLaunchKernelGGL(k_round_to_limbs, g2, dim3(kThreads), 0, s, F, m_points,
                        2.0 * scale / (double)ctx->n, limbs, nl, limbs_stride, ctx->log_n,
-                       ctx->d_modq, (int*)flag->ptr);
+                       ctx->d_modq, (int*)flag->ptr, (1u << sub_log) - 1);
     VR_CHECK_LAUNCH();
     int ovf = 0;
     VR_HIP(hipMemcpyAsync(&ovf, flag->ptr, sizeof(int), hipMemcpyDeviceToHost, s));

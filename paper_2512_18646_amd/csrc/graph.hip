@@ -30,9 +30,13 @@ CnnDesc make_desc(vr_context* ctx, const vr_cnn_desc* d, u32 level_in, hipStream
         const size_t count = (size_t)d->fc_out * c.C_out * c.w_out();
         const u32 nl = level_in - c.square;     // limbs of the FC input (level_in - 1 - square + 1)
         BufPtr hold;
-        c.fc_P = fc_weights(ctx, d->fc_w, count, nl, &c.fc_stride, &c.fc_scale, &c.fc_level, hold, s);
+        c.fc_P = fc_weights(ctx, d->fc_w, count, nl, &c.fc_stride, &c.fc_scale, &c.fc_level, hold, s,
+                            &c.fc_rep);
         if (hold) c.fc_hold.push_back(hold);
-        for (size_t i = 0; i < count; i++) c.fc_hold.push_back(d->fc_w[i]->buf);
+        for (size_t i = 0; i < count; i++) {
+            c.fc_hold.push_back(d->fc_w[i]->buf);
+            if (d->fc_w[i]->cbuf) c.fc_hold.push_back(d->fc_w[i]->cbuf);
+        }
         c.fc_bias.assign(d->fc_bias, d->fc_bias + d->fc_out);
         c.fc_out = d->fc_out;
         c.fc_block = d->fc_block;

@@ -380,13 +380,29 @@ __global__ __launch_bounds__(kThreads) void k_tensor_batch(u64* out, const u64* 
 // P + (o * n_in + i) * p_stride, limbs [N] each.
 constexpr int kFcGroup = 8;
 
+// Compact copy of evaluation-domain limbs that repeat in runs of 2^rep
+// consecutive words: out[v][u] = in[v][u 2^rep]; *bad = 1 when a run holds
+// two different words (then the copy is not used).
+__global__ __launch_bounds__(kThreads) void k_compact_runs(const u64* in, u64* out, u32 log_n, u32 rep, int* bad)
+{
+    const size_t n = (size_t)1 << log_n, cn = n >> rep;
+    const size_t u = (size_t)blockIdx.x * kThreads + threadIdx.x;
+    if (u >= cn) return;
+    const u64* src = in + (size_t)blockIdx.y * n + (u << rep);
+    const u64 v0 = src[0];
+    bool same = true;
+    for (u32 k = 1; k < (1u << rep); k++) same = same && src[k] == v0;
+    if (!same) atomicOr(bad, 1);
+    out[(size_t)blockIdx.y * cn + u] = v0;
+}
+
 // FC weight products of the x^2 tensors (lazy relinearisation): for outputs
 // o0 .. o0 + kFcGroup - 1 and limb l,
 //   out_o = sum_i (y_i0^2, 2 y_i0 y_i1, y_i1^2) P[o][i]     (3 components),
 // the tensor of each input formed once per limb and weight group.
 __global__ __launch_bounds__(kThreads) void k_sqfc_acc(u64* out, u64 out_stride, const u64* Y, u64 y_stride,
                                                        u64 y_comp, u32 n_in, const u64* P, u64 p_stride,
-                                                       u32 n_out, u32 nl, u32 log_n, const ModQ* mq)
+                                                       u32 n_out, u32 nl, u32 log_n, const ModQ* mq, u32 rep)
 {
     const u32 n = 1u << log_n;
     const u32 t = blockIdx.x * kThreads + threadIdx.x;
@@ -401,6 +417,7 @@ __global__ __launch_bounds__(kThreads) void k_sqfc_acc(u64* out, u64 out_stride,
 #pragma unroll
         for (int g = 0; g < kFcGroup; g++) h[c][g] = lo[c][g] = 0;
     const size_t off0 = (size_t)l * n + t, yoff1 = y_comp + off0;
+    const size_t poff = (size_t)l * (n >> rep) + (t >> rep);   // weights: runs of 2^rep words kept once
     for (u32 i = 0; i < n_in; i++) {
         const u64 y0 = Y[(size_t)i * y_stride + off0];
         const u64 y1 = Y[(size_t)i * y_stride + yoff1];
@@ -409,7 +426,7 @@ __global__ __launch_bounds__(kThreads) void k_sqfc_acc(u64* out, u64 out_stride,
 #pragma unroll
         for (int g = 0; g < kFcGroup; g++) {
             if (g < (int)cnt) {
-                const u64 p = P[((size_t)(o0 + g) * n_in + i) * p_stride + off0];
+                const u64 p = P[((size_t)(o0 + g) * n_in + i) * p_stride + poff];
 #pragma unroll
                 for (int c = 0; c < 3; c++) mac128(h[c][g], lo[c][g], d[c], p);
             }
@@ -437,7 +454,8 @@ __global__ __launch_bounds__(kThreads) void k_sqfc_acc(u64* out, u64 out_stride,
 __global__ __launch_bounds__(kThreads) void k_mulplain_acc(u64* out, u64 out_stride,
                                                            const u64* Y, u64 y_stride, u64 y_comp,
                                                            u32 n_in, const u64* P, u64 p_stride,
-                                                           u32 n_out, u32 nl, u32 log_n, const ModQ* mq)
+                                                           u32 n_out, u32 nl, u32 log_n, const ModQ* mq,
+                                                           u32 rep)
 {
     const u32 n = 1u << log_n;
     const u32 t = blockIdx.x * kThreads + threadIdx.x;
@@ -452,13 +470,14 @@ __global__ __launch_bounds__(kThreads) void k_mulplain_acc(u64* out, u64 out_str
     // output limbs [2][nl][N]; input component 1 at y_comp (the inputs may
     // hold more limbs than the nl read here)
     const size_t off0 = (size_t)l * n + t, off1 = (size_t)(nl + l) * n + t, yoff1 = y_comp + off0;
+    const size_t poff = (size_t)l * (n >> rep) + (t >> rep);   // weights: runs of 2^rep words kept once
     for (u32 i = 0; i < n_in; i++) {
         const u64 y0 = Y[(size_t)i * y_stride + off0];
         const u64 y1 = Y[(size_t)i * y_stride + yoff1];
 #pragma unroll
         for (int g = 0; g < kFcGroup; g++) {
             if (g < (int)cnt) {
-                const u64 p = P[((size_t)(o0 + g) * n_in + i) * p_stride + off0];
+                const u64 p = P[((size_t)(o0 + g) * n_in + i) * p_stride + poff];
                 mac128(h0[g], l0[g], y0, p);
                 mac128(h1[g], l1[g], y1, p);
             }
@@ -1105,7 +1124,7 @@ Slab layer_square(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipSt
 }
 
 Slab fc_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& y, const u64* P, u64 p_stride,
-             double p_scale, u32 p_level, u32 n_out, const double* bias, u32 block, hipStream_t s)
+             double p_scale, u32 p_level, u32 n_out, const double* bias, u32 block, hipStream_t s, u32 p_rep)
 {
     if (y.ncomp != 2) throw Error(VR_EINVAL, "FC inputs must be 2-component");
     // weights encoded below the inputs' level: the inputs are read on limbs
@@ -1118,7 +1137,7 @@ Slab fc_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& y, const u64* 
     dim3 grid((ctx->n + kThreads - 1) / kThreads, nl, (n_out + kFcGroup - 1) / kFcGroup);
     hipLaunchKernelGGL(k_mulplain_acc, grid, dim3(kThreads), 0, s, acc.base, acc.stride, y.base,
                        y.stride, (u64)(y.level + 1) * ctx->n, y.n, P, p_stride, n_out, nl, ctx->log_n,
-                       ctx->d_modq);
+                       ctx->d_modq, p_rep);
     VR_CHECK_LAUNCH();
     Slab z = rescale_slab(ctx, acc, s);
     // rotate-and-sum inside each block: z += Rot(z, 2^t)
@@ -1139,22 +1158,39 @@ Slab fc_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& y, const u64* 
 // Weight plaintexts as one [n_out * n_in][>= nl][N] array: in place when the
 // handles already form one (as vr_encode_fc_weights returns them), else a copy.
 const u64* fc_weights(vr_context* ctx, const vr_plaintext* const* W_pt, size_t count, u32 nl,
-                      u64* p_stride, double* p_scale, u32* p_level, BufPtr& holder, hipStream_t s)
+                      u64* p_stride, double* p_scale, u32* p_level, BufPtr& holder, hipStream_t s,
+                      u32* p_rep)
 {
     const vr_plaintext* p0 = W_pt[0];
     if (!p0) throw Error(VR_EINVAL, "null plaintext");
     const u64 stride = (u64)(p0->level + 1) * ctx->n;
     bool contiguous = true;
+    // the compact copies (runs of 2^clog equal words kept once), when every
+    // plaintext has one with the same run length, laid out back to back
+    bool compact = p0->cdata != nullptr && p0->clog > 0;
+    const u64 cstride = compact ? (u64)(p0->level + 1) * (ctx->n >> p0->clog) : 0;
     for (size_t i = 0; i < count; i++) {
         if (!W_pt[i]) throw Error(VR_EINVAL, "null plaintext");
         if (W_pt[i]->level != p0->level) throw Error(VR_ELEVEL, "weight plaintexts at different levels");
         if (W_pt[i]->scale != p0->scale) throw Error(VR_ESCALE, "weight plaintexts at different scales");
         contiguous = contiguous && W_pt[i]->data == p0->data + i * stride;
+        compact = compact && W_pt[i]->clog == p0->clog && W_pt[i]->cdata == p0->cdata + i * cstride;
+    }
+    {
+        std::lock_guard<std::mutex> g(ctx->mu);
+        auto it = ctx->tuning.find("fc_compact");
+        if (it != ctx->tuning.end() && it->second == 1) compact = false;
     }
     *p_scale = p0->scale;
     // the layer runs at min(input level, weight level): nl limbs are read
     nl = std::min(nl, p0->level + 1);
     *p_level = nl - 1;
+    *p_rep = 0;
+    if (compact) {
+        *p_stride = cstride;
+        *p_rep = p0->clog;
+        return p0->cdata;
+    }
     if (contiguous) {
         *p_stride = stride;
         return p0->data;
@@ -1576,11 +1612,11 @@ Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab&
             if (lazy_fc)
                 hipLaunchKernelGGL(k_sqfc_acc, grid, dim3(kThreads), 0, s, z.ct(z_at + st * d.fc_out), z.stride,
                                    y.ct(y_at + st * per), y.stride, (u64)(y.level + 1) * ctx->n, per, d.fc_P,
-                                   d.fc_stride, d.fc_out, fl + 1, ctx->log_n, ctx->d_modq);
+                                   d.fc_stride, d.fc_out, fl + 1, ctx->log_n, ctx->d_modq, d.fc_rep);
             else
                 hipLaunchKernelGGL(k_mulplain_acc, grid, dim3(kThreads), 0, s, z.ct(z_at + st * d.fc_out), z.stride,
                                    y.ct(y_at + st * per), y.stride, (u64)(y.level + 1) * ctx->n, per, d.fc_P,
-                                   d.fc_stride, d.fc_out, fl + 1, ctx->log_n, ctx->d_modq);
+                                   d.fc_stride, d.fc_out, fl + 1, ctx->log_n, ctx->d_modq, d.fc_rep);
             VR_CHECK_LAUNCH();
         }
         kfc.push_back(KeyRange{z_at, z_at + g.n_sets * d.fc_out, g.ek});
@@ -1981,9 +2017,30 @@ vr_status vr_encode_fc_weights(vr_context* ctx, const double* W, uint32_t n_out,
     BufPtr xd = dev_alloc(ctx, slots.size() * sizeof(double), s);
     VR_HIP(hipMemcpyAsync(xd->ptr, slots.data(), slots.size() * sizeof(double), hipMemcpyHostToDevice, s));
     BufPtr mb = dev_alloc(ctx, total * nl * N * sizeof(u64), s);
+    // the slot vectors repeat with period `block`: encoded in Z[X^r],
+    // r = N / (2 block), and in the evaluation domain (bit-reversed order)
+    // every limb then repeats in runs of r consecutive words
+    u32 rep = 0;
+    while ((2ull * block) << (rep + 1) <= N) rep++;
     encode_to_limbs(ctx, (const double*)xd->ptr, (u32)S, (u32)total, S, sc, as_u64(mb), nl,
-                    (u64)nl * N, s);
+                    (u64)nl * N, s, rep);
     ntt_forward(ctx, poly_limbs(as_u64(mb), as_u64(mb), (u32)total, nl, (u64)nl * N, (int)level), s);
+    BufPtr cb;
+    if (rep > 0) {
+        // one compact copy of all of them, checked word for word
+        const size_t cn = N >> rep;
+        cb = dev_alloc(ctx, total * nl * cn * sizeof(u64), s);
+        BufPtr flag = dev_alloc(ctx, sizeof(int), s);
+        VR_HIP(hipMemsetAsync(flag->ptr, 0, sizeof(int), s));
+        dim3 grid((u32)((cn + kThreads - 1) / kThreads), (u32)(total * nl));
+        hipLaunchKernelGGL(k_compact_runs, grid, dim3(kThreads), 0, s, as_u64(mb), as_u64(cb), ctx->log_n, rep,
+                           (int*)flag->ptr);
+        VR_CHECK_LAUNCH();
+        int bad = 0;
+        VR_HIP(hipMemcpyAsync(&bad, flag->ptr, sizeof(int), hipMemcpyDeviceToHost, s));
+        VR_HIP(hipStreamSynchronize(s));
+        if (bad) cb.reset();
+    }
     for (size_t i = 0; i < total; i++) {
         auto* pt = new vr_plaintext;
         pt->ctx = ctx;
@@ -1991,6 +2048,11 @@ vr_status vr_encode_fc_weights(vr_context* ctx, const double* W, uint32_t n_out,
         pt->data = as_u64(mb) + i * nl * N;
         pt->level = level;
         pt->scale = sc;
+        if (cb) {
+            pt->cbuf = cb;
+            pt->cdata = as_u64(cb) + i * nl * (N >> rep);
+            pt->clog = rep;
+        }
         W_pt[i] = pt;
     }
     VR_HIP(hipStreamSynchronize(s));
@@ -2083,9 +2145,10 @@ vr_status vr_fc(vr_context* ctx, const vr_eval_keys* ek, const vr_ciphertext* co
     u64 p_stride = 0;
     double p_scale = 0;
     u32 p_level = 0;
+    u32 p_rep = 0;
     const u64* P = fc_weights(ctx, W_pt, (size_t)n_out * n_in, y.level + 1, &p_stride, &p_scale, &p_level,
-                              hold, s);
-    Slab z = fc_slab(ctx, ek, y, P, p_stride, p_scale, p_level, n_out, bias, block, s);
+                              hold, s, &p_rep);
+    Slab z = fc_slab(ctx, ek, y, P, p_stride, p_scale, p_level, n_out, bias, block, s, p_rep);
     to_handles(ctx, z, out);
     API_END
 }

@@ -42,8 +42,11 @@ Slab layer_square(vr_context* ctx, const vr_eval_keys* ek, const Slab& in, hipSt
 // FC layer: Z_o = RotSum_block(Rescale(sum_i y_i * P[o][i])) + bias_o with the
 // weight plaintexts P[o][i] at P + (o * y.n + i) * p_stride, evaluated at
 // min(y.level, p_level) (inputs above the weights' level are read on its limbs)
+// p_rep > 0: the weights are compact copies (runs of 2^p_rep equal words kept
+// once, N >> p_rep words per limb)
 Slab fc_slab(vr_context* ctx, const vr_eval_keys* ek, const Slab& y, const u64* P, u64 p_stride,
-             double p_scale, u32 p_level, u32 n_out, const double* bias, u32 block, hipStream_t s);
+             double p_scale, u32 p_level, u32 n_out, const double* bias, u32 block, hipStream_t s,
+             u32 p_rep = 0);
 // A network (conv, optional x^2, optional FC) with its constants resolved.
 struct CnnDesc {
     u32 C_in, h, w, pad, C_out, k, stride, square;
@@ -53,6 +56,7 @@ struct CnnDesc {
     u64 fc_stride = 0;
     double fc_scale = 0;
     u32 fc_level = 0;                // level the FC runs at (its weights' level or below)
+    u32 fc_rep = 0;                  // weights compact (runs of 2^fc_rep words kept once)
     u32 fc_out = 0, fc_block = 0;
     u32 w_out() const { return (w + 2 * pad - k) / stride + 1; }
     u32 n_in() const { return C_in * w; }
@@ -100,7 +104,9 @@ void outer_tiles(vr_context* ctx, u32 m, u32 p, u32* Pp, u32* R, u32* T);
 void block_shape(vr_context* ctx, u32 m, u32 n, u32 p, u32* Pp, u32* Mb, u32* c, u32* nb);
 // Weight plaintexts as one array of count plaintexts; *p_level = the level
 // the layer runs at, min(nl - 1, the plaintexts' level).
+// *p_rep > 0: the returned weights are the plaintexts' compact copies
 const u64* fc_weights(vr_context* ctx, const vr_plaintext* const* W_pt, size_t count, u32 nl,
-                      u64* p_stride, double* p_scale, u32* p_level, BufPtr& holder, hipStream_t s);
+                      u64* p_stride, double* p_scale, u32* p_level, BufPtr& holder, hipStream_t s,
+                      u32* p_rep);
 
 }  // namespace vr

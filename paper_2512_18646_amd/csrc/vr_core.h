@@ -365,6 +365,11 @@ struct vr_plaintext {
     vr::u64* data = nullptr;     // [level+1][N]
     vr::u32 level = 0;
     double scale = 1.0;
+    // compact copy when every limb repeats in runs of 2^clog consecutive
+    // evaluation-domain words (a polynomial in Z[X^(2^clog)]): [level+1][N >> clog]
+    vr::BufPtr cbuf;
+    vr::u64* cdata = nullptr;
+    vr::u32 clog = 0;
 };
 
 struct vr_secret_key {

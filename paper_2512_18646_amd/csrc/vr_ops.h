@@ -143,9 +143,11 @@ void launch_decrypt_combine(vr_context* ctx, u64* m, const u64* ct, u32 ncomp, c
 
 // ---------------------------------------------------------- encode / decode
 
-// slots x[n] (n <= S) at `scale` -> integer coefficients reduced into nl limbs (coefficient domain)
+// slots x[n] (n <= S) at `scale` -> integer coefficients reduced into nl limbs
+// (coefficient domain); sub_log > 0: the slots repeat with period S / 2^sub_log
+// and the coefficients off the subring Z[X^(2^sub_log)] (FFT noise) are zero
 void encode_to_limbs(vr_context* ctx, const double* x_dev, u32 n, u32 n_vec, u64 vec_stride_x,
-                     double scale, u64* limbs, u32 nl, u64 limbs_stride, hipStream_t s);
+                     double scale, u64* limbs, u32 nl, u64 limbs_stride, hipStream_t s, u32 sub_log = 0);
 // limb q_0 coefficients (coefficient domain) -> slots out[n] / scale
 void decode_from_limb0(vr_context* ctx, const u64* coef0, double scale, double* out_dev, u32 n,
                        hipStream_t s);

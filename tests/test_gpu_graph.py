@@ -54,6 +54,13 @@ def test_cnn_forward_matches_layer_calls(net):
     out = full.forward(g, gk, sets[0] + sets[1], n_sets=2)
     check(out[:4], layers_ref(g, gk, sets[0], params), "set 0")
     check(out[4:], layers_ref(g, gk, sets[1], params), "set 1")
+    # the FC weights' compact copies (N / (2 H') = 32 words per run) against
+    # the full limbs
+    g.set_tuning("fc_compact", "off")
+    try:
+        check(out, full.forward(g, gk, sets[0] + sets[1], n_sets=2), "full weight limbs")
+    finally:
+        g.set_tuning("fc_compact", "on")
     out2 = conv_sq.forward(g, gk, sets[2], n_sets=1)
     check(out2, layers_ref(g, gk, sets[2], params, fc=False), "conv + x^2")
 

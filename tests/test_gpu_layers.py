@@ -232,9 +232,19 @@ def test_conv_square_fc_bit_exact_small(small_cnn):
     assert gZ1[0].level == 0
     for i, (x, y) in enumerate(zip(gZ1, Z1)):
         assert_same(x, y, "fc below the input level %d" % i)
-    # GPU-encoded weights: decoded logits still within the bar
+    # GPU-encoded weights: decoded logits still within the bar, and the
+    # compact weight copies (runs of N / (2 H') equal words kept once) give the
+    # same words as the full limbs
     gpts2 = g.encode_fc_weights(W, s, Hp, Y2[0].level)
+    assert o.n // (2 * Hp) > 1
     gZ2 = g.fc(gk, gY2, Co, wo, gpts2, fb, Hp)
+    g.set_tuning("fc_compact", "off")
+    try:
+        gZ3 = g.fc(gk, gY2, Co, wo, gpts2, fb, Hp)
+    finally:
+        g.set_tuning("fc_compact", "on")
+    for i, (x, y) in enumerate(zip(gZ2, gZ3)):
+        assert x.meta == y.meta and np.array_equal(x.export(), y.export()), "compact fc %d" % i
     logits = np.zeros((B, 4))
     for oi, z in enumerate(gZ2):
         logits[:, oi] = g.decode(g.decrypt(gk, z))[np.arange(B) * Hp]
@@ -383,9 +393,10 @@ def test_cnn128_full_level_chunked_key_switching():
 def test_cnn128_network_level24_pruned_equals_full():
     """The headline network (3x128x128, conv 3x3/2 pad 1 x8, x^2, FC 32768 ->
     10 with its weights at level 3) entering at level 24: the network call,
-    whose conv makes only the 4 limbs the FC reads, gives the same words as
-    with every conv limb made and dropped after (conv_prune off), and its
-    logits decode to the FP64 network."""
+    whose conv makes only the 4 limbs the FC reads and whose FC reads the
+    compact weight copies, gives the same words as with every conv limb made
+    and dropped after and the full weight limbs read (conv_prune and
+    fc_compact off), and its logits decode to the FP64 network."""
     from paper_2512_18646_amd import vr
     W = SI.CNN_128
     Hp = Ly.image_block(W.h, W.pad)
@@ -400,10 +411,12 @@ def test_cnn128_network_level24_pruned_equals_full():
                  fc_block=Hp)
     out = net.forward(g, gk, cols)
     g.set_tuning("conv_prune", "off")
+    g.set_tuning("fc_compact", "off")
     try:
         full = net.forward(g, gk, cols)
     finally:
         g.set_tuning("conv_prune", "on")
+        g.set_tuning("fc_compact", "on")
     assert len(out) == len(full) == W.fc_out
     for i, (a, b) in enumerate(zip(out, full)):
         assert a.meta == b.meta and a.meta[1] == 1, i

@@ -38,6 +38,28 @@ def test_encode_single_slot_closed_form():
     assert np.max(np.abs(m - want)) <= 0.5 + 1e-3
 
 
+def test_encode_periodic_vector_lies_in_subring():
+    """A slot vector with period H' is fixed by the Galois element 5^H', of
+    order r = S / H' modulo 2N, whose fixed ring is Z[X^r]: the brute-force
+    coefficients (2 scale / N) sum_j z_j cos(pi g_j t / N) vanish for t not a
+    multiple of r, and the subring encoding equals their rounding everywhere
+    and decodes to z."""
+    ctx = small_ctx(log_n=7)
+    S, Hp = ctx.slots, 8
+    r = S // Hp
+    z = np.tile(np.random.default_rng(4).uniform(-1, 1, Hp), r)
+    t = np.arange(ctx.n)
+    want = np.array([2 * ctx.scale / ctx.n * sum(z[j] * np.cos(np.pi * ctx.gexp[j] * tt / ctx.n)
+                                                  for j in range(S)) for tt in t])
+    assert np.max(np.abs(want[t % r != 0])) < 1e-2
+    m = ctx.encode_int(z, ctx.scale, sub_log=r.bit_length() - 1)
+    assert np.all(m[t % r != 0] == 0)
+    assert np.array_equal(m, np.array([rha(x) for x in want]))
+    assert np.array_equal(m[t % r == 0], ctx.encode_int(z, ctx.scale)[t % r == 0])
+    pt = ctx.encode(z, 1, ctx.scale, sub_log=r.bit_length() - 1)
+    assert np.max(np.abs(ctx.decode(pt) - z)) < 2.0 ** -30
+
+
 def test_decode_encode_roundtrip():
     ctx = Context(PRESETS["C2"])
     z = np.random.default_rng(0).uniform(-1, 1, ctx.slots)
