@@ -129,7 +129,10 @@ vr_status vr_context_trim(vr_context *ctx);
  * from vr_encode_fc_weights lie in the subring Z[X^r], r = N / (2 block), so
  * each limb in the evaluation domain repeats in runs of r words; the FC reads
  * a copy that keeps each run once (N / r words per limb) instead of the full
- * limbs ("off"; identical words).
+ * limbs ("off"; identical words).  Knob "lincomb_wide": "on" (default) or
+ * "off": the conv's weighted sums on moduli of 2^51 or more (the 60-bit
+ * q_0) as exact FP64 sums of 21-bit pieces, or ("off") as 64-bit integer
+ * products (identical words).
  * Tuning synchronises
  * once; the transform is the same exact map under every plan. */
 vr_status vr_context_set_tuning(vr_context *ctx, const char *knob, const char *value);

@@ -182,10 +182,11 @@ vr_status vr_context_set_tuning(vr_context* ctx, const char* knob, const char* v
         if (v.compare(0, 5, "cand:") == 0) mode = 2 + std::stoi(v.substr(5));
     }
     else if (k == "switch_chunk" || k == "ntt_chunk") mode = std::stoi(v);
-    else if (k == "conv_prune" || k == "fc_compact") mode = v == "on" ? 0 : v == "off" ? 1 : -1;
+    else if (k == "conv_prune" || k == "fc_compact" || k == "lincomb_wide" || k == "lincomb_mfma")
+        mode = v == "on" ? 0 : v == "off" ? 1 : -1;
     else throw Error(VR_EINVAL, "unknown tuning knob");
     REQUIRE(mode >= 0, "base_convert takes auto, alu, mfma or fp64; ntt takes auto, fixed or cand:k; "
-                       "conv_prune and fc_compact take on or off");
+                       "conv_prune, fc_compact, lincomb_wide and lincomb_mfma take on or off");
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->tuning[k] = mode;
     API_END

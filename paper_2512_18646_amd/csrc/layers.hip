@@ -34,6 +34,14 @@ namespace vr {
 
 namespace {
 constexpr int kThreads = 256;
+
+// value of a tuning knob (0, its default, when never set)
+int knob(vr_context* ctx, const char* name)
+{
+    std::lock_guard<std::mutex> g(ctx->mu);
+    auto it = ctx->tuning.find(name);
+    return it == ctx->tuning.end() ? 0 : it->second;
+}
 }  // namespace
 
 Slab new_slab(vr_context* ctx, u32 n, u32 ncomp, u32 level, double scale, hipStream_t s)
@@ -143,6 +151,13 @@ struct Term {
 };
 constexpr u32 kTermColBits = 24;
 
+// balanced base-256 digits of x < 2^63 as eight signed bytes (host)
+inline u64 balanced_bytes_h(u64 x)
+{
+    const u64 h = 0x8080808080808080ull;
+    return (x + h) ^ h;
+}
+
 // For each of n_sets independent image sets s and each output column j':
 // out[s][f][j'] = sum_{terms of j'} w_f * in (+ bias on component 0) for every
 // filter f, 2 components of nl limbs.  The filters of one column read the
@@ -170,9 +185,14 @@ constexpr u32 kTermColBits = 24;
 // time) into LDS once per block, and each block covers cpb consecutive
 // 256-coefficient chunks with them; the products read the weights with
 // broadcast LDS loads instead of one scalar load each.
+//
+// kFp: the instance for the limbs below 2^51 (the others return at once);
+// !kFp: 64-bit integer Shoup products for the limbs of 2^51 or more (the
+// others return), when k_lincomb_wide does not make them.
 constexpr int kMaxFilters = 8;
 constexpr u32 kTermChunk = 256;
 
+template <bool kFp>
 __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, const u64* x,
                                                       const u64* r, u32 n_x, u32 n_sets, u64 stride,
                                                       u64 rstride, u64 ustride,
@@ -205,7 +225,8 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
     const u64* rb = r + (size_t)set * n_x * rstride;
     const size_t fst = (size_t)w_fstride * nl;
     constexpr u32 kColMask = (1u << kTermColBits) - 1;
-    if (q < (1ull << 51)) {
+    if (kFp) {
+        if (q >= (1ull << 51)) return;   // whole blocks: no barrier is skipped
         // FP64 products (the block's limb has one modulus): inputs and
         // weights balanced, each product within 0.75 q, the sums reduced
         // every four terms (below 3.5 q < 2^53)
@@ -274,6 +295,7 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
         return;
     }
     // integer path (limbs of 2^51 or more): no barrier, scalar weight loads
+    if (q < (1ull << 51)) return;
     for (u32 cc = 0; cc < cpb && chunk0 + cc < chunks; cc++) {
         const u32 t = (chunk0 + cc) * kThreads + threadIdx.x;
         if (t >= n) break;
@@ -321,6 +343,284 @@ __global__ __launch_bounds__(kThreads) void k_lincomb(u64* out, u64 out_stride, 
                     v = v >= q2 ? v - q2 : v;
                     v = v >= q ? v - q : v;
                     out[(size_t)(set * n_out + o) * out_stride + tile] = v;
+                }
+            }
+        }
+    }
+}
+
+// The rows of k_lincomb whose modulus is 2^51 or more (the 60-bit q_0, wide
+// special primes; every such q below 2^63), as exact FP64 sums instead of
+// 64-bit integer products.  Input word x and weight w (canonical residues)
+// are split into 21-bit pieces, x = x_0 + x_1 2^21 + x_2 2^42 and likewise
+// w, so x w = sum_m 2^(21 m) S_m with S_m = sum_{i+j=m} x_i w_j: nine
+// products below 2^42, summed exactly in five doubles per filter (below 2^50
+// over kWideChunk terms).  At the end of each chunk of terms the sums fold
+// into a residue: S_0 + 2^21 S_1 + 2^42 S_2 as a 128-bit value reduced mod
+// q, S_3 and S_4 times 2^63 and 2^84 mod q.  The weight pieces of a chunk
+// ([term][filter][piece], kWideChunk terms) sit in LDS.  Block order and
+// term ranges as in k_lincomb; the rows are (component, wide limb) pairs,
+// the wide limbs the set bits of wide_mask.
+constexpr u32 kWidePieces = 3, kWideChunk = 85;   // 85 x 8 x 3 doubles: 16320 bytes
+
+__global__ __launch_bounds__(kThreads) void k_lincomb_wide(u64* out, u64 out_stride, const u64* x,
+                                                           const u64* r, u32 n_x, u32 n_sets, u64 stride,
+                                                           u64 rstride, u64 ustride, const Term* terms,
+                                                           const u32* term_off, const u32* rot_end,
+                                                           const double* wp, u32 t_total, const u64* bias,
+                                                           u32 nl, u32 nk, u32 lvl, u32 modoff, u32 x_limbs,
+                                                           u32 log_n, const ModQ* mq, u32 wo, u32 n_filters,
+                                                           u64 wide_mask, u32 n_wide, u32 total, u32 per_xcd,
+                                                           u32 cpb)
+{
+    extern __shared__ double wl[];   // [term of the chunk][filter][piece]
+    const u32 logical = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (logical >= total) return;   // whole blocks only: no barrier is skipped
+    const u32 n = 1u << log_n;
+    const u32 chunks = (n + kThreads - 1) / kThreads;
+    const u32 jo = logical % wo;
+    u32 rest = logical / wo;
+    const u32 set = rest % n_sets;
+    rest /= n_sets;
+    const u32 wrow = rest % (2 * n_wide);
+    const u32 chunk0 = (rest / (2 * n_wide)) * cpb;
+    const u32 wi = wrow % n_wide;
+    u64 bits = wide_mask;
+    for (u32 i = 0; i < wi; i++) bits &= bits - 1;
+    const u32 l = (u32)__ffsll((unsigned long long)bits) - 1;
+    const u32 row = (wrow / n_wide) * nl + l;
+    const ModQ m = mq[l < nk ? l : l == nk ? lvl : l + modoff];
+    const u64 c3 = reduce128(0, 1ull << 63, m), c4 = reduce128(1ull << 20, 0, m);
+    const bool x_has = l <= nk;
+    const u32 xl = l < nk ? l : lvl;
+    const u32 a = term_off[jo], b = x_has ? term_off[jo + 1] : rot_end[jo];
+    const u32 n_out = n_filters * wo;
+    const u64* xb = x + (size_t)set * n_x * stride;
+    const u64* rb = r + (size_t)set * n_x * rstride;
+    constexpr u32 kColMask = (1u << kTermColBits) - 1;
+    constexpr u64 kPiece = (1ull << 21) - 1;
+    constexpr u32 kRun = kMaxFilters * kWidePieces;   // doubles per term
+    for (u32 f0 = 0, g = 0; f0 < n_filters; f0 += kMaxFilters, g++) {
+        const u32 nf = min((u32)kMaxFilters, n_filters - f0);
+        const double* wg = wp + (size_t)(g * n_wide + wi) * t_total * kRun;
+        u32 loaded = 0xffffffffu;
+        for (u32 cc = 0; cc < cpb && chunk0 + cc < chunks; cc++) {
+            const u32 t = (chunk0 + cc) * kThreads + threadIdx.x;
+            const bool active = t < n;
+            const size_t tile = (size_t)row * n + t;
+            const size_t xtile = ((size_t)(row / nl) * x_limbs + (x_has ? xl : 0)) * n + t;
+            u64 acc[kMaxFilters];
+#pragma unroll
+            for (int f = 0; f < kMaxFilters; f++) acc[f] = 0;
+            for (u32 c0 = a; c0 < b; c0 += kWideChunk) {
+                const u32 ce = min(b, c0 + kWideChunk);
+                if (c0 != loaded) {
+                    __syncthreads();
+                    for (u32 i = threadIdx.x; i < (ce - c0) * kRun; i += kThreads) wl[i] = wg[(size_t)c0 * kRun + i];
+                    __syncthreads();
+                    loaded = c0;
+                }
+                double S[kMaxFilters][5];
+#pragma unroll
+                for (int f = 0; f < kMaxFilters; f++)
+#pragma unroll
+                    for (int k = 0; k < 5; k++) S[f][k] = 0;
+                for (u32 k0 = c0; k0 < ce; k0 += 4) {
+                    u64 xv[4];
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        xv[i] = 0;
+                        if (k0 + i < ce && active) {
+                            const Term tm = terms[k0 + i];
+                            const u32 u = tm.in_idx >> kTermColBits, j = tm.in_idx & kColMask;
+                            xv[i] = u == 0 ? xb[(size_t)j * stride + xtile]
+                                           : rb[(u - 1) * ustride + (size_t)j * rstride + tile];
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        if (k0 + i < ce) {
+                            const double x0 = u2f(xv[i] & kPiece), x1 = u2f((xv[i] >> 21) & kPiece),
+                                         x2 = u2f(xv[i] >> 42);
+                            const double* wk = wl + (k0 + i - c0) * kRun;
+#pragma unroll
+                            for (int f = 0; f < kMaxFilters; f++) {
+                                if (f < (int)nf) {
+                                    const double w0 = wk[f * 3], w1 = wk[f * 3 + 1], w2 = wk[f * 3 + 2];
+                                    S[f][0] = __fma_rn(x0, w0, S[f][0]);
+                                    S[f][1] = __fma_rn(x1, w0, __fma_rn(x0, w1, S[f][1]));
+                                    S[f][2] = __fma_rn(x2, w0, __fma_rn(x1, w1, __fma_rn(x0, w2, S[f][2])));
+                                    S[f][3] = __fma_rn(x2, w1, __fma_rn(x1, w2, S[f][3]));
+                                    S[f][4] = __fma_rn(x2, w2, S[f][4]);
+                                }
+                            }
+                        }
+                    }
+                }
+#pragma unroll
+                for (int f = 0; f < kMaxFilters; f++) {
+                    if (f < (int)nf) {
+                        const u64 s0 = f2u(S[f][0]), s1 = f2u(S[f][1]), s2 = f2u(S[f][2]);
+                        const u64 l1 = s1 << 21, l2 = s2 << 42;
+                        u64 lo = s0 + l1;
+                        u64 hi = (s1 >> 43) + (s2 >> 22) + (lo < l1 ? 1 : 0);
+                        lo += l2;
+                        hi += lo < l2 ? 1 : 0;
+                        u64 v = reduce128(hi, lo, m);
+                        v = add_mod(v, mul_mod(f2u(S[f][3]), c3, m), m.q);
+                        v = add_mod(v, mul_mod(f2u(S[f][4]), c4, m), m.q);
+                        acc[f] = add_mod(acc[f], v, m.q);
+                    }
+                }
+            }
+            if (!active) continue;
+#pragma unroll
+            for (int f = 0; f < kMaxFilters; f++) {
+                if (f < (int)nf) {
+                    const u32 o = (f0 + f) * wo + jo;
+                    u64 v = acc[f];
+                    if (bias && row < nl) v = add_mod(v, bias[(size_t)o * nl + l], m.q);
+                    out[(size_t)(set * n_out + o) * out_stride + tile] = v;
+                }
+            }
+        }
+    }
+}
+
+// The conv's weighted sums on the matrix cores, exactly.  Per output limb
+// (modulus q), column j' and filter f the sum is sum_k x_k w_{f,k} mod q over
+// the column's terms k.  Each input word x_k < 2^63 is written in balanced
+// base 256, x_k = sum_a x_{k,a} 2^(8a) with signed digits, and the host
+// writes each w'_{f,k,a} = 2^(8a) w_{f,k} mod q in balanced base 256 too,
+// w' = sum_j d_{f,k,a,j} 2^(8j).  Then sum_k x_k w_{f,k} = sum_j 2^(8j) S_{f,j}
+// (mod q) with S_{f,j} = sum_{k,a} x_{k,a} d_{f,k,a,j}: an int8 dot product
+// (|S| < 2^31 for up to 16384 terms).  One v_mfma_i32_16x16x32_i8 takes 4
+// terms x 8 digits a on K and 16 coefficients on N; its 16 rows are
+// 4 filters x 4 digits j, and the four tiles T = 2h + e hold filters
+// 4h + 0..3 with j = 4e + 0..3, so that a lane's accumulators hold all eight
+// S_{f,j} of filters f = g and g + 4 (g = lane / 16) for its coefficient.
+// It folds them into a residue: in FP64 below 2^51 (three exact partial
+// sums, two of them times 2^24 and 2^48 mod q), else as a signed 128-bit
+// value reduced mod q.
+//
+// Table: lane l of (filter group, limb, K-step s, tile T) holds row
+// rho = l % 16 (filter 4h + rho / 4, digit j = 4e + rho % 4) for term
+// 4s + l / 16 of the column; byte a is d_{f,k,a,j}.  Columns with the same
+// weight rows share one table (col_at[j'] its offset).  Each wave covers 64
+// coefficients (four N-tiles) per pass with the weight words of a step held
+// across them; block order as in k_lincomb.
+typedef int v4i __attribute__((ext_vector_type(4)));
+constexpr u32 kMfmaMaxTerms = 16384;
+
+__device__ __forceinline__ u64 bal_bytes(u64 x)
+{
+    const u64 h = 0x8080808080808080ull;
+    return (x + h) ^ h;
+}
+
+template <bool kFp>
+__global__ __launch_bounds__(kThreads) void k_lincomb_mfma(u64* out, u64 out_stride, const u64* x, const u64* r,
+                                                           u32 n_x, u32 n_sets, u64 stride, u64 rstride,
+                                                           u64 ustride, const Term* terms, const u32* term_off,
+                                                           const u32* rot_end, const u64* at, const u64* col_at,
+                                                           const u64* bias, u32 nl, u32 nk, u32 lvl, u32 modoff,
+                                                           u32 x_limbs, u32 log_n, const ModQ* mq, u32 wo,
+                                                           u32 n_filters, u32 total, u32 per_xcd, u32 cpb)
+{
+    const u32 logical = (blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
+    if (logical >= total) return;
+    const u32 n = 1u << log_n;
+    const u32 passes = n / kThreads;
+    const u32 jo = logical % wo;
+    u32 rest = logical / wo;
+    const u32 set = rest % n_sets;
+    rest /= n_sets;
+    const u32 row = rest % (2 * nl);
+    const u32 pass0 = (rest / (2 * nl)) * cpb;
+    const u32 l = row % nl;
+    const ModQ m = mq[l < nk ? l : l == nk ? lvl : l + modoff];
+    const u64 q = m.q;
+    const bool x_has = l <= nk;
+    const u32 xl = l < nk ? l : lvl;
+    const u32 a = term_off[jo];
+    const u32 n_all = term_off[jo + 1] - a;
+    const u32 n_use = x_has ? n_all : rot_end[jo] - a;   // special limbs: rotated terms only
+    const u32 steps_all = (n_all + 3) / 4, steps = (n_use + 3) / 4;
+    const u32 n_out = n_filters * wo;
+    const u64* xb = x + (size_t)set * n_x * stride;
+    const u64* rb = r + (size_t)set * n_x * rstride;
+    constexpr u32 kColMask = (1u << kTermColBits) - 1;
+    const u32 lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const u32 g = lane >> 4, col = lane & 15;
+    // kFp: the rows below 2^51 (FP64 fold), else the others
+    if (kFp != (q < (1ull << 51))) return;
+    const double qd = (double)q, qinv = 1.0 / qd;
+    // 2^24, 2^48 mod q (balanced) for the FP64 fold; 2^128 mod q for the
+    // sign of the 128-bit fold
+    const u64 c24 = (1ull << 24) % q, c48 = (1ull << 48) % q;
+    const double c24b = to_bal(c24, q, qd), c48b = to_bal(c48, q, qd);
+    const u64 c128 = mul_mod(m.r64, m.r64, m);
+    const size_t xrow = ((size_t)(row / nl) * x_limbs + (x_has ? xl : 0)) * n;
+    const size_t orow = (size_t)row * n;
+    for (u32 f0 = 0, grp = 0; f0 < n_filters; f0 += kMaxFilters, grp++) {
+        const u64* tab = at + col_at[jo] + ((size_t)grp * nl + l) * steps_all * 256 + lane;
+        for (u32 cc = 0; cc < cpb && pass0 + cc < passes; cc++) {
+            const u32 base = (pass0 + cc) * kThreads + wave * 64 + col;   // N-tile nt adds 16 nt
+            v4i acc[4][4];
+#pragma unroll
+            for (int i = 0; i < 4; i++)
+#pragma unroll
+                for (int T = 0; T < 4; T++) acc[i][T] = v4i{0, 0, 0, 0};
+            for (u32 s = 0; s < steps; s++) {
+                long w[4];
+#pragma unroll
+                for (int T = 0; T < 4; T++) w[T] = (long)tab[((size_t)s * 4 + T) * 64];
+                const u32 k = 4 * s + g;
+                long b[4] = {0, 0, 0, 0};
+                if (k < n_use) {
+                    const Term tm = terms[a + k];
+                    const u32 u = tm.in_idx >> kTermColBits, j = tm.in_idx & kColMask;
+                    const u64* src = u == 0 ? xb + (size_t)j * stride + xrow
+                                            : rb + (u - 1) * ustride + (size_t)j * rstride + orow;
+#pragma unroll
+                    for (int i = 0; i < 4; i++) b[i] = (long)bal_bytes(src[base + 16 * i]);
+                }
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+#pragma unroll
+                    for (int T = 0; T < 4; T++)
+                        acc[i][T] = __builtin_amdgcn_mfma_i32_16x16x32_i8(w[T], b[i], acc[i][T], 0, 0, 0);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; i++) {
+                const u32 coef = base + 16 * i;
+#pragma unroll
+                for (int h = 0; h < 2; h++) {
+                    const u32 f = f0 + 4 * h + g;
+                    if (f >= n_filters) continue;
+                    const v4i lo4 = acc[i][2 * h], hi4 = acc[i][2 * h + 1];
+                    const u32 o = f * wo + jo;
+                    u64 v;
+                    if (kFp) {
+#pragma clang fp contract(off)
+                        const double A0 = __fma_rn((double)lo4[2], 65536.0, __fma_rn((double)lo4[1], 256.0, (double)lo4[0]));
+                        const double A1 = __fma_rn((double)hi4[1], 65536.0, __fma_rn((double)hi4[0], 256.0, (double)lo4[3]));
+                        const double A2 = __fma_rn((double)hi4[3], 256.0, (double)hi4[2]);
+                        double t = fbal(fmulmod(A1, c24b, qd, qinv) + fmulmod(A2, c48b, qd, qinv), qd, qinv) + A0;
+                        if (bias && row < nl) t += to_bal(bias[(size_t)o * nl + l], q, qd);
+                        v = to_canon(t, qd, qinv);
+                    } else {
+                        const i64 Plo = (i64)lo4[0] + ((i64)lo4[1] << 8) + ((i64)lo4[2] << 16) + ((i64)lo4[3] << 24);
+                        const i64 Phi = (i64)hi4[0] + ((i64)hi4[1] << 8) + ((i64)hi4[2] << 16) + ((i64)hi4[3] << 24);
+                        // V = Plo + Phi 2^32 in two's complement 128 bits
+                        const u64 x1 = (u64)Phi << 32;
+                        u64 lo = (u64)Plo + x1;
+                        u64 hi = (u64)(Plo >> 63) + (u64)(Phi >> 32) + (lo < x1 ? 1 : 0);
+                        v = reduce128(hi, lo, m);
+                        if ((i64)hi < 0) v = sub_mod(v, c128, q);   // the value read as 2^128 + V
+                        if (bias && row < nl) v = add_mod(v, bias[(size_t)o * nl + l], q);
+                    }
+                    out[(size_t)(set * n_out + o) * out_stride + orow + coef] = v;
                 }
             }
         }
@@ -990,6 +1290,18 @@ struct ConvPlan {
     // balanced FP64 weights per filter group g, limb l and term t (global
     // index), filter f: wt[((g nl + l) t_total + t) 8 + f] (moduli below 2^51)
     const double* wt = nullptr;
+    // 21-bit pieces of the canonical weights on the limbs of 2^51 or more
+    // (the set bits of wide_mask, n_wide of them):
+    // wp[(((g n_wide + wi) t_total + t) 8 + f) 3 + j]; none when a wide
+    // modulus reaches 2^63 or nl exceeds 64 (k_lincomb's integer path then)
+    const double* wp = nullptr;
+    u64 wide_mask = 0;
+    u32 n_wide = 0;
+    bool any_wide = false;   // some limb's modulus is 2^51 or more
+    // matrix-core tables (k_lincomb_mfma), one per distinct column pattern;
+    // col_at[j'] the offset of column j''s; absent when too large
+    const u64* at = nullptr;
+    const u64* col_at = nullptr;
     u32 t_total = 0, max_col = 0;   // terms in all, most terms of one column
 };
 
@@ -1082,13 +1394,91 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
                 }
     u32 max_col = 0;
     for (u32 jo = 0; jo < wo; jo++) max_col = std::max(max_col, off[jo + 1] - off[jo]);
+    // 21-bit pieces of the weights on the wide limbs
+    u64 wide_mask = 0;
+    bool wide_ok = nl <= 64, any_wide = false;
+    for (u32 l = 0; l < nl; l++) {
+        const u64 q = ctx->mod[mod_of(l)];
+        any_wide = any_wide || q >= (1ull << 51);
+        if (q >= (1ull << 51) && l < 64) wide_mask |= 1ull << l;
+        wide_ok = wide_ok && q < (1ull << 63);
+    }
+    if (!wide_ok) wide_mask = 0;
+    const u32 n_wide = (u32)__builtin_popcountll(wide_mask);
+    std::vector<double> wpv((size_t)groups * n_wide * t_total * kMaxFilters * kWidePieces, 0.0);
+    for (u32 g = 0, wi = 0; g < groups; g++, wi = 0)
+        for (u32 l = 0; l < nl; l++) {
+            if (!(wide_mask >> l & 1)) continue;
+            for (u32 t = 0; t < t_total; t++)
+                for (u32 f = 0; f < kMaxFilters; f++) {
+                    const u32 co = g * kMaxFilters + f;
+                    if (co >= C_out) continue;
+                    const u64 v = wv[terms[t].w_idx + co * fst + l];
+                    for (u32 j = 0; j < kWidePieces; j++)
+                        wpv[((((size_t)g * n_wide + wi) * t_total + t) * kMaxFilters + f) * kWidePieces + j] =
+                            (double)((v >> (21 * j)) & ((1ull << 21) - 1));
+                }
+            wi++;
+        }
     wfv.swap(wtv);
-    // one device buffer: terms | off | rot_end | w | ws | bias | wt (8-byte
-    // aligned parts)
+    // matrix-core tables: the balanced base-256 digits j of 2^(8a) w mod q
+    // for every (filter group, limb, step of 4 terms, tile, lane), one table
+    // per distinct sequence of weight rows (interior columns share one)
+    bool mfma_ok = ctx->log_n >= 8 && max_col <= kMfmaMaxTerms;
+    for (u32 l = 0; l < nl; l++) mfma_ok = mfma_ok && ctx->mod[mod_of(l)] < (1ull << 62);
+    std::vector<u64> atv, colv(wo, 0);
+    if (mfma_ok) {
+        std::map<std::vector<u32>, u64> seen;
+        for (u32 jo = 0; jo < wo && mfma_ok; jo++) {
+            std::vector<u32> sig;
+            for (u32 t = off[jo]; t < off[jo + 1]; t++) sig.push_back(terms[t].w_idx);
+            auto it = seen.find(sig);
+            if (it != seen.end()) {
+                colv[jo] = it->second;
+                continue;
+            }
+            const u32 nt = (u32)sig.size(), steps = (nt + 3) / 4;
+            const size_t at0 = atv.size();
+            if ((at0 + (size_t)groups * nl * steps * 256) * 8 > (512ull << 20)) {
+                mfma_ok = false;
+                break;
+            }
+            atv.resize(at0 + (size_t)groups * nl * steps * 256, 0);
+            for (u32 g = 0; g < groups; g++)
+                for (u32 l = 0; l < nl; l++) {
+                    const u64 q = ctx->mod[mod_of(l)];
+                    for (u32 kk = 0; kk < nt; kk++)
+                        for (u32 fr = 0; fr < kMaxFilters; fr++) {
+                            const u32 co = g * kMaxFilters + fr;
+                            if (co >= C_out) continue;
+                            const u64 wgt = wv[sig[kk] + co * fst + l];
+                            // bytes of w'_a = 2^(8a) w mod q, a = 0..7
+                            u64 e[8];
+                            for (u32 aa = 0; aa < 8; aa++)
+                                e[aa] = balanced_bytes_h((u64)(((u128)wgt << (8 * aa)) % q));
+                            const u32 s = kk / 4, lane_hi = kk % 4, h = fr / 4, fi = fr % 4;
+                            for (u32 ee = 0; ee < 2; ee++)
+                                for (u32 jr = 0; jr < 4; jr++) {
+                                    const u32 j = 4 * ee + jr, rho = 4 * fi + jr, T = 2 * h + ee;
+                                    u64 word = 0;
+                                    for (u32 aa = 0; aa < 8; aa++) word |= ((e[aa] >> (8 * j)) & 0xff) << (8 * aa);
+                                    atv[at0 + ((((size_t)g * nl + l) * steps + s) * 4 + T) * 64 + lane_hi * 16 + rho] =
+                                        word;
+                                }
+                        }
+                }
+            seen[sig] = at0;
+            colv[jo] = at0;
+        }
+    }
+    if (!mfma_ok) atv.clear();
+    // one device buffer: terms | off | rot_end | w | ws | bias | wt | wp
+    // (8-byte aligned parts)
     size_t b_terms = terms.size() * sizeof(Term), b_off = ((off.size() * 4 + 7) / 8) * 8;
     size_t b_rot = ((rot_end.size() * 4 + 7) / 8) * 8;
     b_off += b_rot;
-    size_t total = b_terms + b_off + (wv.size() + wsv.size() + bv.size() + wfv.size()) * 8;
+    const size_t n_words = wv.size() + wsv.size() + bv.size() + wfv.size() + wpv.size();
+    size_t total = b_terms + b_off + (n_words + (mfma_ok ? atv.size() + colv.size() : 0)) * 8;
     auto plan = std::make_shared<ConvPlan>();
     VR_HIP(hipDeviceSynchronize());
     plan->buf = dev_alloc(ctx, total, nullptr);
@@ -1102,6 +1492,11 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
     memcpy(h.data() + o + wv.size() * 8, wsv.data(), wsv.size() * 8);
     memcpy(h.data() + o + (wv.size() + wsv.size()) * 8, bv.data(), bv.size() * 8);
     memcpy(h.data() + o + (wv.size() + wsv.size() + bv.size()) * 8, wfv.data(), wfv.size() * 8);
+    memcpy(h.data() + o + (wv.size() + wsv.size() + bv.size() + wfv.size()) * 8, wpv.data(), wpv.size() * 8);
+    if (mfma_ok) {
+        memcpy(h.data() + o + n_words * 8, atv.data(), atv.size() * 8);
+        memcpy(h.data() + o + (n_words + atv.size()) * 8, colv.data(), colv.size() * 8);
+    }
     VR_HIP(hipMemcpy(base, h.data(), total, hipMemcpyHostToDevice));
     plan->terms = (const Term*)base;
     plan->off = (const u32*)(base + b_terms);
@@ -1110,6 +1505,14 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
     plan->ws = plan->w + wv.size();
     plan->bias = plan->ws + wsv.size();
     plan->wt = (const double*)(plan->bias + bv.size());
+    plan->wp = plan->wt + wfv.size();
+    plan->wide_mask = wide_mask;
+    plan->n_wide = n_wide;
+    plan->any_wide = any_wide;
+    if (mfma_ok) {
+        plan->at = plan->w + n_words;
+        plan->col_at = plan->at + atv.size();
+    }
     plan->t_total = t_total;
     plan->max_col = max_col;
     ctx->plans[key] = plan;
@@ -1176,11 +1579,7 @@ const u64* fc_weights(vr_context* ctx, const vr_plaintext* const* W_pt, size_t c
         contiguous = contiguous && W_pt[i]->data == p0->data + i * stride;
         compact = compact && W_pt[i]->clog == p0->clog && W_pt[i]->cdata == p0->cdata + i * cstride;
     }
-    {
-        std::lock_guard<std::mutex> g(ctx->mu);
-        auto it = ctx->tuning.find("fc_compact");
-        if (it != ctx->tuning.end() && it->second == 1) compact = false;
-    }
+    if (knob(ctx, "fc_compact") == 1) compact = false;
     *p_scale = p0->scale;
     // the layer runs at min(input level, weight level): nl limbs are read
     nl = std::min(nl, p0->level + 1);
@@ -1295,13 +1694,44 @@ void conv_lincomb_into(vr_context* ctx, const Slab& out, u32 out_at, const Slab&
     const u32 total = ((chunks + cpb - 1) / cpb) * 2 * nl * n_sets * wo;
     const u32 per_xcd = (total + 7) / 8;
     const size_t shmem = (size_t)std::min(plan.max_col, kTermChunk) * kMaxFilters * sizeof(double);
+    // rows on moduli of 2^51 or more by k_lincomb_wide unless the knob
+    // lincomb_wide is off (or the pieces do not apply): k_lincomb's integer
+    // products then
+    const bool wide = plan.n_wide > 0 && knob(ctx, "lincomb_wide") == 0;
     ProfScope prof(ctx, kProfLincomb, s, (u64)n_sets * n_out * 2 * nl);
-    hipLaunchKernelGGL(k_lincomb, dim3(8 * per_xcd), dim3(kThreads), shmem, s, out.ct(out_at), out.stride, x.ct(x_at),
-                       cr.rot.empty() ? x.ct(x_at) : r.ct(r_at), C_in * w, n_sets, x.stride, r.stride,
-                       (u64)r.n * r.stride, plan.terms, plan.off, plan.rot_end, plan.w, plan.ws, plan.wt,
-                       plan.t_total, C_in * k * k, plan.bias, nl, nk, level, ctx->L - nk, nq, ctx->log_n,
-                       ctx->d_modq, wo, C_out, total, per_xcd, cpb);
-    VR_CHECK_LAUNCH();
+    if (plan.at && knob(ctx, "lincomb_mfma") == 0) {
+        for (int fp = 1; fp >= 0; fp--) {
+            if (!fp && !plan.any_wide) break;
+            hipLaunchKernelGGL(fp ? k_lincomb_mfma<true> : k_lincomb_mfma<false>, dim3(8 * per_xcd), dim3(kThreads),
+                               0, s, out.ct(out_at), out.stride, x.ct(x_at), cr.rot.empty() ? x.ct(x_at) : r.ct(r_at),
+                               C_in * w, n_sets, x.stride, r.stride, (u64)r.n * r.stride, plan.terms, plan.off,
+                               plan.rot_end, plan.at, plan.col_at, plan.bias, nl, nk, level, ctx->L - nk, nq,
+                               ctx->log_n, ctx->d_modq, wo, C_out, total, per_xcd, cpb);
+            VR_CHECK_LAUNCH();
+        }
+        return;
+    }
+    for (int fp = 1; fp >= 0; fp--) {
+        if (!fp && (wide || !plan.any_wide)) break;
+        hipLaunchKernelGGL(fp ? k_lincomb<true> : k_lincomb<false>, dim3(8 * per_xcd), dim3(kThreads),
+                           fp ? shmem : 0, s, out.ct(out_at), out.stride, x.ct(x_at),
+                           cr.rot.empty() ? x.ct(x_at) : r.ct(r_at), C_in * w, n_sets, x.stride, r.stride,
+                           (u64)r.n * r.stride, plan.terms, plan.off, plan.rot_end, plan.w, plan.ws, plan.wt,
+                           plan.t_total, C_in * k * k, plan.bias, nl, nk, level, ctx->L - nk, nq, ctx->log_n,
+                           ctx->d_modq, wo, C_out, total, per_xcd, cpb);
+        VR_CHECK_LAUNCH();
+    }
+    if (wide) {
+        const u32 wtotal = ((chunks + cpb - 1) / cpb) * 2 * plan.n_wide * n_sets * wo;
+        const u32 wper = (wtotal + 7) / 8;
+        const size_t wsh = (size_t)std::min(plan.max_col, kWideChunk) * kMaxFilters * kWidePieces * sizeof(double);
+        hipLaunchKernelGGL(k_lincomb_wide, dim3(8 * wper), dim3(kThreads), wsh, s, out.ct(out_at), out.stride,
+                           x.ct(x_at), cr.rot.empty() ? x.ct(x_at) : r.ct(r_at), C_in * w, n_sets, x.stride,
+                           r.stride, (u64)r.n * r.stride, plan.terms, plan.off, plan.rot_end, plan.wp, plan.t_total,
+                           plan.bias, nl, nk, level, ctx->L - nk, nq, ctx->log_n, ctx->d_modq, wo, C_out,
+                           plan.wide_mask, plan.n_wide, wtotal, wper, cpb);
+        VR_CHECK_LAUNCH();
+    }
 }
 
 // Conv layer over n_sets image sets laid out in one slab (set s occupies
@@ -1545,12 +1975,7 @@ Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab&
     const double y_scale = out_scale / (double)ctx->mod[level];
     const u32 fl0 = std::min(level - 1, d0.fc_level);
     const bool lazy_fc = d0.square && d0.fc_out && square_fc_lazy(ctx, y_scale, d0.fc_scale, fl0);
-    bool prune = true;
-    {
-        std::lock_guard<std::mutex> g(ctx->mu);
-        auto it = ctx->tuning.find("conv_prune");
-        if (it != ctx->tuning.end()) prune = it->second == 0;
-    }
+    const bool prune = knob(ctx, "conv_prune") == 0;
     const u32 keep = lazy_fc && prune && fl0 + 1 < level ? fl0 + 1 : 0;
     ConvRot cr = conv_rotations(ctx, kin, x, d0.k, s, keep);
     u32 n_conv = 0;

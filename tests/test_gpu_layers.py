@@ -393,10 +393,12 @@ def test_cnn128_full_level_chunked_key_switching():
 def test_cnn128_network_level24_pruned_equals_full():
     """The headline network (3x128x128, conv 3x3/2 pad 1 x8, x^2, FC 32768 ->
     10 with its weights at level 3) entering at level 24: the network call,
-    whose conv makes only the 4 limbs the FC reads and whose FC reads the
-    compact weight copies, gives the same words as with every conv limb made
-    and dropped after and the full weight limbs read (conv_prune and
-    fc_compact off), and its logits decode to the FP64 network."""
+    whose conv makes only the 4 limbs the FC reads (its weighted sums as
+    int8 matrix-core products) and whose FC reads the compact weight copies,
+    gives the same words as with every conv limb made and dropped after, the
+    sums as FP64 and 64-bit integer products and the full weight limbs read
+    (conv_prune, lincomb_mfma, lincomb_wide and fc_compact off), and its
+    logits decode to the FP64 network."""
     from paper_2512_18646_amd import vr
     W = SI.CNN_128
     Hp = Ly.image_block(W.h, W.pad)
@@ -410,13 +412,14 @@ def test_cnn128_network_level24_pruned_equals_full():
     net = vr.CNN(W.channels, W.h, W.w, W.pad, K, bias, W.stride, square=True, fc_w=pts, fc_bias=bfc,
                  fc_block=Hp)
     out = net.forward(g, gk, cols)
-    g.set_tuning("conv_prune", "off")
-    g.set_tuning("fc_compact", "off")
+    knobs = ("conv_prune", "fc_compact", "lincomb_wide", "lincomb_mfma")
+    for kn in knobs:
+        g.set_tuning(kn, "off")
     try:
         full = net.forward(g, gk, cols)
     finally:
-        g.set_tuning("conv_prune", "on")
-        g.set_tuning("fc_compact", "on")
+        for kn in knobs:
+            g.set_tuning(kn, "on")
     assert len(out) == len(full) == W.fc_out
     for i, (a, b) in enumerate(zip(out, full)):
         assert a.meta == b.meta and a.meta[1] == 1, i
