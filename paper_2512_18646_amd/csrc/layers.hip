@@ -697,57 +697,125 @@ __global__ __launch_bounds__(kThreads) void k_compact_runs(const u64* in, u64* o
 }
 
 // FC weight products of the x^2 tensors (lazy relinearisation): for outputs
-// o0 .. o0 + kFcGroup - 1 and limb l,
+// o0 .. o0 + kSqfcGroup - 1 (o0 = blockIdx.z * kSqfcGroup) and limb l,
 //   out_o = sum_i (y_i0^2, 2 y_i0 y_i1, y_i1^2) P[o][i]     (3 components),
-// the tensor of each input formed once per limb and weight group.
+// the tensor of each input formed once per limb and output group (one group
+// holds the ten classes of the paper's networks).  A block covers 64
+// coefficients; its four waves take every fourth input each and their
+// residues are summed through LDS at the end.  kFp: the limbs below 2^51, as
+// exact FP64 products (balanced operands, sums reduced every four inputs);
+// otherwise 128-bit integer sums (the others return at once).
+constexpr int kSqfcGroup = 10;
+constexpr u32 kSqfcWaves = 4;
+
+template <bool kFp>
 __global__ __launch_bounds__(kThreads) void k_sqfc_acc(u64* out, u64 out_stride, const u64* Y, u64 y_stride,
                                                        u64 y_comp, u32 n_in, const u64* P, u64 p_stride,
                                                        u32 n_out, u32 nl, u32 log_n, const ModQ* mq, u32 rep)
 {
+    __shared__ u64 red[kSqfcWaves - 1][kSqfcGroup][64];
     const u32 n = 1u << log_n;
-    const u32 t = blockIdx.x * kThreads + threadIdx.x;
-    if (t >= n) return;
+    const u32 lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const u32 t = blockIdx.x * 64 + lane;   // n is a multiple of 64
     const u32 l = blockIdx.y;
-    const u32 o0 = blockIdx.z * kFcGroup;
-    const u32 cnt = min((u32)kFcGroup, n_out - o0);
+    const u32 o0 = blockIdx.z * kSqfcGroup;
+    const u32 cnt = min((u32)kSqfcGroup, n_out - o0);
     const ModQ m = mq[l];
-    u64 h[3][kFcGroup], lo[3][kFcGroup];
-#pragma unroll
-    for (int c = 0; c < 3; c++)
-#pragma unroll
-        for (int g = 0; g < kFcGroup; g++) h[c][g] = lo[c][g] = 0;
+    if (kFp != (m.q < (1ull << 51))) return;   // whole blocks: no barrier is skipped
     const size_t off0 = (size_t)l * n + t, yoff1 = y_comp + off0;
     const size_t poff = (size_t)l * (n >> rep) + (t >> rep);   // weights: runs of 2^rep words kept once
-    for (u32 i = 0; i < n_in; i++) {
-        const u64 y0 = Y[(size_t)i * y_stride + off0];
-        const u64 y1 = Y[(size_t)i * y_stride + yoff1];
-        const u64 x01 = mul_mod(y0, y1, m);
-        const u64 d[3] = {mul_mod(y0, y0, m), add_mod(x01, x01, m.q), mul_mod(y1, y1, m)};
+    const u64* Pg = P + (size_t)o0 * n_in * p_stride + poff;
+    u64 res[3][kSqfcGroup];   // this wave's residues
+    if (kFp) {
+        const double qd = (double)m.q, qinv = 1.0 / qd;
+        double acc[3][kSqfcGroup];
 #pragma unroll
-        for (int g = 0; g < kFcGroup; g++) {
-            if (g < (int)cnt) {
-                const u64 p = P[((size_t)(o0 + g) * n_in + i) * p_stride + poff];
+        for (int c = 0; c < 3; c++)
 #pragma unroll
-                for (int c = 0; c < 3; c++) mac128(h[c][g], lo[c][g], d[c], p);
+            for (int g = 0; g < kSqfcGroup; g++) acc[c][g] = 0;
+        u32 k = 0;
+        for (u32 i = wave; i < n_in; i += kSqfcWaves, k++) {
+            const double y0 = to_bal(Y[(size_t)i * y_stride + off0], m.q, qd);
+            const double y1 = to_bal(Y[(size_t)i * y_stride + yoff1], m.q, qd);
+            const double x01 = fmulmod(y0, y1, qd, qinv);
+            // the tensor balanced again (|d| <= q / 2 + 1): each weight
+            // product within 0.75 q
+            const double d[3] = {fbal(fmulmod(y0, y0, qd, qinv), qd, qinv), fbal(x01 + x01, qd, qinv),
+                                 fbal(fmulmod(y1, y1, qd, qinv), qd, qinv)};
+#pragma unroll
+            for (int g = 0; g < kSqfcGroup; g++) {
+                if (g < (int)cnt) {
+                    const double p = to_bal(Pg[((size_t)g * n_in + i) * p_stride], m.q, qd);
+#pragma unroll
+                    for (int c = 0; c < 3; c++) acc[c][g] += fmulmod(d[c], p, qd, qinv);
+                }
+            }
+            if ((k & 3) == 3) {   // below 3.5 q < 2^53
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+#pragma unroll
+                    for (int g = 0; g < kSqfcGroup; g++) acc[c][g] = fbal(acc[c][g], qd, qinv);
             }
         }
-        if ((i & 31) == 31) {   // keep every 128-bit sum below 2^127
 #pragma unroll
-            for (int c = 0; c < 3; c++)
+        for (int c = 0; c < 3; c++)
 #pragma unroll
-                for (int g = 0; g < kFcGroup; g++) {
-                    lo[c][g] = reduce128(h[c][g], lo[c][g], m);
-                    h[c][g] = 0;
+            for (int g = 0; g < kSqfcGroup; g++) res[c][g] = to_canon(acc[c][g], qd, qinv);
+    } else {
+        u64 h[3][kSqfcGroup], lo[3][kSqfcGroup];
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+#pragma unroll
+            for (int g = 0; g < kSqfcGroup; g++) h[c][g] = lo[c][g] = 0;
+        u32 k = 0;
+        for (u32 i = wave; i < n_in; i += kSqfcWaves, k++) {
+            const u64 y0 = Y[(size_t)i * y_stride + off0];
+            const u64 y1 = Y[(size_t)i * y_stride + yoff1];
+            const u64 x01 = mul_mod(y0, y1, m);
+            const u64 d[3] = {mul_mod(y0, y0, m), add_mod(x01, x01, m.q), mul_mod(y1, y1, m)};
+#pragma unroll
+            for (int g = 0; g < kSqfcGroup; g++) {
+                if (g < (int)cnt) {
+                    const u64 p = Pg[((size_t)g * n_in + i) * p_stride];
+#pragma unroll
+                    for (int c = 0; c < 3; c++) mac128(h[c][g], lo[c][g], d[c], p);
                 }
+            }
+            if ((k & 31) == 31) {   // keep every 128-bit sum below 2^127
+#pragma unroll
+                for (int c = 0; c < 3; c++)
+#pragma unroll
+                    for (int g = 0; g < kSqfcGroup; g++) {
+                        lo[c][g] = reduce128(h[c][g], lo[c][g], m);
+                        h[c][g] = 0;
+                    }
+            }
         }
+#pragma unroll
+        for (int c = 0; c < 3; c++)
+#pragma unroll
+            for (int g = 0; g < kSqfcGroup; g++) res[c][g] = reduce128(h[c][g], lo[c][g], m);
     }
+    // sum the waves' residues, one component at a time
 #pragma unroll
-    for (int g = 0; g < kFcGroup; g++) {
-        if (g < (int)cnt) {
-            u64* o = out + (size_t)(o0 + g) * out_stride + off0;
+    for (int c = 0; c < 3; c++) {
+        if (wave > 0) {
 #pragma unroll
-            for (int c = 0; c < 3; c++) o[(size_t)c * nl * n] = reduce128(h[c][g], lo[c][g], m);
+            for (int g = 0; g < kSqfcGroup; g++) red[wave - 1][g][lane] = res[c][g];
         }
+        __syncthreads();
+        if (wave == 0) {
+#pragma unroll
+            for (int g = 0; g < kSqfcGroup; g++) {
+                if (g < (int)cnt) {
+                    u64 v = res[c][g];
+#pragma unroll
+                    for (u32 w = 0; w + 1 < kSqfcWaves; w++) v = add_mod(v, red[w][g][lane], m.q);
+                    out[(size_t)(o0 + g) * out_stride + (size_t)c * nl * n + off0] = v;
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -2034,11 +2102,17 @@ Slab run_cnn_multi(vr_context* ctx, const std::vector<NetSeg>& segs, const Slab&
         for (u32 st = 0; st < g.n_sets; st++) {
             dim3 grid((ctx->n + kThreads - 1) / kThreads, fl + 1, (d.fc_out + kFcGroup - 1) / kFcGroup);
             ProfScope prof(ctx, kProfTensor, s, (u64)d.fc_out * (lazy_fc ? 3 : 2) * (fl + 1));
-            if (lazy_fc)
-                hipLaunchKernelGGL(k_sqfc_acc, grid, dim3(kThreads), 0, s, z.ct(z_at + st * d.fc_out), z.stride,
-                                   y.ct(y_at + st * per), y.stride, (u64)(y.level + 1) * ctx->n, per, d.fc_P,
-                                   d.fc_stride, d.fc_out, fl + 1, ctx->log_n, ctx->d_modq, d.fc_rep);
-            else
+            if (lazy_fc) {
+                // FP64 rows, then the rows of 2^51 or more
+                const dim3 sg(ctx->n / 64, fl + 1, (d.fc_out + kSqfcGroup - 1) / kSqfcGroup);
+                for (int fp = 1; fp >= 0; fp--) {
+                    hipLaunchKernelGGL(fp ? k_sqfc_acc<true> : k_sqfc_acc<false>, sg, dim3(kThreads), 0, s,
+                                       z.ct(z_at + st * d.fc_out), z.stride, y.ct(y_at + st * per), y.stride,
+                                       (u64)(y.level + 1) * ctx->n, per, d.fc_P, d.fc_stride, d.fc_out, fl + 1,
+                                       ctx->log_n, ctx->d_modq, d.fc_rep);
+                    VR_CHECK_LAUNCH();
+                }
+            } else
                 hipLaunchKernelGGL(k_mulplain_acc, grid, dim3(kThreads), 0, s, z.ct(z_at + st * d.fc_out), z.stride,
                                    y.ct(y_at + st * per), y.stride, (u64)(y.level + 1) * ctx->n, per, d.fc_P,
                                    d.fc_stride, d.fc_out, fl + 1, ctx->log_n, ctx->d_modq, d.fc_rep);
