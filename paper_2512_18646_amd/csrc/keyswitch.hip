@@ -330,13 +330,23 @@ struct LimbRuns {
 };
 VR_KERNEL_ARG(LimbRuns);
 
-template <int MAXB, bool FP>
+// Up to two rotation steps per launch (NS): step k has its key, its output
+// slab and g_inv; every digit word (and the c0 word of the fold) is read
+// once for both, and each step writes its own permuted chunk.
+struct KsSteps {
+    const u64* key[2];
+    u64* U[2];
+    u32 g_inv[2];
+};
+VR_KERNEL_ARG(KsSteps);
+
+template <int MAXB, bool FP, int NS>
 __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_stride, const u64* D,
-                                                      u64 d_stride, u32 n_ct, const u64* key, u32 nmod,
+                                                      u64 d_stride, u32 n_ct, KsSteps st, u32 nmod,
                                                       u32 level, u32 next, u32 beta, u32 alpha, u32 L,
-                                                      u32 log_n, u32 g_inv, u64* U, u64 u_stride,
-                                                      const ModQ* mq, LimbRuns runs, const u64* F,
-                                                      u64 f_stride, const ulonglong2* pmod, u32 u_limbs)
+                                                      u32 log_n, u64 u_stride, const ModQ* mq, LimbRuns runs,
+                                                      const u64* F, u64 f_stride, const ulonglong2* pmod,
+                                                      u32 u_limbs)
 {
     const u32 n = 1u << log_n;
     const u32 s = blockIdx.x * kThreads + threadIdx.x;
@@ -347,7 +357,9 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
     e += runs.b[r];
     const u32 mod = e <= level ? e : L + 1 + (e - level - 1);
     const ModQ m = mq[mod];
-    const u32 t = g_inv != 1 ? galois_src(s, g_inv, log_n) : s;
+    u32 t[NS];
+#pragma unroll
+    for (int k = 0; k < NS; k++) t[k] = st.g_inv[k] != 1 ? galois_src(s, st.g_inv[k], log_n) : s;
     // blockIdx.z splits the ciphertexts into groups so small rings still fill the chip
     const u32 per = (n_ct + gridDim.z - 1) / gridDim.z;
     const u32 c_lo = blockIdx.z * per, c_hi = min(n_ct, c_lo + per);
@@ -364,63 +376,80 @@ __global__ __launch_bounds__(kThreads) void k_ks_inner(const u64* X, u64 x_strid
     if constexpr (FP) {
         const double qd = (double)m.q, qinv = 1.0 / qd;
         const double pf = F && e <= level ? to_bal(pmod[mod].x, m.q, qd) : 0.0;
-        double fb[MAXB], fa[MAXB];
+        double fb[NS][MAXB], fa[NS][MAXB];
 #pragma unroll
-        for (int j = 0; j < MAXB; j++) {
-            if (j < (int)beta) {
-                fb[j] = to_bal(key[((size_t)(2 * j) * nmod + mod) * n + t], m.q, qd);
-                fa[j] = to_bal(key[((size_t)(2 * j + 1) * nmod + mod) * n + t], m.q, qd);
+        for (int k = 0; k < NS; k++)
+#pragma unroll
+            for (int j = 0; j < MAXB; j++) {
+                if (j < (int)beta) {
+                    fb[k][j] = to_bal(st.key[k][((size_t)(2 * j) * nmod + mod) * n + t[k]], m.q, qd);
+                    fa[k][j] = to_bal(st.key[k][((size_t)(2 * j + 1) * nmod + mod) * n + t[k]], m.q, qd);
+                }
             }
-        }
         u64 xv[MAXB], xn[MAXB];
         load(c_lo, xv);
         for (u32 c = c_lo; c < c_hi; c++) {
             if (c + 1 < c_hi) load(c + 1, xn);
-            double s0 = 0, s1 = 0;
+            double x[MAXB];
 #pragma unroll
-            for (int j = 0; j < MAXB; j++) {
-                if (j < (int)beta) {
-                    const double x = to_bal(xv[j], m.q, qd);
-                    s0 += fmulmod(x, fb[j], qd, qinv);
-                    s1 += fmulmod(x, fa[j], qd, qinv);
-                    if ((j & 3) == 3) {
-                        s0 = fbal(s0, qd, qinv);
-                        s1 = fbal(s1, qd, qinv);
+            for (int j = 0; j < MAXB; j++)
+                if (j < (int)beta) x[j] = to_bal(xv[j], m.q, qd);
+            // + P sigma_g(c0): c0 read where X is, stored where U is
+            const double fc = F && e <= level
+                                  ? fmulmod(to_bal(F[(size_t)c * f_stride + (size_t)e * n + s], m.q, qd), pf, qd, qinv)
+                                  : 0.0;
+#pragma unroll
+            for (int k = 0; k < NS; k++) {
+                double s0 = 0, s1 = 0;
+#pragma unroll
+                for (int j = 0; j < MAXB; j++) {
+                    if (j < (int)beta) {
+                        s0 += fmulmod(x[j], fb[k][j], qd, qinv);
+                        s1 += fmulmod(x[j], fa[k][j], qd, qinv);
+                        if ((j & 3) == 3) {
+                            s0 = fbal(s0, qd, qinv);
+                            s1 = fbal(s1, qd, qinv);
+                        }
                     }
                 }
+                s0 += fc;
+                u64* u = st.U[k] + (size_t)c * u_stride + (size_t)pos * n + t[k];
+                u[0] = to_canon(s0, qd, qinv);
+                u[(size_t)u_limbs * n] = to_canon(s1, qd, qinv);
             }
-            if (F && e <= level)   // + P sigma_g(c0): c0 read where X is, stored where U is
-                s0 += fmulmod(to_bal(F[(size_t)c * f_stride + (size_t)e * n + s], m.q, qd), pf, qd, qinv);
-            u64* u = U + (size_t)c * u_stride + (size_t)pos * n + t;
-            u[0] = to_canon(s0, qd, qinv);
-            u[(size_t)u_limbs * n] = to_canon(s1, qd, qinv);
 #pragma unroll
             for (int j = 0; j < MAXB; j++) xv[j] = xn[j];
         }
     } else {
-        u64 kb[MAXB], ka[MAXB];
+        u64 kb[NS][MAXB], ka[NS][MAXB];
 #pragma unroll
-        for (int j = 0; j < MAXB; j++) {
-            if (j < (int)beta) {
-                kb[j] = key[((size_t)(2 * j) * nmod + mod) * n + t];
-                ka[j] = key[((size_t)(2 * j + 1) * nmod + mod) * n + t];
-            }
-        }
-        for (u32 c = c_lo; c < c_hi; c++) {
-            u64 xv[MAXB];
-            load(c, xv);
-            u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+        for (int k = 0; k < NS; k++)
 #pragma unroll
             for (int j = 0; j < MAXB; j++) {
                 if (j < (int)beta) {
-                    mac128(h0, l0, xv[j], kb[j]);
-                    mac128(h1, l1, xv[j], ka[j]);
+                    kb[k][j] = st.key[k][((size_t)(2 * j) * nmod + mod) * n + t[k]];
+                    ka[k][j] = st.key[k][((size_t)(2 * j + 1) * nmod + mod) * n + t[k]];
                 }
             }
-            if (F && e <= level) mac128(h0, l0, F[(size_t)c * f_stride + (size_t)e * n + s], pmod[mod].x);
-            u64* u = U + (size_t)c * u_stride + (size_t)pos * n + t;
-            u[0] = reduce128(h0, l0, m);
-            u[(size_t)u_limbs * n] = reduce128(h1, l1, m);
+        for (u32 c = c_lo; c < c_hi; c++) {
+            u64 xv[MAXB];
+            load(c, xv);
+            const u64 fw = F && e <= level ? F[(size_t)c * f_stride + (size_t)e * n + s] : 0;
+#pragma unroll
+            for (int k = 0; k < NS; k++) {
+                u64 h0 = 0, l0 = 0, h1 = 0, l1 = 0;
+#pragma unroll
+                for (int j = 0; j < MAXB; j++) {
+                    if (j < (int)beta) {
+                        mac128(h0, l0, xv[j], kb[k][j]);
+                        mac128(h1, l1, xv[j], ka[k][j]);
+                    }
+                }
+                if (F && e <= level) mac128(h0, l0, fw, pmod[mod].x);
+                u64* u = st.U[k] + (size_t)c * u_stride + (size_t)pos * n + t[k];
+                u[0] = reduce128(h0, l0, m);
+                u[(size_t)u_limbs * n] = reduce128(h1, l1, m);
+            }
         }
     }
 }
@@ -869,9 +898,24 @@ void keyswitch_modup(vr_context* ctx, const u64* d, u32 level, u64* X, u64* coef
     keyswitch_modup_batch(ctx, d, (u64)(level + 1) * ctx->n, 1, level, X, coef, s);
 }
 
-void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u64* d, u64 d_stride,
-                           u32 n_ct, const u64* key, u32 level, u32 g, u64* U, u64 u_stride,
-                           hipStream_t s, const u64* fold_c0, u64 fold_stride, u32 keep_q)
+namespace {
+
+// inverse of g modulo 2N: the odd residues mod 2N = 2^(log N + 1) have
+// exponent N/2, so g^-1 = g^(N/2 - 1)
+u32 galois_inverse(vr_context* ctx, u32 g)
+{
+    const u64 two_n = 2ull * ctx->n;
+    if (g == 1) return 1;
+    u64 r = 1;
+    for (u64 x = g % two_n, ee = two_n / 4 - 1; ee; ee >>= 1, x = x * x % two_n)
+        if (ee & 1) r = r * x % two_n;
+    if (r * g % two_n != 1) throw Error(VR_EINVAL, "key switching: no inverse Galois element");
+    return (u32)r;
+}
+
+void ks_inner_launch(vr_context* ctx, const u64* X, u64 x_stride, const u64* d, u64 d_stride, u32 n_ct,
+                     const KsSteps& st, u32 ns, u32 level, u64 u_stride, hipStream_t s, const u64* fold_c0,
+                     u64 fold_stride, u32 keep_q)
 {
     KsShape k = ks_shape(ctx, level);
     // at least ~4096 blocks: split the ciphertexts (each group re-reads the key)
@@ -880,20 +924,9 @@ void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u6
     if (groups > n_ct) groups = n_ct;
     if (groups < 1) groups = 1;
     dim3 grid((ctx->n + kThreads - 1) / kThreads, k.next, groups);
-    // inverse of g modulo 2N: the odd residues mod 2N = 2^(log N + 1) have
-    // exponent N/2, so g^-1 = g^(N/2 - 1)
-    const u64 two_n = 2ull * ctx->n;
-    u32 g_inv = 1;
-    if (g != 1) {
-        u64 r = 1;
-        for (u64 x = g % two_n, ee = two_n / 4 - 1; ee; ee >>= 1, x = x * x % two_n)
-            if (ee & 1) r = r * x % two_n;
-        if (r * g % two_n != 1) throw Error(VR_EINVAL, "key switching: no inverse Galois element");
-        g_inv = (u32)r;
-    }
     const u32 u_limbs = keep_q ? keep_q + 1 + ctx->K : k.next;
     if (keep_q > level) throw Error(VR_EINVAL, "key switching: kept limbs above the level");
-    ProfScope prof(ctx, kProfKsInner, s, (u64)n_ct * u_limbs);
+    ProfScope prof(ctx, kProfKsInner, s, (u64)n_ct * u_limbs * ns);
     if (k.beta > 16) throw Error(VR_EINVAL, "key switching: more than 16 digits");
     // one launch per path (FP64 below 2^51, else integer) over its runs of
     // consecutive extended limbs, so each kernel gets its own registers
@@ -919,30 +952,71 @@ void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u6
                 rows += runs[r].second;
             }
             dim3 g2(grid.x, rows, grid.z);
-#define VR_KS_INNER(B, F)                                                                             \
-    hipLaunchKernelGGL((k_ks_inner<B, F>), g2, dim3(kThreads), 0, s, X, x_stride, d, d_stride, n_ct, key, \
-                       ctx->nmod(), level, k.next, k.beta, ctx->alpha, ctx->L, ctx->log_n, g_inv, U,   \
-                       u_stride, ctx->d_modq, lr, fold_c0, fold_stride, ctx->d_pmod_tab, u_limbs)
+#define VR_KS_INNER(B, F, S)                                                                               \
+    hipLaunchKernelGGL((k_ks_inner<B, F, S>), g2, dim3(kThreads), 0, s, X, x_stride, d, d_stride, n_ct, st,   \
+                       ctx->nmod(), level, k.next, k.beta, ctx->alpha, ctx->L, ctx->log_n, u_stride, ctx->d_modq, \
+                       lr, fold_c0, fold_stride, ctx->d_pmod_tab, u_limbs)
+#define VR_KS_INNER_S(B, F)      \
+    if (ns == 2)                 \
+        VR_KS_INNER(B, F, 2);    \
+    else                         \
+        VR_KS_INNER(B, F, 1)
             if (k.beta <= 4) {
                 if (fp)
-                    VR_KS_INNER(4, true);
+                    VR_KS_INNER_S(4, true);
                 else
-                    VR_KS_INNER(4, false);
+                    VR_KS_INNER_S(4, false);
             } else if (k.beta <= 8) {
                 if (fp)
-                    VR_KS_INNER(8, true);
+                    VR_KS_INNER_S(8, true);
                 else
-                    VR_KS_INNER(8, false);
+                    VR_KS_INNER_S(8, false);
             } else {
                 if (fp)
-                    VR_KS_INNER(16, true);
+                    VR_KS_INNER(16, true, 1);
                 else
-                    VR_KS_INNER(16, false);
+                    VR_KS_INNER(16, false, 1);
             }
+#undef VR_KS_INNER_S
 #undef VR_KS_INNER
             VR_CHECK_LAUNCH();
         }
     }
+}
+
+}  // namespace
+
+void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u64* d, u64 d_stride,
+                           u32 n_ct, const u64* key, u32 level, u32 g, u64* U, u64 u_stride,
+                           hipStream_t s, const u64* fold_c0, u64 fold_stride, u32 keep_q)
+{
+    KsSteps st = {};
+    st.key[0] = key;
+    st.U[0] = U;
+    st.g_inv[0] = galois_inverse(ctx, g);
+    ks_inner_launch(ctx, X, x_stride, d, d_stride, n_ct, st, 1, level, u_stride, s, fold_c0, fold_stride, keep_q);
+}
+
+void keyswitch_inner_batch2(vr_context* ctx, const u64* X, u64 x_stride, const u64* d, u64 d_stride,
+                            u32 n_ct, const u64* key0, const u64* key1, u32 level, u32 g0, u32 g1, u64* U0,
+                            u64* U1, u64 u_stride, hipStream_t s, const u64* fold_c0, u64 fold_stride,
+                            u32 keep_q)
+{
+    if (ks_shape(ctx, level).beta > 8) {   // one step at a time (registers)
+        keyswitch_inner_batch(ctx, X, x_stride, d, d_stride, n_ct, key0, level, g0, U0, u_stride, s, fold_c0,
+                              fold_stride, keep_q);
+        keyswitch_inner_batch(ctx, X, x_stride, d, d_stride, n_ct, key1, level, g1, U1, u_stride, s, fold_c0,
+                              fold_stride, keep_q);
+        return;
+    }
+    KsSteps st = {};
+    st.key[0] = key0;
+    st.key[1] = key1;
+    st.U[0] = U0;
+    st.U[1] = U1;
+    st.g_inv[0] = galois_inverse(ctx, g0);
+    st.g_inv[1] = galois_inverse(ctx, g1);
+    ks_inner_launch(ctx, X, x_stride, d, d_stride, n_ct, st, 2, level, u_stride, s, fold_c0, fold_stride, keep_q);
 }
 
 

@@ -1001,13 +1001,21 @@ void rotate_slab_ext(vr_context* ctx, const std::vector<KeyRange>& keys, const S
     for (u32 c0 = 0; c0 < n_ct; c0 += cs) {
         const u32 nc = std::min(cs, n_ct - c0);
         keyswitch_modup_batch(ctx, in.ct(c0) + (size_t)k.nq * n, in.stride, nc, level, X, coef, s, keep);
-        for (size_t si = 0; si < steps.size(); si++)
+        // the steps two at a time: each digit word read once for both
+        for (size_t si = 0; si < steps.size(); si += 2)
             for (const KeyRange& kr : keys) {
                 const u32 lo = std::max(kr.begin, c0), hi = std::min(kr.end, c0 + nc);
                 if (lo >= hi) continue;
-                keyswitch_inner_batch(ctx, X + (size_t)(lo - c0) * xs, xs, in.ct(lo) + (size_t)k.nq * n, in.stride,
-                                      hi - lo, rot_key(kr.ek, gs[si]).data, level, gs[si], out[si].ct(lo),
-                                      all.stride, s, in.ct(lo), in.stride, keep);
+                if (si + 1 < steps.size())
+                    keyswitch_inner_batch2(ctx, X + (size_t)(lo - c0) * xs, xs, in.ct(lo) + (size_t)k.nq * n,
+                                           in.stride, hi - lo, rot_key(kr.ek, gs[si]).data,
+                                           rot_key(kr.ek, gs[si + 1]).data, level, gs[si], gs[si + 1],
+                                           out[si].ct(lo), out[si + 1].ct(lo), all.stride, s, in.ct(lo), in.stride,
+                                           keep);
+                else
+                    keyswitch_inner_batch(ctx, X + (size_t)(lo - c0) * xs, xs, in.ct(lo) + (size_t)k.nq * n,
+                                          in.stride, hi - lo, rot_key(kr.ek, gs[si]).data, level, gs[si],
+                                          out[si].ct(lo), all.stride, s, in.ct(lo), in.stride, keep);
             }
     }
 }

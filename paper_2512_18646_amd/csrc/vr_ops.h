@@ -81,6 +81,12 @@ void keyswitch_inner_batch(vr_context* ctx, const u64* X, u64 x_stride, const u6
                            u32 n_ct, const u64* key, u32 level, u32 g, u64* U, u64 u_stride,
                            hipStream_t s, const u64* fold_c0 = nullptr, u64 fold_stride = 0,
                            u32 keep_q = 0);
+// The same for two rotation steps at once (keys key0/key1, Galois elements
+// g0/g1, outputs U0/U1 with one stride): each digit word is read once.
+void keyswitch_inner_batch2(vr_context* ctx, const u64* X, u64 x_stride, const u64* d, u64 d_stride,
+                            u32 n_ct, const u64* key0, const u64* key1, u32 level, u32 g0, u32 g1, u64* U0,
+                            u64* U1, u64 u_stride, hipStream_t s, const u64* fold_c0 = nullptr,
+                            u64 fold_stride = 0, u32 keep_q = 0);
 // ModDown of U ([2][next][N]) to out0/out1 (nq limbs each, may be strided),
 // adding add0 (optionally through sigma_g) and add1 when non-null.
 void keyswitch_moddown(vr_context* ctx, u64* U, u32 level, u64* out0, u64* out1, const u64* add0,
