@@ -176,7 +176,7 @@ vr_status vr_context_set_tuning(vr_context* ctx, const char* knob, const char* v
     std::string k(knob), v(value);
     int mode = -1;
     if (k == "base_convert")
-        mode = v == "auto" ? 0 : v == "alu" ? 1 : v == "mfma" ? 2 : v == "fp64" ? 3 : -1;
+        mode = v == "auto" ? 0 : v == "alu" ? 1 : v == "mfma" ? 2 : v == "fp64" ? 3 : v == "split" ? 4 : -1;
     else if (k == "ntt") {
         mode = v == "auto" ? 0 : v == "fixed" ? 1 : -1;
         if (v.compare(0, 5, "cand:") == 0) mode = 2 + std::stoi(v.substr(5));
@@ -185,7 +185,7 @@ vr_status vr_context_set_tuning(vr_context* ctx, const char* knob, const char* v
     else if (k == "conv_prune" || k == "fc_compact" || k == "lincomb_wide" || k == "lincomb_mfma")
         mode = v == "on" ? 0 : v == "off" ? 1 : -1;
     else throw Error(VR_EINVAL, "unknown tuning knob");
-    REQUIRE(mode >= 0, "base_convert takes auto, alu, mfma or fp64; ntt takes auto, fixed or cand:k; "
+    REQUIRE(mode >= 0, "base_convert takes auto, alu, mfma, fp64 or split; ntt takes auto, fixed or cand:k; "
                        "conv_prune, fc_compact, lincomb_wide and lincomb_mfma take on or off");
     std::lock_guard<std::mutex> g(ctx->mu);
     ctx->tuning[k] = mode;
@@ -198,7 +198,9 @@ vr_status vr_context_tuning_report(vr_context* ctx, char* buf, size_t cap)
     REQUIRE(ctx && buf && cap > 0, "null argument");
     std::string r;
     std::lock_guard<std::mutex> g(ctx->mu);
-    auto name = [](int c) { return c < 0 ? "untimed" : c == 1 ? "mfma" : c == 2 ? "fp64" : "alu"; };
+    auto name = [](int c) {
+        return c < 0 ? "untimed" : c == 1 ? "mfma" : c == 2 ? "fp64" : c == 3 ? "split" : "alu";
+    };
     for (auto& kv : ctx->modup_tables)
         r += "modup l" + std::to_string(kv.first.first) + " d" + std::to_string(kv.first.second) + " " +
              std::to_string(kv.second.n_in) + "->" + std::to_string(kv.second.n_out) + ": " +

@@ -55,6 +55,7 @@ struct ConvArgs {
     u32 n_in, n_out;
     u32 log_n;
     const ModQ* mq;
+    u32 o_lo = 0, o_hi = 0xffffffffu;   // the targets the integer and FP64 kernels make
 };
 VR_KERNEL_ARG(ConvArgs);
 
@@ -104,8 +105,9 @@ __global__ __launch_bounds__(kThreads) void k_base_convert(ConvArgs a)
             y[i] = v;
         }
     }
+    const u32 o_end = min(a.o_hi, a.n_out);
 #pragma unroll 2
-    for (u32 o = 0; o < a.n_out; o++) {
+    for (u32 o = a.o_lo; o < o_end; o++) {
         const u64* c = s_out + 5 * o;
         u64 hi = 0, lo = 0;
         mac128(hi, lo, n_neg, c[4]);
@@ -177,16 +179,17 @@ __global__ __launch_bounds__(kThreads) void k_base_convert_fp(ConvArgs a, ConvFp
     // target o + 1's constants are loaded while target o is summed
     double wc[NI], wh = 0.0, tc[2];
 #pragma unroll
-    for (int i = 0; i < NI; i++) wc[i] = f.w[2 * i];
-    if (W0) wh = f.w[1];
-    tc[0] = f.t[0];
-    tc[1] = f.t[1];
-    for (u32 o = 0; o < a.n_out; o++) {
+    for (int i = 0; i < NI; i++) wc[i] = f.w[(size_t)a.o_lo * kMaxIn * 2 + 2 * i];
+    if (W0) wh = f.w[(size_t)a.o_lo * kMaxIn * 2 + 1];
+    tc[0] = f.t[2 * a.o_lo];
+    tc[1] = f.t[2 * a.o_lo + 1];
+    const u32 o_end = min(a.o_hi, a.n_out);
+    for (u32 o = a.o_lo; o < o_end; o++) {
         const double td = tc[0], tinv = tc[1];
         double w[NI], w1 = wh;
 #pragma unroll
         for (int i = 0; i < NI; i++) w[i] = wc[i];
-        if (o + 1 < a.n_out) {
+        if (o + 1 < o_end) {
             const double* wn = f.w + (size_t)(o + 1) * kMaxIn * 2;
 #pragma unroll
             for (int i = 0; i < NI; i++) wc[i] = wn[2 * i];
@@ -587,6 +590,9 @@ ConvTable build_table(vr_context* ctx, const std::vector<u32>& in, const std::ve
     tb.wide = 0;
     for (u32 i = 0; i < tb.n_in; i++)
         if (ctx->mod[in[i]] >= (1ull << 51)) tb.wide |= 1u << i;
+    tb.wide_out = 0;
+    for (u32 o = 0; o < tb.n_out; o++)
+        if (ctx->mod[out[o]] >= (1ull << 51)) tb.wide_out |= o < 32 ? 1u << o : 0x80000000u;
     for (u32 o = 0; o < tb.n_out; o++) {
         const u64 to = ctx->mod[out[o]];
         wt_t[2 * o] = (double)to;
@@ -737,17 +743,29 @@ void launch_convert(vr_context* ctx, const ConvArgs& a, const ConvTable& tb, u32
         if (it != ctx->tuning.end()) mode = it->second;
     }
     const bool mfma = mfma_usable(ctx, tb), fp = fp_usable(tb);
+    // split: only target 0 is 2^51 or more (q_0 first among narrow targets)
+    const bool split = fp && tb.n_out >= 2 && tb.wide_out == 1u;
+    auto launch_split = [&]() {
+        ConvArgs b = a;
+        b.o_lo = 1;
+        launch_fp(ctx, b, tb, n_polys, s);
+        ConvArgs w = a;
+        w.o_lo = 0;
+        w.o_hi = 1;
+        launch_alu(ctx, w, n_polys, s);
+    };
     if (mode == 1 || (mode == 2 && !mfma) || (mode == 3 && !fp)) return launch_alu(ctx, a, n_polys, s);
     if (mode == 2) return launch_mfma(ctx, a, tb, n_polys, s);
     if (mode == 3) return launch_fp(ctx, a, tb, n_polys, s);
+    if (mode == 4) return split ? launch_split() : launch_alu(ctx, a, n_polys, s);
     int c = tb.choice->load();
     if (c < 0 && !g_capture && ctx->prof.cls < 0) {
         // every candidate twice (each writes the same words; the first
         // launch of a kernel also pays for loading it), the faster of each
         // candidate's two runs counts
-        hipEvent_t ev[4];
+        hipEvent_t ev[5];
         for (auto& e : ev) VR_HIP(hipEventCreate(&e));
-        float ms[3] = {1e30f, 1e30f, 1e30f};
+        float ms[4] = {1e30f, 1e30f, 1e30f, 1e30f};
         for (int round = 0; round < 2; round++) {
             VR_HIP(hipEventRecord(ev[0], s));
             launch_alu(ctx, a, n_polys, s);
@@ -756,21 +774,28 @@ void launch_convert(vr_context* ctx, const ConvArgs& a, const ConvTable& tb, u32
             VR_HIP(hipEventRecord(ev[2], s));
             if (mfma) launch_mfma(ctx, a, tb, n_polys, s);
             VR_HIP(hipEventRecord(ev[3], s));
-            VR_HIP(hipEventSynchronize(ev[3]));
-            for (int k = 0; k < 3; k++) {
+            if (split) launch_split();
+            VR_HIP(hipEventRecord(ev[4], s));
+            VR_HIP(hipEventSynchronize(ev[4]));
+            for (int k = 0; k < 4; k++) {
                 float t = 0;
                 VR_HIP(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
                 ms[k] = std::min(ms[k], t);
             }
         }
         for (auto& e : ev) (void)hipEventDestroy(e);
-        int pick = fp && ms[1] < ms[0] ? 2 : 0;
-        if (mfma && ms[2] < ms[pick == 2 ? 1 : 0]) pick = 1;
+        // choice codes: 0 alu (ms[0]), 2 fp64 (ms[1]), 1 mfma (ms[2]), 3 split (ms[3])
+        int pick = 0;
+        float best = ms[0];
+        if (fp && ms[1] < best) pick = 2, best = ms[1];
+        if (mfma && ms[2] < best) pick = 1, best = ms[2];
+        if (split && ms[3] < best) pick = 3, best = ms[3];
         tb.choice->store(pick);
         return;
     }
     if (c == 1) return launch_mfma(ctx, a, tb, n_polys, s);
     if (c == 2) return launch_fp(ctx, a, tb, n_polys, s);
+    if (c == 3) return launch_split();
     launch_alu(ctx, a, n_polys, s);
 }
 

@@ -295,7 +295,9 @@ struct ConvTable {
     // bit i of wide: input modulus i is 2^51 or more
     double* wf = nullptr;
     u32 wide = 0;
-    // kernel chosen for this table: -1 not yet timed, 0 vector ALU, 1 MFMA, 2 FP64
+    u32 wide_out = 0;   // bit o: target o (o < 31) is 2^51 or more; bit 31: a later one is
+    // kernel chosen for this table: -1 not yet timed, 0 vector ALU, 1 MFMA,
+    // 2 FP64, 3 FP64 for targets 1.. and the vector ALU for target 0
     std::shared_ptr<std::atomic<int>> choice;
 };
 

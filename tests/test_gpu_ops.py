@@ -251,7 +251,7 @@ def test_rotation_decrypts_on_gpu():
         assert np.max(np.abs(d - np.roll(z, -st))) < 2.0 ** -20, st
 
 
-@pytest.mark.parametrize("mode", ["alu", "mfma", "fp64", "auto"])
+@pytest.mark.parametrize("mode", ["alu", "mfma", "fp64", "split", "auto"])
 @pytest.mark.parametrize("name,level", [("C2", 2), ("C2", 7), ("C3", 3), ("C3", 24), ("C3", 20)])
 def test_keyswitch_match_other_chains(name, level, mode):
     """Rotation and relinearisation with 60-bit q_0 / special primes (C2) and
@@ -259,8 +259,9 @@ def test_keyswitch_match_other_chains(name, level, mode):
     holds the 60-bit q_0, split in halves by the FP64 kernel, and q_0 is a
     target of the other digits and of ModDown, taking the integer form), with
     the base conversions on the vector ALU, in FP64, on the INT8 matrix cores,
-    and as the autotuner picks (its first call runs every kernel); one-limb
-    digits (C2) convert inside the NTT's first load whatever the mode."""
+    split (FP64 for the targets after q_0, the ALU kernel for q_0) and as the
+    autotuner picks (its first call runs every kernel); one-limb digits (C2)
+    convert inside the NTT's first load whatever the mode."""
     o, ok, g, gk = pair(name, rot_steps=(1, 3))
     z = np.random.default_rng(level).uniform(-1, 1, o.slots)
     a = o.encrypt(ok, o.encode(z, level, o.scale), 9, level)
