@@ -522,7 +522,7 @@ template <bool kFp>
 __global__ __launch_bounds__(kThreads) void k_lincomb_mfma(u64* out, u64 out_stride, const u64* x, const u64* r,
                                                            u32 n_x, u32 n_sets, u64 stride, u64 rstride,
                                                            u64 ustride, const Term* terms, const u32* term_off,
-                                                           const u32* rot_end, const u64* at, const u64* col_at,
+                                                           const u32* rot_end, const u64* at, const u64* col_at, const u64* kc,
                                                            const u64* bias, u32 nl, u32 nk, u32 lvl, u32 modoff,
                                                            u32 x_limbs, u32 log_n, const ModQ* mq, u32 wo,
                                                            u32 n_filters, u32 total, u32 per_xcd, u32 cpb)
@@ -556,10 +556,9 @@ __global__ __launch_bounds__(kThreads) void k_lincomb_mfma(u64* out, u64 out_str
     if (kFp != (q < (1ull << 51))) return;
     const double qd = (double)q, qinv = 1.0 / qd;
     // 2^24, 2^48 mod q (balanced) for the FP64 fold; 2^128 mod q for the
-    // sign of the 128-bit fold
-    const u64 c24 = (1ull << 24) % q, c48 = (1ull << 48) % q;
-    const double c24b = to_bal(c24, q, qd), c48b = to_bal(c48, q, qd);
-    const u64 c128 = mul_mod(m.r64, m.r64, m);
+    // sign of the 128-bit fold (the plan's table, per limb)
+    const double c24b = to_bal(kc[3 * l], q, qd), c48b = to_bal(kc[3 * l + 1], q, qd);
+    const u64 c128 = kc[3 * l + 2];
     const size_t xrow = ((size_t)(row / nl) * x_limbs + (x_has ? xl : 0)) * n;
     const size_t orow = (size_t)row * n;
     for (u32 f0 = 0, grp = 0; f0 < n_filters; f0 += kMaxFilters, grp++) {
@@ -734,9 +733,16 @@ __global__ __launch_bounds__(kThreads) void k_sqfc_acc(u64* out, u64 out_stride,
 #pragma unroll
             for (int g = 0; g < kSqfcGroup; g++) acc[c][g] = 0;
         u32 k = 0;
+        // the next input's words load while this one is summed
+        u64 n0 = wave < n_in ? Y[(size_t)wave * y_stride + off0] : 0;
+        u64 n1 = wave < n_in ? Y[(size_t)wave * y_stride + yoff1] : 0;
         for (u32 i = wave; i < n_in; i += kSqfcWaves, k++) {
-            const double y0 = to_bal(Y[(size_t)i * y_stride + off0], m.q, qd);
-            const double y1 = to_bal(Y[(size_t)i * y_stride + yoff1], m.q, qd);
+            const double y0 = to_bal(n0, m.q, qd);
+            const double y1 = to_bal(n1, m.q, qd);
+            if (i + kSqfcWaves < n_in) {
+                n0 = Y[(size_t)(i + kSqfcWaves) * y_stride + off0];
+                n1 = Y[(size_t)(i + kSqfcWaves) * y_stride + yoff1];
+            }
             const double x01 = fmulmod(y0, y1, qd, qinv);
             // the tensor balanced again (|d| <= q / 2 + 1): each weight
             // product within 0.75 q
@@ -768,9 +774,14 @@ __global__ __launch_bounds__(kThreads) void k_sqfc_acc(u64* out, u64 out_stride,
 #pragma unroll
             for (int g = 0; g < kSqfcGroup; g++) h[c][g] = lo[c][g] = 0;
         u32 k = 0;
+        u64 n0 = wave < n_in ? Y[(size_t)wave * y_stride + off0] : 0;
+        u64 n1 = wave < n_in ? Y[(size_t)wave * y_stride + yoff1] : 0;
         for (u32 i = wave; i < n_in; i += kSqfcWaves, k++) {
-            const u64 y0 = Y[(size_t)i * y_stride + off0];
-            const u64 y1 = Y[(size_t)i * y_stride + yoff1];
+            const u64 y0 = n0, y1 = n1;
+            if (i + kSqfcWaves < n_in) {
+                n0 = Y[(size_t)(i + kSqfcWaves) * y_stride + off0];
+                n1 = Y[(size_t)(i + kSqfcWaves) * y_stride + yoff1];
+            }
             const u64 x01 = mul_mod(y0, y1, m);
             const u64 d[3] = {mul_mod(y0, y0, m), add_mod(x01, x01, m.q), mul_mod(y1, y1, m)};
 #pragma unroll
@@ -1375,9 +1386,11 @@ struct ConvPlan {
     u32 n_wide = 0;
     bool any_wide = false;   // some limb's modulus is 2^51 or more
     // matrix-core tables (k_lincomb_mfma), one per distinct column pattern;
-    // col_at[j'] the offset of column j''s; absent when too large
+    // col_at[j'] the offset of column j''s; absent when too large; kc per
+    // limb: 2^24, 2^48 and 2^128 mod q
     const u64* at = nullptr;
     const u64* col_at = nullptr;
+    const u64* kc = nullptr;
     u32 t_total = 0, max_col = 0;   // terms in all, most terms of one column
 };
 
@@ -1548,13 +1561,22 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
         }
     }
     if (!mfma_ok) atv.clear();
+    std::vector<u64> kcv;
+    if (mfma_ok)
+        for (u32 l = 0; l < nl; l++) {
+            const u64 q = ctx->mod[mod_of(l)];
+            const u64 r64 = (u64)(((u128)1 << 64) % q);
+            kcv.push_back((u64)(((u128)1 << 24) % q));
+            kcv.push_back((u64)(((u128)1 << 48) % q));
+            kcv.push_back((u64)((u128)r64 * r64 % q));
+        }
     // one device buffer: terms | off | rot_end | w | ws | bias | wt | wp
     // (8-byte aligned parts)
     size_t b_terms = terms.size() * sizeof(Term), b_off = ((off.size() * 4 + 7) / 8) * 8;
     size_t b_rot = ((rot_end.size() * 4 + 7) / 8) * 8;
     b_off += b_rot;
     const size_t n_words = wv.size() + wsv.size() + bv.size() + wfv.size() + wpv.size();
-    size_t total = b_terms + b_off + (n_words + (mfma_ok ? atv.size() + colv.size() : 0)) * 8;
+    size_t total = b_terms + b_off + (n_words + (mfma_ok ? atv.size() + colv.size() + kcv.size() : 0)) * 8;
     auto plan = std::make_shared<ConvPlan>();
     VR_HIP(hipDeviceSynchronize());
     plan->buf = dev_alloc(ctx, total, nullptr);
@@ -1572,6 +1594,7 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
     if (mfma_ok) {
         memcpy(h.data() + o + n_words * 8, atv.data(), atv.size() * 8);
         memcpy(h.data() + o + (n_words + atv.size()) * 8, colv.data(), colv.size() * 8);
+        memcpy(h.data() + o + (n_words + atv.size() + colv.size()) * 8, kcv.data(), kcv.size() * 8);
     }
     VR_HIP(hipMemcpy(base, h.data(), total, hipMemcpyHostToDevice));
     plan->terms = (const Term*)base;
@@ -1588,6 +1611,7 @@ const ConvPlan& conv_plan(vr_context* ctx, u32 C_in, u32 w, u32 pad, const doubl
     if (mfma_ok) {
         plan->at = plan->w + n_words;
         plan->col_at = plan->at + atv.size();
+        plan->kc = plan->col_at + colv.size();
     }
     plan->t_total = t_total;
     plan->max_col = max_col;
@@ -1781,7 +1805,7 @@ void conv_lincomb_into(vr_context* ctx, const Slab& out, u32 out_at, const Slab&
             hipLaunchKernelGGL(fp ? k_lincomb_mfma<true> : k_lincomb_mfma<false>, dim3(8 * per_xcd), dim3(kThreads),
                                0, s, out.ct(out_at), out.stride, x.ct(x_at), cr.rot.empty() ? x.ct(x_at) : r.ct(r_at),
                                C_in * w, n_sets, x.stride, r.stride, (u64)r.n * r.stride, plan.terms, plan.off,
-                               plan.rot_end, plan.at, plan.col_at, plan.bias, nl, nk, level, ctx->L - nk, nq,
+                               plan.rot_end, plan.at, plan.col_at, plan.kc, plan.bias, nl, nk, level, ctx->L - nk, nq,
                                ctx->log_n, ctx->d_modq, wo, C_out, total, per_xcd, cpb);
             VR_CHECK_LAUNCH();
         }
