@@ -161,11 +161,14 @@ __global__ __launch_bounds__(kThreads) void k_base_convert_fp(ConvArgs a, ConvFp
     for (int i = 0; i < NI; i++)
         if (i < (int)a.n_in) x[i] = in[(size_t)i * n + t];
     double yl[NI], yh0 = 0.0;
+    u64 qin[NI];   // input moduli, read once (the integer form for wide targets needs them)
 #pragma unroll
     for (int i = 0; i < NI; i++) {
         yl[i] = 0.0;
+        qin[i] = 0;
         if (i < (int)a.n_in) {
             const u64 q = a.mq[in_mod[i]].q;
+            qin[i] = q;
             const u64 v = shoup(x[i], qinv[i], qinv_s[i], q);
             if (W0 && i == 0) {
                 const i64 y = v > (q >> 1) ? (i64)v - (i64)q : (i64)v;
@@ -220,7 +223,7 @@ __global__ __launch_bounds__(kThreads) void k_base_convert_fp(ConvArgs a, ConvFp
 #pragma unroll
             for (int i = 0; i < NI; i++) {
                 if (i < (int)a.n_in) {
-                    const u64 q = a.mq[in_mod[i]].q;
+                    const u64 q = qin[i];
                     const i64 y = (W0 && i == 0) ? ((i64)(int)yh0 << 30) + (i64)(u32)yl[0] : (i64)yl[i];
                     nn += y < 0 ? 1 : 0;
                     mac128(hi, lo, (u64)(y < 0 ? y + (i64)q : y), qhat[(size_t)i * a.n_out + o]);
