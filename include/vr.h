@@ -114,7 +114,8 @@ vr_status vr_context_trim(vr_context *ctx);
  * INT8-split MFMA kernel and, for tables whose only target of 2^51 or more is
  * the first, the FP64 kernel on the other targets with the ALU kernel on that
  * one ("split"), twice each on its first call, and keeps the fastest; all
- * give identical words), "alu", "fp64", "mfma" or "split".  Knob
+ * give identical words), "alu", "fp64", "mfma" or "split" (split where it
+ * applies, else FP64 where that applies, else the ALU kernel).  Knob
  * "ntt": "auto" (default: the first transform in each direction times the
  * candidate pass plans -- one LDS-resident pass, two passes with every split
  * of log N and 8..128 groups per workgroup, and at N = 2^15, 2^16 the

@@ -760,7 +760,7 @@ void launch_convert(vr_context* ctx, const ConvArgs& a, const ConvTable& tb, u32
     if (mode == 1 || (mode == 2 && !mfma) || (mode == 3 && !fp)) return launch_alu(ctx, a, n_polys, s);
     if (mode == 2) return launch_mfma(ctx, a, tb, n_polys, s);
     if (mode == 3) return launch_fp(ctx, a, tb, n_polys, s);
-    if (mode == 4) return split ? launch_split() : launch_alu(ctx, a, n_polys, s);
+    if (mode == 4) return split ? launch_split() : fp ? launch_fp(ctx, a, tb, n_polys, s) : launch_alu(ctx, a, n_polys, s);
     int c = tb.choice->load();
     if (c < 0 && !g_capture && ctx->prof.cls < 0) {
         // every candidate twice (each writes the same words; the first
