@@ -698,13 +698,14 @@ __global__ __launch_bounds__(kThreads) void k_compact_runs(const u64* in, u64* o
 // FC weight products of the x^2 tensors (lazy relinearisation): for outputs
 // o0 .. o0 + kSqfcGroup - 1 (o0 = blockIdx.z * kSqfcGroup) and limb l,
 //   out_o = sum_i (y_i0^2, 2 y_i0 y_i1, y_i1^2) P[o][i]     (3 components),
-// the tensor of each input formed once per limb and output group (one group
-// holds the ten classes of the paper's networks).  A block covers 64
+// the tensor of each input formed once per limb and output group (groups of
+// five: the ten classes of the paper's networks take two, and the smaller
+// accumulator set leaves more waves per SIMD).  A block covers 64
 // coefficients; its four waves take every fourth input each and their
 // residues are summed through LDS at the end.  kFp: the limbs below 2^51, as
 // exact FP64 products (balanced operands, sums reduced every four inputs);
 // otherwise 128-bit integer sums (the others return at once).
-constexpr int kSqfcGroup = 10;
+constexpr int kSqfcGroup = 5;
 constexpr u32 kSqfcWaves = 4;
 
 template <bool kFp>
