@@ -110,12 +110,12 @@ vr_status vr_context_mem_info(vr_context *ctx, size_t *reserved, size_t *in_use)
  * blocks to the runtime. */
 vr_status vr_context_trim(vr_context *ctx);
 /* Kernel choices.  Knob "base_convert": "auto" (default: each base-conversion
- * table times the 128-bit vector-ALU kernel, the exact FP64 kernel, the
- * INT8-split MFMA kernel and, for tables whose only target of 2^51 or more is
- * the first, the FP64 kernel on the other targets with the ALU kernel on that
- * one ("split"), twice each on its first call, and keeps the fastest; all
- * give identical words), "alu", "fp64", "mfma" or "split" (split where it
- * applies, else FP64 where that applies, else the ALU kernel).  Knob
+ * table times the 128-bit vector-ALU kernel, the exact FP64 kernel and the
+ * INT8-split MFMA kernel, twice each on its first call, and keeps the
+ * fastest; all give identical words), "alu", "fp64", "mfma" or "split" (for
+ * tables whose only target of 2^51 or more is the first, the FP64 kernel on
+ * the other targets with the ALU kernel on that one; elsewhere FP64 where
+ * that applies, else the ALU kernel).  Knob
  * "ntt": "auto" (default: the first transform in each direction times the
  * candidate pass plans -- one LDS-resident pass, two passes with every split
  * of log N and 8..128 groups per workgroup, and at N = 2^15, 2^16 the

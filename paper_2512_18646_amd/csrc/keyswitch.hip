@@ -765,10 +765,12 @@ void launch_convert(vr_context* ctx, const ConvArgs& a, const ConvTable& tb, u32
     if (c < 0 && !g_capture && ctx->prof.cls < 0) {
         // every candidate twice (each writes the same words; the first
         // launch of a kernel also pays for loading it), the faster of each
-        // candidate's two runs counts
-        hipEvent_t ev[5];
+        // candidate's two runs counts.  split is not a candidate: it never
+        // won a clean comparison, and a first call timed while other
+        // streams run (the server's waves) could pick it by noise.
+        hipEvent_t ev[4];
         for (auto& e : ev) VR_HIP(hipEventCreate(&e));
-        float ms[4] = {1e30f, 1e30f, 1e30f, 1e30f};
+        float ms[3] = {1e30f, 1e30f, 1e30f};
         for (int round = 0; round < 2; round++) {
             VR_HIP(hipEventRecord(ev[0], s));
             launch_alu(ctx, a, n_polys, s);
@@ -777,22 +779,19 @@ void launch_convert(vr_context* ctx, const ConvArgs& a, const ConvTable& tb, u32
             VR_HIP(hipEventRecord(ev[2], s));
             if (mfma) launch_mfma(ctx, a, tb, n_polys, s);
             VR_HIP(hipEventRecord(ev[3], s));
-            if (split) launch_split();
-            VR_HIP(hipEventRecord(ev[4], s));
-            VR_HIP(hipEventSynchronize(ev[4]));
-            for (int k = 0; k < 4; k++) {
+            VR_HIP(hipEventSynchronize(ev[3]));
+            for (int k = 0; k < 3; k++) {
                 float t = 0;
                 VR_HIP(hipEventElapsedTime(&t, ev[k], ev[k + 1]));
                 ms[k] = std::min(ms[k], t);
             }
         }
         for (auto& e : ev) (void)hipEventDestroy(e);
-        // choice codes: 0 alu (ms[0]), 2 fp64 (ms[1]), 1 mfma (ms[2]), 3 split (ms[3])
+        // choice codes: 0 alu (ms[0]), 2 fp64 (ms[1]), 1 mfma (ms[2])
         int pick = 0;
         float best = ms[0];
         if (fp && ms[1] < best) pick = 2, best = ms[1];
         if (mfma && ms[2] < best) pick = 1, best = ms[2];
-        if (split && ms[3] < best) pick = 3, best = ms[3];
         tb.choice->store(pick);
         return;
     }
