@@ -508,9 +508,13 @@ __global__ __launch_bounds__(kThreads) void k_lincomb_wide(u64* out, u64 out_str
 // 4s + l / 16 of the column; byte a is d_{f,k,a,j}.  Columns with the same
 // weight rows share one table (col_at[j'] its offset).  Each wave covers 64
 // coefficients (four N-tiles) per pass with the weight words of a step held
-// across them; block order as in k_lincomb.
+// across them; block order as in k_lincomb.  The block's term sources (the
+// input or rotated limb row each term reads) sit in LDS, up to kMfmaSrcChunk
+// terms at a time, and each wave loads the next step's input words while the
+// current step's products run.
 typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr u32 kMfmaMaxTerms = 16384;
+constexpr u32 kMfmaSrcChunk = 512;
 
 __device__ __forceinline__ u64 bal_bytes(u64 x)
 {
@@ -519,7 +523,7 @@ __device__ __forceinline__ u64 bal_bytes(u64 x)
 }
 
 template <bool kFp>
-__global__ __launch_bounds__(kThreads) void k_lincomb_mfma(u64* out, u64 out_stride, const u64* x, const u64* r,
+__global__ __launch_bounds__(kThreads, kFp ? 4 : 2) void k_lincomb_mfma(u64* out, u64 out_stride, const u64* x, const u64* r,
                                                            u32 n_x, u32 n_sets, u64 stride, u64 rstride,
                                                            u64 ustride, const Term* terms, const u32* term_off,
                                                            const u32* rot_end, const u64* at, const u64* col_at, const u64* kc,
@@ -561,6 +565,10 @@ __global__ __launch_bounds__(kThreads) void k_lincomb_mfma(u64* out, u64 out_str
     const u64 c128 = kc[3 * l + 2];
     const size_t xrow = ((size_t)(row / nl) * x_limbs + (x_has ? xl : 0)) * n;
     const size_t orow = (size_t)row * n;
+    // term k's limb row (null past the column's terms), for terms
+    // held_at .. held_at + kMfmaSrcChunk - 1
+    __shared__ const u64* srcs[kMfmaSrcChunk];
+    u32 held_at = 0xffffffffu;
     for (u32 f0 = 0, grp = 0; f0 < n_filters; f0 += kMaxFilters, grp++) {
         const u64* tab = at + col_at[jo] + ((size_t)grp * nl + l) * steps_all * 256 + lane;
         for (u32 cc = 0; cc < cpb && pass0 + cc < passes; cc++) {
@@ -570,25 +578,51 @@ __global__ __launch_bounds__(kThreads) void k_lincomb_mfma(u64* out, u64 out_str
             for (int i = 0; i < 4; i++)
 #pragma unroll
                 for (int T = 0; T < 4; T++) acc[i][T] = v4i{0, 0, 0, 0};
-            for (u32 s = 0; s < steps; s++) {
-                long w[4];
-#pragma unroll
-                for (int T = 0; T < 4; T++) w[T] = (long)tab[((size_t)s * 4 + T) * 64];
-                const u32 k = 4 * s + g;
-                long b[4] = {0, 0, 0, 0};
-                if (k < n_use) {
-                    const Term tm = terms[a + k];
-                    const u32 u = tm.in_idx >> kTermColBits, j = tm.in_idx & kColMask;
-                    const u64* src = u == 0 ? xb + (size_t)j * stride + xrow
-                                            : rb + (u - 1) * ustride + (size_t)j * rstride + orow;
-#pragma unroll
-                    for (int i = 0; i < 4; i++) b[i] = (long)bal_bytes(src[base + 16 * i]);
+            for (u32 k0 = 0; k0 < 4 * steps; k0 += kMfmaSrcChunk) {
+                const u32 kn = min(4 * steps - k0, kMfmaSrcChunk);   // a multiple of 4
+                if (k0 != held_at) {
+                    __syncthreads();
+                    for (u32 i = threadIdx.x; i < kn; i += kThreads) {
+                        const u32 k = k0 + i;
+                        const u64* src = nullptr;
+                        if (k < n_use) {
+                            const Term tm = terms[a + k];
+                            const u32 u = tm.in_idx >> kTermColBits, j = tm.in_idx & kColMask;
+                            src = u == 0 ? xb + (size_t)j * stride + xrow
+                                         : rb + (u - 1) * ustride + (size_t)j * rstride + orow;
+                        }
+                        srcs[i] = src;
+                    }
+                    __syncthreads();
+                    held_at = k0;
                 }
+                const u32 s0 = k0 / 4, s1 = s0 + kn / 4;
+                long cur[4] = {0, 0, 0, 0};
+                if (const u64* src = srcs[g]) {
 #pragma unroll
-                for (int i = 0; i < 4; i++)
+                    for (int i = 0; i < 4; i++) cur[i] = (long)src[base + 16 * i];
+                }
+                for (u32 s = s0; s < s1; s++) {
+                    long w[4];
 #pragma unroll
-                    for (int T = 0; T < 4; T++)
-                        acc[i][T] = __builtin_amdgcn_mfma_i32_16x16x32_i8(w[T], b[i], acc[i][T], 0, 0, 0);
+                    for (int T = 0; T < 4; T++) w[T] = (long)tab[((size_t)s * 4 + T) * 64];
+                    long nxt[4] = {0, 0, 0, 0};
+                    if (s + 1 < s1) {
+                        if (const u64* src = srcs[4 * (s + 1 - s0) + g]) {
+#pragma unroll
+                            for (int i = 0; i < 4; i++) nxt[i] = (long)src[base + 16 * i];
+                        }
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; i++) {
+                        const long b = (long)bal_bytes((u64)cur[i]);
+#pragma unroll
+                        for (int T = 0; T < 4; T++)
+                            acc[i][T] = __builtin_amdgcn_mfma_i32_16x16x32_i8(w[T], b, acc[i][T], 0, 0, 0);
+                    }
+#pragma unroll
+                    for (int i = 0; i < 4; i++) cur[i] = nxt[i];
+                }
             }
 #pragma unroll
             for (int i = 0; i < 4; i++) {
