@@ -1099,6 +1099,9 @@ __device__ __forceinline__ u32 split_addr(u32 e, u32 wg)
         return (wg << (LOGN - A + LC)) + e;
 }
 
+// words whose finish operands a thread loads together in the last round
+constexpr int kFinBatch = 4;
+
 template <int LOGN, int A, int LC, int PASS, int I, bool INV, bool FP, int RED>
 __device__ __forceinline__ void split_round(u64* lds, const LimbK& c, u32 wg)
 {
@@ -1116,6 +1119,7 @@ __device__ __forceinline__ void split_round(u64* lds, const LimbK& c, u32 wg)
     // wave staging its own 64 groups through their LDS words
     constexpr bool XPOSE = LB == 0;
     const u32 hoff = PASS == 1 ? wg << (LC + SGL) : 0u;
+    constexpr int FB = E < kFinBatch ? E : kFinBatch;
     const u32 lane = c.tid & 63;
     double* ldf = (double*)lds;
 #pragma unroll
@@ -1171,17 +1175,22 @@ __device__ __forceinline__ void split_round(u64* lds, const LimbK& c, u32 wg)
                     for (int m = 0; m < E; m++)
                         c.dst[split_addr<LOGN, A, LC, PASS>(gword(m), wg)] = __double_as_longlong(x[m]);
                 } else if (!INV && c.ea) {
-                    u64 av[E], bv[E];
+                    // the finish's operands in batches of kFinBatch words,
+                    // so the pass keeps 4 waves per SIMD
 #pragma unroll
-                    for (int m = 0; m < E; m++) {
-                        const u32 idx = split_addr<LOGN, A, LC, PASS>(gword(m), wg);
-                        av[m] = c.ea[idx];
-                        if (c.eb) bv[m] = c.eb[c.eb_g != 1 ? galois_src(idx, c.eb_g, LOGN) : idx];
-                    }
+                    for (int m0 = 0; m0 < E; m0 += FB) {
+                        u64 av[FB], bv[FB];
 #pragma unroll
-                    for (int m = 0; m < E; m++) {
-                        const u32 idx = split_addr<LOGN, A, LC, PASS>(gword(m), wg);
-                        c.eo[idx] = finish_fp(c, av[m], bv[m], x[m]);
+                        for (int m = 0; m < FB; m++) {
+                            const u32 idx = split_addr<LOGN, A, LC, PASS>(gword(m0 + m), wg);
+                            av[m] = c.ea[idx];
+                            if (c.eb) bv[m] = c.eb[c.eb_g != 1 ? galois_src(idx, c.eb_g, LOGN) : idx];
+                        }
+#pragma unroll
+                        for (int m = 0; m < FB; m++) {
+                            const u32 idx = split_addr<LOGN, A, LC, PASS>(gword(m0 + m), wg);
+                            c.eo[idx] = finish_fp(c, av[m], bv[m], x[m0 + m]);
+                        }
                     }
                 } else {
 #pragma unroll
@@ -1226,16 +1235,20 @@ __device__ __forceinline__ void split_round(u64* lds, const LimbK& c, u32 wg)
 #pragma unroll
                     for (int m = 0; m < E; m++) c.dst[split_addr<LOGN, A, LC, PASS>(gword(m), wg)] = x[m];
                 } else if (!INV && c.ea) {
-                    u64 av[E], bv[E];
 #pragma unroll
-                    for (int m = 0; m < E; m++) {
-                        const u32 idx = split_addr<LOGN, A, LC, PASS>(gword(m), wg);
-                        av[m] = c.ea[idx];
-                        if (c.eb) bv[m] = c.eb[c.eb_g != 1 ? galois_src(idx, c.eb_g, LOGN) : idx];
+                    for (int m0 = 0; m0 < E; m0 += FB) {
+                        u64 av[FB], bv[FB];
+#pragma unroll
+                        for (int m = 0; m < FB; m++) {
+                            const u32 idx = split_addr<LOGN, A, LC, PASS>(gword(m0 + m), wg);
+                            av[m] = c.ea[idx];
+                            if (c.eb) bv[m] = c.eb[c.eb_g != 1 ? galois_src(idx, c.eb_g, LOGN) : idx];
+                        }
+#pragma unroll
+                        for (int m = 0; m < FB; m++)
+                            c.eo[split_addr<LOGN, A, LC, PASS>(gword(m0 + m), wg)] =
+                                finish_int(c, av[m], bv[m], x[m0 + m]);
                     }
-#pragma unroll
-                    for (int m = 0; m < E; m++)
-                        c.eo[split_addr<LOGN, A, LC, PASS>(gword(m), wg)] = finish_int(c, av[m], bv[m], x[m]);
                 } else {
 #pragma unroll
                     for (int m = 0; m < E; m++) {
