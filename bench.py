@@ -639,7 +639,7 @@ def rotations_bench(vr, level, n_ct, reps, ntt_plan="auto"):
         ctx.set_tuning("ntt", ntt_plan)
     keys = ctx.keygen(1003, rot_steps=[1])
     z = np.random.default_rng(3).uniform(-1, 1, ctx.slots)
-    cts = [ctx.encrypt(keys, ctx.encode(z, level), 1003, i) for i in range(n_ct)]
+    cts = [ctx.encrypt(keys, ctx.encode(z, level), 1003, (3 << 20) + 64 * level + i) for i in range(n_ct)]
     out = {}
     ctx.rotate_batch(keys, cts, 1)
     sync()
@@ -1089,7 +1089,7 @@ def cpu_rotations_n16(counts=((24, 2), (3, 4))):
     z = np.random.default_rng(3).uniform(-1, 1, o.slots)
     res = {}
     for lv, count in counts:
-        cts = [o.encrypt(ok, o.encode(z, lv, o.scale), 1003, i) for i in range(count)]
+        cts = [o.encrypt(ok, o.encode(z, lv, o.scale), 1003, (3 << 20) + 64 * lv + i) for i in range(count)]
         t = time.perf_counter()
         for c in cts:
             o.rotate(c, 1, ok)
