@@ -141,7 +141,7 @@ VR_KERNEL_ARG(ConvFp);
 constexpr double kTwo51 = 2251799813685248.0;
 
 template <int NI, bool W0>
-__global__ __launch_bounds__(kThreads) void k_base_convert_fp(ConvArgs a, ConvFp f)
+__global__ __launch_bounds__(kThreads, NI <= 10 ? 5 : 1) void k_base_convert_fp(ConvArgs a, ConvFp f)
 {
     const u32 n = 1u << a.log_n;
     const u32 poly = blockIdx.y;

@@ -523,7 +523,7 @@ __device__ __forceinline__ u64 bal_bytes(u64 x)
 }
 
 template <bool kFp>
-__global__ __launch_bounds__(kThreads, kFp ? 4 : 2) void k_lincomb_mfma(u64* out, u64 out_stride, const u64* x, const u64* r,
+__global__ __launch_bounds__(kThreads, kFp ? 4 : 3) void k_lincomb_mfma(u64* out, u64 out_stride, const u64* x, const u64* r,
                                                            u32 n_x, u32 n_sets, u64 stride, u64 rstride,
                                                            u64 ustride, const Term* terms, const u32* term_off,
                                                            const u32* rot_end, const u64* at, const u64* col_at, const u64* kc,
