@@ -1160,7 +1160,7 @@ def main():
     ap.add_argument("--no-graph", action="store_true")
     ap.add_argument("--no-uneven", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
-                    help="run a plain 1 GiB device copy first (counter calibration)")
+                    help="run a plain 1 GiB device copy first (counter calibration; its timed bandwidth goes into the JSON line as copy_probe)")
     ap.add_argument("--cnn-sets", type=int, default=2)
     ap.add_argument("--serve-requests", type=int, default=60)
     ap.add_argument("--serve-n16-requests", type=int, default=100,
@@ -1206,14 +1206,24 @@ def main():
         sys.exit(2)
 
     from paper_2512_18646_amd import vr, perop
+    copy_probe = None
     if args.copy_probe:
-        # a plain 1 GiB device copy, cold then warm: the HBM counters' scale
+        # a plain 1 GiB device copy, cold then warm: the HBM counters' scale;
+        # then ten more, timed: the copy bandwidth the NTT passes compare with
         import torch
         src = torch.ones(1 << 27, dtype=torch.int64, device="cuda")
         dst = torch.empty_like(src)
         for _ in range(2):
             dst.copy_(src)
         sync()
+        t = time.perf_counter()
+        for _ in range(10):
+            dst.copy_(src)
+        sync()
+        dt = (time.perf_counter() - t) / 10
+        copy_probe = {"bytes_moved": 2 << 30, "us_per_copy": round(dt * 1e6, 1),
+                      "tb_per_s": round((2 << 30) / dt / 1e12, 3)}
+        log("copy probe: 1 GiB in %.1f us, %.2f TB/s moved" % (dt * 1e6, (2 << 30) / dt / 1e12))
         del src, dst
     if args.rotations_only:
         out = {"rotations_per_s_n16": {"level24": rotations_bench(vr, 24, 8, args.steps, args.ntt_plan_n16),
@@ -1277,6 +1287,8 @@ def main():
            "latency_ms_p50": round(percentile(lat, 50), 3), "latency_ms_p99": round(percentile(lat, 99), 3),
            "roofline": roofline, "decoded_rel_error": err, "setup_s": round(setup_s, 1)}
     out["autotuned"] = ctx.tuning_report().splitlines()
+    if copy_probe:
+        out["copy_probe"] = copy_probe
 
     if args.breakdown:
         bd = {}
