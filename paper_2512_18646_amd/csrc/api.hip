@@ -207,8 +207,11 @@ vr_status vr_context_tuning_report(vr_context* ctx, char* buf, size_t cap)
              name(kv.second.choice ? kv.second.choice->load() : -1) + "\n";
     for (auto& kv : ctx->modup_range_tables)
         r += "modup l" + std::to_string(kv.first[0]) + " d" + std::to_string(kv.first[1]) + " [" +
-             std::to_string(kv.first[2]) + "," + std::to_string(kv.first[3]) + ") " +
-             std::to_string(kv.second.n_in) + "->" + std::to_string(kv.second.n_out) + ": " +
+             std::to_string(kv.first[2]) + "," + std::to_string(kv.first[3]) + ")" +
+             (kv.first[5] > kv.first[4]
+                  ? "+[" + std::to_string(kv.first[4]) + "," + std::to_string(kv.first[5]) + ")"
+                  : std::string()) +
+             " " + std::to_string(kv.second.n_in) + "->" + std::to_string(kv.second.n_out) + ": " +
              name(kv.second.choice ? kv.second.choice->load() : -1) + "\n";
     for (auto& kv : ctx->moddown_tables)
         r += "moddown l" + std::to_string(kv.first) + " " + std::to_string(kv.second.n_in) + "->" +

@@ -629,17 +629,19 @@ const ConvTable& modup_table(vr_context* ctx, u32 level, u32 j)
     return ctx->modup_tables[key] = build_table(ctx, in, out);
 }
 
-// digit j of `level` to the extended limbs [e0, e1) (none of them its own)
-const ConvTable& modup_range_table(vr_context* ctx, u32 level, u32 j, u32 e0, u32 e1)
+// digit j of `level` to the extended limbs [e0, e1) and then [e2, e3) (none
+// of them its own; e2 = e3 for one run)
+const ConvTable& modup_range_table(vr_context* ctx, u32 level, u32 j, u32 e0, u32 e1, u32 e2 = 0, u32 e3 = 0)
 {
     std::lock_guard<std::mutex> g(ctx->mu);
-    const std::array<int, 4> key{(int)level, (int)j, (int)e0, (int)e1};
+    const std::array<int, 6> key{(int)level, (int)j, (int)e0, (int)e1, (int)e2, (int)e3};
     auto it = ctx->modup_range_tables.find(key);
     if (it != ctx->modup_range_tables.end()) return it->second;
     u32 lo = j * ctx->alpha, hi = std::min((j + 1) * ctx->alpha, level + 1);
     std::vector<u32> in, out;
     for (u32 i = lo; i < hi; i++) in.push_back(i);
     for (u32 e = e0; e < e1; e++) out.push_back(ctx->ext_mod(e, level));
+    for (u32 e = e2; e < e3; e++) out.push_back(ctx->ext_mod(e, level));
     return ctx->modup_range_tables[key] = build_table(ctx, in, out);
 }
 
@@ -840,7 +842,10 @@ void keyswitch_modup_batch(vr_context* ctx, const u64* d, u64 d_stride, u32 n_ct
     if (keep_q && ctx->alpha > 1) {
         // only the extended limbs the inner product will read, q_0..q_{keep-1},
         // q_level and the special primes, outside each digit's own limbs: per
-        // digit at most three runs, each converted and transformed on its own
+        // digit at most three runs, each transformed on its own.  Two runs
+        // share one conversion (the gap between them is the kernels' output
+        // skip), so the digit's inputs are read and centred once; three
+        // convert one by one.
         if (keep_q > level) throw Error(VR_EINVAL, "ModUp: kept limbs above the level");
         for (u32 j = 0; j < k.beta; j++) {
             const u32 lo = j * ctx->alpha, hi = std::min((j + 1) * ctx->alpha, k.nq);
@@ -848,21 +853,26 @@ void keyswitch_modup_batch(vr_context* ctx, const u64* d, u64 d_stride, u32 n_ct
             if (std::min(keep_q, lo) > 0) runs.push_back({0, std::min(keep_q, lo)});
             if (hi < keep_q) runs.push_back({hi, keep_q});
             runs.push_back({std::max(level, hi), k.next});
-            for (const auto& r : runs) {
-                const ConvTable& tb = modup_range_table(ctx, level, j, r.first, r.second);
+            auto convert = [&](u32 e0, u32 e1, u32 e2, u32 e3) {
+                const ConvTable& tb = modup_range_table(ctx, level, j, e0, e1, e2, e3);
                 ConvArgs a;
                 a.in = coef + (size_t)lo * n;
                 a.in_stride = (u64)k.nq * n;
-                a.out = X + ((size_t)j * k.next + r.first) * n;
+                a.out = X + ((size_t)j * k.next + e0) * n;
                 a.out_stride = xs;
-                a.skip_at = 0xffffffffu;
-                a.skip_len = 0;
+                a.skip_at = e3 > e2 ? e1 - e0 : 0xffffffffu;
+                a.skip_len = e3 > e2 ? e2 - e1 : 0;
                 a.tab = tb.dev;
                 a.n_in = tb.n_in;
                 a.n_out = tb.n_out;
                 a.log_n = ctx->log_n;
                 a.mq = ctx->d_modq;
                 launch_convert(ctx, a, tb, n_ct, s);
+            };
+            if (runs.size() == 2)
+                convert(runs[0].first, runs[0].second, runs[1].first, runs[1].second);
+            for (const auto& r : runs) {
+                if (runs.size() != 2) convert(r.first, r.second, 0, 0);
                 LimbSet t = poly_limbs(X + (size_t)j * k.next * n, X + (size_t)j * k.next * n, n_ct,
                                        r.second - r.first, xs, (int)level);
                 t.slot0 = r.first;

@@ -327,7 +327,7 @@ struct vr_context {
     vr::u64 cdt[20];
     std::map<std::pair<int, int>, vr::ConvTable> modup_tables;   // (level, digit)
     // (level, digit, first, end): digit to the extended limbs [first, end)
-    std::map<std::array<int, 4>, vr::ConvTable> modup_range_tables;
+    std::map<std::array<int, 6>, vr::ConvTable> modup_range_tables;   // {level, digit, e0, e1, e2, e3}
     std::map<int, vr::ConvTable> moddown_tables;                 // level
     std::map<int, vr::ConvTable> moddown_rs_tables;              // level * 1024 + nk: {q_l, P} -> q_<nk
     // device-resident constants of layer calls (weights, term lists), keyed by
