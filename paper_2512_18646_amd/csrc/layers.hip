@@ -511,7 +511,8 @@ __global__ __launch_bounds__(kThreads) void k_lincomb_wide(u64* out, u64 out_str
 // across them; block order as in k_lincomb.  The block's term sources (the
 // input or rotated limb row each term reads) sit in LDS, up to kMfmaSrcChunk
 // terms at a time, and each wave loads the next step's input words while the
-// current step's products run.
+// current step's products run.  Occupancy floors: 4 waves per SIMD for the
+// FP64-fold instance (127 VGPRs), 3 for the 128-bit one (a few bytes spill).
 typedef int v4i __attribute__((ext_vector_type(4)));
 constexpr u32 kMfmaMaxTerms = 16384;
 constexpr u32 kMfmaSrcChunk = 512;
